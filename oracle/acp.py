@@ -1,0 +1,162 @@
+"""(c,k)-ACP by radius filtering, Section 6.3 (oracle, FP64).
+
+Steps (Section 6.3, Algorithm 4, in canonical form):
+  1. self-join: every pair of points stored in the same leaf of the index is
+     verified (exact distance); ub is the k-th smallest of those distances
+     (+inf when the leaves hold fewer than k pairs);
+  2. filter: every other pair whose projected distance is strictly below
+     t * ub becomes a candidate (Lemma 4 with the roles of r and ub swapped);
+  3. budget: at most T = beta * n(n-1)/2 + k pairs are verified in total;
+     if the seeds and candidates exceed T, the candidates kept are the
+     T - |seeds| with the smallest projected distance (ties by (i, j));
+  4. the k verified pairs with the smallest exact distance, ties by (i, j),
+     are returned.
+
+Readings. Algorithm 4 lowers ub while it verifies, restricts the scan to the
+subtrees returned by FindLCA (Algorithm 5) with the factor gamma, and stops
+after T pairs in a traversal-dependent order. Here ub stays at its
+self-join value, every cross-leaf pair is tested against t * ub, and the
+T-cut keeps the projected-nearest candidates. This verifies a superset of
+the pairs the paper verifies (so recall can only be higher) and makes the
+result independent of traversal order. The self-join seeds still depend on
+which points share a leaf, so the leaf partition is an input: the oracle
+takes it as data (a permutation and leaf offsets), never as code.
+
+Candidates are found by brute force over all pairs: no tree is used here, so
+a pruned pair scan elsewhere is checked for losing nothing.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class AcpResult:
+    pairs: np.ndarray      # (k, 2) int64, i < j, ascending (dist, i, j)
+    dist: np.ndarray       # (k,) float64
+    ub: float              # k-th smallest seed distance
+    n_seed: int
+    n_cand: int            # candidates kept after the T cut
+    n_cand_raw: int        # candidates before the T cut
+    margin: float
+    margin_kind: str
+
+
+def _pair_key_order(dist: np.ndarray, pi: np.ndarray, pj: np.ndarray):
+    return np.lexsort((pj, pi, dist))
+
+
+def seed_pairs(perm: np.ndarray, offsets: np.ndarray):
+    """All within-leaf pairs as (i, j) with i < j (original ids)."""
+    out_i, out_j = [], []
+    for b in range(offsets.shape[0] - 1):
+        members = np.sort(perm[offsets[b]:offsets[b + 1]].astype(np.int64))
+        L = members.shape[0]
+        if L < 2:
+            continue
+        a, c = np.triu_indices(L, k=1)
+        out_i.append(members[a])
+        out_j.append(members[c])
+    if not out_i:
+        e = np.empty(0, dtype=np.int64)
+        return e, e.copy()
+    return np.concatenate(out_i), np.concatenate(out_j)
+
+
+def pair_dist(X: np.ndarray, pi: np.ndarray, pj: np.ndarray,
+              block: int = 1 << 15) -> np.ndarray:
+    """Euclidean distances of pairs of rows of X, FP64 direct differences."""
+    out = np.empty(pi.shape[0], dtype=np.float64)
+    for s in range(0, pi.shape[0], block):
+        e = min(pi.shape[0], s + block)
+        diff = X[pi[s:e]].astype(np.float64) - X[pj[s:e]].astype(np.float64)
+        out[s:e] = np.sqrt(np.sum(diff * diff, axis=1))
+    return out
+
+
+def _cross_pairs_below(Dp: np.ndarray, leaf_of: np.ndarray, radius: float,
+                       block: int = 256):
+    """All pairs i < j in different leaves with ||o_i' - o_j'|| < radius.
+
+    Brute force over row blocks; also returns the pair closest to the
+    threshold (its relative gap) for the margin report."""
+    n = Dp.shape[0]
+    out_i, out_j, out_pd = [], [], []
+    best_gap = math.inf
+    for s in range(0, n, block):
+        e = min(n, s + block)
+        acc = np.zeros((e - s, n), dtype=np.float64)
+        for dim in range(Dp.shape[1]):
+            diff = Dp[s:e, dim][:, None] - Dp[None, :, dim]
+            acc += diff * diff
+        pd = np.sqrt(acc)
+        rows = np.arange(s, e)[:, None]
+        cols = np.arange(n)[None, :]
+        valid = (cols > rows) & (leaf_of[s:e][:, None] != leaf_of[None, :])
+        if math.isfinite(radius) and radius > 0:
+            gaps = np.abs(pd[valid] - radius) / radius
+            if gaps.size:
+                best_gap = min(best_gap, float(gaps.min()))
+        hit = valid & (pd < radius)
+        r_idx, c_idx = np.nonzero(hit)
+        out_i.append(r_idx + s)
+        out_j.append(c_idx)
+        out_pd.append(pd[r_idx, c_idx])
+    return (np.concatenate(out_i).astype(np.int64),
+            np.concatenate(out_j).astype(np.int64),
+            np.concatenate(out_pd), best_gap)
+
+
+def run(D: np.ndarray, Dp: np.ndarray, perm: np.ndarray, offsets: np.ndarray,
+        k: int, t: float, T: int) -> AcpResult:
+    """Radius-filtering ACP. D: (n,d) FP32 data; Dp: FP64 projections (n,m);
+    perm/offsets: leaf partition (leaf b holds ids perm[offsets[b]:offsets[b+1]])."""
+    n = D.shape[0]
+    leaf_of = np.empty(n, dtype=np.int64)
+    for b in range(offsets.shape[0] - 1):
+        leaf_of[perm[offsets[b]:offsets[b + 1]]] = b
+    margins = []
+
+    # 1. self-join of every leaf, all seed pairs verified
+    si, sj = seed_pairs(perm, offsets)
+    sd = pair_dist(D, si, sj)
+    so = _pair_key_order(sd, si, sj)
+    ub = float(sd[so[k - 1]]) if sd.shape[0] >= k else math.inf
+
+    # 2. every cross-leaf pair with projected distance < t * ub
+    R = t * ub
+    ci, cj, cpd, gap = _cross_pairs_below(Dp, leaf_of, R)
+    margins.append((gap, "pair_filter"))
+    n_raw = ci.shape[0]
+
+    # 3. the budget T on verified pairs, nearest-by-projection kept
+    keep = max(0, T - si.shape[0])
+    if n_raw > keep:
+        co = np.lexsort((cj, ci, cpd))
+        if keep > 0:
+            margins.append((abs(cpd[co[keep]] - cpd[co[keep - 1]])
+                            / max(cpd[co[keep - 1]], 1e-300), "budget_cut"))
+        sel = co[:keep]
+        ci, cj, cpd = ci[sel], cj[sel], cpd[sel]
+
+    # 4. verify candidates; top-k over seeds and candidates by (dist, i, j)
+    cd = pair_dist(D, ci, cj)
+    ai = np.concatenate([si, ci])
+    aj = np.concatenate([sj, cj])
+    ad = np.concatenate([sd, cd])
+    o = _pair_key_order(ad, ai, aj)
+    kk = min(k, o.shape[0])
+    top = o[:kk]
+    srt = ad[o[:kk + 1]]
+    for a, b in zip(srt[:-1], srt[1:]):
+        margins.append(((b - a) / a if a > 0 else (math.inf if b > 0 else 0.0),
+                        "topk_order"))
+    mval, mkind = min(margins, key=lambda x: x[0])
+    return AcpResult(pairs=np.stack([ai[top], aj[top]], axis=1),
+                     dist=ad[top], ub=ub, n_seed=int(si.shape[0]),
+                     n_cand=int(ci.shape[0]), n_cand_raw=int(n_raw),
+                     margin=mval, margin_kind=mkind)

@@ -1,0 +1,154 @@
+"""Pins of the oracle's (c,k)-ACP by radius filtering (Section 6.3).
+
+* One leaf holding every point: every pair is a self-join seed, so the
+  answer is the exact k closest pairs (SciPy's pdist as the reference).
+* Leaves of one point: no seeds, ub = inf, every pair is a candidate; with
+  an unbounded budget the answer is again exact.
+* The filter keeps exactly the cross-leaf pairs with projected distance
+  strictly below t*ub (SciPy's pdist on projected points as the reference).
+* Planted near-duplicates: the top-k are the k closest planted pairs.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import pdist
+
+import synth
+from oracle import acp, ann, brute, chi2, metrics
+
+
+def _exact_pairs(D, k):
+    dv = pdist(D.astype(np.float64))
+    n = D.shape[0]
+    ii, jj = np.triu_indices(n, k=1)
+    o = np.lexsort((jj, ii, dv))[:k]
+    return np.stack([ii[o], jj[o]], axis=1), dv[o]
+
+
+@pytest.fixture(scope="module")
+def small():
+    rng = np.random.Generator(np.random.PCG64(21))
+    D = rng.standard_normal((300, 24)).astype(np.float32)
+    A = rng.standard_normal((15, 24)).astype(np.float32)
+    return D, A, ann.project(D, A)
+
+
+def test_single_leaf_is_exact(small):
+    D, A, Dp = small
+    n, k = D.shape[0], 25
+    perm = np.arange(n)
+    offsets = np.array([0, n])
+    res = acp.run(D, Dp, perm, offsets, k=k, t=3.0, T=10 ** 9)
+    ep, ed = _exact_pairs(D, k)
+    assert res.pairs.tolist() == ep.tolist()
+    np.testing.assert_allclose(res.dist, ed, rtol=1e-12)
+    assert res.n_cand_raw == 0
+
+
+def test_singleton_leaves_unbounded_budget_is_exact(small):
+    D, A, Dp = small
+    n, k = D.shape[0], 10
+    res = acp.run(D, Dp, np.arange(n), np.arange(n + 1), k=k, t=3.0, T=10 ** 9)
+    assert math.isinf(res.ub) and res.n_seed == 0
+    assert res.n_cand_raw == n * (n - 1) // 2
+    ep, ed = _exact_pairs(D, k)
+    assert res.pairs.tolist() == ep.tolist()
+
+
+def test_brute_closest_pairs_matches_pdist(small):
+    D, _, _ = small
+    bp, bd = brute.closest_pairs(D, 17)
+    ep, ed = _exact_pairs(D, 17)
+    assert bp.tolist() == ep.tolist()
+    np.testing.assert_allclose(bd, ed, rtol=1e-12)
+
+
+def test_filter_is_strict_threshold_on_projected_distance(small):
+    D, A, Dp = small
+    n, k = D.shape[0], 5
+    rng = np.random.Generator(np.random.PCG64(4))
+    perm = rng.permutation(n)
+    L = 10
+    offsets = np.arange(0, n + 1, L)
+    t = chi2.radius_factor(1 / math.e, 15)
+    res = acp.run(D, Dp, perm, offsets, k=k, t=t, T=10 ** 9)
+    leaf_of = np.empty(n, dtype=np.int64)
+    for b in range(len(offsets) - 1):
+        leaf_of[perm[offsets[b]:offsets[b + 1]]] = b
+    pv = pdist(Dp)
+    ii, jj = np.triu_indices(n, k=1)
+    expect = int(np.count_nonzero((pv < t * res.ub) & (leaf_of[ii] != leaf_of[jj])))
+    assert res.n_cand_raw == expect
+    assert res.n_seed == (n // L) * L * (L - 1) // 2
+    # ub is the k-th smallest within-leaf distance
+    dv = pdist(D.astype(np.float64))
+    same = leaf_of[ii] == leaf_of[jj]
+    assert res.ub == pytest.approx(np.sort(dv[same])[k - 1], rel=1e-12)
+
+
+def test_budget_keeps_projected_nearest(small):
+    D, A, Dp = small
+    n, k = D.shape[0], 3
+    perm = np.arange(n)
+    offsets = np.arange(0, n + 1, 2)           # leaves of two points
+    full = acp.run(D, Dp, perm, offsets, k=k, t=50.0, T=10 ** 9)
+    T = full.n_seed + 40
+    cut = acp.run(D, Dp, perm, offsets, k=k, t=50.0, T=T)
+    assert cut.n_cand == 40 and cut.n_cand_raw == full.n_cand_raw
+    assert T < full.n_seed + full.n_cand_raw
+    # verified pairs of the cut run are a subset of the full run: the result
+    # can only be worse or equal rank by rank
+    assert np.all(cut.dist >= full.dist - 1e-12)
+
+
+def test_planted_pairs_are_found():
+    w = synth.planted_pairs(n=2000, d=32, n_centres=10)
+    D, A, pairs = w["D"], w["A"], w["pairs"]
+    Dp = ann.project(D, A)
+    n, k = D.shape[0], 10
+    rng = np.random.Generator(np.random.PCG64(9))
+    perm = rng.permutation(n)                  # leaves unrelated to geometry
+    offsets = np.arange(0, n + 1, 50)
+    t = chi2.radius_factor(1 / math.e, 15)
+    res = acp.run(D, Dp, perm, offsets, k=k, t=t, T=10 ** 9)
+    pd_ = np.sqrt(((D[pairs[:, 0]].astype(np.float64) - D[pairs[:, 1]]) ** 2).sum(1))
+    o = np.lexsort((pairs[:, 1], pairs[:, 0], pd_))[:k]
+    assert metrics.pair_recall(res.pairs, pairs[o]) >= 0.8
+    ep, ed = _exact_pairs(D, k)
+    assert set(map(tuple, ep.tolist())) <= set(map(tuple, pairs.tolist()))
+    assert np.all(res.dist >= ed - 1e-12)
+    key = list(zip(res.dist.tolist(), res.pairs[:, 0].tolist(),
+                   res.pairs[:, 1].tolist()))
+    assert key == sorted(key)
+    assert np.all(res.pairs[:, 0] < res.pairs[:, 1])
+
+
+def _axis(points, scale):
+    D = np.asarray(points, dtype=np.float32)
+    A = np.array([[scale, 0.0]], dtype=np.float32)
+    return D, ann.project(D, A)
+
+
+def test_filter_threshold_is_strict():
+    # leaves {0,1}, {2,3}, {4,5}; seed distances 2, 2, 1 -> ub (k=2) = 2 and
+    # with t = 1 the filter radius is 2.  Every cross pair of the first two
+    # leaves has projected distance exactly 2 (projection 2x), so none is a
+    # candidate, although (0,2) and (1,3) are at exact distance 1.
+    D, Dp = _axis([(0, 0), (0, 2), (1, 0), (1, 2), (50, 0), (50, 1)], 2.0)
+    res = acp.run(D, Dp, np.arange(6), np.array([0, 2, 4, 6]), k=2, t=1.0,
+                  T=10 ** 6)
+    assert res.ub == 2.0 and res.n_cand_raw == 0
+    assert res.pairs.tolist() == [[4, 5], [0, 1]]
+
+
+def test_budget_cut_ranks_by_projected_distance():
+    # singleton leaves: no seeds, ub = inf, all 3 pairs are candidates. T = 1
+    # keeps the pair with the smallest projected distance, (0,1) (pd 1, exact
+    # sqrt 26), not the exactly-closest pair (0,2) (pd 4, exact 4).
+    D, Dp = _axis([(0, 0), (1, 5), (4, 0)], 1.0)
+    res = acp.run(D, Dp, np.arange(3), np.arange(4), k=1, t=2.0, T=1)
+    assert res.n_cand == 1 and res.n_cand_raw == 3
+    assert res.pairs.tolist() == [[0, 1]]
+    assert res.dist[0] == pytest.approx(math.sqrt(26.0))
