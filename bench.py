@@ -1,0 +1,253 @@
+"""Benchmark of the PM-LSH (c,k)-ANN query path on one MI355X.
+
+Workload: 1,000,000 x 256 Gaussian mixture (1,000 centres of variance 4,
+per-centre sigma U[0.2, 0.5]), m = 15 projections, 10,000 fresh queries in
+batches of 1,024 per launch, k = 10, c = 1.5, confidence 1 - 1/e. Inputs are
+synthetic (seeded) and resident in HBM before timing starts.
+
+Metric: queries/s at recall@10 >= 0.9. The candidate fraction beta is swept
+({5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3}); the smallest beta whose recall@10
+over all 10,000 queries reaches 0.9 is the operating point, and only that
+point is timed. A step is one pmlsh_ann call on one batch (projection, range
+filter over the PM-tree, budget selection, exact verification, top-k).
+
+Also reported: p50/p99 batch latency, the roofline of the query kernel
+(algorithmic bytes per launch / measured time against 8 TB/s) and the FP64
+CPU oracle timed on this host on a bounded sample of the same queries.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BETAS = [5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3]
+K = 10
+C = 1.5
+CONF = 1 - 1 / math.e
+BATCH = 1024
+PMC_FILE = os.path.join(ROOT, "profiles", "ann_kernel_headline_pmc.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def exact_knn_gpu(torch, D, Q, k, chunk=128):
+    """Ground-truth exact kNN (ids sorted by (distance, id)) for recall.
+
+    Measurement only, not part of the timed path: FP64 distances by the
+    norm expansion on the GPU pick 4k candidates, which are re-ranked by FP64
+    direct differences."""
+    Dd = D.double()
+    dn = (Dd * Dd).sum(1)
+    out = []
+    for s in range(0, Q.shape[0], chunk):
+        q = Q[s:s + chunk].double()
+        d2 = (q * q).sum(1, keepdim=True) + dn[None, :] - 2.0 * (q @ Dd.T)
+        cand = torch.topk(d2, 4 * k, dim=1, largest=False).indices
+        diff = Dd[cand] - q[:, None, :]
+        ex = (diff * diff).sum(2)
+        # order by (exact distance, id)
+        key_id = cand.double()
+        o = torch.argsort(key_id, dim=1)
+        ex, cand = torch.gather(ex, 1, o), torch.gather(cand, 1, o)
+        o = torch.argsort(ex, dim=1, stable=True)
+        out.append(torch.gather(cand, 1, o)[:, :k])
+    return torch.cat(out)
+
+
+def recall_at_k(ids, truth):
+    hit = (ids[:, :, None] == truth[:, None, :]).any(2).sum(1).double()
+    return float((hit / truth.shape[1]).mean())
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ann.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2107_05537_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, beta, r_min, budget_s=12.0, max_q=64):
+    """The FP64 oracle on this host's cores, bounded sample of the queries."""
+    from oracle import ann as oann
+    from oracle import chi2
+    D, A, Q = w["D"], w["A"], w["Q"]
+    n = D.shape[0]
+    t = chi2.radius_factor(1 - CONF, A.shape[0])
+    B = chi2.ann_budget(beta, n, K)
+    Dp = oann.project(D, A)              # index construction, not timed
+    done = 0
+    t0 = time.perf_counter()
+    while done < max_q and time.perf_counter() - t0 < budget_s:
+        qp = oann.project(Q[done:done + 1], A)[0]
+        oann.query(D, Dp, Q[done], qp, K, C, t, B, r_min)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of the 10,000 queries at beta={beta}, "
+                      f"{dt:.1f} s on one host thread (FP64 NumPy, projection of D precomputed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--beta", type=float, default=None, help="skip the sweep")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                                   f"--gpus {args.gpus} is not supported"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2107_05537_amd as pm
+    import synth
+
+    pm.load_library()
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    w = synth.headline()
+    log(f"workload generated in {time.perf_counter() - t0:.1f} s")
+    D = torch.from_numpy(w["D"]).to(dev)
+    A = torch.from_numpy(w["A"]).to(dev)
+    Q = torch.from_numpy(w["Q"]).to(dev)
+    n, d = D.shape
+    nq = Q.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx = pm.Index(D, A)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(f"index built in {build_s:.2f} s: {idx.info()}")
+
+    t0 = time.perf_counter()
+    truth = exact_knn_gpu(torch, D, Q, K)
+    torch.cuda.synchronize()
+    log(f"ground truth in {time.perf_counter() - t0:.1f} s")
+
+    batches = [(s, min(nq, s + BATCH)) for s in range(0, nq, BATCH)]
+    ids = torch.empty((nq, K), dtype=torch.int64, device=dev)
+    dist = torch.empty((nq, K), dtype=torch.float32, device=dev)
+    stats = torch.empty((nq, 4), dtype=torch.int32, device=dev)
+
+    def run_all(beta):
+        for s, e in batches:
+            idx.ann_into(Q[s:e], K, C, CONF, beta, 0.0, ids[s:e], dist[s:e], stats[s:e])
+        torch.cuda.synchronize()
+
+    sweep = []
+    betas = BETAS if args.beta is None else [args.beta]
+    chosen = None
+    for beta in betas:
+        run_all(beta)
+        rec = recall_at_k(ids, truth)
+        sweep.append({"beta": beta, "recall@10": round(rec, 4)})
+        log(f"beta={beta:g} recall@10={rec:.4f} exits={np.bincount(stats[:, 2].cpu().numpy(), minlength=3).tolist()}")
+        if rec >= 0.9 and chosen is None:
+            chosen = beta
+            break
+    if chosen is None:
+        chosen = betas[-1]
+    beta = chosen
+    plan = pm.plan_params(n, A.shape[0], K, C, CONF, beta)
+    B = plan["budget"]
+    r_min = idx.default_r_min(B)
+
+    # recall/ratio and algorithmic bytes at the operating point
+    run_all(beta)
+    rec = recall_at_k(ids, truth)
+    st = stats.cpu().numpy().astype(np.int64)
+    d_pad = (d + 3) // 4 * 4
+    bytes_per_query = 4 * d + 64 * st[:, 3] + 4 * d_pad * st[:, 1] + 12 * K
+    batch_bytes = [float(bytes_per_query[s:e].sum()) for s, e in batches]
+
+    # timed region
+    for i in range(args.warmup):
+        s, e = batches[i % len(batches)]
+        idx.ann_into(Q[s:e], K, C, CONF, beta, r_min, ids[s:e], dist[s:e], stats[s:e])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    queries = 0
+    algo_bytes = 0.0
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for i in range(args.steps):
+        b = i % len(batches)
+        s, e = batches[b]
+        ev[i][0].record()
+        idx.ann_into(Q[s:e], K, C, CONF, beta, r_min, ids[s:e], dist[s:e], stats[s:e])
+        ev[i][1].record()
+        queries += e - s
+        algo_bytes += batch_bytes[b]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])          # ms per batch
+    gpu_s = lat.sum() / 1e3
+    value = queries / wall
+    achieved = algo_bytes / gpu_s / 1e9
+
+    traffic = None
+    if os.path.exists(PMC_FILE):
+        with open(PMC_FILE) as fh:
+            pmc = json.load(fh)
+        if pmc.get("kernel_source_sha") == kernel_source_hash():
+            traffic = pmc.get("traffic")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, beta, r_min)
+
+    out = {
+        "metric": "c-ANN queries/s at recall@10>=0.9 (1M x 256)",
+        "value": round(value, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(float(wall * 1e3 / args.steps), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gaussian-mixture 1,000,000 x 256, 1,000 centres, "
+                               "10,000 queries in batches of 1,024",
+                   "k": K, "c": C, "confidence": round(CONF, 6), "m": 15,
+                   "beta": beta, "budget_B": B, "r_min": r_min,
+                   "batch": BATCH, "parallelism": "single GPU"},
+        "recall@10": round(rec, 4),
+        "sweep": sweep,
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4),
+                       "per": "batch of up to 1,024 queries"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "ann_kernel (with the query projection in the same call)"},
+        "build_s": round(build_s, 2),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * pmlsh.h - C ABI of the PM-LSH query path on AMD Instinct MI355X (gfx950).
+ *
+ * PM-LSH (Zheng et al., "PM-LSH: a fast and accurate in-memory framework for
+ * high-dimensional approximate NN and closest pair search") answers
+ *   (c,k)-ANN  (Definition 2, Section 2.1) with Algorithm 2 (Section 5.2), and
+ *   (c,k)-ACP  (Definition 4, Section 2.1) with radius filtering (Section 6.3)
+ * over points projected by m Gaussian hash functions h*(o) = a . o (Eq. 3,
+ * Section 3.2) and indexed by a PM-tree in the projected space (Section 4.1).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: PMLSH_OK (0) on success, a negative PMLSH_E* code on error.
+ *     On error no output buffer has been written and a message is available
+ *     from pmlsh_last_error() on the calling thread. No C++ exception crosses
+ *     this interface.
+ *   - Argument validation happens before any HIP call: invalid arguments are
+ *     reported without touching the GPU.
+ *   - Matrices are row-major FP32. Ids are 0-based row numbers of the data
+ *     matrix passed to pmlsh_build, int64 at this interface.
+ *   - Distances returned are Euclidean (not squared), FP32. Results are
+ *     sorted ascending by (distance, id) for ANN and by (distance, i, j) with
+ *     i < j for ACP.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
+ *     enqueued on it; pmlsh_ann returns before the results are ready (read
+ *     them after synchronising the stream), pmlsh_build and pmlsh_acp return
+ *     after their work on the stream has completed.
+ *   - An index may be used by several threads for concurrent queries on
+ *     different streams; calls on the same index and the same stream are
+ *     serialised by the stream.
+ */
+#ifndef PMLSH_H
+#define PMLSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMLSH_OK 0
+#define PMLSH_EINVAL (-1)       /* invalid argument                          */
+#define PMLSH_ENOMEM (-2)       /* device or host memory exhausted           */
+#define PMLSH_EDEVICE (-3)      /* a HIP call failed                         */
+#define PMLSH_EUNSUPPORTED (-4) /* valid but outside this build's limits     */
+
+#define PMLSH_MAX_M 16          /* hash functions per index                  */
+#define PMLSH_MAX_PIVOTS 8      /* global pivots of the PM-tree              */
+#define PMLSH_MAX_K 1024        /* results per ANN query / ACP call          */
+
+/* exit kinds reported per ANN query (Algorithm 2)                          */
+#define PMLSH_EXIT_LINE4 1      /* k verified points within c*r              */
+#define PMLSH_EXIT_BUDGET 2     /* the range query reached beta*n + k points */
+
+typedef struct pmlsh_index pmlsh_index; /* opaque, owned by the caller once built */
+
+/*
+ * Index construction (Sections 3.2 and 4.1).
+ *   data   n x d FP32, row-major. Device pointer if data_on_device != 0, else
+ *          host pointer. Read only; the index keeps its own copy (rows
+ *          permuted to leaf order), so the caller may free `data` on return.
+ *   hash   m x d FP32, row-major: the m projection vectors a_1..a_m, whose
+ *          entries the caller draws i.i.d. from N(0,1) (2-stable, Section 2.2).
+ *          Same residency as `data`. Copied.
+ *   n >= 1, 1 <= d <= 65536, 1 <= m <= PMLSH_MAX_M. Every value must be finite.
+ *   num_pivots   s, 0..PMLSH_MAX_PIVOTS (the paper uses 5, Section 7.1).
+ *   leaf_size    points per leaf, 8..256 (0 = 64).
+ *   fanout       children per inner node, a power of two in 2..64 (0 = 16).
+ *   sample_seed  seed of the pair sample that estimates the distance
+ *                distribution F used for r_min (Section 5.2).
+ *   r_min_kappa  r_min = kappa * F^-1(B/n); in (0, 1]; 0 selects 0.9.
+ * Errors: EINVAL (arguments, non-finite values), ENOMEM, EDEVICE,
+ * EUNSUPPORTED. On success *out receives the index; free it with pmlsh_free.
+ */
+typedef struct {
+    const float* data;
+    int64_t n;
+    int32_t d;
+    const float* hash;
+    int32_t m;
+    int32_t data_on_device;
+    int32_t num_pivots;
+    int32_t leaf_size;
+    int32_t fanout;
+    int32_t reserved;
+    uint64_t sample_seed;
+    double r_min_kappa;
+    void* stream;
+} pmlsh_build_args;
+
+int pmlsh_build(const pmlsh_build_args* args, pmlsh_index** out);
+
+/* Releases every host and device resource of the index. NULL is a no-op.
+ * The caller must make sure no work using the index is still in flight. */
+void pmlsh_free(pmlsh_index* index);
+
+/*
+ * Query parameters of Algorithm 2 (Lemma 3, Eq. 10, Lemma 5, Section 5.2).
+ * Host-only computation: never touches the GPU.
+ *   confidence  Pr[E1] = 1 - alpha1 in (0,1): t = sqrt(chi^2_{alpha1}(m)),
+ *               the upper alpha1 quantile (Lemma 3, first line of Eq. 10).
+ *   c > 1       approximation ratio; alpha2 solves t^2 = c^2 chi^2_{1-alpha2}(m).
+ *   beta        fraction of false positives budgeted; beta < 0 selects
+ *               2 * alpha2 (Lemma 5); beta must be <= 1.
+ *   budget      B = ceil(beta * n) + k, capped at n (candidates of Algorithm 2).
+ *   acp_budget  T = ceil(beta * n (n-1) / 2) + k (pairs of Section 6.3).
+ * Errors: EINVAL for n < 1, m outside 1..16, k < 1, c <= 1 or not finite,
+ * confidence outside (0,1), beta > 1 or NaN.
+ */
+typedef struct {
+    double t;          /* radius factor                                  */
+    double alpha1;
+    double alpha2;
+    double beta;       /* the beta actually used                         */
+    int64_t budget;    /* B                                              */
+    int64_t acp_budget;/* T                                              */
+} pmlsh_plan;
+
+int pmlsh_plan_params(int64_t n, int32_t m, int32_t k, double c,
+                      double confidence, double beta, pmlsh_plan* out);
+
+/* r_min of Section 5.2 for a candidate budget B on this index:
+ * kappa * (sample distance at index ceil(min(1, B/n) * S) - 1), S the sample
+ * size. Host-only. Errors: EINVAL for a NULL argument or budget < 1. */
+int pmlsh_default_r_min(const pmlsh_index* index, int64_t budget, double* r_min);
+
+/*
+ * (c,k)-ANN, Algorithm 2 (Section 5.2), for a batch of queries.
+ *   queries   nq x d FP32 device pointer (row-major).
+ *   nq >= 0 (0 is a no-op), 1 <= k <= min(n, PMLSH_MAX_K), c, confidence,
+ *   beta as in pmlsh_plan_params; r_min > 0 is the first radius, r_min <= 0
+ *   selects pmlsh_default_r_min for the budget B.
+ *   out_ids   nq x k int64 device pointer; out_dist nq x k FP32 device pointer.
+ *   out_stats optional (NULL allowed) nq x 4 int32 device pointer; per query:
+ *             range queries issued, final |C|, exit kind (PMLSH_EXIT_*),
+ *             points scanned in leaves over all rounds (saturating at 2^31-1).
+ * Each query: project q with the index's hash matrix; starting at r = r_min,
+ * (a) from the second round on, stop if k candidates lie within c*r of q;
+ * (b) collect the points whose projected distance to q' is <= t*r, using
+ *     the PM-tree's node test (Eq. 5) to skip subtrees;
+ * (c) if they number >= B, the candidate set C is the B of them nearest to q'
+ *     in the projected space (ties by id) and the loop stops; otherwise
+ *     C is all of them and r <- c*r.
+ * The answer is the k members of C nearest to q by exact distance.
+ * Asynchronous on `stream`. Errors: EINVAL, ENOMEM (workspace), EDEVICE,
+ * EUNSUPPORTED (k > PMLSH_MAX_K).
+ */
+int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq,
+              int32_t k, double c, double confidence, double beta, double r_min,
+              int64_t* out_ids, float* out_dist, int32_t* out_stats,
+              void* stream);
+
+/*
+ * (c,k)-ACP by radius filtering (Section 6.3, Algorithm 4), canonical form.
+ *   1. every pair inside one leaf is verified; ub = the k-th smallest such
+ *      distance (+inf if fewer than k pairs);
+ *   2. every pair (i<j) in different leaves with projected distance < t*ub is
+ *      a candidate; pairs of leaves whose Mindist (Eq. 11) is at least t*ub
+ *      are skipped whole;
+ *   3. at most T pairs are verified in total; above that the candidates with
+ *      the smallest projected distance (ties by (i,j)) are kept;
+ *   4. the k verified pairs with the smallest exact distance are returned.
+ *   n >= 2, 1 <= k <= min(n(n-1)/2, PMLSH_MAX_K); c, confidence, beta as in
+ *   pmlsh_plan_params.
+ *   out_pairs k x 2 int64 device pointer (i < j); out_dist k FP32 device.
+ *   stats     optional host pointer, filled on success.
+ * Synchronous: returns after the work on `stream` has completed.
+ * Errors: EINVAL, ENOMEM (candidate buffers), EDEVICE, EUNSUPPORTED.
+ */
+typedef struct {
+    double t;
+    double ub;            /* k-th smallest self-join distance                 */
+    int64_t budget;       /* T                                                */
+    int64_t n_seed;       /* pairs verified by the self-join                  */
+    int64_t n_cand_raw;   /* cross-leaf pairs with projected distance < t*ub  */
+    int64_t n_cand;       /* candidates verified after the T cut              */
+    int64_t tiles_total;  /* leaf pairs (e1 < e2)                             */
+    int64_t tiles_scanned;/* leaf pairs that survived the Mindist test        */
+} pmlsh_acp_stats;
+
+int pmlsh_acp(const pmlsh_index* index, int32_t k, double c, double confidence,
+              double beta, int64_t* out_pairs, float* out_dist,
+              pmlsh_acp_stats* stats, void* stream);
+
+/* Shape and size of a built index. Host-only. */
+typedef struct {
+    int64_t n;
+    int32_t d;
+    int32_t m;
+    int32_t leaf_size;
+    int32_t fanout;
+    int32_t num_pivots;
+    int32_t levels;       /* tree levels including the leaf level           */
+    int64_t n_leaves;
+    int64_t n_nodes;      /* all levels                                       */
+    int64_t sample_size;  /* pairs in the r_min sample                        */
+    int64_t device_bytes; /* HBM held by the index                            */
+} pmlsh_index_info;
+
+int pmlsh_get_index_info(const pmlsh_index* index, pmlsh_index_info* out);
+
+/* Leaf partition of the index, for checking ACP against an independent
+ * implementation: leaf b holds the ids perm[offsets[b] .. offsets[b+1]).
+ * perm: n int32 host buffer; offsets: n_leaves + 1 int64 host buffer.
+ * Host-only (copied at build). */
+int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
+                              int64_t* offsets);
+
+/* Message of the last failed call on this thread ("" if none). The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* pmlsh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMLSH_H */

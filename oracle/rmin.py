@@ -15,7 +15,9 @@ margin. Reading used here:
         sm(x) = z ^ (z >> 31)          (all arithmetic mod 2^64);
   * the pair distances (Euclidean, FP64) are sorted ascending and the
     element at index ceil(q*S) - 1 is taken, q = min(1, B/n) with B the
-    candidate budget; r_min = kappa * that element, kappa = 0.9.
+    candidate budget; r_min = kappa * that element, kappa = 0.9;
+  * a zero element (duplicate points) would make r <- c r stall at 0, so the
+    smallest positive sample distance replaces it (1 if there is none).
 """
 
 from __future__ import annotations
@@ -68,9 +70,15 @@ def r_min_from_sample(sorted_dist: np.ndarray, n: int, budget: int,
                       kappa: float = KAPPA) -> float:
     """kappa * F^-1(B/n) read off the sorted sample (Section 5.2)."""
     S = sorted_dist.shape[0]
+    if S == 0:
+        return 1.0
     q = min(1.0, budget / n)
     idx = max(0, int(math.ceil(q * S)) - 1)
-    return kappa * float(sorted_dist[idx])
+    v = float(sorted_dist[idx])
+    if not v > 0.0:
+        pos = sorted_dist[sorted_dist > 0.0]
+        v = float(pos[0]) if pos.size else 1.0 / kappa
+    return kappa * v
 
 
 def r_min(D: np.ndarray, seed: int, budget: int, kappa: float = KAPPA) -> float:

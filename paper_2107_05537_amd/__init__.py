@@ -1,0 +1,249 @@
+"""PM-LSH query path on AMD Instinct MI355X: Python binding of the C ABI.
+
+This module only marshals arguments: every step of index construction,
+(c,k)-ANN (Algorithm 2) and (c,k)-ACP (Section 6.3) runs in the HIP library
+``libpmlsh.so`` (declared in ``include/pmlsh.h``). PyTorch supplies device
+memory and the current HIP stream. There is no CPU fallback: a missing
+library or a tensor that is not on the GPU raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = ["Index", "PmlshError", "plan_params", "library_path", "load_library"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libpmlsh.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+EXIT_LINE4, EXIT_BUDGET = 1, 2
+MAX_K = 1024
+
+
+class PmlshError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"pmlsh error {code}: {message}")
+        self.code = code
+
+
+class _BuildArgs(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("hash", ctypes.c_void_p), ("m", ctypes.c_int32),
+                ("data_on_device", ctypes.c_int32), ("num_pivots", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("fanout", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("sample_seed", ctypes.c_uint64),
+                ("r_min_kappa", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class _Plan(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("alpha2", ctypes.c_double), ("beta", ctypes.c_double),
+                ("budget", ctypes.c_int64), ("acp_budget", ctypes.c_int64)]
+
+
+class _AcpStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("ub", ctypes.c_double), ("budget", ctypes.c_int64),
+                ("n_seed", ctypes.c_int64), ("n_cand_raw", ctypes.c_int64),
+                ("n_cand", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
+                ("tiles_scanned", ctypes.c_int64)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("fanout", ctypes.c_int32),
+                ("num_pivots", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("n_leaves", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("sample_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+_LIB = None
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "pmlsh_build": (ctypes.c_int, [ctypes.POINTER(_BuildArgs), ctypes.POINTER(ctypes.c_void_p)]),
+    "pmlsh_free": (None, [ctypes.c_void_p]),
+    "pmlsh_plan_params": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(_Plan)]),
+    "pmlsh_default_r_min": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "pmlsh_ann": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pmlsh_acp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.POINTER(_AcpStats), ctypes.c_void_p]),
+    "pmlsh_get_index_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
+    "pmlsh_index_export_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
+    "pmlsh_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load_library():
+    """Loads libpmlsh.so (built in-tree); raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(
+                f"{library_path} is missing: build it with "
+                "`python -m paper_2107_05537_amd.build_lib`")
+        lib = ctypes.CDLL(library_path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(code: int):
+    if code != OK:
+        msg = load_library().pmlsh_last_error()
+        raise PmlshError(code, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_gpu_f32(name, t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return t.contiguous()
+
+
+def plan_params(n: int, m: int, k: int, c: float, confidence: float, beta: float = -1.0):
+    """Parameters of Algorithm 2 / Section 6.3 as computed by the library (host only)."""
+    out = _Plan()
+    _check(load_library().pmlsh_plan_params(n, m, k, c, confidence, beta, ctypes.byref(out)))
+    return {f: getattr(out, f) for f, _ in _Plan._fields_}
+
+
+class Index:
+    """A PM-tree index over FP32 data, resident in HBM.
+
+    data: (n, d) float32 torch tensor on the GPU, or a NumPy array on the host.
+    hash: (m, d) float32 projection vectors (N(0,1) entries), same residency.
+    """
+
+    def __init__(self, data, hash, num_pivots: int = 5, leaf_size: int = 64,
+                 fanout: int = 16, sample_seed: int = 0x5EED, r_min_kappa: float = 0.9):
+        lib = load_library()
+        self._h = ctypes.c_void_p()
+        args = _BuildArgs()
+        keep = []
+        if isinstance(data, np.ndarray):
+            if not isinstance(hash, np.ndarray):
+                raise TypeError("data and hash must both be NumPy arrays or both GPU tensors")
+            D = np.ascontiguousarray(data, dtype=np.float32)
+            H = np.ascontiguousarray(hash, dtype=np.float32)
+            keep += [D, H]
+            args.data, args.hash = D.ctypes.data, H.ctypes.data
+            args.data_on_device = 0
+            self.device = None
+            stream = None
+        else:
+            D = _require_gpu_f32("data", data)
+            H = _require_gpu_f32("hash", hash)
+            if H.device != D.device:
+                raise ValueError("data and hash must be on the same device")
+            keep += [D, H]
+            args.data, args.hash = D.data_ptr(), H.data_ptr()
+            args.data_on_device = 1
+            self.device = D.device
+            stream = _stream_handle(D.device)
+        if D.ndim != 2 or H.ndim != 2 or H.shape[1] != D.shape[1]:
+            raise ValueError("data must be (n, d) and hash (m, d)")
+        args.n, args.d = D.shape[0], D.shape[1]
+        args.m = H.shape[0]
+        args.num_pivots, args.leaf_size, args.fanout = num_pivots, leaf_size, fanout
+        args.sample_seed = sample_seed
+        args.r_min_kappa = r_min_kappa
+        args.stream = stream
+        _check(lib.pmlsh_build(ctypes.byref(args), ctypes.byref(self._h)))
+        if self.device is None:
+            self.device = _torch().device("cuda", _torch().cuda.current_device())
+        info = self.info()
+        self.n, self.d, self.m = info["n"], info["d"], info["m"]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.pmlsh_free(h)
+            self._h = None
+
+    def info(self) -> dict:
+        out = _Info()
+        _check(load_library().pmlsh_get_index_info(self._h, ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in _Info._fields_}
+
+    def default_r_min(self, budget: int) -> float:
+        v = ctypes.c_double()
+        _check(load_library().pmlsh_default_r_min(self._h, budget, ctypes.byref(v)))
+        return v.value
+
+    def export_leaves(self):
+        """Leaf partition: leaf b holds ids perm[offsets[b]:offsets[b+1]]."""
+        info = self.info()
+        perm = np.empty(info["n"], dtype=np.int32)
+        offsets = np.empty(info["n_leaves"] + 1, dtype=np.int64)
+        _check(load_library().pmlsh_index_export_leaves(self._h, perm.ctypes.data,
+                                                        offsets.ctypes.data))
+        return perm, offsets
+
+    def ann(self, queries, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
+            beta: float = -1.0, r_min: float = 0.0, stats: bool = False):
+        """(c,k)-ANN for every row of `queries` ((nq, d) float32 on the GPU).
+
+        Returns (ids int64 (nq,k), dist float32 (nq,k)) and, with stats=True,
+        an int32 (nq, 4) tensor: rounds, |C|, exit kind, points scanned.
+        Enqueued on the current stream (results valid after it completes).
+        """
+        torch = _torch()
+        Q = _require_gpu_f32("queries", queries)
+        if Q.ndim != 2 or Q.shape[1] != self.d:
+            raise ValueError(f"queries must be (nq, {self.d})")
+        nq = Q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=Q.device) if stats else None
+        _check(load_library().pmlsh_ann(
+            self._h, Q.data_ptr(), nq, k, c, confidence, beta, r_min, ids.data_ptr(),
+            dist.data_ptr(), st.data_ptr() if st is not None else None,
+            _stream_handle(Q.device)))
+        return (ids, dist, st) if stats else (ids, dist)
+
+    def ann_into(self, queries, k, c, confidence, beta, r_min, ids, dist, stats=None):
+        """Like ann() but writes into caller-provided GPU tensors (no allocation)."""
+        _check(load_library().pmlsh_ann(
+            self._h, queries.data_ptr(), queries.shape[0], k, c, confidence, beta, r_min,
+            ids.data_ptr(), dist.data_ptr(), stats.data_ptr() if stats is not None else None,
+            _stream_handle(queries.device)))
+
+    def acp(self, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
+            beta: float = -1.0):
+        """(c,k)-ACP. Returns (pairs int64 (k,2) with i<j, dist float32 (k,), stats dict)."""
+        torch = _torch()
+        pairs = torch.empty((k, 2), dtype=torch.int64, device=self.device)
+        dist = torch.empty((k,), dtype=torch.float32, device=self.device)
+        st = _AcpStats()
+        _check(load_library().pmlsh_acp(self._h, k, c, confidence, beta, pairs.data_ptr(),
+                                        dist.data_ptr(), ctypes.byref(st),
+                                        _stream_handle(self.device)))
+        return pairs, dist, {f: getattr(st, f) for f, _ in _AcpStats._fields_}

@@ -1,0 +1,606 @@
+// (c,k)-ACP by radius filtering (Section 6.3) on gfx950.
+//
+//   seeds    every pair inside one leaf, exact FP32 squared distance by direct
+//            differences (acp_self_join_kernel);
+//   ub       the k-th smallest seed distance (device-wide radix select);
+//   tiles    leaf pairs (e1 < e2) whose Mindist of Eq. 11 can fall below
+//            t*ub (acp_tile_filter_kernel), a lossless skip of whole leaf pairs;
+//   scan     all point pairs of the surviving tiles, projected distance from
+//            the hi/lo coordinate pairs, kept when strictly below t*ub
+//            (acp_tile_scan_kernel);
+//   budget   at most T verified pairs: the projected-nearest candidates are
+//            kept (device-wide radix select on (pd^2, i, j));
+//   verify   exact FP32 squared distance of the kept candidates;
+//   top-k    the k smallest (dist^2, i, j) over seeds and candidates.
+//
+// Pairs are carried as three uint32 arrays: the FP32 bit pattern of a squared
+// distance (monotone for non-negative floats), then the ids i < j. Ordering by
+// the 96-bit concatenation is ordering by (distance, i, j).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pmlsh {
+namespace {
+
+constexpr int WG = 256;
+constexpr int NB = 2048;
+constexpr int SJ_KC = 16;          // columns staged per self-join step
+constexpr int SJ_PER = 8;          // pairs owned by a thread per batch
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Slot for lanes with take == true, one global atomic per wave; returns -1
+// for lanes that do not take.
+__device__ __forceinline__ int64_t wave_append_global(bool take, unsigned long long* counter) {
+    const uint64_t m = __ballot(take);
+    if (m == 0) return -1;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+// ---------------------------------------------------------------- seeds
+__global__ __launch_bounds__(WG) void acp_self_join_kernel(
+    const float* __restrict__ data, int d_pad, const int32_t* __restrict__ perm, int64_t n,
+    int L, const int64_t* __restrict__ seed_off, uint32_t* __restrict__ k0,
+    uint32_t* __restrict__ ii, uint32_t* __restrict__ jj) {
+    __shared__ float xs[256][SJ_KC + 1];
+    const int64_t leaf = blockIdx.x;
+    const int64_t p0 = leaf * L;
+    const int cnt = (int)(n - p0 < L ? n - p0 : L);
+    const int P = cnt * (cnt - 1) / 2;
+    const int64_t out0 = seed_off[leaf];
+    for (int base = 0; base < P; base += WG * SJ_PER) {
+        int ra[SJ_PER], rb[SJ_PER];
+        float acc[SJ_PER];
+#pragma unroll
+        for (int u = 0; u < SJ_PER; ++u) {
+            const int p = base + threadIdx.x + u * WG;
+            ra[u] = -1; rb[u] = -1; acc[u] = 0.f;
+            if (p < P) {
+                int a = 0, rem = p;
+                while (rem >= cnt - 1 - a) { rem -= cnt - 1 - a; ++a; }
+                ra[u] = a;
+                rb[u] = a + 1 + rem;
+            }
+        }
+        for (int c0 = 0; c0 < d_pad; c0 += SJ_KC) {
+            for (int e = threadIdx.x; e < cnt * SJ_KC; e += WG) {
+                const int r = e / SJ_KC, c = e % SJ_KC;
+                xs[r][c] = (c0 + c < d_pad) ? data[(p0 + r) * d_pad + c0 + c] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < SJ_PER; ++u) {
+                if (ra[u] >= 0) {
+#pragma unroll
+                    for (int c = 0; c < SJ_KC; ++c) {
+                        const float t = xs[ra[u]][c] - xs[rb[u]][c];
+                        acc[u] = __fmaf_rn(t, t, acc[u]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < SJ_PER; ++u) {
+            if (ra[u] >= 0) {
+                const int p = base + threadIdx.x + u * WG;
+                const uint32_t ia = (uint32_t)perm[p0 + ra[u]], ib = (uint32_t)perm[p0 + rb[u]];
+                k0[out0 + p] = __float_as_uint(acc[u]);
+                ii[out0 + p] = ia < ib ? ia : ib;
+                jj[out0 + p] = ia < ib ? ib : ia;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- tiles
+struct NodeView {
+    const float* cen;
+    const float* rad;
+    const float* hrmin;
+    const float* hrmax;
+    int64_t n_nodes;
+    int s;
+};
+
+// Mindist of Eq. 11: the larger of the pivot-ring gap and the centre gap.
+__device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b) {
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+        const float t = v.cen[(int64_t)j * v.n_nodes + a] - v.cen[(int64_t)j * v.n_nodes + b];
+        acc = fmaf(t, t, acc);
+    }
+    float m = sqrtf(acc) - v.rad[a] - v.rad[b];
+    for (int i = 0; i < v.s; ++i) {
+        const int64_t oa = (int64_t)i * v.n_nodes + a, ob = (int64_t)i * v.n_nodes + b;
+        m = fmaxf(m, v.hrmin[ob] - v.hrmax[oa]);
+        m = fmaxf(m, v.hrmin[oa] - v.hrmax[ob]);
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(WG) void acp_tile_filter_kernel(
+    NodeView v, int64_t leaf_base, int64_t n_leaves, float limit,
+    int2* __restrict__ tiles, int64_t cap, unsigned long long* __restrict__ counter) {
+    const int64_t e1 = blockIdx.y;
+    const int64_t e2 = (int64_t)blockIdx.x * WG + threadIdx.x;
+    bool keep = false;
+    if (e2 > e1 && e2 < n_leaves) keep = mindist(v, leaf_base + e1, leaf_base + e2) <= limit;
+    const int64_t slot = wave_append_global(keep, counter);
+    if (keep && slot < cap) tiles[slot] = make_int2((int)e1, (int)e2);
+}
+
+__global__ __launch_bounds__(WG) void acp_tile_scan_kernel(
+    const float* __restrict__ phi, const float* __restrict__ plo,
+    const int32_t* __restrict__ perm, int64_t n, int L, const int2* __restrict__ tiles,
+    int64_t n_tiles, float R2, uint32_t* __restrict__ ck0, uint32_t* __restrict__ cii,
+    uint32_t* __restrict__ cjj, int64_t cap, unsigned long long* __restrict__ counter) {
+    extern __shared__ __align__(16) float lds[];
+    float* h1 = lds;
+    float* l1 = h1 + L * MP;
+    float* h2 = l1 + L * MP;
+    float* l2 = h2 + L * MP;
+    int32_t* id1 = reinterpret_cast<int32_t*>(l2 + L * MP);
+    int32_t* id2 = id1 + L;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int2 tl = tiles[t];
+        const int64_t a0 = (int64_t)tl.x * L, b0 = (int64_t)tl.y * L;
+        const int ca = (int)(n - a0 < L ? n - a0 : L);
+        const int cb = (int)(n - b0 < L ? n - b0 : L);
+        for (int e = threadIdx.x; e < ca * MP; e += WG) {
+            h1[e] = phi[a0 * MP + e];
+            l1[e] = plo[a0 * MP + e];
+        }
+        for (int e = threadIdx.x; e < cb * MP; e += WG) {
+            h2[e] = phi[b0 * MP + e];
+            l2[e] = plo[b0 * MP + e];
+        }
+        for (int e = threadIdx.x; e < ca; e += WG) id1[e] = perm[a0 + e];
+        for (int e = threadIdx.x; e < cb; e += WG) id2[e] = perm[b0 + e];
+        __syncthreads();
+        const int P = ca * cb;
+        for (int base = 0; base < P; base += WG) {
+            const int p = base + threadIdx.x;
+            bool hit = false;
+            float pd2 = 0.f;
+            int a = 0, b = 0;
+            if (p < P) {
+                a = p / cb;
+                b = p - a * cb;
+                const float* x1 = h1 + a * MP;
+                const float* y1 = l1 + a * MP;
+                const float* x2 = h2 + b * MP;
+                const float* y2 = l2 + b * MP;
+#pragma unroll
+                for (int j = 0; j < MP; ++j) {
+                    // (hi1 - hi2) is exact for nearby points (Sterbenz); the lo
+                    // parts restore what rounding the projection to FP32 lost
+                    const float dt = __fadd_rn(__fsub_rn(x1[j], x2[j]), __fsub_rn(y1[j], y2[j]));
+                    pd2 = __fmaf_rn(dt, dt, pd2);
+                }
+                hit = pd2 < R2;
+            }
+            const int64_t slot = wave_append_global(hit, counter);
+            if (hit && slot < cap) {
+                const uint32_t ia = (uint32_t)id1[a], ib = (uint32_t)id2[b];
+                ck0[slot] = __float_as_uint(pd2);
+                cii[slot] = ia < ib ? ia : ib;
+                cjj[slot] = ia < ib ? ib : ia;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- verify
+__global__ __launch_bounds__(WG) void acp_verify_kernel(
+    const float* __restrict__ data, int d_pad, const int32_t* __restrict__ inv_perm,
+    const uint32_t* __restrict__ cii, const uint32_t* __restrict__ cjj, int64_t count,
+    uint32_t* __restrict__ k0, uint32_t* __restrict__ ii, uint32_t* __restrict__ jj) {
+    const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int d4 = d_pad >> 2;
+    for (int64_t base = (int64_t)blockIdx.x * (WG / 16); base < count;
+         base += (int64_t)gridDim.x * (WG / 16)) {
+        const int64_t e = base + g;
+        float acc = 0.f;
+        if (e < count) {
+            const float4* r1 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[cii[e]] * d_pad);
+            const float4* r2 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[cjj[e]] * d_pad);
+            for (int c = l16; c < d4; c += 16) {
+                const float4 x = r1[c], y = r2[c];
+                float t;
+                t = x.x - y.x; acc = __fmaf_rn(t, t, acc);
+                t = x.y - y.y; acc = __fmaf_rn(t, t, acc);
+                t = x.z - y.z; acc = __fmaf_rn(t, t, acc);
+                t = x.w - y.w; acc = __fmaf_rn(t, t, acc);
+            }
+        }
+        acc += __shfl_xor(acc, 8, 16);
+        acc += __shfl_xor(acc, 4, 16);
+        acc += __shfl_xor(acc, 2, 16);
+        acc += __shfl_xor(acc, 1, 16);
+        if (e < count && l16 == 0) {
+            k0[e] = __float_as_uint(acc);
+            ii[e] = cii[e];
+            jj[e] = cjj[e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- select
+// Radix-select step over the 96-bit keys (k0, ii, jj): elements whose leading
+// sub-keys equal v0 (depth >= 1) and v1 (depth 2) take part; their sub-key at
+// `depth` contributes its bits [shift, shift + 11) to the histogram when its
+// higher bits equal `prefix` (prefix_bits of them).
+struct SelStep {
+    int depth;
+    uint32_t v0, v1;
+    int shift;
+    uint32_t mask;
+    int prefix_bits;
+    uint32_t prefix;
+};
+
+__device__ __forceinline__ bool sel_member(const SelStep& s, uint32_t a, uint32_t b, uint32_t c,
+                                           uint32_t* sub) {
+    if (s.depth >= 1 && a != s.v0) return false;
+    if (s.depth >= 2 && b != s.v1) return false;
+    const uint32_t x = s.depth == 0 ? a : (s.depth == 1 ? b : c);
+    if (s.prefix_bits > 0 && (x >> (32 - s.prefix_bits)) != s.prefix) return false;
+    *sub = x;
+    return true;
+}
+
+__global__ __launch_bounds__(WG) void acp_hist_kernel(
+    const uint32_t* __restrict__ k0, const uint32_t* __restrict__ ii,
+    const uint32_t* __restrict__ jj, int64_t count, SelStep s, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[NB];
+    for (int i = threadIdx.x; i < NB; i += WG) h[i] = 0;
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * WG) {
+        uint32_t x;
+        if (sel_member(s, k0[e], ii[e], jj[e], &x)) atomicAdd(&h[(x >> s.shift) & s.mask], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += WG)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+struct SelKey {
+    int depth;
+    uint32_t v0, v1, v2;
+};
+
+// (a, b, c) <= the selected key, comparing the first depth+1 sub-keys
+__device__ __forceinline__ bool key_le(const SelKey& K, uint32_t a, uint32_t b, uint32_t c) {
+    if (a != K.v0) return a < K.v0;
+    if (K.depth == 0) return true;
+    if (b != K.v1) return b < K.v1;
+    if (K.depth == 1) return true;
+    return c <= K.v2;
+}
+
+__global__ __launch_bounds__(WG) void acp_gather_kernel(
+    const uint32_t* __restrict__ k0, const uint32_t* __restrict__ ii,
+    const uint32_t* __restrict__ jj, int64_t count, SelKey K, uint32_t* __restrict__ ok0,
+    uint32_t* __restrict__ oii, uint32_t* __restrict__ ojj, int64_t cap,
+    unsigned long long* __restrict__ counter) {
+    for (int64_t base = (int64_t)blockIdx.x * WG; base < count; base += (int64_t)gridDim.x * WG) {
+        const int64_t e = base + threadIdx.x;
+        bool take = false;
+        uint32_t a = 0, b = 0, c = 0;
+        if (e < count) {
+            a = k0[e]; b = ii[e]; c = jj[e];
+            take = key_le(K, a, b, c);
+        }
+        const int64_t slot = wave_append_global(take, counter);
+        if (take && slot < cap) { ok0[slot] = a; oii[slot] = b; ojj[slot] = c; }
+    }
+}
+
+// Sorts `count` (<= 1024) keys by (k0, ii, jj) and writes the k results.
+__global__ __launch_bounds__(WG) void acp_final_kernel(
+    const uint32_t* __restrict__ k0, const uint32_t* __restrict__ ii,
+    const uint32_t* __restrict__ jj, int count, int64_t* __restrict__ out_pairs,
+    float* __restrict__ out_dist) {
+    __shared__ uint64_t hk[1024];
+    __shared__ uint32_t lk[1024];
+    int P = 1;
+    while (P < count) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += WG) {
+        if (i < count) {
+            hk[i] = ((uint64_t)k0[i] << 32) | ii[i];
+            lk[i] = jj[i];
+        } else {
+            hk[i] = ~0ull;
+            lk[i] = ~0u;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += WG) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const bool gt = hk[i] > hk[ixj] || (hk[i] == hk[ixj] && lk[i] > lk[ixj]);
+                    if (gt == up) {
+                        const uint64_t th = hk[i]; hk[i] = hk[ixj]; hk[ixj] = th;
+                        const uint32_t tl = lk[i]; lk[i] = lk[ixj]; lk[ixj] = tl;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < count; i += WG) {
+        out_pairs[2 * i] = (int64_t)(uint32_t)(hk[i] & 0xffffffffull);
+        out_pairs[2 * i + 1] = (int64_t)lk[i];
+        out_dist[i] = sqrtf(__uint_as_float((uint32_t)(hk[i] >> 32)));
+    }
+}
+
+// ---------------------------------------------------------------- host side
+struct DevBuf {
+    void* p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    void alloc(size_t bytes) {
+        if (p) { (void)hipFree(p); p = nullptr; }
+        PMLSH_HIP(hipMalloc(&p, bytes ? bytes : 1));
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Triplets {
+    DevBuf k0, ii, jj;
+    int64_t cap = 0;
+    void alloc(int64_t c) {
+        cap = c;
+        k0.alloc((size_t)c * 4);
+        ii.alloc((size_t)c * 4);
+        jj.alloc((size_t)c * 4);
+    }
+};
+
+int grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    g = std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
+    return (int)g;
+}
+
+// Device-wide selection of the need-th smallest key. With value_only, only the
+// first sub-key (the distance bits) is resolved.
+SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, int64_t count,
+                  int64_t need, bool value_only, uint32_t* dhist, hipStream_t st) {
+    SelKey K{0, 0, 0, 0};
+    uint32_t v[3] = {0, 0, 0};
+    std::vector<uint32_t> h(NB);
+    for (int depth = 0; depth < 3; ++depth) {
+        uint32_t prefix = 0;
+        int pbits = 0;
+        uint32_t last = 0;
+        for (int pass = 0; pass < 3; ++pass) {
+            const int width = pass < 2 ? 11 : 10;
+            const int shift = 32 - pbits - width;
+            SelStep s{depth, v[0], v[1], shift, (1u << width) - 1u, pbits, prefix};
+            PMLSH_HIP(hipMemsetAsync(dhist, 0, NB * sizeof(uint32_t), st));
+            hipLaunchKernelGGL(acp_hist_kernel, dim3(grid_for(count, WG * 16)), dim3(WG), 0, st,
+                               k0, ii, jj, count, s, dhist);
+            PMLSH_HIP(hipGetLastError());
+            PMLSH_HIP(hipMemcpyAsync(h.data(), dhist, NB * sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, st));
+            PMLSH_HIP(hipStreamSynchronize(st));
+            int64_t cum = 0;
+            int T = -1;
+            for (int b = 0; b < (1 << width); ++b) {
+                if (cum + h[b] >= need) { T = b; break; }
+                cum += h[b];
+            }
+            if (T < 0) fail(PMLSH_EDEVICE, "radix select lost elements");
+            need -= cum;
+            prefix = (prefix << width) | (uint32_t)T;
+            pbits += width;
+            last = h[T];
+        }
+        v[depth] = prefix;
+        K.depth = depth;
+        K.v0 = v[0];
+        K.v1 = v[1];
+        K.v2 = v[2];
+        if (value_only || (int64_t)last == need) return K;
+    }
+    return K;
+}
+
+}  // namespace
+
+void run_acp(const pmlsh_index* x, int k, double c, double confidence, double beta,
+             int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+             hipStream_t st) {
+    pmlsh_plan plan;
+    plan_params(x->n, x->m, k, c, confidence, beta, &plan);
+    const int64_t n = x->n;
+    const int L = x->leaf_size;
+    const int64_t NL = x->n_leaves;
+
+    DevBuf dhist, dcount;
+    dhist.alloc(NB * sizeof(uint32_t));
+    dcount.alloc(sizeof(unsigned long long));
+    auto reset_counter = [&] {
+        PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
+    };
+    auto read_counter = [&]() -> int64_t {
+        unsigned long long v = 0;
+        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        return (int64_t)v;
+    };
+
+    // ---- seeds: every within-leaf pair
+    std::vector<int64_t> seed_off(NL + 1, 0);
+    for (int64_t b = 0; b < NL; ++b) {
+        const int64_t cnt = std::min<int64_t>(L, n - b * L);
+        seed_off[b + 1] = seed_off[b] + cnt * (cnt - 1) / 2;
+    }
+    const int64_t n_seed = seed_off[NL];
+    Triplets seeds;
+    seeds.alloc(n_seed);
+    if (n_seed > 0) {
+        DevBuf doff;
+        doff.alloc((NL + 1) * sizeof(int64_t));
+        PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(acp_self_join_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
+                           x->d_pad, x->perm, n, L, doff.as<int64_t>(), seeds.k0.as<uint32_t>(),
+                           seeds.ii.as<uint32_t>(), seeds.jj.as<uint32_t>());
+        PMLSH_HIP(hipGetLastError());
+        PMLSH_HIP(hipStreamSynchronize(st));
+    }
+
+    // ---- ub: k-th smallest seed distance
+    double ub = HUGE_VAL;
+    if (n_seed >= k) {
+        SelKey K = select_kth(seeds.k0.as<uint32_t>(), seeds.ii.as<uint32_t>(),
+                              seeds.jj.as<uint32_t>(), n_seed, k, true, dhist.as<uint32_t>(), st);
+        uint32_t bits = K.v0;
+        float ub2;
+        std::memcpy(&ub2, &bits, 4);
+        ub = std::sqrt((double)ub2);
+    }
+    const double R = plan.t * ub;
+    const float R2 = std::isinf(R) ? INFINITY : (float)(R * R);
+    const float slack = (float)(1e-5 * (2.0 * x->coord_scale + (std::isinf(R) ? 0.0 : R)));
+    const float limit = std::isinf(R) ? INFINITY : (float)R + slack;
+
+    // ---- tiles surviving Mindist (Eq. 11)
+    const int64_t tiles_total = NL * (NL - 1) / 2;
+    int64_t n_tiles = 0;
+    DevBuf tiles;
+    if (tiles_total > 0) {
+        if (tiles_total > (int64_t(1) << 31) || NL > 65535)
+            fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
+        tiles.alloc((size_t)tiles_total * sizeof(int2));
+        reset_counter();
+        const int64_t leaf_base = x->level_begin[x->levels - 1];
+        NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
+                   x->num_pivots};
+        dim3 grid((unsigned)((NL + WG - 1) / WG), (unsigned)NL);
+        hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL, limit,
+                           tiles.as<int2>(), tiles_total,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        n_tiles = read_counter();
+    }
+
+    // ---- pair scan of the surviving tiles
+    constexpr int64_t kMaxCand = int64_t(1) << 28;
+    Triplets cand;
+    int64_t n_raw = 0;
+    if (n_tiles > 0) {
+        int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
+        const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 2 * 4;
+        PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            cand.alloc(cap);
+            reset_counter();
+            hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds,
+                               st, x->proj_hi, x->proj_lo, x->perm, n, L, tiles.as<int2>(),
+                               n_tiles, R2, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                               cand.jj.as<uint32_t>(), cap,
+                               static_cast<unsigned long long*>(dcount.p));
+            PMLSH_HIP(hipGetLastError());
+            n_raw = read_counter();
+            if (n_raw <= cap) break;
+            if (n_raw > kMaxCand)
+                fail(PMLSH_EUNSUPPORTED, "more than 2^28 candidate pairs pass the radius filter");
+            cap = n_raw;
+        }
+    }
+
+    // ---- budget T: keep the projected-nearest candidates
+    const int64_t keep = std::max<int64_t>(0, plan.acp_budget - n_seed);
+    int64_t n_keep = std::min(n_raw, keep);
+    Triplets kept;
+    const Triplets* cands = &cand;
+    if (n_raw > keep && keep > 0) {
+        SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                              cand.jj.as<uint32_t>(), n_raw, keep, false, dhist.as<uint32_t>(), st);
+        kept.alloc(keep);
+        reset_counter();
+        hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_raw, WG)), dim3(WG), 0, st,
+                           cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(), cand.jj.as<uint32_t>(),
+                           n_raw, K, kept.k0.as<uint32_t>(), kept.ii.as<uint32_t>(),
+                           kept.jj.as<uint32_t>(), keep,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        if (read_counter() != keep) fail(PMLSH_EDEVICE, "budget cut lost candidates");
+        cands = &kept;
+    }
+
+    // ---- verify the candidates; the pool is seeds followed by candidates
+    Triplets pool;
+    const int64_t n_pool = n_seed + n_keep;
+    pool.alloc(n_pool);
+    if (n_seed > 0) {
+        PMLSH_HIP(hipMemcpyAsync(pool.k0.p, seeds.k0.p, n_seed * 4, hipMemcpyDeviceToDevice, st));
+        PMLSH_HIP(hipMemcpyAsync(pool.ii.p, seeds.ii.p, n_seed * 4, hipMemcpyDeviceToDevice, st));
+        PMLSH_HIP(hipMemcpyAsync(pool.jj.p, seeds.jj.p, n_seed * 4, hipMemcpyDeviceToDevice, st));
+    }
+    if (n_keep > 0) {
+        hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(n_keep, WG / 16)), dim3(WG), 0, st,
+                           x->data, x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(),
+                           cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_seed,
+                           pool.ii.as<uint32_t>() + n_seed, pool.jj.as<uint32_t>() + n_seed);
+        PMLSH_HIP(hipGetLastError());
+    }
+    if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
+
+    // ---- top-k over the pool
+    SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                          n_pool, k, false, dhist.as<uint32_t>(), st);
+    Triplets top;
+    top.alloc(k);
+    reset_counter();
+    hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
+                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                       n_pool, K, top.k0.as<uint32_t>(), top.ii.as<uint32_t>(),
+                       top.jj.as<uint32_t>(), (int64_t)k,
+                       static_cast<unsigned long long*>(dcount.p));
+    PMLSH_HIP(hipGetLastError());
+    if (read_counter() != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+    hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
+                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs, out_dist);
+    PMLSH_HIP(hipGetLastError());
+    PMLSH_HIP(hipStreamSynchronize(st));
+
+    if (stats) {
+        stats->t = plan.t;
+        stats->ub = ub;
+        stats->budget = plan.acp_budget;
+        stats->n_seed = n_seed;
+        stats->n_cand_raw = n_raw;
+        stats->n_cand = n_keep;
+        stats->tiles_total = tiles_total;
+        stats->tiles_scanned = n_tiles;
+    }
+}
+
+}  // namespace pmlsh

@@ -1,0 +1,200 @@
+// extern "C" boundary of the PM-LSH library: argument validation (before any
+// HIP call), error codes, the thread-local error message, and the host-side
+// orchestration of the ANN batches.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace pmlsh {
+
+pmlsh_index* index_build(const pmlsh_build_args* a);
+void index_release(pmlsh_index* x);
+double index_default_r_min(const pmlsh_index* x, int64_t budget);
+void run_acp(const pmlsh_index* x, int k, double c, double confidence, double beta,
+             int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+             hipStream_t stream);
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+const char* error_cstr() { return g_error.c_str(); }
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+template <class F>
+int guarded(F&& fn) {
+    try {
+        fn();
+        return PMLSH_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host memory exhausted");
+        return PMLSH_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return PMLSH_EDEVICE;
+    } catch (...) {
+        set_error("unknown error");
+        return PMLSH_EDEVICE;
+    }
+}
+
+// Per-query workspace bytes of the ANN kernel and the batch that fits a cap.
+constexpr int64_t kWorkspaceCap = int64_t(4) << 30;
+
+void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
+             double confidence, double beta, double r_min, int64_t* out_ids,
+             float* out_dist, int32_t* out_stats, hipStream_t st) {
+    pmlsh_plan plan;
+    plan_params(x->n, x->m, k, c, confidence, beta, &plan);
+    if (!(r_min > 0.0)) r_min = index_default_r_min(x, plan.budget);
+    if (!std::isfinite(r_min)) fail(PMLSH_EINVAL, "r_min must be finite");
+    if (nq == 0) return;
+    const int64_t B = plan.budget;
+    const int64_t per_query = (int64_t)MP * 4 + 2 * x->n_leaves * 4 + B * 8 + 3 * (int64_t)k * 4;
+    int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query));
+    batch = std::min<int64_t>(batch, 65535);
+    void* ws = nullptr;
+    PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query), st));
+    char* base = static_cast<char*>(ws);
+    float* qproj = reinterpret_cast<float*>(base);
+    int32_t* front = reinterpret_cast<int32_t*>(base + batch * MP * 4);
+    int32_t* cpos = front + batch * 2 * x->n_leaves;
+    float* cdist = reinterpret_cast<float*>(cpos + batch * B);
+    int32_t* topk = reinterpret_cast<int32_t*>(cdist + batch * B);
+    try {
+        for (int64_t q0 = 0; q0 < nq; q0 += batch) {
+            const int64_t nb = std::min(batch, nq - q0);
+            const float* qb = queries + q0 * x->d;
+            launch_project(qb, nb, x->d, x->d, x->hash, qproj, nullptr, st);
+            AnnLaunch L{};
+            L.idx = x;
+            L.queries = qb;
+            L.qproj = qproj;
+            L.nq = nb;
+            L.k = k;
+            L.c = c;
+            L.t = plan.t;
+            L.r_min = r_min;
+            L.budget = B;
+            L.ws_front = front;
+            L.ws_cpos = cpos;
+            L.ws_cdist = cdist;
+            L.ws_topk = topk;
+            L.out_ids = out_ids + q0 * k;
+            L.out_dist = out_dist + q0 * k;
+            L.out_stats = out_stats ? out_stats + q0 * 4 : nullptr;
+            launch_ann(L, st);
+        }
+    } catch (...) {
+        (void)hipFreeAsync(ws, st);
+        throw;
+    }
+    PMLSH_HIP(hipFreeAsync(ws, st));
+}
+
+}  // namespace pmlsh
+
+using namespace pmlsh;
+
+extern "C" {
+
+int pmlsh_build(const pmlsh_build_args* args, pmlsh_index** out) {
+    return guarded([&] {
+        if (!out) fail(PMLSH_EINVAL, "out is NULL");
+        *out = index_build(args);
+    });
+}
+
+void pmlsh_free(pmlsh_index* index) { index_release(index); }
+
+int pmlsh_plan_params(int64_t n, int32_t m, int32_t k, double c, double confidence,
+                      double beta, pmlsh_plan* out) {
+    return guarded([&] {
+        if (!out) fail(PMLSH_EINVAL, "out is NULL");
+        pmlsh_plan p;
+        plan_params(n, m, k, c, confidence, beta, &p);
+        *out = p;
+    });
+}
+
+int pmlsh_default_r_min(const pmlsh_index* index, int64_t budget, double* r_min) {
+    return guarded([&] {
+        if (!index || !r_min) fail(PMLSH_EINVAL, "NULL argument");
+        if (budget < 1) fail(PMLSH_EINVAL, "budget must be >= 1");
+        *r_min = index_default_r_min(index, budget);
+    });
+}
+
+int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq, int32_t k,
+              double c, double confidence, double beta, double r_min, int64_t* out_ids,
+              float* out_dist, int32_t* out_stats, void* stream) {
+    return guarded([&] {
+        if (!index) fail(PMLSH_EINVAL, "index is NULL");
+        if (nq < 0) fail(PMLSH_EINVAL, "nq must be >= 0");
+        if (nq > 0 && (!queries || !out_ids || !out_dist))
+            fail(PMLSH_EINVAL, "queries and outputs must not be NULL");
+        if (k < 1) fail(PMLSH_EINVAL, "k must be >= 1");
+        if (k > index->n) fail(PMLSH_EINVAL, "k must be <= n");
+        if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
+        if (index->d_pad > 8192) fail(PMLSH_EUNSUPPORTED, "ANN supports d <= 8192");
+        if (std::isnan(r_min)) fail(PMLSH_EINVAL, "r_min is NaN");
+        run_ann(index, queries, nq, k, c, confidence, beta, r_min, out_ids, out_dist,
+                out_stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_acp(const pmlsh_index* index, int32_t k, double c, double confidence,
+              double beta, int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+              void* stream) {
+    return guarded([&] {
+        if (!index) fail(PMLSH_EINVAL, "index is NULL");
+        if (!out_pairs || !out_dist) fail(PMLSH_EINVAL, "outputs must not be NULL");
+        if (index->n < 2) fail(PMLSH_EINVAL, "ACP needs n >= 2");
+        if (k < 1) fail(PMLSH_EINVAL, "k must be >= 1");
+        const double pairs = (double)index->n * (double)(index->n - 1) / 2.0;
+        if ((double)k > pairs) fail(PMLSH_EINVAL, "k must be <= n(n-1)/2");
+        if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
+        run_acp(index, k, c, confidence, beta, out_pairs, out_dist, stats,
+                static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_get_index_info(const pmlsh_index* index, pmlsh_index_info* out) {
+    return guarded([&] {
+        if (!index || !out) fail(PMLSH_EINVAL, "NULL argument");
+        pmlsh_index_info i{};
+        i.n = index->n;
+        i.d = index->d;
+        i.m = index->m;
+        i.leaf_size = index->leaf_size;
+        i.fanout = index->fanout;
+        i.num_pivots = index->num_pivots;
+        i.levels = index->levels;
+        i.n_leaves = index->n_leaves;
+        i.n_nodes = index->n_nodes;
+        i.sample_size = (int64_t)index->sample_sorted.size();
+        i.device_bytes = index->device_bytes;
+        *out = i;
+    });
+}
+
+int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm, int64_t* offsets) {
+    return guarded([&] {
+        if (!index || !perm || !offsets) fail(PMLSH_EINVAL, "NULL argument");
+        std::memcpy(perm, index->perm_host.data(), index->perm_host.size() * sizeof(int32_t));
+        const int64_t L = index->leaf_size;
+        for (int64_t b = 0; b <= index->n_leaves; ++b) offsets[b] = std::min(index->n, b * L);
+    });
+}
+
+const char* pmlsh_last_error(void) { return error_cstr(); }
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal declarations shared by the host-side translation units of the
+// PM-LSH library: error reporting, the index object and the device layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pmlsh.h"
+
+namespace pmlsh {
+
+// Projected coordinates are padded from m to MP floats (zero pad lanes).
+constexpr int MP = 16;
+
+// Thread-local error message returned by pmlsh_last_error().
+void set_error(const std::string& msg);
+void clear_error();
+const char* error_cstr();
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+// Throws pmlsh::Error; caught at the C boundary.
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define PMLSH_HIP(call)                                                          \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            ::pmlsh::fail(e_ == hipErrorOutOfMemory ? PMLSH_ENOMEM : PMLSH_EDEVICE, \
+                          std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------- planner
+double chi2_cdf(double x, int m);
+double chi2_upper_quantile(double alpha, int m);
+uint64_t splitmix64(uint64_t x);
+void plan_params(int64_t n, int m, int k, double c, double confidence,
+                 double beta, pmlsh_plan* out);  // throws on invalid input
+
+// ---------------------------------------------------------------- tree
+// Flattened PM-tree, structure-of-arrays over all nodes; levels are stored
+// top-down and contiguously, level l holding nodes
+// [level_begin[l], level_begin[l+1]). Leaves form the last level and hold
+// the contiguous point range [child_begin, child_end) of the leaf order.
+struct HostTree {
+    int levels = 0;
+    int64_t n_nodes = 0;
+    std::vector<int64_t> level_begin;     // levels + 1
+    std::vector<float> centre;            // MP x n_nodes (dimension-major)
+    std::vector<float> radius;            // n_nodes
+    std::vector<float> hr_min, hr_max;    // s x n_nodes
+    std::vector<int32_t> child_begin, child_end;
+    std::vector<float> pivots;            // s x MP
+    std::vector<int32_t> perm;            // leaf position -> original id
+    float coord_scale = 0.f;              // max ||o'|| + max ||p_i||
+};
+
+// Bulk-loads the tree over projected points proj (n x MP, original order).
+void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
+                int num_pivots, HostTree* out);
+
+// ---------------------------------------------------------------- index
+struct DeviceTree {
+    float* centre = nullptr;
+    float* radius = nullptr;
+    float* hr_min = nullptr;
+    float* hr_max = nullptr;
+    int32_t* child_begin = nullptr;
+    int32_t* child_end = nullptr;
+    float* pivots = nullptr;
+};
+
+}  // namespace pmlsh
+
+struct pmlsh_index {
+    int64_t n = 0;
+    int d = 0, d_pad = 0, m = 0;
+    int leaf_size = 0, fanout = 0, num_pivots = 0, levels = 0;
+    int64_t n_leaves = 0, n_nodes = 0;
+    int device = 0;
+    // device buffers, all in leaf order
+    float* data = nullptr;       // n x d_pad, zero padded
+    float* proj_hi = nullptr;    // n x MP: FP32 rounding of the FP64 projection
+    float* proj_lo = nullptr;    // n x MP: FP32 rounding of (projection - hi)
+    int32_t* perm = nullptr;     // leaf position -> id
+    int32_t* inv_perm = nullptr; // id -> leaf position
+    float* hash = nullptr;       // MP x d, zero rows beyond m
+    pmlsh::DeviceTree tree;
+    int64_t device_bytes = 0;
+    // host copies
+    std::vector<int64_t> level_begin;
+    std::vector<int32_t> perm_host;
+    std::vector<double> sample_sorted;   // ascending pair distances (r_min rule)
+    double kappa = 0.9;
+    float coord_scale = 0.f;
+};
+
+namespace pmlsh {
+
+// ---------------------------------------------------------------- kernels
+// Launch wrappers (defined in the .hip translation units). All take the
+// stream the work is enqueued on and throw on launch failure.
+void launch_project(const float* x, int64_t rows, int d, int64_t ld,
+                    const float* hash, float* out_hi, float* out_lo,
+                    hipStream_t stream);
+void launch_gather_rows(const float* src, int d, int64_t ld_src, const int32_t* perm,
+                        int64_t rows, float* dst, int d_pad, hipStream_t stream);
+void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
+                        float* dst, hipStream_t stream);
+void launch_pair_dist_f64(const float* x, int d, int64_t ld, const int64_t* pairs,
+                          int64_t count, double* out, hipStream_t stream);
+
+struct AnnLaunch {
+    const pmlsh_index* idx;
+    const float* queries;   // nq x d (caller layout)
+    const float* qproj;     // nq x MP
+    int64_t nq;
+    int k;
+    double c, t, r_min;
+    int64_t budget;
+    int32_t* ws_front;      // nq x 2 x n_leaves
+    int32_t* ws_cpos;       // nq x budget
+    float* ws_cdist;        // nq x budget
+    int32_t* ws_topk;       // nq x 3 x k
+    int64_t* out_ids;
+    float* out_dist;
+    int32_t* out_stats;
+};
+void launch_ann(const AnnLaunch& a, hipStream_t stream);
+int ann_lds_bytes(int d_pad);
+
+}  // namespace pmlsh

@@ -1,0 +1,158 @@
+// Projection and layout kernels (gfx950).
+//
+// project_kernel computes o' = (a_1.o, ..., a_m.o) (Eq. 3, Section 3.2) for a
+// block of rows with the FP64 matrix cores (v_mfma_f64_16x16x4f64): FP32
+// inputs are widened to FP64, accumulated in FP64 and the result is stored as
+// the FP32 rounding `hi` plus the FP32 rounding of the remainder `lo`, so
+// hi + lo carries the projection to ~2^-48 relative. The hash matrix is padded
+// to 16 rows with zeros (m <= 16), which fills the 16-wide MFMA tile.
+//
+// One workgroup (4 waves) projects 64 rows; each wave owns a 16 x 16 output
+// tile (16 rows x 16 hash functions). Rows and hash columns are staged through
+// LDS in 64-column chunks with coalesced loads; the row stride of 65 floats
+// keeps the column-wise MFMA operand reads free of bank conflicts.
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace pmlsh {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int PJ_ROWS = 64;
+constexpr int PJ_KC = 64;
+
+__global__ __launch_bounds__(256) void project_kernel(
+    const float* __restrict__ x, int64_t rows, int d, int64_t ld,
+    const float* __restrict__ hash, float* __restrict__ out_hi,
+    float* __restrict__ out_lo) {
+    __shared__ float xs[PJ_ROWS][PJ_KC + 1];
+    __shared__ float hs[MP][PJ_KC + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * PJ_ROWS;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < d; k0 += PJ_KC) {
+        for (int i = tid; i < PJ_ROWS * PJ_KC; i += 256) {
+            const int r = i / PJ_KC, c = i % PJ_KC;
+            const int64_t gr = row0 + r;
+            const int gc = k0 + c;
+            xs[r][c] = (gr < rows && gc < d) ? x[gr * ld + gc] : 0.f;
+        }
+        for (int i = tid; i < MP * PJ_KC; i += 256) {
+            const int r = i / PJ_KC, c = i % PJ_KC;
+            const int gc = k0 + c;
+            hs[r][c] = gc < d ? hash[(int64_t)r * d + gc] : 0.f;
+        }
+        __syncthreads();
+        // A operand: row (lane % 16) of this wave's tile, k = lane / 16;
+        // B operand: hash function (lane % 16), k = lane / 16.
+#pragma unroll 4
+        for (int kk = 0; kk < PJ_KC; kk += 4) {
+            const double a = (double)xs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
+            const double b = (double)hs[lane & 15][kk + (lane >> 4)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // result element i of a lane: row 4*(lane/16) + i, hash function lane % 16
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t gr = row0 + wave * 16 + 4 * (lane >> 4) + i;
+        const int col = lane & 15;
+        if (gr < rows) {
+            const double v = acc[i];
+            const float hi = (float)v;
+            out_hi[gr * MP + col] = hi;
+            if (out_lo) out_lo[gr * MP + col] = (float)(v - (double)hi);
+        }
+    }
+}
+
+// dst row j = src row perm[j], zero padded from d to d_pad columns.
+__global__ __launch_bounds__(256) void gather_rows_kernel(
+    const float* __restrict__ src, int d, int64_t ld_src,
+    const int32_t* __restrict__ perm, int64_t rows, float* __restrict__ dst,
+    int d_pad) {
+    const int64_t total = rows * (int64_t)d_pad;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / d_pad;
+        const int c = (int)(e - j * d_pad);
+        dst[e] = c < d ? src[(int64_t)perm[j] * ld_src + c] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void gather_proj_kernel(
+    const float* __restrict__ src, const int32_t* __restrict__ perm,
+    int64_t rows, float* __restrict__ dst) {
+    const int64_t total = rows * MP;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / MP;
+        dst[e] = src[(int64_t)perm[j] * MP + (e - j * MP)];
+    }
+}
+
+// FP64 Euclidean distance of row pairs (one wave per pair).
+__global__ __launch_bounds__(256) void pair_dist_f64_kernel(
+    const float* __restrict__ x, int d, int64_t ld,
+    const int64_t* __restrict__ pairs, int64_t count, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= count) return;
+    const float* a = x + pairs[2 * p] * ld;
+    const float* b = x + pairs[2 * p + 1] * ld;
+    double s = 0.0;
+    for (int c = lane; c < d; c += 64) {
+        const double t = (double)a[c] - (double)b[c];
+        s = fma(t, t, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) out[p] = sqrt(s);
+}
+
+int grid_for(int64_t work) {
+    int64_t g = (work + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+void launch_project(const float* x, int64_t rows, int d, int64_t ld,
+                    const float* hash, float* out_hi, float* out_lo,
+                    hipStream_t stream) {
+    if (rows <= 0) return;
+    const int64_t blocks = (rows + PJ_ROWS - 1) / PJ_ROWS;
+    hipLaunchKernelGGL(project_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       x, rows, d, ld, hash, out_hi, out_lo);
+    PMLSH_HIP(hipGetLastError());
+}
+
+void launch_gather_rows(const float* src, int d, int64_t ld_src, const int32_t* perm,
+                        int64_t rows, float* dst, int d_pad, hipStream_t stream) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(rows * d_pad)), dim3(256), 0,
+                       stream, src, d, ld_src, perm, rows, dst, d_pad);
+    PMLSH_HIP(hipGetLastError());
+}
+
+void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
+                        float* dst, hipStream_t stream) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(gather_proj_kernel, dim3(grid_for(rows * MP)), dim3(256), 0,
+                       stream, src, perm, rows, dst);
+    PMLSH_HIP(hipGetLastError());
+}
+
+void launch_pair_dist_f64(const float* x, int d, int64_t ld, const int64_t* pairs,
+                          int64_t count, double* out, hipStream_t stream) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(pair_dist_f64_kernel, dim3((unsigned)((count + 3) / 4)), dim3(256),
+                       0, stream, x, d, ld, pairs, count, out);
+    PMLSH_HIP(hipGetLastError());
+}
+
+}  // namespace pmlsh

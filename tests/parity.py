@@ -1,0 +1,70 @@
+"""Shared helpers of the GPU parity tests: run the oracle and the library on
+the same seeded inputs and compare them under the tolerance rule.
+
+Rule (ids bit-exact except near ties; distances to 1e-5 relative):
+  * a query whose smallest oracle decision margin exceeds FRAGILE must come
+    back with exactly the oracle's ids, in order, the same exit kind, number
+    of range queries and candidate count, and distances within TOL;
+  * a fragile query (some comparison within FRAGILE of its threshold, where
+    FP32 and FP64 may decide differently) must return distinct ids, sorted by
+    (distance, id), whose distances agree with their FP64 exact distances to
+    TOL, and share all but at most one id with the oracle.
+"""
+
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+from oracle import ann as oann
+from oracle import chi2, rmin
+
+TOL = 1e-5          # relative distance tolerance (FP32 vs FP64)
+FRAGILE = 1e-5      # decision margin below which FP32 may legitimately differ
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_ann(D, A, Q, k, c, confidence, beta, r_min, Dp=None):
+    n = D.shape[0]
+    t = chi2.radius_factor(1 - confidence, A.shape[0])
+    if beta < 0:
+        beta = chi2.default_beta(1 - confidence, c, A.shape[0])
+    B = chi2.ann_budget(beta, n, k)
+    return oann.run(D, A, Q, k=k, c=c, t=t, budget=B, r_min=r_min, Dp=Dp), B
+
+
+def compare_ann(D, Q, res, ids, dist, stats=None, max_fragile_frac=0.05):
+    """res: oracle results; ids/dist/stats: library outputs as NumPy arrays."""
+    n_fragile = 0
+    for qi, r in enumerate(res):
+        gi = ids[qi].tolist()
+        gd = dist[qi].astype(np.float64)
+        if r.margin > FRAGILE:
+            assert gi == r.ids.tolist(), (qi, gi, r.ids.tolist(), r.margin_kind, r.margin)
+            np.testing.assert_allclose(gd, r.dist, rtol=TOL, atol=1e-6,
+                                       err_msg=f"query {qi}")
+            if stats is not None:
+                assert stats[qi, 0] == r.rounds, (qi, stats[qi], r.rounds)
+                assert stats[qi, 1] == r.n_cand, (qi, stats[qi], r.n_cand)
+                assert stats[qi, 2] == r.exit_kind, (qi, stats[qi], r.exit_kind)
+        else:
+            n_fragile += 1
+            assert len(set(gi)) == len(gi)
+            assert min(gi) >= 0 and max(gi) < D.shape[0]
+            ex = oann.exact_dist(D, Q[qi], np.asarray(gi))
+            np.testing.assert_allclose(gd, ex, rtol=TOL, atol=1e-6)
+            key = list(zip(gd.tolist(), gi))
+            assert key == sorted(key)
+            assert len(set(gi) & set(r.ids.tolist())) >= len(gi) - 1
+    assert n_fragile <= max(1, max_fragile_frac * len(res)), n_fragile
+    return n_fragile
+
+
+def oracle_r_min(D, seed, budget):
+    return rmin.r_min(D, seed, budget)

@@ -1,0 +1,151 @@
+"""GPU parity of (c,k)-ACP through the C ABI against the FP64 oracle.
+
+The oracle takes the index's leaf partition as data (pmlsh_index_export_leaves)
+and finds candidates by brute force over all pairs, so a pair lost by the
+Mindist tile pruning shows up as a mismatch.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import pdist
+
+import synth
+from oracle import acp as oacp
+from oracle import ann as oann
+from oracle import chi2
+from parity import FRAGILE, TOL, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2107_05537_amd as pm
+    pm.load_library()
+    return pm
+
+
+def _index(pm, D, A, **kw):
+    dev = torch.device("cuda", 0)
+    return pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev), **kw)
+
+
+def _oracle(idx, D, A, k, c, conf, beta):
+    perm, offsets = idx.export_leaves()
+    m = A.shape[0]
+    t = chi2.radius_factor(1 - conf, m)
+    if beta < 0:
+        beta = chi2.default_beta(1 - conf, c, m)
+    T = chi2.acp_budget(beta, D.shape[0], k)
+    return oacp.run(D, oann.project(D, A), perm, offsets, k=k, t=t, T=T), T
+
+
+def _compare(res, pairs, dist, st):
+    pairs = pairs.cpu().numpy()
+    dist = dist.cpu().numpy().astype(np.float64)
+    assert st["n_seed"] == res.n_seed
+    if res.margin > FRAGILE:
+        assert pairs.tolist() == res.pairs.tolist()
+        np.testing.assert_allclose(dist, res.dist, rtol=TOL, atol=1e-7)
+        assert st["n_cand_raw"] == res.n_cand_raw
+        assert st["n_cand"] == res.n_cand
+        assert st["ub"] == pytest.approx(res.ub, rel=TOL)
+    else:
+        say("fragile ACP case:", res.margin_kind, res.margin)
+        assert np.all(pairs[:, 0] < pairs[:, 1])
+        assert len(set(map(tuple, pairs.tolist())) & set(map(tuple, res.pairs.tolist()))) \
+            >= len(pairs) - 1
+
+
+def test_planted_small():
+    pm = _gpu()
+    say("case: ACP planted n=3000 d=32")
+    w = synth.planted_pairs(n=3000, d=32, n_centres=10)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A)
+    for k in (1, 10, 30):
+        pairs, dist, st = idx.acp(k, c=1.5)
+        torch.cuda.synchronize()
+        res, T = _oracle(idx, D, A, k, 1.5, 1 - 1 / math.e, -1.0)
+        say("k", k, "stats", st)
+        assert st["budget"] == T
+        _compare(res, pairs, dist, st)
+
+
+def test_uniform_many_leaf_pairs():
+    """Structureless data: the radius filter admits many cross-leaf pairs."""
+    pm = _gpu()
+    say("case: ACP uniform n=2500 d=12")
+    w = synth.uniform_cube(3, 2500, 12, 1)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A, leaf_size=32, fanout=4)
+    pairs, dist, st = idx.acp(20, c=1.5)
+    torch.cuda.synchronize()
+    res, _ = _oracle(idx, D, A, 20, 1.5, 1 - 1 / math.e, -1.0)
+    say("stats", st, "oracle raw", res.n_cand_raw)
+    assert st["tiles_scanned"] < st["tiles_total"]
+    _compare(res, pairs, dist, st)
+
+
+def test_single_leaf_is_exact():
+    pm = _gpu()
+    say("case: ACP single leaf")
+    rng = np.random.Generator(np.random.PCG64(8))
+    D = rng.standard_normal((200, 40)).astype(np.float32)
+    A = rng.standard_normal((15, 40)).astype(np.float32)
+    idx = _index(pm, D, A, leaf_size=256)
+    pairs, dist, st = idx.acp(50)
+    dv = pdist(D.astype(np.float64))
+    ii, jj = np.triu_indices(200, k=1)
+    o = np.lexsort((jj, ii, dv))[:50]
+    assert pairs.cpu().numpy().tolist() == np.stack([ii[o], jj[o]], 1).tolist()
+    np.testing.assert_allclose(dist.cpu().numpy(), dv[o], rtol=TOL)
+    assert st["n_cand_raw"] == 0 and st["tiles_total"] == 0
+
+
+def test_budget_binding_and_unbounded_ub():
+    pm = _gpu()
+    say("case: ACP budget cut / ub = inf")
+    rng = np.random.Generator(np.random.PCG64(12))
+    D = rng.standard_normal((300, 16)).astype(np.float32)
+    A = rng.standard_normal((15, 16)).astype(np.float32)
+    idx = _index(pm, D, A, leaf_size=8, fanout=2)
+    # tiny beta: T = k + ceil(beta n(n-1)/2) below the candidate count
+    pairs, dist, st = idx.acp(5, beta=2e-3)
+    res, T = _oracle(idx, D, A, 5, 1.5, 1 - 1 / math.e, 2e-3)
+    say("budget", T, "stats", st, "oracle", res.n_seed, res.n_cand_raw, res.n_cand)
+    assert res.n_seed + res.n_cand_raw > T
+    _compare(res, pairs, dist, st)
+    # k above the number of seed pairs: ub = inf, every cross pair is a candidate
+    n_seed = st["n_seed"]
+    k = n_seed + 10
+    if k <= 1024:
+        pairs, dist, st = idx.acp(k, beta=1.0)
+        res, _ = _oracle(idx, D, A, k, 1.5, 1 - 1 / math.e, 1.0)
+        assert math.isinf(st["ub"])
+        _compare(res, pairs, dist, st)
+
+
+def test_acp_scale_planted():
+    """200,000 x 512 with 2,000 planted near-duplicates: the k closest pairs
+    are the k closest planted pairs (each ~0.023 apart, every other pair
+    several units apart)."""
+    pm = _gpu()
+    say("case: ACP scale n=200000 d=512")
+    w = synth.planted_pairs()
+    D, A, planted = w["D"], w["A"], w["pairs"]
+    idx = _index(pm, D, A)
+    pd_ = np.sqrt(((D[planted[:, 0]].astype(np.float64) - D[planted[:, 1]]) ** 2).sum(1))
+    order = np.lexsort((planted[:, 1], planted[:, 0], pd_))
+    for k in (1, 10, 100):
+        pairs, dist, st = idx.acp(k, c=1.5)
+        torch.cuda.synchronize()
+        say("k", k, "stats", st)
+        got = pairs.cpu().numpy()
+        assert got.tolist() == planted[order[:k]].tolist()
+        np.testing.assert_allclose(dist.cpu().numpy(), pd_[order[:k]], rtol=TOL)

@@ -1,0 +1,223 @@
+"""GPU parity of (c,k)-ANN through the C ABI against the FP64 oracle.
+
+Every case runs the library (pmlsh_build + pmlsh_ann on the GPU) and the
+oracle on the same seeded inputs and compares them with the rule in
+tests/parity.py. Sizes span many leaves and tiles with ragged tails; edge
+cases cover tiny and degenerate inputs, ties, multi-round searches and budgets
+larger than one LDS sort.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import brute
+from parity import compare_ann, oracle_ann, oracle_r_min, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2107_05537_amd as pm
+    pm.load_library()
+    return pm
+
+
+def _run(pm, D, A, Q, k, c, conf, beta, r_min, **build_kw):
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev), **build_kw)
+    ids, dist, st = idx.ann(torch.from_numpy(Q).to(dev), k, c=c, confidence=conf,
+                            beta=beta, r_min=r_min, stats=True)
+    torch.cuda.synchronize()
+    return idx, ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def parity_wl():
+    return synth.parity()
+
+
+def test_parity_workload_full(parity_wl):
+    """10,000 x 128, 100 queries, k=10, c=1.5, confidence 0.9, beta 0.1."""
+    pm = _gpu()
+    w = parity_wl
+    D, A, Q = w["D"], w["A"], w["Q"]
+    say("case: parity workload n=10000 d=128 nq=100")
+    res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=1.0)   # B only
+    r0 = oracle_r_min(D, 0x5EED, B)
+    res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=r0)
+    idx, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.1, r0)
+    # the library's own r_min rule reproduces the oracle's
+    assert idx.default_r_min(B) == pytest.approx(r0, rel=1e-12)
+    nf = compare_ann(D, Q, res, ids, dist, st)
+    say("fragile queries:", nf)
+    # default r_min (0) gives the same answers as passing it explicitly
+    ids2, dist2 = idx.ann(torch.from_numpy(Q).cuda(), 10, c=1.5, confidence=0.9, beta=0.1)
+    assert np.array_equal(ids2.cpu().numpy(), ids)
+
+
+def test_exact_special_case(parity_wl):
+    """B = n and an unbounded first radius: exact kNN, ties by id."""
+    pm = _gpu()
+    w = parity_wl
+    D, A, Q = w["D"], w["A"], w["Q"][:40]
+    say("case: exact special case")
+    _, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 1.0, 1e30)
+    eid, ed = brute.knn(D, Q, 10)
+    assert np.array_equal(ids, eid)
+    np.testing.assert_allclose(dist, ed, rtol=1e-5)
+    assert np.all(st[:, 2] == 2) and np.all(st[:, 1] == D.shape[0])
+
+
+@pytest.mark.parametrize("scale,beta,k", [(0.05, 0.1, 10), (0.3, 0.02, 1), (0.5, 0.05, 100)])
+def test_multi_round_and_line4(parity_wl, scale, beta, k):
+    """Small first radius: several range queries, line-4 and budget exits."""
+    pm = _gpu()
+    w = parity_wl
+    D, A, Q = w["D"], w["A"], w["Q"][:60]
+    say(f"case: multi-round scale={scale} beta={beta} k={k}")
+    res, B = oracle_ann(D, A, Q, k, 1.5, 0.9, beta, r_min=1.0)
+    r0 = scale * oracle_r_min(D, 7, B)
+    res, _ = oracle_ann(D, A, Q, k, 1.5, 0.9, beta, r_min=r0)
+    _, ids, dist, st = _run(pm, D, A, Q, k, 1.5, 0.9, beta, r0)
+    compare_ann(D, Q, res, ids, dist, st)
+    kinds = {r.exit_kind for r in res}
+    rounds = max(r.rounds for r in res)
+    say("exit kinds", kinds, "max rounds", rounds)
+    assert rounds >= 2
+
+
+def test_budget_larger_than_one_sort(parity_wl):
+    """B = 4010 > 2048: the radix-select refinement and the top-k selection
+    over a candidate set larger than one LDS sort."""
+    pm = _gpu()
+    w = parity_wl
+    D, A, Q = w["D"], w["A"], w["Q"][:30]
+    say("case: B > CAP")
+    res, B = oracle_ann(D, A, Q, 50, 1.5, 0.9, 0.4, r_min=1e30)
+    assert B == 4050
+    _, ids, dist, st = _run(pm, D, A, Q, 50, 1.5, 0.9, 0.4, 1e30)
+    compare_ann(D, Q, res, ids, dist, st)
+
+
+@pytest.mark.parametrize("n,d,m,leaf,fan,piv", [
+    (3001, 130, 7, 16, 4, 0),      # ragged n and d, deep tree, no pivots
+    (5000, 64, 15, 256, 64, 8),    # wide leaves and fanout, 8 pivots
+    (777, 33, 16, 8, 2, 3),        # binary inner levels, d not a multiple of 4
+    (50, 16, 15, 64, 16, 5),       # a single leaf
+])
+def test_shapes(n, d, m, leaf, fan, piv):
+    pm = _gpu()
+    say(f"case: shape n={n} d={d} m={m} L={leaf} F={fan} s={piv}")
+    rng = np.random.Generator(np.random.PCG64(n + d))
+    cen = rng.standard_normal((20, d)).astype(np.float32) * 2
+    lab = rng.integers(0, 20, n)
+    D = (cen[lab] + 0.4 * rng.standard_normal((n, d))).astype(np.float32)
+    Q = (cen[rng.integers(0, 20, 25)] + 0.4 * rng.standard_normal((25, d))).astype(np.float32)
+    A = rng.standard_normal((m, d)).astype(np.float32)
+    k = min(10, n)
+    res, B = oracle_ann(D, A, Q, k, 1.5, 0.9, 0.05, r_min=1.0)
+    r0 = oracle_r_min(D, 3, B)
+    res, _ = oracle_ann(D, A, Q, k, 1.5, 0.9, 0.05, r_min=r0)
+    idx, ids, dist, st = _run(pm, D, A, Q, k, 1.5, 0.9, 0.05, r0, leaf_size=leaf,
+                              fanout=fan, num_pivots=piv, sample_seed=3)
+    info = idx.info()
+    say("levels", info["levels"], "leaves", info["n_leaves"])
+    compare_ann(D, Q, res, ids, dist, st)
+
+
+def test_ties_duplicates_and_self_queries():
+    """Exact duplicate points (equal projected and exact distances: ties go to
+    the smaller id) and queries that are data points (distance 0)."""
+    pm = _gpu()
+    say("case: duplicates")
+    rng = np.random.Generator(np.random.PCG64(99))
+    base = rng.standard_normal((300, 24)).astype(np.float32)
+    D = np.concatenate([base, base[:150], base[:50]])     # ids 300.. duplicate 0..
+    perm = rng.permutation(D.shape[0])
+    D = D[perm]
+    A = rng.standard_normal((15, 24)).astype(np.float32)
+    Q = np.concatenate([D[:10], rng.standard_normal((10, 24)).astype(np.float32)])
+    res, B = oracle_ann(D, A, Q, 7, 1.5, 0.9, 0.1, r_min=1e30)
+    _, ids, dist, st = _run(pm, D, A, Q, 7, 1.5, 0.9, 0.1, 1e30, leaf_size=16)
+    # duplicates tie exactly in FP32 as in FP64, so both sides break the tie
+    # on the id: the answers must agree id for id
+    compare_ann(D, Q, res, ids, dist, st, max_fragile_frac=1.0)
+    assert np.array_equal(ids, np.stack([r.ids for r in res]))
+    assert np.all(dist[:10, 0] == 0)
+
+
+def test_tiny_inputs():
+    pm = _gpu()
+    say("case: tiny")
+    rng = np.random.Generator(np.random.PCG64(5))
+    D = rng.standard_normal((1, 8)).astype(np.float32)
+    A = rng.standard_normal((15, 8)).astype(np.float32)
+    Q = rng.standard_normal((3, 8)).astype(np.float32)
+    _, ids, dist, st = _run(pm, D, A, Q, 1, 1.5, 0.9, -1.0, 0.0)
+    assert np.all(ids == 0)
+    np.testing.assert_allclose(dist[:, 0], np.sqrt(((Q - D[0]) ** 2).sum(1)), rtol=1e-5)
+    # k = n, several rounds from a tiny radius
+    D = rng.standard_normal((9, 8)).astype(np.float32)
+    res, B = oracle_ann(D, A, Q, 9, 2.0, 0.9, 0.0, r_min=1e-3)
+    _, ids, dist, st = _run(pm, D, A, Q, 9, 2.0, 0.9, 0.0, 1e-3)
+    compare_ann(D, Q, res, ids, dist, st)
+
+
+def test_empty_batch_and_errors(parity_wl):
+    pm = _gpu()
+    w = parity_wl
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(w["D"][:500]).to(dev), torch.from_numpy(w["A"]).to(dev))
+    ids, dist = idx.ann(torch.empty((0, 128), device=dev), 5)
+    assert ids.shape == (0, 5)
+    with pytest.raises(pm.PmlshError) as e:
+        idx.ann(torch.zeros((2, 128), device=dev), 501)
+    assert e.value.code == pm.EINVAL
+    with pytest.raises(pm.PmlshError) as e:
+        idx.ann(torch.zeros((2, 128), device=dev), 5, c=0.5)
+    assert e.value.code == pm.EINVAL
+
+
+def test_deterministic(parity_wl):
+    pm = _gpu()
+    w = parity_wl
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(w["D"]).to(dev), torch.from_numpy(w["A"]).to(dev))
+    Q = torch.from_numpy(w["Q"]).to(dev)
+    a = idx.ann(Q, 10, confidence=0.9, beta=0.1, stats=True)
+    b = idx.ann(Q, 10, confidence=0.9, beta=0.1, stats=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_headline_scale_sampled():
+    """1,000,000 x 256 headline workload, one 1,024-query launch as the
+    benchmark issues it; 16 sampled queries checked against the oracle."""
+    pm = _gpu()
+    say("case: headline scale")
+    w = synth.headline(n_queries=1024)
+    D, A, Q = w["D"], w["A"], w["Q"]
+    beta, k = 1e-3, 10
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    B = min(D.shape[0], math.ceil(beta * D.shape[0]) + k)
+    r0 = oracle_r_min(D, 0x5EED, B)
+    assert idx.default_r_min(B) == pytest.approx(r0, rel=1e-12)
+    ids, dist, st = idx.ann(torch.from_numpy(Q).to(dev), k, c=1.5, beta=beta, r_min=r0,
+                            stats=True)
+    torch.cuda.synchronize()
+    ids, dist, st = ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
+    from oracle import ann as oann
+    Dp = oann.project(D, A)
+    sample = np.arange(0, 1024, 64)
+    res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
+    compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
+    say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
