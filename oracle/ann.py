@@ -53,6 +53,7 @@ class AnnResult:
     margin: float          # smallest relative decision margin
     margin_kind: str       # which comparison produced it
     r_final: float
+    margins: dict          # smallest margin of each kind of comparison
 
 
 def project(X: np.ndarray, A: np.ndarray) -> np.ndarray:
@@ -131,9 +132,12 @@ def query(D: np.ndarray, Dp: np.ndarray, q: np.ndarray, qp: np.ndarray,
         margins.append((_rel(b, a) if a > 0 else (math.inf if b > 0 else 0.0),
                         "topk_order"))
     mval, mkind = min(margins, key=lambda x: x[0]) if margins else (math.inf, "")
+    by_kind = {}
+    for v, kind in margins:
+        by_kind[kind] = min(v, by_kind.get(kind, math.inf))
     return AnnResult(ids=top_ids, dist=top_dist, exit_kind=exit_kind,
                      rounds=rounds, n_cand=int(cand.size), margin=mval,
-                     margin_kind=mkind, r_final=r)
+                     margin_kind=mkind, r_final=r, margins=by_kind)
 
 
 def run(D: np.ndarray, A: np.ndarray, Q: np.ndarray, k: int, c: float,

@@ -56,10 +56,11 @@ __global__ __launch_bounds__(256) void project_kernel(
         }
         __syncthreads();
     }
-    // result element i of a lane: row 4*(lane/16) + i, hash function lane % 16
+    // result element i of a lane: row lane/16 + 4*i, hash function lane % 16
+    // (the v_mfma_f64_16x16x4f64 accumulator layout on gfx950)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int64_t gr = row0 + wave * 16 + 4 * (lane >> 4) + i;
+        const int64_t gr = row0 + wave * 16 + (lane >> 4) + 4 * i;
         const int col = lane & 15;
         if (gr < rows) {
             const double v = acc[i];

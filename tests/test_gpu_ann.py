@@ -75,8 +75,23 @@ def test_exact_special_case(parity_wl):
     assert np.all(st[:, 2] == 2) and np.all(st[:, 1] == D.shape[0])
 
 
-@pytest.mark.parametrize("scale,beta,k", [(0.05, 0.1, 10), (0.3, 0.02, 1), (0.5, 0.05, 100)])
-def test_multi_round_and_line4(parity_wl, scale, beta, k):
+def test_projected_knn_special_case(parity_wl):
+    """B = k and an unbounded first radius: C is the k projected-nearest
+    points (the projection and the budget cut alone decide the answer)."""
+    pm = _gpu()
+    w = parity_wl
+    D, A, Q = w["D"], w["A"], w["Q"][:50]
+    say("case: projected kNN special case")
+    res, B = oracle_ann(D, A, Q, 8, 1.5, 0.9, 0.0, r_min=1e30)
+    assert B == 8
+    _, ids, dist, st = _run(pm, D, A, Q, 8, 1.5, 0.9, 0.0, 1e30)
+    compare_ann(D, Q, res, ids, dist, st)
+
+
+@pytest.mark.parametrize("scale,beta,k,expect", [(0.05, 0.1, 10, "multi"),
+                                                 (0.3, 0.02, 1, "multi"),
+                                                 (0.5, 0.05, 100, "line4")])
+def test_multi_round_and_line4(parity_wl, scale, beta, k, expect):
     """Small first radius: several range queries, line-4 and budget exits."""
     pm = _gpu()
     w = parity_wl
@@ -90,7 +105,10 @@ def test_multi_round_and_line4(parity_wl, scale, beta, k):
     kinds = {r.exit_kind for r in res}
     rounds = max(r.rounds for r in res)
     say("exit kinds", kinds, "max rounds", rounds)
-    assert rounds >= 2
+    if expect == "multi":
+        assert rounds >= 2          # several range queries
+    else:
+        assert 1 in kinds           # Algorithm 2's line-4 exit
 
 
 def test_budget_larger_than_one_sort(parity_wl):
@@ -148,7 +166,7 @@ def test_ties_duplicates_and_self_queries():
     _, ids, dist, st = _run(pm, D, A, Q, 7, 1.5, 0.9, 0.1, 1e30, leaf_size=16)
     # duplicates tie exactly in FP32 as in FP64, so both sides break the tie
     # on the id: the answers must agree id for id
-    compare_ann(D, Q, res, ids, dist, st, max_fragile_frac=1.0)
+    compare_ann(D, Q, res, ids, dist, st)
     assert np.array_equal(ids, np.stack([r.ids for r in res]))
     assert np.all(dist[:10, 0] == 0)
 
