@@ -48,6 +48,7 @@ struct AnnArgs {
     const float* hrmax;
     const int32_t* cb;
     const int32_t* ce;
+    const int32_t* npts;
     const float* piv;
     int64_t n_nodes;
     int64_t n_leaves;
@@ -68,6 +69,20 @@ struct AnnArgs {
     int64_t* out_ids;
     float* out_dist;
     int32_t* out_stats;
+    // leaf-major fast path (per query): radius bound, its square and test
+    // slack, fallback flag, candidate count, scanned points, candidate list
+    float* q_tau;
+    float* q_tau2;
+    float* q_slack;
+    int32_t* q_flag;
+    uint32_t* l_count;          // candidates per query
+    uint32_t* q_scanned;
+    uint32_t* q_base;           // start of the query's range in the pool
+    uint32_t* blk_cnt;          // nq x leaf blocks: counts, then offsets
+    unsigned long long* pool_top;
+    uint2* l_list;              // shared pool of (leaf position, pd^2 bits)
+    int64_t pool_cap;
+    int nq;
 };
 
 struct Smem {
@@ -154,70 +169,15 @@ __device__ __forceinline__ float node_dist(const AnnArgs& a, int node, const flo
 __device__ __forceinline__ bool node_pass(const AnnArgs& a, int node, const float* qp,
                                           const float* qpiv, float R, float slack) {
     if (node_dist(a, node, qp) > a.nrad[node] + R + slack) return false;
-    for (int i = 0; i < a.s; ++i) {
-        const int64_t o = (int64_t)i * a.n_nodes + node;
-        if (qpiv[i] - R > a.hrmax[o] + slack) return false;
-        if (qpiv[i] + R < a.hrmin[o] - slack) return false;
+#pragma unroll
+    for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i) {
+        if (i < a.s) {
+            const int64_t o = (int64_t)i * a.n_nodes + node;
+            if (qpiv[i] - R > a.hrmax[o] + slack) return false;
+            if (qpiv[i] + R < a.hrmin[o] - slack) return false;
+        }
     }
     return true;
-}
-
-// Level-by-level traversal; returns the number of leaves passing Eq. 5, whose
-// ids are left in *out (one of the two per-query frontier buffers).
-__device__ int traverse(const AnnArgs& a, const float* qp, const float* qpiv, float R,
-                        float slack, int32_t* fa, int32_t* fb, int32_t** out, Smem& sh) {
-    int32_t* cur = fa;
-    int32_t* nxt = fb;
-    int ncur = a.level_begin[1] - a.level_begin[0];
-    for (int l = 0; l < a.levels; ++l) {
-        const bool leaf_level = (l == a.levels - 1);
-        if (threadIdx.x == 0) sh.cnt0 = 0;
-        __syncthreads();
-        for (int base = 0; base < ncur; base += WG) {
-            const int i = base + threadIdx.x;
-            bool pass = false;
-            int node = 0;
-            if (i < ncur) {
-                node = (l == 0) ? a.level_begin[0] + i : cur[i];
-                // entries always lie in this level; the check only keeps a
-                // corrupted list from reading outside the node arrays
-                if (node >= a.level_begin[l] && node < a.level_begin[l + 1])
-                    pass = node_pass(a, node, qp, qpiv, R, slack);
-            }
-            if (leaf_level) {
-                const int slot = wave_append(pass, &sh.cnt0);
-                if (pass && slot < a.n_leaves) nxt[slot] = node;
-            } else if (pass) {
-                const int b = a.cb[node], e = a.ce[node];
-                const int slot = atomicAdd(&sh.cnt0, e - b);
-                if (slot + (e - b) <= a.n_leaves)
-                    for (int j = b; j < e; ++j) nxt[slot + (j - b)] = j;
-            }
-        }
-        __syncthreads();
-        ncur = sh.cnt0 < a.n_leaves ? sh.cnt0 : (int)a.n_leaves;
-        __syncthreads();
-        int32_t* t = cur; cur = nxt; nxt = t;
-    }
-    *out = cur;
-    return ncur;
-}
-
-// Calls f(valid, pos, pd2) for every point of the listed leaves; wave-uniform.
-template <class F>
-__device__ __forceinline__ void scan_leaves(const AnnArgs& a, const int32_t* leaves, int nl,
-                                            const float* qp, F&& f) {
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    for (int li = wave; li < nl; li += NWAVE) {
-        const int leaf = leaves[li];
-        const int p0 = a.cb[leaf], p1 = a.ce[leaf];
-        for (int base = p0; base < p1; base += 64) {
-            const int pos = base + lane;
-            const bool valid = pos < p1;
-            const float pd2 = valid ? proj_dist2(a.proj + (int64_t)pos * MP, qp) : FLT_MAX;
-            f(valid, pos, pd2);
-        }
-    }
 }
 
 __device__ __forceinline__ int shift_for(uint64_t lo, uint64_t hi) {
@@ -255,6 +215,124 @@ __device__ void find_threshold(int need, Smem& sh) {
         }
     }
     __syncthreads();
+}
+
+// Histogram bin of a non-negative radius below R: 256 bins per octave over
+// [R / 2^8, R], everything smaller in bin 0.
+__device__ __forceinline__ int radius_bin(float v, uint32_t base) {
+    const uint32_t b = __float_as_uint(v) >> 15;
+    return b <= base ? 0 : (int)(b - base);
+}
+
+// Level-by-level traversal with Eq. 5; returns the number of leaves that pass
+// and leaves their ids in fa (the first of the two per-query buffers).
+//
+// With `shrink`, the radius R (in/out) is lowered level by level to an upper
+// bound tau on the budget-th smallest projected distance: the passing nodes
+// whose every point lies within dist(q', centre) + radius <= tau hold at least
+// `budget` points. Then every point of the final ball of radius tau lies in a
+// kept leaf, the ball holds at least `budget` points, and its `budget`
+// nearest points are those of the ball of the original radius.
+__device__ int traverse(const AnnArgs& a, const float* qp, const float* qpiv, float& R,
+                        float slack, bool shrink, int budget, int32_t* fa, int32_t* fb,
+                        Smem& sh, bool tau_only = false) {
+    int ncur = a.level_begin[1] - a.level_begin[0];
+    for (int l = 0; l < a.levels; ++l) {
+        const bool leaf_level = (l == a.levels - 1);
+        // A: test the candidates of this level at R; the passing ones go to fb
+        if (threadIdx.x == 0) sh.cnt0 = 0;
+        __syncthreads();
+        for (int base = 0; base < ncur; base += WG) {
+            const int i = base + threadIdx.x;
+            bool pass = false;
+            int node = 0;
+            if (i < ncur) {
+                node = (l == 0) ? a.level_begin[0] + i : fa[i];
+                // entries always lie in this level; the check only keeps a
+                // corrupted list from reading outside the node arrays
+                if (node >= a.level_begin[l] && node < a.level_begin[l + 1])
+                    pass = node_pass(a, node, qp, qpiv, R, slack);
+            }
+            const int slot = wave_append(pass, &sh.cnt0);
+            if (pass && slot < a.n_leaves) fb[slot] = node;
+        }
+        __syncthreads();
+        const int np = sh.cnt0 < a.n_leaves ? sh.cnt0 : (int)a.n_leaves;
+        __syncthreads();
+        // B: weighted histogram of the nodes' distance upper bounds -> tau
+        float Rn = R;
+        if (shrink) {
+            const uint32_t hb = __float_as_uint(R) >> 15;
+            const uint32_t base = hb > (uint32_t)(NB - 1) ? hb - (uint32_t)(NB - 1) : 0u;
+            clear_hist(sh);
+            int loc = 0;
+            for (int i = threadIdx.x; i < np; i += WG) {
+                const int node = fb[i];
+                const float ub = node_dist(a, node, qp) + a.nrad[node] + slack;
+                if (ub <= R) {
+                    atomicAdd(&sh.hist[radius_bin(ub, base)], (uint32_t)a.npts[node]);
+                    loc += a.npts[node];
+                }
+            }
+            __syncthreads();
+            if (block_sum(loc, sh) >= budget) {
+                if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+                __syncthreads();
+                find_threshold(budget, sh);
+                // upper edge of the threshold bin: every counted ub is below it
+                const float tau = __uint_as_float((base + (uint32_t)sh.thr_bin + 1u) << 15);
+                Rn = tau < R ? tau : R;
+            }
+            __syncthreads();
+        }
+        if (tau_only && leaf_level) {
+            R = Rn;
+            return np;     // the leaves passing at the incoming radius, in fb
+        }
+        // C: keep what passes at the lowered radius; expand inner nodes into fa
+        if (threadIdx.x == 0) sh.cnt1 = 0;
+        __syncthreads();
+        for (int base = 0; base < np; base += WG) {
+            const int i = base + threadIdx.x;
+            bool keep = false;
+            int node = 0;
+            if (i < np) {
+                node = fb[i];
+                keep = Rn == R || node_pass(a, node, qp, qpiv, Rn, slack);
+            }
+            if (leaf_level) {
+                const int slot = wave_append(keep, &sh.cnt1);
+                if (keep && slot < a.n_leaves) fa[slot] = node;
+            } else if (keep) {
+                const int b = a.cb[node], e = a.ce[node];
+                const int slot = atomicAdd(&sh.cnt1, e - b);
+                if (slot + (e - b) <= a.n_leaves)
+                    for (int j = b; j < e; ++j) fa[slot + (j - b)] = j;
+            }
+        }
+        __syncthreads();
+        ncur = sh.cnt1 < a.n_leaves ? sh.cnt1 : (int)a.n_leaves;
+        R = Rn;
+        __syncthreads();
+    }
+    return ncur;
+}
+
+// Calls f(valid, pos, pd2) for every point of the listed leaves; wave-uniform.
+template <class F>
+__device__ __forceinline__ void scan_leaves(const AnnArgs& a, const int32_t* leaves, int nl,
+                                            const float* qp, F&& f) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int li = wave; li < nl; li += NWAVE) {
+        const int leaf = leaves[li];
+        const int p0 = a.cb[leaf], p1 = a.ce[leaf];
+        for (int base = p0; base < p1; base += 64) {
+            const int pos = base + lane;
+            const bool valid = pos < p1;
+            const float pd2 = valid ? proj_dist2(a.proj + (int64_t)pos * MP, qp) : FLT_MAX;
+            f(valid, pos, pd2);
+        }
+    }
 }
 
 __device__ void bitonic_sort(int count, Smem& sh) {
@@ -378,120 +456,42 @@ __device__ void verify(const AnnArgs& a, const float* qs, const int32_t* cpos, f
     }
 }
 
-__global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
-    float* qs = reinterpret_cast<float*>(smem_raw + ((sizeof(Smem) + 15) & ~size_t(15)));
-
-    const int64_t qi = blockIdx.x;
-    const float* qrow = a.q + qi * a.d;
-    for (int c = threadIdx.x; c < a.d_pad; c += WG) qs[c] = c < a.d ? qrow[c] : 0.f;
-
+// Loads the query into LDS (zero padded), its projection and pivot
+// distances into registers.
+struct QueryCtx {
     float qp[MP];
-#pragma unroll
-    for (int j = 0; j < MP; ++j) qp[j] = a.qp[qi * MP + j];
     float qpiv[PMLSH_MAX_PIVOTS];
-    float qn2 = 0.f;
+    float qn2;
+};
+
+__device__ __forceinline__ void load_query(const AnnArgs& a, int64_t qi, float* qs, QueryCtx& c) {
+    const float* qrow = a.q + qi * a.d;
+    if (qs)
+        for (int j = threadIdx.x; j < a.d_pad; j += WG) qs[j] = j < a.d ? qrow[j] : 0.f;
 #pragma unroll
-    for (int j = 0; j < MP; ++j) qn2 = fmaf(qp[j], qp[j], qn2);
-    for (int i = 0; i < a.s; ++i) {
+    for (int j = 0; j < MP; ++j) c.qp[j] = a.qp[qi * MP + j];
+    c.qn2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) c.qn2 = fmaf(c.qp[j], c.qp[j], c.qn2);
+#pragma unroll
+    for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i) {
         float acc = 0.f;
+        if (i < a.s) {
 #pragma unroll
-        for (int j = 0; j < MP; ++j) {
-            const float t = qp[j] - a.piv[i * MP + j];
-            acc = fmaf(t, t, acc);
+            for (int j = 0; j < MP; ++j) {
+                const float t = c.qp[j] - a.piv[i * MP + j];
+                acc = fmaf(t, t, acc);
+            }
         }
-        qpiv[i] = sqrtf(acc);
+        c.qpiv[i] = sqrtf(acc);
     }
-    __syncthreads();
+}
 
-    int32_t* fa = a.ws_front + qi * 2 * a.n_leaves;
-    int32_t* fb = fa + a.n_leaves;
-    int32_t* cpos = a.ws_cpos + qi * (int64_t)a.budget;
-    float* cdist = a.ws_cdist + qi * (int64_t)a.budget;
+// Sorts the first n_ver members of C by (distance^2 bits, id) and writes the
+// k nearest and the per-query statistics.
+__device__ void write_topk(const AnnArgs& a, int64_t qi, const int32_t* cpos, const float* cdist,
+                           int n_ver, int rounds, int exit_kind, int64_t scanned, Smem& sh) {
     const int32_t* perm = a.perm;
-    const int B = a.budget;
-
-    double r = a.r_min;
-    int n_ver = 0;
-    int rounds = 0;
-    int exit_kind = 0;
-    int64_t scanned = 0;
-    uint32_t prev_hi = 0;     // bits of the previous squared radius
-    bool first = true;
-
-    for (;;) {
-        if (rounds > 0) {
-            const double cr = a.c * r;
-            const float thr2 = (float)(cr * cr);
-            int loc = 0;
-            for (int i = threadIdx.x; i < n_ver; i += WG) loc += cdist[i] <= thr2;
-            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
-        }
-        if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
-        const double Rd = a.t * r;
-        const float R = (float)Rd;
-        const float R2 = (float)(Rd * Rd);
-        ++rounds;
-        const float slack = 1e-5f * (sqrtf(qn2) + a.coord_scale + R);
-
-        int32_t* leaves = nullptr;
-        const int nl = traverse(a, qp, qpiv, R, slack, fa, fb, &leaves, sh);
-
-        // shell (prev, R2] on the 64-bit keys (pd^2 bits << 32 | id)
-        const uint32_t lo_hi = first ? 0u : prev_hi + 1u;
-        const uint32_t hi_hi = __float_as_uint(R2);
-        const uint64_t klo = (uint64_t)lo_hi << 32;
-        const uint64_t khi = ((uint64_t)hi_hi << 32) | 0xffffffffull;
-        const int sh0 = shift_for(klo, khi);
-        auto ball_src = [&](auto&& v) {
-            scan_leaves(a, leaves, nl, qp, [&](bool valid, int pos, float pd2) {
-                const uint32_t b = __float_as_uint(pd2);
-                const bool mem = valid && b >= lo_hi && b <= hi_hi;
-                const uint64_t key = mem ? (((uint64_t)b << 32) | (uint32_t)perm[pos]) : 0ull;
-                v(mem, key, pos);
-            });
-        };
-
-        clear_hist(sh);
-        int loc = 0, sc = 0;
-        ball_src([&](bool mem, uint64_t key, int32_t) {
-            if (mem) { ++loc; atomicAdd(&sh.hist[(key - klo) >> sh0], 1u); }
-        });
-        for (int li = threadIdx.x; li < nl; li += WG) sc += a.ce[leaves[li]] - a.cb[leaves[li]];
-        scanned += block_sum(sc, sh);
-        const int shell = block_sum(loc, sh);
-
-        if (n_ver + shell >= B) {
-            const int need = B - n_ver;
-            block_select(ball_src,
-                         [&](int32_t pos, int slot) {
-                             if (slot < need) cpos[n_ver + slot] = pos;
-                         },
-                         klo, khi, need, true, shell, sh);
-            __syncthreads();
-            verify(a, qs, cpos, cdist, n_ver, B);
-            n_ver = B;
-            exit_kind = PMLSH_EXIT_BUDGET;
-            __syncthreads();
-            break;
-        }
-        if (threadIdx.x == 0) sh.cnt1 = 0;
-        __syncthreads();
-        ball_src([&](bool mem, uint64_t, int32_t pos) {
-            const int slot = wave_append(mem, &sh.cnt1);
-            if (mem && n_ver + slot < B) cpos[n_ver + slot] = pos;
-        });
-        __syncthreads();
-        verify(a, qs, cpos, cdist, n_ver, n_ver + shell);
-        n_ver += shell;
-        __syncthreads();
-        prev_hi = hi_hi;
-        first = false;
-        r = a.c * r;
-    }
-
-    // top-k of C by (distance^2 bits, id)
     auto c_src = [&](auto&& v) {
         for (int base = 0; base < n_ver; base += WG) {
             const int i = base + threadIdx.x;
@@ -538,7 +538,525 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
     }
 }
 
+__global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
+    float* qs = reinterpret_cast<float*>(smem_raw + ((sizeof(Smem) + 15) & ~size_t(15)));
+
+    const int64_t qi = blockIdx.x;
+    if (a.q_flag && a.q_flag[qi] == 0) return;   // answered by the leaf-major path
+    QueryCtx qc;
+    load_query(a, qi, qs, qc);
+    const float* qp = qc.qp;
+    const float* qpiv = qc.qpiv;
+    const float qn2 = qc.qn2;
+    __syncthreads();
+
+    int32_t* fa = a.ws_front + qi * 2 * a.n_leaves;
+    int32_t* fb = fa + a.n_leaves;
+    int32_t* cpos = a.ws_cpos + qi * (int64_t)a.budget;
+    float* cdist = a.ws_cdist + qi * (int64_t)a.budget;
+    const int32_t* perm = a.perm;
+    const int B = a.budget;
+
+    double r = a.r_min;
+    int n_ver = 0;
+    int rounds = 0;
+    int exit_kind = 0;
+    int64_t scanned = 0;
+    uint32_t prev_hi = 0;     // bits of the previous squared radius
+    bool first = true;
+
+    for (;;) {
+        if (rounds > 0) {
+            const double cr = a.c * r;
+            const float thr2 = (float)(cr * cr);
+            int loc = 0;
+            for (int i = threadIdx.x; i < n_ver; i += WG) loc += cdist[i] <= thr2;
+            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
+        }
+        if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
+        const double Rd = a.t * r;
+        const float R = (float)Rd;
+        const float R2 = (float)(Rd * Rd);
+        ++rounds;
+        const float slack = 1e-5f * (sqrtf(qn2) + a.coord_scale + R);
+
+        // range query (q', R), shrunk to the budget when the ball is large
+        float Rq = R;
+        int nl = traverse(a, qp, qpiv, Rq, slack, true, B, fa, fb, sh);
+        const int32_t* leaves = fa;
+        const float R2q = Rq < R ? (float)((double)Rq * (double)Rq) : R2;
+
+        // shell (prev, R2q] on the 64-bit keys (pd^2 bits << 32 | id)
+        const uint32_t lo_hi = first ? 0u : prev_hi + 1u;
+        uint32_t hi_hi = __float_as_uint(R2q);
+        const uint64_t klo = (uint64_t)lo_hi << 32;
+        uint64_t khi = ((uint64_t)hi_hi << 32) | 0xffffffffull;
+        int sh0 = shift_for(klo, khi);
+        auto ball_src = [&](auto&& v) {
+            scan_leaves(a, leaves, nl, qp, [&](bool valid, int pos, float pd2) {
+                const uint32_t b = __float_as_uint(pd2);
+                const bool mem = valid && b >= lo_hi && b <= hi_hi;
+                const uint64_t key = mem ? (((uint64_t)b << 32) | (uint32_t)perm[pos]) : 0ull;
+                v(mem, key, pos);
+            });
+        };
+        auto count_pass = [&]() {
+            clear_hist(sh);
+            int loc = 0, sc = 0;
+            ball_src([&](bool mem, uint64_t key, int32_t) {
+                if (mem) { ++loc; atomicAdd(&sh.hist[(key - klo) >> sh0], 1u); }
+            });
+            for (int li = threadIdx.x; li < nl; li += WG) sc += a.ce[leaves[li]] - a.cb[leaves[li]];
+            scanned += block_sum(sc, sh);
+            return block_sum(loc, sh);
+        };
+        int shell = count_pass();
+        if (Rq < R && n_ver + shell < B) {
+            // the lowered radius fell short (rounding at the bound): redo the
+            // range query at the full radius
+            Rq = R;
+            nl = traverse(a, qp, qpiv, Rq, slack, false, B, fa, fb, sh);
+            hi_hi = __float_as_uint(R2);
+            khi = ((uint64_t)hi_hi << 32) | 0xffffffffull;
+            sh0 = shift_for(klo, khi);
+            shell = count_pass();
+        }
+
+        if (n_ver + shell >= B) {
+            const int need = B - n_ver;
+            block_select(ball_src,
+                         [&](int32_t pos, int slot) {
+                             if (slot < need) cpos[n_ver + slot] = pos;
+                         },
+                         klo, khi, need, true, shell, sh);
+            __syncthreads();
+            verify(a, qs, cpos, cdist, n_ver, B);
+            n_ver = B;
+            exit_kind = PMLSH_EXIT_BUDGET;
+            __syncthreads();
+            break;
+        }
+        if (threadIdx.x == 0) sh.cnt1 = 0;
+        __syncthreads();
+        ball_src([&](bool mem, uint64_t, int32_t pos) {
+            const int slot = wave_append(mem, &sh.cnt1);
+            if (mem && n_ver + slot < B) cpos[n_ver + slot] = pos;
+        });
+        __syncthreads();
+        verify(a, qs, cpos, cdist, n_ver, n_ver + shell);
+        n_ver += shell;
+        __syncthreads();
+        prev_hi = hi_hi;
+        first = false;
+        r = a.c * r;
+    }
+
+    write_topk(a, qi, cpos, cdist, n_ver, rounds, exit_kind, scanned, sh);
+}
+
+// ------------------------------------------------------------------------
+// Leaf-major fast path for B <= CAP.
+//
+// Every candidate set of Algorithm 2 is a prefix of the order of the data by
+// (projected distance, id) (the ball of a round holds the points up to t*r;
+// a budget exit keeps the B first), and "the ball holds at least B points"
+// is "the B-th projected distance is <= t*r". So the list L of the B
+// projected-nearest points, verified as far as the rounds need, decides
+// every round. The path finds L in three kernels:
+//   tau     per query: an upper bound tau on the B-th projected distance
+//           from the tree alone (the traversal's budget shrink);
+//   filter  per leaf block x query block: each leaf's points are loaded once
+//           into registers and tested against every query of the block whose
+//           range query (q', tau) reaches the leaf (Eq. 5); points with
+//           pd^2 <= tau^2 are appended to the query's candidate list;
+//   finish  per query: exact radix select of L from the list, the rounds of
+//           Algorithm 2 on L with incremental verification, the top-k.
+// Queries whose list overflows (or that fall outside the path) are flagged
+// and answered by the per-query kernel above.
+
+__global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
+    const int64_t qi = blockIdx.x;
+    QueryCtx qc;
+    load_query(a, qi, nullptr, qc);
+    // starting radius: the largest upper bound over the top level, which
+    // every point of the data satisfies
+    float ub0 = 0.f;
+    for (int i = a.level_begin[0] + threadIdx.x; i < a.level_begin[1]; i += WG)
+        ub0 = fmaxf(ub0, node_dist(a, i, qc.qp) + a.nrad[i]);
+    for (int off = 32; off > 0; off >>= 1) ub0 = fmaxf(ub0, __shfl_xor(ub0, off));
+    if (lane_id() == 0) sh.red[threadIdx.x >> 6] = __float_as_int(ub0);
+    __syncthreads();
+    float R = 0.f;
+    for (int w = 0; w < NWAVE; ++w) R = fmaxf(R, __int_as_float(sh.red[w]));
+    __syncthreads();
+    const float slack = 1e-5f * (sqrtf(qc.qn2) + a.coord_scale + R);
+    R = R + 2.f * slack;
+    int32_t* fa = a.ws_front + qi * 2 * a.n_leaves;
+    int32_t* lv = fa + a.n_leaves;
+    const int np = traverse(a, qc.qp, qc.qpiv, R, slack, true, a.budget, fa, lv, sh, true);
+    float R2 = (float)((double)R * (double)R);
+
+    // Refinement: among the candidate leaves nearest to q' by centre distance
+    // (at least 4B points), the exact B-th smallest projected distance is an
+    // upper bound on the B-th smallest over the whole data, and a tight one.
+    {
+        const uint32_t hb = __float_as_uint(R) >> 15;
+        const uint32_t base = hb > (uint32_t)(NB - 1) ? hb - (uint32_t)(NB - 1) : 0u;
+        clear_hist(sh);
+        int loc = 0;
+        for (int i = threadIdx.x; i < np; i += WG) {
+            const int node = lv[i];
+            const float dd = node_dist(a, node, qc.qp);
+            if (dd <= R) {
+                atomicAdd(&sh.hist[radius_bin(dd, base)], (uint32_t)a.npts[node]);
+                loc += a.npts[node];
+            }
+        }
+        __syncthreads();
+        const int total = block_sum(loc, sh);
+        if (total >= a.budget) {
+            const int want = total < 4 * a.budget ? total : 4 * a.budget;
+            if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+            __syncthreads();
+            find_threshold(want, sh);
+            const float dedge = __uint_as_float((base + (uint32_t)sh.thr_bin + 1u) << 15);
+            __syncthreads();
+            // compact those leaves (thread-parallel) into fa
+            if (threadIdx.x == 0) sh.cnt1 = 0;
+            __syncthreads();
+            for (int b0 = 0; b0 < np; b0 += WG) {
+                const int i = b0 + threadIdx.x;
+                bool take = false;
+                int node = 0;
+                if (i < np) {
+                    node = lv[i];
+                    take = node_dist(a, node, qc.qp) < dedge;
+                }
+                const int slot = wave_append(take, &sh.cnt1);
+                if (take && slot < a.n_leaves) fa[slot] = node;
+            }
+            __syncthreads();
+            const int nsel = sh.cnt1 < a.n_leaves ? sh.cnt1 : (int)a.n_leaves;
+            // histogram of pd^2 over the points of those leaves
+            const uint32_t hb2 = __float_as_uint(R2) >> 15;
+            const uint32_t base2 = hb2 > (uint32_t)(NB - 1) ? hb2 - (uint32_t)(NB - 1) : 0u;
+            clear_hist(sh);
+            int cnt = 0;
+            const int lane = lane_id(), wave = threadIdx.x >> 6;
+            for (int li = wave; li < nsel; li += NWAVE) {
+                const int node = fa[li];
+                const int p0 = a.cb[node], p1 = a.ce[node];
+                for (int b0 = p0; b0 < p1; b0 += 64) {
+                    const int pos = b0 + lane;
+                    if (pos < p1) {
+                        const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
+                        if (pd2 <= R2) {
+                            atomicAdd(&sh.hist[radius_bin(pd2, base2)], 1u);
+                            ++cnt;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (block_sum(cnt, sh) >= a.budget) {
+                if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+                __syncthreads();
+                find_threshold(a.budget, sh);
+                const float e2 = __uint_as_float((base2 + (uint32_t)sh.thr_bin + 1u) << 15);
+                if (e2 < R2) {
+                    R2 = e2;
+                    R = sqrtf(e2);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        a.q_tau[qi] = R;
+        a.q_tau2[qi] = R2;
+        a.q_slack[qi] = slack;
+        a.l_count[qi] = 0u;
+        a.q_scanned[qi] = 0u;
+        a.q_flag[qi] = 0;
+        if (qi == 0) *a.pool_top = 0ull;
+    }
+}
+
+constexpr int FQB = 256;   // queries per filter block
+constexpr int FLB = 32;    // leaves per filter block (FLB / NWAVE per wave)
+
+// Leaf-major range filter over one (leaf block, query block) tile. Each leaf
+// of the block is loaded once; its Eq. 5 test runs with one query per lane,
+// then every passing query's projected distances are computed with one point
+// per lane. Points with pd^2 <= tau^2 are hits.
+//   WRITE == false: counts hits per (leaf block, query) into LDS, then into
+//                   blk_cnt[query][leaf block]; also counts scanned points.
+//   WRITE == true : recomputes the same hits and writes them at the offsets
+//                   the offsets kernel put in blk_cnt (no global atomics).
+template <bool WRITE>
+__global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
+    __shared__ float sq[FQB][MP + 1];
+    __shared__ float sr[FQB];        // tau
+    __shared__ float sr2[FQB];       // tau^2
+    __shared__ float ssl[FQB];       // slack
+    __shared__ float spv[FQB][PMLSH_MAX_PIVOTS + 1];
+    __shared__ uint32_t scnt[FQB];   // hits (count pass) / write cursor (write pass)
+    __shared__ uint32_t sscan[FQB];  // scanned points (count pass) / base offset (write pass)
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int q0 = blockIdx.y * FQB;
+    const int nqb = min(FQB, a.nq - q0);
+    const int nlb = (int)((a.n_leaves + FLB - 1) / FLB);
+    for (int e = threadIdx.x; e < nqb * MP; e += WG) sq[e / MP][e % MP] = a.qp[(int64_t)q0 * MP + e];
+    for (int e = threadIdx.x; e < FQB; e += WG) {
+        if (e < nqb) {
+            sr[e] = a.q_tau[q0 + e];
+            sr2[e] = a.q_tau2[q0 + e];
+            ssl[e] = a.q_slack[q0 + e];
+        }
+        scnt[e] = 0u;
+        sscan[e] = WRITE && e < nqb ? a.blk_cnt[(int64_t)(q0 + e) * nlb + blockIdx.x] : 0u;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nqb * a.s; e += WG) {
+        const int q = e / a.s, i = e % a.s;
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < MP; ++j) {
+            const float t = sq[q][j] - a.piv[i * MP + j];
+            acc = fmaf(t, t, acc);
+        }
+        spv[q][i] = sqrtf(acc);
+    }
+    __syncthreads();
+
+    const int leaf_base = a.level_begin[a.levels - 1];
+    for (int j = wave; j < FLB; j += NWAVE) {
+        const int64_t leaf = (int64_t)blockIdx.x * FLB + j;
+        if (leaf >= a.n_leaves) break;
+        const int node = leaf_base + (int)leaf;
+        float cen[MP];
+#pragma unroll
+        for (int t = 0; t < MP; ++t) cen[t] = a.ncen[(int64_t)t * a.n_nodes + node];
+        float hmin[PMLSH_MAX_PIVOTS], hmax[PMLSH_MAX_PIVOTS];
+        for (int i = 0; i < a.s; ++i) {
+            hmin[i] = a.hrmin[(int64_t)i * a.n_nodes + node];
+            hmax[i] = a.hrmax[(int64_t)i * a.n_nodes + node];
+        }
+        const float rad = a.nrad[node];
+        const int p0 = a.cb[node], p1 = a.ce[node];
+        // this lane's point while the leaf fits one wave
+        float o[MP];
+        const bool small_leaf = p1 - p0 <= 64;
+        if (small_leaf) {
+            const int pos = p0 + lane < p1 ? p0 + lane : p0;
+            const float4* o4 = reinterpret_cast<const float4*>(a.proj + (int64_t)pos * MP);
+#pragma unroll
+            for (int t = 0; t < MP / 4; ++t) {
+                const float4 v = o4[t];
+                o[4 * t] = v.x; o[4 * t + 1] = v.y; o[4 * t + 2] = v.z; o[4 * t + 3] = v.w;
+            }
+        }
+        for (int qb = 0; qb < nqb; qb += 64) {
+            // Eq. 5 for (this leaf, query qb + lane)
+            const int ql = qb + lane;
+            bool pass = false;
+            if (ql < nqb) {
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < MP; ++t) {
+                    const float u = sq[ql][t] - cen[t];
+                    acc = fmaf(u, u, acc);
+                }
+                const float R = sr[ql], sl = ssl[ql];
+                pass = sqrtf(acc) <= rad + R + sl;
+                for (int i = 0; i < a.s; ++i)
+                    pass = pass && (spv[ql][i] - R <= hmax[i] + sl) && (spv[ql][i] + R >= hmin[i] - sl);
+            }
+            uint64_t m = __ballot(pass);
+            while (m) {
+                const int bit = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const int q = qb + bit;
+                const float R2 = sr2[q];
+                if (!WRITE && lane == 0) atomicAdd(&sscan[q], (uint32_t)(p1 - p0));
+                for (int base = p0; base < p1; base += 64) {
+                    const int pp = base + lane;
+                    const bool v2 = pp < p1;
+                    float pd2 = FLT_MAX;
+                    if (small_leaf) {
+                        if (v2) {
+                            float acc = 0.f;
+#pragma unroll
+                            for (int t = 0; t < MP; ++t) {
+                                const float u = __fsub_rn(sq[q][t], o[t]);
+                                acc = __fmaf_rn(u, u, acc);
+                            }
+                            pd2 = acc;
+                        }
+                    } else if (v2) {
+                        pd2 = proj_dist2(a.proj + (int64_t)pp * MP, sq[q]);
+                    }
+                    const bool hit = v2 && pd2 <= R2;
+                    const uint64_t hm = __ballot(hit);
+                    if (hm) {
+                        const int leader = __ffsll((unsigned long long)hm) - 1;
+                        if (!WRITE) {
+                            if (lane == leader) atomicAdd(&scnt[q], (uint32_t)__popcll(hm));
+                        } else {
+                            uint32_t b = 0;
+                            if (lane == leader) b = atomicAdd(&scnt[q], (uint32_t)__popcll(hm));
+                            b = __shfl(b, leader);
+                            const uint64_t slot = (uint64_t)sscan[q] + b +
+                                                  (uint32_t)__popcll(hm & lanemask_lt());
+                            if (hit && slot < (uint64_t)a.pool_cap)
+                                a.l_list[slot] = make_uint2((uint32_t)pp, __float_as_uint(pd2));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (!WRITE) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < nqb; e += WG) {
+            a.blk_cnt[(int64_t)(q0 + e) * nlb + blockIdx.x] = scnt[e];
+            if (sscan[e]) atomicAdd(&a.q_scanned[q0 + e], sscan[e]);
+        }
+    }
+}
+
+// Per query: exclusive prefix of its hit counts over the leaf blocks, and a
+// contiguous range of the shared candidate pool taken with one atomic.
+// Queries whose range does not fit the pool are flagged for the per-query path.
+__global__ __launch_bounds__(WG) void filter_offsets_kernel(AnnArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
+    const int64_t qi = blockIdx.x;
+    const int nlb = (int)((a.n_leaves + FLB - 1) / FLB);
+    uint32_t* row = a.blk_cnt + qi * nlb;
+    int loc = 0;
+    for (int i = threadIdx.x; i < nlb; i += WG) loc += (int)row[i];
+    const int total = block_sum(loc, sh);
+    if (threadIdx.x == 0) {
+        const unsigned long long base = atomicAdd(a.pool_top, (unsigned long long)total);
+        sh.cnt0 = (int)(base + (unsigned long long)total > (unsigned long long)a.pool_cap);
+        // a flagged query's offsets start past the pool: its writes are skipped
+        a.q_base[qi] = (uint32_t)(sh.cnt0 ? (unsigned long long)a.pool_cap : base);
+        a.l_count[qi] = (uint32_t)total;
+        if (sh.cnt0) a.q_flag[qi] = 1;
+    }
+    __syncthreads();
+    uint32_t running = a.q_base[qi];
+    for (int b0 = 0; b0 < nlb; b0 += WG) {
+        const int i = b0 + threadIdx.x;
+        const int v = i < nlb ? (int)row[i] : 0;
+        const int ex = block_exclusive_scan(v, sh);
+        const int chunk = block_sum(v, sh);
+        if (i < nlb) row[i] = running + (uint32_t)ex;
+        running += (uint32_t)chunk;
+    }
+}
+
+__global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
+    float* qs = reinterpret_cast<float*>(smem_raw + ((sizeof(Smem) + 15) & ~size_t(15)));
+    const int64_t qi = blockIdx.x;
+    const int B = a.budget;
+    const uint32_t cnt = a.l_count[qi];
+    if (a.q_flag[qi] || cnt < (uint32_t)B) {
+        // list overflow, or the bound fell short: the per-query kernel answers
+        if (threadIdx.x == 0) a.q_flag[qi] = 1;
+        return;
+    }
+    QueryCtx qc;
+    load_query(a, qi, qs, qc);
+    int32_t* cpos = a.ws_cpos + qi * (int64_t)B;
+    float* cdist = a.ws_cdist + qi * (int64_t)B;
+    const uint2* list = a.l_list + a.q_base[qi];
+    const int32_t* perm = a.perm;
+    const int n = (int)cnt;
+
+    // L: the B smallest (pd^2 bits, id) of the list, sorted
+    auto list_src = [&](auto&& v) {
+        for (int base = 0; base < n; base += WG) {
+            const int i = base + threadIdx.x;
+            const bool valid = i < n;
+            uint64_t key = 0;
+            int32_t pos = 0;
+            if (valid) {
+                const uint2 e = list[i];
+                pos = (int32_t)e.x;
+                key = ((uint64_t)e.y << 32) | (uint32_t)perm[pos];
+            }
+            v(valid, key, pos);
+        }
+    };
+    __syncthreads();
+    if (n <= CAP) {
+        if (threadIdx.x == 0) sh.cnt1 = 0;
+        __syncthreads();
+        list_src([&](bool valid, uint64_t key, int32_t pos) {
+            const int slot = wave_append(valid, &sh.cnt1);
+            if (valid && slot < CAP) { sh.skey[slot] = key; sh.spos[slot] = pos; }
+        });
+        __syncthreads();
+        bitonic_sort(n, sh);
+    } else {
+        block_select(list_src, [&](int32_t pos, int slot) { if (slot < B) cpos[slot] = pos; },
+                     0ull, ~0ull, B, false, 0, sh);
+        __syncthreads();
+        for (int j = threadIdx.x; j < B; j += WG) {
+            const int32_t pos = cpos[j];
+            sh.skey[j] = ((uint64_t)__float_as_uint(proj_dist2(a.proj + (int64_t)pos * MP, qc.qp)) << 32) |
+                         (uint32_t)perm[pos];
+            sh.spos[j] = pos;
+        }
+        __syncthreads();
+        bitonic_sort(B, sh);
+    }
+    // sh.skey/sh.spos now hold L in (pd^2, id) order; C is always a prefix
+    for (int j = threadIdx.x; j < B; j += WG) cpos[j] = sh.spos[j];
+    __syncthreads();
+
+    double r = a.r_min;
+    int n_ver = 0, rounds = 0, exit_kind = 0;
+    for (;;) {
+        if (rounds > 0) {
+            const double cr = a.c * r;
+            const float thr2 = (float)(cr * cr);
+            int loc = 0;
+            for (int i = threadIdx.x; i < n_ver; i += WG) loc += cdist[i] <= thr2;
+            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
+        }
+        if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
+        const double Rd = a.t * r;
+        const uint32_t r2bits = __float_as_uint((float)(Rd * Rd));
+        ++rounds;
+        // points of L inside the ball (a prefix, as L is sorted)
+        int loc = 0;
+        for (int i = threadIdx.x; i < B; i += WG) loc += (uint32_t)(sh.skey[i] >> 32) <= r2bits;
+        const int nb = block_sum(loc, sh);
+        verify(a, qs, cpos, cdist, n_ver, nb);
+        n_ver = nb;
+        __syncthreads();
+        if (nb == B) { exit_kind = PMLSH_EXIT_BUDGET; break; }
+        r = a.c * r;
+    }
+    write_topk(a, qi, cpos, cdist, n_ver, rounds, exit_kind, (int64_t)a.q_scanned[qi], sh);
+}
+
 }  // namespace
+
+int64_t ann_pool_per_query(int64_t n) { return n < 65536 ? n : 65536; }
+
+int ann_leaf_blocks(int64_t n_leaves) { return (int)((n_leaves + FLB - 1) / FLB); }
+
+bool ann_fast_path(int64_t budget) { return budget <= CAP; }
 
 int ann_lds_bytes(int d_pad) {
     return (int)(((sizeof(Smem) + 15) & ~size_t(15)) + (size_t)d_pad * sizeof(float));
@@ -558,6 +1076,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.hrmax = x.tree.hr_max;
     a.cb = x.tree.child_begin;
     a.ce = x.tree.child_end;
+    a.npts = x.tree.npts;
     a.piv = x.tree.pivots;
     a.n_nodes = x.n_nodes;
     a.n_leaves = x.n_leaves;
@@ -581,9 +1100,39 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.out_ids = L.out_ids;
     a.out_dist = L.out_dist;
     a.out_stats = L.out_stats;
+    a.nq = (int)L.nq;
     const int lds = ann_lds_bytes(x.d_pad);
     PMLSH_HIP(hipFuncSetAttribute((const void*)ann_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    if (ann_fast_path(L.budget)) {
+        a.q_tau = L.q_tau;
+        a.q_tau2 = L.q_tau2;
+        a.q_slack = L.q_slack;
+        a.q_flag = L.q_flag;
+        a.l_count = L.l_count;
+        a.q_scanned = L.q_scanned;
+        a.q_base = L.q_base;
+        a.blk_cnt = L.blk_cnt;
+        a.pool_top = L.pool_top;
+        a.l_list = L.l_list;
+        a.pool_cap = L.pool_cap;
+        const int lds0 = ann_lds_bytes(0);
+        hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
+        PMLSH_HIP(hipGetLastError());
+        dim3 fgrid((unsigned)ann_leaf_blocks(x.n_leaves), (unsigned)((L.nq + FQB - 1) / FQB));
+        hipLaunchKernelGGL(filter_kernel<false>, fgrid, dim3(WG), 0, stream, a);
+        PMLSH_HIP(hipGetLastError());
+        hipLaunchKernelGGL(filter_offsets_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
+        PMLSH_HIP(hipGetLastError());
+        hipLaunchKernelGGL(filter_kernel<true>, fgrid, dim3(WG), 0, stream, a);
+        PMLSH_HIP(hipGetLastError());
+        PMLSH_HIP(hipFuncSetAttribute((const void*)finish_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        hipLaunchKernelGGL(finish_kernel, dim3((unsigned)L.nq), dim3(WG), lds, stream, a);
+        PMLSH_HIP(hipGetLastError());
+    }
+    // per-query path: every query when the fast path does not apply, else only
+    // the queries the fast path flagged
     hipLaunchKernelGGL(ann_kernel, dim3((unsigned)L.nq), dim3(WG), lds, stream, a);
     PMLSH_HIP(hipGetLastError());
 }

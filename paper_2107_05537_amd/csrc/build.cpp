@@ -39,7 +39,8 @@ void index_release(pmlsh_index* x) {
     if (!x) return;
     void* bufs[] = {x->data, x->proj_hi, x->proj_lo, x->perm, x->inv_perm, x->hash,
                     x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max,
-                    x->tree.child_begin, x->tree.child_end, x->tree.pivots};
+                    x->tree.child_begin, x->tree.child_end, x->tree.npts,
+                    x->tree.pivots};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete x;
@@ -146,6 +147,7 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     upload(T.hr_max, &x->tree.hr_max);
     upload(T.child_begin, &x->tree.child_begin);
     upload(T.child_end, &x->tree.child_end);
+    upload(T.npts, &x->tree.npts);
     std::vector<float> piv = T.pivots;
     if (piv.empty()) piv.assign(MP, 0.f);
     upload(piv, &x->tree.pivots);

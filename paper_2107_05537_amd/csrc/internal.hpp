@@ -56,6 +56,7 @@ struct HostTree {
     std::vector<float> radius;            // n_nodes
     std::vector<float> hr_min, hr_max;    // s x n_nodes
     std::vector<int32_t> child_begin, child_end;
+    std::vector<int32_t> npts;            // points in the subtree of each node
     std::vector<float> pivots;            // s x MP
     std::vector<int32_t> perm;            // leaf position -> original id
     float coord_scale = 0.f;              // max ||o'|| + max ||p_i||
@@ -73,6 +74,7 @@ struct DeviceTree {
     float* hr_max = nullptr;
     int32_t* child_begin = nullptr;
     int32_t* child_end = nullptr;
+    int32_t* npts = nullptr;
     float* pivots = nullptr;
 };
 
@@ -128,11 +130,26 @@ struct AnnLaunch {
     int32_t* ws_cpos;       // nq x budget
     float* ws_cdist;        // nq x budget
     int32_t* ws_topk;       // nq x 3 x k
+    // leaf-major fast path, per query
+    float* q_tau;
+    float* q_tau2;
+    float* q_slack;
+    int32_t* q_flag;
+    uint32_t* l_count;
+    uint32_t* q_scanned;
+    uint32_t* q_base;
+    uint32_t* blk_cnt;      // nq x leaf blocks
+    unsigned long long* pool_top;
+    uint2* l_list;          // shared pool of (leaf position, pd^2 bits)
+    int64_t pool_cap;
     int64_t* out_ids;
     float* out_dist;
     int32_t* out_stats;
 };
 void launch_ann(const AnnLaunch& a, hipStream_t stream);
 int ann_lds_bytes(int d_pad);
+int64_t ann_pool_per_query(int64_t n);
+int ann_leaf_blocks(int64_t n_leaves);
+bool ann_fast_path(int64_t budget);
 
 }  // namespace pmlsh

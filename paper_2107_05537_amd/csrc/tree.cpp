@@ -67,39 +67,81 @@ double dist64(const float* a, const float* b) {
     return std::sqrt(s);
 }
 
+// Recursive split of idx[b, e) into whole leaves. A node is cut along its
+// principal direction (power iteration on its 16 x 16 covariance) at the
+// leaf boundary, within the middle 60 % of its leaves, where the sorted
+// projections show the widest gap, so cuts fall between clusters rather
+// than through them. Ties in the projection are ordered by id.
 struct Splitter {
     const float* proj;
     int64_t leaf;
     std::vector<int32_t>& idx;
 
-    int best_axis(int64_t b, int64_t e) const {
-        double mean[MP] = {0}, sq[MP] = {0};
+    void direction(int64_t b, int64_t e, double* dir) const {
+        double mean[MP] = {0};
         for (int64_t i = b; i < e; ++i) {
             const float* p = proj + (int64_t)idx[i] * MP;
-            for (int j = 0; j < MP; ++j) { mean[j] += p[j]; sq[j] += (double)p[j] * p[j]; }
+            for (int j = 0; j < MP; ++j) mean[j] += p[j];
         }
-        int axis = 0;
-        double best = -1;
         const double cnt = (double)(e - b);
-        for (int j = 0; j < MP; ++j) {
-            double v = sq[j] / cnt - (mean[j] / cnt) * (mean[j] / cnt);
-            if (v > best) { best = v; axis = j; }
+        for (int j = 0; j < MP; ++j) mean[j] /= cnt;
+        double cov[MP][MP] = {{0}};
+        for (int64_t i = b; i < e; ++i) {
+            const float* p = proj + (int64_t)idx[i] * MP;
+            double c[MP];
+            for (int j = 0; j < MP; ++j) c[j] = p[j] - mean[j];
+            for (int j = 0; j < MP; ++j)
+                for (int k = j; k < MP; ++k) cov[j][k] += c[j] * c[k];
         }
-        return axis;
+        for (int j = 0; j < MP; ++j)
+            for (int k = 0; k < j; ++k) cov[j][k] = cov[k][j];
+        // start from the coordinate axis of largest variance
+        int ax = 0;
+        for (int j = 1; j < MP; ++j)
+            if (cov[j][j] > cov[ax][ax]) ax = j;
+        for (int j = 0; j < MP; ++j) dir[j] = j == ax ? 1.0 : 0.0;
+        for (int it = 0; it < 30; ++it) {
+            double nd[MP] = {0}, nrm = 0;
+            for (int j = 0; j < MP; ++j) {
+                for (int k = 0; k < MP; ++k) nd[j] += cov[j][k] * dir[k];
+                nrm += nd[j] * nd[j];
+            }
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 0)) break;
+            for (int j = 0; j < MP; ++j) dir[j] = nd[j] / nrm;
+        }
     }
 
     void split(int64_t b, int64_t e, int depth) {
         const int64_t cnt = e - b;
         if (cnt <= leaf) return;
         const int64_t nleaves = (cnt + leaf - 1) / leaf;
-        const int64_t mid = b + (nleaves / 2) * leaf;
-        const int axis = best_axis(b, e);
-        const float* P = proj;
-        std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e,
-                         [P, axis](int32_t x, int32_t y) {
-                             float a = P[(int64_t)x * MP + axis], c = P[(int64_t)y * MP + axis];
-                             return a < c || (a == c && x < y);
-                         });
+        double dir[MP];
+        direction(b, e, dir);
+        std::vector<std::pair<double, int32_t>> key((size_t)cnt);
+        for (int64_t i = 0; i < cnt; ++i) {
+            const float* p = proj + (int64_t)idx[b + i] * MP;
+            double v = 0;
+            for (int j = 0; j < MP; ++j) v += dir[j] * p[j];
+            key[(size_t)i] = {v, idx[b + i]};
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t i = 0; i < cnt; ++i) idx[b + i] = key[(size_t)i].second;
+        // candidate cuts after j whole leaves, j in the middle 60 %
+        int64_t jlo = std::max<int64_t>(1, (nleaves * 2) / 10);
+        int64_t jhi = std::min<int64_t>(nleaves - 1, nleaves - (nleaves * 2) / 10);
+        if (jhi < jlo) jlo = jhi = nleaves / 2;
+        int64_t best = nleaves / 2;
+        double gap = -1;
+        for (int64_t j = jlo; j <= jhi; ++j) {
+            const int64_t p = j * leaf;
+            if (p <= 0 || p >= cnt) continue;
+            const double g = key[(size_t)p].first - key[(size_t)p - 1].first;
+            if (g > gap) { gap = g; best = j; }
+        }
+        const int64_t mid = b + best * leaf;
+        key.clear();
+        key.shrink_to_fit();
         if (depth < 4 && cnt > 200000) {
             std::thread left([&] { split(b, mid, depth + 1); });
             split(mid, e, depth + 1);
@@ -173,6 +215,7 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
     T.hr_max.assign((size_t)std::max(s, 1) * N, 0.f);
     T.child_begin.assign(N, 0);
     T.child_end.assign(N, 0);
+    T.npts.assign(N, 0);
 
     // point range [p0, p1) of every node, in leaf order
     std::vector<int64_t> p0(N), p1(N);
@@ -187,6 +230,7 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
             const int64_t j = i - lb;
             p0[i] = j * group;
             p1[i] = std::min<int64_t>(n, (j + 1) * group);
+            T.npts[i] = (int32_t)(p1[i] - p0[i]);
             if (l == T.levels - 1) {
                 T.child_begin[i] = (int32_t)p0[i];
                 T.child_end[i] = (int32_t)p1[i];
