@@ -77,11 +77,8 @@ struct AnnArgs {
     int32_t* q_flag;
     uint32_t* l_count;          // candidates per query
     uint32_t* q_scanned;
-    uint32_t* q_base;           // start of the query's range in the pool
-    uint32_t* blk_cnt;          // nq x leaf blocks: counts, then offsets
-    unsigned long long* pool_top;
-    uint2* l_list;              // shared pool of (leaf position, pd^2 bits)
-    int64_t pool_cap;
+    uint2* l_list;              // nq x q_cap (leaf position, pd^2 bits)
+    int q_cap;
     int nq;
 };
 
@@ -782,54 +779,73 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         a.l_count[qi] = 0u;
         a.q_scanned[qi] = 0u;
         a.q_flag[qi] = 0;
-        if (qi == 0) *a.pool_top = 0ull;
     }
 }
 
-constexpr int FQB = 256;   // queries per filter block
+constexpr int FQB = 128;   // queries per filter block
 constexpr int FLB = 32;    // leaves per filter block (FLB / NWAVE per wave)
+constexpr int STG = 1024;  // hits staged in LDS per filter block
+constexpr uint8_t kStageUnused = 0xff;   // stage entry reserved but not written
+static_assert(FQB < kStageUnused, "query index of a block must fit below the marker");
 
 // Leaf-major range filter over one (leaf block, query block) tile. Each leaf
-// of the block is loaded once; its Eq. 5 test runs with one query per lane,
-// then every passing query's projected distances are computed with one point
-// per lane. Points with pd^2 <= tau^2 are hits.
-//   WRITE == false: counts hits per (leaf block, query) into LDS, then into
-//                   blk_cnt[query][leaf block]; also counts scanned points.
-//   WRITE == true : recomputes the same hits and writes them at the offsets
-//                   the offsets kernel put in blk_cnt (no global atomics).
-template <bool WRITE>
+// of the block is loaded once into registers (one point per lane); its Eq. 5
+// test runs with one query per lane, then every passing query is compared
+// with the leaf's points:
+//   * a cheap bound |q'|^2 + |o'|^2 - 2 q'.o' (16 FMAs) with a rounding margin
+//     discards points that cannot be within tau;
+//   * the remaining points get the exact direct-difference pd^2, the value
+//     every later decision uses; pd^2 <= tau^2 is a hit.
+// Hits are staged in LDS and written at the end with one reservation per
+// (block, query) in the query's region of the pool; a full stage falls back
+// to direct reservations. A region that overflows flags its query for the
+// per-query kernel.
 __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
-    __shared__ float sq[FQB][MP + 1];
-    __shared__ float sr[FQB];        // tau
-    __shared__ float sr2[FQB];       // tau^2
-    __shared__ float ssl[FQB];       // slack
-    __shared__ float spv[FQB][PMLSH_MAX_PIVOTS + 1];
-    __shared__ uint32_t scnt[FQB];   // hits (count pass) / write cursor (write pass)
-    __shared__ uint32_t sscan[FQB];  // scanned points (count pass) / base offset (write pass)
+    __shared__ __align__(16) float sq[FQB][MP];     // query rows (broadcast reads)
+    __shared__ float sqt[MP][FQB];                  // transposed (per-lane reads)
+    __shared__ float sr[FQB], sr2[FQB], ssl[FQB], sqn[FQB], smg[FQB];
+    __shared__ float spv[PMLSH_MAX_PIVOTS][FQB];
+    __shared__ uint32_t shits[FQB], sbase[FQB], sscan[FQB];
+    __shared__ uint2 stg[STG];
+    __shared__ uint8_t stq[STG];
+    __shared__ uint32_t nstg;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int q0 = blockIdx.y * FQB;
     const int nqb = min(FQB, a.nq - q0);
-    const int nlb = (int)((a.n_leaves + FLB - 1) / FLB);
-    for (int e = threadIdx.x; e < nqb * MP; e += WG) sq[e / MP][e % MP] = a.qp[(int64_t)q0 * MP + e];
+    const float u = 5.9604645e-08f;   // 2^-24
+    for (int e = threadIdx.x; e < nqb * MP; e += WG) {
+        const float v = a.qp[(int64_t)q0 * MP + e];
+        sq[e / MP][e % MP] = v;
+        sqt[e % MP][e / MP] = v;
+    }
+    if (threadIdx.x == 0) nstg = 0u;
     for (int e = threadIdx.x; e < FQB; e += WG) {
-        if (e < nqb) {
-            sr[e] = a.q_tau[q0 + e];
-            sr2[e] = a.q_tau2[q0 + e];
-            ssl[e] = a.q_slack[q0 + e];
-        }
-        scnt[e] = 0u;
-        sscan[e] = WRITE && e < nqb ? a.blk_cnt[(int64_t)(q0 + e) * nlb + blockIdx.x] : 0u;
+        shits[e] = 0u;
+        sscan[e] = 0u;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nqb * a.s; e += WG) {
-        const int q = e / a.s, i = e % a.s;
-        float acc = 0.f;
+    for (int e = threadIdx.x; e < nqb; e += WG) {
+        sr[e] = a.q_tau[q0 + e];
+        sr2[e] = a.q_tau2[q0 + e];
+        ssl[e] = a.q_slack[q0 + e];
+        float n2 = 0.f;
 #pragma unroll
-        for (int j = 0; j < MP; ++j) {
-            const float t = sq[q][j] - a.piv[i * MP + j];
-            acc = fmaf(t, t, acc);
+        for (int t = 0; t < MP; ++t) n2 = fmaf(sq[e][t], sq[e][t], n2);
+        sqn[e] = n2;
+        const float big = sqrtf(n2) + a.coord_scale;
+        smg[e] = 64.f * u * big * big;     // bound on the error of the cheap form
+    }
+    for (int e = threadIdx.x; e < nqb * PMLSH_MAX_PIVOTS; e += WG) {
+        const int q = e / PMLSH_MAX_PIVOTS, i = e % PMLSH_MAX_PIVOTS;
+        float acc = 0.f;
+        if (i < a.s) {
+#pragma unroll
+            for (int j = 0; j < MP; ++j) {
+                const float t = sq[q][j] - a.piv[i * MP + j];
+                acc = fmaf(t, t, acc);
+            }
         }
-        spv[q][i] = sqrtf(acc);
+        spv[i][q] = sqrtf(acc);
     }
     __syncthreads();
 
@@ -842,15 +858,17 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
 #pragma unroll
         for (int t = 0; t < MP; ++t) cen[t] = a.ncen[(int64_t)t * a.n_nodes + node];
         float hmin[PMLSH_MAX_PIVOTS], hmax[PMLSH_MAX_PIVOTS];
-        for (int i = 0; i < a.s; ++i) {
-            hmin[i] = a.hrmin[(int64_t)i * a.n_nodes + node];
-            hmax[i] = a.hrmax[(int64_t)i * a.n_nodes + node];
+#pragma unroll
+        for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i) {
+            hmin[i] = i < a.s ? a.hrmin[(int64_t)i * a.n_nodes + node] : 0.f;
+            hmax[i] = i < a.s ? a.hrmax[(int64_t)i * a.n_nodes + node] : 0.f;
         }
         const float rad = a.nrad[node];
         const int p0 = a.cb[node], p1 = a.ce[node];
+        const bool small_leaf = p1 - p0 <= 64;
         // this lane's point while the leaf fits one wave
         float o[MP];
-        const bool small_leaf = p1 - p0 <= 64;
+        float on2 = 0.f;
         if (small_leaf) {
             const int pos = p0 + lane < p1 ? p0 + lane : p0;
             const float4* o4 = reinterpret_cast<const float4*>(a.proj + (int64_t)pos * MP);
@@ -859,6 +877,8 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
                 const float4 v = o4[t];
                 o[4 * t] = v.x; o[4 * t + 1] = v.y; o[4 * t + 2] = v.z; o[4 * t + 3] = v.w;
             }
+#pragma unroll
+            for (int t = 0; t < MP; ++t) on2 = fmaf(o[t], o[t], on2);
         }
         for (int qb = 0; qb < nqb; qb += 64) {
             // Eq. 5 for (this leaf, query qb + lane)
@@ -868,96 +888,103 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
                 float acc = 0.f;
 #pragma unroll
                 for (int t = 0; t < MP; ++t) {
-                    const float u = sq[ql][t] - cen[t];
-                    acc = fmaf(u, u, acc);
+                    const float d = sqt[t][ql] - cen[t];
+                    acc = fmaf(d, d, acc);
                 }
                 const float R = sr[ql], sl = ssl[ql];
                 pass = sqrtf(acc) <= rad + R + sl;
-                for (int i = 0; i < a.s; ++i)
-                    pass = pass && (spv[ql][i] - R <= hmax[i] + sl) && (spv[ql][i] + R >= hmin[i] - sl);
+#pragma unroll
+                for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i)
+                    if (i < a.s)
+                        pass = pass && (spv[i][ql] - R <= hmax[i] + sl) &&
+                               (spv[i][ql] + R >= hmin[i] - sl);
             }
             uint64_t m = __ballot(pass);
             while (m) {
                 const int bit = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
                 const int q = qb + bit;
+                const int64_t gq = q0 + q;
                 const float R2 = sr2[q];
-                if (!WRITE && lane == 0) atomicAdd(&sscan[q], (uint32_t)(p1 - p0));
+                if (lane == 0) atomicAdd(&sscan[q], (uint32_t)(p1 - p0));
+                const float4* qv4 = reinterpret_cast<const float4*>(&sq[q][0]);
+                float qv[MP];
+#pragma unroll
+                for (int t = 0; t < MP / 4; ++t) {
+                    const float4 v = qv4[t];
+                    qv[4 * t] = v.x; qv[4 * t + 1] = v.y; qv[4 * t + 2] = v.z; qv[4 * t + 3] = v.w;
+                }
                 for (int base = p0; base < p1; base += 64) {
                     const int pp = base + lane;
                     const bool v2 = pp < p1;
-                    float pd2 = FLT_MAX;
+                    bool hit = false;
+                    float pd2 = 0.f;
                     if (small_leaf) {
-                        if (v2) {
+                        float dot = 0.f;
+#pragma unroll
+                        for (int t = 0; t < MP; ++t) dot = fmaf(qv[t], o[t], dot);
+                        const float approx = sqn[q] + on2 - 2.f * dot;
+                        if (v2 && approx <= R2 + smg[q]) {
                             float acc = 0.f;
 #pragma unroll
                             for (int t = 0; t < MP; ++t) {
-                                const float u = __fsub_rn(sq[q][t], o[t]);
-                                acc = __fmaf_rn(u, u, acc);
+                                const float d = __fsub_rn(qv[t], o[t]);
+                                acc = __fmaf_rn(d, d, acc);
                             }
                             pd2 = acc;
+                            hit = pd2 <= R2;
                         }
                     } else if (v2) {
-                        pd2 = proj_dist2(a.proj + (int64_t)pp * MP, sq[q]);
+                        pd2 = proj_dist2(a.proj + (int64_t)pp * MP, qv);
+                        hit = pd2 <= R2;
                     }
-                    const bool hit = v2 && pd2 <= R2;
                     const uint64_t hm = __ballot(hit);
                     if (hm) {
                         const int leader = __ffsll((unsigned long long)hm) - 1;
-                        if (!WRITE) {
-                            if (lane == leader) atomicAdd(&scnt[q], (uint32_t)__popcll(hm));
+                        const uint32_t nh = (uint32_t)__popcll(hm);
+                        const uint32_t rank = (uint32_t)__popcll(hm & lanemask_lt());
+                        uint32_t b = 0;
+                        if (lane == leader) b = atomicAdd(&nstg, nh);
+                        b = __shfl(b, leader);
+                        if (b + nh <= (uint32_t)STG) {
+                            if (hit) {
+                                stg[b + rank] = make_uint2((uint32_t)pp, __float_as_uint(pd2));
+                                stq[b + rank] = (uint8_t)q;
+                            }
                         } else {
-                            uint32_t b = 0;
-                            if (lane == leader) b = atomicAdd(&scnt[q], (uint32_t)__popcll(hm));
-                            b = __shfl(b, leader);
-                            const uint64_t slot = (uint64_t)sscan[q] + b +
-                                                  (uint32_t)__popcll(hm & lanemask_lt());
-                            if (hit && slot < (uint64_t)a.pool_cap)
-                                a.l_list[slot] = make_uint2((uint32_t)pp, __float_as_uint(pd2));
+                            // stage full: the part of this reservation that lies
+                            // inside the stage is marked unused, and the hits are
+                            // reserved in the query's region directly
+                            if (hit && b + rank < (uint32_t)STG) stq[b + rank] = kStageUnused;
+                            uint32_t g = 0;
+                            if (lane == leader) g = atomicAdd(&a.l_count[gq], nh);
+                            g = __shfl(g, leader);
+                            const uint32_t slot = g + rank;
+                            if (hit && slot < (uint32_t)a.q_cap)
+                                a.l_list[gq * a.q_cap + slot] = make_uint2((uint32_t)pp, __float_as_uint(pd2));
                         }
                     }
                 }
             }
         }
     }
-    if (!WRITE) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < nqb; e += WG) {
-            a.blk_cnt[(int64_t)(q0 + e) * nlb + blockIdx.x] = scnt[e];
-            if (sscan[e]) atomicAdd(&a.q_scanned[q0 + e], sscan[e]);
-        }
-    }
-}
-
-// Per query: exclusive prefix of its hit counts over the leaf blocks, and a
-// contiguous range of the shared candidate pool taken with one atomic.
-// Queries whose range does not fit the pool are flagged for the per-query path.
-__global__ __launch_bounds__(WG) void filter_offsets_kernel(AnnArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
-    const int64_t qi = blockIdx.x;
-    const int nlb = (int)((a.n_leaves + FLB - 1) / FLB);
-    uint32_t* row = a.blk_cnt + qi * nlb;
-    int loc = 0;
-    for (int i = threadIdx.x; i < nlb; i += WG) loc += (int)row[i];
-    const int total = block_sum(loc, sh);
-    if (threadIdx.x == 0) {
-        const unsigned long long base = atomicAdd(a.pool_top, (unsigned long long)total);
-        sh.cnt0 = (int)(base + (unsigned long long)total > (unsigned long long)a.pool_cap);
-        // a flagged query's offsets start past the pool: its writes are skipped
-        a.q_base[qi] = (uint32_t)(sh.cnt0 ? (unsigned long long)a.pool_cap : base);
-        a.l_count[qi] = (uint32_t)total;
-        if (sh.cnt0) a.q_flag[qi] = 1;
+    __syncthreads();
+    // flush the stage: one reservation per query of the block
+    const uint32_t ns = nstg < (uint32_t)STG ? nstg : (uint32_t)STG;
+    for (uint32_t e = threadIdx.x; e < ns; e += WG)
+        if (stq[e] != kStageUnused) atomicAdd(&shits[stq[e]], 1u);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nqb; e += WG) {
+        if (shits[e]) sbase[e] = atomicAdd(&a.l_count[q0 + e], shits[e]);
+        if (sscan[e]) atomicAdd(&a.q_scanned[q0 + e], sscan[e]);
+        shits[e] = 0u;
     }
     __syncthreads();
-    uint32_t running = a.q_base[qi];
-    for (int b0 = 0; b0 < nlb; b0 += WG) {
-        const int i = b0 + threadIdx.x;
-        const int v = i < nlb ? (int)row[i] : 0;
-        const int ex = block_exclusive_scan(v, sh);
-        const int chunk = block_sum(v, sh);
-        if (i < nlb) row[i] = running + (uint32_t)ex;
-        running += (uint32_t)chunk;
+    for (uint32_t e = threadIdx.x; e < ns; e += WG) {
+        const int q = stq[e];
+        if (q == kStageUnused) continue;
+        const uint32_t slot = sbase[q] + atomicAdd(&shits[q], 1u);
+        if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = stg[e];
     }
 }
 
@@ -968,7 +995,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     const int64_t qi = blockIdx.x;
     const int B = a.budget;
     const uint32_t cnt = a.l_count[qi];
-    if (a.q_flag[qi] || cnt < (uint32_t)B) {
+    if (cnt > (uint32_t)a.q_cap || cnt < (uint32_t)B) {
         // list overflow, or the bound fell short: the per-query kernel answers
         if (threadIdx.x == 0) a.q_flag[qi] = 1;
         return;
@@ -977,7 +1004,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     load_query(a, qi, qs, qc);
     int32_t* cpos = a.ws_cpos + qi * (int64_t)B;
     float* cdist = a.ws_cdist + qi * (int64_t)B;
-    const uint2* list = a.l_list + a.q_base[qi];
+    const uint2* list = a.l_list + qi * a.q_cap;
     const int32_t* perm = a.perm;
     const int n = (int)cnt;
 
@@ -1052,7 +1079,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
 
 }  // namespace
 
-int64_t ann_pool_per_query(int64_t n) { return n < 65536 ? n : 65536; }
+int64_t ann_pool_per_query(int64_t n) { return n < 16384 ? n : 16384; }
 
 int ann_leaf_blocks(int64_t n_leaves) { return (int)((n_leaves + FLB - 1) / FLB); }
 
@@ -1111,20 +1138,13 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;
-        a.q_base = L.q_base;
-        a.blk_cnt = L.blk_cnt;
-        a.pool_top = L.pool_top;
         a.l_list = L.l_list;
-        a.pool_cap = L.pool_cap;
+        a.q_cap = (int)L.pool_cap;
         const int lds0 = ann_lds_bytes(0);
         hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
         PMLSH_HIP(hipGetLastError());
         dim3 fgrid((unsigned)ann_leaf_blocks(x.n_leaves), (unsigned)((L.nq + FQB - 1) / FQB));
-        hipLaunchKernelGGL(filter_kernel<false>, fgrid, dim3(WG), 0, stream, a);
-        PMLSH_HIP(hipGetLastError());
-        hipLaunchKernelGGL(filter_offsets_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
-        PMLSH_HIP(hipGetLastError());
-        hipLaunchKernelGGL(filter_kernel<true>, fgrid, dim3(WG), 0, stream, a);
+        hipLaunchKernelGGL(filter_kernel, fgrid, dim3(WG), 0, stream, a);
         PMLSH_HIP(hipGetLastError());
         PMLSH_HIP(hipFuncSetAttribute((const void*)finish_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds));

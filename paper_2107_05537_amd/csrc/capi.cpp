@@ -60,19 +60,16 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     const int64_t B = plan.budget;
     const bool fast = ann_fast_path(B);
     const int64_t pool_q = fast ? ann_pool_per_query(x->n) : 0;
-    const int64_t nlb = fast ? ann_leaf_blocks(x->n_leaves) : 0;
     // per query: projection, two frontier lists, C, top-k scratch, and for the
-    // leaf-major path seven scalars, the per-leaf-block counts and a share of
-    // the candidate pool
+    // leaf-major path six scalars and a candidate region
     const int64_t per_query = (int64_t)MP * 4 + 2 * x->n_leaves * 4 + B * 8 +
-                              3 * (int64_t)k * 4 + (fast ? 7 * 4 + nlb * 4 + pool_q * 8 : 0);
+                              3 * (int64_t)k * 4 + (fast ? 6 * 4 + pool_q * 8 : 0);
     int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query));
     batch = std::min<int64_t>(batch, 65535);
     void* ws = nullptr;
-    PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query + 256), st));
+    PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query), st));
     char* base = static_cast<char*>(ws);
-    unsigned long long* pool_top = reinterpret_cast<unsigned long long*>(base);
-    uint2* list = reinterpret_cast<uint2*>(base + 256);
+    uint2* list = reinterpret_cast<uint2*>(base);
     float* qproj = reinterpret_cast<float*>(list + batch * pool_q);
     int32_t* front = reinterpret_cast<int32_t*>(qproj + batch * MP);
     int32_t* cpos = front + batch * 2 * x->n_leaves;
@@ -84,8 +81,6 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     int32_t* q_flag = reinterpret_cast<int32_t*>(q_slack + batch);
     uint32_t* l_count = reinterpret_cast<uint32_t*>(q_flag + batch);
     uint32_t* q_scanned = l_count + batch;
-    uint32_t* q_base = q_scanned + batch;
-    uint32_t* blk_cnt = q_base + batch;
     try {
         for (int64_t q0 = 0; q0 < nq; q0 += batch) {
             const int64_t nb = std::min(batch, nq - q0);
@@ -112,11 +107,8 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
                 L.q_flag = q_flag;
                 L.l_count = l_count;
                 L.q_scanned = q_scanned;
-                L.q_base = q_base;
-                L.blk_cnt = blk_cnt;
-                L.pool_top = pool_top;
                 L.l_list = list;
-                L.pool_cap = batch * pool_q;
+                L.pool_cap = pool_q;
             }
             L.out_ids = out_ids + q0 * k;
             L.out_dist = out_dist + q0 * k;

@@ -137,11 +137,8 @@ struct AnnLaunch {
     int32_t* q_flag;
     uint32_t* l_count;
     uint32_t* q_scanned;
-    uint32_t* q_base;
-    uint32_t* blk_cnt;      // nq x leaf blocks
-    unsigned long long* pool_top;
-    uint2* l_list;          // shared pool of (leaf position, pd^2 bits)
-    int64_t pool_cap;
+    uint2* l_list;          // nq x pool_cap (leaf position, pd^2 bits)
+    int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;
     int32_t* out_stats;
