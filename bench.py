@@ -11,9 +11,14 @@ over all 10,000 queries reaches 0.9 is the operating point, and only that
 point is timed. A step is one pmlsh_ann call on one batch (projection, range
 filter over the PM-tree, budget selection, exact verification, top-k).
 
-Also reported: p50/p99 batch latency, the roofline of the query kernel
-(algorithmic bytes per launch / measured time against 8 TB/s) and the FP64
-CPU oracle timed on this host on a bounded sample of the same queries.
+Also reported: p50/p99 batch latency; per-stage GPU time (HIP events around
+each kernel of the query path, recorded inside the timed region); the
+roofline of the dominant stage (algorithmic work per launch / its measured
+launch time: flops against the FP32 vector peak for the ALU-bound filter,
+bytes against 8 TB/s for the HBM-bound stages), with the HBM traffic that
+rocprofv3 counters measured for that kernel when profiles/ holds them for
+the current kernel sources; and the FP64 CPU oracle timed on this host on a
+bounded sample of the same queries.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -34,12 +39,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 BETAS = [5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3]
 K = 10
 C = 1.5
 CONF = 1 - 1 / math.e
 BATCH = 1024
-PMC_FILE = os.path.join(ROOT, "profiles", "ann_kernel_headline_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "ann_headline_pmc.json")
+CALIB_BYTES = 256 << 20     # copy kernel of known size for counter calibration
 
 
 def log(*a):
@@ -77,7 +84,7 @@ def recall_at_k(ids, truth):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("ann.hip", "internal.hpp"):
+    for f in ("ann.hip", "project.hip", "internal.hpp"):
         with open(os.path.join(ROOT, "paper_2107_05537_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -111,6 +118,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--beta", type=float, default=None, help="skip the sweep")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-truth", action="store_true",
+                    help="skip ground truth and recall (needs --beta; for profiler runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, run a plain 256 MiB device copy (for counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -138,10 +149,14 @@ def main():
     build_s = time.perf_counter() - t0
     log(f"index built in {build_s:.2f} s: {idx.info()}")
 
-    t0 = time.perf_counter()
-    truth = exact_knn_gpu(torch, D, Q, K)
-    torch.cuda.synchronize()
-    log(f"ground truth in {time.perf_counter() - t0:.1f} s")
+    if args.no_truth and args.beta is None:
+        ap.error("--no-truth needs --beta")
+    truth = None
+    if not args.no_truth:
+        t0 = time.perf_counter()
+        truth = exact_knn_gpu(torch, D, Q, K)
+        torch.cuda.synchronize()
+        log(f"ground truth in {time.perf_counter() - t0:.1f} s")
 
     batches = [(s, min(nq, s + BATCH)) for s in range(0, nq, BATCH)]
     ids = torch.empty((nq, K), dtype=torch.int64, device=dev)
@@ -158,6 +173,9 @@ def main():
     chosen = None
     for beta in betas:
         run_all(beta)
+        if truth is None:
+            chosen = beta
+            break
         rec = recall_at_k(ids, truth)
         sweep.append({"beta": beta, "recall@10": round(rec, 4)})
         log(f"beta={beta:g} recall@10={rec:.4f} exits={np.bincount(stats[:, 2].cpu().numpy(), minlength=3).tolist()}")
@@ -173,11 +191,10 @@ def main():
 
     # recall/ratio and algorithmic bytes at the operating point
     run_all(beta)
-    rec = recall_at_k(ids, truth)
+    rec = recall_at_k(ids, truth) if truth is not None else None
     st = stats.cpu().numpy().astype(np.int64)
-    d_pad = (d + 3) // 4 * 4
-    bytes_per_query = 4 * d + 64 * st[:, 3] + 4 * d_pad * st[:, 1] + 12 * K
-    batch_bytes = [float(bytes_per_query[s:e].sum()) for s, e in batches]
+    batch_scan = [float(st[s:e, 3].sum()) for s, e in batches]
+    batch_cand = [float(st[s:e, 1].sum()) for s, e in batches]
 
     # timed region
     for i in range(args.warmup):
@@ -187,8 +204,11 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     queries = 0
-    algo_bytes = 0.0
+    scan_pts = 0.0
+    cand_rows = 0.0
     torch.cuda.synchronize()
+    pm.ann_timing_read(reset=True)
+    pm.ann_timing_enable(True)
     wall0 = time.perf_counter()
     for i in range(args.steps):
         b = i % len(batches)
@@ -197,20 +217,54 @@ def main():
         idx.ann_into(Q[s:e], K, C, CONF, beta, r_min, ids[s:e], dist[s:e], stats[s:e])
         ev[i][1].record()
         queries += e - s
-        algo_bytes += batch_bytes[b]
+        scan_pts += batch_scan[b]
+        cand_rows += batch_cand[b]
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    pm.ann_timing_enable(False)
+    stages = pm.ann_timing_read(reset=True)
     lat = np.array([a.elapsed_time(b) for a, b in ev])          # ms per batch
-    gpu_s = lat.sum() / 1e3
     value = queries / wall
-    achieved = algo_bytes / gpu_s / 1e9
+
+    # roofline of the dominant stage, from its live per-launch duration
+    d_pad = (d + 3) // 4 * 4
+    dom = max(("tau", "filter", "finish", "per_query"), key=lambda k: stages[k]["ms"])
+    launches = max(1, stages[dom]["launches"])
+    per_launch_ms = stages[dom]["ms"] / launches
+    if dom == "filter":
+        # 3 flops (difference, multiply, add) per projected coordinate of
+        # every point of every leaf the range query reaches (16 coordinates)
+        work = 48.0 * scan_pts / launches
+        achieved = work / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    else:
+        # verification rows of C, the query, the output
+        work = (4.0 * d_pad * cand_rows + (4 * d + 12 * K) * queries) / launches
+        achieved = work / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof["kernel"] = {"tau": "tau_kernel", "filter": "filter_kernel",
+                      "finish": "finish_kernel", "per_query": "ann_kernel"}[dom]
+    roof["per_launch_ms"] = round(per_launch_ms, 4)
+    roof["work_per_launch"] = work
 
     traffic = None
     if os.path.exists(PMC_FILE):
         with open(PMC_FILE) as fh:
             pmc = json.load(fh)
-        if pmc.get("kernel_source_sha") == kernel_source_hash():
-            traffic = pmc.get("traffic")
+        kern = pmc.get("kernels", {}).get(roof["kernel"])
+        if pmc.get("kernel_source_sha") == kernel_source_hash() and kern:
+            traffic = kern.get("hbm_bytes_per_launch")
+    roof["traffic"] = traffic
+
+    if args.calib_copy:
+        x = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).uniform_()
+        for _ in range(3):
+            y = x.clone()
+        torch.cuda.synchronize()
+        del x, y
 
     cpu = None
     if not args.no_cpu:
@@ -234,15 +288,14 @@ def main():
                    "k": K, "c": C, "confidence": round(CONF, 6), "m": 15,
                    "beta": beta, "budget_B": B, "r_min": r_min,
                    "batch": BATCH, "parallelism": "single GPU"},
-        "recall@10": round(rec, 4),
+        "recall@10": round(rec, 4) if rec is not None else None,
         "sweep": sweep,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "per": "batch of up to 1,024 queries"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "ann_kernel (with the query projection in the same call)"},
+        "roofline": roof,
+        "stages_ms_per_batch": {k: round(v["ms"] / max(1, args.steps), 4)
+                                for k, v in stages.items()},
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
     }

@@ -205,6 +205,34 @@ int pmlsh_get_index_info(const pmlsh_index* index, pmlsh_index_info* out);
 int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
                               int64_t* offsets);
 
+/*
+ * Tracing aid: per-stage GPU time of pmlsh_ann. While enabled (process-wide),
+ * every kernel launch of the query path is bracketed by two HIP events on the
+ * caller's stream; pmlsh_ann_timing_read() waits for the recorded events and
+ * returns the summed milliseconds and launch counts per stage since the last
+ * reset (reset != 0 clears the totals after reading). Stages:
+ *   PMLSH_STAGE_PROJECT   query projection (FP64 matrix cores)
+ *   PMLSH_STAGE_TAU       per-query bound on the B-th projected distance
+ *   PMLSH_STAGE_FILTER    leaf-major range filter (Eq. 5) and candidate lists
+ *   PMLSH_STAGE_FINISH    budget cut, rounds of Algorithm 2, verification, top-k
+ *   PMLSH_STAGE_PERQUERY  per-query kernel (queries outside the leaf-major path)
+ * Host-side bookkeeping only; enabling it does not change any result.
+ */
+#define PMLSH_STAGE_PROJECT 0
+#define PMLSH_STAGE_TAU 1
+#define PMLSH_STAGE_FILTER 2
+#define PMLSH_STAGE_FINISH 3
+#define PMLSH_STAGE_PERQUERY 4
+#define PMLSH_N_STAGES 5
+
+typedef struct {
+    double ms[PMLSH_N_STAGES];
+    int64_t launches[PMLSH_N_STAGES];
+} pmlsh_ann_timing;
+
+int pmlsh_ann_timing_enable(int enable);
+int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
+
 /* Message of the last failed call on this thread ("" if none). The pointer
  * stays valid until the next failing call on the same thread. */
 const char* pmlsh_last_error(void);

@@ -15,7 +15,8 @@ import os
 
 import numpy as np
 
-__all__ = ["Index", "PmlshError", "plan_params", "library_path", "load_library"]
+__all__ = ["Index", "PmlshError", "plan_params", "library_path", "load_library",
+           "ann_timing_enable", "ann_timing_read"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libpmlsh.so")
@@ -61,6 +62,12 @@ class _Info(ctypes.Structure):
                 ("sample_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
+class _Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5)]
+
+
+STAGES = ("project", "tau", "filter", "finish", "per_query")
+
 _LIB = None
 
 # exported symbol -> (restype, argtypes)
@@ -82,6 +89,8 @@ SIGNATURES = {
     "pmlsh_get_index_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "pmlsh_index_export_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p]),
+    "pmlsh_ann_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "pmlsh_ann_timing_read": (ctypes.c_int, [ctypes.POINTER(_Timing), ctypes.c_int]),
     "pmlsh_last_error": (ctypes.c_char_p, []),
 }
 
@@ -133,6 +142,19 @@ def plan_params(n: int, m: int, k: int, c: float, confidence: float, beta: float
     out = _Plan()
     _check(load_library().pmlsh_plan_params(n, m, k, c, confidence, beta, ctypes.byref(out)))
     return {f: getattr(out, f) for f, _ in _Plan._fields_}
+
+
+def ann_timing_enable(enable: bool = True):
+    """Switch the per-stage HIP-event timing of pmlsh_ann on or off."""
+    _check(load_library().pmlsh_ann_timing_enable(1 if enable else 0))
+
+
+def ann_timing_read(reset: bool = True) -> dict:
+    """Per-stage GPU milliseconds and launch counts since the last reset."""
+    out = _Timing()
+    _check(load_library().pmlsh_ann_timing_read(ctypes.byref(out), 1 if reset else 0))
+    return {name: {"ms": out.ms[i], "launches": out.launches[i]}
+            for i, name in enumerate(STAGES)}
 
 
 class Index:

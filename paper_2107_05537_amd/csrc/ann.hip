@@ -1141,18 +1141,28 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.l_list = L.l_list;
         a.q_cap = (int)L.pool_cap;
         const int lds0 = ann_lds_bytes(0);
-        hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
-        PMLSH_HIP(hipGetLastError());
+        {
+            StageTimer tm(PMLSH_STAGE_TAU, stream);
+            hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
+            PMLSH_HIP(hipGetLastError());
+        }
         dim3 fgrid((unsigned)ann_leaf_blocks(x.n_leaves), (unsigned)((L.nq + FQB - 1) / FQB));
-        hipLaunchKernelGGL(filter_kernel, fgrid, dim3(WG), 0, stream, a);
-        PMLSH_HIP(hipGetLastError());
+        {
+            StageTimer tm(PMLSH_STAGE_FILTER, stream);
+            hipLaunchKernelGGL(filter_kernel, fgrid, dim3(WG), 0, stream, a);
+            PMLSH_HIP(hipGetLastError());
+        }
         PMLSH_HIP(hipFuncSetAttribute((const void*)finish_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        hipLaunchKernelGGL(finish_kernel, dim3((unsigned)L.nq), dim3(WG), lds, stream, a);
-        PMLSH_HIP(hipGetLastError());
+        {
+            StageTimer tm(PMLSH_STAGE_FINISH, stream);
+            hipLaunchKernelGGL(finish_kernel, dim3((unsigned)L.nq), dim3(WG), lds, stream, a);
+            PMLSH_HIP(hipGetLastError());
+        }
     }
     // per-query path: every query when the fast path does not apply, else only
     // the queries the fast path flagged
+    StageTimer tm(PMLSH_STAGE_PERQUERY, stream);
     hipLaunchKernelGGL(ann_kernel, dim3((unsigned)L.nq), dim3(WG), lds, stream, a);
     PMLSH_HIP(hipGetLastError());
 }

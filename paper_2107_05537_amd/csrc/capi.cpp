@@ -85,7 +85,10 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
         for (int64_t q0 = 0; q0 < nq; q0 += batch) {
             const int64_t nb = std::min(batch, nq - q0);
             const float* qb = queries + q0 * x->d;
-            launch_project(qb, nb, x->d, x->d, x->hash, qproj, nullptr, st);
+            {
+                StageTimer tm(PMLSH_STAGE_PROJECT, st);
+                launch_project(qb, nb, x->d, x->d, x->hash, qproj, nullptr, st);
+            }
             AnnLaunch L{};
             L.idx = x;
             L.queries = qb;
@@ -214,6 +217,17 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm, int64_t* 
         std::memcpy(perm, index->perm_host.data(), index->perm_host.size() * sizeof(int32_t));
         const int64_t L = index->leaf_size;
         for (int64_t b = 0; b <= index->n_leaves; ++b) offsets[b] = std::min(index->n, b * L);
+    });
+}
+
+int pmlsh_ann_timing_enable(int enable) {
+    return guarded([&] { timing_set(enable != 0); });
+}
+
+int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset) {
+    return guarded([&] {
+        if (!out) fail(PMLSH_EINVAL, "out is NULL");
+        timing_read(out, reset != 0);
     });
 }
 

@@ -105,6 +105,27 @@ struct pmlsh_index {
 
 namespace pmlsh {
 
+// ---------------------------------------------------------------- timing
+bool timing_enabled();
+void timing_set(bool on);
+void timing_read(pmlsh_ann_timing* out, bool reset);
+
+// Brackets the launches issued during its lifetime with HIP events when
+// per-stage timing is enabled.
+class StageTimer {
+public:
+    StageTimer(int stage, hipStream_t st);
+    ~StageTimer();
+    StageTimer(const StageTimer&) = delete;
+    StageTimer& operator=(const StageTimer&) = delete;
+
+private:
+    int stage_;
+    hipStream_t st_;
+    bool on_ = false;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
 // ---------------------------------------------------------------- kernels
 // Launch wrappers (defined in the .hip translation units). All take the
 // stream the work is enqueued on and throw on launch failure.

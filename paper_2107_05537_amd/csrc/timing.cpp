@@ -1,0 +1,81 @@
+// Opt-in per-stage timing of pmlsh_ann: when enabled, each kernel launch of
+// the query path is bracketed by two HIP events on the caller's stream. The
+// events are resolved (synchronised and summed) only when the totals are
+// read, so enabling the timer adds two event records per launch and no host
+// synchronisation to the query path.
+
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pmlsh {
+namespace {
+
+struct Pending {
+    int stage;
+    hipEvent_t a, b;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Pending> g_pending;
+double g_ms[PMLSH_N_STAGES] = {0};
+int64_t g_count[PMLSH_N_STAGES] = {0};
+
+}  // namespace
+
+bool timing_enabled() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_on;
+}
+
+void timing_set(bool on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_on = on;
+}
+
+StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
+    if (!timing_enabled()) return;
+    PMLSH_HIP(hipEventCreate(&a_));
+    PMLSH_HIP(hipEventCreate(&b_));
+    PMLSH_HIP(hipEventRecord(a_, st_));
+    on_ = true;
+}
+
+StageTimer::~StageTimer() {
+    if (!on_) return;
+    if (hipEventRecord(b_, st_) != hipSuccess) {
+        (void)hipEventDestroy(a_);
+        (void)hipEventDestroy(b_);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_pending.push_back({stage_, a_, b_});
+}
+
+void timing_read(pmlsh_ann_timing* out, bool reset) {
+    std::vector<Pending> p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        p.swap(g_pending);
+    }
+    for (const Pending& e : p) {
+        float ms = 0.f;
+        if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_ms[e.stage] += ms;
+            g_count[e.stage] += 1;
+        }
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int i = 0; i < PMLSH_N_STAGES; ++i) {
+        out->ms[i] = g_ms[i];
+        out->launches[i] = g_count[i];
+        if (reset) { g_ms[i] = 0; g_count[i] = 0; }
+    }
+}
+
+}  // namespace pmlsh
