@@ -425,31 +425,52 @@ __device__ void block_select(Src&& src, Emit&& emit, uint64_t lo, uint64_t hi, i
     }
 }
 
-// Exact squared distances of C entries [v0, v1): 16 lanes per row.
+// Exact squared distances of C entries [v0, v1): 16 lanes per row, each
+// 16-lane group keeping VR rows in flight (VR independent loads per column
+// step) so the gather of 1 KB rows runs at HBM rate rather than at latency.
+constexpr int VR = 4;
+
 __device__ void verify(const AnnArgs& a, const float* qs, const int32_t* cpos, float* cdist,
                        int v0, int v1) {
     const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
     const int d4 = a.d_pad >> 2;
     const float4* q4 = reinterpret_cast<const float4*>(qs);
-    for (int base = v0; base < v1; base += WG / 16) {
-        const int i = base + g;
-        float acc = 0.f;
-        if (i < v1) {
-            const float4* row = reinterpret_cast<const float4*>(a.data + (int64_t)cpos[i] * a.d_pad);
-            for (int c = l16; c < d4; c += 16) {
-                const float4 x = row[c], y = q4[c];
+    constexpr int GROUPS = WG / 16;
+    for (int base = v0; base < v1; base += GROUPS * VR) {
+        const float4* row[VR];
+        bool ok[VR];
+        float acc[VR];
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            const int i = base + g + GROUPS * r;
+            ok[r] = i < v1;
+            row[r] = reinterpret_cast<const float4*>(a.data + (int64_t)cpos[ok[r] ? i : v0] * a.d_pad);
+            acc[r] = 0.f;
+        }
+#pragma unroll 2
+        for (int c = l16; c < d4; c += 16) {
+            float4 x[VR];
+#pragma unroll
+            for (int r = 0; r < VR; ++r) x[r] = row[r][c];
+            const float4 y = q4[c];
+#pragma unroll
+            for (int r = 0; r < VR; ++r) {
                 float t;
-                t = y.x - x.x; acc = __fmaf_rn(t, t, acc);
-                t = y.y - x.y; acc = __fmaf_rn(t, t, acc);
-                t = y.z - x.z; acc = __fmaf_rn(t, t, acc);
-                t = y.w - x.w; acc = __fmaf_rn(t, t, acc);
+                t = y.x - x[r].x; acc[r] = __fmaf_rn(t, t, acc[r]);
+                t = y.y - x[r].y; acc[r] = __fmaf_rn(t, t, acc[r]);
+                t = y.z - x[r].z; acc[r] = __fmaf_rn(t, t, acc[r]);
+                t = y.w - x[r].w; acc[r] = __fmaf_rn(t, t, acc[r]);
             }
         }
-        acc += __shfl_xor(acc, 8, 16);
-        acc += __shfl_xor(acc, 4, 16);
-        acc += __shfl_xor(acc, 2, 16);
-        acc += __shfl_xor(acc, 1, 16);
-        if (i < v1 && l16 == 0) cdist[i] = acc;
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            float v = acc[r];
+            v += __shfl_xor(v, 8, 16);
+            v += __shfl_xor(v, 4, 16);
+            v += __shfl_xor(v, 2, 16);
+            v += __shfl_xor(v, 1, 16);
+            if (ok[r] && l16 == 0) cdist[base + g + GROUPS * r] = v;
+        }
     }
 }
 

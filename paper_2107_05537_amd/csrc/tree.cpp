@@ -8,8 +8,9 @@
 //   * leaves by recursive median splits along the coordinate of largest
 //     variance, the left part always holding a whole number of leaves, so
 //     every leaf has exactly leaf_size points except the last one;
-//   * inner levels by grouping `fanout` consecutive nodes of the level below
-//     (consecutive leaves of the recursion are spatial neighbours).
+//   * inner levels from the binary split tree: level l holds the maximal
+//     subtrees with at most fanout^(H-1-l) leaves, so inner nodes are compact
+//     regions and the fanout is about `fanout` (not exactly).
 // Every node stores what Eq. 5 and Eq. 11 need: a centre e.RO (the mean of
 // its points, rounded to FP32), the covering radius e.r about that centre and
 // the hyper-ring e.HR[i] = [min, max] distance of its points to pivot i, all
@@ -19,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -72,10 +74,28 @@ double dist64(const float* a, const float* b) {
 // leaf boundary, within the middle 60 % of its leaves, where the sorted
 // projections show the widest gap, so cuts fall between clusters rather
 // than through them. Ties in the projection are ordered by id.
+struct BinNode {
+    int64_t leaf_begin, leaf_end;   // leaf range [begin, end)
+    int32_t left, right;            // children (-1 for a leaf)
+};
+
 struct Splitter {
     const float* proj;
     int64_t leaf;
     std::vector<int32_t>& idx;
+    std::vector<BinNode> nodes;
+    std::mutex mu;
+
+    int32_t add_node(int64_t b, int64_t e) {
+        std::lock_guard<std::mutex> lk(mu);
+        nodes.push_back({b / leaf, (e + leaf - 1) / leaf, -1, -1});
+        return (int32_t)nodes.size() - 1;
+    }
+    void set_children(int32_t id, int32_t l, int32_t r) {
+        std::lock_guard<std::mutex> lk(mu);
+        nodes[id].left = l;
+        nodes[id].right = r;
+    }
 
     void direction(int64_t b, int64_t e, double* dir) const {
         double mean[MP] = {0};
@@ -112,9 +132,10 @@ struct Splitter {
         }
     }
 
-    void split(int64_t b, int64_t e, int depth) {
+    int32_t split(int64_t b, int64_t e, int depth) {
+        const int32_t id = add_node(b, e);
         const int64_t cnt = e - b;
-        if (cnt <= leaf) return;
+        if (cnt <= leaf) return id;
         const int64_t nleaves = (cnt + leaf - 1) / leaf;
         double dir[MP];
         direction(b, e, dir);
@@ -142,14 +163,17 @@ struct Splitter {
         const int64_t mid = b + best * leaf;
         key.clear();
         key.shrink_to_fit();
+        int32_t l = -1, r = -1;
         if (depth < 4 && cnt > 200000) {
-            std::thread left([&] { split(b, mid, depth + 1); });
-            split(mid, e, depth + 1);
+            std::thread left([&] { l = split(b, mid, depth + 1); });
+            r = split(mid, e, depth + 1);
             left.join();
         } else {
-            split(b, mid, depth + 1);
-            split(mid, e, depth + 1);
+            l = split(b, mid, depth + 1);
+            r = split(mid, e, depth + 1);
         }
+        set_children(id, l, r);
+        return id;
     }
 };
 
@@ -189,24 +213,45 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
         }
     }
 
-    // ---- leaf order by recursive median splits
+    // ---- leaf order by recursive gap-aware splits; the binary split tree is
+    // recorded (leaf ranges) to derive the inner levels from it
     T.perm.resize(n);
     std::iota(T.perm.begin(), T.perm.end(), 0);
     Splitter sp{proj, leaf_size, T.perm};
     sp.split(0, n, 0);
+    const int64_t n_leaves = (n + leaf_size - 1) / leaf_size;
+    const std::vector<BinNode>& bt = sp.nodes;   // node 0 is the root
 
-    // ---- level sizes, bottom-up; stored top-down
-    std::vector<int64_t> sizes;  // bottom-up node counts
-    int64_t cnt = (n + leaf_size - 1) / leaf_size;
-    sizes.push_back(cnt);
-    while (cnt > fanout) {
-        cnt = (cnt + fanout - 1) / fanout;
-        sizes.push_back(cnt);
+    // Level l (of H) holds the maximal binary subtrees with at most
+    // fanout^(H-1-l) leaves, left to right: compact regions, nested in the
+    // level above, each a contiguous range of leaves. H is the smallest depth
+    // whose top level has at most `fanout` nodes.
+    auto level_nodes = [&](int64_t cap) {
+        std::vector<std::pair<int64_t, int64_t>> out;   // leaf ranges
+        std::vector<int32_t> stack{0};
+        while (!stack.empty()) {
+            const BinNode& b = bt[stack.back()];
+            stack.pop_back();
+            if (b.leaf_end - b.leaf_begin <= cap || b.left < 0) {
+                out.push_back({b.leaf_begin, b.leaf_end});
+            } else {
+                stack.push_back(b.right);
+                stack.push_back(b.left);
+            }
+        }
+        return out;
+    };
+    std::vector<int64_t> caps{1};                    // bottom-up
+    while (true) {
+        const int64_t cap = caps.back();
+        if (cap >= n_leaves || (int64_t)level_nodes(cap).size() <= fanout) break;
+        caps.push_back(cap * fanout);
     }
-    T.levels = (int)sizes.size();
+    T.levels = (int)caps.size();
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> lv(T.levels);
+    for (int l = 0; l < T.levels; ++l) lv[l] = level_nodes(caps[T.levels - 1 - l]);
     T.level_begin.assign(T.levels + 1, 0);
-    for (int l = 0; l < T.levels; ++l)
-        T.level_begin[l + 1] = T.level_begin[l] + sizes[T.levels - 1 - l];
+    for (int l = 0; l < T.levels; ++l) T.level_begin[l + 1] = T.level_begin[l] + (int64_t)lv[l].size();
     T.n_nodes = T.level_begin[T.levels];
     const int64_t N = T.n_nodes;
     T.centre.assign((size_t)MP * N, 0.f);
@@ -217,28 +262,26 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
     T.child_end.assign(N, 0);
     T.npts.assign(N, 0);
 
-    // point range [p0, p1) of every node, in leaf order
+    // point range [p0, p1) of every node, in leaf order; children are the
+    // nodes of the next level inside the node's leaf range
     std::vector<int64_t> p0(N), p1(N);
-    for (int l = T.levels - 1; l >= 0; --l) {
-        const int64_t lb = T.level_begin[l], le = T.level_begin[l + 1];
-        const int64_t group = [&] {
-            int64_t g = leaf_size;
-            for (int u = T.levels - 1; u > l; --u) g *= fanout;
-            return g;
-        }();
-        for (int64_t i = lb; i < le; ++i) {
-            const int64_t j = i - lb;
-            p0[i] = j * group;
-            p1[i] = std::min<int64_t>(n, (j + 1) * group);
+    for (int l = 0; l < T.levels; ++l) {
+        size_t c = 0;   // cursor into the next level
+        for (size_t j = 0; j < lv[l].size(); ++j) {
+            const int64_t i = T.level_begin[l] + (int64_t)j;
+            const int64_t lb = lv[l][j].first, le = lv[l][j].second;
+            p0[i] = lb * leaf_size;
+            p1[i] = std::min<int64_t>(n, le * leaf_size);
             T.npts[i] = (int32_t)(p1[i] - p0[i]);
             if (l == T.levels - 1) {
                 T.child_begin[i] = (int32_t)p0[i];
                 T.child_end[i] = (int32_t)p1[i];
             } else {
-                const int64_t cb = T.level_begin[l + 1] + j * fanout;
-                const int64_t ce = std::min<int64_t>(T.level_begin[l + 2], cb + fanout);
-                T.child_begin[i] = (int32_t)cb;
-                T.child_end[i] = (int32_t)ce;
+                const std::vector<std::pair<int64_t, int64_t>>& nx = lv[l + 1];
+                const size_t c0 = c;
+                while (c < nx.size() && nx[c].second <= le) ++c;
+                T.child_begin[i] = (int32_t)(T.level_begin[l + 1] + (int64_t)c0);
+                T.child_end[i] = (int32_t)(T.level_begin[l + 1] + (int64_t)c);
             }
         }
     }
