@@ -74,6 +74,7 @@ struct AnnArgs {
     float* q_tau;
     float* q_tau2;
     float* q_slack;
+    float* q_thr;               // tau^2 + margin - ||q'||^2 (cheap-bound threshold)
     int32_t* q_flag;
     uint32_t* l_count;          // candidates per query
     uint32_t* q_scanned;
@@ -797,215 +798,254 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         a.q_tau[qi] = R;
         a.q_tau2[qi] = R2;
         a.q_slack[qi] = slack;
+        // Threshold of the filter's cheap bound ||o'||^2 - 2 q'.o' <= thr. The
+        // FP32 errors of ||q'||^2, ||o'||^2 and q'.o' (16-term chains) and of
+        // the two roundings here stay below 72 u (||q'|| + S)^2, S bounding
+        // every ||o'||; 96 u covers them, so no point whose computed pd^2 is
+        // within tau^2 is discarded.
+        const float u = 5.9604645e-08f;   // 2^-24
+        const float big = sqrtf(qc.qn2) + a.coord_scale;
+        a.q_thr[qi] = (R2 + 96.f * u * big * big) - qc.qn2;
         a.l_count[qi] = 0u;
         a.q_scanned[qi] = 0u;
         a.q_flag[qi] = 0;
     }
 }
 
-constexpr int FQB = 128;   // queries per filter block
-constexpr int FLB = 32;    // leaves per filter block (FLB / NWAVE per wave)
+constexpr int FQB = 128;   // queries per filter block (two 64-bit masks per leaf)
+constexpr int FLB = 32;    // leaves per filter block
 constexpr int STG = 1024;  // hits staged in LDS per filter block
 constexpr uint8_t kStageUnused = 0xff;   // stage entry reserved but not written
+static_assert(FQB == 128, "a leaf's passing queries are two 64-bit masks");
 static_assert(FQB < kStageUnused, "query index of a block must fit below the marker");
 
-// Leaf-major range filter over one (leaf block, query block) tile. Each leaf
-// of the block is loaded once into registers (one point per lane); its Eq. 5
-// test runs with one query per lane, then every passing query is compared
-// with the leaf's points:
-//   * a cheap bound |q'|^2 + |o'|^2 - 2 q'.o' (16 FMAs) with a rounding margin
-//     discards points that cannot be within tau;
-//   * the remaining points get the exact direct-difference pd^2, the value
-//     every later decision uses; pd^2 <= tau^2 is a hit.
-// Hits are staged in LDS and written at the end with one reservation per
-// (block, query) in the query's region of the pool; a full stage falls back
-// to direct reservations. A region that overflows flags its query for the
-// per-query kernel.
+// Arrays the filter reads at wave-uniform addresses and never writes. Read
+// through the constant address space they become scalar loads, and their
+// values enter the vector FMAs as SGPR operands.
+typedef __attribute__((address_space(4))) const float cfloat;
+typedef __attribute__((address_space(4))) const int32_t cint32;
+
+struct FilterShared {
+    uint64_t mask[FLB][2];      // queries passing Eq. 5 for each leaf
+    uint2 stg[STG];             // staged hits (leaf position, pd^2 bits)
+    uint8_t stq[STG];           // query of each staged hit
+    uint32_t hits[FQB], base[FQB], scan[FQB];
+    uint32_t nstg, next;
+};
+
+// Appends this wave's hits for query q (block-local) to the stage; when the
+// stage is full they are reserved in the query's region of the pool directly.
+__device__ __forceinline__ void stage_hits(const AnnArgs& a, FilterShared& fs, bool hit,
+                                           uint32_t pp, float pd2, int q, int64_t gq) {
+    const uint64_t hm = __ballot(hit);
+    if (!hm) return;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)hm) - 1;
+    const uint32_t nh = (uint32_t)__popcll(hm);
+    const uint32_t rank = (uint32_t)__popcll(hm & lanemask_lt());
+    uint32_t b = 0;
+    if (lane == leader) b = atomicAdd(&fs.nstg, nh);
+    b = __shfl(b, leader);
+    if (b + nh <= (uint32_t)STG) {
+        if (hit) {
+            fs.stg[b + rank] = make_uint2(pp, __float_as_uint(pd2));
+            fs.stq[b + rank] = (uint8_t)q;
+        }
+    } else {
+        // stage full: the part of this reservation inside the stage is marked
+        // unused, and the hits go to the query's region directly
+        if (hit && b + rank < (uint32_t)STG) fs.stq[b + rank] = kStageUnused;
+        uint32_t g = 0;
+        if (lane == leader) g = atomicAdd(&a.l_count[gq], nh);
+        g = __shfl(g, leader);
+        const uint32_t slot = g + rank;
+        if (hit && slot < (uint32_t)a.q_cap)
+            a.l_list[gq * a.q_cap + slot] = make_uint2(pp, __float_as_uint(pd2));
+    }
+}
+
+// Leaf-major range filter over one (leaf block, query block) tile.
+//   Phase 1: the Eq. 5 test of every (leaf, query) pair of the tile, one
+//            query per lane; the passing queries of each leaf become a
+//            128-bit mask in LDS.
+//   Phase 2: waves take leaves from a shared counter. A leaf's points are
+//            held in registers (one point per lane) while its passing queries
+//            are taken two at a time; each query's projection is read with
+//            scalar loads. A cheap bound ||o'||^2 - 2 q'.o' <= thr (thr =
+//            tau^2 + margin - ||q'||^2, set by the bound kernel) discards
+//            points that cannot lie within tau; the survivors get the exact
+//            direct-difference pd^2, the value every later decision uses, and
+//            pd^2 <= tau^2 is a hit.
+//   Phase 3: staged hits are written with one reservation per (block, query)
+//            in the query's region of the pool. A region that overflows
+//            makes the finishing kernel hand its query to the per-query path.
 __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
-    __shared__ __align__(16) float sq[FQB][MP];     // query rows (broadcast reads)
-    __shared__ float sqt[MP][FQB];                  // transposed (per-lane reads)
-    __shared__ float sr[FQB], sr2[FQB], ssl[FQB], sqn[FQB], smg[FQB];
-    __shared__ float spv[PMLSH_MAX_PIVOTS][FQB];
-    __shared__ uint32_t shits[FQB], sbase[FQB], sscan[FQB];
-    __shared__ uint2 stg[STG];
-    __shared__ uint8_t stq[STG];
-    __shared__ uint32_t nstg;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    __shared__ FilterShared fs;
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q0 = blockIdx.y * FQB;
     const int nqb = min(FQB, a.nq - q0);
-    const float u = 5.9604645e-08f;   // 2^-24
-    for (int e = threadIdx.x; e < nqb * MP; e += WG) {
-        const float v = a.qp[(int64_t)q0 * MP + e];
-        sq[e / MP][e % MP] = v;
-        sqt[e % MP][e / MP] = v;
-    }
-    if (threadIdx.x == 0) nstg = 0u;
+    const int64_t leaf0 = (int64_t)blockIdx.x * FLB;
+    const int nlb = (int)(a.n_leaves - leaf0 < FLB ? a.n_leaves - leaf0 : FLB);
+    const int leaf_base = a.level_begin[a.levels - 1];
     for (int e = threadIdx.x; e < FQB; e += WG) {
-        shits[e] = 0u;
-        sscan[e] = 0u;
+        fs.hits[e] = 0u;
+        fs.scan[e] = 0u;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nqb; e += WG) {
-        sr[e] = a.q_tau[q0 + e];
-        sr2[e] = a.q_tau2[q0 + e];
-        ssl[e] = a.q_slack[q0 + e];
-        float n2 = 0.f;
-#pragma unroll
-        for (int t = 0; t < MP; ++t) n2 = fmaf(sq[e][t], sq[e][t], n2);
-        sqn[e] = n2;
-        const float big = sqrtf(n2) + a.coord_scale;
-        smg[e] = 64.f * u * big * big;     // bound on the error of the cheap form
-    }
-    for (int e = threadIdx.x; e < nqb * PMLSH_MAX_PIVOTS; e += WG) {
-        const int q = e / PMLSH_MAX_PIVOTS, i = e % PMLSH_MAX_PIVOTS;
-        float acc = 0.f;
-        if (i < a.s) {
-#pragma unroll
-            for (int j = 0; j < MP; ++j) {
-                const float t = sq[q][j] - a.piv[i * MP + j];
-                acc = fmaf(t, t, acc);
-            }
-        }
-        spv[i][q] = sqrtf(acc);
+    if (threadIdx.x == 0) {
+        fs.nstg = 0u;
+        fs.next = 0u;
     }
     __syncthreads();
 
-    const int leaf_base = a.level_begin[a.levels - 1];
-    for (int j = wave; j < FLB; j += NWAVE) {
-        const int64_t leaf = (int64_t)blockIdx.x * FLB + j;
-        if (leaf >= a.n_leaves) break;
-        const int node = leaf_base + (int)leaf;
-        float cen[MP];
+    // Phase 1: waves 0 and 2 take queries 0..63, waves 1 and 3 queries
+    // 64..127; waves 0, 1 take the even leaves, waves 2, 3 the odd ones.
+    {
+        const int half = wave & 1;
+        const int ql = half * 64 + lane;
+        const bool qok = ql < nqb;
+        const int64_t gq = q0 + (qok ? ql : 0);
+        float qv[MP];
 #pragma unroll
-        for (int t = 0; t < MP; ++t) cen[t] = a.ncen[(int64_t)t * a.n_nodes + node];
-        float hmin[PMLSH_MAX_PIVOTS], hmax[PMLSH_MAX_PIVOTS];
+        for (int t = 0; t < MP; ++t) qv[t] = a.qp[gq * MP + t];
+        const float R = a.q_tau[gq], sl = a.q_slack[gq];
+        cfloat* piv = (cfloat*)a.piv;
+        float pv[PMLSH_MAX_PIVOTS];
 #pragma unroll
         for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i) {
-            hmin[i] = i < a.s ? a.hrmin[(int64_t)i * a.n_nodes + node] : 0.f;
-            hmax[i] = i < a.s ? a.hrmax[(int64_t)i * a.n_nodes + node] : 0.f;
+            float acc = 0.f;
+            if (i < a.s) {
+#pragma unroll
+                for (int t = 0; t < MP; ++t) {
+                    const float d = qv[t] - piv[i * MP + t];
+                    acc = fmaf(d, d, acc);
+                }
+            }
+            pv[i] = sqrtf(acc);
         }
-        const float rad = a.nrad[node];
-        const int p0 = a.cb[node], p1 = a.ce[node];
-        const bool small_leaf = p1 - p0 <= 64;
-        // this lane's point while the leaf fits one wave
-        float o[MP];
-        float on2 = 0.f;
-        if (small_leaf) {
-            const int pos = p0 + lane < p1 ? p0 + lane : p0;
-            const float4* o4 = reinterpret_cast<const float4*>(a.proj + (int64_t)pos * MP);
+        cfloat* cen = (cfloat*)a.ncen;
+        cfloat* rad = (cfloat*)a.nrad;
+        cfloat* hmin = (cfloat*)a.hrmin;
+        cfloat* hmax = (cfloat*)a.hrmax;
+        cint32* npts = (cint32*)a.npts;
+        uint32_t scanned = 0;
+        for (int j = wave >> 1; j < nlb; j += 2) {
+            const int node = leaf_base + (int)leaf0 + j;
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < MP; ++t) {
+                const float d = qv[t] - cen[(int64_t)t * a.n_nodes + node];
+                acc = fmaf(d, d, acc);
+            }
+            bool pass = qok & (sqrtf(acc) <= rad[node] + R + sl);
+#pragma unroll
+            for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i)
+                if (i < a.s)
+                    pass = pass & (pv[i] - R <= hmax[(int64_t)i * a.n_nodes + node] + sl) &
+                           (pv[i] + R >= hmin[(int64_t)i * a.n_nodes + node] - sl);
+            const uint64_t m = __ballot(pass);
+            if (lane == 0) fs.mask[j][half] = m;
+            if (pass) scanned += (uint32_t)npts[node];
+        }
+        if (scanned) atomicAdd(&fs.scan[ql], scanned);
+    }
+    __syncthreads();
+
+    // Phase 2
+    cfloat* qpc = (cfloat*)a.qp;
+    cfloat* thr = (cfloat*)a.q_thr;
+    cfloat* tau2 = (cfloat*)a.q_tau2;
+    cint32* cb = (cint32*)a.cb;
+    cint32* ce = (cint32*)a.ce;
+    for (;;) {
+        uint32_t jn = 0;
+        if (lane == 0) jn = atomicAdd(&fs.next, 1u);
+        const int j = __builtin_amdgcn_readfirstlane((int)__shfl(jn, 0));
+        if (j >= nlb) break;
+        const uint64_t mk0 = fs.mask[j][0], mk1 = fs.mask[j][1];
+        const uint64_t m0i = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(mk0 >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mk0);
+        const uint64_t m1i = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(mk1 >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mk1);
+        if (!(m0i | m1i)) continue;
+        const int node = leaf_base + (int)leaf0 + j;
+        const int p0 = cb[node], p1 = ce[node];
+        for (int base = p0; base < p1; base += 64) {
+            const int pp = base + lane;
+            const bool valid = pp < p1;
+            float o[MP];
+            const float4* o4 = reinterpret_cast<const float4*>(a.proj + (int64_t)(valid ? pp : base) * MP);
 #pragma unroll
             for (int t = 0; t < MP / 4; ++t) {
                 const float4 v = o4[t];
                 o[4 * t] = v.x; o[4 * t + 1] = v.y; o[4 * t + 2] = v.z; o[4 * t + 3] = v.w;
             }
+            float on2 = 0.f;
 #pragma unroll
             for (int t = 0; t < MP; ++t) on2 = fmaf(o[t], o[t], on2);
-        }
-        for (int qb = 0; qb < nqb; qb += 64) {
-            // Eq. 5 for (this leaf, query qb + lane)
-            const int ql = qb + lane;
-            bool pass = false;
-            if (ql < nqb) {
-                float acc = 0.f;
+            // the two halves of the mask, two queries at a time
 #pragma unroll
-                for (int t = 0; t < MP; ++t) {
-                    const float d = sqt[t][ql] - cen[t];
-                    acc = fmaf(d, d, acc);
-                }
-                const float R = sr[ql], sl = ssl[ql];
-                pass = sqrtf(acc) <= rad + R + sl;
+            for (int h = 0; h < 2; ++h) {
+                uint64_t m = h ? m1i : m0i;
+                while (m) {
+                    const int qa = h * 64 + __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const bool has_b = m != 0;
+                    const int qb = has_b ? h * 64 + __ffsll((unsigned long long)m) - 1 : qa;
+                    m &= m - 1;
+                    const int64_t ga = q0 + qa, gb = q0 + qb;
+                    cfloat* va = qpc + ga * MP;
+                    cfloat* vb = qpc + gb * MP;
+                    const float ta = thr[ga], tb = thr[gb];
+                    const float ra = tau2[ga], rb = tau2[gb];
+                    float da = 0.f, db = 0.f;
 #pragma unroll
-                for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i)
-                    if (i < a.s)
-                        pass = pass && (spv[i][ql] - R <= hmax[i] + sl) &&
-                               (spv[i][ql] + R >= hmin[i] - sl);
-            }
-            uint64_t m = __ballot(pass);
-            while (m) {
-                const int bit = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1;
-                const int q = qb + bit;
-                const int64_t gq = q0 + q;
-                const float R2 = sr2[q];
-                if (lane == 0) atomicAdd(&sscan[q], (uint32_t)(p1 - p0));
-                const float4* qv4 = reinterpret_cast<const float4*>(&sq[q][0]);
-                float qv[MP];
-#pragma unroll
-                for (int t = 0; t < MP / 4; ++t) {
-                    const float4 v = qv4[t];
-                    qv[4 * t] = v.x; qv[4 * t + 1] = v.y; qv[4 * t + 2] = v.z; qv[4 * t + 3] = v.w;
-                }
-                for (int base = p0; base < p1; base += 64) {
-                    const int pp = base + lane;
-                    const bool v2 = pp < p1;
-                    bool hit = false;
-                    float pd2 = 0.f;
-                    if (small_leaf) {
-                        float dot = 0.f;
-#pragma unroll
-                        for (int t = 0; t < MP; ++t) dot = fmaf(qv[t], o[t], dot);
-                        const float approx = sqn[q] + on2 - 2.f * dot;
-                        if (v2 && approx <= R2 + smg[q]) {
-                            float acc = 0.f;
-#pragma unroll
-                            for (int t = 0; t < MP; ++t) {
-                                const float d = __fsub_rn(qv[t], o[t]);
-                                acc = __fmaf_rn(d, d, acc);
-                            }
-                            pd2 = acc;
-                            hit = pd2 <= R2;
-                        }
-                    } else if (v2) {
-                        pd2 = proj_dist2(a.proj + (int64_t)pp * MP, qv);
-                        hit = pd2 <= R2;
+                    for (int t = 0; t < MP; ++t) {
+                        da = fmaf(va[t], o[t], da);
+                        db = fmaf(vb[t], o[t], db);
                     }
-                    const uint64_t hm = __ballot(hit);
-                    if (hm) {
-                        const int leader = __ffsll((unsigned long long)hm) - 1;
-                        const uint32_t nh = (uint32_t)__popcll(hm);
-                        const uint32_t rank = (uint32_t)__popcll(hm & lanemask_lt());
-                        uint32_t b = 0;
-                        if (lane == leader) b = atomicAdd(&nstg, nh);
-                        b = __shfl(b, leader);
-                        if (b + nh <= (uint32_t)STG) {
-                            if (hit) {
-                                stg[b + rank] = make_uint2((uint32_t)pp, __float_as_uint(pd2));
-                                stq[b + rank] = (uint8_t)q;
-                            }
-                        } else {
-                            // stage full: the part of this reservation that lies
-                            // inside the stage is marked unused, and the hits are
-                            // reserved in the query's region directly
-                            if (hit && b + rank < (uint32_t)STG) stq[b + rank] = kStageUnused;
-                            uint32_t g = 0;
-                            if (lane == leader) g = atomicAdd(&a.l_count[gq], nh);
-                            g = __shfl(g, leader);
-                            const uint32_t slot = g + rank;
-                            if (hit && slot < (uint32_t)a.q_cap)
-                                a.l_list[gq * a.q_cap + slot] = make_uint2((uint32_t)pp, __float_as_uint(pd2));
+                    const bool ca = valid & (fmaf(-2.f, da, on2) <= ta);
+                    const bool cb2 = valid & has_b & (fmaf(-2.f, db, on2) <= tb);
+                    if (__ballot(ca)) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int t = 0; t < MP; ++t) {
+                            const float d = __fsub_rn(va[t], o[t]);
+                            acc = __fmaf_rn(d, d, acc);
                         }
+                        stage_hits(a, fs, ca & (acc <= ra), (uint32_t)pp, acc, qa, ga);
+                    }
+                    if (__ballot(cb2)) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int t = 0; t < MP; ++t) {
+                            const float d = __fsub_rn(vb[t], o[t]);
+                            acc = __fmaf_rn(d, d, acc);
+                        }
+                        stage_hits(a, fs, cb2 & (acc <= rb), (uint32_t)pp, acc, qb, gb);
                     }
                 }
             }
         }
     }
     __syncthreads();
-    // flush the stage: one reservation per query of the block
-    const uint32_t ns = nstg < (uint32_t)STG ? nstg : (uint32_t)STG;
+
+    // Phase 3: flush the stage with one reservation per query of the block
+    const uint32_t ns = fs.nstg < (uint32_t)STG ? fs.nstg : (uint32_t)STG;
     for (uint32_t e = threadIdx.x; e < ns; e += WG)
-        if (stq[e] != kStageUnused) atomicAdd(&shits[stq[e]], 1u);
+        if (fs.stq[e] != kStageUnused) atomicAdd(&fs.hits[fs.stq[e]], 1u);
     __syncthreads();
     for (int e = threadIdx.x; e < nqb; e += WG) {
-        if (shits[e]) sbase[e] = atomicAdd(&a.l_count[q0 + e], shits[e]);
-        if (sscan[e]) atomicAdd(&a.q_scanned[q0 + e], sscan[e]);
-        shits[e] = 0u;
+        if (fs.hits[e]) fs.base[e] = atomicAdd(&a.l_count[q0 + e], fs.hits[e]);
+        if (fs.scan[e]) atomicAdd(&a.q_scanned[q0 + e], fs.scan[e]);
+        fs.hits[e] = 0u;
     }
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < ns; e += WG) {
-        const int q = stq[e];
+        const int q = fs.stq[e];
         if (q == kStageUnused) continue;
-        const uint32_t slot = sbase[q] + atomicAdd(&shits[q], 1u);
-        if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = stg[e];
+        const uint32_t slot = fs.base[q] + atomicAdd(&fs.hits[q], 1u);
+        if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = fs.stg[e];
     }
 }
 
@@ -1156,6 +1196,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.q_tau = L.q_tau;
         a.q_tau2 = L.q_tau2;
         a.q_slack = L.q_slack;
+        a.q_thr = L.q_thr;
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;

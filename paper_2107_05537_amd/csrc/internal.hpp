@@ -155,6 +155,7 @@ struct AnnLaunch {
     float* q_tau;
     float* q_tau2;
     float* q_slack;
+    float* q_thr;
     int32_t* q_flag;
     uint32_t* l_count;
     uint32_t* q_scanned;
