@@ -164,18 +164,25 @@ __device__ __forceinline__ float node_dist(const AnnArgs& a, int node, const flo
 
 // Eq. 5: the node is accessed iff its covering ball and every pivot ring can
 // hold a point within R of q'. `slack` absorbs FP32 rounding (conservative).
+// All of the node's data is loaded before any test, so the loads overlap.
 __device__ __forceinline__ bool node_pass(const AnnArgs& a, int node, const float* qp,
                                           const float* qpiv, float R, float slack) {
-    if (node_dist(a, node, qp) > a.nrad[node] + R + slack) return false;
+    float hmn[PMLSH_MAX_PIVOTS], hmx[PMLSH_MAX_PIVOTS];
 #pragma unroll
     for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i) {
+        hmn[i] = hmx[i] = 0.f;
         if (i < a.s) {
-            const int64_t o = (int64_t)i * a.n_nodes + node;
-            if (qpiv[i] - R > a.hrmax[o] + slack) return false;
-            if (qpiv[i] + R < a.hrmin[o] - slack) return false;
+            hmn[i] = a.hrmin[(int64_t)i * a.n_nodes + node];
+            hmx[i] = a.hrmax[(int64_t)i * a.n_nodes + node];
         }
     }
-    return true;
+    const float rad = a.nrad[node];
+    bool pass = node_dist(a, node, qp) <= rad + R + slack;
+#pragma unroll
+    for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i)
+        if (i < a.s)
+            pass = pass & (qpiv[i] - R <= hmx[i] + slack) & (qpiv[i] + R >= hmn[i] - slack);
+    return pass;
 }
 
 __device__ __forceinline__ int shift_for(uint64_t lo, uint64_t hi) {
@@ -233,7 +240,7 @@ __device__ __forceinline__ int radius_bin(float v, uint32_t base) {
 // nearest points are those of the ball of the original radius.
 __device__ int traverse(const AnnArgs& a, const float* qp, const float* qpiv, float& R,
                         float slack, bool shrink, int budget, int32_t* fa, int32_t* fb,
-                        Smem& sh, bool tau_only = false) {
+                        Smem& sh) {
     int ncur = a.level_begin[1] - a.level_begin[0];
     for (int l = 0; l < a.levels; ++l) {
         const bool leaf_level = (l == a.levels - 1);
@@ -282,10 +289,6 @@ __device__ int traverse(const AnnArgs& a, const float* qp, const float* qpiv, fl
                 Rn = tau < R ? tau : R;
             }
             __syncthreads();
-        }
-        if (tau_only && leaf_level) {
-            R = Rn;
-            return np;     // the leaves passing at the incoming radius, in fb
         }
         // C: keep what passes at the lowered radius; expand inner nodes into fa
         if (threadIdx.x == 0) sh.cnt1 = 0;
@@ -695,105 +698,157 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
 // Queries whose list overflows (or that fall outside the path) are flagged
 // and answered by the per-query kernel above.
 
+// Shift that maps the 32-bit keys [lo, hi] onto NB bins: (key - lo) >> shift.
+__device__ __forceinline__ int shift32(uint32_t lo, uint32_t hi) {
+    const uint32_t span = hi - lo;
+    if (span < (uint32_t)NB) return 0;
+    return (32 - __clz((int)span)) - 11;
+}
+
+// Upper bound tau on the budget-th smallest projected distance of one query:
+//   1. squared distance from q' to every leaf centre;
+//   2. the leaves nearest to q' that hold at least min(n, 4 * budget) points,
+//      chosen with a histogram of those distances weighted by leaf sizes;
+//   3. over the points of the chosen leaves, the budget-th smallest pd^2
+//      (upper edge of its histogram bin) is tau^2.
+// The chosen points are data points, so the ball of radius tau holds at least
+// `budget` points and therefore the budget nearest points by projected
+// distance. The choice of leaves only affects how tight tau is, never its
+// validity, so the centre distances need no care about rounding.
 __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
     const int64_t qi = blockIdx.x;
     QueryCtx qc;
     load_query(a, qi, nullptr, qc);
-    // starting radius: the largest upper bound over the top level, which
-    // every point of the data satisfies
-    float ub0 = 0.f;
-    for (int i = a.level_begin[0] + threadIdx.x; i < a.level_begin[1]; i += WG)
-        ub0 = fmaxf(ub0, node_dist(a, i, qc.qp) + a.nrad[i]);
-    for (int off = 32; off > 0; off >>= 1) ub0 = fmaxf(ub0, __shfl_xor(ub0, off));
-    if (lane_id() == 0) sh.red[threadIdx.x >> 6] = __float_as_int(ub0);
-    __syncthreads();
-    float R = 0.f;
-    for (int w = 0; w < NWAVE; ++w) R = fmaxf(R, __int_as_float(sh.red[w]));
-    __syncthreads();
-    const float slack = 1e-5f * (sqrtf(qc.qn2) + a.coord_scale + R);
-    R = R + 2.f * slack;
-    int32_t* fa = a.ws_front + qi * 2 * a.n_leaves;
-    int32_t* lv = fa + a.n_leaves;
-    const int np = traverse(a, qc.qp, qc.qpiv, R, slack, true, a.budget, fa, lv, sh, true);
-    float R2 = (float)((double)R * (double)R);
+    const int nl = (int)a.n_leaves;
+    const int leaf_base = a.level_begin[a.levels - 1];
+    float* dl = reinterpret_cast<float*>(a.ws_front + qi * 2 * a.n_leaves);
+    int32_t* sel = a.ws_front + qi * 2 * a.n_leaves + a.n_leaves;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
 
-    // Refinement: among the candidate leaves nearest to q' by centre distance
-    // (at least 4B points), the exact B-th smallest projected distance is an
-    // upper bound on the B-th smallest over the whole data, and a tight one.
-    {
-        const uint32_t hb = __float_as_uint(R) >> 15;
-        const uint32_t base = hb > (uint32_t)(NB - 1) ? hb - (uint32_t)(NB - 1) : 0u;
-        clear_hist(sh);
-        int loc = 0;
-        for (int i = threadIdx.x; i < np; i += WG) {
-            const int node = lv[i];
-            const float dd = node_dist(a, node, qc.qp);
-            if (dd <= R) {
-                atomicAdd(&sh.hist[radius_bin(dd, base)], (uint32_t)a.npts[node]);
-                loc += a.npts[node];
+    // 1: centre distances, four leaves in flight per thread
+    constexpr int U = 4;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    for (int i0 = threadIdx.x; i0 < nl; i0 += U * WG) {
+        float acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = min(i0 + u * WG, nl - 1);
+                const float dd = qc.qp[t] - a.ncen[(int64_t)t * a.n_nodes + leaf_base + i];
+                acc[u] = fmaf(dd, dd, acc[u]);
             }
         }
-        __syncthreads();
-        const int total = block_sum(loc, sh);
-        if (total >= a.budget) {
-            const int want = total < 4 * a.budget ? total : 4 * a.budget;
-            if (threadIdx.x == 0) sh.thr_bin = NB - 1;
-            __syncthreads();
-            find_threshold(want, sh);
-            const float dedge = __uint_as_float((base + (uint32_t)sh.thr_bin + 1u) << 15);
-            __syncthreads();
-            // compact those leaves (thread-parallel) into fa
-            if (threadIdx.x == 0) sh.cnt1 = 0;
-            __syncthreads();
-            for (int b0 = 0; b0 < np; b0 += WG) {
-                const int i = b0 + threadIdx.x;
-                bool take = false;
-                int node = 0;
-                if (i < np) {
-                    node = lv[i];
-                    take = node_dist(a, node, qc.qp) < dedge;
-                }
-                const int slot = wave_append(take, &sh.cnt1);
-                if (take && slot < a.n_leaves) fa[slot] = node;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * WG;
+            if (i < nl) {
+                dl[i] = acc[u];
+                const uint32_t b = __float_as_uint(acc[u]);
+                lo = min(lo, b);
+                hi = max(hi, b);
             }
-            __syncthreads();
-            const int nsel = sh.cnt1 < a.n_leaves ? sh.cnt1 : (int)a.n_leaves;
-            // histogram of pd^2 over the points of those leaves
-            const uint32_t hb2 = __float_as_uint(R2) >> 15;
-            const uint32_t base2 = hb2 > (uint32_t)(NB - 1) ? hb2 - (uint32_t)(NB - 1) : 0u;
-            clear_hist(sh);
-            int cnt = 0;
-            const int lane = lane_id(), wave = threadIdx.x >> 6;
-            for (int li = wave; li < nsel; li += NWAVE) {
-                const int node = fa[li];
-                const int p0 = a.cb[node], p1 = a.ce[node];
-                for (int b0 = p0; b0 < p1; b0 += 64) {
-                    const int pos = b0 + lane;
-                    if (pos < p1) {
-                        const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
-                        if (pd2 <= R2) {
-                            atomicAdd(&sh.hist[radius_bin(pd2, base2)], 1u);
-                            ++cnt;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            if (block_sum(cnt, sh) >= a.budget) {
-                if (threadIdx.x == 0) sh.thr_bin = NB - 1;
-                __syncthreads();
-                find_threshold(a.budget, sh);
-                const float e2 = __uint_as_float((base2 + (uint32_t)sh.thr_bin + 1u) << 15);
-                if (e2 < R2) {
-                    R2 = e2;
-                    R = sqrtf(e2);
-                }
-            }
-            __syncthreads();
         }
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
+    }
+    if (lane == 0) {
+        sh.red[wave] = (int)lo;
+        sh.red[NWAVE + wave] = (int)hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) {
+        lo = min(lo, (uint32_t)sh.red[w]);
+        hi = max(hi, (uint32_t)sh.red[NWAVE + w]);
+    }
+    __syncthreads();
+
+    // 2: weighted histogram of the centre distances
+    const int sft = shift32(lo, hi);
+    clear_hist(sh);
+    int loc = 0;
+    for (int i = threadIdx.x; i < nl; i += WG) {
+        const int w = a.npts[leaf_base + i];
+        atomicAdd(&sh.hist[(__float_as_uint(dl[i]) - lo) >> sft], (uint32_t)w);
+        loc += w;
+    }
+    __syncthreads();
+    const int total = block_sum(loc, sh);
+    const int want = total < 4 * a.budget ? total : 4 * a.budget;
+    if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+    __syncthreads();
+    find_threshold(want, sh);
+    const uint32_t tbin = (uint32_t)sh.thr_bin;
+    if (threadIdx.x == 0) sh.cnt1 = 0;
+    __syncthreads();
+
+    // the chosen leaves, and the largest distance bound over their points
+    float rmax = 0.f;
+    for (int b0 = 0; b0 < nl; b0 += WG) {
+        const int i = b0 + threadIdx.x;
+        bool take = false;
+        if (i < nl) {
+            const float d2 = dl[i];
+            take = ((__float_as_uint(d2) - lo) >> sft) <= tbin;
+            if (take) rmax = fmaxf(rmax, sqrtf(d2) + a.nrad[leaf_base + i]);
+        }
+        const int slot = wave_append(take, &sh.cnt1);
+        if (take) sel[slot] = leaf_base + i;
+    }
+    for (int off = 32; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
+    if (lane == 0) sh.red[wave] = __float_as_int(rmax);
+    __syncthreads();
+    const int nsel = sh.cnt1;
+    float R = 0.f;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) R = fmaxf(R, __int_as_float(sh.red[w]));
+    __syncthreads();
+    // every chosen point lies within R up to rounding; the margin keeps the
+    // histogram range above all of them
+    R = R * 1.0001f + 1e-5f * (sqrtf(qc.qn2) + a.coord_scale);
+    float R2 = (float)((double)R * (double)R);
+
+    // 3: histogram of pd^2 over the chosen points -> budget-th smallest
+    const uint32_t hb2 = __float_as_uint(R2) >> 15;
+    const uint32_t base2 = hb2 > (uint32_t)(NB - 1) ? hb2 - (uint32_t)(NB - 1) : 0u;
+    clear_hist(sh);
+    int cnt = 0;
+    for (int li = wave; li < nsel; li += NWAVE) {
+        const int node = sel[li];
+        const int p0 = a.cb[node], p1 = a.ce[node];
+        for (int b0 = p0; b0 < p1; b0 += 64) {
+            const int pos = b0 + lane;
+            if (pos < p1) {
+                const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
+                if (pd2 <= R2) {
+                    atomicAdd(&sh.hist[radius_bin(pd2, base2)], 1u);
+                    ++cnt;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (block_sum(cnt, sh) >= a.budget) {
+        if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+        __syncthreads();
+        find_threshold(a.budget, sh);
+        const float e2 = __uint_as_float((base2 + (uint32_t)sh.thr_bin + 1u) << 15);
+        if (e2 < R2) {
+            R2 = e2;
+            R = sqrtf(e2);
+        }
+    } else {
+        // rounding left fewer than `budget` chosen points inside R: no bound
+        R = R2 = __int_as_float(0x7f800000);
+    }
+    const float slack = 1e-5f * (sqrtf(qc.qn2) + a.coord_scale + R);
     if (threadIdx.x == 0) {
         a.q_tau[qi] = R;
         a.q_tau2[qi] = R2;
