@@ -359,6 +359,67 @@ __device__ void bitonic_sort(int count, Smem& sh) {
     }
 }
 
+// The need-th smallest (need in [1, n]) of the n <= CAP distinct 64-bit keys
+// in sh.skey: NB-bin histogram passes over LDS, each narrowing the key range
+// to the bin that holds it.
+__device__ uint64_t lds_select(int n, int need, Smem& sh) {
+    uint64_t lo = ~0ull, hi = 0ull;
+    for (int i = threadIdx.x; i < n; i += WG) {
+        const uint64_t k = sh.skey[i];
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    uint64_t* red = reinterpret_cast<uint64_t*>(sh.hist);
+    if (lane_id() == 0) {
+        red[threadIdx.x >> 6] = lo;
+        red[NWAVE + (threadIdx.x >> 6)] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) {
+        lo = red[w] < lo ? red[w] : lo;
+        hi = red[NWAVE + w] > hi ? red[NWAVE + w] : hi;
+    }
+    __syncthreads();
+    for (;;) {
+        const int sft = shift_for(lo, hi);
+        clear_hist(sh);
+        for (int i = threadIdx.x; i < n; i += WG) {
+            const uint64_t k = sh.skey[i];
+            if (k >= lo && k <= hi) atomicAdd(&sh.hist[(int)((k - lo) >> sft)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+        __syncthreads();
+        find_threshold(need, sh);
+        const int T = sh.thr_bin, below = sh.thr_below, inT = sh.thr_in;
+        const uint64_t nlo = lo + ((uint64_t)T << sft);
+        const uint64_t span = (1ull << sft) - 1ull;
+        const uint64_t nhi = hi - nlo > span ? nlo + span : hi;
+        __syncthreads();
+        if (sft == 0) return nlo;
+        if (inT == 1) {
+            // the bin holds one key: that key
+            for (int i = threadIdx.x; i < n; i += WG) {
+                const uint64_t k = sh.skey[i];
+                if (k >= nlo && k <= nhi) red[0] = k;
+            }
+            __syncthreads();
+            const uint64_t key = red[0];
+            __syncthreads();
+            return key;
+        }
+        need -= below;
+        lo = nlo;
+        hi = nhi;
+    }
+}
+
 // Exact selection of the `need` smallest 64-bit keys among the members of a
 // source with key in [lo, hi] (radix select with NB-bin steps). src(v) calls
 // v(valid, key, payload) wave-uniformly over all members; emit(payload, slot)
@@ -509,47 +570,67 @@ __device__ __forceinline__ void load_query(const AnnArgs& a, int64_t qi, float* 
     }
 }
 
-// Sorts the first n_ver members of C by (distance^2 bits, id) and writes the
-// k nearest and the per-query statistics.
+// Writes the k members of C (the first n_ver entries, n_ver >= k) with the
+// smallest (distance^2 bits, id), in that order, and the per-query statistics.
 __device__ void write_topk(const AnnArgs& a, int64_t qi, const int32_t* cpos, const float* cdist,
                            int n_ver, int rounds, int exit_kind, int64_t scanned, Smem& sh) {
     const int32_t* perm = a.perm;
-    auto c_src = [&](auto&& v) {
-        for (int base = 0; base < n_ver; base += WG) {
-            const int i = base + threadIdx.x;
-            const bool valid = i < n_ver;
-            uint64_t key = 0;
-            if (valid) key = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
-            v(valid, key, i);
-        }
-    };
-    int32_t* topk = a.ws_topk + qi * 3 * (int64_t)a.k;
     const int k = a.k;
     if (n_ver <= CAP) {
-        if (threadIdx.x == 0) sh.cnt1 = 0;
+        for (int i = threadIdx.x; i < n_ver; i += WG)
+            sh.skey[i] = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
         __syncthreads();
-        c_src([&](bool valid, uint64_t key, int32_t i) {
-            const int slot = wave_append(valid, &sh.cnt1);
-            if (valid && slot < CAP) { sh.skey[slot] = key; sh.spos[slot] = i; }
-        });
-        __syncthreads();
-        bitonic_sort(n_ver, sh);
+        int m = n_ver;
+        if (n_ver > k) {
+            const uint64_t kth = lds_select(n_ver, k, sh);
+            // the k smallest keys, gathered through the histogram space
+            uint64_t* tmp = reinterpret_cast<uint64_t*>(sh.hist);
+            static_assert(NB * sizeof(uint32_t) >= PMLSH_MAX_K * sizeof(uint64_t),
+                          "top-k staging must fit the histogram");
+            if (threadIdx.x == 0) sh.cnt1 = 0;
+            __syncthreads();
+            for (int b0 = 0; b0 < n_ver; b0 += WG) {
+                const int i = b0 + threadIdx.x;
+                const bool take = i < n_ver && sh.skey[i] <= kth;
+                const int slot = wave_append(take, &sh.cnt1);
+                if (take) tmp[slot] = sh.skey[i];
+            }
+            __syncthreads();
+            for (int j = threadIdx.x; j < k; j += WG) sh.skey[j] = tmp[j];
+            __syncthreads();
+            m = k;
+        }
+        bitonic_sort(m, sh);
+        for (int j = threadIdx.x; j < k; j += WG) {
+            const uint64_t key = sh.skey[j];
+            a.out_ids[qi * k + j] = (int64_t)(uint32_t)key;
+            a.out_dist[qi * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+        }
     } else {
+        auto c_src = [&](auto&& v) {
+            for (int base = 0; base < n_ver; base += WG) {
+                const int i = base + threadIdx.x;
+                const bool valid = i < n_ver;
+                uint64_t key = 0;
+                if (valid) key = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
+                v(valid, key, i);
+            }
+        };
+        int32_t* topk = a.ws_topk + qi * 3 * (int64_t)a.k;
         block_select(c_src, [&](int32_t i, int slot) { if (slot < k) topk[slot] = i; }, 0ull,
                      ~0ull, k, false, 0, sh);
         __syncthreads();
         for (int j = threadIdx.x; j < k; j += WG) {
             const int i = topk[j];
             sh.skey[j] = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
-            sh.spos[j] = i;
         }
         __syncthreads();
         bitonic_sort(k, sh);
-    }
-    for (int j = threadIdx.x; j < k; j += WG) {
-        const int i = sh.spos[j];
-        a.out_ids[qi * k + j] = (int64_t)perm[cpos[i]];
-        a.out_dist[qi * k + j] = sqrtf(cdist[i]);
+        for (int j = threadIdx.x; j < k; j += WG) {
+            const uint64_t key = sh.skey[j];
+            a.out_ids[qi * k + j] = (int64_t)(uint32_t)key;
+            a.out_dist[qi * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+        }
     }
     if (a.out_stats && threadIdx.x == 0) {
         int32_t* st = a.out_stats + qi * 4;
@@ -1124,32 +1205,41 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     const int32_t* perm = a.perm;
     const int n = (int)cnt;
 
-    // L: the B smallest (pd^2 bits, id) of the list, sorted
-    auto list_src = [&](auto&& v) {
-        for (int base = 0; base < n; base += WG) {
-            const int i = base + threadIdx.x;
-            const bool valid = i < n;
-            uint64_t key = 0;
-            int32_t pos = 0;
-            if (valid) {
-                const uint2 e = list[i];
-                pos = (int32_t)e.x;
-                key = ((uint64_t)e.y << 32) | (uint32_t)perm[pos];
-            }
-            v(valid, key, pos);
-        }
-    };
+    // L: the B smallest (pd^2 bits, id) of the list, kept in LDS as keys and
+    // leaf positions (entries outside L get the key ~0). Every ball of the
+    // rounds below holds the members of L with pd^2 bits <= its radius bits,
+    // which is the prefix of L in (pd^2, id) order, so L needs no sorting.
+    int nl;
     __syncthreads();
     if (n <= CAP) {
-        if (threadIdx.x == 0) sh.cnt1 = 0;
+        for (int i = threadIdx.x; i < n; i += WG) {
+            const uint2 e = list[i];
+            sh.skey[i] = ((uint64_t)e.y << 32) | (uint32_t)perm[e.x];
+            sh.spos[i] = (int32_t)e.x;
+        }
         __syncthreads();
-        list_src([&](bool valid, uint64_t key, int32_t pos) {
-            const int slot = wave_append(valid, &sh.cnt1);
-            if (valid && slot < CAP) { sh.skey[slot] = key; sh.spos[slot] = pos; }
-        });
-        __syncthreads();
-        bitonic_sort(n, sh);
+        if (n > B) {
+            const uint64_t kth = lds_select(n, B, sh);
+            for (int i = threadIdx.x; i < n; i += WG)
+                if (sh.skey[i] > kth) sh.skey[i] = ~0ull;
+            __syncthreads();
+        }
+        nl = n;
     } else {
+        auto list_src = [&](auto&& v) {
+            for (int base = 0; base < n; base += WG) {
+                const int i = base + threadIdx.x;
+                const bool valid = i < n;
+                uint64_t key = 0;
+                int32_t pos = 0;
+                if (valid) {
+                    const uint2 e = list[i];
+                    pos = (int32_t)e.x;
+                    key = ((uint64_t)e.y << 32) | (uint32_t)perm[pos];
+                }
+                v(valid, key, pos);
+            }
+        };
         block_select(list_src, [&](int32_t pos, int slot) { if (slot < B) cpos[slot] = pos; },
                      0ull, ~0ull, B, false, 0, sh);
         __syncthreads();
@@ -1160,14 +1250,12 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
             sh.spos[j] = pos;
         }
         __syncthreads();
-        bitonic_sort(B, sh);
+        nl = B;
     }
-    // sh.skey/sh.spos now hold L in (pd^2, id) order; C is always a prefix
-    for (int j = threadIdx.x; j < B; j += WG) cpos[j] = sh.spos[j];
-    __syncthreads();
 
     double r = a.r_min;
     int n_ver = 0, rounds = 0, exit_kind = 0;
+    uint32_t prev_bits = 0;
     for (;;) {
         if (rounds > 0) {
             const double cr = a.c * r;
@@ -1179,13 +1267,27 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
         const double Rd = a.t * r;
         const uint32_t r2bits = __float_as_uint((float)(Rd * Rd));
+        // members of L that the ball gains this round go to C after the
+        // n_ver verified ones
+        if (threadIdx.x == 0) sh.cnt1 = n_ver;
+        __syncthreads();
+        for (int b0 = 0; b0 < nl; b0 += WG) {
+            const int i = b0 + threadIdx.x;
+            bool take = false;
+            if (i < nl) {
+                const uint64_t key = sh.skey[i];
+                const uint32_t kb = (uint32_t)(key >> 32);
+                take = key != ~0ull && kb <= r2bits && (rounds == 0 || kb > prev_bits);
+            }
+            const int slot = wave_append(take, &sh.cnt1);
+            if (take && slot < B) cpos[slot] = sh.spos[i];
+        }
+        __syncthreads();
+        const int nb = sh.cnt1 < B ? sh.cnt1 : B;
         ++rounds;
-        // points of L inside the ball (a prefix, as L is sorted)
-        int loc = 0;
-        for (int i = threadIdx.x; i < B; i += WG) loc += (uint32_t)(sh.skey[i] >> 32) <= r2bits;
-        const int nb = block_sum(loc, sh);
         verify(a, qs, cpos, cdist, n_ver, nb);
         n_ver = nb;
+        prev_bits = r2bits;
         __syncthreads();
         if (nb == B) { exit_kind = PMLSH_EXIT_BUDGET; break; }
         r = a.c * r;
