@@ -78,7 +78,7 @@ struct AnnArgs {
     int32_t* q_flag;
     uint32_t* l_count;          // candidates per query
     uint32_t* q_scanned;
-    uint2* l_list;              // nq x q_cap (leaf position, pd^2 bits)
+    uint32_t* l_list;           // nq x q_cap leaf positions (candidate pool)
     int q_cap;
     int nq;
 };
@@ -950,10 +950,8 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
 
 constexpr int FQB = 128;   // queries per filter block (two 64-bit masks per leaf)
 constexpr int FLB = 32;    // leaves per filter block
-constexpr int STG = 1024;  // hits staged in LDS per filter block
-constexpr uint8_t kStageUnused = 0xff;   // stage entry reserved but not written
+constexpr int WSTG = 256;  // hits staged in LDS per wave of a filter block
 static_assert(FQB == 128, "a leaf's passing queries are two 64-bit masks");
-static_assert(FQB < kStageUnused, "query index of a block must fit below the marker");
 
 // Arrays the filter reads at wave-uniform addresses and never writes. Read
 // through the constant address space they become scalar loads, and their
@@ -962,41 +960,38 @@ typedef __attribute__((address_space(4))) const float cfloat;
 typedef __attribute__((address_space(4))) const int32_t cint32;
 
 struct FilterShared {
-    uint64_t mask[FLB][2];      // queries passing Eq. 5 for each leaf
-    uint2 stg[STG];             // staged hits (leaf position, pd^2 bits)
-    uint8_t stq[STG];           // query of each staged hit
+    uint64_t mask[FLB][2];          // queries passing Eq. 5 for each leaf
+    uint32_t stg[NWAVE][WSTG];      // staged hits of each wave (leaf positions)
+    uint8_t stq[NWAVE][WSTG];       // query of each staged hit
     uint32_t hits[FQB], base[FQB], scan[FQB];
-    uint32_t nstg, next;
+    uint32_t wn[NWAVE];             // staged hits per wave
+    uint32_t next;
 };
 
-// Appends this wave's hits for query q (block-local) to the stage; when the
-// stage is full they are reserved in the query's region of the pool directly.
-__device__ __forceinline__ void stage_hits(const AnnArgs& a, FilterShared& fs, bool hit,
-                                           uint32_t pp, float pd2, int q, int64_t gq) {
-    const uint64_t hm = __ballot(hit);
+// Appends this wave's hits for query q (block-local) to the wave's own stage
+// (fill count wn, wave-uniform); when it is full they are reserved in the
+// query's region of the pool directly.
+__device__ __forceinline__ void stage_hits(const AnnArgs& a, uint32_t* wstg, uint8_t* wstq,
+                                           uint32_t& wn, bool hit, uint32_t pp, int q,
+                                           int64_t gq) {
+    const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
     if (!hm) return;
-    const int lane = lane_id();
-    const int leader = __ffsll((unsigned long long)hm) - 1;
     const uint32_t nh = (uint32_t)__popcll(hm);
-    const uint32_t rank = (uint32_t)__popcll(hm & lanemask_lt());
-    uint32_t b = 0;
-    if (lane == leader) b = atomicAdd(&fs.nstg, nh);
-    b = __shfl(b, leader);
-    if (b + nh <= (uint32_t)STG) {
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+    if (wn + nh <= (uint32_t)WSTG) {
         if (hit) {
-            fs.stg[b + rank] = make_uint2(pp, __float_as_uint(pd2));
-            fs.stq[b + rank] = (uint8_t)q;
+            wstg[wn + rank] = pp;
+            wstq[wn + rank] = (uint8_t)q;
         }
+        wn += nh;
     } else {
-        // stage full: the part of this reservation inside the stage is marked
-        // unused, and the hits go to the query's region directly
-        if (hit && b + rank < (uint32_t)STG) fs.stq[b + rank] = kStageUnused;
+        const int leader = __ffsll((unsigned long long)hm) - 1;
         uint32_t g = 0;
-        if (lane == leader) g = atomicAdd(&a.l_count[gq], nh);
-        g = __shfl(g, leader);
+        if (lane_id() == leader) g = atomicAdd(&a.l_count[gq], nh);
+        g = (uint32_t)__builtin_amdgcn_readlane((int)g, leader);
         const uint32_t slot = g + rank;
-        if (hit && slot < (uint32_t)a.q_cap)
-            a.l_list[gq * a.q_cap + slot] = make_uint2(pp, __float_as_uint(pd2));
+        if (hit && slot < (uint32_t)a.q_cap) a.l_list[gq * a.q_cap + slot] = pp;
     }
 }
 
@@ -1007,13 +1002,14 @@ __device__ __forceinline__ void stage_hits(const AnnArgs& a, FilterShared& fs, b
 //   Phase 2: waves take leaves from a shared counter. A leaf's points are
 //            held in registers (one point per lane) while its passing queries
 //            are taken two at a time; each query's projection is read with
-//            scalar loads. A cheap bound ||o'||^2 - 2 q'.o' <= thr (thr =
-//            tau^2 + margin - ||q'||^2, set by the bound kernel) discards
-//            points that cannot lie within tau; the survivors get the exact
-//            direct-difference pd^2, the value every later decision uses, and
-//            pd^2 <= tau^2 is a hit.
+//            scalar loads. The cheap bound ||o'||^2 - 2 q'.o' <= thr (thr =
+//            tau^2 + margin - ||q'||^2, set by the bound kernel) keeps every
+//            point whose direct-difference pd^2 is within tau^2, plus a few
+//            just outside; the finishing kernel computes the exact pd^2 of
+//            the kept points, so the surplus never reaches a decision.
 //   Phase 3: staged hits are written with one reservation per (block, query)
-//            in the query's region of the pool. A region that overflows
+//            in the query's region of the pool (a wave whose stage is full
+//            reserves its further hits there directly). A region that overflows
 //            makes the finishing kernel hand its query to the per-query path.
 __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
     __shared__ FilterShared fs;
@@ -1028,10 +1024,7 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
         fs.hits[e] = 0u;
         fs.scan[e] = 0u;
     }
-    if (threadIdx.x == 0) {
-        fs.nstg = 0u;
-        fs.next = 0u;
-    }
+    if (threadIdx.x == 0) fs.next = 0u;
     __syncthreads();
 
     // Phase 1: waves 0 and 2 take queries 0..63, waves 1 and 3 queries
@@ -1088,11 +1081,14 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
     __syncthreads();
 
     // Phase 2
-    cfloat* qpc = (cfloat*)a.qp;
-    cfloat* thr = (cfloat*)a.q_thr;
-    cfloat* tau2 = (cfloat*)a.q_tau2;
+    // block-relative bases: per-query offsets stay 32-bit scalar arithmetic
+    cfloat* qblk = (cfloat*)(a.qp + (int64_t)q0 * MP);
+    cfloat* tblk = (cfloat*)(a.q_thr + q0);
     cint32* cb = (cint32*)a.cb;
     cint32* ce = (cint32*)a.ce;
+    uint32_t* wstg = fs.stg[wave];
+    uint8_t* wstq = fs.stq[wave];
+    uint32_t wn = 0;
     for (;;) {
         uint32_t jn = 0;
         if (lane == 0) jn = atomicAdd(&fs.next, 1u);
@@ -1130,10 +1126,9 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
                     const int qb = has_b ? h * 64 + __ffsll((unsigned long long)m) - 1 : qa;
                     m &= m - 1;
                     const int64_t ga = q0 + qa, gb = q0 + qb;
-                    cfloat* va = qpc + ga * MP;
-                    cfloat* vb = qpc + gb * MP;
-                    const float ta = thr[ga], tb = thr[gb];
-                    const float ra = tau2[ga], rb = tau2[gb];
+                    cfloat* va = qblk + qa * MP;
+                    cfloat* vb = qblk + qb * MP;
+                    const float ta = tblk[qa], tb = tblk[qb];
                     float da = 0.f, db = 0.f;
 #pragma unroll
                     for (int t = 0; t < MP; ++t) {
@@ -1142,34 +1137,19 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
                     }
                     const bool ca = valid & (fmaf(-2.f, da, on2) <= ta);
                     const bool cb2 = valid & has_b & (fmaf(-2.f, db, on2) <= tb);
-                    if (__ballot(ca)) {
-                        float acc = 0.f;
-#pragma unroll
-                        for (int t = 0; t < MP; ++t) {
-                            const float d = __fsub_rn(va[t], o[t]);
-                            acc = __fmaf_rn(d, d, acc);
-                        }
-                        stage_hits(a, fs, ca & (acc <= ra), (uint32_t)pp, acc, qa, ga);
-                    }
-                    if (__ballot(cb2)) {
-                        float acc = 0.f;
-#pragma unroll
-                        for (int t = 0; t < MP; ++t) {
-                            const float d = __fsub_rn(vb[t], o[t]);
-                            acc = __fmaf_rn(d, d, acc);
-                        }
-                        stage_hits(a, fs, cb2 & (acc <= rb), (uint32_t)pp, acc, qb, gb);
-                    }
+                    stage_hits(a, wstg, wstq, wn, ca, (uint32_t)pp, qa, ga);
+                    stage_hits(a, wstg, wstq, wn, cb2, (uint32_t)pp, qb, gb);
                 }
             }
         }
     }
     __syncthreads();
 
-    // Phase 3: flush the stage with one reservation per query of the block
-    const uint32_t ns = fs.nstg < (uint32_t)STG ? fs.nstg : (uint32_t)STG;
-    for (uint32_t e = threadIdx.x; e < ns; e += WG)
-        if (fs.stq[e] != kStageUnused) atomicAdd(&fs.hits[fs.stq[e]], 1u);
+    // Phase 3: flush the stages with one reservation per query of the block
+    if (lane_id() == 0) fs.wn[wave] = wn;
+    __syncthreads();
+    for (int w = 0; w < NWAVE; ++w)
+        for (uint32_t e = threadIdx.x; e < fs.wn[w]; e += WG) atomicAdd(&fs.hits[fs.stq[w][e]], 1u);
     __syncthreads();
     for (int e = threadIdx.x; e < nqb; e += WG) {
         if (fs.hits[e]) fs.base[e] = atomicAdd(&a.l_count[q0 + e], fs.hits[e]);
@@ -1177,12 +1157,12 @@ __global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
         fs.hits[e] = 0u;
     }
     __syncthreads();
-    for (uint32_t e = threadIdx.x; e < ns; e += WG) {
-        const int q = fs.stq[e];
-        if (q == kStageUnused) continue;
-        const uint32_t slot = fs.base[q] + atomicAdd(&fs.hits[q], 1u);
-        if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = fs.stg[e];
-    }
+    for (int w = 0; w < NWAVE; ++w)
+        for (uint32_t e = threadIdx.x; e < fs.wn[w]; e += WG) {
+            const int q = fs.stq[w][e];
+            const uint32_t slot = fs.base[q] + atomicAdd(&fs.hits[q], 1u);
+            if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = fs.stg[w][e];
+        }
 }
 
 __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
@@ -1201,7 +1181,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     load_query(a, qi, qs, qc);
     int32_t* cpos = a.ws_cpos + qi * (int64_t)B;
     float* cdist = a.ws_cdist + qi * (int64_t)B;
-    const uint2* list = a.l_list + qi * a.q_cap;
+    const uint32_t* list = a.l_list + qi * a.q_cap;
     const int32_t* perm = a.perm;
     const int n = (int)cnt;
 
@@ -1213,9 +1193,10 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     __syncthreads();
     if (n <= CAP) {
         for (int i = threadIdx.x; i < n; i += WG) {
-            const uint2 e = list[i];
-            sh.skey[i] = ((uint64_t)e.y << 32) | (uint32_t)perm[e.x];
-            sh.spos[i] = (int32_t)e.x;
+            const int32_t pos = (int32_t)list[i];
+            const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
+            sh.skey[i] = ((uint64_t)__float_as_uint(pd2) << 32) | (uint32_t)perm[pos];
+            sh.spos[i] = pos;
         }
         __syncthreads();
         if (n > B) {
@@ -1233,9 +1214,9 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
                 uint64_t key = 0;
                 int32_t pos = 0;
                 if (valid) {
-                    const uint2 e = list[i];
-                    pos = (int32_t)e.x;
-                    key = ((uint64_t)e.y << 32) | (uint32_t)perm[pos];
+                    pos = (int32_t)list[i];
+                    const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
+                    key = ((uint64_t)__float_as_uint(pd2) << 32) | (uint32_t)perm[pos];
                 }
                 v(valid, key, pos);
             }

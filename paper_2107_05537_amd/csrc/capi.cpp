@@ -63,7 +63,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // per query: projection, two frontier lists, C, top-k scratch, and for the
     // leaf-major path seven scalars and a candidate region
     const int64_t per_query = (int64_t)MP * 4 + 2 * x->n_leaves * 4 + B * 8 +
-                              3 * (int64_t)k * 4 + (fast ? 7 * 4 + pool_q * 8 : 0);
+                              3 * (int64_t)k * 4 + (fast ? 7 * 4 + pool_q * 4 : 0);
     int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query));
     batch = std::min<int64_t>(batch, 65535);
     void* ws = nullptr;
@@ -71,7 +71,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     char* base = static_cast<char*>(ws);
     // projections first: every row starts on a 64-byte boundary
     float* qproj = reinterpret_cast<float*>(base);
-    uint2* list = reinterpret_cast<uint2*>(qproj + batch * MP);
+    uint32_t* list = reinterpret_cast<uint32_t*>(qproj + batch * MP);
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
     int32_t* cpos = front + batch * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);

@@ -159,7 +159,7 @@ struct AnnLaunch {
     int32_t* q_flag;
     uint32_t* l_count;
     uint32_t* q_scanned;
-    uint2* l_list;          // nq x pool_cap (leaf position, pd^2 bits)
+    uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
     int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;
