@@ -37,6 +37,7 @@ constexpr int NB = 2048;    // histogram bins of one radix-select step
 constexpr int CAP = 2048;   // keys sorted in LDS at once (power of two)
 constexpr int MAX_LEVELS = 16;
 constexpr int MAX_ROUNDS = 1000;
+constexpr int64_t kScanBlocks = 1024;   // scan workgroups striding over point chunks
 
 struct AnnArgs {
     const float* data;
@@ -71,16 +72,19 @@ struct AnnArgs {
     int32_t* out_stats;
     // leaf-major fast path (per query): radius bound, its square and test
     // slack, fallback flag, candidate count, scanned points, candidate list
-    float* q_tau;
-    float* q_tau2;
-    float* q_slack;
-    float* q_thr;               // tau^2 + margin - ||q'||^2 (cheap-bound threshold)
     int32_t* q_flag;
     uint32_t* l_count;          // candidates per query
     uint32_t* q_scanned;
     uint32_t* l_list;           // nq x q_cap leaf positions (candidate pool)
     int q_cap;
     int nq;
+    int64_t n;
+    // matrix-core scan: FP16 point rows, their count (padded to 64), scale,
+    // and the per-query FP16 rows
+    const uint16_t* proj16;
+    int64_t n_pad16;
+    float scale16;
+    uint16_t* qaug;
 };
 
 struct Smem {
@@ -929,239 +933,195 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         // rounding left fewer than `budget` chosen points inside R: no bound
         R = R2 = __int_as_float(0x7f800000);
     }
-    const float slack = 1e-5f * (sqrtf(qc.qn2) + a.coord_scale + R);
     if (threadIdx.x == 0) {
-        a.q_tau[qi] = R;
-        a.q_tau2[qi] = R2;
-        a.q_slack[qi] = slack;
-        // Threshold of the filter's cheap bound ||o'||^2 - 2 q'.o' <= thr. The
-        // FP32 errors of ||q'||^2, ||o'||^2 and q'.o' (16-term chains) and of
-        // the two roundings here stay below 72 u (||q'|| + S)^2, S bounding
-        // every ||o'||; 96 u covers them, so no point whose computed pd^2 is
-        // within tau^2 is discarded.
-        const float u = 5.9604645e-08f;   // 2^-24
-        const float big = sqrtf(qc.qn2) + a.coord_scale;
-        a.q_thr[qi] = (R2 + 96.f * u * big * big) - qc.qn2;
         a.l_count[qi] = 0u;
-        a.q_scanned[qi] = 0u;
+        a.q_scanned[qi] = (uint32_t)(a.n < 0x7fffffff ? a.n : 0x7fffffff);
         a.q_flag[qi] = 0;
+        // The query's FP16 row of the matrix-core scan. thr = tau^2 - |q'|^2
+        // plus 96 u (|q'| + S)^2 (S bounds every |o'|) covers the FP32 errors
+        // of the exact pd^2 and of |q'|^2; the further 2^-15 (|q'| + S)^2
+        // covers the FP32 accumulation of the scan and its hi/lo splits.
+        const float u = 5.9604645e-08f;   // 2^-24
+        const float qn = sqrtf(qc.qn2);
+        const float big = qn + a.coord_scale;
+        const float thr = (R2 + 96.f * u * big * big) - qc.qn2 + 3.0517578e-05f * big * big;
+        const float s = a.scale16;
+        const float v = -(s * s) * thr;
+        float qmax = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) qmax = fmaxf(qmax, fabsf(qc.qp[t]));
+        const bool ok = fabsf(v) < 30000.f && 2.f * s * qmax < 30000.f && s * qn < 30000.f;
+        _Float16 w[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) w[i] = (_Float16)0.f;
+        if (ok) {
+#pragma unroll
+            for (int t = 0; t < MP; ++t) w[t] = (_Float16)(-2.f * s * qc.qp[t]);
+            w[16] = (_Float16)1.f;
+            w[17] = (_Float16)1.f;
+            const _Float16 hi = (_Float16)v;
+            w[18] = hi;
+            w[19] = (_Float16)(v - (float)hi);
+            w[20] = (_Float16)(-s * qn);
+        } else {
+            // outside the FP16 range (or no finite bound): every product is
+            // +1, no candidate, and the per-query path answers the query
+            w[18] = (_Float16)1.f;
+        }
+        uint4* dst = reinterpret_cast<uint4*>(a.qaug + qi * 32);
+        const uint4* src = reinterpret_cast<const uint4*>(w);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = src[i];
     }
 }
 
-constexpr int FQB = 128;   // queries per filter block (two 64-bit masks per leaf)
-constexpr int FLB = 32;    // leaves per filter block
-constexpr int WSTG = 256;  // hits staged in LDS per wave of a filter block
-static_assert(FQB == 128, "a leaf's passing queries are two 64-bit masks");
+// ---- Matrix-core scan (the range filter of the batched path) ----
+//
+// For every (point, query) pair of the batch one FP16 MFMA dot product of
+// 32-half rows decides whether the point can lie within tau of the query:
+//   point row P: s*o'_0..s*o'_15, hi(s^2|o'|^2), lo(s^2|o'|^2), 1, 1,
+//                cm*s*|o'|, zeros
+//   query row Q: -2s*q'_0..-2s*q'_15, 1, 1, hi(-s^2 thr), lo(-s^2 thr),
+//                -s*|q'|, zeros
+// so P.Q = s^2 (|o'|^2 - 2 q'.o' - thr - cm |q'||o'|), accumulated in FP32.
+// thr is tau^2 - |q'|^2 plus margins for the FP32 errors of the exact pd^2 and
+// of the split terms; the FP16 rounding of the dot product is bounded by
+// 2^-9 |q'||o'|, which the cm term covers pair by pair. Hence every point
+// whose FP32 direct-difference pd^2 is within tau^2 gives P.Q < 0, and the
+// pool also receives a few points just outside, which the finishing kernel
+// removes with the exact pd^2. This is the PM-tree range query of the
+// paper computed without the tree: the node tests of Eq. 5 only save work on
+// a processor that compares one pair at a time, while the matrix cores
+// compare all pairs of a batch at 16 x 16 x 32 per instruction.
+//
+// Grid: x strides over 64-point chunks, y over blocks of 1,024 queries. Each
+// wave keeps the FP16 rows of its 16 query tiles in registers as B operands
+// (lane l: query 16 t + l % 16, halves 8 (l / 16) .. + 7); the chunk's four
+// 16-point tiles are the A operands. A result register r of lane l holds
+// point 4 (l / 16) + r of the tile and query l % 16.
 
-// Arrays the filter reads at wave-uniform addresses and never writes. Read
-// through the constant address space they become scalar loads, and their
-// values enter the vector FMAs as SGPR operands.
-typedef __attribute__((address_space(4))) const float cfloat;
-typedef __attribute__((address_space(4))) const int32_t cint32;
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
-struct FilterShared {
-    uint64_t mask[FLB][2];          // queries passing Eq. 5 for each leaf
-    uint32_t stg[NWAVE][WSTG];      // staged hits of each wave (leaf positions)
-    uint8_t stq[NWAVE][WSTG];       // query of each staged hit
-    uint32_t hits[FQB], base[FQB], scan[FQB];
-    uint32_t wn[NWAVE];             // staged hits per wave
-    uint32_t next;
+constexpr int SQB = 1024;               // queries per scan block
+constexpr int SQT = SQB / 16 / NWAVE;   // query tiles per wave
+constexpr int SSTG = 1024;              // candidates staged per wave
+
+struct ScanShared {
+    uint32_t pos[NWAVE][SSTG];          // staged candidates: leaf position
+    uint16_t qid[NWAVE][SSTG];          // and query within the block
+    uint32_t hits[SQB], base[SQB];
+    uint8_t ovf[SQB];                   // query lost candidates to a full stage
+    uint32_t wn[NWAVE];
 };
 
-// Appends this wave's hits for query q (block-local) to the wave's own stage
-// (fill count wn, wave-uniform); when it is full they are reserved in the
-// query's region of the pool directly.
-__device__ __forceinline__ void stage_hits(const AnnArgs& a, uint32_t* wstg, uint8_t* wstq,
-                                           uint32_t& wn, bool hit, uint32_t pp, int q,
-                                           int64_t gq) {
-    const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
-    if (!hm) return;
-    const uint32_t nh = (uint32_t)__popcll(hm);
-    const uint32_t rank =
-        __builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-    if (wn + nh <= (uint32_t)WSTG) {
-        if (hit) {
-            wstg[wn + rank] = pp;
-            wstq[wn + rank] = (uint8_t)q;
+__device__ __forceinline__ half8_t load_half8(const uint16_t* p) {
+    return __builtin_bit_cast(half8_t, *reinterpret_cast<const uint4*>(p));
+}
+
+// One 64-point x 16-query block: four MFMAs, then the negative results are
+// staged. Register r of the four tiles is tested together first; most
+// register positions hold no candidate.
+__device__ __forceinline__ void scan_tile(ScanShared& ss, int wave, int lane, uint32_t& wn,
+                                          const half8_t (&av)[4], half8_t b, int64_t p0, int qt) {
+    float4_t cc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        cc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[mt], b, float4_t{}, 0, 0, 0);
+    const int q = qt + (lane & 15);
+    const uint32_t prow = (uint32_t)p0 + 4u * (uint32_t)(lane >> 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t z = __float_as_uint(cc[0][r]) | __float_as_uint(cc[1][r]) |
+                           __float_as_uint(cc[2][r]) | __float_as_uint(cc[3][r]);
+        if (!__builtin_amdgcn_ballot_w64((int32_t)z < 0)) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bool c = __float_as_int(cc[mt][r]) < 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(c);
+            if (!m) continue;
+            const uint32_t nh = (uint32_t)__popcll(m);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t pos = prow + (uint32_t)(mt * 16 + r);
+            if (wn + nh <= (uint32_t)SSTG) {
+                if (c) {
+                    ss.pos[wave][wn + rank] = pos;
+                    ss.qid[wave][wn + rank] = (uint16_t)q;
+                }
+                wn += nh;
+            } else if (c) {
+                // stage full: the query is marked and handed to the per-query
+                // path (its pool count is pushed past the capacity)
+                ss.ovf[q] = 1u;
+            }
         }
-        wn += nh;
-    } else {
-        const int leader = __ffsll((unsigned long long)hm) - 1;
-        uint32_t g = 0;
-        if (lane_id() == leader) g = atomicAdd(&a.l_count[gq], nh);
-        g = (uint32_t)__builtin_amdgcn_readlane((int)g, leader);
-        const uint32_t slot = g + rank;
-        if (hit && slot < (uint32_t)a.q_cap) a.l_list[gq * a.q_cap + slot] = pp;
     }
 }
 
-// Leaf-major range filter over one (leaf block, query block) tile.
-//   Phase 1: the Eq. 5 test of every (leaf, query) pair of the tile, one
-//            query per lane; the passing queries of each leaf become a
-//            128-bit mask in LDS.
-//   Phase 2: waves take leaves from a shared counter. A leaf's points are
-//            held in registers (one point per lane) while its passing queries
-//            are taken two at a time; each query's projection is read with
-//            scalar loads. The cheap bound ||o'||^2 - 2 q'.o' <= thr (thr =
-//            tau^2 + margin - ||q'||^2, set by the bound kernel) keeps every
-//            point whose direct-difference pd^2 is within tau^2, plus a few
-//            just outside; the finishing kernel computes the exact pd^2 of
-//            the kept points, so the surplus never reaches a decision.
-//   Phase 3: staged hits are written with one reservation per (block, query)
-//            in the query's region of the pool (a wave whose stage is full
-//            reserves its further hits there directly). A region that overflows
-//            makes the finishing kernel hand its query to the per-query path.
-__global__ __launch_bounds__(WG) void filter_kernel(AnnArgs a) {
-    __shared__ FilterShared fs;
+// The wave's query tiles T, T + 1, ... with compile-time register indices.
+template <int T>
+__device__ __forceinline__ void scan_tiles(ScanShared& ss, int wave, int lane, uint32_t& wn,
+                                           const half8_t (&av)[4], const half8_t (&bq)[SQT],
+                                           int nt, int64_t p0, int t0) {
+    if constexpr (T < SQT) {
+        if (T < nt) scan_tile(ss, wave, lane, wn, av, bq[T], p0, (t0 + T) * 16);
+        scan_tiles<T + 1>(ss, wave, lane, wn, av, bq, nt, p0, t0);
+    }
+}
+
+__global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
+    __shared__ ScanShared ss;
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int q0 = blockIdx.y * FQB;
-    const int nqb = min(FQB, a.nq - q0);
-    const int64_t leaf0 = (int64_t)blockIdx.x * FLB;
-    const int nlb = (int)(a.n_leaves - leaf0 < FLB ? a.n_leaves - leaf0 : FLB);
-    const int leaf_base = a.level_begin[a.levels - 1];
-    for (int e = threadIdx.x; e < FQB; e += WG) {
-        fs.hits[e] = 0u;
-        fs.scan[e] = 0u;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int q0 = blockIdx.y * SQB;
+    const int nqb = min(SQB, a.nq - q0);
+    const int ntile = (nqb + 15) >> 4;
+    const int tpw = (ntile + NWAVE - 1) / NWAVE;
+    const int t0 = wave * tpw;
+    const int nt = max(0, min(ntile - t0, tpw));
+    for (int e = threadIdx.x; e < SQB; e += WG) {
+        ss.hits[e] = 0u;
+        ss.ovf[e] = 0u;
     }
-    if (threadIdx.x == 0) fs.next = 0u;
-    __syncthreads();
 
-    // Phase 1: waves 0 and 2 take queries 0..63, waves 1 and 3 queries
-    // 64..127; waves 0, 1 take the even leaves, waves 2, 3 the odd ones.
-    {
-        const int half = wave & 1;
-        const int ql = half * 64 + lane;
-        const bool qok = ql < nqb;
-        const int64_t gq = q0 + (qok ? ql : 0);
-        float qv[MP];
+    half8_t bq[SQT];
 #pragma unroll
-        for (int t = 0; t < MP; ++t) qv[t] = a.qp[gq * MP + t];
-        const float R = a.q_tau[gq], sl = a.q_slack[gq];
-        cfloat* piv = (cfloat*)a.piv;
-        float pv[PMLSH_MAX_PIVOTS];
-#pragma unroll
-        for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i) {
-            float acc = 0.f;
-            if (i < a.s) {
-#pragma unroll
-                for (int t = 0; t < MP; ++t) {
-                    const float d = qv[t] - piv[i * MP + t];
-                    acc = fmaf(d, d, acc);
-                }
-            }
-            pv[i] = sqrtf(acc);
-        }
-        cfloat* cen = (cfloat*)a.ncen;
-        cfloat* rad = (cfloat*)a.nrad;
-        cfloat* hmin = (cfloat*)a.hrmin;
-        cfloat* hmax = (cfloat*)a.hrmax;
-        cint32* npts = (cint32*)a.npts;
-        uint32_t scanned = 0;
-        for (int j = wave >> 1; j < nlb; j += 2) {
-            const int node = leaf_base + (int)leaf0 + j;
-            float acc = 0.f;
-#pragma unroll
-            for (int t = 0; t < MP; ++t) {
-                const float d = qv[t] - cen[(int64_t)t * a.n_nodes + node];
-                acc = fmaf(d, d, acc);
-            }
-            bool pass = qok & (sqrtf(acc) <= rad[node] + R + sl);
-#pragma unroll
-            for (int i = 0; i < PMLSH_MAX_PIVOTS; ++i)
-                if (i < a.s)
-                    pass = pass & (pv[i] - R <= hmax[(int64_t)i * a.n_nodes + node] + sl) &
-                           (pv[i] + R >= hmin[(int64_t)i * a.n_nodes + node] - sl);
-            const uint64_t m = __ballot(pass);
-            if (lane == 0) fs.mask[j][half] = m;
-            if (pass) scanned += (uint32_t)npts[node];
-        }
-        if (scanned) atomicAdd(&fs.scan[ql], scanned);
+    for (int t = 0; t < SQT; ++t) {
+        bq[t] = half8_t{};
+        const int qc = (t0 + t) * 16 + l16;
+        if (t < nt && qc < nqb) bq[t] = load_half8(a.qaug + (int64_t)(q0 + qc) * 32 + lq * 8);
     }
-    __syncthreads();
 
-    // Phase 2
-    // block-relative bases: per-query offsets stay 32-bit scalar arithmetic
-    cfloat* qblk = (cfloat*)(a.qp + (int64_t)q0 * MP);
-    cfloat* tblk = (cfloat*)(a.q_thr + q0);
-    cint32* cb = (cint32*)a.cb;
-    cint32* ce = (cint32*)a.ce;
-    uint32_t* wstg = fs.stg[wave];
-    uint8_t* wstq = fs.stq[wave];
     uint32_t wn = 0;
-    for (;;) {
-        uint32_t jn = 0;
-        if (lane == 0) jn = atomicAdd(&fs.next, 1u);
-        const int j = __builtin_amdgcn_readfirstlane((int)__shfl(jn, 0));
-        if (j >= nlb) break;
-        const uint64_t mk0 = fs.mask[j][0], mk1 = fs.mask[j][1];
-        const uint64_t m0i = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(mk0 >> 32)) << 32) |
-                             (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mk0);
-        const uint64_t m1i = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(mk1 >> 32)) << 32) |
-                             (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mk1);
-        if (!(m0i | m1i)) continue;
-        const int node = leaf_base + (int)leaf0 + j;
-        const int p0 = cb[node], p1 = ce[node];
-        for (int base = p0; base < p1; base += 64) {
-            const int pp = base + lane;
-            const bool valid = pp < p1;
-            float o[MP];
-            const float4* o4 = reinterpret_cast<const float4*>(a.proj + (int64_t)(valid ? pp : base) * MP);
+    const int64_t nchunk = a.n_pad16 >> 6;
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const int64_t p0 = c << 6;
+        half8_t av[4];
 #pragma unroll
-            for (int t = 0; t < MP / 4; ++t) {
-                const float4 v = o4[t];
-                o[4 * t] = v.x; o[4 * t + 1] = v.y; o[4 * t + 2] = v.z; o[4 * t + 3] = v.w;
-            }
-            float on2 = 0.f;
-#pragma unroll
-            for (int t = 0; t < MP; ++t) on2 = fmaf(o[t], o[t], on2);
-            // the two halves of the mask, two queries at a time
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint64_t m = h ? m1i : m0i;
-                while (m) {
-                    const int qa = h * 64 + __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1;
-                    const bool has_b = m != 0;
-                    const int qb = has_b ? h * 64 + __ffsll((unsigned long long)m) - 1 : qa;
-                    m &= m - 1;
-                    const int64_t ga = q0 + qa, gb = q0 + qb;
-                    cfloat* va = qblk + qa * MP;
-                    cfloat* vb = qblk + qb * MP;
-                    const float ta = tblk[qa], tb = tblk[qb];
-                    float da = 0.f, db = 0.f;
-#pragma unroll
-                    for (int t = 0; t < MP; ++t) {
-                        da = fmaf(va[t], o[t], da);
-                        db = fmaf(vb[t], o[t], db);
-                    }
-                    const bool ca = valid & (fmaf(-2.f, da, on2) <= ta);
-                    const bool cb2 = valid & has_b & (fmaf(-2.f, db, on2) <= tb);
-                    stage_hits(a, wstg, wstq, wn, ca, (uint32_t)pp, qa, ga);
-                    stage_hits(a, wstg, wstq, wn, cb2, (uint32_t)pp, qb, gb);
-                }
-            }
-        }
+        for (int mt = 0; mt < 4; ++mt)
+            av[mt] = load_half8(a.proj16 + (p0 + mt * 16 + l16) * 32 + lq * 8);
+        scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, p0, t0);
     }
-    __syncthreads();
 
-    // Phase 3: flush the stages with one reservation per query of the block
-    if (lane_id() == 0) fs.wn[wave] = wn;
+    // flush the stages with one reservation per query of the block
+    if (lane == 0) ss.wn[wave] = wn;
     __syncthreads();
     for (int w = 0; w < NWAVE; ++w)
-        for (uint32_t e = threadIdx.x; e < fs.wn[w]; e += WG) atomicAdd(&fs.hits[fs.stq[w][e]], 1u);
+        for (uint32_t e = threadIdx.x; e < ss.wn[w]; e += WG) atomicAdd(&ss.hits[ss.qid[w][e]], 1u);
     __syncthreads();
     for (int e = threadIdx.x; e < nqb; e += WG) {
-        if (fs.hits[e]) fs.base[e] = atomicAdd(&a.l_count[q0 + e], fs.hits[e]);
-        if (fs.scan[e]) atomicAdd(&a.q_scanned[q0 + e], fs.scan[e]);
-        fs.hits[e] = 0u;
+        const uint32_t h = ss.hits[e] + (ss.ovf[e] ? (uint32_t)a.q_cap + 1u : 0u);
+        if (h) ss.base[e] = atomicAdd(&a.l_count[q0 + e], h);
+        ss.hits[e] = 0u;
     }
     __syncthreads();
     for (int w = 0; w < NWAVE; ++w)
-        for (uint32_t e = threadIdx.x; e < fs.wn[w]; e += WG) {
-            const int q = fs.stq[w][e];
-            const uint32_t slot = fs.base[q] + atomicAdd(&fs.hits[q], 1u);
-            if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = fs.stg[w][e];
+        for (uint32_t e = threadIdx.x; e < ss.wn[w]; e += WG) {
+            const int q = ss.qid[w][e];
+            const uint32_t slot = ss.base[q] + atomicAdd(&ss.hits[q], 1u);
+            if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = ss.pos[w][e];
         }
 }
 
@@ -1280,8 +1240,6 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
 
 int64_t ann_pool_per_query(int64_t n) { return n < 16384 ? n : 16384; }
 
-int ann_leaf_blocks(int64_t n_leaves) { return (int)((n_leaves + FLB - 1) / FLB); }
-
 bool ann_fast_path(int64_t budget) { return budget <= CAP; }
 
 int ann_lds_bytes(int d_pad) {
@@ -1327,14 +1285,15 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.out_dist = L.out_dist;
     a.out_stats = L.out_stats;
     a.nq = (int)L.nq;
+    a.n = x.n;
+    a.proj16 = x.proj16;
+    a.n_pad16 = x.n_pad16;
+    a.scale16 = x.scale16;
     const int lds = ann_lds_bytes(x.d_pad);
     PMLSH_HIP(hipFuncSetAttribute((const void*)ann_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     if (ann_fast_path(L.budget)) {
-        a.q_tau = L.q_tau;
-        a.q_tau2 = L.q_tau2;
-        a.q_slack = L.q_slack;
-        a.q_thr = L.q_thr;
+        a.qaug = L.ws_qaug;
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;
@@ -1346,10 +1305,12 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
             hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
-        dim3 fgrid((unsigned)ann_leaf_blocks(x.n_leaves), (unsigned)((L.nq + FQB - 1) / FQB));
+        const int64_t nchunk = x.n_pad16 / 64;
+        dim3 sgrid((unsigned)(nchunk < kScanBlocks ? nchunk : kScanBlocks),
+                   (unsigned)((L.nq + SQB - 1) / SQB));
         {
             StageTimer tm(PMLSH_STAGE_FILTER, stream);
-            hipLaunchKernelGGL(filter_kernel, fgrid, dim3(WG), 0, stream, a);
+            hipLaunchKernelGGL(scan_kernel, sgrid, dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
         PMLSH_HIP(hipFuncSetAttribute((const void*)finish_kernel,

@@ -160,6 +160,18 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     launch_gather_proj(static_cast<const float*>(phi.p), x->perm, n, x->proj_hi, st);
     launch_gather_proj(static_cast<const float*>(plo.p), x->perm, n, x->proj_lo, st);
 
+    // ---- FP16 rows of the matrix-core scan, scaled by a power of two s with
+    // s * max ||o'|| < 32, so every entry stays far inside the FP16 range
+    {
+        int e = 0;
+        const float S = x->coord_scale;
+        if (S > 0.f && std::isfinite(S)) (void)std::frexp(S, &e);
+        x->scale16 = std::ldexp(1.f, 5 - e);
+        x->n_pad16 = (n + 63) / 64 * 64;
+        x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * 32);
+        launch_augment16(x->proj_hi, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
+    }
+
     // ---- r_min sample (Section 5.2): FP64 distances of sampled pairs
     if (n >= 2) {
         const int64_t S = std::min<int64_t>(n * (n - 1) / 2, kSamplePairs);

@@ -60,27 +60,25 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     const int64_t B = plan.budget;
     const bool fast = ann_fast_path(B);
     const int64_t pool_q = fast ? ann_pool_per_query(x->n) : 0;
-    // per query: projection, two frontier lists, C, top-k scratch, and for the
-    // leaf-major path seven scalars and a candidate region
-    const int64_t per_query = (int64_t)MP * 4 + 2 * x->n_leaves * 4 + B * 8 +
-                              3 * (int64_t)k * 4 + (fast ? 7 * 4 + pool_q * 4 : 0);
+    // per query: projection, FP16 scan row, two frontier lists, C, top-k
+    // scratch, and for the batched path three counters and a candidate region
+    const int64_t per_query = (int64_t)MP * 4 + 64 + 2 * x->n_leaves * 4 + B * 8 +
+                              3 * (int64_t)k * 4 + (fast ? 3 * 4 + pool_q * 4 : 0);
     int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query));
     batch = std::min<int64_t>(batch, 65535);
     void* ws = nullptr;
     PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query), st));
     char* base = static_cast<char*>(ws);
-    // projections first: every row starts on a 64-byte boundary
+    // projections and FP16 scan rows first: every row starts on a 64-byte
+    // boundary
     float* qproj = reinterpret_cast<float*>(base);
-    uint32_t* list = reinterpret_cast<uint32_t*>(qproj + batch * MP);
+    uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
+    uint32_t* list = reinterpret_cast<uint32_t*>(qaug + batch * 32);
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
     int32_t* cpos = front + batch * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);
     int32_t* topk = reinterpret_cast<int32_t*>(cdist + batch * B);
-    float* q_tau = reinterpret_cast<float*>(topk + batch * 3 * (int64_t)k);
-    float* q_tau2 = q_tau + batch;
-    float* q_slack = q_tau2 + batch;
-    float* q_thr = q_slack + batch;
-    int32_t* q_flag = reinterpret_cast<int32_t*>(q_thr + batch);
+    int32_t* q_flag = topk + batch * 3 * (int64_t)k;
     uint32_t* l_count = reinterpret_cast<uint32_t*>(q_flag + batch);
     uint32_t* q_scanned = l_count + batch;
     try {
@@ -106,10 +104,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             L.ws_cdist = cdist;
             L.ws_topk = topk;
             if (fast) {
-                L.q_tau = q_tau;
-                L.q_tau2 = q_tau2;
-                L.q_slack = q_slack;
-                L.q_thr = q_thr;
+                L.ws_qaug = qaug;
                 L.q_flag = q_flag;
                 L.l_count = l_count;
                 L.q_scanned = q_scanned;

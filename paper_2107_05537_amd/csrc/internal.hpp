@@ -14,6 +14,10 @@ namespace pmlsh {
 
 // Projected coordinates are padded from m to MP floats (zero pad lanes).
 constexpr int MP = 16;
+// Weight cm of the per-pair rounding margin cm * ||q'|| * ||o'|| of the FP16
+// scan: 2^-9 bounds the FP16 rounding of the projected dot product, the extra
+// 2^-14 absorbs the rounding of the margin term itself.
+constexpr float kScanMarginWeight = 0.001953125f + 0.00006103515625f;
 
 // Thread-local error message returned by pmlsh_last_error().
 void set_error(const std::string& msg);
@@ -90,6 +94,9 @@ struct pmlsh_index {
     float* data = nullptr;       // n x d_pad, zero padded
     float* proj_hi = nullptr;    // n x MP: FP32 rounding of the FP64 projection
     float* proj_lo = nullptr;    // n x MP: FP32 rounding of (projection - hi)
+    uint16_t* proj16 = nullptr;  // n_pad16 x 32 FP16 rows of the matrix-core scan
+    int64_t n_pad16 = 0;         // n rounded up to 64
+    float scale16 = 1.f;         // power-of-two scale s of those rows
     int32_t* perm = nullptr;     // leaf position -> id
     int32_t* inv_perm = nullptr; // id -> leaf position
     float* hash = nullptr;       // MP x d, zero rows beyond m
@@ -136,6 +143,8 @@ void launch_gather_rows(const float* src, int d, int64_t ld_src, const int32_t* 
                         int64_t rows, float* dst, int d_pad, hipStream_t stream);
 void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
                         float* dst, hipStream_t stream);
+void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm,
+                      uint16_t* out, hipStream_t stream);
 void launch_pair_dist_f64(const float* x, int d, int64_t ld, const int64_t* pairs,
                           int64_t count, double* out, hipStream_t stream);
 
@@ -152,14 +161,11 @@ struct AnnLaunch {
     float* ws_cdist;        // nq x budget
     int32_t* ws_topk;       // nq x 3 x k
     // leaf-major fast path, per query
-    float* q_tau;
-    float* q_tau2;
-    float* q_slack;
-    float* q_thr;
     int32_t* q_flag;
     uint32_t* l_count;
     uint32_t* q_scanned;
     uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
+    uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
     int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;
@@ -168,7 +174,6 @@ struct AnnLaunch {
 void launch_ann(const AnnLaunch& a, hipStream_t stream);
 int ann_lds_bytes(int d_pad);
 int64_t ann_pool_per_query(int64_t n);
-int ann_leaf_blocks(int64_t n_leaves);
 bool ann_fast_path(int64_t budget);
 
 }  // namespace pmlsh

@@ -96,6 +96,42 @@ __global__ __launch_bounds__(256) void gather_proj_kernel(
     }
 }
 
+// Rows of the FP16 matrix-core scan, 32 halves per point (the layout is
+// described with scan_kernel): s * o' (16 dims, pad zero), the hi/lo FP16 pair
+// of s^2 ||o'||^2, two ones that carry the query's threshold pair, and
+// cm * s * ||o'||, the weight of the rounding margin. Rows from n to n_pad are
+// zero, which never produce a candidate.
+__global__ __launch_bounds__(256) void augment16_kernel(
+    const float* __restrict__ proj, int64_t n, int64_t n_pad, float s, float cm,
+    uint4* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pad) return;
+    _Float16 v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = (_Float16)0.f;
+    if (p < n) {
+        float o[MP];
+        float on2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            o[t] = proj[p * MP + t];
+            on2 = fmaf(o[t], o[t], on2);
+        }
+#pragma unroll
+        for (int t = 0; t < MP; ++t) v[t] = (_Float16)(s * o[t]);
+        const float sn = s * s * on2;
+        const _Float16 hi = (_Float16)sn;
+        v[16] = hi;
+        v[17] = (_Float16)(sn - (float)hi);
+        v[18] = (_Float16)1.f;
+        v[19] = (_Float16)1.f;
+        v[20] = (_Float16)(cm * s * sqrtf(on2));
+    }
+    const uint4* src = reinterpret_cast<const uint4*>(v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[p * 4 + i] = src[i];
+}
+
 // FP64 Euclidean distance of row pairs (one wave per pair).
 __global__ __launch_bounds__(256) void pair_dist_f64_kernel(
     const float* __restrict__ x, int d, int64_t ld,
@@ -145,6 +181,14 @@ void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
     if (rows <= 0) return;
     hipLaunchKernelGGL(gather_proj_kernel, dim3(grid_for(rows * MP)), dim3(256), 0,
                        stream, src, perm, rows, dst);
+    PMLSH_HIP(hipGetLastError());
+}
+
+void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm,
+                      uint16_t* out, hipStream_t stream) {
+    if (n_pad <= 0) return;
+    hipLaunchKernelGGL(augment16_kernel, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0,
+                       stream, proj, n, n_pad, s, cm, reinterpret_cast<uint4*>(out));
     PMLSH_HIP(hipGetLastError());
 }
 
