@@ -213,9 +213,10 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
  * reset (reset != 0 clears the totals after reading). Stages:
  *   PMLSH_STAGE_PROJECT   query projection (FP64 matrix cores)
  *   PMLSH_STAGE_TAU       per-query bound on the B-th projected distance
- *   PMLSH_STAGE_FILTER    leaf-major range filter (Eq. 5) and candidate lists
+ *   PMLSH_STAGE_FILTER    range filter on the FP16 matrix cores, candidate pools
  *   PMLSH_STAGE_FINISH    budget cut, rounds of Algorithm 2, verification, top-k
- *   PMLSH_STAGE_PERQUERY  per-query kernel (queries outside the leaf-major path)
+ *   PMLSH_STAGE_PERQUERY  per-query kernel (queries outside the batched path)
+ *   PMLSH_STAGE_MASK      chunk-ball test (Eq. 5 on 64-point chunks) per query
  * Host-side bookkeeping only; enabling it does not change any result.
  */
 #define PMLSH_STAGE_PROJECT 0
@@ -223,7 +224,8 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
 #define PMLSH_STAGE_FILTER 2
 #define PMLSH_STAGE_FINISH 3
 #define PMLSH_STAGE_PERQUERY 4
-#define PMLSH_N_STAGES 5
+#define PMLSH_STAGE_MASK 5
+#define PMLSH_N_STAGES 6
 
 typedef struct {
     double ms[PMLSH_N_STAGES];

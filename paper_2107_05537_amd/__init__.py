@@ -63,10 +63,10 @@ class _Info(ctypes.Structure):
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5)]
+    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
 
 
-STAGES = ("project", "tau", "filter", "finish", "per_query")
+STAGES = ("project", "tau", "filter", "finish", "per_query", "mask")
 
 _LIB = None
 

@@ -26,6 +26,9 @@ FLAGS = [
     "-Wall", "-Wno-unused-result",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: the scan reads every result with
+    # vector instructions, which the AGPR form would precede with copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

@@ -85,6 +85,13 @@ struct AnnArgs {
     int64_t n_pad16;
     float scale16;
     uint16_t* qaug;
+    // chunk balls, the per-query radius of their test, and the resulting
+    // chunk x query bit mask (ceil(nq / 64) words per chunk)
+    const float* chunk_cen;
+    const float* chunk_rad;
+    float* qtau;
+    uint64_t* cmask;
+    int mwords;
 };
 
 struct Smem {
@@ -934,6 +941,10 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         R = R2 = __int_as_float(0x7f800000);
     }
     if (threadIdx.x == 0) {
+        // radius of the chunk-ball test: covers the FP32 errors of pd^2 and
+        // of the test's own distance (relative 2^-16 and 1e-5 (tau + S))
+        const float tq = sqrtf(R2);
+        a.qtau[qi] = tq * (1.f + 1.52587890625e-05f) + 1e-5f * (tq + a.coord_scale);
         a.l_count[qi] = 0u;
         a.q_scanned[qi] = (uint32_t)(a.n < 0x7fffffff ? a.n : 0x7fffffff);
         a.q_flag[qi] = 0;
@@ -1015,19 +1026,25 @@ struct ScanShared {
     uint32_t wn[NWAVE];
 };
 
+// Arrays read at wave-uniform addresses and never written by the kernel: the
+// constant address space turns their reads into scalar loads.
+typedef __attribute__((address_space(4))) const uint64_t cuint64;
+
 __device__ __forceinline__ half8_t load_half8(const uint16_t* p) {
     return __builtin_bit_cast(half8_t, *reinterpret_cast<const uint4*>(p));
 }
 
-// One 64-point x 16-query block: four MFMAs, then the negative results are
-// staged. Register r of the four tiles is tested together first; most
-// register positions hold no candidate.
-__device__ __forceinline__ void scan_tile(ScanShared& ss, int wave, int lane, uint32_t& wn,
-                                          const half8_t (&av)[4], half8_t b, int64_t p0, int qt) {
-    float4_t cc[4];
+__device__ __forceinline__ void scan_mfma(const half8_t (&av)[4], half8_t b, float4_t (&cc)[4]) {
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
         cc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[mt], b, float4_t{}, 0, 0, 0);
+}
+
+// Stages the negative results of one 64-point x 16-query block. Register r
+// of the four tiles is tested together first; most register positions hold
+// no candidate.
+__device__ __forceinline__ void scan_emit(ScanShared& ss, int wave, int lane, uint32_t& wn,
+                                          const float4_t (&cc)[4], int64_t p0, int qt) {
     const int q = qt + (lane & 15);
     const uint32_t prow = (uint32_t)p0 + 4u * (uint32_t)(lane >> 4);
 #pragma unroll
@@ -1060,13 +1077,65 @@ __device__ __forceinline__ void scan_tile(ScanShared& ss, int wave, int lane, ui
 }
 
 // The wave's query tiles T, T + 1, ... with compile-time register indices.
+// A tile is computed only when its 16-bit field of the chunk mask (one bit
+// per query) is non-zero.
 template <int T>
 __device__ __forceinline__ void scan_tiles(ScanShared& ss, int wave, int lane, uint32_t& wn,
                                            const half8_t (&av)[4], const half8_t (&bq)[SQT],
-                                           int nt, int64_t p0, int t0) {
+                                           int nt, int64_t p0, int t0, const uint64_t* cm) {
     if constexpr (T < SQT) {
-        if (T < nt) scan_tile(ss, wave, lane, wn, av, bq[T], p0, (t0 + T) * 16);
-        scan_tiles<T + 1>(ss, wave, lane, wn, av, bq, nt, p0, t0);
+        if (T < nt) {
+            // t0 is a multiple of 4: tile T's field is in word T / 4
+            if ((cm[T >> 2] >> (16 * (T & 3))) & 0xffffull) {
+                float4_t cc[4];
+                scan_mfma(av, bq[T], cc);
+                scan_emit(ss, wave, lane, wn, cc, p0, (t0 + T) * 16);
+            }
+        }
+        scan_tiles<T + 1>(ss, wave, lane, wn, av, bq, nt, p0, t0, cm);
+    }
+}
+
+// Chunk-ball test of Eq. 5 for every (chunk, query) pair: the chunk can hold
+// a point within tau of q' only if |q' - centre| <= radius + tau. One wave
+// tests 64 queries (one mask word) against 16 chunks in FP32.
+constexpr int MCH = 16;   // chunks per mask workgroup
+
+__global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
+    __shared__ float scen[MCH][MP];
+    __shared__ float srad[MCH];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * MCH;
+    const int64_t nchunk = a.n_pad16 >> 6;
+    for (int e = threadIdx.x; e < MCH * MP; e += WG) {
+        const int64_t c = c0 + e / MP;
+        scen[e / MP][e % MP] = c < nchunk ? a.chunk_cen[c * MP + e % MP] : 0.f;
+    }
+    for (int e = threadIdx.x; e < MCH; e += WG) srad[e] = c0 + e < nchunk ? a.chunk_rad[c0 + e] : -1.f;
+    __syncthreads();
+    const int q0 = blockIdx.y * SQB;
+    for (int w = wave; w < SQB / 64; w += NWAVE) {
+        const int q = q0 + w * 64 + lane;
+        if (q0 + w * 64 >= a.nq) break;
+        const bool valid = q < a.nq;
+        float qv[MP];
+        const int64_t qr = valid ? q : q0;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) qv[t] = a.qp[qr * MP + t];
+        const float tq = a.qtau[qr];
+        for (int i = 0; i < MCH; ++i) {
+            if (c0 + i >= nchunk) break;
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < MP; ++t) {
+                const float dlt = qv[t] - scen[i][t];
+                acc = fmaf(dlt, dlt, acc);
+            }
+            const float r = srad[i] + tq;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(valid && acc <= r * r);
+            if (lane == 0) a.cmask[(c0 + i) * a.mwords + (q0 >> 6) + w] = m;
+        }
     }
 }
 
@@ -1078,7 +1147,9 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     const int q0 = blockIdx.y * SQB;
     const int nqb = min(SQB, a.nq - q0);
     const int ntile = (nqb + 15) >> 4;
-    const int tpw = (ntile + NWAVE - 1) / NWAVE;
+    // tiles per wave, a multiple of 4 so that each wave's tiles start on a
+    // 64-query word of the chunk mask
+    const int tpw = (((ntile + NWAVE - 1) / NWAVE) + 3) & ~3;
     const int t0 = wave * tpw;
     const int nt = max(0, min(ntile - t0, tpw));
     for (int e = threadIdx.x; e < SQB; e += WG) {
@@ -1095,14 +1166,35 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     }
 
     uint32_t wn = 0;
+    // point chunks, the next chunk's rows loaded while this one is scanned
     const int64_t nchunk = a.n_pad16 >> 6;
-    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    int64_t c = blockIdx.x;
+    half8_t an[4];
+    if (c < nchunk) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            an[mt] = load_half8(a.proj16 + ((c << 6) + mt * 16 + l16) * 32 + lq * 8);
+    }
+    for (; c < nchunk; c += gridDim.x) {
         const int64_t p0 = c << 6;
         half8_t av[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-            av[mt] = load_half8(a.proj16 + (p0 + mt * 16 + l16) * 32 + lq * 8);
-        scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, p0, t0);
+        for (int mt = 0; mt < 4; ++mt) av[mt] = an[mt];
+        const int64_t cn = c + gridDim.x;
+        if (cn < nchunk) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                an[mt] = load_half8(a.proj16 + ((cn << 6) + mt * 16 + l16) * 32 + lq * 8);
+        }
+        // this wave's words of the chunk's query mask
+        uint64_t cm[SQT / 4];
+        cuint64* crow = (cuint64*)(a.cmask + c * a.mwords + (q0 >> 6));
+#pragma unroll
+        for (int k = 0; k < SQT / 4; ++k) {
+            const int wi = (t0 >> 2) + k;
+            cm[k] = wi < ((nqb + 63) >> 6) ? crow[wi] : 0ull;
+        }
+        scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, p0, t0, cm);
     }
 
     // flush the stages with one reservation per query of the block
@@ -1289,11 +1381,16 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.proj16 = x.proj16;
     a.n_pad16 = x.n_pad16;
     a.scale16 = x.scale16;
+    a.chunk_cen = x.chunk_cen;
+    a.chunk_rad = x.chunk_rad;
     const int lds = ann_lds_bytes(x.d_pad);
     PMLSH_HIP(hipFuncSetAttribute((const void*)ann_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     if (ann_fast_path(L.budget)) {
         a.qaug = L.ws_qaug;
+        a.qtau = L.ws_qtau;
+        a.cmask = L.ws_cmask;
+        a.mwords = (int)((L.nq + 63) / 64);
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;
@@ -1306,6 +1403,12 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
             PMLSH_HIP(hipGetLastError());
         }
         const int64_t nchunk = x.n_pad16 / 64;
+        {
+            StageTimer tm(PMLSH_STAGE_MASK, stream);
+            dim3 mgrid((unsigned)((nchunk + MCH - 1) / MCH), (unsigned)((L.nq + SQB - 1) / SQB));
+            hipLaunchKernelGGL(mask_kernel, mgrid, dim3(WG), 0, stream, a);
+            PMLSH_HIP(hipGetLastError());
+        }
         dim3 sgrid((unsigned)(nchunk < kScanBlocks ? nchunk : kScanBlocks),
                    (unsigned)((L.nq + SQB - 1) / SQB));
         {

@@ -170,6 +170,30 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         x->n_pad16 = (n + 63) / 64 * 64;
         x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * 32);
         launch_augment16(x->proj_hi, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
+        // covering ball of every 64-point chunk of the leaf order (the leaves
+        // themselves when the leaf size is 64): FP64 mean rounded to FP32,
+        // radius measured from that FP32 centre and rounded up
+        const int64_t nch = x->n_pad16 / 64;
+        std::vector<float> ccen((size_t)nch * MP, 0.f), crad((size_t)nch, 0.f);
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t j0 = c * 64, j1 = std::min<int64_t>(n, j0 + 64);
+            double mean[MP] = {0.0};
+            for (int64_t j = j0; j < j1; ++j)
+                for (int t = 0; t < MP; ++t) mean[t] += proj[(size_t)T.perm[j] * MP + t];
+            for (int t = 0; t < MP; ++t) ccen[(size_t)c * MP + t] = (float)(mean[t] / (double)(j1 - j0));
+            double r2 = 0.0;
+            for (int64_t j = j0; j < j1; ++j) {
+                double acc = 0.0;
+                for (int t = 0; t < MP; ++t) {
+                    const double dlt = (double)proj[(size_t)T.perm[j] * MP + t] - ccen[(size_t)c * MP + t];
+                    acc += dlt * dlt;
+                }
+                r2 = std::max(r2, acc);
+            }
+            crad[c] = std::nextafter((float)(std::sqrt(r2) * (1.0 + 1e-6)), INFINITY);
+        }
+        upload(ccen, &x->chunk_cen);
+        upload(crad, &x->chunk_rad);
     }
 
     // ---- r_min sample (Section 5.2): FP64 distances of sampled pairs

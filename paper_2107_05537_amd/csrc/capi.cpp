@@ -64,16 +64,23 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // scratch, and for the batched path three counters and a candidate region
     const int64_t per_query = (int64_t)MP * 4 + 64 + 2 * x->n_leaves * 4 + B * 8 +
                               3 * (int64_t)k * 4 + (fast ? 3 * 4 + pool_q * 4 : 0);
-    int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query));
+    // plus, for the batched path, the chunk x query mask: a 64-bit word per
+    // chunk and 64 queries
+    const int64_t nchunk = x->n_pad16 / 64;
+    const int64_t per_query_all = per_query + (fast ? 4 + (nchunk + 7) / 8 : 0);
+    int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     batch = std::min<int64_t>(batch, 65535);
+    const int64_t mask_bytes = fast ? nchunk * ((batch + 63) / 64) * 8 + batch * 4 : 0;
     void* ws = nullptr;
-    PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query), st));
+    PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query + mask_bytes), st));
     char* base = static_cast<char*>(ws);
     // projections and FP16 scan rows first: every row starts on a 64-byte
     // boundary
     float* qproj = reinterpret_cast<float*>(base);
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
-    uint32_t* list = reinterpret_cast<uint32_t*>(qaug + batch * 32);
+    uint64_t* cmask = reinterpret_cast<uint64_t*>(qaug + batch * 32);
+    float* qtau = reinterpret_cast<float*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
+    uint32_t* list = reinterpret_cast<uint32_t*>(qtau + (fast ? batch : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
     int32_t* cpos = front + batch * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);
@@ -105,6 +112,8 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             L.ws_topk = topk;
             if (fast) {
                 L.ws_qaug = qaug;
+                L.ws_qtau = qtau;
+                L.ws_cmask = cmask;
                 L.q_flag = q_flag;
                 L.l_count = l_count;
                 L.q_scanned = q_scanned;

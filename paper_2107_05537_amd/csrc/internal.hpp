@@ -97,6 +97,8 @@ struct pmlsh_index {
     uint16_t* proj16 = nullptr;  // n_pad16 x 32 FP16 rows of the matrix-core scan
     int64_t n_pad16 = 0;         // n rounded up to 64
     float scale16 = 1.f;         // power-of-two scale s of those rows
+    float* chunk_cen = nullptr;  // n_pad16 / 64 x MP: centre of each 64-point chunk
+    float* chunk_rad = nullptr;  // n_pad16 / 64: radius covering the chunk's points
     int32_t* perm = nullptr;     // leaf position -> id
     int32_t* inv_perm = nullptr; // id -> leaf position
     float* hash = nullptr;       // MP x d, zero rows beyond m
@@ -166,6 +168,8 @@ struct AnnLaunch {
     uint32_t* q_scanned;
     uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
     uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
+    float* ws_qtau;         // nq: radius of the chunk-ball test
+    uint64_t* ws_cmask;     // chunks x ceil(nq / 64): chunks each query must scan
     int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;
