@@ -23,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cstdint>
 
@@ -37,7 +38,7 @@ constexpr int NB = 2048;    // histogram bins of one radix-select step
 constexpr int CAP = 2048;   // keys sorted in LDS at once (power of two)
 constexpr int MAX_LEVELS = 16;
 constexpr int MAX_ROUNDS = 1000;
-constexpr int64_t kScanBlocks = 1024;   // scan workgroups striding over point chunks
+constexpr int64_t kScanBlocks = 1024;   // scan workgroups if the occupancy query fails
 
 struct AnnArgs {
     const float* data;
@@ -1018,12 +1019,15 @@ constexpr int SQB = 1024;               // queries per scan block
 constexpr int SQT = SQB / 16 / NWAVE;   // query tiles per wave
 constexpr int SSTG = 1024;              // candidates staged per wave
 
+constexpr int SQW = SQT * 16;           // queries per wave
+
+// Per-wave candidate stages: every wave stages, counts and flushes its own
+// candidates, so the scan needs no workgroup barrier.
 struct ScanShared {
     uint32_t pos[NWAVE][SSTG];          // staged candidates: leaf position
-    uint16_t qid[NWAVE][SSTG];          // and query within the block
-    uint32_t hits[SQB], base[SQB];
-    uint8_t ovf[SQB];                   // query lost candidates to a full stage
-    uint32_t wn[NWAVE];
+    uint8_t qid[NWAVE][SSTG];           // and query within the wave's range
+    uint32_t hits[NWAVE][SQW], base[NWAVE][SQW];
+    uint8_t ovf[NWAVE][SQW];            // query lost candidates to a full stage
 };
 
 // Arrays read at wave-uniform addresses and never written by the kernel: the
@@ -1045,7 +1049,7 @@ __device__ __forceinline__ void scan_mfma(const half8_t (&av)[4], half8_t b, flo
 // no candidate.
 __device__ __forceinline__ void scan_emit(ScanShared& ss, int wave, int lane, uint32_t& wn,
                                           const float4_t (&cc)[4], int64_t p0, int qt) {
-    const int q = qt + (lane & 15);
+    const int q = qt + (lane & 15);     // query within the wave's range
     const uint32_t prow = (uint32_t)p0 + 4u * (uint32_t)(lane >> 4);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1064,13 +1068,13 @@ __device__ __forceinline__ void scan_emit(ScanShared& ss, int wave, int lane, ui
             if (wn + nh <= (uint32_t)SSTG) {
                 if (c) {
                     ss.pos[wave][wn + rank] = pos;
-                    ss.qid[wave][wn + rank] = (uint16_t)q;
+                    ss.qid[wave][wn + rank] = (uint8_t)q;
                 }
                 wn += nh;
             } else if (c) {
-                // stage full: the query is marked and handed to the per-query
-                // path (its pool count is pushed past the capacity)
-                ss.ovf[q] = 1u;
+                // stage full within one chunk: the query is marked and handed
+                // to the per-query path (its pool count passes the capacity)
+                ss.ovf[wave][q] = 1u;
             }
         }
     }
@@ -1089,7 +1093,7 @@ __device__ __forceinline__ void scan_tiles(ScanShared& ss, int wave, int lane, u
             if ((cm[T >> 2] >> (16 * (T & 3))) & 0xffffull) {
                 float4_t cc[4];
                 scan_mfma(av, bq[T], cc);
-                scan_emit(ss, wave, lane, wn, cc, p0, (t0 + T) * 16);
+                scan_emit(ss, wave, lane, wn, cc, p0, T * 16);
             }
         }
         scan_tiles<T + 1>(ss, wave, lane, wn, av, bq, nt, p0, t0, cm);
@@ -1139,6 +1143,33 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
     }
 }
 
+// Writes the wave's staged candidates to the pool with one reservation per
+// query (queries qw0 .. qw0 + SQW - 1 of the batch) and empties the stage.
+// Only this wave touches its part of the shared memory.
+__device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared& ss, int wave, int lane, uint32_t& wn,
+                           int64_t qw0, int nqw) {
+    uint32_t* hits = ss.hits[wave];
+    uint32_t* base = ss.base[wave];
+    for (uint32_t e = lane; e < wn; e += 64) atomicAdd(&hits[ss.qid[wave][e]], 1u);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int e = lane; e < nqw; e += 64) {
+        const uint32_t h = hits[e] + (ss.ovf[wave][e] ? (uint32_t)a.q_cap + 1u : 0u);
+        if (h) base[e] = atomicAdd(&a.l_count[qw0 + e], h);
+        hits[e] = 0u;
+        ss.ovf[wave][e] = 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t e = lane; e < wn; e += 64) {
+        const int q = ss.qid[wave][e];
+        const uint32_t slot = base[q] + atomicAdd(&hits[q], 1u);
+        if (slot < (uint32_t)a.q_cap) a.l_list[(qw0 + q) * a.q_cap + slot] = ss.pos[wave][e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int e = lane; e < nqw; e += 64) hits[e] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wn = 0;
+}
+
 __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     __shared__ ScanShared ss;
     const int lane = lane_id();
@@ -1152,10 +1183,13 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     const int tpw = (((ntile + NWAVE - 1) / NWAVE) + 3) & ~3;
     const int t0 = wave * tpw;
     const int nt = max(0, min(ntile - t0, tpw));
-    for (int e = threadIdx.x; e < SQB; e += WG) {
-        ss.hits[e] = 0u;
-        ss.ovf[e] = 0u;
+    for (int e = lane; e < SQW; e += 64) {
+        ss.hits[wave][e] = 0u;
+        ss.ovf[wave][e] = 0u;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int64_t qw0 = (int64_t)q0 + t0 * 16;          // first query of this wave
+    const int nqw = max(0, min(nqb - t0 * 16, nt * 16));  // its queries
 
     half8_t bq[SQT];
 #pragma unroll
@@ -1166,55 +1200,53 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     }
 
     uint32_t wn = 0;
-    // point chunks, the next chunk's rows loaded while this one is scanned
+    // Point chunks. The FP16 rows are loaded two chunks ahead and the mask
+    // words one chunk ahead, so neither load is waited for on arrival.
     const int64_t nchunk = a.n_pad16 >> 6;
-    int64_t c = blockIdx.x;
-    half8_t an[4];
-    if (c < nchunk) {
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-            an[mt] = load_half8(a.proj16 + ((c << 6) + mt * 16 + l16) * 32 + lq * 8);
-    }
-    for (; c < nchunk; c += gridDim.x) {
-        const int64_t p0 = c << 6;
-        half8_t av[4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) av[mt] = an[mt];
-        const int64_t cn = c + gridDim.x;
-        if (cn < nchunk) {
+    const int64_t G = gridDim.x;
+    const int nwq = (nqb + 63) >> 6;   // mask words of this query block
+    auto load_rows = [&](int64_t cc, half8_t (&dst)[4]) {
+        if (cc < nchunk) {
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
-                an[mt] = load_half8(a.proj16 + ((cn << 6) + mt * 16 + l16) * 32 + lq * 8);
+                dst[mt] = load_half8(a.proj16 + ((cc << 6) + mt * 16 + l16) * 32 + lq * 8);
         }
-        // this wave's words of the chunk's query mask
-        uint64_t cm[SQT / 4];
-        cuint64* crow = (cuint64*)(a.cmask + c * a.mwords + (q0 >> 6));
+    };
+    auto load_mask = [&](int64_t cc, uint64_t (&dst)[SQT / 4]) {
+        if (cc < nchunk) {
+            cuint64* crow = (cuint64*)(a.cmask + cc * a.mwords + (q0 >> 6));
 #pragma unroll
-        for (int k = 0; k < SQT / 4; ++k) {
-            const int wi = (t0 >> 2) + k;
-            cm[k] = wi < ((nqb + 63) >> 6) ? crow[wi] : 0ull;
+            for (int k = 0; k < SQT / 4; ++k) {
+                const int wi = (t0 >> 2) + k;
+                dst[k] = wi < nwq ? crow[wi] : 0ull;
+            }
         }
+    };
+    int64_t c = blockIdx.x;
+    half8_t a1[4], a2[4];
+    uint64_t m1[SQT / 4];
+    load_rows(c, a1);
+    load_rows(c + G, a2);
+    load_mask(c, m1);
+    for (; c < nchunk; c += G) {
+        const int64_t p0 = c << 6;
+        half8_t av[4];
+        uint64_t cm[SQT / 4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            av[mt] = a1[mt];
+            a1[mt] = a2[mt];
+        }
+#pragma unroll
+        for (int k = 0; k < SQT / 4; ++k) cm[k] = m1[k];
+        load_rows(c + 2 * G, a2);
+        load_mask(c + G, m1);
+        // room for a chunk's typical candidates; a chunk that alone overflows
+        // the stage marks its queries instead
+        if (wn > (uint32_t)(SSTG - 256)) scan_flush(a, ss, wave, lane, wn, qw0, nqw);
         scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, p0, t0, cm);
     }
-
-    // flush the stages with one reservation per query of the block
-    if (lane == 0) ss.wn[wave] = wn;
-    __syncthreads();
-    for (int w = 0; w < NWAVE; ++w)
-        for (uint32_t e = threadIdx.x; e < ss.wn[w]; e += WG) atomicAdd(&ss.hits[ss.qid[w][e]], 1u);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nqb; e += WG) {
-        const uint32_t h = ss.hits[e] + (ss.ovf[e] ? (uint32_t)a.q_cap + 1u : 0u);
-        if (h) ss.base[e] = atomicAdd(&a.l_count[q0 + e], h);
-        ss.hits[e] = 0u;
-    }
-    __syncthreads();
-    for (int w = 0; w < NWAVE; ++w)
-        for (uint32_t e = threadIdx.x; e < ss.wn[w]; e += WG) {
-            const int q = ss.qid[w][e];
-            const uint32_t slot = ss.base[q] + atomicAdd(&ss.hits[q], 1u);
-            if (slot < (uint32_t)a.q_cap) a.l_list[(int64_t)(q0 + q) * a.q_cap + slot] = ss.pos[w][e];
-        }
+    scan_flush(a, ss, wave, lane, wn, qw0, nqw);
 }
 
 __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
@@ -1409,8 +1441,19 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
             hipLaunchKernelGGL(mask_kernel, mgrid, dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
-        dim3 sgrid((unsigned)(nchunk < kScanBlocks ? nchunk : kScanBlocks),
-                   (unsigned)((L.nq + SQB - 1) / SQB));
+        // one resident wave of workgroups striding over the chunks
+        static thread_local int scan_slots[64] = {0};
+        int& slots = scan_slots[x.device & 63];
+        if (slots == 0) {
+            int per_cu = 0, cus = 0;
+            PMLSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scan_kernel, WG, 0));
+            PMLSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x.device));
+            slots = per_cu > 0 && cus > 0 ? per_cu * cus : (int)kScanBlocks;
+        }
+        const int64_t ny = (L.nq + SQB - 1) / SQB;
+        int64_t gx = std::max<int64_t>(1, slots / ny);
+        gx = std::min(gx, nchunk);
+        dim3 sgrid((unsigned)gx, (unsigned)ny);
         {
             StageTimer tm(PMLSH_STAGE_FILTER, stream);
             hipLaunchKernelGGL(scan_kernel, sgrid, dim3(WG), 0, stream, a);
