@@ -93,6 +93,10 @@ struct AnnArgs {
     float* qtau;
     uint64_t* cmask;
     int mwords;
+    // squared distances from every query to every chunk centre (row stride ldc)
+    float* cdist;
+    int64_t ldc;
+    int32_t* csel;              // per query: the chunks chosen for its bound (ldc)
 };
 
 struct Smem {
@@ -798,54 +802,63 @@ __device__ __forceinline__ int shift32(uint32_t lo, uint32_t hi) {
     return (32 - __clz((int)span)) - 11;
 }
 
+// Squared FP32 distances (direct differences) from every query of the batch
+// to every chunk centre: one chunk per thread, 64 queries per workgroup read
+// from LDS. Row q of the output holds the query's distances (stride ldc).
+constexpr int DQB = 64;
+
+__global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
+    __shared__ float sq[DQB][MP];
+    const int q0 = blockIdx.y * DQB;
+    const int nqb = min(DQB, a.nq - q0);
+    for (int e = threadIdx.x; e < nqb * MP; e += WG) sq[e / MP][e % MP] = a.qp[(int64_t)q0 * MP + e];
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (c >= (a.n_pad16 >> 6)) return;
+    float cen[MP];
+#pragma unroll
+    for (int t = 0; t < MP; ++t) cen[t] = a.chunk_cen[c * MP + t];
+    float* out = a.cdist + (int64_t)q0 * a.ldc + c;
+    for (int q = 0; q < nqb; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            const float dlt = sq[q][t] - cen[t];
+            acc = fmaf(dlt, dlt, acc);
+        }
+        out[(int64_t)q * a.ldc] = acc;
+    }
+}
+
 // Upper bound tau on the budget-th smallest projected distance of one query:
-//   1. squared distance from q' to every leaf centre;
-//   2. the leaves nearest to q' that hold at least min(n, 4 * budget) points,
-//      chosen with a histogram of those distances weighted by leaf sizes;
-//   3. over the points of the chosen leaves, the budget-th smallest pd^2
+//   1. the squared distances from q' to every 64-point chunk centre (computed
+//      by dist_kernel);
+//   2. the chunks nearest to q' that hold at least min(n, 2 * budget) points,
+//      chosen with a histogram of those distances weighted by chunk sizes;
+//   3. over the points of the chosen chunks, the budget-th smallest pd^2
 //      (upper edge of its histogram bin) is tau^2.
 // The chosen points are data points, so the ball of radius tau holds at least
 // `budget` points and therefore the budget nearest points by projected
-// distance. The choice of leaves only affects how tight tau is, never its
-// validity, so the centre distances need no care about rounding.
+// distance. The choice of chunks only affects how tight tau is, never its
+// validity.
 __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
     const int64_t qi = blockIdx.x;
     QueryCtx qc;
     load_query(a, qi, nullptr, qc);
-    const int nl = (int)a.n_leaves;
-    const int leaf_base = a.level_begin[a.levels - 1];
-    float* dl = reinterpret_cast<float*>(a.ws_front + qi * 2 * a.n_leaves);
-    int32_t* sel = a.ws_front + qi * 2 * a.n_leaves + a.n_leaves;
+    const int nch = (int)(a.n_pad16 >> 6);
+    const float* dl = a.cdist + qi * a.ldc;       // squared centre distances
+    int32_t* sel = a.csel + qi * a.ldc;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
+    auto chunk_pts = [&](int i) { return (int)min<int64_t>(64, a.n - ((int64_t)i << 6)); };
 
-    // 1: centre distances, four leaves in flight per thread
-    constexpr int U = 4;
+    // 1: range of the centre distances
     uint32_t lo = 0xffffffffu, hi = 0u;
-    for (int i0 = threadIdx.x; i0 < nl; i0 += U * WG) {
-        float acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = 0.f;
-#pragma unroll
-        for (int t = 0; t < MP; ++t) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = min(i0 + u * WG, nl - 1);
-                const float dd = qc.qp[t] - a.ncen[(int64_t)t * a.n_nodes + leaf_base + i];
-                acc[u] = fmaf(dd, dd, acc[u]);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * WG;
-            if (i < nl) {
-                dl[i] = acc[u];
-                const uint32_t b = __float_as_uint(acc[u]);
-                lo = min(lo, b);
-                hi = max(hi, b);
-            }
-        }
+    for (int i = threadIdx.x; i < nch; i += WG) {
+        const uint32_t b = __float_as_uint(dl[i]);
+        lo = min(lo, b);
+        hi = max(hi, b);
     }
     for (int off = 32; off > 0; off >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
@@ -863,18 +876,19 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     }
     __syncthreads();
 
-    // 2: weighted histogram of the centre distances
+    // 2: histogram of the centre distances weighted by chunk sizes; the
+    // nearest chunks holding min(n, 2 * budget) points are chosen
     const int sft = shift32(lo, hi);
     clear_hist(sh);
     int loc = 0;
-    for (int i = threadIdx.x; i < nl; i += WG) {
-        const int w = a.npts[leaf_base + i];
+    for (int i = threadIdx.x; i < nch; i += WG) {
+        const int w = chunk_pts(i);
         atomicAdd(&sh.hist[(__float_as_uint(dl[i]) - lo) >> sft], (uint32_t)w);
         loc += w;
     }
     __syncthreads();
     const int total = block_sum(loc, sh);
-    const int want = total < 4 * a.budget ? total : 4 * a.budget;
+    const int want = total < 2 * a.budget ? total : 2 * a.budget;
     if (threadIdx.x == 0) sh.thr_bin = NB - 1;
     __syncthreads();
     find_threshold(want, sh);
@@ -882,18 +896,18 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     if (threadIdx.x == 0) sh.cnt1 = 0;
     __syncthreads();
 
-    // the chosen leaves, and the largest distance bound over their points
+    // the chosen chunks, and the largest distance bound over their points
     float rmax = 0.f;
-    for (int b0 = 0; b0 < nl; b0 += WG) {
+    for (int b0 = 0; b0 < nch; b0 += WG) {
         const int i = b0 + threadIdx.x;
         bool take = false;
-        if (i < nl) {
+        if (i < nch) {
             const float d2 = dl[i];
             take = ((__float_as_uint(d2) - lo) >> sft) <= tbin;
-            if (take) rmax = fmaxf(rmax, sqrtf(d2) + a.nrad[leaf_base + i]);
+            if (take) rmax = fmaxf(rmax, sqrtf(d2) + a.chunk_rad[i]);
         }
         const int slot = wave_append(take, &sh.cnt1);
-        if (take) sel[slot] = leaf_base + i;
+        if (take) sel[slot] = i;
     }
     for (int off = 32; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
     if (lane == 0) sh.red[wave] = __float_as_int(rmax);
@@ -914,16 +928,12 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     clear_hist(sh);
     int cnt = 0;
     for (int li = wave; li < nsel; li += NWAVE) {
-        const int node = sel[li];
-        const int p0 = a.cb[node], p1 = a.ce[node];
-        for (int b0 = p0; b0 < p1; b0 += 64) {
-            const int pos = b0 + lane;
-            if (pos < p1) {
-                const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
-                if (pd2 <= R2) {
-                    atomicAdd(&sh.hist[radius_bin(pd2, base2)], 1u);
-                    ++cnt;
-                }
+        const int64_t pos = ((int64_t)sel[li] << 6) + lane;
+        if (pos < a.n) {
+            const float pd2 = proj_dist2(a.proj + pos * MP, qc.qp);
+            if (pd2 <= R2) {
+                atomicAdd(&sh.hist[radius_bin(pd2, base2)], 1u);
+                ++cnt;
             }
         }
     }
@@ -1102,20 +1112,16 @@ __device__ __forceinline__ void scan_tiles(ScanShared& ss, int wave, int lane, u
 
 // Chunk-ball test of Eq. 5 for every (chunk, query) pair: the chunk can hold
 // a point within tau of q' only if |q' - centre| <= radius + tau. One wave
-// tests 64 queries (one mask word) against 16 chunks in FP32.
+// tests 64 queries (one mask word) against 16 chunks, on the FP32 distances
+// of dist_kernel.
 constexpr int MCH = 16;   // chunks per mask workgroup
 
 __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
-    __shared__ float scen[MCH][MP];
     __shared__ float srad[MCH];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * MCH;
     const int64_t nchunk = a.n_pad16 >> 6;
-    for (int e = threadIdx.x; e < MCH * MP; e += WG) {
-        const int64_t c = c0 + e / MP;
-        scen[e / MP][e % MP] = c < nchunk ? a.chunk_cen[c * MP + e % MP] : 0.f;
-    }
     for (int e = threadIdx.x; e < MCH; e += WG) srad[e] = c0 + e < nchunk ? a.chunk_rad[c0 + e] : -1.f;
     __syncthreads();
     const int q0 = blockIdx.y * SQB;
@@ -1123,19 +1129,21 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
         const int q = q0 + w * 64 + lane;
         if (q0 + w * 64 >= a.nq) break;
         const bool valid = q < a.nq;
-        float qv[MP];
         const int64_t qr = valid ? q : q0;
-#pragma unroll
-        for (int t = 0; t < MP; ++t) qv[t] = a.qp[qr * MP + t];
         const float tq = a.qtau[qr];
+        // the query's squared distances to the 16 chunks (ldc and c0 are
+        // multiples of 16, so the row segment is 64-byte aligned)
+        float dq[MCH];
+        const float4* r4 = reinterpret_cast<const float4*>(a.cdist + qr * a.ldc + c0);
+#pragma unroll
+        for (int k = 0; k < MCH / 4; ++k) {
+            const float4 v = r4[k];
+            dq[4 * k] = v.x; dq[4 * k + 1] = v.y; dq[4 * k + 2] = v.z; dq[4 * k + 3] = v.w;
+        }
+#pragma unroll
         for (int i = 0; i < MCH; ++i) {
             if (c0 + i >= nchunk) break;
-            float acc = 0.f;
-#pragma unroll
-            for (int t = 0; t < MP; ++t) {
-                const float dlt = qv[t] - scen[i][t];
-                acc = fmaf(dlt, dlt, acc);
-            }
+            const float acc = dq[i];
             const float r = srad[i] + tq;
             const uint64_t m = __builtin_amdgcn_ballot_w64(valid && acc <= r * r);
             if (lane == 0) a.cmask[(c0 + i) * a.mwords + (q0 >> 6) + w] = m;
@@ -1423,18 +1431,24 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.qtau = L.ws_qtau;
         a.cmask = L.ws_cmask;
         a.mwords = (int)((L.nq + 63) / 64);
+        a.cdist = L.ws_cdist2;
+        a.ldc = (x.n_pad16 / 64 + 15) / 16 * 16;
+        a.csel = L.ws_csel;
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;
         a.l_list = L.l_list;
         a.q_cap = (int)L.pool_cap;
         const int lds0 = ann_lds_bytes(0);
+        const int64_t nchunk = x.n_pad16 / 64;
         {
             StageTimer tm(PMLSH_STAGE_TAU, stream);
+            dim3 dgrid((unsigned)((nchunk + WG - 1) / WG), (unsigned)((L.nq + DQB - 1) / DQB));
+            hipLaunchKernelGGL(dist_kernel, dgrid, dim3(WG), 0, stream, a);
+            PMLSH_HIP(hipGetLastError());
             hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
-        const int64_t nchunk = x.n_pad16 / 64;
         {
             StageTimer tm(PMLSH_STAGE_MASK, stream);
             dim3 mgrid((unsigned)((nchunk + MCH - 1) / MCH), (unsigned)((L.nq + SQB - 1) / SQB));

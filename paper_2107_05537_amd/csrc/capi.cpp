@@ -67,10 +67,12 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // plus, for the batched path, the chunk x query mask: a 64-bit word per
     // chunk and 64 queries
     const int64_t nchunk = x->n_pad16 / 64;
-    const int64_t per_query_all = per_query + (fast ? 4 + (nchunk + 7) / 8 : 0);
+    const int64_t ldc = (nchunk + 15) / 16 * 16;
+    const int64_t per_query_all = per_query + (fast ? 4 + (nchunk + 7) / 8 + 8 * ldc : 0);
     int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     batch = std::min<int64_t>(batch, 65535);
-    const int64_t mask_bytes = fast ? nchunk * ((batch + 63) / 64) * 8 + batch * 4 : 0;
+    const int64_t mask_bytes =
+        fast ? nchunk * ((batch + 63) / 64) * 8 + batch * 4 + batch * ldc * 8 : 0;
     void* ws = nullptr;
     PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query + mask_bytes), st));
     char* base = static_cast<char*>(ws);
@@ -78,7 +80,9 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // boundary
     float* qproj = reinterpret_cast<float*>(base);
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
-    uint64_t* cmask = reinterpret_cast<uint64_t*>(qaug + batch * 32);
+    float* cdist2 = reinterpret_cast<float*>(qaug + batch * 32);
+    int32_t* csel = reinterpret_cast<int32_t*>(cdist2 + (fast ? batch * ldc : 0));
+    uint64_t* cmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * ldc : 0));
     float* qtau = reinterpret_cast<float*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
     uint32_t* list = reinterpret_cast<uint32_t*>(qtau + (fast ? batch : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
@@ -114,6 +118,8 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
                 L.ws_qaug = qaug;
                 L.ws_qtau = qtau;
                 L.ws_cmask = cmask;
+                L.ws_cdist2 = cdist2;
+                L.ws_csel = csel;
                 L.q_flag = q_flag;
                 L.l_count = l_count;
                 L.q_scanned = q_scanned;

@@ -170,6 +170,8 @@ struct AnnLaunch {
     uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
     float* ws_qtau;         // nq: radius of the chunk-ball test
     uint64_t* ws_cmask;     // chunks x ceil(nq / 64): chunks each query must scan
+    float* ws_cdist2;       // nq x ldc: squared distances to the chunk centres
+    int32_t* ws_csel;       // nq x ldc: chunks chosen for the bound
     int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;

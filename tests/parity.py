@@ -75,8 +75,9 @@ def compare_ann(D, Q, res, ids, dist, stats=None):
         assert min(gi) >= 0 and max(gi) < D.shape[0]
         ex = oann.exact_dist(D, Q[qi], np.asarray(gi))
         np.testing.assert_allclose(gd, ex, rtol=TOL, atol=1e-6)
-        key = list(zip(gd.tolist(), gi))
-        assert key == sorted(key)
+        # the library orders by (FP32 squared distance, id); the square root
+        # can merge two squared distances, so only the distances are checked
+        assert np.all(np.diff(gd) >= 0), (qi, gd)
         set_fragile = any(v <= FRAGILE for kind, v in r.margins.items()
                           if kind != "topk_order")
         if not set_fragile:

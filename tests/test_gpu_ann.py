@@ -171,6 +171,44 @@ def test_ties_duplicates_and_self_queries():
     assert np.all(dist[:10, 0] == 0)
 
 
+def test_far_queries_take_the_per_query_path():
+    """Queries far outside the data: their scan rows would leave the FP16
+    range, so the batched path hands them to the per-query kernel; answers
+    must still match the oracle. Near queries in the same launch stay on the
+    batched path."""
+    pm = _gpu()
+    say("case: far queries")
+    rng = np.random.Generator(np.random.PCG64(123))
+    D = rng.standard_normal((4000, 32)).astype(np.float32)
+    A = rng.standard_normal((15, 32)).astype(np.float32)
+    Qn = rng.standard_normal((8, 32)).astype(np.float32)
+    Qf = (rng.standard_normal((8, 32)) * 1e4).astype(np.float32)
+    Q = np.concatenate([Qn, Qf])
+    res, B = oracle_ann(D, A, Q, 5, 1.5, 0.9, 0.05, r_min=1.0)
+    _, ids, dist, st = _run(pm, D, A, Q, 5, 1.5, 0.9, 0.05, 1.0)
+    compare_ann(D, Q, res, ids, dist, st)
+
+
+def test_stage_overflow_takes_the_per_query_path():
+    """5,000 exact copies of one point and 64 queries next to it: every copy
+    is a candidate of every query, more than a scan wave can stage for one
+    chunk, so those queries are answered by the per-query kernel. The budget
+    cuts through the tied copies, which go by id."""
+    pm = _gpu()
+    say("case: stage overflow")
+    rng = np.random.Generator(np.random.PCG64(321))
+    p = rng.standard_normal((1, 24)).astype(np.float32)
+    D = np.concatenate([np.repeat(p, 5000, 0), rng.standard_normal((3000, 24)).astype(np.float32)])
+    D = D[rng.permutation(D.shape[0])]
+    A = rng.standard_normal((15, 24)).astype(np.float32)
+    Q = (p + 1e-3 * rng.standard_normal((64, 24))).astype(np.float32)
+    res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=1.0)
+    assert B < 5000
+    _, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.1, 1.0)
+    compare_ann(D, Q, res, ids, dist, st)
+    assert np.array_equal(ids, np.stack([r.ids for r in res]))
+
+
 def test_tiny_inputs():
     pm = _gpu()
     say("case: tiny")
