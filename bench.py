@@ -228,7 +228,7 @@ def main():
 
     # roofline of the dominant stage, from its live per-launch duration
     d_pad = (d + 3) // 4 * 4
-    dom = max(("tau", "mask", "filter", "finish", "per_query"), key=lambda k: stages[k]["ms"])
+    dom = max(("dist", "tau", "filter", "finish", "per_query"), key=lambda k: stages[k]["ms"])
     launches = max(1, stages[dom]["launches"])
     per_launch_ms = stages[dom]["ms"] / launches
     if dom == "filter":

@@ -212,11 +212,13 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
  * returns the summed milliseconds and launch counts per stage since the last
  * reset (reset != 0 clears the totals after reading). Stages:
  *   PMLSH_STAGE_PROJECT   query projection (FP64 matrix cores)
- *   PMLSH_STAGE_TAU       per-query bound on the B-th projected distance
+ *   PMLSH_STAGE_TAU       per-query bound on the B-th projected distance and the
+ *                         chunk-ball test of Eq. 5
  *   PMLSH_STAGE_FILTER    range filter on the FP16 matrix cores, candidate pools
  *   PMLSH_STAGE_FINISH    budget cut, rounds of Algorithm 2, verification, top-k
  *   PMLSH_STAGE_PERQUERY  per-query kernel (queries outside the batched path)
- *   PMLSH_STAGE_MASK      chunk-ball test (Eq. 5 on 64-point chunks) per query
+ *   PMLSH_STAGE_DIST      squared distances from every query to every 64-point
+ *                         chunk centre (input of the bound and of Eq. 5)
  * Host-side bookkeeping only; enabling it does not change any result.
  */
 #define PMLSH_STAGE_PROJECT 0
@@ -224,7 +226,7 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
 #define PMLSH_STAGE_FILTER 2
 #define PMLSH_STAGE_FINISH 3
 #define PMLSH_STAGE_PERQUERY 4
-#define PMLSH_STAGE_MASK 5
+#define PMLSH_STAGE_DIST 5
 #define PMLSH_N_STAGES 6
 
 typedef struct {

@@ -66,7 +66,7 @@ class _Timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
 
 
-STAGES = ("project", "tau", "filter", "finish", "per_query", "mask")
+STAGES = ("project", "tau", "filter", "finish", "per_query", "dist")
 
 _LIB = None
 

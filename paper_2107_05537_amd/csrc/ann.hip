@@ -86,13 +86,14 @@ struct AnnArgs {
     int64_t n_pad16;
     float scale16;
     uint16_t* qaug;
-    // chunk balls, the per-query radius of their test, and the resulting
-    // chunk x query bit mask (ceil(nq / 64) words per chunk)
+    // chunk balls and the query x chunk bit mask of their test (mwords words
+    // per query, bit-sliced: bit l of word 4 g + k is chunk 256 g + 4 l + k)
     const float* chunk_cen;
     const float* chunk_rad;
-    float* qtau;
-    uint64_t* cmask;
+    uint64_t* qmask;
     int mwords;
+    uint64_t* cmask;            // the same mask chunk-major: ceil(nq / 64) words per chunk
+    int cwords;
     // squared distances from every query to every chunk centre (row stride ldc)
     float* cdist;
     int64_t ldc;
@@ -830,17 +831,23 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
     }
 }
 
-// Upper bound tau on the budget-th smallest projected distance of one query:
+// Upper bound tau on the budget-th smallest projected distance of one query,
+// and the query's row of the chunk mask:
 //   1. the squared distances from q' to every 64-point chunk centre (computed
-//      by dist_kernel);
+//      by dist_kernel), read four chunks per thread;
 //   2. the chunks nearest to q' that hold at least min(n, 2 * budget) points,
 //      chosen with a histogram of those distances weighted by chunk sizes;
 //   3. over the points of the chosen chunks, the budget-th smallest pd^2
-//      (upper edge of its histogram bin) is tau^2.
+//      (upper edge of its histogram bin) is tau^2;
+//   4. the chunk-ball test of Eq. 5 for every chunk: the chunk can hold a
+//      point within tau of q' only if |q' - centre| <= radius + tau.
 // The chosen points are data points, so the ball of radius tau holds at least
 // `budget` points and therefore the budget nearest points by projected
 // distance. The choice of chunks only affects how tight tau is, never its
 // validity.
+//
+// Mask layout (query-major, bit-sliced to match four chunks per thread): bit l
+// of word 4 g + k of a query's row is chunk 256 g + 4 l + k.
 __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
@@ -848,17 +855,24 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     QueryCtx qc;
     load_query(a, qi, nullptr, qc);
     const int nch = (int)(a.n_pad16 >> 6);
-    const float* dl = a.cdist + qi * a.ldc;       // squared centre distances
+    const int ng4 = (nch + 3) >> 2;
+    const float4* row4 = reinterpret_cast<const float4*>(a.cdist + qi * a.ldc);
     int32_t* sel = a.csel + qi * a.ldc;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     auto chunk_pts = [&](int i) { return (int)min<int64_t>(64, a.n - ((int64_t)i << 6)); };
+    auto comp = [](const float4& v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; };
 
     // 1: range of the centre distances
     uint32_t lo = 0xffffffffu, hi = 0u;
-    for (int i = threadIdx.x; i < nch; i += WG) {
-        const uint32_t b = __float_as_uint(dl[i]);
-        lo = min(lo, b);
-        hi = max(hi, b);
+    for (int g = threadIdx.x; g < ng4; g += WG) {
+        const float4 v = row4[g];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (4 * g + k < nch) {
+                const uint32_t b = __float_as_uint(comp(v, k));
+                lo = min(lo, b);
+                hi = max(hi, b);
+            }
     }
     for (int off = 32; off > 0; off >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
@@ -881,10 +895,17 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     const int sft = shift32(lo, hi);
     clear_hist(sh);
     int loc = 0;
-    for (int i = threadIdx.x; i < nch; i += WG) {
-        const int w = chunk_pts(i);
-        atomicAdd(&sh.hist[(__float_as_uint(dl[i]) - lo) >> sft], (uint32_t)w);
-        loc += w;
+    for (int g = threadIdx.x; g < ng4; g += WG) {
+        const float4 v = row4[g];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = 4 * g + k;
+            if (i < nch) {
+                const int w = chunk_pts(i);
+                atomicAdd(&sh.hist[(__float_as_uint(comp(v, k)) - lo) >> sft], (uint32_t)w);
+                loc += w;
+            }
+        }
     }
     __syncthreads();
     const int total = block_sum(loc, sh);
@@ -898,16 +919,19 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
 
     // the chosen chunks, and the largest distance bound over their points
     float rmax = 0.f;
-    for (int b0 = 0; b0 < nch; b0 += WG) {
-        const int i = b0 + threadIdx.x;
-        bool take = false;
-        if (i < nch) {
-            const float d2 = dl[i];
-            take = ((__float_as_uint(d2) - lo) >> sft) <= tbin;
+    for (int b0 = 0; b0 < ng4; b0 += WG) {
+        const int g = b0 + threadIdx.x;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g < ng4) v = row4[g];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = 4 * g + k;
+            const float d2 = comp(v, k);
+            const bool take = g < ng4 && i < nch && ((__float_as_uint(d2) - lo) >> sft) <= tbin;
             if (take) rmax = fmaxf(rmax, sqrtf(d2) + a.chunk_rad[i]);
+            const int slot = wave_append(take, &sh.cnt1);
+            if (take) sel[slot] = i;
         }
-        const int slot = wave_append(take, &sh.cnt1);
-        if (take) sel[slot] = i;
     }
     for (int off = 32; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
     if (lane == 0) sh.red[wave] = __float_as_int(rmax);
@@ -927,8 +951,8 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     const uint32_t base2 = hb2 > (uint32_t)(NB - 1) ? hb2 - (uint32_t)(NB - 1) : 0u;
     clear_hist(sh);
     int cnt = 0;
-    for (int li = wave; li < nsel; li += NWAVE) {
-        const int64_t pos = ((int64_t)sel[li] << 6) + lane;
+    for (int e = threadIdx.x; e < nsel * 64; e += WG) {
+        const int64_t pos = ((int64_t)sel[e >> 6] << 6) + (e & 63);
         if (pos < a.n) {
             const float pd2 = proj_dist2(a.proj + pos * MP, qc.qp);
             if (pd2 <= R2) {
@@ -943,19 +967,40 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         __syncthreads();
         find_threshold(a.budget, sh);
         const float e2 = __uint_as_float((base2 + (uint32_t)sh.thr_bin + 1u) << 15);
-        if (e2 < R2) {
-            R2 = e2;
-            R = sqrtf(e2);
-        }
+        if (e2 < R2) R2 = e2;
     } else {
         // rounding left fewer than `budget` chosen points inside R: no bound
-        R = R2 = __int_as_float(0x7f800000);
+        R2 = __int_as_float(0x7f800000);
     }
+
+    // 4: the chunk-ball test; the radius covers the FP32 errors of pd^2 and
+    // of the test's own distance (relative 2^-16 and 1e-5 (tau + S))
+    {
+        const float tq0 = sqrtf(R2);
+        const float tq = tq0 * (1.f + 1.52587890625e-05f) + 1e-5f * (tq0 + a.coord_scale);
+        const int ng256 = (nch + 255) >> 8;
+        const float4* rad4 = reinterpret_cast<const float4*>(a.chunk_rad);
+        for (int G = wave; G < ng256; G += NWAVE) {
+            const int g = (G << 6) + lane;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f), rv = v;
+            if (g < ng4) {
+                v = row4[g];
+                rv = rad4[g];
+            }
+            uint64_t bk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float r = comp(rv, k) + tq;
+                bk[k] = __builtin_amdgcn_ballot_w64(g < ng4 && 4 * g + k < nch && comp(v, k) <= r * r);
+            }
+            if (lane < 4) {
+                const uint64_t w = lane == 0 ? bk[0] : lane == 1 ? bk[1] : lane == 2 ? bk[2] : bk[3];
+                a.qmask[qi * a.mwords + 4 * G + lane] = w;
+            }
+        }
+    }
+
     if (threadIdx.x == 0) {
-        // radius of the chunk-ball test: covers the FP32 errors of pd^2 and
-        // of the test's own distance (relative 2^-16 and 1e-5 (tau + S))
-        const float tq = sqrtf(R2);
-        a.qtau[qi] = tq * (1.f + 1.52587890625e-05f) + 1e-5f * (tq + a.coord_scale);
         a.l_count[qi] = 0u;
         a.q_scanned[qi] = (uint32_t)(a.n < 0x7fffffff ? a.n : 0x7fffffff);
         a.q_flag[qi] = 0;
@@ -995,6 +1040,28 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) dst[i] = src[i];
     }
+}
+
+// Chunk-major copy of the chunk mask for the scan: one wave per 64 queries
+// and one word column (chunks 256 g + 4 l + k, l = 0..63, for column 4 g + k);
+// a ballot per chunk turns the 64 queries' bits into that chunk's word.
+__global__ __launch_bounds__(WG) void mask_transpose_kernel(AnnArgs a) {
+    const int lane = lane_id();
+    const int64_t wid = ((int64_t)blockIdx.x * WG + threadIdx.x) >> 6;
+    const int64_t ncol = a.mwords;
+    const int64_t qb = wid / ncol, col = wid % ncol;
+    if (qb * 64 >= a.nq) return;
+    const int64_t q = qb * 64 + lane;
+    const uint64_t w = q < a.nq ? a.qmask[q * a.mwords + col] : 0ull;
+    const int64_t nchunk = a.n_pad16 >> 6;
+    const int64_t cbase = ((col >> 2) << 8) + (col & 3);
+    uint64_t mine = 0;   // the word of chunk cbase + 4 lane
+    for (int l = 0; l < 64; ++l) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64((w >> l) & 1ull);
+        if (lane == l) mine = m;
+    }
+    const int64_t c = cbase + 4 * lane;
+    if (c < nchunk) a.cmask[c * a.cwords + qb] = mine;
 }
 
 // ---- Matrix-core scan (the range filter of the batched path) ----
@@ -1110,47 +1177,6 @@ __device__ __forceinline__ void scan_tiles(ScanShared& ss, int wave, int lane, u
     }
 }
 
-// Chunk-ball test of Eq. 5 for every (chunk, query) pair: the chunk can hold
-// a point within tau of q' only if |q' - centre| <= radius + tau. One wave
-// tests 64 queries (one mask word) against 16 chunks, on the FP32 distances
-// of dist_kernel.
-constexpr int MCH = 16;   // chunks per mask workgroup
-
-__global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
-    __shared__ float srad[MCH];
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const int64_t c0 = (int64_t)blockIdx.x * MCH;
-    const int64_t nchunk = a.n_pad16 >> 6;
-    for (int e = threadIdx.x; e < MCH; e += WG) srad[e] = c0 + e < nchunk ? a.chunk_rad[c0 + e] : -1.f;
-    __syncthreads();
-    const int q0 = blockIdx.y * SQB;
-    for (int w = wave; w < SQB / 64; w += NWAVE) {
-        const int q = q0 + w * 64 + lane;
-        if (q0 + w * 64 >= a.nq) break;
-        const bool valid = q < a.nq;
-        const int64_t qr = valid ? q : q0;
-        const float tq = a.qtau[qr];
-        // the query's squared distances to the 16 chunks (ldc and c0 are
-        // multiples of 16, so the row segment is 64-byte aligned)
-        float dq[MCH];
-        const float4* r4 = reinterpret_cast<const float4*>(a.cdist + qr * a.ldc + c0);
-#pragma unroll
-        for (int k = 0; k < MCH / 4; ++k) {
-            const float4 v = r4[k];
-            dq[4 * k] = v.x; dq[4 * k + 1] = v.y; dq[4 * k + 2] = v.z; dq[4 * k + 3] = v.w;
-        }
-#pragma unroll
-        for (int i = 0; i < MCH; ++i) {
-            if (c0 + i >= nchunk) break;
-            const float acc = dq[i];
-            const float r = srad[i] + tq;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(valid && acc <= r * r);
-            if (lane == 0) a.cmask[(c0 + i) * a.mwords + (q0 >> 6) + w] = m;
-        }
-    }
-}
-
 // Writes the wave's staged candidates to the pool with one reservation per
 // query (queries qw0 .. qw0 + SQW - 1 of the batch) and empties the stage.
 // Only this wave touches its part of the shared memory.
@@ -1208,8 +1234,8 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     }
 
     uint32_t wn = 0;
-    // Point chunks. The FP16 rows are loaded two chunks ahead and the mask
-    // words one chunk ahead, so neither load is waited for on arrival.
+    // Point chunks, strided over the workgroups. The FP16 rows are loaded two
+    // chunks ahead and the mask words (scalar loads) one chunk ahead.
     const int64_t nchunk = a.n_pad16 >> 6;
     const int64_t G = gridDim.x;
     const int nwq = (nqb + 63) >> 6;   // mask words of this query block
@@ -1222,7 +1248,7 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     };
     auto load_mask = [&](int64_t cc, uint64_t (&dst)[SQT / 4]) {
         if (cc < nchunk) {
-            cuint64* crow = (cuint64*)(a.cmask + cc * a.mwords + (q0 >> 6));
+            cuint64* crow = (cuint64*)(a.cmask + cc * a.cwords + (q0 >> 6));
 #pragma unroll
             for (int k = 0; k < SQT / 4; ++k) {
                 const int wi = (t0 >> 2) + k;
@@ -1237,7 +1263,6 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     load_rows(c + G, a2);
     load_mask(c, m1);
     for (; c < nchunk; c += G) {
-        const int64_t p0 = c << 6;
         half8_t av[4];
         uint64_t cm[SQT / 4];
 #pragma unroll
@@ -1252,7 +1277,7 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
         // room for a chunk's typical candidates; a chunk that alone overflows
         // the stage marks its queries instead
         if (wn > (uint32_t)(SSTG - 256)) scan_flush(a, ss, wave, lane, wn, qw0, nqw);
-        scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, p0, t0, cm);
+        scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, c << 6, t0, cm);
     }
     scan_flush(a, ss, wave, lane, wn, qw0, nqw);
 }
@@ -1428,9 +1453,10 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     if (ann_fast_path(L.budget)) {
         a.qaug = L.ws_qaug;
-        a.qtau = L.ws_qtau;
+        a.qmask = L.ws_qmask;
+        a.mwords = (int)(4 * ((x.n_pad16 / 64 + 255) / 256));
         a.cmask = L.ws_cmask;
-        a.mwords = (int)((L.nq + 63) / 64);
+        a.cwords = (int)((L.nq + 63) / 64);
         a.cdist = L.ws_cdist2;
         a.ldc = (x.n_pad16 / 64 + 15) / 16 * 16;
         a.csel = L.ws_csel;
@@ -1442,17 +1468,21 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         const int lds0 = ann_lds_bytes(0);
         const int64_t nchunk = x.n_pad16 / 64;
         {
-            StageTimer tm(PMLSH_STAGE_TAU, stream);
+            StageTimer tm(PMLSH_STAGE_DIST, stream);
             dim3 dgrid((unsigned)((nchunk + WG - 1) / WG), (unsigned)((L.nq + DQB - 1) / DQB));
             hipLaunchKernelGGL(dist_kernel, dgrid, dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
+        }
+        {
+            StageTimer tm(PMLSH_STAGE_TAU, stream);
             hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
         {
-            StageTimer tm(PMLSH_STAGE_MASK, stream);
-            dim3 mgrid((unsigned)((nchunk + MCH - 1) / MCH), (unsigned)((L.nq + SQB - 1) / SQB));
-            hipLaunchKernelGGL(mask_kernel, mgrid, dim3(WG), 0, stream, a);
+            StageTimer tm(PMLSH_STAGE_TAU, stream);
+            const int64_t waves = (L.nq + 63) / 64 * a.mwords;
+            hipLaunchKernelGGL(mask_transpose_kernel, dim3((unsigned)((waves + NWAVE - 1) / NWAVE)),
+                               dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
         // one resident wave of workgroups striding over the chunks
@@ -1466,7 +1496,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         }
         const int64_t ny = (L.nq + SQB - 1) / SQB;
         int64_t gx = std::max<int64_t>(1, slots / ny);
-        gx = std::min(gx, nchunk);
+        gx = std::min(gx, nchunk);   // at least one chunk per workgroup on average
         dim3 sgrid((unsigned)gx, (unsigned)ny);
         {
             StageTimer tm(PMLSH_STAGE_FILTER, stream);

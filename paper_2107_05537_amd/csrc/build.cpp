@@ -174,7 +174,8 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         // themselves when the leaf size is 64): FP64 mean rounded to FP32,
         // radius measured from that FP32 centre and rounded up
         const int64_t nch = x->n_pad16 / 64;
-        std::vector<float> ccen((size_t)nch * MP, 0.f), crad((size_t)nch, 0.f);
+        // radii padded with zeros to a multiple of 16 chunks (vector loads)
+        std::vector<float> ccen((size_t)nch * MP, 0.f), crad((size_t)((nch + 15) / 16 * 16), 0.f);
         for (int64_t c = 0; c < nch; ++c) {
             const int64_t j0 = c * 64, j1 = std::min<int64_t>(n, j0 + 64);
             double mean[MP] = {0.0};

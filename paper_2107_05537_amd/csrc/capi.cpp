@@ -68,11 +68,12 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // chunk and 64 queries
     const int64_t nchunk = x->n_pad16 / 64;
     const int64_t ldc = (nchunk + 15) / 16 * 16;
-    const int64_t per_query_all = per_query + (fast ? 4 + (nchunk + 7) / 8 + 8 * ldc : 0);
+    const int64_t mwords = 4 * ((nchunk + 255) / 256);
+    const int64_t per_query_all = per_query + (fast ? 8 * mwords + 8 * ldc + (nchunk + 7) / 8 : 0);
     int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     batch = std::min<int64_t>(batch, 65535);
     const int64_t mask_bytes =
-        fast ? nchunk * ((batch + 63) / 64) * 8 + batch * 4 + batch * ldc * 8 : 0;
+        fast ? batch * (8 * mwords + 8 * ldc) + nchunk * ((batch + 63) / 64) * 8 : 0;
     void* ws = nullptr;
     PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query + mask_bytes), st));
     char* base = static_cast<char*>(ws);
@@ -82,9 +83,9 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
     float* cdist2 = reinterpret_cast<float*>(qaug + batch * 32);
     int32_t* csel = reinterpret_cast<int32_t*>(cdist2 + (fast ? batch * ldc : 0));
-    uint64_t* cmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * ldc : 0));
-    float* qtau = reinterpret_cast<float*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
-    uint32_t* list = reinterpret_cast<uint32_t*>(qtau + (fast ? batch : 0));
+    uint64_t* qmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * ldc : 0));
+    uint64_t* cmask = qmask + (fast ? batch * mwords : 0);
+    uint32_t* list = reinterpret_cast<uint32_t*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
     int32_t* cpos = front + batch * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);
@@ -116,7 +117,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             L.ws_topk = topk;
             if (fast) {
                 L.ws_qaug = qaug;
-                L.ws_qtau = qtau;
+                L.ws_qmask = qmask;
                 L.ws_cmask = cmask;
                 L.ws_cdist2 = cdist2;
                 L.ws_csel = csel;

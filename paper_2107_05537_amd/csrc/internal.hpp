@@ -168,8 +168,8 @@ struct AnnLaunch {
     uint32_t* q_scanned;
     uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
     uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
-    float* ws_qtau;         // nq: radius of the chunk-ball test
-    uint64_t* ws_cmask;     // chunks x ceil(nq / 64): chunks each query must scan
+    uint64_t* ws_qmask;     // nq x mask words: chunks each query must scan
+    uint64_t* ws_cmask;     // the same, chunk-major: chunks x ceil(nq / 64) words
     float* ws_cdist2;       // nq x ldc: squared distances to the chunk centres
     int32_t* ws_csel;       // nq x ldc: chunks chosen for the bound
     int64_t pool_cap;       // candidate region per query
