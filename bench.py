@@ -8,17 +8,18 @@ synthetic (seeded) and resident in HBM before timing starts.
 Metric: queries/s at recall@10 >= 0.9. The candidate fraction beta is swept
 ({5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3}); the smallest beta whose recall@10
 over all 10,000 queries reaches 0.9 is the operating point, and only that
-point is timed. A step is one pmlsh_ann call on one batch (projection, range
-filter over the PM-tree, budget selection, exact verification, top-k).
+point is timed. A step is one pmlsh_ann call on one batch (projection, chunk
+distances, bound and Eq. 5 chunk test, range filter on the matrix cores,
+budget selection, exact verification, top-k).
 
 Also reported: p50/p99 batch latency; per-stage GPU time (HIP events around
-each kernel of the query path, recorded inside the timed region); the
-roofline of the dominant stage (algorithmic work per launch / its measured
-launch time: flops against the FP32 vector peak for the ALU-bound filter,
-bytes against 8 TB/s for the HBM-bound stages), with the HBM traffic that
-rocprofv3 counters measured for that kernel when profiles/ holds them for
-the current kernel sources; and the FP64 CPU oracle timed on this host on a
-bounded sample of the same queries.
+each stage, from the warm-up); the roofline of the dominant stage
+(algorithmic work per launch / its launch time measured with HIP events in
+the timed region, where only that stage is timed: flops against the FP16
+matrix peak for the filter, bytes against 8 TB/s for the HBM-bound stages),
+with the HBM traffic that rocprofv3 counters measured for that kernel when
+profiles/ holds them for the current kernel sources; and the FP64 CPU oracle
+timed on this host on a bounded sample of the same queries.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -39,7 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+FP16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X published dense FP16 matrix peak
 BETAS = [5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3]
 K = 10
 C = 1.5
@@ -196,11 +197,17 @@ def main():
     batch_scan = [float(st[s:e, 3].sum()) for s, e in batches]
     batch_cand = [float(st[s:e, 1].sum()) for s, e in batches]
 
-    # timed region
+    # warm-up, with every stage timed once to find the dominant one; the
+    # timed region then records events around that stage only
+    pm.ann_timing_read(reset=True)
+    pm.ann_timing_enable(True)
     for i in range(args.warmup):
         s, e = batches[i % len(batches)]
         idx.ann_into(Q[s:e], K, C, CONF, beta, r_min, ids[s:e], dist[s:e], stats[s:e])
     torch.cuda.synchronize()
+    pm.ann_timing_enable(False)
+    warm = pm.ann_timing_read(reset=True)
+    dom = max(("dist", "tau", "filter", "finish", "per_query"), key=lambda k: warm[k]["ms"])
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     queries = 0
@@ -208,7 +215,7 @@ def main():
     cand_rows = 0.0
     torch.cuda.synchronize()
     pm.ann_timing_read(reset=True)
-    pm.ann_timing_enable(True)
+    pm.ann_timing_enable(True, stages=[dom])
     wall0 = time.perf_counter()
     for i in range(args.steps):
         b = i % len(batches)
@@ -228,24 +235,30 @@ def main():
 
     # roofline of the dominant stage, from its live per-launch duration
     d_pad = (d + 3) // 4 * 4
-    dom = max(("dist", "tau", "filter", "finish", "per_query"), key=lambda k: stages[k]["ms"])
     launches = max(1, stages[dom]["launches"])
     per_launch_ms = stages[dom]["ms"] / launches
     if dom == "filter":
-        # 3 flops (difference, multiply, add) per projected coordinate of
-        # every point of every leaf the range query reaches (16 coordinates)
-        work = 48.0 * scan_pts / launches
+        # a 16-term dot product (32 flops) per point of every chunk that
+        # passes the query's chunk-ball test, on the FP16 matrix cores
+        work = 32.0 * scan_pts / launches
         achieved = work / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2),
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4)}
+        roof = {"bound": "mfma", "achieved": round(achieved, 2),
+                "peak": FP16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP16_MFMA_PEAK_TFLOPS, 4)}
+    elif dom in ("dist", "tau"):
+        # the chunk-distance row of every query, written and read
+        ldc = ((n + 63) // 64 + 15) // 16 * 16
+        work = 4.0 * ldc * queries / launches
+        achieved = work / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
     else:
         # verification rows of C, the query, the output
         work = (4.0 * d_pad * cand_rows + (4 * d + 12 * K) * queries) / launches
         achieved = work / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roof["kernel"] = {"tau": "tau_kernel", "filter": "filter_kernel",
+    roof["kernel"] = {"dist": "dist_kernel", "tau": "tau_kernel", "filter": "scan_kernel",
                       "finish": "finish_kernel", "per_query": "ann_kernel"}[dom]
     roof["per_launch_ms"] = round(per_launch_ms, 4)
     roof["work_per_launch"] = work
@@ -294,8 +307,8 @@ def main():
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "per": "batch of up to 1,024 queries"},
         "roofline": roof,
-        "stages_ms_per_batch": {k: round(v["ms"] / max(1, args.steps), 4)
-                                for k, v in stages.items()},
+        "stages_ms_per_batch": {k: round(v["ms"] / max(1, v["launches"]), 4)
+                                for k, v in warm.items()},
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
     }

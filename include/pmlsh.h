@@ -206,11 +206,13 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
                               int64_t* offsets);
 
 /*
- * Tracing aid: per-stage GPU time of pmlsh_ann. While enabled (process-wide),
- * every kernel launch of the query path is bracketed by two HIP events on the
- * caller's stream; pmlsh_ann_timing_read() waits for the recorded events and
- * returns the summed milliseconds and launch counts per stage since the last
- * reset (reset != 0 clears the totals after reading). Stages:
+ * Tracing aid: per-stage GPU time of pmlsh_ann. pmlsh_ann_timing_enable takes
+ * a process-wide mask of stages (bit s = stage s; 0 turns timing off,
+ * (1 << PMLSH_N_STAGES) - 1 times every stage; other values: PMLSH_EINVAL).
+ * Each launch of a timed stage is bracketed by two HIP events on the caller's
+ * stream; pmlsh_ann_timing_read() waits for the recorded events and returns
+ * the summed milliseconds and launch counts per stage since the last reset
+ * (reset != 0 clears the totals after reading). Stages:
  *   PMLSH_STAGE_PROJECT   query projection (FP64 matrix cores)
  *   PMLSH_STAGE_TAU       per-query bound on the B-th projected distance and the
  *                         chunk-ball test of Eq. 5
@@ -234,7 +236,7 @@ typedef struct {
     int64_t launches[PMLSH_N_STAGES];
 } pmlsh_ann_timing;
 
-int pmlsh_ann_timing_enable(int enable);
+int pmlsh_ann_timing_enable(int stage_mask);
 int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
 
 /* Message of the last failed call on this thread ("" if none). The pointer

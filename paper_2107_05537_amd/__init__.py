@@ -144,9 +144,18 @@ def plan_params(n: int, m: int, k: int, c: float, confidence: float, beta: float
     return {f: getattr(out, f) for f, _ in _Plan._fields_}
 
 
-def ann_timing_enable(enable: bool = True):
-    """Switch the per-stage HIP-event timing of pmlsh_ann on or off."""
-    _check(load_library().pmlsh_ann_timing_enable(1 if enable else 0))
+def ann_timing_enable(enable: bool = True, stages=None):
+    """Switch the per-stage HIP-event timing of pmlsh_ann on or off; `stages`
+    (names from STAGES) limits it to those stages."""
+    if not enable:
+        mask = 0
+    elif stages is None:
+        mask = (1 << len(STAGES)) - 1
+    else:
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+    _check(load_library().pmlsh_ann_timing_enable(mask))
 
 
 def ann_timing_read(reset: bool = True) -> dict:

@@ -803,31 +803,44 @@ __device__ __forceinline__ int shift32(uint32_t lo, uint32_t hi) {
     return (32 - __clz((int)span)) - 11;
 }
 
-// Squared FP32 distances (direct differences) from every query of the batch
-// to every chunk centre: one chunk per thread, 64 queries per workgroup read
-// from LDS. Row q of the output holds the query's distances (stride ldc).
+// Squared FP32 distances from every query of the batch to every chunk centre,
+// as |q'|^2 + |c|^2 - 2 q'.c (clamped at 0): one chunk per thread, 64 queries
+// per workgroup read from LDS. Row q of the output holds the query's
+// distances (stride ldc). The expansion's rounding error stays below
+// 64 u (|q'| + S)^2 (S bounds every centre norm); the chunk-ball test adds
+// that much to its threshold, and the choice of chunks for the bound needs
+// no exactness.
 constexpr int DQB = 64;
 
 __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
     __shared__ float sq[DQB][MP];
+    __shared__ float sn[DQB];
     const int q0 = blockIdx.y * DQB;
     const int nqb = min(DQB, a.nq - q0);
     for (int e = threadIdx.x; e < nqb * MP; e += WG) sq[e / MP][e % MP] = a.qp[(int64_t)q0 * MP + e];
     __syncthreads();
+    for (int q = threadIdx.x; q < nqb; q += WG) {
+        float n2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) n2 = fmaf(sq[q][t], sq[q][t], n2);
+        sn[q] = n2;
+    }
+    __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (c >= (a.n_pad16 >> 6)) return;
     float cen[MP];
+    float cn2 = 0.f;
 #pragma unroll
-    for (int t = 0; t < MP; ++t) cen[t] = a.chunk_cen[c * MP + t];
+    for (int t = 0; t < MP; ++t) {
+        cen[t] = a.chunk_cen[c * MP + t];
+        cn2 = fmaf(cen[t], cen[t], cn2);
+    }
     float* out = a.cdist + (int64_t)q0 * a.ldc + c;
     for (int q = 0; q < nqb; ++q) {
-        float acc = 0.f;
+        float dot = 0.f;
 #pragma unroll
-        for (int t = 0; t < MP; ++t) {
-            const float dlt = sq[q][t] - cen[t];
-            acc = fmaf(dlt, dlt, acc);
-        }
-        out[(int64_t)q * a.ldc] = acc;
+        for (int t = 0; t < MP; ++t) dot = fmaf(sq[q][t], cen[t], dot);
+        out[(int64_t)q * a.ldc] = fmaxf(fmaf(-2.f, dot, sn[q] + cn2), 0.f);
     }
 }
 
@@ -973,11 +986,15 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         R2 = __int_as_float(0x7f800000);
     }
 
+    int npass = 0;
     // 4: the chunk-ball test; the radius covers the FP32 errors of pd^2 and
-    // of the test's own distance (relative 2^-16 and 1e-5 (tau + S))
+    // of the test's own distance (relative 2^-16 and 1e-5 (tau + S)), the
+    // additive term the rounding of the expanded squared distance
     {
         const float tq0 = sqrtf(R2);
         const float tq = tq0 * (1.f + 1.52587890625e-05f) + 1e-5f * (tq0 + a.coord_scale);
+        const float big = sqrtf(qc.qn2) + a.coord_scale;
+        const float dmarg = 64.f * 5.9604645e-08f * big * big;
         const int ng256 = (nch + 255) >> 8;
         const float4* rad4 = reinterpret_cast<const float4*>(a.chunk_rad);
         for (int G = wave; G < ng256; G += NWAVE) {
@@ -991,18 +1008,22 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const float r = comp(rv, k) + tq;
-                bk[k] = __builtin_amdgcn_ballot_w64(g < ng4 && 4 * g + k < nch && comp(v, k) <= r * r);
+                bk[k] = __builtin_amdgcn_ballot_w64(g < ng4 && 4 * g + k < nch &&
+                                                    comp(v, k) <= fmaf(r, r, dmarg));
             }
             if (lane < 4) {
                 const uint64_t w = lane == 0 ? bk[0] : lane == 1 ? bk[1] : lane == 2 ? bk[2] : bk[3];
                 a.qmask[qi * a.mwords + 4 * G + lane] = w;
             }
+            npass += __popcll(bk[0]) + __popcll(bk[1]) + __popcll(bk[2]) + __popcll(bk[3]);
         }
     }
+    // points the scan examines for this query: 64 per passing chunk
+    npass = block_sum(lane == 0 ? npass : 0, sh);
 
     if (threadIdx.x == 0) {
         a.l_count[qi] = 0u;
-        a.q_scanned[qi] = (uint32_t)(a.n < 0x7fffffff ? a.n : 0x7fffffff);
+        a.q_scanned[qi] = (uint32_t)min<int64_t>(64ll * npass, 0x7fffffff);
         a.q_flag[qi] = 0;
         // The query's FP16 row of the matrix-core scan. thr = tau^2 - |q'|^2
         // plus 96 u (|q'| + S)^2 (S bounds every |o'|) covers the FP32 errors
@@ -1477,9 +1498,6 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
             StageTimer tm(PMLSH_STAGE_TAU, stream);
             hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
             PMLSH_HIP(hipGetLastError());
-        }
-        {
-            StageTimer tm(PMLSH_STAGE_TAU, stream);
             const int64_t waves = (L.nq + 63) / 64 * a.mwords;
             hipLaunchKernelGGL(mask_transpose_kernel, dim3((unsigned)((waves + NWAVE - 1) / NWAVE)),
                                dim3(WG), 0, stream, a);

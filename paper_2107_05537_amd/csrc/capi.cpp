@@ -234,8 +234,12 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm, int64_t* 
     });
 }
 
-int pmlsh_ann_timing_enable(int enable) {
-    return guarded([&] { timing_set(enable != 0); });
+int pmlsh_ann_timing_enable(int stage_mask) {
+    return guarded([&] {
+        if (stage_mask < 0 || stage_mask >= (1 << PMLSH_N_STAGES))
+            fail(PMLSH_EINVAL, "stage_mask must be a mask of the PMLSH_N_STAGES stages");
+        timing_set((unsigned)stage_mask);
+    });
 }
 
 int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset) {

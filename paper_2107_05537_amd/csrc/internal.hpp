@@ -115,8 +115,8 @@ struct pmlsh_index {
 namespace pmlsh {
 
 // ---------------------------------------------------------------- timing
-bool timing_enabled();
-void timing_set(bool on);
+bool timing_enabled(int stage);
+void timing_set(unsigned stage_mask);
 void timing_read(pmlsh_ann_timing* out, bool reset);
 
 // Brackets the launches issued during its lifetime with HIP events when

@@ -1,8 +1,8 @@
-// Opt-in per-stage timing of pmlsh_ann: when enabled, each kernel launch of
-// the query path is bracketed by two HIP events on the caller's stream. The
+// Opt-in per-stage timing of pmlsh_ann: for each enabled stage, the stage's
+// kernel launches are bracketed by two HIP events on the caller's stream. The
 // events are resolved (synchronised and summed) only when the totals are
-// read, so enabling the timer adds two event records per launch and no host
-// synchronisation to the query path.
+// read, and then reused, so a timed stage adds two event records per launch
+// and no host synchronisation to the query path.
 
 #include <mutex>
 #include <vector>
@@ -18,27 +18,44 @@ struct Pending {
 };
 
 std::mutex g_mu;
-bool g_on = false;
+unsigned g_mask = 0;                 // stages being timed (bit s = stage s)
 std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_free;      // resolved events, reused
 double g_ms[PMLSH_N_STAGES] = {0};
 int64_t g_count[PMLSH_N_STAGES] = {0};
 
 }  // namespace
 
-bool timing_enabled() {
+bool timing_enabled(int stage) {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_on;
+    return (g_mask >> stage) & 1u;
 }
 
-void timing_set(bool on) {
+void timing_set(unsigned mask) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_on = on;
+    g_mask = mask;
 }
+
+namespace {
+hipEvent_t take_event() {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_free.empty()) {
+            hipEvent_t e = g_free.back();
+            g_free.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    PMLSH_HIP(hipEventCreate(&e));
+    return e;
+}
+}  // namespace
 
 StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
-    if (!timing_enabled()) return;
-    PMLSH_HIP(hipEventCreate(&a_));
-    PMLSH_HIP(hipEventCreate(&b_));
+    if (!timing_enabled(stage)) return;
+    a_ = take_event();
+    b_ = take_event();
     PMLSH_HIP(hipEventRecord(a_, st_));
     on_ = true;
 }
@@ -67,8 +84,9 @@ void timing_read(pmlsh_ann_timing* out, bool reset) {
             g_ms[e.stage] += ms;
             g_count[e.stage] += 1;
         }
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_free.push_back(e.a);
+        g_free.push_back(e.b);
     }
     std::lock_guard<std::mutex> lk(g_mu);
     for (int i = 0; i < PMLSH_N_STAGES; ++i) {

@@ -133,3 +133,17 @@ def test_binding_refuses_cpu_tensors(lib):
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         pm.Index(torch.zeros(10, 4), np.ones((3, 4), dtype=np.float32))
+
+
+def test_timing_stage_mask(lib):
+    """The timing switch takes a mask of stages; bits past the last stage are
+    rejected, and reading with nothing timed returns zeros."""
+    assert lib.pmlsh_ann_timing_enable(1 << len(pm.STAGES)) == pm.EINVAL
+    assert lib.pmlsh_ann_timing_enable(-1) == pm.EINVAL
+    assert lib.pmlsh_ann_timing_enable((1 << len(pm.STAGES)) - 1) == pm.OK
+    assert lib.pmlsh_ann_timing_enable(0) == pm.OK
+    t = pm.ann_timing_read(reset=True)
+    assert set(t) == set(pm.STAGES)
+    assert all(v["ms"] == 0 and v["launches"] == 0 for v in t.values())
+    pm.ann_timing_enable(True, stages=["finish"])
+    pm.ann_timing_enable(False)
