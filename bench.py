@@ -253,8 +253,12 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
     else:
-        # verification rows of C, the query, the output
-        work = (4.0 * d_pad * cand_rows + (4 * d + 12 * K) * queries) / launches
+        # bounded verification: the FP16 row and the 64 B projection row of
+        # every member of C, the FP32 rows of the k answers, the query and
+        # the output
+        d16 = (d + 7) // 8 * 8
+        work = ((2.0 * d16 + 64.0) * cand_rows
+                + (4.0 * d_pad * K + 4 * d + 12 * K) * queries) / launches
         achieved = work / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}

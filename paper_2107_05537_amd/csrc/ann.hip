@@ -98,6 +98,14 @@ struct AnnArgs {
     float* cdist;
     int64_t ldc;
     int32_t* csel;              // per query: the chunks chosen for its bound (ldc)
+    // bounded verification: FP16 rows (stride d16), their scales and error
+    // bounds, and per C member a lower bound of its squared distance (the
+    // upper bound goes to ws_cdist; equal bounds mean the exact value)
+    const uint16_t* data16;
+    const float* d16_scale;
+    const float* d16_eps;
+    int d16;
+    float* ws_clo;
 };
 
 struct Smem {
@@ -556,6 +564,124 @@ __device__ void verify(const AnnArgs& a, const float* qs, const int32_t* cpos, f
     }
 }
 
+// Exact squared distances (same operation sequence as verify) of the C
+// members listed in idx[0, cnt); both bounds of each become the exact value.
+__device__ void verify_list(const AnnArgs& a, const float* qs, const int32_t* cpos,
+                            const int32_t* idx, int cnt, float* lo2, float* hi2) {
+    const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int d4 = a.d_pad >> 2;
+    const float4* q4 = reinterpret_cast<const float4*>(qs);
+    constexpr int GROUPS = WG / 16;
+    for (int base = 0; base < cnt; base += GROUPS * VR) {
+        const float4* row[VR];
+        bool ok[VR];
+        float acc[VR];
+        int mi[VR];
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            const int j = base + g + GROUPS * r;
+            ok[r] = j < cnt;
+            mi[r] = idx[ok[r] ? j : 0];
+            row[r] = reinterpret_cast<const float4*>(a.data + (int64_t)cpos[mi[r]] * a.d_pad);
+            acc[r] = 0.f;
+        }
+#pragma unroll 2
+        for (int c = l16; c < d4; c += 16) {
+            float4 x[VR];
+#pragma unroll
+            for (int r = 0; r < VR; ++r) x[r] = row[r][c];
+            const float4 y = q4[c];
+#pragma unroll
+            for (int r = 0; r < VR; ++r) {
+                float t;
+                t = y.x - x[r].x; acc[r] = __fmaf_rn(t, t, acc[r]);
+                t = y.y - x[r].y; acc[r] = __fmaf_rn(t, t, acc[r]);
+                t = y.z - x[r].z; acc[r] = __fmaf_rn(t, t, acc[r]);
+                t = y.w - x[r].w; acc[r] = __fmaf_rn(t, t, acc[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            float v = acc[r];
+            v += __shfl_xor(v, 8, 16);
+            v += __shfl_xor(v, 4, 16);
+            v += __shfl_xor(v, 2, 16);
+            v += __shfl_xor(v, 1, 16);
+            if (ok[r] && l16 == 0) {
+                lo2[mi[r]] = v;
+                hi2[mi[r]] = v;
+            }
+        }
+    }
+}
+
+// Bounds on the exact FP32 squared distance (the value verify would compute)
+// of C members [v0, v1), from the FP16 rows: with D16 the distance to the
+// FP16 row (accumulated in FP32 like verify, relative error <= gamma) and eps
+// the row's bound |x - s x16|, the true distance lies in [D16 - eps, D16 +
+// eps] and the FP32 value within a further factor (1 +- gamma); every
+// rounding of the bound arithmetic is covered by extra factors of a few u.
+__device__ void verify16(const AnnArgs& a, const float* qs, const int32_t* cpos,
+                         float* lo2, float* hi2, int v0, int v1) {
+    const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int d8 = a.d16 >> 3;
+    constexpr int GROUPS = WG / 16;
+    const float u = 5.9604645e-08f;
+    const float gam = 2.f * u * (float)(a.d16 / 16 + 8);
+    for (int base = v0; base < v1; base += GROUPS * VR) {
+        const uint4* row[VR];
+        bool ok[VR];
+        float acc[VR], sc[VR];
+        int pr[VR];
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            const int i = base + g + GROUPS * r;
+            ok[r] = i < v1;
+            pr[r] = cpos[ok[r] ? i : v0];
+            row[r] = reinterpret_cast<const uint4*>(a.data16 + (int64_t)pr[r] * a.d16);
+            sc[r] = a.d16_scale[pr[r]];
+            acc[r] = 0.f;
+        }
+#pragma unroll 2
+        for (int c = l16; c < d8; c += 16) {
+            uint4 h[VR];
+#pragma unroll
+            for (int r = 0; r < VR; ++r) h[r] = row[r][c];
+            float y[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) y[e] = qs[8 * c + e];
+#pragma unroll
+            for (int r = 0; r < VR; ++r) {
+                const uint32_t w[4] = {h[r].x, h[r].y, h[r].z, h[r].w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint16_t bits = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+                    const float xv = (float)__builtin_bit_cast(_Float16, bits);
+                    const float t = __fmaf_rn(-sc[r], xv, y[e]);
+                    acc[r] = __fmaf_rn(t, t, acc[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            float v = acc[r];
+            v += __shfl_xor(v, 8, 16);
+            v += __shfl_xor(v, 4, 16);
+            v += __shfl_xor(v, 2, 16);
+            v += __shfl_xor(v, 1, 16);
+            if (ok[r] && l16 == 0) {
+                const float eps = a.d16_eps[pr[r]];
+                const float dlo = sqrtf(v * (1.f - gam)) * (1.f - 4.f * u);
+                const float dhi = sqrtf(v * (1.f + 2.f * gam)) * (1.f + 4.f * u);
+                const float tlo = fmaxf((dlo - eps) * (1.f - 2.f * u), 0.f);
+                const float thi = (dhi + eps) * (1.f + 2.f * u);
+                lo2[base + g + GROUPS * r] = tlo * tlo * (1.f - gam) * (1.f - 4.f * u);
+                hi2[base + g + GROUPS * r] = thi * thi * (1.f + gam) * (1.f + 4.f * u);
+            }
+        }
+    }
+}
+
 // Loads the query into LDS (zero padded), its projection and pivot
 // distances into registers.
 struct QueryCtx {
@@ -567,7 +693,7 @@ struct QueryCtx {
 __device__ __forceinline__ void load_query(const AnnArgs& a, int64_t qi, float* qs, QueryCtx& c) {
     const float* qrow = a.q + qi * a.d;
     if (qs)
-        for (int j = threadIdx.x; j < a.d_pad; j += WG) qs[j] = j < a.d ? qrow[j] : 0.f;
+        for (int j = threadIdx.x; j < a.d16; j += WG) qs[j] = j < a.d ? qrow[j] : 0.f;
 #pragma unroll
     for (int j = 0; j < MP; ++j) c.qp[j] = a.qp[qi * MP + j];
     c.qn2 = 0.f;
@@ -1372,16 +1498,46 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         nl = B;
     }
 
+    // Verification keeps, per member of C, bounds lo2 <= exact <= hi2 on the
+    // FP32 squared distance that verify would compute (FP16 rows, verify16);
+    // a decision that the bounds cannot settle reads the FP32 rows of the
+    // members concerned (verify_list), so every decision equals the one
+    // taken on exact values. The index lists live in the histogram space.
+    float* lo2 = a.ws_clo + qi * (int64_t)B;
+    float* hi2 = cdist;
+    int32_t* ilist = reinterpret_cast<int32_t*>(sh.hist);
     double r = a.r_min;
     int n_ver = 0, rounds = 0, exit_kind = 0;
     uint32_t prev_bits = 0;
     for (;;) {
         if (rounds > 0) {
+            // line 4: at least k verified members within c r
             const double cr = a.c * r;
             const float thr2 = (float)(cr * cr);
-            int loc = 0;
-            for (int i = threadIdx.x; i < n_ver; i += WG) loc += cdist[i] <= thr2;
-            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
+            int sure = 0, maybe = 0;
+            for (int i = threadIdx.x; i < n_ver; i += WG) {
+                sure += hi2[i] <= thr2;
+                maybe += lo2[i] <= thr2 && hi2[i] > thr2;
+            }
+            sure = block_sum(sure, sh);
+            maybe = block_sum(maybe, sh);
+            if (sure < a.k && sure + maybe >= a.k) {
+                if (threadIdx.x == 0) sh.cnt1 = 0;
+                __syncthreads();
+                for (int b0 = 0; b0 < n_ver; b0 += WG) {
+                    const int i = b0 + threadIdx.x;
+                    const bool take = i < n_ver && lo2[i] <= thr2 && hi2[i] > thr2;
+                    const int slot = wave_append(take, &sh.cnt1);
+                    if (take) ilist[slot] = i;
+                }
+                __syncthreads();
+                verify_list(a, qs, cpos, ilist, sh.cnt1, lo2, hi2);
+                __syncthreads();
+                int loc = 0;
+                for (int i = threadIdx.x; i < n_ver; i += WG) loc += hi2[i] <= thr2;
+                sure = block_sum(loc, sh);
+            }
+            if (sure >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
         }
         if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
         const double Rd = a.t * r;
@@ -1404,14 +1560,75 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         __syncthreads();
         const int nb = sh.cnt1 < B ? sh.cnt1 : B;
         ++rounds;
-        verify(a, qs, cpos, cdist, n_ver, nb);
+        verify16(a, qs, cpos, lo2, hi2, n_ver, nb);
         n_ver = nb;
         prev_bits = r2bits;
         __syncthreads();
         if (nb == B) { exit_kind = PMLSH_EXIT_BUDGET; break; }
         r = a.c * r;
     }
-    write_topk(a, qi, cpos, cdist, n_ver, rounds, exit_kind, (int64_t)a.q_scanned[qi], sh);
+
+    // Top-k: the k smallest upper bounds give hk; only members with lo2 <= hk
+    // can be among the k nearest, and those are verified exactly.
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_ver; i += WG)
+        sh.skey[i] = ((uint64_t)__float_as_uint(hi2[i]) << 32) | (uint32_t)i;
+    __syncthreads();
+    const float hk = n_ver > a.k ? __uint_as_float((uint32_t)(lds_select(n_ver, a.k, sh) >> 32))
+                                 : __int_as_float(0x7f800000);
+    if (threadIdx.x == 0) sh.cnt1 = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < n_ver; b0 += WG) {
+        const int i = b0 + threadIdx.x;
+        const bool take = i < n_ver && lo2[i] <= hk && lo2[i] != hi2[i];
+        const int slot = wave_append(take, &sh.cnt1);
+        if (take) ilist[slot] = i;
+    }
+    __syncthreads();
+    verify_list(a, qs, cpos, ilist, sh.cnt1, lo2, hi2);
+    __syncthreads();
+    // the possible members, now exact, keyed by (distance^2 bits, id)
+    if (threadIdx.x == 0) sh.cnt1 = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < n_ver; b0 += WG) {
+        const int i = b0 + threadIdx.x;
+        const bool take = i < n_ver && lo2[i] <= hk;
+        const int slot = wave_append(take, &sh.cnt1);
+        if (take) {
+            sh.skey[slot] = ((uint64_t)__float_as_uint(hi2[i]) << 32) | (uint32_t)perm[cpos[i]];
+            sh.spos[slot] = i;
+        }
+    }
+    __syncthreads();
+    const int m = sh.cnt1;
+    if (m > a.k) {
+        const uint64_t kth = lds_select(m, a.k, sh);
+        uint64_t* tmp = reinterpret_cast<uint64_t*>(sh.hist);
+        if (threadIdx.x == 0) sh.cnt1 = 0;
+        __syncthreads();
+        for (int b0 = 0; b0 < m; b0 += WG) {
+            const int i = b0 + threadIdx.x;
+            const bool take = i < m && sh.skey[i] <= kth;
+            const int slot = wave_append(take, &sh.cnt1);
+            if (take) tmp[slot] = sh.skey[i];
+        }
+        __syncthreads();
+        for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) sh.skey[j2] = tmp[j2];
+        __syncthreads();
+    }
+    bitonic_sort(m < a.k ? m : a.k, sh);
+    for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) {
+        const uint64_t key = sh.skey[j2];
+        a.out_ids[qi * a.k + j2] = (int64_t)(uint32_t)key;
+        a.out_dist[qi * a.k + j2] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+    }
+    if (a.out_stats && threadIdx.x == 0) {
+        int32_t* st = a.out_stats + qi * 4;
+        st[0] = rounds;
+        st[1] = n_ver;
+        st[2] = exit_kind;
+        st[3] = (int32_t)a.q_scanned[qi];
+    }
 }
 
 }  // namespace
@@ -1469,7 +1686,11 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.scale16 = x.scale16;
     a.chunk_cen = x.chunk_cen;
     a.chunk_rad = x.chunk_rad;
-    const int lds = ann_lds_bytes(x.d_pad);
+    a.data16 = x.data16;
+    a.d16_scale = x.data16_scale;
+    a.d16_eps = x.data16_eps;
+    a.d16 = x.d16;
+    const int lds = ann_lds_bytes(x.d16);
     PMLSH_HIP(hipFuncSetAttribute((const void*)ann_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     if (ann_fast_path(L.budget)) {
@@ -1481,6 +1702,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.cdist = L.ws_cdist2;
         a.ldc = (x.n_pad16 / 64 + 15) / 16 * 16;
         a.csel = L.ws_csel;
+        a.ws_clo = L.ws_clo;
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;

@@ -159,6 +159,12 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     launch_gather_rows(D, d, d, x->perm, n, x->data, x->d_pad, st);
     launch_gather_proj(static_cast<const float*>(phi.p), x->perm, n, x->proj_hi, st);
     launch_gather_proj(static_cast<const float*>(plo.p), x->perm, n, x->proj_lo, st);
+    // FP16 copy for the bounded verification
+    x->d16 = (x->d + 7) / 8 * 8;
+    x->data16 = dev_alloc<uint16_t>(x, n * x->d16);
+    x->data16_scale = dev_alloc<float>(x, n);
+    x->data16_eps = dev_alloc<float>(x, n);
+    launch_half_rows(x->data, n, x->d_pad, x->d16, x->data16, x->data16_scale, x->data16_eps, st);
 
     // ---- FP16 rows of the matrix-core scan, scaled by a power of two s with
     // s * max ||o'|| < 32, so every entry stays far inside the FP16 range

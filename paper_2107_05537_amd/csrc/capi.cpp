@@ -61,9 +61,10 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     const bool fast = ann_fast_path(B);
     const int64_t pool_q = fast ? ann_pool_per_query(x->n) : 0;
     // per query: projection, FP16 scan row, two frontier lists, C, top-k
-    // scratch, and for the batched path three counters and a candidate region
+    // scratch, and for the batched path three counters, a candidate region and
+    // the lower distance bounds of C
     const int64_t per_query = (int64_t)MP * 4 + 64 + 2 * x->n_leaves * 4 + B * 8 +
-                              3 * (int64_t)k * 4 + (fast ? 3 * 4 + pool_q * 4 : 0);
+                              3 * (int64_t)k * 4 + (fast ? 3 * 4 + pool_q * 4 + B * 4 : 0);
     // plus, for the batched path, the chunk x query mask: a 64-bit word per
     // chunk and 64 queries
     const int64_t nchunk = x->n_pad16 / 64;
@@ -90,7 +91,8 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     int32_t* cpos = front + batch * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);
     int32_t* topk = reinterpret_cast<int32_t*>(cdist + batch * B);
-    int32_t* q_flag = topk + batch * 3 * (int64_t)k;
+    float* clo = reinterpret_cast<float*>(topk + batch * 3 * (int64_t)k);
+    int32_t* q_flag = reinterpret_cast<int32_t*>(clo + (fast ? batch * B : 0));
     uint32_t* l_count = reinterpret_cast<uint32_t*>(q_flag + batch);
     uint32_t* q_scanned = l_count + batch;
     try {
@@ -118,6 +120,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             if (fast) {
                 L.ws_qaug = qaug;
                 L.ws_qmask = qmask;
+                L.ws_clo = clo;
                 L.ws_cmask = cmask;
                 L.ws_cdist2 = cdist2;
                 L.ws_csel = csel;

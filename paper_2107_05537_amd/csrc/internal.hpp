@@ -99,6 +99,10 @@ struct pmlsh_index {
     float scale16 = 1.f;         // power-of-two scale s of those rows
     float* chunk_cen = nullptr;  // n_pad16 / 64 x MP: centre of each 64-point chunk
     float* chunk_rad = nullptr;  // n_pad16 / 64: radius covering the chunk's points
+    uint16_t* data16 = nullptr;  // n x d16 FP16 copy of D_leaf, rows scaled by a power of two
+    float* data16_scale = nullptr;  // n: that power of two
+    float* data16_eps = nullptr;    // n: bound on |row - scale * FP16 row|
+    int d16 = 0;                    // d rounded up to a multiple of 8
     int32_t* perm = nullptr;     // leaf position -> id
     int32_t* inv_perm = nullptr; // id -> leaf position
     float* hash = nullptr;       // MP x d, zero rows beyond m
@@ -147,6 +151,8 @@ void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
                         float* dst, hipStream_t stream);
 void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm,
                       uint16_t* out, hipStream_t stream);
+void launch_half_rows(const float* data, int64_t n, int d_pad, int d16, uint16_t* out,
+                      float* scale, float* eps, hipStream_t stream);
 void launch_pair_dist_f64(const float* x, int d, int64_t ld, const int64_t* pairs,
                           int64_t count, double* out, hipStream_t stream);
 
@@ -161,6 +167,7 @@ struct AnnLaunch {
     int32_t* ws_front;      // nq x 2 x n_leaves
     int32_t* ws_cpos;       // nq x budget
     float* ws_cdist;        // nq x budget
+    float* ws_clo;          // nq x budget: lower bounds of the verified distances
     int32_t* ws_topk;       // nq x 3 x k
     // leaf-major fast path, per query
     int32_t* q_flag;

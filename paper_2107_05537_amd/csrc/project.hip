@@ -132,6 +132,41 @@ __global__ __launch_bounds__(256) void augment16_kernel(
     for (int i = 0; i < 4; ++i) out[p * 4 + i] = src[i];
 }
 
+// FP16 copy of the leaf-order data for the bounded verification: one wave
+// per row. The row is scaled by a power of two s (its largest magnitude maps
+// below 2^15), rounded to FP16, and the exact norm of the rounding error
+// |x - s x16| is accumulated in FP64 and rounded up: the distance from any
+// query to the FP16 row then lies within eps of the distance to x.
+__global__ __launch_bounds__(256) void half_rows_kernel(
+    const float* __restrict__ data, int64_t n, int d_pad, int d16,
+    uint16_t* __restrict__ out, float* __restrict__ scale, float* __restrict__ eps) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const float* x = data + row * d_pad;
+    float mx = 0.f;
+    for (int c = lane; c < d_pad; c += 64) mx = fmaxf(mx, fabsf(x[c]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    int e = 0;
+    if (mx > 0.f) (void)frexpf(mx, &e);
+    const float s = ldexpf(1.f, e - 15);          // mx / s < 2^15
+    double err = 0.0;
+    _Float16* o = reinterpret_cast<_Float16*>(out + row * d16);
+    for (int c = lane; c < d16; c += 64) {
+        const float v = c < d_pad ? x[c] : 0.f;
+        const _Float16 h = (_Float16)(v / s);
+        o[c] = h;
+        const double dlt = (double)v - (double)s * (double)(float)h;
+        err += dlt * dlt;
+    }
+    for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
+    if (lane == 0) {
+        scale[row] = s;
+        const float ef = (float)sqrt(err);
+        eps[row] = nextafterf(ef * (1.f + 9.5367431640625e-07f), INFINITY);
+    }
+}
+
 // FP64 Euclidean distance of row pairs (one wave per pair).
 __global__ __launch_bounds__(256) void pair_dist_f64_kernel(
     const float* __restrict__ x, int d, int64_t ld,
@@ -189,6 +224,14 @@ void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, floa
     if (n_pad <= 0) return;
     hipLaunchKernelGGL(augment16_kernel, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0,
                        stream, proj, n, n_pad, s, cm, reinterpret_cast<uint4*>(out));
+    PMLSH_HIP(hipGetLastError());
+}
+
+void launch_half_rows(const float* data, int64_t n, int d_pad, int d16, uint16_t* out,
+                      float* scale, float* eps, hipStream_t stream) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(half_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
+                       data, n, d_pad, d16, out, scale, eps);
     PMLSH_HIP(hipGetLastError());
 }
 
