@@ -7,10 +7,12 @@
 // hi + lo carries the projection to ~2^-48 relative. The hash matrix is padded
 // to 16 rows with zeros (m <= 16), which fills the 16-wide MFMA tile.
 //
-// One workgroup (4 waves) projects 64 rows; each wave owns a 16 x 16 output
-// tile (16 rows x 16 hash functions). Rows and hash columns are staged through
-// LDS in 64-column chunks with coalesced loads; the row stride of 65 floats
-// keeps the column-wise MFMA operand reads free of bank conflicts.
+// One workgroup (4 waves) projects 16 rows: the 16 x 16 output tile (16 rows x
+// 16 hash functions) is split along the columns, each wave accumulating a
+// quarter of every 256-column chunk, and the four partial tiles are summed in
+// FP64 at the end. Rows and hash columns are staged through LDS with coalesced
+// loads; the row stride of 257 floats keeps the column-wise operand reads free
+// of bank conflicts. Small batches (1,024 queries) thus use 64 workgroups.
 
 #include <hip/hip_runtime.h>
 
@@ -21,8 +23,8 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int PJ_ROWS = 64;
-constexpr int PJ_KC = 64;
+constexpr int PJ_ROWS = 16;    // rows per workgroup: one 16 x 16 output tile
+constexpr int PJ_KC = 256;     // columns staged per step (64 per wave)
 
 __global__ __launch_bounds__(256) void project_kernel(
     const float* __restrict__ x, int64_t rows, int d, int64_t ld,
@@ -30,6 +32,7 @@ __global__ __launch_bounds__(256) void project_kernel(
     float* __restrict__ out_lo) {
     __shared__ float xs[PJ_ROWS][PJ_KC + 1];
     __shared__ float hs[MP][PJ_KC + 1];
+    __shared__ double part[3][64][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * PJ_ROWS;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -46,24 +49,29 @@ __global__ __launch_bounds__(256) void project_kernel(
             hs[r][c] = gc < d ? hash[(int64_t)r * d + gc] : 0.f;
         }
         __syncthreads();
-        // A operand: row (lane % 16) of this wave's tile, k = lane / 16;
-        // B operand: hash function (lane % 16), k = lane / 16.
+        // each wave takes 64 of the staged columns. A operand: row
+        // (lane % 16), k = lane / 16; B operand: hash function (lane % 16).
 #pragma unroll 4
-        for (int kk = 0; kk < PJ_KC; kk += 4) {
-            const double a = (double)xs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
+        for (int kk = wave * 64; kk < wave * 64 + 64; kk += 4) {
+            const double a = (double)xs[lane & 15][kk + (lane >> 4)];
             const double b = (double)hs[lane & 15][kk + (lane >> 4)];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
         __syncthreads();
     }
+    // the four waves' partial tiles are summed by wave 0
+    if (wave > 0)
+        for (int i = 0; i < 4; ++i) part[wave - 1][lane][i] = acc[i];
+    __syncthreads();
+    if (wave != 0) return;
     // result element i of a lane: row lane/16 + 4*i, hash function lane % 16
     // (the v_mfma_f64_16x16x4f64 accumulator layout on gfx950)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int64_t gr = row0 + wave * 16 + (lane >> 4) + 4 * i;
+        const double v = acc[i] + part[0][lane][i] + part[1][lane][i] + part[2][lane][i];
+        const int64_t gr = row0 + (lane >> 4) + 4 * i;
         const int col = lane & 15;
         if (gr < rows) {
-            const double v = acc[i];
             const float hi = (float)v;
             out_hi[gr * MP + col] = hi;
             if (out_lo) out_lo[gr * MP + col] = (float)(v - (double)hi);
