@@ -1456,11 +1456,31 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     int nl;
     __syncthreads();
     if (n <= CAP) {
-        for (int i = threadIdx.x; i < n; i += WG) {
-            const int32_t pos = (int32_t)list[i];
-            const float pd2 = proj_dist2(a.proj + (int64_t)pos * MP, qc.qp);
-            sh.skey[i] = ((uint64_t)__float_as_uint(pd2) << 32) | (uint32_t)perm[pos];
-            sh.spos[i] = pos;
+        // four entries per thread in flight: their list, projection and id
+        // loads are issued together
+        constexpr int PU = 4;
+        for (int i0 = threadIdx.x; i0 < n; i0 += PU * WG) {
+            int32_t pos[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int i = i0 + u * WG;
+                pos[u] = (int32_t)list[i < n ? i : i0];
+            }
+            float pd2[PU];
+            int32_t id[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                pd2[u] = proj_dist2(a.proj + (int64_t)pos[u] * MP, qc.qp);
+                id[u] = perm[pos[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int i = i0 + u * WG;
+                if (i < n) {
+                    sh.skey[i] = ((uint64_t)__float_as_uint(pd2[u]) << 32) | (uint32_t)id[u];
+                    sh.spos[i] = pos[u];
+                }
+            }
         }
         __syncthreads();
         if (n > B) {
