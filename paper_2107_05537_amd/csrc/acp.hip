@@ -5,9 +5,11 @@
 //   ub       the k-th smallest seed distance (device-wide radix select);
 //   tiles    leaf pairs (e1 < e2) whose Mindist of Eq. 11 can fall below
 //            t*ub (acp_tile_filter_kernel), a lossless skip of whole leaf pairs;
-//   scan     all point pairs of the surviving tiles, projected distance from
-//            the hi/lo coordinate pairs, kept when strictly below t*ub
-//            (acp_tile_scan_kernel);
+//   scan     all point pairs of the surviving tiles: pairs whose parent-
+//            distance bound (PD, Sec. 4.1) already reaches t*ub are dropped,
+//            the others get the projected distance from the hi/lo coordinate
+//            pairs and are kept when strictly below t*ub (acp_pd_kernel,
+//            acp_tile_scan_kernel);
 //   budget   at most T verified pairs: the projected-nearest candidates are
 //            kept (device-wide radix select on (pd^2, i, j));
 //   verify   exact FP32 squared distance of the kept candidates;
@@ -143,18 +145,52 @@ __global__ __launch_bounds__(WG) void acp_tile_filter_kernel(
     if (keep && slot < cap) tiles[slot] = make_int2((int)e1, (int)e2);
 }
 
+// Distance from every point (hi + lo) to the centre of its own leaf, FP32:
+// the parent distance PD that the PM-tree keeps for leaf entries.
+__global__ __launch_bounds__(WG) void acp_pd_kernel(
+    const float* __restrict__ phi, const float* __restrict__ plo, NodeView v, int64_t leaf_base,
+    int64_t n, int L, float* __restrict__ pd) {
+    const int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (j >= n) return;
+    const int64_t node = leaf_base + j / L;
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < MP; ++t) {
+        const float dt = __fadd_rn(__fsub_rn(phi[j * MP + t], v.cen[(int64_t)t * v.n_nodes + node]),
+                                   plo[j * MP + t]);
+        acc = __fmaf_rn(dt, dt, acc);
+    }
+    pd[j] = sqrtf(acc);
+}
+
+// All point pairs (a in leaf e1, b in leaf e2) of the surviving tiles.
+//   1. PD filter: |dist(a, centre of e2) - PD(b)| is a lower bound of the
+//      projected distance (triangle inequality); pairs whose bound (less its
+//      FP32 error) reaches R cannot pass and are dropped. One wave takes one a
+//      at a time, lanes take b; the passing pairs are compacted in LDS.
+//   2. the remaining pairs get the projected distance from the hi/lo
+//      coordinate pairs and are kept when pd^2 < R2.
+// The kept set is exactly the set a scan of every pair would keep.
 __global__ __launch_bounds__(WG) void acp_tile_scan_kernel(
-    const float* __restrict__ phi, const float* __restrict__ plo,
-    const int32_t* __restrict__ perm, int64_t n, int L, const int2* __restrict__ tiles,
-    int64_t n_tiles, float R2, uint32_t* __restrict__ ck0, uint32_t* __restrict__ cii,
-    uint32_t* __restrict__ cjj, int64_t cap, unsigned long long* __restrict__ counter) {
+    const float* __restrict__ phi, const float* __restrict__ plo, const float* __restrict__ ppd,
+    NodeView v, int64_t leaf_base, const int32_t* __restrict__ perm, int64_t n, int L,
+    const int2* __restrict__ tiles, int64_t n_tiles, float R2, float Rlim,
+    uint32_t* __restrict__ ck0, uint32_t* __restrict__ cii, uint32_t* __restrict__ cjj,
+    int64_t cap, unsigned long long* __restrict__ counter) {
     extern __shared__ __align__(16) float lds[];
     float* h1 = lds;
     float* l1 = h1 + L * MP;
     float* h2 = l1 + L * MP;
     float* l2 = h2 + L * MP;
-    int32_t* id1 = reinterpret_cast<int32_t*>(l2 + L * MP);
+    float* da = l2 + L * MP;              // dist(a, centre of e2)
+    float* pb = da + L;                   // PD(b)
+    int32_t* id1 = reinterpret_cast<int32_t*>(pb + L);
     int32_t* id2 = id1 + L;
+    uint32_t* plist = reinterpret_cast<uint32_t*>(id2 + L);   // 64 x 64 pairs (a << 16 | b)
+    __shared__ float cen[MP];
+    __shared__ int npl;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const float u = 5.9604645e-08f;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int2 tl = tiles[t];
         const int64_t a0 = (int64_t)tl.x * L, b0 = (int64_t)tl.y * L;
@@ -169,36 +205,82 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_kernel(
             l2[e] = plo[b0 * MP + e];
         }
         for (int e = threadIdx.x; e < ca; e += WG) id1[e] = perm[a0 + e];
-        for (int e = threadIdx.x; e < cb; e += WG) id2[e] = perm[b0 + e];
+        for (int e = threadIdx.x; e < cb; e += WG) {
+            id2[e] = perm[b0 + e];
+            pb[e] = ppd[b0 + e];
+        }
+        if (threadIdx.x < MP) cen[threadIdx.x] = v.cen[(int64_t)threadIdx.x * v.n_nodes + leaf_base + tl.y];
+        if (threadIdx.x == 0) npl = 0;
         __syncthreads();
-        const int P = ca * cb;
-        for (int base = 0; base < P; base += WG) {
-            const int p = base + threadIdx.x;
-            bool hit = false;
-            float pd2 = 0.f;
-            int a = 0, b = 0;
-            if (p < P) {
-                a = p / cb;
-                b = p - a * cb;
-                const float* x1 = h1 + a * MP;
-                const float* y1 = l1 + a * MP;
-                const float* x2 = h2 + b * MP;
-                const float* y2 = l2 + b * MP;
+        for (int a = threadIdx.x; a < ca; a += WG) {
+            float acc = 0.f;
 #pragma unroll
-                for (int j = 0; j < MP; ++j) {
-                    // (hi1 - hi2) is exact for nearby points (Sterbenz); the lo
-                    // parts restore what rounding the projection to FP32 lost
-                    const float dt = __fadd_rn(__fsub_rn(x1[j], x2[j]), __fsub_rn(y1[j], y2[j]));
-                    pd2 = __fmaf_rn(dt, dt, pd2);
-                }
-                hit = pd2 < R2;
+            for (int j = 0; j < MP; ++j) {
+                const float dt = __fadd_rn(__fsub_rn(h1[a * MP + j], cen[j]), l1[a * MP + j]);
+                acc = __fmaf_rn(dt, dt, acc);
             }
-            const int64_t slot = wave_append_global(hit, counter);
-            if (hit && slot < cap) {
-                const uint32_t ia = (uint32_t)id1[a], ib = (uint32_t)id2[b];
-                ck0[slot] = __float_as_uint(pd2);
-                cii[slot] = ia < ib ? ia : ib;
-                cjj[slot] = ia < ib ? ib : ia;
+            da[a] = sqrtf(acc);
+        }
+        __syncthreads();
+        // pairs in blocks of 64 x 64, so the compacted list holds at most 4,096
+        for (int ab = 0; ab < ca; ab += 64) {
+            for (int bb = 0; bb < cb; bb += 64) {
+                // 1: PD filter and compaction
+                const int ae = min(ca, ab + 64);
+                for (int a = ab + wave; a < ae; a += WG / 64) {
+                    const float x = da[a];
+                    const int b = bb + lane;
+                    bool pass = false;
+                    if (b < cb) {
+                        const float y = pb[b];
+                        // each distance carries at most ~12 u of relative error
+                        pass = fabsf(x - y) - 32.f * u * (x + y) < Rlim;
+                    }
+                    const uint64_t m = __ballot(pass);
+                    if (m) {
+                        const int leader = __ffsll((unsigned long long)m) - 1;
+                        int base = 0;
+                        if (lane == leader) base = atomicAdd(&npl, __popcll(m));
+                        base = __shfl(base, leader);
+                        if (pass) plist[base + __popcll(m & ((1ull << lane) - 1ull))] =
+                            ((uint32_t)a << 16) | (uint32_t)b;
+                    }
+                }
+                __syncthreads();
+                // 2: projected distance of the remaining pairs
+                const int np = npl;
+                for (int base = 0; base < np; base += WG) {
+                    const int q = base + threadIdx.x;
+                    bool hit = false;
+                    float pd2 = 0.f;
+                    int a = 0, b = 0;
+                    if (q < np) {
+                        a = (int)(plist[q] >> 16);
+                        b = (int)(plist[q] & 0xffffu);
+                        const float* x1 = h1 + a * MP;
+                        const float* y1 = l1 + a * MP;
+                        const float* x2 = h2 + b * MP;
+                        const float* y2 = l2 + b * MP;
+#pragma unroll
+                        for (int j = 0; j < MP; ++j) {
+                            // (hi1 - hi2) is exact for nearby points (Sterbenz);
+                            // the lo parts restore what rounding to FP32 lost
+                            const float dt = __fadd_rn(__fsub_rn(x1[j], x2[j]), __fsub_rn(y1[j], y2[j]));
+                            pd2 = __fmaf_rn(dt, dt, pd2);
+                        }
+                        hit = pd2 < R2;
+                    }
+                    const int64_t slot = wave_append_global(hit, counter);
+                    if (hit && slot < cap) {
+                        const uint32_t ia = (uint32_t)id1[a], ib = (uint32_t)id2[b];
+                        ck0[slot] = __float_as_uint(pd2);
+                        cii[slot] = ia < ib ? ia : ib;
+                        cjj[slot] = ia < ib ? ib : ia;
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) npl = 0;
+                __syncthreads();
             }
         }
         __syncthreads();
@@ -515,15 +597,27 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     int64_t n_raw = 0;
     if (n_tiles > 0) {
         int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
-        const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 2 * 4;
+        // parent distances of every point (PD of the PM-tree leaf entries)
+        DevBuf ppd;
+        ppd.alloc((size_t)n * sizeof(float));
+        const int64_t leaf_base = x->level_begin[x->levels - 1];
+        NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
+                   x->num_pivots};
+        hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
+                           x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
+        PMLSH_HIP(hipGetLastError());
+        const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
+        if (lds > 160 * 1024 - 256)
+            fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
         PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         for (int attempt = 0; attempt < 2; ++attempt) {
             cand.alloc(cap);
             reset_counter();
             hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds,
-                               st, x->proj_hi, x->proj_lo, x->perm, n, L, tiles.as<int2>(),
-                               n_tiles, R2, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                               st, x->proj_hi, x->proj_lo, ppd.as<float>(), v, leaf_base,
+                               x->perm, n, L, tiles.as<int2>(), n_tiles, R2, limit,
+                               cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
                                cand.jj.as<uint32_t>(), cap,
                                static_cast<unsigned long long*>(dcount.p));
             PMLSH_HIP(hipGetLastError());
