@@ -6,7 +6,7 @@ batches of 1,024 per launch, k = 10, c = 1.5, confidence 1 - 1/e. Inputs are
 synthetic (seeded) and resident in HBM before timing starts.
 
 Metric: queries/s at recall@10 >= 0.9. The candidate fraction beta is swept
-({5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3}); the smallest beta whose recall@10
+({5e-4, 6e-4, ..., 1e-3 in steps of 5e-5 to 1e-4, then 1.5e-3, 2e-3, 5e-3}); the smallest beta whose recall@10
 over all 10,000 queries reaches 0.9 is the operating point, and only that
 point is timed. A step is one pmlsh_ann call on one batch (projection, chunk
 distances, bound and Eq. 5 chunk test, range filter on the matrix cores,
@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X published dense FP16 matrix peak
-BETAS = [5e-4, 7.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3]
+BETAS = [5e-4, 6e-4, 7e-4, 7.5e-4, 8e-4, 8.5e-4, 9e-4, 9.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3]
 K = 10
 C = 1.5
 CONF = 1 - 1 / math.e
@@ -307,7 +307,8 @@ def main():
         with open(PMC_FILE) as fh:
             pmc = json.load(fh)
         kern = pmc.get("kernels", {}).get(roof["kernel"])
-        if pmc.get("kernel_source_sha") == kernel_source_hash() and kern:
+        if (pmc.get("kernel_source_sha") == kernel_source_hash() and kern
+                and pmc.get("beta") == beta):
             traffic = kern.get("hbm_bytes_per_launch")
     roof["traffic"] = traffic
 
