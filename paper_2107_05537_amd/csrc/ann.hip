@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <cstddef>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -94,8 +95,9 @@ struct AnnArgs {
     int mwords;
     uint64_t* cmask;            // the same mask chunk-major: ceil(nq / 64) words per chunk
     int cwords;
-    // squared distances from every query to every chunk centre (row stride ldc)
-    float* cdist;
+    // squared distances from every query to every chunk centre (row stride
+    // ldc), as bf16 bit patterns rounded toward zero (lower bounds)
+    uint16_t* cdist;
     int64_t ldc;
     int32_t* csel;              // per query: the chunks chosen for its bound (ldc)
     // bounded verification: FP16 rows (stride d16), their scales and error
@@ -108,14 +110,18 @@ struct AnnArgs {
     float* ws_clo;
 };
 
+// skey and spos come last: the bound kernel uses only the fields before
+// them and keeps its row of centre distances in their place.
 struct Smem {
     uint32_t hist[NB];
-    uint64_t skey[CAP];
-    int32_t spos[CAP];
     int32_t red[NWAVE * 2];
     int32_t cnt0, cnt1, cnt2;
     int32_t thr_bin, thr_below, thr_in;
+    int32_t pad_[2];
+    uint64_t skey[CAP];
+    int32_t spos[CAP];
 };
+static_assert(offsetof(Smem, skey) % 16 == 0, "row area must be 16-byte aligned");
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -922,21 +928,21 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
 // Queries whose list overflows (or that fall outside the path) are flagged
 // and answered by the per-query kernel above.
 
-// Shift that maps the 32-bit keys [lo, hi] onto NB bins: (key - lo) >> shift.
-__device__ __forceinline__ int shift32(uint32_t lo, uint32_t hi) {
-    const uint32_t span = hi - lo;
-    if (span < (uint32_t)NB) return 0;
-    return (32 - __clz((int)span)) - 11;
-}
-
 // Squared FP32 distances from every query of the batch to every chunk centre,
 // as |q'|^2 + |c|^2 - 2 q'.c (clamped at 0): one chunk per thread, 64 queries
 // per workgroup read from LDS. Row q of the output holds the query's
-// distances (stride ldc). The expansion's rounding error stays below
-// 64 u (|q'| + S)^2 (S bounds every centre norm); the chunk-ball test adds
-// that much to its threshold, and the choice of chunks for the bound needs
-// no exactness.
+// distances (stride ldc) as bf16 bit patterns, rounded toward zero (the FP32
+// value's upper half), so each stored value is at most the FP32 value and
+// above it by less than a factor 1 + 2^-7. The expansion's rounding error
+// stays below 64 u (|q'| + S)^2 (S bounds every centre norm); the chunk-ball
+// test adds that much to its threshold and tests the rounded-down value, and
+// the choice of chunks for the bound needs no exactness.
 constexpr int DQB = 64;
+// float bits >> 19 of 2^-64: the first of the fixed centre-distance bins
+constexpr uint32_t kCenBinBase = 63u << 4;
+// largest LDS footprint of the bound kernel with its row in LDS (two
+// workgroups per compute unit at the most)
+constexpr size_t kTauRowLds = 80 * 1024;
 
 __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
     __shared__ float sq[DQB][MP];
@@ -961,19 +967,21 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
         cen[t] = a.chunk_cen[c * MP + t];
         cn2 = fmaf(cen[t], cen[t], cn2);
     }
-    float* out = a.cdist + (int64_t)q0 * a.ldc + c;
+    uint16_t* out = a.cdist + (int64_t)q0 * a.ldc + c;
     for (int q = 0; q < nqb; ++q) {
         float dot = 0.f;
 #pragma unroll
         for (int t = 0; t < MP; ++t) dot = fmaf(sq[q][t], cen[t], dot);
-        out[(int64_t)q * a.ldc] = fmaxf(fmaf(-2.f, dot, sn[q] + cn2), 0.f);
+        const float d2 = fmaxf(fmaf(-2.f, dot, sn[q] + cn2), 0.f);
+        out[(int64_t)q * a.ldc] = (uint16_t)(__float_as_uint(d2) >> 16);
     }
 }
 
 // Upper bound tau on the budget-th smallest projected distance of one query,
 // and the query's row of the chunk mask:
 //   1. the squared distances from q' to every 64-point chunk centre (computed
-//      by dist_kernel), read four chunks per thread;
+//      by dist_kernel, bf16 lower bounds), read four chunks per thread; with
+//      LROW the row is read from HBM once into LDS and every pass reads LDS;
 //   2. the chunks nearest to q' that hold at least min(n, 2 * budget) points,
 //      chosen with a histogram of those distances weighted by chunk sizes;
 //   3. over the points of the chosen chunks, the budget-th smallest pd^2
@@ -987,6 +995,7 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
 //
 // Mask layout (query-major, bit-sliced to match four chunks per thread): bit l
 // of word 4 g + k of a query's row is chunk 256 g + 4 l + k.
+template <bool LROW>
 __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
@@ -995,81 +1004,90 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     load_query(a, qi, nullptr, qc);
     const int nch = (int)(a.n_pad16 >> 6);
     const int ng4 = (nch + 3) >> 2;
-    const float4* row4 = reinterpret_cast<const float4*>(a.cdist + qi * a.ldc);
+    // four bf16 distances per 8-byte element (element g: chunks 4 g .. 4 g + 3)
+    const uint2* grow = reinterpret_cast<const uint2*>(a.cdist + qi * a.ldc);
+    uint2* lrow = reinterpret_cast<uint2*>(smem_raw + offsetof(Smem, skey));
+    if (LROW) {
+        for (int g = threadIdx.x; g < ng4; g += WG) lrow[g] = grow[g];
+        __syncthreads();
+    }
+    const uint2* row4 = LROW ? lrow : grow;
     int32_t* sel = a.csel + qi * a.ldc;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    auto chunk_pts = [&](int i) { return (int)min<int64_t>(64, a.n - ((int64_t)i << 6)); };
-    auto comp = [](const float4& v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; };
+    // bf16 bit pattern k of an element (non-negative values: ordered as
+    // unsigned integers)
+    auto half_k = [](const uint2& v, int k) {
+        const uint32_t w = k < 2 ? v.x : v.y;
+        return (k & 1) ? (w >> 16) : (w & 0xffffu);
+    };
 
-    // 1: range of the centre distances
-    uint32_t lo = 0xffffffffu, hi = 0u;
+    // 1: histogram of the centre distances (chunk counts) on fixed bins: 16
+    // per octave of the squared distance over [2^-64, 2^64), clamped at both
+    // ends, so no range pass is needed. The chosen chunks are those of the
+    // bins up to the one where the running count reaches wc = min(n_chunks,
+    // ceil(want / 64) + 1) chunks, want = min(n, 2 * budget) points (the
+    // extra chunk covers the one chunk with fewer than 64 points).
+    const uint32_t hbase = kCenBinBase;
+    auto cbin = [&](uint32_t h) { return min(max(h >> 3, hbase) - hbase, (uint32_t)(NB - 1)); };
+    clear_hist(sh);
     for (int g = threadIdx.x; g < ng4; g += WG) {
-        const float4 v = row4[g];
+        const uint2 v = row4[g];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (4 * g + k < nch) {
-                const uint32_t b = __float_as_uint(comp(v, k));
-                lo = min(lo, b);
-                hi = max(hi, b);
-            }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
-    }
-    if (lane == 0) {
-        sh.red[wave] = (int)lo;
-        sh.red[NWAVE + wave] = (int)hi;
+            if (4 * g + k < nch) atomicAdd(&sh.hist[cbin(half_k(v, k))], 1u);
     }
     __syncthreads();
-#pragma unroll
-    for (int w = 0; w < NWAVE; ++w) {
-        lo = min(lo, (uint32_t)sh.red[w]);
-        hi = max(hi, (uint32_t)sh.red[NWAVE + w]);
-    }
-    __syncthreads();
-
-    // 2: histogram of the centre distances weighted by chunk sizes; the
-    // nearest chunks holding min(n, 2 * budget) points are chosen
-    const int sft = shift32(lo, hi);
-    clear_hist(sh);
-    int loc = 0;
-    for (int g = threadIdx.x; g < ng4; g += WG) {
-        const float4 v = row4[g];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = 4 * g + k;
-            if (i < nch) {
-                const int w = chunk_pts(i);
-                atomicAdd(&sh.hist[(__float_as_uint(comp(v, k)) - lo) >> sft], (uint32_t)w);
-                loc += w;
-            }
-        }
-    }
-    __syncthreads();
-    const int total = block_sum(loc, sh);
-    const int want = total < 2 * a.budget ? total : 2 * a.budget;
+    const int64_t want = a.n < 2 * (int64_t)a.budget ? a.n : 2 * (int64_t)a.budget;
+    const int wc = (int)min<int64_t>(nch, (want + 63) / 64 + 1);
     if (threadIdx.x == 0) sh.thr_bin = NB - 1;
     __syncthreads();
-    find_threshold(want, sh);
+    find_threshold(wc, sh);
     const uint32_t tbin = (uint32_t)sh.thr_bin;
+    const int need = wc - sh.thr_below;   // chunks still wanted from bin tbin
+    const int in_bin = sh.thr_in;
+    // every chunk with a stored value <= tlim is chosen: all of bin tbin, or,
+    // when that bin holds more than eight chunks beyond those wanted, only
+    // its sub-bins (the three low bits of the bf16 pattern) up to the one
+    // where the count reaches `need` (the clamped end bins stay whole)
+    uint32_t tlim = tbin == (uint32_t)(NB - 1) ? 0xffffu : ((tbin + hbase) << 3) | 7u;
+    if (in_bin - need > 8 && tbin != 0u && tbin != (uint32_t)(NB - 1)) {
+        __syncthreads();
+        clear_hist(sh);
+        for (int g = threadIdx.x; g < ng4; g += WG) {
+            const uint2 v = row4[g];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t h = half_k(v, k);
+                if (4 * g + k < nch && (h >> 3) == tbin + hbase) atomicAdd(&sh.hist[h & 7u], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+        __syncthreads();
+        find_threshold(need, sh);
+        tlim = ((tbin + hbase) << 3) | (uint32_t)sh.thr_bin;
+    }
     if (threadIdx.x == 0) sh.cnt1 = 0;
     __syncthreads();
 
-    // the chosen chunks, and the largest distance bound over their points
+    // 2: the chosen chunks, and the largest distance bound over their points
     float rmax = 0.f;
-    for (int b0 = 0; b0 < ng4; b0 += WG) {
-        const int g = b0 + threadIdx.x;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g < ng4) v = row4[g];
+    for (int g = threadIdx.x; g < ng4; g += WG) {
+        const uint2 v = row4[g];
+        bool tk[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = 4 * g + k;
-            const float d2 = comp(v, k);
-            const bool take = g < ng4 && i < nch && ((__float_as_uint(d2) - lo) >> sft) <= tbin;
-            if (take) rmax = fmaxf(rmax, sqrtf(d2) + a.chunk_rad[i]);
-            const int slot = wave_append(take, &sh.cnt1);
-            if (take) sel[slot] = i;
+        for (int k = 0; k < 4; ++k) tk[k] = 4 * g + k < nch && half_k(v, k) <= tlim;
+        if (tk[0] | tk[1] | tk[2] | tk[3]) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (tk[k]) {
+                    const int i = 4 * g + k;
+                    // the stored distance is low by less than a factor 1 + 2^-7
+                    const float d = sqrtf(__uint_as_float(half_k(v, k) << 16)) * 1.0079f;
+                    rmax = fmaxf(rmax, d + a.chunk_rad[i]);
+                    sel[atomicAdd(&sh.cnt1, 1)] = i;
+                }
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
@@ -1125,7 +1143,8 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         const float4* rad4 = reinterpret_cast<const float4*>(a.chunk_rad);
         for (int G = wave; G < ng256; G += NWAVE) {
             const int g = (G << 6) + lane;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f), rv = v;
+            uint2 v = make_uint2(0u, 0u);
+            float4 rv = make_float4(0.f, 0.f, 0.f, 0.f);
             if (g < ng4) {
                 v = row4[g];
                 rv = rad4[g];
@@ -1133,9 +1152,10 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             uint64_t bk[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float r = comp(rv, k) + tq;
+                const float r = (k == 0 ? rv.x : k == 1 ? rv.y : k == 2 ? rv.z : rv.w) + tq;
+                const float d2 = __uint_as_float(half_k(v, k) << 16);
                 bk[k] = __builtin_amdgcn_ballot_w64(g < ng4 && 4 * g + k < nch &&
-                                                    comp(v, k) <= fmaf(r, r, dmarg));
+                                                    d2 <= fmaf(r, r, dmarg));
             }
             if (lane < 4) {
                 const uint64_t w = lane == 0 ? bk[0] : lane == 1 ? bk[1] : lane == 2 ? bk[2] : bk[3];
@@ -1621,7 +1641,18 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     }
     __syncthreads();
     const int m = sh.cnt1;
-    if (m > a.k) {
+    if (m <= WG) {
+        // keys are distinct (ids): the rank of each among the m is its slot
+        if (threadIdx.x < m) {
+            const uint64_t key = sh.skey[threadIdx.x];
+            int rank = 0;
+            for (int y = 0; y < m; ++y) rank += sh.skey[y] < key;
+            if (rank < a.k) {
+                a.out_ids[qi * a.k + rank] = (int64_t)(uint32_t)key;
+                a.out_dist[qi * a.k + rank] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+            }
+        }
+    } else {
         const uint64_t kth = lds_select(m, a.k, sh);
         uint64_t* tmp = reinterpret_cast<uint64_t*>(sh.hist);
         if (threadIdx.x == 0) sh.cnt1 = 0;
@@ -1635,12 +1666,12 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         __syncthreads();
         for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) sh.skey[j2] = tmp[j2];
         __syncthreads();
-    }
-    bitonic_sort(m < a.k ? m : a.k, sh);
-    for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) {
-        const uint64_t key = sh.skey[j2];
-        a.out_ids[qi * a.k + j2] = (int64_t)(uint32_t)key;
-        a.out_dist[qi * a.k + j2] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+        bitonic_sort(a.k, sh);
+        for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) {
+            const uint64_t key = sh.skey[j2];
+            a.out_ids[qi * a.k + j2] = (int64_t)(uint32_t)key;
+            a.out_dist[qi * a.k + j2] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+        }
     }
     if (a.out_stats && threadIdx.x == 0) {
         int32_t* st = a.out_stats + qi * 4;
@@ -1738,7 +1769,20 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         }
         {
             StageTimer tm(PMLSH_STAGE_TAU, stream);
-            hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), lds0, stream, a);
+            // the query's row of centre distances stays in LDS (in place of
+            // the selection arrays the bound kernel does not use) when it
+            // fits there
+            const size_t row_bytes = (size_t)8 * ((nchunk + 3) / 4);
+            const size_t lds_row = offsetof(Smem, skey) + row_bytes;
+            if (lds_row <= kTauRowLds) {
+                const int lds_t = (int)std::max(lds_row, (size_t)lds0);
+                PMLSH_HIP(hipFuncSetAttribute((const void*)tau_kernel<true>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_t));
+                hipLaunchKernelGGL(tau_kernel<true>, dim3((unsigned)L.nq), dim3(WG), lds_t, stream, a);
+            } else {
+                hipLaunchKernelGGL(tau_kernel<false>, dim3((unsigned)L.nq), dim3(WG), lds0, stream,
+                                   a);
+            }
             PMLSH_HIP(hipGetLastError());
             const int64_t waves = (L.nq + 63) / 64 * a.mwords;
             hipLaunchKernelGGL(mask_transpose_kernel, dim3((unsigned)((waves + NWAVE - 1) / NWAVE)),

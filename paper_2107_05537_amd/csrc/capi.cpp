@@ -70,11 +70,11 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     const int64_t nchunk = x->n_pad16 / 64;
     const int64_t ldc = (nchunk + 15) / 16 * 16;
     const int64_t mwords = 4 * ((nchunk + 255) / 256);
-    const int64_t per_query_all = per_query + (fast ? 8 * mwords + 8 * ldc + (nchunk + 7) / 8 : 0);
+    const int64_t per_query_all = per_query + (fast ? 8 * mwords + 6 * ldc + (nchunk + 7) / 8 : 0);
     int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     batch = std::min<int64_t>(batch, 65535);
     const int64_t mask_bytes =
-        fast ? batch * (8 * mwords + 8 * ldc) + nchunk * ((batch + 63) / 64) * 8 : 0;
+        fast ? batch * (8 * mwords + 6 * ldc) + nchunk * ((batch + 63) / 64) * 8 : 0;
     void* ws = nullptr;
     PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query + mask_bytes), st));
     char* base = static_cast<char*>(ws);
@@ -82,7 +82,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // boundary
     float* qproj = reinterpret_cast<float*>(base);
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
-    float* cdist2 = reinterpret_cast<float*>(qaug + batch * 32);
+    uint16_t* cdist2 = qaug + batch * 32;
     int32_t* csel = reinterpret_cast<int32_t*>(cdist2 + (fast ? batch * ldc : 0));
     uint64_t* qmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * ldc : 0));
     uint64_t* cmask = qmask + (fast ? batch * mwords : 0);

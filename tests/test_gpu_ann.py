@@ -111,6 +111,19 @@ def test_multi_round_and_line4(parity_wl, scale, beta, k, expect):
         assert 1 in kinds           # Algorithm 2's line-4 exit
 
 
+def test_topk_larger_than_one_workgroup(parity_wl):
+    """k = 300: more top-k members than threads of a workgroup (the top-k is
+    then selected and sorted rather than ranked in one step)."""
+    pm = _gpu()
+    w = parity_wl
+    D, A, Q = w["D"], w["A"], w["Q"][:20]
+    say("case: k=300")
+    res, B = oracle_ann(D, A, Q, 300, 1.5, 0.9, 0.05, r_min=1e30)
+    assert B == 800
+    _, ids, dist, st = _run(pm, D, A, Q, 300, 1.5, 0.9, 0.05, 1e30)
+    compare_ann(D, Q, res, ids, dist, st)
+
+
 def test_budget_larger_than_one_sort(parity_wl):
     """B = 4010 > 2048: the radix-select refinement and the top-k selection
     over a candidate set larger than one LDS sort."""
@@ -261,7 +274,7 @@ def test_headline_scale_sampled():
     say("case: headline scale")
     w = synth.headline(n_queries=1024)
     D, A, Q = w["D"], w["A"], w["Q"]
-    beta, k = 1e-3, 10
+    beta, k = 9e-4, 10
     dev = torch.device("cuda", 0)
     idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
     B = min(D.shape[0], math.ceil(beta * D.shape[0]) + k)
@@ -274,6 +287,33 @@ def test_headline_scale_sampled():
     from oracle import ann as oann
     Dp = oann.project(D, A)
     sample = np.arange(0, 1024, 64)
+    res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
+    compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
+    say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
+
+
+def test_large_n_row_in_hbm_sampled():
+    """2,600,000 x 16 mixture: the per-query row of chunk-centre distances is
+    too long for LDS, so the bound kernel reads it from HBM in every pass;
+    16 sampled queries of one launch checked against the oracle."""
+    pm = _gpu()
+    say("case: n=2.6M, d=16")
+    spec = synth.MixtureSpec(n=2_600_000, d=16, n_centres=2_000, centre_std=2.0,
+                             sigma_lo=0.2, sigma_hi=0.5, n_queries=512)
+    w = synth.mixture(spec, 7)
+    D, A, Q = w["D"], w["A"], w["Q"]
+    beta, k = 2e-4, 10
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    B = min(D.shape[0], math.ceil(beta * D.shape[0]) + k)
+    r0 = oracle_r_min(D, 0x5EED, B)
+    ids, dist, st = idx.ann(torch.from_numpy(Q).to(dev), k, c=1.5, beta=beta, r_min=r0,
+                            stats=True)
+    torch.cuda.synchronize()
+    ids, dist, st = ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
+    from oracle import ann as oann
+    Dp = oann.project(D, A)
+    sample = np.arange(0, 512, 32)
     res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
     compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
     say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
