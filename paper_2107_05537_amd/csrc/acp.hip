@@ -437,15 +437,30 @@ __global__ __launch_bounds__(WG) void acp_final_kernel(
 }
 
 // ---------------------------------------------------------------- host side
+// Workspace buffer of one role, kept in the index between calls and grown
+// (freed and allocated anew) only when a call needs more than it holds.
+enum Slot {
+    S_HIST, S_COUNT, S_DOFF, S_TILES, S_PPD, S_SEEDS, S_CAND = S_SEEDS + 3, S_KEPT = S_CAND + 3,
+    S_POOL = S_KEPT + 3, S_TOP = S_POOL + 3, S_COUNT_ALL = S_TOP + 3
+};
+
 struct DevBuf {
     void* p = nullptr;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    const pmlsh_index* x;
+    int slot;
+    DevBuf(const pmlsh_index* idx, int s) : x(idx), slot(s) {}
     void alloc(size_t bytes) {
-        if (p) { (void)hipFree(p); p = nullptr; }
-        PMLSH_HIP(hipMalloc(&p, bytes ? bytes : 1));
+        if (bytes == 0) bytes = 1;
+        auto& b = x->acp_bufs[slot];
+        if (b.second < bytes) {
+            if (b.first) {
+                (void)hipFree(b.first);
+                b = {nullptr, 0};
+            }
+            PMLSH_HIP(hipMalloc(&b.first, bytes));
+            b.second = bytes;
+        }
+        p = b.first;
     }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
@@ -453,6 +468,7 @@ struct DevBuf {
 struct Triplets {
     DevBuf k0, ii, jj;
     int64_t cap = 0;
+    Triplets(const pmlsh_index* idx, int s) : k0(idx, s), ii(idx, s + 1), jj(idx, s + 2) {}
     void alloc(int64_t c) {
         cap = c;
         k0.alloc((size_t)c * 4);
@@ -522,7 +538,9 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     const int L = x->leaf_size;
     const int64_t NL = x->n_leaves;
 
-    DevBuf dhist, dcount;
+    std::lock_guard<std::mutex> lock(x->acp_mu);
+    if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});
+    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT);
     dhist.alloc(NB * sizeof(uint32_t));
     dcount.alloc(sizeof(unsigned long long));
     auto reset_counter = [&] {
@@ -542,10 +560,10 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         seed_off[b + 1] = seed_off[b] + cnt * (cnt - 1) / 2;
     }
     const int64_t n_seed = seed_off[NL];
-    Triplets seeds;
+    Triplets seeds(x, S_SEEDS);
     seeds.alloc(n_seed);
     if (n_seed > 0) {
-        DevBuf doff;
+        DevBuf doff(x, S_DOFF);
         doff.alloc((NL + 1) * sizeof(int64_t));
         PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
                                  hipMemcpyHostToDevice, st));
@@ -574,7 +592,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     // ---- tiles surviving Mindist (Eq. 11)
     const int64_t tiles_total = NL * (NL - 1) / 2;
     int64_t n_tiles = 0;
-    DevBuf tiles;
+    DevBuf tiles(x, S_TILES);
     if (tiles_total > 0) {
         if (tiles_total > (int64_t(1) << 31) || NL > 65535)
             fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
@@ -593,12 +611,12 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
 
     // ---- pair scan of the surviving tiles
     constexpr int64_t kMaxCand = int64_t(1) << 28;
-    Triplets cand;
+    Triplets cand(x, S_CAND);
     int64_t n_raw = 0;
     if (n_tiles > 0) {
         int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
         // parent distances of every point (PD of the PM-tree leaf entries)
-        DevBuf ppd;
+        DevBuf ppd(x, S_PPD);
         ppd.alloc((size_t)n * sizeof(float));
         const int64_t leaf_base = x->level_begin[x->levels - 1];
         NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
@@ -632,7 +650,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     // ---- budget T: keep the projected-nearest candidates
     const int64_t keep = std::max<int64_t>(0, plan.acp_budget - n_seed);
     int64_t n_keep = std::min(n_raw, keep);
-    Triplets kept;
+    Triplets kept(x, S_KEPT);
     const Triplets* cands = &cand;
     if (n_raw > keep && keep > 0) {
         SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
@@ -650,7 +668,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     }
 
     // ---- verify the candidates; the pool is seeds followed by candidates
-    Triplets pool;
+    Triplets pool(x, S_POOL);
     const int64_t n_pool = n_seed + n_keep;
     pool.alloc(n_pool);
     if (n_seed > 0) {
@@ -670,7 +688,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     // ---- top-k over the pool
     SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
                           n_pool, k, false, dhist.as<uint32_t>(), st);
-    Triplets top;
+    Triplets top(x, S_TOP);
     top.alloc(k);
     reset_counter();
     hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,

@@ -37,12 +37,15 @@ struct TmpBuf {
 
 void index_release(pmlsh_index* x) {
     if (!x) return;
-    void* bufs[] = {x->data, x->proj_hi, x->proj_lo, x->perm, x->inv_perm, x->hash,
+    void* bufs[] = {x->data, x->proj_hi, x->proj_lo, x->proj16, x->chunk_cen, x->chunk_rad,
+                    x->data16, x->data16_scale, x->data16_eps, x->perm, x->inv_perm, x->hash,
                     x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max,
                     x->tree.child_begin, x->tree.child_end, x->tree.npts,
                     x->tree.pivots};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (auto& b : x->acp_bufs)
+        if (b.first) (void)hipFree(b.first);
     delete x;
 }
 

@@ -76,7 +76,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     const int64_t mask_bytes =
         fast ? batch * (8 * mwords + 6 * ldc) + nchunk * ((batch + 63) / 64) * 8 : 0;
     void* ws = nullptr;
-    PMLSH_HIP(hipMallocAsync(&ws, (size_t)(batch * per_query + mask_bytes), st));
+    ws = ws_alloc((size_t)(batch * per_query + mask_bytes), st);
     char* base = static_cast<char*>(ws);
     // projections and FP16 scan rows first: every row starts on a 64-byte
     // boundary
@@ -136,10 +136,10 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             launch_ann(L, st);
         }
     } catch (...) {
-        (void)hipFreeAsync(ws, st);
+        ws_free(ws, st);
         throw;
     }
-    PMLSH_HIP(hipFreeAsync(ws, st));
+    ws_free(ws, st);
 }
 
 }  // namespace pmlsh

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pmlsh.h"
@@ -39,6 +41,12 @@ struct Error {
             ::pmlsh::fail(e_ == hipErrorOutOfMemory ? PMLSH_ENOMEM : PMLSH_EDEVICE, \
                           std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Stream-ordered device memory from the library's per-device pool (freed
+// blocks are kept for reuse by later calls). ws_free never throws.
+void* ws_alloc(size_t bytes, hipStream_t st);
+void ws_free(void* p, hipStream_t st);
 
 // ---------------------------------------------------------------- planner
 double chi2_cdf(double x, int m);
@@ -114,6 +122,11 @@ struct pmlsh_index {
     std::vector<double> sample_sorted;   // ascending pair distances (r_min rule)
     double kappa = 0.9;
     float coord_scale = 0.f;
+    // (c,k)-ACP workspace kept between calls: one device buffer per role,
+    // grown on demand, freed with the index; calls on one index serialise on
+    // the mutex
+    mutable std::mutex acp_mu;
+    mutable std::vector<std::pair<void*, size_t>> acp_bufs;
 };
 
 namespace pmlsh {
