@@ -41,6 +41,9 @@ constexpr int MAX_LEVELS = 16;
 constexpr int MAX_ROUNDS = 1000;
 constexpr int64_t kScanBlocks = 1024;   // scan workgroups if the occupancy query fails
 
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
 struct AnnArgs {
     const float* data;
     const float* proj;
@@ -929,53 +932,110 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
 // and answered by the per-query kernel above.
 
 // Squared FP32 distances from every query of the batch to every chunk centre,
-// as |q'|^2 + |c|^2 - 2 q'.c (clamped at 0): one chunk per thread, 64 queries
-// per workgroup read from LDS. Row q of the output holds the query's
-// distances (stride ldc) as bf16 bit patterns, rounded toward zero (the FP32
-// value's upper half), so each stored value is at most the FP32 value and
-// above it by less than a factor 1 + 2^-7. The expansion's rounding error
-// stays below 64 u (|q'| + S)^2 (S bounds every centre norm); the chunk-ball
-// test adds that much to its threshold and tests the rounded-down value, and
-// the choice of chunks for the bound needs no exactness.
-constexpr int DQB = 64;
+// as |q'|^2 + |c|^2 - 2 q'.c (clamped at 0), on the FP32 matrix cores: a
+// workgroup takes 64 queries x 256 chunks in four sub-tiles of 64 chunks,
+// each wave a strip of 16 queries x 64 chunks per sub-tile (four 16 x 16
+// tiles of v_mfma_f32_16x16x4_f32, K = 16 in four steps; the next
+// sub-tile's centres are loaded meanwhile); each sub-tile goes through LDS
+// so that every query's 64 values leave as one 128-byte segment. Row q of the output holds the query's distances
+// (stride ldc) as bf16 bit patterns, rounded toward zero (the FP32 value's
+// upper half), so each stored value is at most the FP32 value and above it
+// by less than a factor 1 + 2^-7. The expansion's rounding error, in any
+// summation order of the 16 products, stays below 64 u (|q'| + S)^2 (S
+// bounds every centre norm); the chunk-ball test adds that much to its
+// threshold and tests the rounded-down value, and the choice of chunks for
+// the bound needs no exactness.
+constexpr int DQB = 64;    // queries per workgroup
+constexpr int DCS = 64;    // chunks per sub-tile
+constexpr int DCB = 256;   // chunks per workgroup (four sub-tiles)
+
+__global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
+    __shared__ float sq[DQB][MP + 1];
+    __shared__ float sc[DCS][MP + 1];
+    __shared__ float sqn[DQB], scn[DCS];
+    __shared__ __align__(16) uint16_t tile[DQB][DCS];
+    const int q0 = blockIdx.y * DQB;
+    const int nch = (int)(a.n_pad16 >> 6);
+    const int nqb = min(DQB, a.nq - q0);
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // one centre coordinate quadruple per thread: centre e / 4, columns 4 (e % 4)
+    const int ce = threadIdx.x >> 2, cq = (threadIdx.x & 3) * 4;
+    auto load_cen = [&](int c0) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c0 + ce < nch) v = *reinterpret_cast<const float4*>(a.chunk_cen + (int64_t)(c0 + ce) * MP + cq);
+        return v;
+    };
+    float4 cnext = load_cen(blockIdx.x * DCB);
+    for (int e = threadIdx.x; e < DQB * MP; e += WG) {
+        const int r = e / MP, t = e % MP;
+        sq[r][t] = r < nqb ? a.qp[(int64_t)(q0 + r) * MP + t] : 0.f;
+    }
+    __syncthreads();
+    if (threadIdx.x < DQB) {
+        float n2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) n2 = fmaf(sq[threadIdx.x][t], sq[threadIdx.x][t], n2);
+        sqn[threadIdx.x] = n2;
+    }
+    // A operand (16 queries x 16): lane holds row li, columns lk, 4 + lk, ...
+    float av[MP / 4];
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < MP / 4; ++kk) av[kk] = sq[16 * wave + li][4 * kk + lk];
+    for (int sub = 0; sub < DCB / DCS; ++sub) {
+        const int c0 = blockIdx.x * DCB + sub * DCS;
+        if (c0 >= nch) break;
+        sc[ce][cq] = cnext.x;
+        sc[ce][cq + 1] = cnext.y;
+        sc[ce][cq + 2] = cnext.z;
+        sc[ce][cq + 3] = cnext.w;
+        if (sub + 1 < DCB / DCS) cnext = load_cen(c0 + DCS);
+        __syncthreads();
+        if (threadIdx.x < DCS) {
+            float n2 = 0.f;
+#pragma unroll
+            for (int t = 0; t < MP; ++t) n2 = fmaf(sc[threadIdx.x][t], sc[threadIdx.x][t], n2);
+            scn[threadIdx.x] = n2;
+        }
+        // B (16 x 16 chunks): lane holds row lk, column li; result register v
+        // of lane l is query 4 (l / 16) + v and chunk l % 16 of the tile
+        float4_t acc[4] = {};
+#pragma unroll
+        for (int kk = 0; kk < MP / 4; ++kk)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], sc[16 * t + li][4 * kk + lk],
+                                                              acc[t], 0, 0, 0);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int cl = 16 * t + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ql = 16 * wave + 4 * lk + v;
+                const float d2 = fmaxf(fmaf(-2.f, acc[t][v], sqn[ql] + scn[cl]), 0.f);
+                tile[ql][cl] = (uint16_t)(__float_as_uint(d2) >> 16);
+            }
+        }
+        __syncthreads();
+        // four threads per query row, 16 chunks (32 bytes) each; ldc is a
+        // multiple of 16, so a segment that starts below ldc lies inside the row
+        const int ql = threadIdx.x >> 2, seg = (threadIdx.x & 3) * 16;
+        if (ql < nqb && c0 + seg < a.ldc) {
+            const uint4* src = reinterpret_cast<const uint4*>(&tile[ql][seg]);
+            uint4* dst = reinterpret_cast<uint4*>(a.cdist + (int64_t)(q0 + ql) * a.ldc + c0 + seg);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        }
+    }
+}
+
 // float bits >> 19 of 2^-64: the first of the fixed centre-distance bins
 constexpr uint32_t kCenBinBase = 63u << 4;
 // largest LDS footprint of the bound kernel with its row in LDS (two
 // workgroups per compute unit at the most)
 constexpr size_t kTauRowLds = 80 * 1024;
-
-__global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
-    __shared__ float sq[DQB][MP];
-    __shared__ float sn[DQB];
-    const int q0 = blockIdx.y * DQB;
-    const int nqb = min(DQB, a.nq - q0);
-    for (int e = threadIdx.x; e < nqb * MP; e += WG) sq[e / MP][e % MP] = a.qp[(int64_t)q0 * MP + e];
-    __syncthreads();
-    for (int q = threadIdx.x; q < nqb; q += WG) {
-        float n2 = 0.f;
-#pragma unroll
-        for (int t = 0; t < MP; ++t) n2 = fmaf(sq[q][t], sq[q][t], n2);
-        sn[q] = n2;
-    }
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (c >= (a.n_pad16 >> 6)) return;
-    float cen[MP];
-    float cn2 = 0.f;
-#pragma unroll
-    for (int t = 0; t < MP; ++t) {
-        cen[t] = a.chunk_cen[c * MP + t];
-        cn2 = fmaf(cen[t], cen[t], cn2);
-    }
-    uint16_t* out = a.cdist + (int64_t)q0 * a.ldc + c;
-    for (int q = 0; q < nqb; ++q) {
-        float dot = 0.f;
-#pragma unroll
-        for (int t = 0; t < MP; ++t) dot = fmaf(sq[q][t], cen[t], dot);
-        const float d2 = fmaxf(fmaf(-2.f, dot, sn[q] + cn2), 0.f);
-        out[(int64_t)q * a.ldc] = (uint16_t)(__float_as_uint(d2) >> 16);
-    }
-}
 
 // Upper bound tau on the budget-th smallest projected distance of one query,
 // and the query's row of the chunk mask:
@@ -1255,9 +1315,6 @@ __global__ __launch_bounds__(WG) void mask_transpose_kernel(AnnArgs a) {
 // (lane l: query 16 t + l % 16, halves 8 (l / 16) .. + 7); the chunk's four
 // 16-point tiles are the A operands. A result register r of lane l holds
 // point 4 (l / 16) + r of the tile and query l % 16.
-
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int SQB = 1024;               // queries per scan block
 constexpr int SQT = SQB / 16 / NWAVE;   // query tiles per wave
@@ -1763,7 +1820,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         const int64_t nchunk = x.n_pad16 / 64;
         {
             StageTimer tm(PMLSH_STAGE_DIST, stream);
-            dim3 dgrid((unsigned)((nchunk + WG - 1) / WG), (unsigned)((L.nq + DQB - 1) / DQB));
+            dim3 dgrid((unsigned)((nchunk + DCB - 1) / DCB), (unsigned)((L.nq + DQB - 1) / DQB));
             hipLaunchKernelGGL(dist_kernel, dgrid, dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }

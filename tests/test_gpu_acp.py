@@ -5,6 +5,7 @@ and finds candidates by brute force over all pairs, so a pair lost by the
 Mindist tile pruning shows up as a mismatch.
 """
 
+import gc
 import math
 
 import numpy as np
@@ -149,3 +150,31 @@ def test_acp_scale_planted():
         got = pairs.cpu().numpy()
         assert got.tolist() == planted[order[:k]].tolist()
         np.testing.assert_allclose(dist.cpu().numpy(), pd_[order[:k]], rtol=TOL)
+
+
+def test_free_releases_device_memory():
+    """Building, using and freeing an index returns its device memory (the
+    FP16 rows, chunk balls and the ACP buffers kept in the index included)."""
+    pm = _gpu()
+    say("case: build/free cycles")
+    dev = torch.device("cuda", 0)
+    w = synth.planted_pairs(n=100_000, d=256)
+    D = torch.from_numpy(w["D"]).to(dev)
+    A = torch.from_numpy(w["A"]).to(dev)
+    torch.cuda.synchronize()
+
+    def cycle():
+        idx = pm.Index(D, A)
+        idx.acp(5)
+        torch.cuda.synchronize()
+        del idx
+        gc.collect()
+        torch.cuda.synchronize()
+
+    cycle()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(4):
+        cycle()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("free bytes before/after", free0, free1)
+    assert free0 - free1 < 64 << 20
