@@ -6,20 +6,25 @@ batches of 1,024 per launch, k = 10, c = 1.5, confidence 1 - 1/e. Inputs are
 synthetic (seeded) and resident in HBM before timing starts.
 
 Metric: queries/s at recall@10 >= 0.9. The candidate fraction beta is swept
-({5e-4, 6e-4, ..., 1e-3 in steps of 5e-5 to 1e-4, then 1.5e-3, 2e-3, 5e-3}); the smallest beta whose recall@10
-over all 10,000 queries reaches 0.9 is the operating point, and only that
-point is timed. A step is one pmlsh_ann call on one batch (projection, chunk
-distances, bound and Eq. 5 chunk test, range filter on the matrix cores,
-budget selection, exact verification, top-k).
+({5e-4, 6e-4, ..., 1e-3 in steps of 5e-5 to 1e-4, then 1.5e-3, 2e-3,
+5e-3}); the smallest beta whose recall@10 over all 10,000 queries reaches
+0.9 is the operating point, and only that point is timed. A step is one pmlsh_ann call on one batch of 1,024 queries
+(projection, chunk distances, bound and Eq. 5 chunk test, range filter on
+the matrix cores, budget selection, bounded verification, top-k); the calls
+are asynchronous, back to back on one stream (--streams S issues them
+round-robin on S streams instead). The same loop gives the operating points
+for k = 1, 50 and 100 ("other_k").
 
-Also reported: p50/p99 batch latency; per-stage GPU time (HIP events around
-each stage, from the warm-up); the roofline of the dominant stage
-(algorithmic work per launch / its launch time measured with HIP events in
-the timed region, where only that stage is timed: flops against the FP16
-matrix peak for the filter, bytes against 8 TB/s for the HBM-bound stages),
-with the HBM traffic that rocprofv3 counters measured for that kernel when
-profiles/ holds them for the current kernel sources; and the FP64 CPU oracle
-timed on this host on a bounded sample of the same queries.
+Also reported: p50/p99 latency of one batch alone on one stream; per-stage
+GPU time (HIP events around each stage, from the warm-up); the roofline of
+the dominant stage (algorithmic work per launch / its launch time measured
+with HIP events in the timed region, where only that stage of every eighth
+batch is timed: flops
+against the FP16 matrix peak for the filter, bytes against 8 TB/s for the
+HBM-bound stages), with the HBM traffic that rocprofv3 counters measured for
+that kernel when profiles/ holds them for the current kernel sources; the
+FP64 CPU oracle timed on this host on a bounded sample of the same queries;
+(c,k)-ACP time per call on the planted-pair workload for k = 1, 10, 100.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -43,9 +48,11 @@ HBM_PEAK_GBS = 8000.0
 FP16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X published dense FP16 matrix peak
 BETAS = [5e-4, 6e-4, 7e-4, 7.5e-4, 8e-4, 8.5e-4, 9e-4, 9.5e-4, 1e-3, 1.5e-3, 2e-3, 5e-3]
 K = 10
+KS = (1, 10, 50, 100)        # k of the operating points (K is the headline)
 C = 1.5
 CONF = 1 - 1 / math.e
 BATCH = 1024
+PROBE_EVERY = 8              # batches per timed launch of the dominant stage
 PMC_FILE = os.path.join(ROOT, "profiles", "ann_headline_pmc.json")
 CALIB_BYTES = 256 << 20     # copy kernel of known size for counter calibration
 
@@ -112,10 +119,10 @@ def cpu_baseline(w, beta, r_min, budget_s=12.0, max_q=64):
                       f"{dt:.1f} s on one host thread (FP64 NumPy, projection of D precomputed)"}
 
 
-def acp_bench(pm, torch, dev, k=10, c=1.5, calls=3):
+def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
     """(c,k)-ACP on 200,000 x 512 with 2,000 planted near-duplicate pairs:
-    time per call (index built beforehand, data resident in HBM) and whether
-    the k pairs returned are the k closest planted pairs."""
+    time per call for each k (index built beforehand, data resident in HBM)
+    and whether the k pairs returned are the k closest planted pairs."""
     import synth
     w = synth.planted_pairs()
     D = torch.from_numpy(w["D"]).to(dev)
@@ -125,30 +132,34 @@ def acp_bench(pm, torch, dev, k=10, c=1.5, calls=3):
     idx = pm.Index(D, A)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    pairs, dist, st = idx.acp(k, c=c)                     # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(calls):
-        pairs, dist, st = idx.acp(k, c=c)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / calls
     Dn = w["D"].astype(np.float64)
     pl = w["pairs"]
     pd_ = np.sqrt(((Dn[pl[:, 0]] - Dn[pl[:, 1]]) ** 2).sum(1))
     order = np.lexsort((pl[:, 1], pl[:, 0], pd_))
-    correct = pairs.cpu().numpy().tolist() == pl[order[:k]].tolist()
-    log(f"ACP k={k}: {ms:.2f} ms per call, stats {st}, planted pairs found: {correct}")
+    per_k = []
+    for k in ks:
+        pairs, dist, st = idx.acp(k, c=c)                     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            pairs, dist, st = idx.acp(k, c=c)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / calls
+        correct = pairs.cpu().numpy().tolist() == pl[order[:k]].tolist()
+        log(f"ACP k={k}: {ms:.2f} ms per call, stats {st}, planted pairs found: {correct}")
+        per_k.append({"k": k, "ms_per_call": round(ms, 3), "calls": calls,
+                      "k_closest_planted_pairs_returned": bool(correct),
+                      "tiles_scanned": int(st["tiles_scanned"]),
+                      "tiles_total": int(st["tiles_total"]), "candidates": int(st["n_cand"]),
+                      "budget_T": int(st["budget"])})
     return {"workload": "200,000 x 512 Gaussian mixture with 2,000 planted near-duplicate pairs",
-            "k": k, "c": c, "ms_per_call": round(ms, 3), "calls": calls,
-            "build_s": round(build_s, 2), "k_closest_planted_pairs_returned": bool(correct),
-            "tiles_scanned": int(st["tiles_scanned"]), "tiles_total": int(st["tiles_total"]),
-            "candidates": int(st["n_cand"]), "budget_T": int(st["budget"])}
+            "c": c, "build_s": round(build_s, 2), "per_k": per_k}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--beta", type=float, default=None, help="skip the sweep")
     ap.add_argument("--no-cpu", action="store_true")
@@ -158,6 +169,10 @@ def main():
                     help="after timing, run a plain 256 MiB device copy (for counters)")
     ap.add_argument("--no-acp", action="store_true",
                     help="skip the (c,k)-ACP timing at 200,000 x 512")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="HIP streams the batches are issued on, round-robin")
+    ap.add_argument("--no-ksweep", action="store_true",
+                    help="skip the operating points for k = 1, 50, 100")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -190,7 +205,8 @@ def main():
     truth = None
     if not args.no_truth:
         t0 = time.perf_counter()
-        truth = exact_knn_gpu(torch, D, Q, K)
+        truth_all = exact_knn_gpu(torch, D, Q, 10 if args.no_ksweep else max(KS))
+        truth = truth_all[:, :K]
         torch.cuda.synchronize()
         log(f"ground truth in {time.perf_counter() - t0:.1f} s")
 
@@ -243,30 +259,58 @@ def main():
     pm.ann_timing_enable(False)
     warm = pm.ann_timing_read(reset=True)
     dom = max(("dist", "tau", "filter", "finish", "per_query"), key=lambda k: warm[k]["ms"])
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream()
+                                               for _ in range(max(1, args.streams) - 1)]
+
+    def timed(k, beta_k, rmin_k, steps, out_ids, out_dist, out_stats, probe=None):
+        """Wall time of `steps` batches issued round-robin on the streams.
+        With probe = (stage, every), that stage of every `every`-th batch is
+        bracketed by the library's HIP events (events on every batch would
+        hold back the overlap of the streams)."""
+        torch.cuda.synchronize()
+        t_0 = time.perf_counter()
+        nq_done = 0
+        for i in range(steps):
+            s_, e_ = batches[i % len(batches)]
+            on = probe is not None and i % probe[1] == 0
+            if on:
+                pm.ann_timing_enable(True, stages=[probe[0]])
+            with torch.cuda.stream(streams[i % len(streams)]):
+                idx.ann_into(Q[s_:e_], k, C, CONF, beta_k, rmin_k, out_ids[s_:e_],
+                             out_dist[s_:e_], out_stats[s_:e_])
+            if on:
+                pm.ann_timing_enable(False)
+            nq_done += e_ - s_
+        torch.cuda.synchronize()
+        return time.perf_counter() - t_0, nq_done
+
+    # queries of the timed steps; work of the probed ones (the launches whose
+    # dominant stage is timed)
     queries = 0
-    scan_pts = 0.0
-    cand_rows = 0.0
-    torch.cuda.synchronize()
-    pm.ann_timing_read(reset=True)
-    pm.ann_timing_enable(True, stages=[dom])
-    wall0 = time.perf_counter()
+    p_queries, scan_pts, cand_rows = 0, 0.0, 0.0
     for i in range(args.steps):
         b = i % len(batches)
-        s, e = batches[b]
-        ev[i][0].record()
-        idx.ann_into(Q[s:e], K, C, CONF, beta, r_min, ids[s:e], dist[s:e], stats[s:e])
-        ev[i][1].record()
-        queries += e - s
-        scan_pts += batch_scan[b]
-        cand_rows += batch_cand[b]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    pm.ann_timing_enable(False)
+        queries += batches[b][1] - batches[b][0]
+        if i % PROBE_EVERY == 0:
+            p_queries += batches[b][1] - batches[b][0]
+            scan_pts += batch_scan[b]
+            cand_rows += batch_cand[b]
+    pm.ann_timing_read(reset=True)
+    wall, _ = timed(K, beta, r_min, args.steps, ids, dist, stats, probe=(dom, PROBE_EVERY))
     stages = pm.ann_timing_read(reset=True)
-    lat = np.array([a.elapsed_time(b) for a, b in ev])          # ms per batch
     value = queries / wall
+
+    # latency of one batch, alone on one stream (outside the timed region)
+    lat = []
+    for i in range(min(args.steps, 40)):
+        s, e = batches[i % len(batches)]
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        idx.ann_into(Q[s:e], K, C, CONF, beta, r_min, ids[s:e], dist[s:e], stats[s:e])
+        ev1.record()
+        ev1.synchronize()
+        lat.append(ev0.elapsed_time(ev1))
+    lat = np.array(lat)
 
     # roofline of the dominant stage, from its live per-launch duration
     d_pad = (d + 3) // 4 * 4
@@ -281,9 +325,9 @@ def main():
                 "peak": FP16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP16_MFMA_PEAK_TFLOPS, 4)}
     elif dom in ("dist", "tau"):
-        # the chunk-distance row of every query, written and read
+        # the bf16 chunk-distance row of every query, written and read
         ldc = ((n + 63) // 64 + 15) // 16 * 16
-        work = 4.0 * ldc * queries / launches
+        work = 2.0 * ldc * p_queries / launches
         achieved = work / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
@@ -293,7 +337,7 @@ def main():
         # the output
         d16 = (d + 7) // 8 * 8
         work = ((2.0 * d16 + 64.0) * cand_rows
-                + (4.0 * d_pad * K + 4 * d + 12 * K) * queries) / launches
+                + (4.0 * d_pad * K + 4 * d + 12 * K) * p_queries) / launches
         achieved = work / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
@@ -318,6 +362,35 @@ def main():
             y = x.clone()
         torch.cuda.synchronize()
         del x, y
+
+    # operating points for the other k of the workload: smallest beta with
+    # recall@k >= 0.9, then the same timed loop
+    ksweep = []
+    if truth is not None and not args.no_ksweep:
+        for k in KS:
+            if k == K:
+                continue
+            ids_k = torch.empty((nq, k), dtype=torch.int64, device=dev)
+            dist_k = torch.empty((nq, k), dtype=torch.float32, device=dev)
+            b_k, rec_k = None, None
+            for bt in BETAS:
+                for s_, e_ in batches:
+                    idx.ann_into(Q[s_:e_], k, C, CONF, bt, 0.0, ids_k[s_:e_], dist_k[s_:e_],
+                                 stats[s_:e_])
+                torch.cuda.synchronize()
+                rec_k = recall_at_k(ids_k, truth_all[:, :k])
+                if rec_k >= 0.9:
+                    b_k = bt
+                    break
+            if b_k is None:
+                b_k = BETAS[-1]
+            B_k = pm.plan_params(n, A.shape[0], k, C, CONF, b_k)["budget"]
+            rmin_k = idx.default_r_min(B_k)
+            timed(k, b_k, rmin_k, 10, ids_k, dist_k, stats)          # warm-up
+            wall_k, q_k = timed(k, b_k, rmin_k, args.steps, ids_k, dist_k, stats)
+            log(f"k={k}: beta={b_k:g} recall@{k}={rec_k:.4f} {q_k / wall_k:.0f} queries/s")
+            ksweep.append({"k": k, "beta": b_k, "budget_B": B_k, f"recall@{k}": round(rec_k, 4),
+                           "queries_per_s": round(q_k / wall_k, 1)})
 
     cpu = None
     if not args.no_cpu:
@@ -345,12 +418,13 @@ def main():
                                "10,000 queries in batches of 1,024",
                    "k": K, "c": C, "confidence": round(CONF, 6), "m": 15,
                    "beta": beta, "budget_B": B, "r_min": r_min,
-                   "batch": BATCH, "parallelism": "single GPU"},
+                   "batch": BATCH, "streams": len(streams), "parallelism": "single GPU"},
         "recall@10": round(rec, 4) if rec is not None else None,
         "sweep": sweep,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
-                       "per": "batch of up to 1,024 queries"},
+                       "per": "batch of up to 1,024 queries, alone on one stream"},
+        "other_k": ksweep,
         "roofline": roof,
         "stages_ms_per_batch": {k: round(v["ms"] / max(1, v["launches"]), 4)
                                 for k, v in warm.items()},
