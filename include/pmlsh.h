@@ -181,6 +181,78 @@ int pmlsh_acp(const pmlsh_index* index, int32_t k, double c, double confidence,
               double beta, int64_t* out_pairs, float* out_dist,
               pmlsh_acp_stats* stats, void* stream);
 
+/*
+ * Serving loop: continuous batching of (c,k)-ANN requests on a resident
+ * index. Each request is Algorithm 2 (Section 5.2) for its own queries with
+ * its own k, c, confidence and beta, exactly as pmlsh_ann would answer it
+ * alone (results are identical bit for bit).
+ *
+ * A server owns one host worker thread and one HIP stream of the index's
+ * device (default priority). Requests wait in arrival order; the worker
+ * forms each launch from the oldest waiting request and the requests after
+ * it with the same (k, c, confidence, beta, r_min), up to max_batch queries
+ * (a larger request is split over several launches), gathers their queries
+ * into a staging buffer, runs the batched ANN path on it and scatters the
+ * answers to each request's outputs. Up to max_inflight launches are queued
+ * on the stream at once, so requests that arrive while others run on the GPU
+ * are admitted as soon as a launch slot and the HBM budget allow: a launch
+ * is admitted while the staging and workspace bytes of the launches in
+ * flight, its own included, stay within hbm_budget (one launch is always
+ * admitted when none is in flight).
+ *
+ *   max_batch     queries per launch, 1..65535 (0 selects 1024)
+ *   max_inflight  launches queued at once, 1..64 (0 selects 2)
+ *   hbm_budget    bytes, 0 selects 8 GiB
+ * pmlsh_server_create errors: EINVAL, EDEVICE (stream or thread creation).
+ */
+typedef struct pmlsh_server pmlsh_server;
+
+typedef struct {
+    int64_t max_batch;
+    int32_t max_inflight;
+    int64_t hbm_budget;
+} pmlsh_server_args;
+
+int pmlsh_server_create(const pmlsh_index* index, const pmlsh_server_args* args,
+                        pmlsh_server** out);
+
+/* Submits one request: queries nq x d FP32 device pointer, outputs nq x k
+ * int64 ids and FP32 distances (device), arguments as in pmlsh_ann. The
+ * caller keeps the buffers alive and untouched until the request completes.
+ * When `stream` is not NULL, the server waits for the work queued on it so
+ * far before reading the queries; otherwise the queries must already be
+ * complete. Validation happens here (EINVAL / EUNSUPPORTED as pmlsh_ann);
+ * on success *ticket identifies the request (nq = 0 completes at once). */
+int pmlsh_server_submit(pmlsh_server* server, const float* queries, int64_t nq,
+                        int32_t k, double c, double confidence, double beta,
+                        double r_min, int64_t* out_ids, float* out_dist,
+                        void* stream, uint64_t* ticket);
+
+/* *done = 1 when the request has completed (its outputs are written), else
+ * 0. EINVAL for an unknown ticket. */
+int pmlsh_server_test(pmlsh_server* server, uint64_t ticket, int* done);
+
+/* Blocks until the request has completed and releases the ticket. Returns
+ * the request's result: PMLSH_OK, or the error its launch hit. */
+int pmlsh_server_wait(pmlsh_server* server, uint64_t ticket);
+
+/* Counters since creation: requests and queries completed, launches, and
+ * request latency (submission to completion seen by the worker) in ms. */
+typedef struct {
+    int64_t requests;
+    int64_t queries;
+    int64_t launches;
+    double latency_p50_ms;
+    double latency_p99_ms;
+    double latency_max_ms;
+} pmlsh_server_stats;
+
+int pmlsh_server_get_stats(pmlsh_server* server, pmlsh_server_stats* out);
+
+/* Completes every submitted request, stops the worker and frees the server
+ * (its tickets become invalid). */
+void pmlsh_server_destroy(pmlsh_server* server);
+
 /* Shape and size of a built index. Host-only. */
 typedef struct {
     int64_t n;

@@ -15,7 +15,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Index", "PmlshError", "plan_params", "library_path", "load_library",
+__all__ = ["Index", "Server", "PmlshError", "plan_params", "library_path", "load_library",
            "ann_timing_enable", "ann_timing_read"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -62,6 +62,17 @@ class _Info(ctypes.Structure):
                 ("sample_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
+class _ServerArgs(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("queries", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double)]
+
+
 class _Timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
 
@@ -92,6 +103,18 @@ SIGNATURES = {
     "pmlsh_ann_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "pmlsh_ann_timing_read": (ctypes.c_int, [ctypes.POINTER(_Timing), ctypes.c_int]),
     "pmlsh_last_error": (ctypes.c_char_p, []),
+    "pmlsh_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_ServerArgs),
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "pmlsh_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "pmlsh_server_test": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "pmlsh_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "pmlsh_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_ServerStats)]),
+    "pmlsh_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -278,3 +301,74 @@ class Index:
                                         dist.data_ptr(), ctypes.byref(st),
                                         _stream_handle(self.device)))
         return pairs, dist, {f: getattr(st, f) for f, _ in _AcpStats._fields_}
+
+
+class Request:
+    """One submitted request of a Server; holds its tensors until it completes."""
+
+    def __init__(self, server, ticket, queries, ids, dist):
+        self._server, self.ticket = server, ticket
+        self._queries, self.ids, self.dist = queries, ids, dist
+        self._done = False
+
+    def done(self) -> bool:
+        if self._done:
+            return True
+        flag = ctypes.c_int(0)
+        _check(load_library().pmlsh_server_test(self._server._h, self.ticket,
+                                                 ctypes.byref(flag)))
+        return bool(flag.value)
+
+    def wait(self):
+        """Blocks until the answers are written; returns (ids, dist)."""
+        if not self._done:
+            # the GIL is released by ctypes during the call
+            code = load_library().pmlsh_server_wait(self._server._h, self.ticket)
+            self._done = True
+            self._queries = None
+            _check(code)
+        return self.ids, self.dist
+
+
+class Server:
+    """Serving loop over a resident index (continuous batching, see
+    pmlsh_server_create in include/pmlsh.h). submit() may be called from
+    several threads; each request's answer equals Index.ann on its own."""
+
+    def __init__(self, index: "Index", max_batch: int = 1024, max_inflight: int = 2,
+                 hbm_budget: int = 0):
+        self.index = index
+        args = _ServerArgs(max_batch, max_inflight, hbm_budget)
+        self._h = ctypes.c_void_p()
+        _check(load_library().pmlsh_server_create(index._h, ctypes.byref(args),
+                                                  ctypes.byref(self._h)))
+
+    def submit(self, queries, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
+               beta: float = -1.0, r_min: float = 0.0) -> Request:
+        torch = _torch()
+        Q = _require_gpu_f32("queries", queries)
+        if Q.ndim != 2 or Q.shape[1] != self.index.d:
+            raise ValueError(f"queries must be (nq, {self.index.d})")
+        nq = Q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        ticket = ctypes.c_uint64(0)
+        _check(load_library().pmlsh_server_submit(
+            self._h, Q.data_ptr(), nq, k, c, confidence, beta, r_min, ids.data_ptr(),
+            dist.data_ptr(), _stream_handle(Q.device), ctypes.byref(ticket)))
+        return Request(self, ticket.value, Q, ids, dist)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(load_library().pmlsh_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        """Completes every submitted request and stops the server."""
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.pmlsh_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -26,28 +26,62 @@ void clear_error() { g_error.clear(); }
 const char* error_cstr() { return g_error.c_str(); }
 [[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
-template <class F>
-int guarded(F&& fn) {
-    try {
-        fn();
-        return PMLSH_OK;
-    } catch (const Error& e) {
-        set_error(e.msg);
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        set_error("host memory exhausted");
-        return PMLSH_ENOMEM;
-    } catch (const std::exception& e) {
-        set_error(e.what());
-        return PMLSH_EDEVICE;
-    } catch (...) {
-        set_error("unknown error");
-        return PMLSH_EDEVICE;
-    }
-}
-
 // Per-query workspace bytes of the ANN kernel and the batch that fits a cap.
 constexpr int64_t kWorkspaceCap = int64_t(4) << 30;
+
+namespace {
+
+// Workspace layout sizes of one ANN call: per query: projection, FP16 scan
+// row, two frontier lists, C, top-k scratch, and for the batched path three
+// counters, a candidate region and the lower distance bounds of C; plus, for
+// the batched path, the chunk distances, chosen chunks and the chunk x query
+// mask (a 64-bit word per chunk and 64 queries, both layouts).
+struct AnnWorkspace {
+    int64_t B, pool_q, per_query, nchunk, ldc, mwords, batch, bytes;
+    bool fast;
+};
+
+AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
+    AnnWorkspace w{};
+    w.B = B;
+    w.fast = ann_fast_path(B);
+    w.pool_q = w.fast ? ann_pool_per_query(x->n) : 0;
+    w.per_query = (int64_t)MP * 4 + 64 + 2 * x->n_leaves * 4 + B * 8 + 3 * (int64_t)k * 4 +
+                  (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
+    w.nchunk = x->n_pad16 / 64;
+    w.ldc = (w.nchunk + 15) / 16 * 16;
+    w.mwords = 4 * ((w.nchunk + 255) / 256);
+    const int64_t per_query_all =
+        w.per_query + (w.fast ? 8 * w.mwords + 6 * w.ldc + (w.nchunk + 7) / 8 : 0);
+    w.batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
+    w.batch = std::min<int64_t>(w.batch, 65535);
+    const int64_t mask_bytes =
+        w.fast ? w.batch * (8 * w.mwords + 6 * w.ldc) + w.nchunk * ((w.batch + 63) / 64) * 8 : 0;
+    w.bytes = w.batch * w.per_query + mask_bytes;
+    return w;
+}
+
+}  // namespace
+
+void validate_ann(const pmlsh_index* index, const float* queries, int64_t nq, int k,
+                  const int64_t* out_ids, const float* out_dist, double r_min) {
+    if (!index) fail(PMLSH_EINVAL, "index is NULL");
+    if (nq < 0) fail(PMLSH_EINVAL, "nq must be >= 0");
+    if (nq > 0 && (!queries || !out_ids || !out_dist))
+        fail(PMLSH_EINVAL, "queries and outputs must not be NULL");
+    if (k < 1) fail(PMLSH_EINVAL, "k must be >= 1");
+    if (k > index->n) fail(PMLSH_EINVAL, "k must be <= n");
+    if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
+    if (index->d_pad > 8192) fail(PMLSH_EUNSUPPORTED, "ANN supports d <= 8192");
+    if (std::isnan(r_min)) fail(PMLSH_EINVAL, "r_min is NaN");
+}
+
+int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
+                            double confidence, double beta) {
+    pmlsh_plan plan;
+    plan_params(x->n, x->m, k, c, confidence, beta, &plan);
+    return nq > 0 ? ann_workspace(x, nq, k, plan.budget).bytes : 0;
+}
 
 void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
              double confidence, double beta, double r_min, int64_t* out_ids,
@@ -57,26 +91,11 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     if (!(r_min > 0.0)) r_min = index_default_r_min(x, plan.budget);
     if (!std::isfinite(r_min)) fail(PMLSH_EINVAL, "r_min must be finite");
     if (nq == 0) return;
-    const int64_t B = plan.budget;
-    const bool fast = ann_fast_path(B);
-    const int64_t pool_q = fast ? ann_pool_per_query(x->n) : 0;
-    // per query: projection, FP16 scan row, two frontier lists, C, top-k
-    // scratch, and for the batched path three counters, a candidate region and
-    // the lower distance bounds of C
-    const int64_t per_query = (int64_t)MP * 4 + 64 + 2 * x->n_leaves * 4 + B * 8 +
-                              3 * (int64_t)k * 4 + (fast ? 3 * 4 + pool_q * 4 + B * 4 : 0);
-    // plus, for the batched path, the chunk x query mask: a 64-bit word per
-    // chunk and 64 queries
-    const int64_t nchunk = x->n_pad16 / 64;
-    const int64_t ldc = (nchunk + 15) / 16 * 16;
-    const int64_t mwords = 4 * ((nchunk + 255) / 256);
-    const int64_t per_query_all = per_query + (fast ? 8 * mwords + 6 * ldc + (nchunk + 7) / 8 : 0);
-    int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
-    batch = std::min<int64_t>(batch, 65535);
-    const int64_t mask_bytes =
-        fast ? batch * (8 * mwords + 6 * ldc) + nchunk * ((batch + 63) / 64) * 8 : 0;
-    void* ws = nullptr;
-    ws = ws_alloc((size_t)(batch * per_query + mask_bytes), st);
+    const AnnWorkspace w = ann_workspace(x, nq, k, plan.budget);
+    const int64_t B = w.B, pool_q = w.pool_q, nchunk = w.nchunk, ldc = w.ldc,
+                  mwords = w.mwords, batch = w.batch;
+    const bool fast = w.fast;
+    void* ws = ws_alloc((size_t)w.bytes, st);
     char* base = static_cast<char*>(ws);
     // projections and FP16 scan rows first: every row starts on a 64-byte
     // boundary
@@ -179,15 +198,7 @@ int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq, int32_
               double c, double confidence, double beta, double r_min, int64_t* out_ids,
               float* out_dist, int32_t* out_stats, void* stream) {
     return guarded([&] {
-        if (!index) fail(PMLSH_EINVAL, "index is NULL");
-        if (nq < 0) fail(PMLSH_EINVAL, "nq must be >= 0");
-        if (nq > 0 && (!queries || !out_ids || !out_dist))
-            fail(PMLSH_EINVAL, "queries and outputs must not be NULL");
-        if (k < 1) fail(PMLSH_EINVAL, "k must be >= 1");
-        if (k > index->n) fail(PMLSH_EINVAL, "k must be <= n");
-        if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
-        if (index->d_pad > 8192) fail(PMLSH_EUNSUPPORTED, "ANN supports d <= 8192");
-        if (std::isnan(r_min)) fail(PMLSH_EINVAL, "r_min is NaN");
+        validate_ann(index, queries, nq, k, out_ids, out_dist, r_min);
         run_ann(index, queries, nq, k, c, confidence, beta, r_min, out_ids, out_dist,
                 out_stats, static_cast<hipStream_t>(stream));
     });

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
 #include <mutex>
+#include <new>
 #include <string>
 #include <utility>
 #include <vector>
@@ -34,6 +36,27 @@ struct Error {
 // Throws pmlsh::Error; caught at the C boundary.
 [[noreturn]] void fail(int code, const std::string& msg);
 
+// Runs fn and turns any exception into an error code and message.
+template <class F>
+int guarded(F&& fn) {
+    try {
+        fn();
+        return PMLSH_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host memory exhausted");
+        return PMLSH_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return PMLSH_EDEVICE;
+    } catch (...) {
+        set_error("unknown error");
+        return PMLSH_EDEVICE;
+    }
+}
+
 #define PMLSH_HIP(call)                                                          \
     do {                                                                         \
         hipError_t e_ = (call);                                                  \
@@ -47,6 +70,18 @@ struct Error {
 // blocks are kept for reuse by later calls). ws_free never throws.
 void* ws_alloc(size_t bytes, hipStream_t st);
 void ws_free(void* p, hipStream_t st);
+
+// ---------------------------------------------------------------- ANN host path
+// Argument checks of pmlsh_ann (throw EINVAL / EUNSUPPORTED).
+void validate_ann(const pmlsh_index* index, const float* queries, int64_t nq, int k,
+                  const int64_t* out_ids, const float* out_dist, double r_min);
+// Bytes of the device workspace one pmlsh_ann call on nq queries allocates.
+int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
+                            double confidence, double beta);
+// pmlsh_ann after validation: asynchronous on st.
+void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
+             double confidence, double beta, double r_min, int64_t* out_ids,
+             float* out_dist, int32_t* out_stats, hipStream_t st);
 
 // ---------------------------------------------------------------- planner
 double chi2_cdf(double x, int m);

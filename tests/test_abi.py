@@ -147,3 +147,17 @@ def test_timing_stage_mask(lib):
     assert all(v["ms"] == 0 and v["launches"] == 0 for v in t.values())
     pm.ann_timing_enable(True, stages=["finish"])
     pm.ann_timing_enable(False)
+
+
+def test_server_null_handles_rejected(lib):
+    """The serving-loop entry points check their arguments before any HIP call."""
+    t = ctypes.c_uint64(0)
+    done = ctypes.c_int(0)
+    out = ctypes.c_void_p()
+    assert lib.pmlsh_server_create(None, None, ctypes.byref(out)) == pm.EINVAL
+    assert lib.pmlsh_server_submit(None, None, 0, 1, 1.5, 0.9, 0.1, 0.0, None, None, None,
+                                   ctypes.byref(t)) == pm.EINVAL
+    assert lib.pmlsh_server_test(None, 1, ctypes.byref(done)) == pm.EINVAL
+    assert lib.pmlsh_server_wait(None, 1) == pm.EINVAL
+    assert lib.pmlsh_server_get_stats(None, None) == pm.EINVAL
+    lib.pmlsh_server_destroy(None)   # no-op
