@@ -156,6 +156,136 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
             "c": c, "build_s": round(build_s, 2), "per_k": per_k}
 
 
+def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), duration_s=2.0,
+                  beta=1e-4,
+                  conf=1 - 1 / math.e):
+    """Serving loop on a resident 10,000,000 x 128 index: Poisson request
+    streams (sizes log-uniform in 1..4,096, k in {1,10,50,100}, c in
+    {1.2,1.5,2.0}) answered by the continuous-batching server and, for
+    comparison, by one synchronous pmlsh_ann call per request in arrival
+    order (the plain per-batch path). Latency is arrival to completion."""
+    import threading
+    import synth
+    t0 = time.perf_counter()
+    w = synth.serving(n_queries=20_000)
+    D = torch.from_numpy(w["D"]).to(dev)
+    A = torch.from_numpy(w["A"]).to(dev)
+    Q = torch.from_numpy(w["Q"]).to(dev)
+    del w
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    idx = pm.Index(D, A)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t1
+    log(f"serving index built in {build_s:.1f} s ({t1 - t0:.1f} s to draw the data)")
+    nq_all = Q.shape[0]
+
+    def slices(reqs):
+        out, pos = [], 0
+        for (_, size, _, _) in reqs:
+            if pos + size > nq_all:
+                pos = 0
+            out.append((pos, pos + size))
+            pos += size
+        return out
+
+    def pct(v, p):
+        return round(float(np.percentile(np.asarray(v), p)), 3)
+
+    per_rate = []
+    for rate in rates:
+        reqs = synth.requests(int(rate), rate, duration_s)
+        sl = slices(reqs)
+        nq_tot = sum(e - s for s, e in sl)
+        # server
+        srv = pm.Server(idx, max_batch=1024, max_inflight=2)
+        srv.submit(Q[:1024], 10, c=1.5, confidence=conf, beta=beta).wait()    # warm-up
+        srv.close()
+        srv = pm.Server(idx, max_batch=1024, max_inflight=2)
+        handles = [None] * len(reqs)
+        done_t = [0.0] * len(reqs)
+        start = time.perf_counter() + 0.05
+
+        def submitter():
+            for i, (t_arr, _, k, c) in enumerate(reqs):
+                while time.perf_counter() < start + t_arr:
+                    time.sleep(0.0001)
+                s_, e_ = sl[i]
+                handles[i] = srv.submit(Q[s_:e_], k, c=c, confidence=conf, beta=beta)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        for i in range(len(reqs)):
+            while handles[i] is None:
+                time.sleep(0.0001)
+            handles[i].wait()
+            done_t[i] = time.perf_counter()
+        th.join()
+        st = srv.stats()
+        srv.close()
+        lat_srv = [(done_t[i] - (start + reqs[i][0])) * 1e3 for i in range(len(reqs))]
+        wall_srv = max(done_t) - start
+        # plain path: one synchronous call per request, in arrival order
+        lat_pl, t_free = [], 0.0
+        start = time.perf_counter() + 0.05
+        last = start
+        for i, (t_arr, _, k, c) in enumerate(reqs):
+            while time.perf_counter() < start + t_arr:
+                time.sleep(0.0001)
+            s_, e_ = sl[i]
+            idx.ann(Q[s_:e_], k, c=c, confidence=conf, beta=beta)
+            torch.cuda.synchronize()
+            last = time.perf_counter()
+            lat_pl.append((last - (start + t_arr)) * 1e3)
+        wall_pl = last - start
+        row = {"offered_qps": rate, "requests": len(reqs), "queries": nq_tot,
+               "server": {"qps": round(nq_tot / wall_srv, 1), "p50_ms": pct(lat_srv, 50),
+                          "p99_ms": pct(lat_srv, 99), "launches": int(st["launches"])},
+               "plain": {"qps": round(nq_tot / wall_pl, 1), "p50_ms": pct(lat_pl, 50),
+                         "p99_ms": pct(lat_pl, 99)}}
+        log(f"serving at {rate} queries/s offered: {row}")
+        per_rate.append(row)
+    # saturation: every request of the heaviest stream submitted at once
+    reqs = synth.requests(int(rates[-1]) + 1, rates[-1], duration_s)
+    sl = slices(reqs)
+    nq_tot = sum(e - s for s, e in sl)
+    srv = pm.Server(idx, max_batch=1024, max_inflight=2)
+    torch.cuda.synchronize()
+    t_0 = time.perf_counter()
+    hs = [srv.submit(Q[s_:e_], k, c=c, confidence=conf, beta=beta)
+          for (s_, e_), (_, _, k, c) in zip(sl, reqs)]
+    for h in hs:
+        h.wait()
+    sat_srv = nq_tot / (time.perf_counter() - t_0)
+    srv.close()
+    torch.cuda.synchronize()
+    t_0 = time.perf_counter()
+    for (s_, e_), (_, _, k, c) in zip(sl, reqs):
+        idx.ann(Q[s_:e_], k, c=c, confidence=conf, beta=beta)
+    torch.cuda.synchronize()
+    sat_pl = nq_tot / (time.perf_counter() - t_0)
+    log(f"saturation: server {sat_srv:.0f} queries/s, plain {sat_pl:.0f} queries/s")
+    # recall@k of the server's answers on a sample of the heaviest stream
+    rec = []
+    Dd = D.double()
+    for i in range(0, len(hs), max(1, len(hs) // 16)):
+        ids, _ = hs[i].wait()
+        s_, e_ = sl[i]
+        k = reqs[i][2]
+        for j in range(0, e_ - s_, max(1, (e_ - s_) // 4)):
+            q = Q[s_ + j].double()
+            d2 = ((Dd - q) ** 2).sum(1)
+            true = set(torch.topk(d2, k, largest=False).indices.tolist())
+            rec.append(len(true & set(ids[j].tolist())) / k)
+    del Dd
+    return {"workload": "10,000,000 x 128 FP16 values in [0, 255], 10,000 centres, sigma 8; "
+                        "Poisson requests of 1..4,096 queries, k in {1,10,50,100}, "
+                        "c in {1.2,1.5,2.0}",
+            "beta": beta, "build_s": round(build_s, 1), "per_rate": per_rate,
+            "saturation_qps": {"server": round(sat_srv, 1), "plain": round(sat_pl, 1)},
+            "recall_sampled": round(float(np.mean(rec)), 4), "recall_samples": len(rec)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +301,8 @@ def main():
                     help="skip the (c,k)-ACP timing at 200,000 x 512")
     ap.add_argument("--streams", type=int, default=1,
                     help="HIP streams the batches are issued on, round-robin")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-loop run on the 10,000,000 x 128 index")
     ap.add_argument("--no-ksweep", action="store_true",
                     help="skip the operating points for k = 1, 50, 100")
     args = ap.parse_args()
@@ -396,10 +528,15 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(w, beta, r_min)
     acp = None
-    if not args.no_acp:
+    serving = None
+    if not (args.no_acp and args.no_serving):
         del idx
         torch.cuda.empty_cache()
+    if not args.no_acp:
         acp = acp_bench(pm, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        serving = serving_bench(pm, torch, dev)
 
     out = {
         "metric": "c-ANN queries/s at recall@10>=0.9 (1M x 256)",
@@ -431,6 +568,7 @@ def main():
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
         "acp": acp,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -37,6 +37,7 @@ constexpr int WG = 256;
 constexpr int NWAVE = WG / 64;
 constexpr int NB = 2048;    // histogram bins of one radix-select step
 constexpr int CAP = 2048;   // keys sorted in LDS at once (power of two)
+static_assert(kSelCap * 64 >= 2 * CAP + 64, "the chosen-chunk list must hold 2 * budget points");
 constexpr int MAX_LEVELS = 16;
 constexpr int MAX_ROUNDS = 1000;
 constexpr int64_t kScanBlocks = 1024;   // scan workgroups if the occupancy query fails
@@ -102,7 +103,7 @@ struct AnnArgs {
     // ldc), as bf16 bit patterns rounded toward zero (lower bounds)
     uint16_t* cdist;
     int64_t ldc;
-    int32_t* csel;              // per query: the chunks chosen for its bound (ldc)
+    int32_t* csel;              // per query: the chunks chosen for its bound (kSelCap)
     // bounded verification: FP16 rows (stride d16), their scales and error
     // bounds, and per C member a lower bound of its squared distance (the
     // upper bound goes to ws_cdist; equal bounds mean the exact value)
@@ -793,13 +794,28 @@ __device__ void write_topk(const AnnArgs& a, int64_t qi, const int32_t* cpos, co
     }
 }
 
+__device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, float* qs,
+                        Smem& sh);
+
 __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
     float* qs = reinterpret_cast<float*>(smem_raw + ((sizeof(Smem) + 15) & ~size_t(15)));
 
-    const int64_t qi = blockIdx.x;
-    if (a.q_flag && a.q_flag[qi] == 0) return;   // answered by the leaf-major path
+    // workgroup b answers queries b, b + G, b + 2G, ... with the frontier
+    // lists of slot b (G = gridDim.x slots)
+    int32_t* fa = a.ws_front + (int64_t)blockIdx.x * 2 * a.n_leaves;
+    int32_t* fb = fa + a.n_leaves;
+    for (int64_t qi = blockIdx.x; qi < a.nq; qi += gridDim.x) {
+        if (a.q_flag && a.q_flag[qi] == 0) continue;   // answered by the leaf-major path
+        __syncthreads();
+        ann_one(a, qi, fa, fb, qs, sh);
+    }
+}
+
+// Algorithm 2 for query qi, round by round with PM-tree walks.
+__device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, float* qs,
+                        Smem& sh) {
     QueryCtx qc;
     load_query(a, qi, qs, qc);
     const float* qp = qc.qp;
@@ -807,8 +823,6 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
     const float qn2 = qc.qn2;
     __syncthreads();
 
-    int32_t* fa = a.ws_front + qi * 2 * a.n_leaves;
-    int32_t* fb = fa + a.n_leaves;
     int32_t* cpos = a.ws_cpos + qi * (int64_t)a.budget;
     float* cdist = a.ws_cdist + qi * (int64_t)a.budget;
     const int32_t* perm = a.perm;
@@ -1072,7 +1086,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         __syncthreads();
     }
     const uint2* row4 = LROW ? lrow : grow;
-    int32_t* sel = a.csel + qi * a.ldc;
+    int32_t* sel = a.csel + qi * kSelCap;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     // bf16 bit pattern k of an element (non-negative values: ordered as
     // unsigned integers)
@@ -1103,7 +1117,8 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     __syncthreads();
     find_threshold(wc, sh);
     const uint32_t tbin = (uint32_t)sh.thr_bin;
-    const int need = wc - sh.thr_below;   // chunks still wanted from bin tbin
+    const int nlow = sh.thr_below;         // chunks of the bins below tbin (< wc)
+    const int need = wc - nlow;           // chunks still wanted from bin tbin
     const int in_bin = sh.thr_in;
     // every chunk with a stored value <= tlim is chosen: all of bin tbin, or,
     // when that bin holds more than eight chunks beyond those wanted, only
@@ -1130,7 +1145,12 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     if (threadIdx.x == 0) sh.cnt1 = 0;
     __syncthreads();
 
-    // 2: the chosen chunks, and the largest distance bound over their points
+    // 2: the chosen chunks, and the largest distance bound over their points.
+    // The list holds kSelCap chunks: those of the bins below tbin (fewer than
+    // wc) come first, then as many of bin tbin's as fit; any kSelCap chunks
+    // hold at least 64 kSelCap >= 2 * budget points, so the bound stays valid
+    if (threadIdx.x == 0) sh.cnt2 = 0;
+    __syncthreads();
     float rmax = 0.f;
     for (int g = threadIdx.x; g < ng4; g += WG) {
         const uint2 v = row4[g];
@@ -1142,10 +1162,15 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             for (int k = 0; k < 4; ++k) {
                 if (tk[k]) {
                     const int i = 4 * g + k;
-                    // the stored distance is low by less than a factor 1 + 2^-7
-                    const float d = sqrtf(__uint_as_float(half_k(v, k) << 16)) * 1.0079f;
-                    rmax = fmaxf(rmax, d + a.chunk_rad[i]);
-                    sel[atomicAdd(&sh.cnt1, 1)] = i;
+                    const uint32_t h = half_k(v, k);
+                    const int slot = cbin(h) < tbin ? atomicAdd(&sh.cnt1, 1)
+                                                    : nlow + atomicAdd(&sh.cnt2, 1);
+                    if (slot < kSelCap) {
+                        // the stored distance is low by less than a factor 1 + 2^-7
+                        const float d = sqrtf(__uint_as_float(h << 16)) * 1.0079f;
+                        rmax = fmaxf(rmax, d + a.chunk_rad[i]);
+                        sel[slot] = i;
+                    }
                 }
             }
         }
@@ -1153,7 +1178,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     for (int off = 32; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
     if (lane == 0) sh.red[wave] = __float_as_int(rmax);
     __syncthreads();
-    const int nsel = sh.cnt1;
+    const int nsel = min(nlow + sh.cnt2, kSelCap);
     float R = 0.f;
 #pragma unroll
     for (int w = 0; w < NWAVE; ++w) R = fmaxf(R, __int_as_float(sh.red[w]));
@@ -1875,7 +1900,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     // per-query path: every query when the fast path does not apply, else only
     // the queries the fast path flagged
     StageTimer tm(PMLSH_STAGE_PERQUERY, stream);
-    hipLaunchKernelGGL(ann_kernel, dim3((unsigned)L.nq), dim3(WG), lds, stream, a);
+    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(L.front_slots, L.nq));
+    hipLaunchKernelGGL(ann_kernel, dim3((unsigned)slots), dim3(WG), lds, stream, a);
     PMLSH_HIP(hipGetLastError());
 }
 

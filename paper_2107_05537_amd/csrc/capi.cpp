@@ -32,32 +32,47 @@ constexpr int64_t kWorkspaceCap = int64_t(4) << 30;
 namespace {
 
 // Workspace layout sizes of one ANN call: per query: projection, FP16 scan
-// row, two frontier lists, C, top-k scratch, and for the batched path three
-// counters, a candidate region and the lower distance bounds of C; plus, for
-// the batched path, the chunk distances, chosen chunks and the chunk x query
-// mask (a 64-bit word per chunk and 64 queries, both layouts).
+// row, C, top-k scratch, and for the batched path three counters, a
+// candidate region and the lower distance bounds of C; plus, for the batched
+// path, the chunk distances, chosen chunks and the chunk x query mask (a
+// 64-bit word per chunk and 64 queries, both layouts); plus the frontier
+// lists of the per-query kernel's workgroups.
 struct AnnWorkspace {
-    int64_t B, pool_q, per_query, nchunk, ldc, mwords, batch, bytes;
+    int64_t B, pool_q, per_query, nchunk, ldc, mwords, batch, slots, bytes;
     bool fast;
 };
+
+// Workgroups of the per-query kernel, each with its own pair of frontier
+// lists: few on the batched path (only the queries it hands over), more
+// when every query takes the per-query path.
+int64_t front_slots(const pmlsh_index* x, bool fast, int64_t batch) {
+    const int64_t by_memory = std::max<int64_t>(1, (int64_t(1) << 30) / (8 * x->n_leaves));
+    return std::min<int64_t>({batch, fast ? 256 : 2048, by_memory});
+}
 
 AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
     AnnWorkspace w{};
     w.B = B;
     w.fast = ann_fast_path(B);
     w.pool_q = w.fast ? ann_pool_per_query(x->n) : 0;
-    w.per_query = (int64_t)MP * 4 + 64 + 2 * x->n_leaves * 4 + B * 8 + 3 * (int64_t)k * 4 +
+    w.per_query = (int64_t)MP * 4 + 64 + B * 8 + 3 * (int64_t)k * 4 +
                   (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
     w.ldc = (w.nchunk + 15) / 16 * 16;
     w.mwords = 4 * ((w.nchunk + 255) / 256);
     const int64_t per_query_all =
-        w.per_query + (w.fast ? 8 * w.mwords + 6 * w.ldc + (w.nchunk + 7) / 8 : 0);
+        w.per_query + (w.fast ? 8 * w.mwords + 2 * w.ldc + 4 * kSelCap + (w.nchunk + 7) / 8 : 0);
     w.batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     w.batch = std::min<int64_t>(w.batch, 65535);
     const int64_t mask_bytes =
-        w.fast ? w.batch * (8 * w.mwords + 6 * w.ldc) + w.nchunk * ((w.batch + 63) / 64) * 8 : 0;
-    w.bytes = w.batch * w.per_query + mask_bytes;
+        w.fast ? w.batch * (8 * w.mwords + 2 * w.ldc + 4 * kSelCap) + w.nchunk * ((w.batch + 63) / 64) * 8
+               : 0;
+    w.slots = front_slots(x, w.fast, w.batch);
+    w.bytes = w.batch * w.per_query + mask_bytes + w.slots * 2 * x->n_leaves * 4;
+    // sizes rounded up (to 1 MiB, or 64 MiB above 256 MiB) so that calls of
+    // different batch sizes reuse the same pool blocks
+    const int64_t q = w.bytes > (int64_t(256) << 20) ? int64_t(64) << 20 : int64_t(1) << 20;
+    w.bytes = (w.bytes + q - 1) / q * q;
     return w;
 }
 
@@ -103,11 +118,11 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
     uint16_t* cdist2 = qaug + batch * 32;
     int32_t* csel = reinterpret_cast<int32_t*>(cdist2 + (fast ? batch * ldc : 0));
-    uint64_t* qmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * ldc : 0));
+    uint64_t* qmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * kSelCap : 0));
     uint64_t* cmask = qmask + (fast ? batch * mwords : 0);
     uint32_t* list = reinterpret_cast<uint32_t*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
-    int32_t* cpos = front + batch * 2 * x->n_leaves;
+    int32_t* cpos = front + w.slots * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);
     int32_t* topk = reinterpret_cast<int32_t*>(cdist + batch * B);
     float* clo = reinterpret_cast<float*>(topk + batch * 3 * (int64_t)k);
@@ -133,6 +148,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             L.r_min = r_min;
             L.budget = B;
             L.ws_front = front;
+            L.front_slots = std::min<int64_t>(w.slots, nb);
             L.ws_cpos = cpos;
             L.ws_cdist = cdist;
             L.ws_topk = topk;

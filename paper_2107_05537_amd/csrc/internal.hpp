@@ -22,6 +22,9 @@ constexpr int MP = 16;
 // scan: 2^-9 bounds the FP16 rounding of the projected dot product, the extra
 // 2^-14 absorbs the rounding of the margin term itself.
 constexpr float kScanMarginWeight = 0.001953125f + 0.00006103515625f;
+// Chunks the ANN bound may choose per query (64 points each; at least twice
+// the largest budget of the batched path).
+constexpr int kSelCap = 1024;
 
 // Thread-local error message returned by pmlsh_last_error().
 void set_error(const std::string& msg);
@@ -212,7 +215,8 @@ struct AnnLaunch {
     int k;
     double c, t, r_min;
     int64_t budget;
-    int32_t* ws_front;      // nq x 2 x n_leaves
+    int32_t* ws_front;      // front_slots x 2 x n_leaves: frontier lists of the tree walk
+    int64_t front_slots;    // workgroups of the per-query kernel (one frontier pair each)
     int32_t* ws_cpos;       // nq x budget
     float* ws_cdist;        // nq x budget
     float* ws_clo;          // nq x budget: lower bounds of the verified distances

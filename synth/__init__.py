@@ -20,6 +20,8 @@ these mixtures stand in for them by shape only:
   * ``acp``      - 200,000 x 512, 500 centres N(0, var 4), sigma
     U[0.2, 0.5]; 198,000 originals plus 2,000 copies of distinct originals
     perturbed by N(0, 1e-3^2) (a 1 % planted near-duplicate fraction).
+  * ``serving``  - 10,000,000 x 128 FP16 values in [0, 255], 10,000 centres
+    uniform in the cube, sigma 8; plus Poisson request streams.
 """
 
 from __future__ import annotations
@@ -52,7 +54,7 @@ SPECS = {
                             sigma_lo=0.2, sigma_hi=0.5, n_queries=10_000),
 }
 
-SEEDS = {"parity": 20210712, "headline": 20210713, "acp": 20210714}
+SEEDS = {"parity": 20210712, "headline": 20210713, "acp": 20210714, "serving": 20210715}
 
 
 def _draw_points(rng, labels, centres, sigmas, d):
@@ -150,3 +152,47 @@ def uniform_cube(seed: int, n: int, d: int, n_queries: int, m: int = M_DEFAULT,
     Q = rng.uniform(lo, hi, size=(n_queries, d)).astype(np.float32)
     A = hash_matrix(rng, m, d)
     return {"D": D, "Q": Q, "A": A}
+
+
+def serving(seed: int = SEEDS["serving"], n: int = 10_000_000, d: int = 128,
+            n_centres: int = 10_000, sigma: float = 8.0, n_queries: int = 20_000,
+            m: int = M_DEFAULT):
+    """Serving workload: a resident index of FP16-valued points in [0, 255].
+
+    Centres uniform in [0, 255]^d; each point is a centre plus N(0, sigma^2)
+    noise, clipped to [0, 255] and rounded to the nearest FP16 value (held as
+    float32); queries drawn the same way. The request stream is drawn
+    separately (``requests``).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = rng.uniform(0.0, 255.0, size=(n_centres, d)).astype(np.float32)
+    sig = np.full(n_centres, sigma, dtype=np.float32)
+
+    def draw(count):
+        lab = rng.integers(0, n_centres, size=count)
+        X = _draw_points(rng, lab, centres, sig, d)
+        np.clip(X, 0.0, 255.0, out=X)
+        return X.astype(np.float16).astype(np.float32)
+
+    D = draw(n)
+    Q = draw(n_queries)
+    A = hash_matrix(rng, m, d)
+    return {"D": D, "Q": Q, "A": A}
+
+
+def requests(seed: int, rate_qps: float, duration_s: float, max_batch: int = 4096,
+             ks=(1, 10, 50, 100), cs=(1.2, 1.5, 2.0)):
+    """A Poisson stream of requests: arrival times (s), batch sizes
+    (log-uniform in [1, max_batch]), k and c drawn uniformly from ks and cs.
+    The request rate is rate_qps divided by the mean batch size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mean_b = (max_batch - 1) / np.log(max_batch)     # mean of the log-uniform size
+    lam = rate_qps / mean_b
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / lam)
+        if t >= duration_s:
+            break
+        size = int(min(max_batch, max(1, np.floor(np.exp(rng.uniform(0.0, np.log(max_batch + 1)))))))
+        out.append((t, size, int(rng.choice(ks)), float(rng.choice(cs))))
+    return out
