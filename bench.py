@@ -157,8 +157,7 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
 
 
 def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), duration_s=2.0,
-                  beta=1e-4,
-                  conf=1 - 1 / math.e):
+                  beta=1e-4, conf=1 - 1 / math.e):
     """Serving loop on a resident 10,000,000 x 128 index: Poisson request
     streams (sizes log-uniform in 1..4,096, k in {1,10,50,100}, c in
     {1.2,1.5,2.0}) answered by the continuous-batching server and, for
