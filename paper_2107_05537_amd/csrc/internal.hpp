@@ -69,8 +69,10 @@ int guarded(F&& fn) {
     } while (0)
 
 // ---------------------------------------------------------------- workspace
-// Stream-ordered device memory from the library's per-device pool (freed
-// blocks are kept for reuse by later calls). ws_free never throws.
+// Device memory from the library's per-device caching allocator: a released
+// block is reused at once on the stream it was released on, and on other
+// streams once the work queued before its release has completed. ws_free
+// never throws.
 void* ws_alloc(size_t bytes, hipStream_t st);
 void ws_free(void* p, hipStream_t st);
 

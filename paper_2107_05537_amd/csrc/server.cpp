@@ -409,7 +409,10 @@ void pmlsh_server_destroy(pmlsh_server* server) {
     }
     server->cv_work.notify_all();
     if (server->worker.joinable()) server->worker.join();
-    if (server->stream) (void)hipStreamDestroy(server->stream);
+    if (server->stream) {
+        (void)hipStreamSynchronize(server->stream);
+        (void)hipStreamDestroy(server->stream);
+    }
     delete server;
 }
 
