@@ -150,6 +150,26 @@ int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq,
               void* stream);
 
 /*
+ * (r,c)-BC (ball cover) query, Algorithm 1 (Section 5.1), for a batch of
+ * queries: one range query of radius t*r around q' with the budget
+ * B = beta*n + 1 (the same reading of the budget as pmlsh_ann: when the ball
+ * holds at least B points, C is the B of them nearest to q' in the projected
+ * space, ties by id; otherwise C is the ball). The answer is the point of C
+ * nearest to q (ties by id) when the ball reached B points, or when that
+ * point lies within c*r of q; otherwise nothing.
+ *   queries   nq x d FP32 device pointer; r > 0 finite; c, confidence,
+ *             beta as in pmlsh_plan_params (k = 1).
+ *   out_ids   nq int64 device pointer: the point's id, or -1 for nothing.
+ *   out_dist  nq FP32 device pointer: its Euclidean distance, or +inf.
+ *   out_stats optional nq x 4 int32 device pointer, as for pmlsh_ann (1
+ *             range query; exit kind PMLSH_EXIT_BUDGET or 0).
+ * Asynchronous on `stream`. Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int pmlsh_bc(const pmlsh_index* index, const float* queries, int64_t nq, double r,
+             double c, double confidence, double beta, int64_t* out_ids,
+             float* out_dist, int32_t* out_stats, void* stream);
+
+/*
  * (c,k)-ACP by radius filtering (Section 6.3, Algorithm 4), canonical form.
  *   1. every pair inside one leaf is verified; ub = the k-th smallest such
  *      distance (+inf if fewer than k pairs);

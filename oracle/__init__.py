@@ -11,6 +11,7 @@ Modules
            Lemma 3 and Eq. 10 (t, alpha2, beta, budgets)
   rmin     the r_min rule of Section 5.2 (distance-distribution quantile)
   ann      (c,k)-ANN, Algorithm 2, one query at a time
+  bc       (r,c)-BC, Algorithm 1, one query at a time
   acp      (c,k)-ACP by radius filtering (Section 6.3), canonical form
   brute    exact kNN and exact k closest pairs, straight from Defs. 1-4
   metrics  overall ratio and recall, Eqs. 12-14

@@ -94,6 +94,10 @@ SIGNATURES = {
                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pmlsh_bc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p]),
     "pmlsh_acp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.POINTER(_AcpStats), ctypes.c_void_p]),
@@ -289,6 +293,26 @@ class Index:
             self._h, queries.data_ptr(), queries.shape[0], k, c, confidence, beta, r_min,
             ids.data_ptr(), dist.data_ptr(), stats.data_ptr() if stats is not None else None,
             _stream_handle(queries.device)))
+
+    def bc(self, queries, r: float, c: float = 1.5, confidence: float = 1 - 1 / math.e,
+           beta: float = -1.0, stats: bool = False):
+        """(r,c)-BC query (Algorithm 1) for every row of `queries`.
+
+        Returns (ids int64 (nq,), dist float32 (nq,)): the point found, or -1
+        and +inf for nothing; with stats=True also the int32 (nq, 4) stats.
+        Enqueued on the current stream."""
+        torch = _torch()
+        Q = _require_gpu_f32("queries", queries)
+        if Q.ndim != 2 or Q.shape[1] != self.d:
+            raise ValueError(f"queries must be (nq, {self.d})")
+        nq = Q.shape[0]
+        ids = torch.empty((nq,), dtype=torch.int64, device=Q.device)
+        dist = torch.empty((nq,), dtype=torch.float32, device=Q.device)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=Q.device) if stats else None
+        _check(load_library().pmlsh_bc(
+            self._h, Q.data_ptr(), nq, r, c, confidence, beta, ids.data_ptr(), dist.data_ptr(),
+            st.data_ptr() if st is not None else None, _stream_handle(Q.device)))
+        return (ids, dist, st) if stats else (ids, dist)
 
     def acp(self, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
             beta: float = -1.0):

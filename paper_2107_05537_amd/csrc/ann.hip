@@ -69,6 +69,7 @@ struct AnnArgs {
     int k;
     int32_t budget;
     double c, t, r_min;
+    int max_rounds;             // range queries per query at most ((r,c)-BC: 1)
     int32_t* ws_front;
     int32_t* ws_cpos;
     float* ws_cdist;
@@ -919,6 +920,7 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
         __syncthreads();
         prev_hi = hi_hi;
         first = false;
+        if (rounds >= a.max_rounds) break;
         r = a.c * r;
     }
 
@@ -1687,6 +1689,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         prev_bits = r2bits;
         __syncthreads();
         if (nb == B) { exit_kind = PMLSH_EXIT_BUDGET; break; }
+        if (rounds >= a.max_rounds) break;
         r = a.c * r;
     }
 
@@ -1768,6 +1771,35 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
 
 int64_t ann_pool_per_query(int64_t n) { return n < 16384 ? n : 16384; }
 
+namespace {
+
+// (r,c)-BC answer from one round of Algorithm 2 with k = 1 (Algorithm 1):
+// when the ball fell short of the budget, the nearest candidate is the
+// answer only if it lies within c r; otherwise (and for an empty ball) the
+// answer is "nothing", id -1 and distance +inf.
+__global__ __launch_bounds__(WG) void bc_finalize_kernel(int64_t* ids, float* dist,
+                                                         const int32_t* stats, int64_t nq,
+                                                         float cr) {
+    const int64_t q = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (q >= nq) return;
+    const int32_t n_cand = stats[q * 4 + 1], exit_kind = stats[q * 4 + 2];
+    if (exit_kind == PMLSH_EXIT_BUDGET) return;
+    if (n_cand == 0 || !(dist[q] <= cr)) {
+        ids[q] = -1;
+        dist[q] = __int_as_float(0x7f800000);
+    }
+}
+
+}  // namespace
+
+void launch_bc_finalize(int64_t* ids, float* dist, const int32_t* stats, int64_t nq, float cr,
+                        hipStream_t stream) {
+    if (nq <= 0) return;
+    hipLaunchKernelGGL(bc_finalize_kernel, dim3((unsigned)((nq + WG - 1) / WG)), dim3(WG), 0,
+                       stream, ids, dist, stats, nq, cr);
+    PMLSH_HIP(hipGetLastError());
+}
+
 bool ann_fast_path(int64_t budget) { return budget <= CAP; }
 
 int ann_lds_bytes(int d_pad) {
@@ -1805,6 +1837,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.c = L.c;
     a.t = L.t;
     a.r_min = L.r_min;
+    a.max_rounds = L.max_rounds > 0 ? L.max_rounds : 0x7fffffff;
     a.ws_front = L.ws_front;
     a.ws_cpos = L.ws_cpos;
     a.ws_cdist = L.ws_cdist;

@@ -100,7 +100,7 @@ int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
 
 void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
              double confidence, double beta, double r_min, int64_t* out_ids,
-             float* out_dist, int32_t* out_stats, hipStream_t st) {
+             float* out_dist, int32_t* out_stats, hipStream_t st, int max_rounds) {
     pmlsh_plan plan;
     plan_params(x->n, x->m, k, c, confidence, beta, &plan);
     if (!(r_min > 0.0)) r_min = index_default_r_min(x, plan.budget);
@@ -146,6 +146,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             L.c = c;
             L.t = plan.t;
             L.r_min = r_min;
+            L.max_rounds = max_rounds;
             L.budget = B;
             L.ws_front = front;
             L.front_slots = std::min<int64_t>(w.slots, nb);
@@ -217,6 +218,33 @@ int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq, int32_
         validate_ann(index, queries, nq, k, out_ids, out_dist, r_min);
         run_ann(index, queries, nq, k, c, confidence, beta, r_min, out_ids, out_dist,
                 out_stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_bc(const pmlsh_index* index, const float* queries, int64_t nq, double r, double c,
+             double confidence, double beta, int64_t* out_ids, float* out_dist,
+             int32_t* out_stats, void* stream) {
+    return guarded([&] {
+        validate_ann(index, queries, nq, 1, out_ids, out_dist, r);
+        if (!(r > 0.0) || !std::isfinite(r)) fail(PMLSH_EINVAL, "r must be positive and finite");
+        pmlsh_plan plan;
+        plan_params(index->n, index->m, 1, c, confidence, beta, &plan);
+        if (nq == 0) return;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        int32_t* stats = out_stats;
+        void* tmp = nullptr;
+        if (!stats) {
+            tmp = ws_alloc((size_t)nq * 4 * sizeof(int32_t), st);
+            stats = static_cast<int32_t*>(tmp);
+        }
+        try {
+            run_ann(index, queries, nq, 1, c, confidence, beta, r, out_ids, out_dist, stats, st, 1);
+            launch_bc_finalize(out_ids, out_dist, stats, nq, (float)(c * r), st);
+        } catch (...) {
+            ws_free(tmp, st);
+            throw;
+        }
+        ws_free(tmp, st);
     });
 }
 

@@ -83,10 +83,14 @@ void validate_ann(const pmlsh_index* index, const float* queries, int64_t nq, in
 // Bytes of the device workspace one pmlsh_ann call on nq queries allocates.
 int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
                             double confidence, double beta);
-// pmlsh_ann after validation: asynchronous on st.
+// pmlsh_ann after validation: asynchronous on st. max_rounds > 0 stops
+// Algorithm 2 after that many range queries.
 void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
              double confidence, double beta, double r_min, int64_t* out_ids,
-             float* out_dist, int32_t* out_stats, hipStream_t st);
+             float* out_dist, int32_t* out_stats, hipStream_t st, int max_rounds = 0);
+// (r,c)-BC answers from the per-query stats of one round with k = 1.
+void launch_bc_finalize(int64_t* ids, float* dist, const int32_t* stats, int64_t nq, float cr,
+                        hipStream_t stream);
 
 // ---------------------------------------------------------------- planner
 double chi2_cdf(double x, int m);
@@ -216,6 +220,7 @@ struct AnnLaunch {
     int64_t nq;
     int k;
     double c, t, r_min;
+    int max_rounds;         // range queries per query at most (0: no limit)
     int64_t budget;
     int32_t* ws_front;      // front_slots x 2 x n_leaves: frontier lists of the tree walk
     int64_t front_slots;    // workgroups of the per-query kernel (one frontier pair each)
