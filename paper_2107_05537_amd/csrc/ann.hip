@@ -1083,8 +1083,24 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     // four bf16 distances per 8-byte element (element g: chunks 4 g .. 4 g + 3)
     const uint2* grow = reinterpret_cast<const uint2*>(a.cdist + qi * a.ldc);
     uint2* lrow = reinterpret_cast<uint2*>(smem_raw + offsetof(Smem, skey));
+    // each thread's smallest stored value (bf16 patterns of non-negative
+    // values order as unsigned integers), taken while the row is copied to
+    // LDS (a row read from HBM in every pass skips this bound: an extra pass
+    // costs more there than the atomics it saves)
+    uint32_t tmin = 0xffffu;
+    auto min4 = [](const uint2& v) {
+        return min(min(v.x & 0xffffu, v.x >> 16), min(v.y & 0xffffu, v.y >> 16));
+    };
     if (LROW) {
-        for (int g = threadIdx.x; g < ng4; g += WG) lrow[g] = grow[g];
+        for (int g = threadIdx.x; g < ng4; g += WG) {
+            const uint2 v = grow[g];
+            lrow[g] = v;
+            if (4 * g + 3 < nch) tmin = min(tmin, min4(v));
+            else
+                for (int k = 0; 4 * g + k < nch; ++k)
+                    tmin = min(tmin, (k & 1) ? ((k < 2 ? v.x : v.y) >> 16)
+                                             : ((k < 2 ? v.x : v.y) & 0xffffu));
+        }
         __syncthreads();
     }
     const uint2* row4 = LROW ? lrow : grow;
@@ -1103,18 +1119,35 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     // bins up to the one where the running count reaches wc = min(n_chunks,
     // ceil(want / 64) + 1) chunks, want = min(n, 2 * budget) points (the
     // extra chunk covers the one chunk with fewer than 64 points).
+    // Only the low end of the histogram matters: with b0 the bin where the
+    // running count of the threads' minima reaches wc, at least wc chunks
+    // lie in bins <= b0, so the bin sought is <= b0 and only those chunks
+    // need to be counted (most of the row lies far above).
     const uint32_t hbase = kCenBinBase;
     auto cbin = [&](uint32_t h) { return min(max(h >> 3, hbase) - hbase, (uint32_t)(NB - 1)); };
+    const int64_t want = a.n < 2 * (int64_t)a.budget ? a.n : 2 * (int64_t)a.budget;
+    const int wc = (int)min<int64_t>(nch, (want + 63) / 64 + 1);
+    uint32_t b0 = NB - 1;
+    if (LROW && min(ng4, WG) >= wc) {
+        clear_hist(sh);
+        if (threadIdx.x < ng4) atomicAdd(&sh.hist[cbin(tmin)], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) sh.thr_bin = NB - 1;
+        __syncthreads();
+        find_threshold(wc, sh);
+        b0 = (uint32_t)sh.thr_bin;
+        __syncthreads();
+    }
     clear_hist(sh);
     for (int g = threadIdx.x; g < ng4; g += WG) {
         const uint2 v = row4[g];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (4 * g + k < nch) atomicAdd(&sh.hist[cbin(half_k(v, k))], 1u);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t b = cbin(half_k(v, k));
+            if (4 * g + k < nch && b <= b0) atomicAdd(&sh.hist[b], 1u);
+        }
     }
     __syncthreads();
-    const int64_t want = a.n < 2 * (int64_t)a.budget ? a.n : 2 * (int64_t)a.budget;
-    const int wc = (int)min<int64_t>(nch, (want + 63) / 64 + 1);
     if (threadIdx.x == 0) sh.thr_bin = NB - 1;
     __syncthreads();
     find_threshold(wc, sh);
