@@ -273,6 +273,20 @@ int pmlsh_server_get_stats(pmlsh_server* server, pmlsh_server_stats* out);
  * (its tickets become invalid). */
 void pmlsh_server_destroy(pmlsh_server* server);
 
+/*
+ * (c,k)-ACP by the branch-and-bound algorithm (Algorithm 3, Section 6.2):
+ * the T = beta*n(n-1)/2 + k pairs (capped at n(n-1)/2) with the smallest
+ * projected distances over all pairs, ties by (i, j), are verified and the k
+ * with the smallest exact distance (ties by (i, j)) are returned. Arguments,
+ * outputs and errors as pmlsh_acp; EUNSUPPORTED when more than 2^28 pairs
+ * lie within the T-th smallest projected distance. In stats, ub is that
+ * distance's bound d_T used by the scan, n_seed is 0, n_cand_raw the pairs
+ * within d_T, n_cand = T. Synchronous.
+ */
+int pmlsh_acp_bb(const pmlsh_index* index, int32_t k, double c, double confidence,
+                 double beta, int64_t* out_pairs, float* out_dist,
+                 pmlsh_acp_stats* stats, void* stream);
+
 /* Shape and size of a built index. Host-only. */
 typedef struct {
     int64_t n;

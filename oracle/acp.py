@@ -24,6 +24,10 @@ takes it as data (a permutation and leaf offsets), never as code.
 
 Candidates are found by brute force over all pairs: no tree is used here, so
 a pruned pair scan elsewhere is checked for losing nothing.
+
+``branch_and_bound`` is the branch-and-bound algorithm of Section 6.2
+(Algorithm 3) in the same brute-force form: the T projected-closest pairs,
+verified.
 """
 
 from __future__ import annotations
@@ -160,3 +164,55 @@ def run(D: np.ndarray, Dp: np.ndarray, perm: np.ndarray, offsets: np.ndarray,
                      dist=ad[top], ub=ub, n_seed=int(si.shape[0]),
                      n_cand=int(ci.shape[0]), n_cand_raw=int(n_raw),
                      margin=mval, margin_kind=mkind)
+
+
+def _all_pairs_pd(Dp: np.ndarray, block: int = 256):
+    """Projected distances of all pairs i < j (brute force, FP64)."""
+    n = Dp.shape[0]
+    out_i, out_j, out_pd = [], [], []
+    for s in range(0, n, block):
+        e = min(n, s + block)
+        acc = np.zeros((e - s, n), dtype=np.float64)
+        for dim in range(Dp.shape[1]):
+            diff = Dp[s:e, dim][:, None] - Dp[None, :, dim]
+            acc += diff * diff
+        r_idx, c_idx = np.nonzero(np.arange(n)[None, :] > np.arange(s, e)[:, None])
+        out_i.append(r_idx + s)
+        out_j.append(c_idx)
+        out_pd.append(np.sqrt(acc[r_idx, c_idx]))
+    return (np.concatenate(out_i).astype(np.int64), np.concatenate(out_j).astype(np.int64),
+            np.concatenate(out_pd))
+
+
+def branch_and_bound(D: np.ndarray, Dp: np.ndarray, k: int, T: int) -> AcpResult:
+    """(c,k)-ACP by branch and bound, Section 6.2 (Algorithm 3).
+
+    The best-first search over node pairs with the Mindist bound stops once
+    no unexamined node pair can hold a pair closer (in the projected space)
+    than the T-th closest pair found, so its candidate set is the T pairs
+    with the smallest projected distance over all pairs. Reading: ties of the
+    projected distance go to the smaller (i, j), like every cut here. The T
+    pairs are verified and the k with the smallest exact distance, ties by
+    (i, j), returned. Computed by brute force over all pairs (no tree)."""
+    n = D.shape[0]
+    T = min(T, n * (n - 1) // 2)
+    pi, pj, pd = _all_pairs_pd(Dp)
+    o = np.lexsort((pj, pi, pd))
+    margins = []
+    if T < o.shape[0]:
+        margins.append((abs(pd[o[T]] - pd[o[T - 1]]) / max(pd[o[T - 1]], 1e-300),
+                        "budget_cut"))
+    sel = o[:T]
+    ci, cj = pi[sel], pj[sel]
+    cd = pair_dist(D, ci, cj)
+    oo = _pair_key_order(cd, ci, cj)
+    kk = min(k, oo.shape[0])
+    srt = cd[oo[:kk + 1]]
+    for a, b in zip(srt[:-1], srt[1:]):
+        margins.append(((b - a) / a if a > 0 else (math.inf if b > 0 else 0.0),
+                        "topk_order"))
+    mval, mkind = min(margins, key=lambda x: x[0]) if margins else (math.inf, "")
+    top = oo[:kk]
+    return AcpResult(pairs=np.stack([ci[top], cj[top]], axis=1), dist=cd[top],
+                     ub=float(pd[o[T - 1]]), n_seed=0, n_cand=int(T),
+                     n_cand_raw=int(T), margin=mval, margin_kind=mkind)

@@ -101,6 +101,9 @@ SIGNATURES = {
     "pmlsh_acp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.POINTER(_AcpStats), ctypes.c_void_p]),
+    "pmlsh_acp_bb": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.POINTER(_AcpStats), ctypes.c_void_p]),
     "pmlsh_get_index_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "pmlsh_index_export_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p]),
@@ -324,6 +327,19 @@ class Index:
         _check(load_library().pmlsh_acp(self._h, k, c, confidence, beta, pairs.data_ptr(),
                                         dist.data_ptr(), ctypes.byref(st),
                                         _stream_handle(self.device)))
+        return pairs, dist, {f: getattr(st, f) for f, _ in _AcpStats._fields_}
+
+    def acp_bb(self, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
+               beta: float = -1.0):
+        """(c,k)-ACP by branch and bound (Algorithm 3): the T projected-nearest
+        pairs are verified. Returns (pairs, dist, stats dict) like acp()."""
+        torch = _torch()
+        pairs = torch.empty((k, 2), dtype=torch.int64, device=self.device)
+        dist = torch.empty((k,), dtype=torch.float32, device=self.device)
+        st = _AcpStats()
+        _check(load_library().pmlsh_acp_bb(self._h, k, c, confidence, beta, pairs.data_ptr(),
+                                           dist.data_ptr(), ctypes.byref(st),
+                                           _stream_handle(self.device)))
         return pairs, dist, {f: getattr(st, f) for f, _ in _AcpStats._fields_}
 
 

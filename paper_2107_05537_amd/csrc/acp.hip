@@ -134,13 +134,16 @@ __device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b
     return m;
 }
 
+// Leaf pairs (e1 < e2; with diag also e1 = e2) whose Mindist can fall below
+// `limit`.
 __global__ __launch_bounds__(WG) void acp_tile_filter_kernel(
-    NodeView v, int64_t leaf_base, int64_t n_leaves, float limit,
+    NodeView v, int64_t leaf_base, int64_t n_leaves, float limit, int diag,
     int2* __restrict__ tiles, int64_t cap, unsigned long long* __restrict__ counter) {
     const int64_t e1 = blockIdx.y;
     const int64_t e2 = (int64_t)blockIdx.x * WG + threadIdx.x;
     bool keep = false;
     if (e2 > e1 && e2 < n_leaves) keep = mindist(v, leaf_base + e1, leaf_base + e2) <= limit;
+    if (diag && e2 == e1) keep = true;
     const int64_t slot = wave_append_global(keep, counter);
     if (keep && slot < cap) tiles[slot] = make_int2((int)e1, (int)e2);
 }
@@ -163,7 +166,8 @@ __global__ __launch_bounds__(WG) void acp_pd_kernel(
     pd[j] = sqrtf(acc);
 }
 
-// All point pairs (a in leaf e1, b in leaf e2) of the surviving tiles.
+// All point pairs (a in leaf e1, b in leaf e2; a < b when e1 = e2) of the
+// surviving tiles.
 //   1. PD filter: |dist(a, centre of e2) - PD(b)| is a lower bound of the
 //      projected distance (triangle inequality); pairs whose bound (less its
 //      FP32 error) reaches R cannot pass and are dropped. One wave takes one a
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_kernel(
                     const float x = da[a];
                     const int b = bb + lane;
                     bool pass = false;
-                    if (b < cb) {
+                    if (b < cb && (tl.x != tl.y || b > a)) {
                         const float y = pb[b];
                         // each distance carries at most ~12 u of relative error
                         pass = fabsf(x - y) - 32.f * u * (x + y) < Rlim;
@@ -603,7 +607,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
                    x->num_pivots};
         dim3 grid((unsigned)((NL + WG - 1) / WG), (unsigned)NL);
         hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL, limit,
-                           tiles.as<int2>(), tiles_total,
+                           0, tiles.as<int2>(), tiles_total,
                            static_cast<unsigned long long*>(dcount.p));
         PMLSH_HIP(hipGetLastError());
         n_tiles = read_counter();
@@ -711,6 +715,194 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         stats->n_cand_raw = n_raw;
         stats->n_cand = n_keep;
         stats->tiles_total = tiles_total;
+        stats->tiles_scanned = n_tiles;
+    }
+}
+
+// (c,k)-ACP by the branch-and-bound algorithm (Algorithm 3, Section 6.2): the
+// T pairs with the smallest projected distances over all pairs (ties by
+// (i, j)) are verified and the k nearest returned. Best-first search with
+// Mindist pruning finds exactly those T pairs; here a projected distance d_T
+// with at least T pairs at or below it is found first (the T-th smallest
+// projected distance of the pairs inside leaves, or a radius grown by 4x
+// from their largest while fewer than T pairs are found), the pairs at or
+// below d_T are collected by the tile scan (leaf pairs whose Mindist
+// exceeds d_T skipped whole, as the search would) and the T smallest are
+// cut by a radix select on (pd^2, i, j).
+void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double beta,
+                int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats, hipStream_t st) {
+    pmlsh_plan plan;
+    plan_params(x->n, x->m, k, c, confidence, beta, &plan);
+    const int64_t n = x->n;
+    const int L = x->leaf_size;
+    const int64_t NL = x->n_leaves;
+    const int64_t n_pairs = n * (n - 1) / 2;
+    const int64_t T = std::min<int64_t>(plan.acp_budget, n_pairs);
+    constexpr int64_t kMaxCand = int64_t(1) << 28;
+    if (NL > 65535) fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
+
+    std::lock_guard<std::mutex> lock(x->acp_mu);
+    if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});
+    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), tiles(x, S_TILES), ppd(x, S_PPD);
+    Triplets cand(x, S_CAND), kept(x, S_KEPT), pool(x, S_POOL), top(x, S_TOP);
+    dhist.alloc(NB * sizeof(uint32_t));
+    dcount.alloc(sizeof(unsigned long long));
+    auto read_counter = [&]() -> int64_t {
+        unsigned long long v = 0;
+        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        return (int64_t)v;
+    };
+    auto reset_counter = [&] {
+        PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
+    };
+    const int64_t leaf_base = x->level_begin[x->levels - 1];
+    NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
+               x->num_pivots};
+    ppd.alloc((size_t)n * sizeof(float));
+    hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
+                       x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
+    PMLSH_HIP(hipGetLastError());
+    const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
+    if (lds > 160 * 1024 - 256)
+        fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
+    PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int64_t tiles_all = NL * (NL - 1) / 2 + NL;
+    tiles.alloc((size_t)tiles_all * sizeof(int2));
+
+    // tiles: the diagonal ones only (d2 < 0), or every leaf pair whose
+    // Mindist can reach the projected distance sqrt(d2)
+    auto make_tiles = [&](float d2) -> int64_t {
+        if (d2 < 0.f) {
+            std::vector<int2> diag((size_t)NL);
+            for (int64_t e = 0; e < NL; ++e) diag[(size_t)e] = make_int2((int)e, (int)e);
+            PMLSH_HIP(hipMemcpyAsync(tiles.p, diag.data(), diag.size() * sizeof(int2),
+                                     hipMemcpyHostToDevice, st));
+            PMLSH_HIP(hipStreamSynchronize(st));
+            return NL;
+        }
+        const double R = std::sqrt((double)d2);
+        const float limit = std::isinf(R)
+                                ? INFINITY
+                                : (float)(R + 1e-5 * (2.0 * x->coord_scale + R)) * 1.0001f;
+        reset_counter();
+        dim3 grid((unsigned)((NL + WG - 1) / WG), (unsigned)NL);
+        hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL,
+                           limit, 1, tiles.as<int2>(), tiles_all,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        return read_counter();
+    };
+    // pairs of the tiles with pd^2 <= d2 (counted; written when cap > 0)
+    auto scan = [&](int64_t n_tiles, float d2, float limit, int64_t cap) -> int64_t {
+        const float R2 = std::isinf(d2) ? INFINITY : std::nextafter(d2, INFINITY);
+        reset_counter();
+        hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds, st,
+                           x->proj_hi, x->proj_lo, ppd.as<float>(), v, leaf_base, x->perm, n, L,
+                           tiles.as<int2>(), n_tiles, R2, limit,
+                           cap > 0 ? cand.k0.as<uint32_t>() : nullptr,
+                           cap > 0 ? cand.ii.as<uint32_t>() : nullptr,
+                           cap > 0 ? cand.jj.as<uint32_t>() : nullptr, cap,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        return read_counter();
+    };
+    auto limit_of = [&](float d2) {
+        const double R = std::sqrt((double)d2);
+        return std::isinf(R) ? INFINITY
+                             : (float)(R + 1e-5 * (2.0 * x->coord_scale + R)) * 1.0001f;
+    };
+
+    // d_T: the T-th smallest projected distance inside leaves bounds the
+    // global one from above; with fewer such pairs, grow a radius until at
+    // least T pairs lie within it
+    float d2 = INFINITY;
+    if (T < n_pairs) {
+        const int64_t nd = make_tiles(-1.f);
+        const int64_t n_in = scan(nd, INFINITY, INFINITY, 0);
+        if (n_in > kMaxCand) fail(PMLSH_EUNSUPPORTED, "too many pairs inside leaves");
+        cand.alloc(std::max<int64_t>(n_in, 1));
+        scan(nd, INFINITY, INFINITY, n_in);
+        if (n_in >= T && n_in > 0) {
+            SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                                  cand.jj.as<uint32_t>(), n_in, T, true, dhist.as<uint32_t>(),
+                                  st);
+            std::memcpy(&d2, &K.v0, 4);
+        } else {
+            // start from the largest pair distance inside leaves (or, with no
+            // such pair, from a millionth of the coordinate range squared)
+            float top2 = (float)(4e-6 * (double)x->coord_scale * (double)x->coord_scale);
+            if (n_in > 0) {
+                SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                                      cand.jj.as<uint32_t>(), n_in, n_in, true,
+                                      dhist.as<uint32_t>(), st);
+                std::memcpy(&top2, &K.v0, 4);
+            }
+            d2 = std::max(top2, 1e-30f) * 4.f;
+            for (;;) {
+                const int64_t nt = make_tiles(d2);
+                if (scan(nt, d2, limit_of(d2), 0) >= T || std::isinf(d2)) break;
+                d2 = d2 * 4.f;
+            }
+        }
+    }
+    const int64_t n_tiles = make_tiles(d2);
+    const int64_t n_raw = scan(n_tiles, d2, limit_of(d2), 0);
+    if (n_raw > kMaxCand)
+        fail(PMLSH_EUNSUPPORTED, "more than 2^28 pairs lie within the T-th projected distance");
+    if (n_raw < std::min<int64_t>(T, 1)) fail(PMLSH_EDEVICE, "pair scan found no pairs");
+    cand.alloc(n_raw);
+    if (scan(n_tiles, d2, limit_of(d2), n_raw) != n_raw)
+        fail(PMLSH_EDEVICE, "pair scan counts disagree");
+    // the T smallest (pd^2, i, j)
+    const int64_t keep = std::min(T, n_raw);
+    const Triplets* cands = &cand;
+    if (n_raw > keep) {
+        SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                              cand.jj.as<uint32_t>(), n_raw, keep, false, dhist.as<uint32_t>(), st);
+        kept.alloc(keep);
+        reset_counter();
+        hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_raw, WG)), dim3(WG), 0, st,
+                           cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(), cand.jj.as<uint32_t>(),
+                           n_raw, K, kept.k0.as<uint32_t>(), kept.ii.as<uint32_t>(),
+                           kept.jj.as<uint32_t>(), keep,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        if (read_counter() != keep) fail(PMLSH_EDEVICE, "budget cut lost candidates");
+        cands = &kept;
+    }
+    // verify, then the k nearest
+    pool.alloc(keep);
+    hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(keep, WG / 16)), dim3(WG), 0, st, x->data,
+                       x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(), cands->jj.as<uint32_t>(),
+                       keep, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                       pool.jj.as<uint32_t>());
+    PMLSH_HIP(hipGetLastError());
+    if (keep < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
+    SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                          keep, k, false, dhist.as<uint32_t>(), st);
+    top.alloc(k);
+    reset_counter();
+    hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(keep, WG)), dim3(WG), 0, st,
+                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                       keep, K, top.k0.as<uint32_t>(), top.ii.as<uint32_t>(),
+                       top.jj.as<uint32_t>(), (int64_t)k,
+                       static_cast<unsigned long long*>(dcount.p));
+    PMLSH_HIP(hipGetLastError());
+    if (read_counter() != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+    hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
+                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs, out_dist);
+    PMLSH_HIP(hipGetLastError());
+    PMLSH_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        stats->t = plan.t;
+        stats->ub = std::sqrt((double)d2);
+        stats->budget = T;
+        stats->n_seed = 0;
+        stats->n_cand_raw = n_raw;
+        stats->n_cand = keep;
+        stats->tiles_total = tiles_all;
         stats->tiles_scanned = n_tiles;
     }
 }

@@ -16,6 +16,9 @@ double index_default_r_min(const pmlsh_index* x, int64_t budget);
 void run_acp(const pmlsh_index* x, int k, double c, double confidence, double beta,
              int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
              hipStream_t stream);
+void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double beta,
+                int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+                hipStream_t stream);
 
 namespace {
 thread_local std::string g_error;
@@ -261,6 +264,22 @@ int pmlsh_acp(const pmlsh_index* index, int32_t k, double c, double confidence,
         if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
         run_acp(index, k, c, confidence, beta, out_pairs, out_dist, stats,
                 static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_acp_bb(const pmlsh_index* index, int32_t k, double c, double confidence,
+                 double beta, int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+                 void* stream) {
+    return guarded([&] {
+        if (!index) fail(PMLSH_EINVAL, "index is NULL");
+        if (!out_pairs || !out_dist) fail(PMLSH_EINVAL, "outputs must not be NULL");
+        if (index->n < 2) fail(PMLSH_EINVAL, "ACP needs n >= 2");
+        if (k < 1) fail(PMLSH_EINVAL, "k must be >= 1");
+        const double pairs = (double)index->n * (double)(index->n - 1) / 2.0;
+        if ((double)k > pairs) fail(PMLSH_EINVAL, "k must be <= n(n-1)/2");
+        if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
+        run_acp_bb(index, k, c, confidence, beta, out_pairs, out_dist, stats,
+                   static_cast<hipStream_t>(stream));
     });
 }
 

@@ -152,6 +152,33 @@ def test_acp_scale_planted():
         np.testing.assert_allclose(dist.cpu().numpy(), pd_[order[:k]], rtol=TOL)
 
 
+@pytest.mark.parametrize("beta", [1e-4, 0.05, 1.0])
+def test_branch_and_bound_matches_oracle(beta):
+    """Algorithm 3: the T projected-closest pairs verified. beta = 1e-4 puts
+    T below the pairs inside leaves (d_T from their T-th projected distance),
+    0.05 above them (d_T found by growing a radius), 1.0 takes every pair."""
+    pm = _gpu()
+    say(f"case: ACP branch and bound beta={beta}")
+    w = synth.planted_pairs(n=3000, d=32, n_centres=10)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A)
+    k = 10
+    pairs, dist, st = idx.acp_bb(k, c=1.5, beta=beta)
+    torch.cuda.synchronize()
+    T = min(chi2.acp_budget(beta, D.shape[0], k), D.shape[0] * (D.shape[0] - 1) // 2)
+    res = oacp.branch_and_bound(D, oann.project(D, A), k, T)
+    say("stats", st, "T", T, "margin", res.margin, res.margin_kind)
+    assert st["n_cand"] == T and st["n_seed"] == 0
+    assert st["n_cand_raw"] >= T
+    pairs, dist = pairs.cpu().numpy(), dist.cpu().numpy().astype(np.float64)
+    if res.margin > FRAGILE:
+        assert pairs.tolist() == res.pairs.tolist()
+        np.testing.assert_allclose(dist, res.dist, rtol=TOL, atol=1e-7)
+    else:
+        assert len(set(map(tuple, pairs.tolist())) & set(map(tuple, res.pairs.tolist()))) \
+            >= len(pairs) - 1
+
+
 def test_free_releases_device_memory():
     """Building, using and freeing an index returns its device memory (the
     FP16 rows, chunk balls and the ACP buffers kept in the index included)."""

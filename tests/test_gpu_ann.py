@@ -163,6 +163,27 @@ def test_shapes(n, d, m, leaf, fan, piv):
     compare_ann(D, Q, res, ids, dist, st)
 
 
+@pytest.mark.parametrize("scale", [1e-4, 1e4])
+def test_data_scale_extremes(scale):
+    """The same mixture scaled by 1e-4 and 1e4: the FP16 scan rows, the bf16
+    chunk distances and the FP16 verification rows all rescale (power-of-two
+    factors per index and per row), so answers must match the oracle."""
+    pm = _gpu()
+    say(f"case: data scale {scale}")
+    rng = np.random.Generator(np.random.PCG64(77))
+    n, d = 4000, 96
+    cen = rng.standard_normal((20, d)) * 2
+    lab = rng.integers(0, 20, n)
+    D = ((cen[lab] + 0.4 * rng.standard_normal((n, d))) * scale).astype(np.float32)
+    Q = ((cen[rng.integers(0, 20, 40)] + 0.4 * rng.standard_normal((40, d))) * scale).astype(np.float32)
+    A = rng.standard_normal((15, d)).astype(np.float32)
+    res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.05, r_min=1.0)
+    r0 = oracle_r_min(D, 3, B)
+    res, _ = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.05, r_min=r0)
+    _, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.05, r0, sample_seed=3)
+    compare_ann(D, Q, res, ids, dist, st)
+
+
 def test_ties_duplicates_and_self_queries():
     """Exact duplicate points (equal projected and exact distances: ties go to
     the smaller id) and queries that are data points (distance 0)."""

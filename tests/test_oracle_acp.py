@@ -13,7 +13,7 @@ import math
 
 import numpy as np
 import pytest
-from scipy.spatial.distance import pdist
+from scipy.spatial.distance import pdist, squareform
 
 import synth
 from oracle import acp, ann, brute, chi2, metrics
@@ -152,3 +152,55 @@ def test_budget_cut_ranks_by_projected_distance():
     assert res.n_cand == 1 and res.n_cand_raw == 3
     assert res.pairs.tolist() == [[0, 1]]
     assert res.dist[0] == pytest.approx(math.sqrt(26.0))
+
+
+# ---- branch and bound (Algorithm 3): the T projected-closest pairs, verified
+
+def test_bb_trace_on_a_line():
+    # projection onto the first coordinate: pd = |x_i - x_j|. Points
+    # x = 0, 1, 3, 3.5 with y = 0, 5, 0, 0. Projected pair distances:
+    # (2,3) 0.5, (0,1) 1, (1,2) 2, (1,3) 2.5, (0,2) 3, (0,3) 3.5. With T = 2
+    # the candidates are (2,3) and (0,1), whose exact distances are 0.5 and
+    # sqrt(26); k = 1 returns (2,3)
+    D = np.array([[0, 0], [1, 5], [3, 0], [3.5, 0]], dtype=np.float32)
+    A = np.array([[1.0, 0.0]], dtype=np.float32)
+    res = acp.branch_and_bound(D, ann.project(D, A), k=2, T=2)
+    assert res.pairs.tolist() == [[2, 3], [0, 1]]
+    assert res.dist[0] == pytest.approx(0.5) and res.dist[1] == pytest.approx(math.sqrt(26))
+    assert res.ub == pytest.approx(1.0)
+    # T = 3 adds (1,2), exact sqrt(29): still ranked after (0,1)
+    res = acp.branch_and_bound(D, ann.project(D, A), k=3, T=3)
+    assert res.pairs.tolist() == [[2, 3], [0, 1], [1, 2]]
+
+
+def test_bb_all_pairs_is_exact_closest_pairs():
+    rng = np.random.Generator(np.random.PCG64(9))
+    D = rng.standard_normal((120, 10)).astype(np.float32)
+    A = rng.standard_normal((6, 10)).astype(np.float32)
+    res = acp.branch_and_bound(D, ann.project(D, A), k=7, T=120 * 119 // 2)
+    pairs, dist = brute.closest_pairs(D, 7)
+    assert res.pairs.tolist() == pairs.tolist()
+    np.testing.assert_allclose(res.dist, dist, rtol=1e-12)
+    ref = np.sort(pdist(D.astype(np.float64)))[:7]
+    np.testing.assert_allclose(res.dist, ref, rtol=1e-12)
+
+
+def test_bb_candidates_are_the_projected_closest_pairs():
+    rng = np.random.Generator(np.random.PCG64(10))
+    D = rng.standard_normal((150, 12)).astype(np.float32)
+    A = rng.standard_normal((5, 12)).astype(np.float32)
+    Dp = ann.project(D, A)
+    T = 40
+    res = acp.branch_and_bound(D, Dp, k=40, T=T)
+    # every pair returned is among the T smallest projected distances
+    # (SciPy's pdist on the projections, an independent computation)
+    pdp = squareform(pdist(Dp))
+    thr = np.sort(pdist(Dp))[T - 1]
+    for (i, j) in res.pairs:
+        assert pdp[i, j] <= thr * (1 + 1e-12)
+    assert res.n_cand == T
+    # with an exact (orthonormal) projection the answer is the exact CP
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    res = acp.branch_and_bound(D, ann.project(D, Q.T.astype(np.float32)), k=5, T=5)
+    pairs, _ = brute.closest_pairs(D, 5)
+    assert res.pairs.tolist() == pairs.tolist()
