@@ -287,6 +287,41 @@ int pmlsh_acp_bb(const pmlsh_index* index, int32_t k, double c, double confidenc
                  double beta, int64_t* out_pairs, float* out_dist,
                  pmlsh_acp_stats* stats, void* stream);
 
+/*
+ * (c,k)-ACP by radius filtering with FindLCA (Algorithm 4 with Algorithm 5,
+ * Section 6.3):
+ *   1. every pair inside one leaf is verified; ub = the k-th smallest exact
+ *      distance; count = the number of verified pairs;
+ *   2. FindLCA: walking down from the root, the inner nodes whose radius is
+ *      below gamma * t * ub (a found node's subtree is not searched further);
+ *   3. the found nodes in ascending order of radius (ties by node index);
+ *      in each, every pair of points in different leaves of its subtree
+ *      with projected distance below t * ub is verified; then ub becomes the
+ *      k-th smallest verified distance and count grows by those pairs; the
+ *      scan stops after the first node that leaves count > T;
+ *   4. the k verified pairs with the smallest (distance, i, j).
+ * ub and count are updated after each node (the paper updates them after
+ * each verified pair). gamma > 0 is used as given; gamma <= 0 estimates it
+ * so that Pr(gamma) = 0.85 over 100,000 random pairs (the ratio of the
+ * radius of their lowest common ancestor to their projected distance).
+ * gamma_used (optional host pointer) receives the gamma applied. Other
+ * arguments, outputs and errors as pmlsh_acp; stats: ub is the final ub,
+ * n_cand_raw = n_cand = the candidates verified, tiles_total the leaf pairs
+ * under the found nodes, tiles_scanned those scanned. Synchronous.
+ */
+int pmlsh_acp_lca(const pmlsh_index* index, int32_t k, double c, double confidence,
+                  double beta, double gamma, int64_t* out_pairs, float* out_dist,
+                  pmlsh_acp_stats* stats, double* gamma_used, void* stream);
+
+/* Node structure of the index, for checking pmlsh_acp_lca against an
+ * independent implementation: for each of the n_nodes nodes (levels top
+ * down, the leaves last), its level (0 = root level), the range
+ * [first_leaf, end_leaf) of leaves under it (leaf b holds the ids listed by
+ * pmlsh_index_export_leaves for b) and its covering radius in the projected
+ * space. Host buffers of n_nodes entries each. */
+int pmlsh_index_export_nodes(const pmlsh_index* index, int32_t* level, int32_t* first_leaf,
+                             int32_t* end_leaf, float* radius);
+
 /* Shape and size of a built index. Host-only. */
 typedef struct {
     int64_t n;

@@ -27,7 +27,8 @@ a pruned pair scan elsewhere is checked for losing nothing.
 
 ``branch_and_bound`` is the branch-and-bound algorithm of Section 6.2
 (Algorithm 3) in the same brute-force form: the T projected-closest pairs,
-verified.
+verified. ``radius_filtering_lca`` is Algorithm 4 as printed (FindLCA with
+gamma, a live ub, the count > T stop), with the tree as data.
 """
 
 from __future__ import annotations
@@ -216,3 +217,90 @@ def branch_and_bound(D: np.ndarray, Dp: np.ndarray, k: int, T: int) -> AcpResult
     return AcpResult(pairs=np.stack([ci[top], cj[top]], axis=1), dist=cd[top],
                      ub=float(pd[o[T - 1]]), n_seed=0, n_cand=int(T),
                      n_cand_raw=int(T), margin=mval, margin_kind=mkind)
+
+
+def radius_filtering_lca(D: np.ndarray, Dp: np.ndarray, perm: np.ndarray, offsets: np.ndarray,
+                         level: np.ndarray, first_leaf: np.ndarray, end_leaf: np.ndarray,
+                         radius: np.ndarray, k: int, t: float, T: int,
+                         gamma: float) -> AcpResult:
+    """(c,k)-ACP by radius filtering with FindLCA, Section 6.3 (Algorithms 4-5).
+
+    1. self-join of every leaf, all seed pairs verified; ub = the k-th
+       smallest exact distance; count = number of verified pairs;
+    2. FindLCA from the root with R = gamma * t * ub: an inner node with
+       radius below R is returned (its subtree is not searched further),
+       otherwise its children are searched; leaves are never returned;
+    3. the returned nodes in ascending radius (ties by node index): every
+       pair of points in different leaves under the node whose projected
+       distance is below t * ub is verified, then ub becomes the k-th
+       smallest verified distance and count grows by those pairs; the scan
+       stops after the first node that leaves count > T;
+    4. the k verified pairs with the smallest (distance, i, j).
+    Reading: ub and count are updated node by node (Algorithm 4 updates them
+    after every verified pair, in an order inside the node it leaves open).
+    The tree is data (node levels, leaf ranges and radii of the index under
+    test); pairs are found by brute force inside each node."""
+    n = D.shape[0]
+    leaf_of = np.empty(n, dtype=np.int64)
+    for b in range(offsets.shape[0] - 1):
+        leaf_of[perm[offsets[b]:offsets[b + 1]]] = b
+    margins = []
+    si, sj = seed_pairs(perm, offsets)
+    sd = pair_dist(D, si, sj)
+    pi, pj, pdv = [si], [sj], [sd]
+
+    def kth():
+        allv = np.concatenate(pdv)
+        return float(np.partition(allv, k - 1)[k - 1]) if allv.shape[0] >= k else math.inf
+
+    ub = kth()
+    count = int(si.shape[0])
+    n_levels = int(level.max()) + 1
+    R = gamma * t * ub
+    found, stack = [], [int(e) for e in np.nonzero(level == 0)[0]]
+    while stack:
+        e = stack.pop()
+        if level[e] == n_levels - 1:
+            continue
+        if math.isfinite(R):
+            margins.append((abs(float(radius[e]) - R) / R if R > 0 else math.inf, "find_lca"))
+        if float(radius[e]) < R:
+            found.append(e)
+        else:
+            kids = np.nonzero((level == level[e] + 1) & (first_leaf >= first_leaf[e])
+                              & (end_leaf <= end_leaf[e]))[0]
+            stack.extend(int(x) for x in kids)
+    found.sort(key=lambda e: (float(radius[e]), e))
+    n_cand = 0
+    for e in found:
+        if count > T:
+            break
+        members = np.nonzero((leaf_of >= first_leaf[e]) & (leaf_of < end_leaf[e]))[0]
+        thr = t * ub
+        a, b = np.triu_indices(members.shape[0], k=1)
+        ia, ib = members[a], members[b]
+        cross = leaf_of[ia] != leaf_of[ib]
+        ia, ib = ia[cross], ib[cross]
+        pd = pair_dist(Dp, ia, ib)
+        if math.isfinite(thr) and thr > 0 and pd.shape[0]:
+            margins.append((float(np.min(np.abs(pd - thr))) / thr, "pair_filter"))
+        hit = pd < thr
+        ci, cj = np.minimum(ia[hit], ib[hit]), np.maximum(ia[hit], ib[hit])
+        cd = pair_dist(D, ci, cj)
+        pi.append(ci)
+        pj.append(cj)
+        pdv.append(cd)
+        count += int(ci.shape[0])
+        n_cand += int(ci.shape[0])
+        ub = kth()
+    ai, aj, ad = np.concatenate(pi), np.concatenate(pj), np.concatenate(pdv)
+    o = _pair_key_order(ad, ai, aj)
+    kk = min(k, o.shape[0])
+    srt = ad[o[:kk + 1]]
+    for x, y in zip(srt[:-1], srt[1:]):
+        margins.append(((y - x) / x if x > 0 else (math.inf if y > 0 else 0.0), "topk_order"))
+    mval, mkind = min(margins, key=lambda z: z[0]) if margins else (math.inf, "")
+    top = o[:kk]
+    return AcpResult(pairs=np.stack([ai[top], aj[top]], axis=1), dist=ad[top], ub=ub,
+                     n_seed=int(si.shape[0]), n_cand=n_cand, n_cand_raw=n_cand,
+                     margin=mval, margin_kind=mkind)

@@ -104,6 +104,14 @@ SIGNATURES = {
     "pmlsh_acp_bb": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.POINTER(_AcpStats), ctypes.c_void_p]),
+    "pmlsh_acp_lca": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(_AcpStats),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "pmlsh_index_export_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
     "pmlsh_get_index_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "pmlsh_index_export_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p]),
@@ -328,6 +336,34 @@ class Index:
                                         dist.data_ptr(), ctypes.byref(st),
                                         _stream_handle(self.device)))
         return pairs, dist, {f: getattr(st, f) for f, _ in _AcpStats._fields_}
+
+    def acp_lca(self, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
+                beta: float = -1.0, gamma: float = 0.0):
+        """(c,k)-ACP by radius filtering with FindLCA (Algorithms 4-5); gamma <= 0
+        estimates it (Pr(gamma) = 0.85). Returns (pairs, dist, stats dict with
+        the gamma applied under "gamma")."""
+        torch = _torch()
+        pairs = torch.empty((k, 2), dtype=torch.int64, device=self.device)
+        dist = torch.empty((k,), dtype=torch.float32, device=self.device)
+        st = _AcpStats()
+        g = ctypes.c_double(0.0)
+        _check(load_library().pmlsh_acp_lca(self._h, k, c, confidence, beta, gamma,
+                                            pairs.data_ptr(), dist.data_ptr(), ctypes.byref(st),
+                                            ctypes.byref(g), _stream_handle(self.device)))
+        out = {f: getattr(st, f) for f, _ in _AcpStats._fields_}
+        out["gamma"] = g.value
+        return pairs, dist, out
+
+    def export_nodes(self):
+        """Node structure (level, first_leaf, end_leaf, radius), NumPy arrays."""
+        nn = self.info()["n_nodes"]
+        level = np.empty(nn, dtype=np.int32)
+        lf = np.empty(nn, dtype=np.int32)
+        le = np.empty(nn, dtype=np.int32)
+        rad = np.empty(nn, dtype=np.float32)
+        _check(load_library().pmlsh_index_export_nodes(
+            self._h, level.ctypes.data, lf.ctypes.data, le.ctypes.data, rad.ctypes.data))
+        return {"level": level, "first_leaf": lf, "end_leaf": le, "radius": rad}
 
     def acp_bb(self, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
                beta: float = -1.0):

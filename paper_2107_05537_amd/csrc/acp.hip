@@ -907,4 +907,323 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     }
 }
 
+// Host copy of the node structure of the index: level of every node, the
+// range [lf, le) of leaves its subtree covers, its parent and its radius.
+struct NodeInfo {
+    std::vector<int32_t> level, lf, le, parent;
+    std::vector<float> rad;
+};
+
+NodeInfo fetch_nodes(const pmlsh_index* x) {
+    const int64_t N = x->n_nodes;
+    NodeInfo I;
+    I.level.assign(N, 0);
+    I.lf.assign(N, 0);
+    I.le.assign(N, 0);
+    I.parent.assign(N, -1);
+    I.rad.assign(N, 0.f);
+    std::vector<int32_t> cb(N), ce(N);
+    PMLSH_HIP(hipMemcpy(cb.data(), x->tree.child_begin, N * 4, hipMemcpyDeviceToHost));
+    PMLSH_HIP(hipMemcpy(ce.data(), x->tree.child_end, N * 4, hipMemcpyDeviceToHost));
+    PMLSH_HIP(hipMemcpy(I.rad.data(), x->tree.radius, N * 4, hipMemcpyDeviceToHost));
+    const int levels = x->levels;
+    const int64_t leaf_base = x->level_begin[levels - 1];
+    for (int l = levels - 1; l >= 0; --l) {
+        for (int64_t i = x->level_begin[l]; i < x->level_begin[l + 1]; ++i) {
+            I.level[i] = l;
+            if (l == levels - 1) {
+                I.lf[i] = (int32_t)(i - leaf_base);
+                I.le[i] = I.lf[i] + 1;
+            } else {
+                I.lf[i] = I.lf[cb[i]];
+                I.le[i] = I.le[ce[i] - 1];
+                for (int32_t ch = cb[i]; ch < ce[i]; ++ch) I.parent[ch] = (int32_t)i;
+            }
+        }
+    }
+    return I;
+}
+
+// gamma of Section 6.3 with Pr(gamma) = prob: over pairs of points drawn at
+// random (SplitMix64 from a fixed seed), the prob-quantile of the ratio of
+// the radius of the pair's lowest common ancestor to its projected distance.
+double estimate_gamma(const pmlsh_index* x, const NodeInfo& I, double prob) {
+    const int64_t n = x->n;
+    const int64_t L = x->leaf_size;
+    const int64_t leaf_base = x->level_begin[x->levels - 1];
+    std::vector<float> hi((size_t)n * MP), lo((size_t)n * MP);
+    PMLSH_HIP(hipMemcpy(hi.data(), x->proj_hi, hi.size() * 4, hipMemcpyDeviceToHost));
+    PMLSH_HIP(hipMemcpy(lo.data(), x->proj_lo, lo.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> pos_of(n);
+    for (int64_t p = 0; p < n; ++p) pos_of[x->perm_host[p]] = p;
+    // radius of a ball around the top-level nodes' mean centre covering them
+    // all (the tree's top level may hold several nodes)
+    double r_top = 0;
+    {
+        const int64_t N = x->n_nodes, t0 = x->level_begin[0], t1 = x->level_begin[1];
+        std::vector<float> cen((size_t)MP * N);
+        PMLSH_HIP(hipMemcpy(cen.data(), x->tree.centre, cen.size() * 4, hipMemcpyDeviceToHost));
+        double mean[MP] = {0};
+        for (int64_t i = t0; i < t1; ++i)
+            for (int t = 0; t < MP; ++t) mean[t] += cen[(size_t)t * N + i] / (double)(t1 - t0);
+        for (int64_t i = t0; i < t1; ++i) {
+            double acc = 0;
+            for (int t = 0; t < MP; ++t) {
+                const double dt = cen[(size_t)t * N + i] - mean[t];
+                acc += dt * dt;
+            }
+            r_top = std::max(r_top, std::sqrt(acc) + (double)I.rad[i]);
+        }
+    }
+    const double pairs = (double)n * (double)(n - 1) / 2.0;
+    const int64_t S = (int64_t)std::min(100000.0, pairs);
+    const uint64_t seed = 0x6761u;   // fixed: "ga"
+    std::vector<double> ratio;
+    ratio.reserve(S);
+    for (int64_t j = 0; j < S; ++j) {
+        const int64_t i = (int64_t)(splitmix64(seed + (uint64_t)j) % (uint64_t)n);
+        const int64_t o = 1 + (int64_t)(splitmix64(seed + (uint64_t)S + (uint64_t)j) %
+                                         (uint64_t)(n - 1));
+        const int64_t pa = pos_of[i], pb = pos_of[(i + o) % n];
+        int64_t node = leaf_base + pa / L;
+        const int64_t b = pb / L;
+        // up to the lowest common ancestor; pairs under different top-level
+        // nodes have the covering ball of the whole tree as theirs
+        while (node >= 0 && !(I.lf[node] <= b && b < I.le[node])) node = I.parent[node];
+        const double r_lca = node >= 0 ? (double)I.rad[node] : r_top;
+        double acc = 0;
+        for (int t = 0; t < MP; ++t) {
+            const double dt = ((double)hi[pa * MP + t] + (double)lo[pa * MP + t]) -
+                              ((double)hi[pb * MP + t] + (double)lo[pb * MP + t]);
+            acc += dt * dt;
+        }
+        if (acc > 0) ratio.push_back(r_lca / std::sqrt(acc));
+    }
+    if (ratio.empty()) return 1.0;
+    std::sort(ratio.begin(), ratio.end());
+    const size_t at = (size_t)std::max(1.0, std::ceil(prob * (double)ratio.size())) - 1;
+    return ratio[std::min(at, ratio.size() - 1)];
+}
+
+// (c,k)-ACP by radius filtering with FindLCA (Algorithm 4 with Algorithm 5):
+//   1. self-join of every leaf, all seed pairs verified; ub = the k-th
+//      smallest exact distance; count = number of verified pairs;
+//   2. R = gamma t ub; FindLCA: walking down from the root, the inner nodes
+//      with radius below R (a found node's subtree is not searched further);
+//   3. the found nodes in ascending order of radius (ties by node); in each,
+//      every pair of points in different leaves of the subtree whose
+//      projected distance is below t ub is verified, then ub becomes the
+//      k-th smallest verified distance and count grows by those pairs;
+//      after a node that leaves count > T the scan stops;
+//   4. the k verified pairs with the smallest (distance, i, j).
+// Reading: ub and count are updated after each node (the paper updates them
+// after every verified pair, within the node's own order).
+void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, double beta,
+                 double gamma, int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+                 double* gamma_used, hipStream_t st) {
+    pmlsh_plan plan;
+    plan_params(x->n, x->m, k, c, confidence, beta, &plan);
+    const int64_t n = x->n;
+    const int L = x->leaf_size;
+    const int64_t NL = x->n_leaves;
+    const int64_t T = plan.acp_budget;
+    constexpr int64_t kMaxCand = int64_t(1) << 28;
+
+    std::lock_guard<std::mutex> lock(x->acp_mu);
+    if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});
+    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), tiles(x, S_TILES), ppd(x, S_PPD);
+    Triplets seeds(x, S_SEEDS), cand(x, S_CAND), pool(x, S_POOL), kept(x, S_KEPT),
+        top(x, S_TOP);
+    dhist.alloc(NB * sizeof(uint32_t));
+    dcount.alloc(sizeof(unsigned long long));
+    auto reset_counter = [&] {
+        PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
+    };
+    auto read_counter = [&]() -> int64_t {
+        unsigned long long v = 0;
+        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        return (int64_t)v;
+    };
+
+    // 1. seeds
+    std::vector<int64_t> seed_off(NL + 1, 0);
+    for (int64_t b = 0; b < NL; ++b) {
+        const int64_t cnt = std::min<int64_t>(L, n - b * L);
+        seed_off[b + 1] = seed_off[b] + cnt * (cnt - 1) / 2;
+    }
+    const int64_t n_seed = seed_off[NL];
+    // the pool of verified pairs: seeds first, candidates appended
+    int64_t pool_cap = std::max<int64_t>(n_seed + (int64_t(1) << 20), k);
+    pool.alloc(pool_cap);
+    if (n_seed > 0) {
+        DevBuf doff(x, S_DOFF);
+        doff.alloc((NL + 1) * sizeof(int64_t));
+        PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(acp_self_join_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
+                           x->d_pad, x->perm, n, L, doff.as<int64_t>(), pool.k0.as<uint32_t>(),
+                           pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>());
+        PMLSH_HIP(hipGetLastError());
+        PMLSH_HIP(hipStreamSynchronize(st));
+    }
+    int64_t n_pool = n_seed;
+    auto kth_dist = [&]() -> double {
+        if (n_pool < k) return HUGE_VAL;
+        SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                              pool.jj.as<uint32_t>(), n_pool, k, true, dhist.as<uint32_t>(), st);
+        float v2;
+        std::memcpy(&v2, &K.v0, 4);
+        return std::sqrt((double)v2);
+    };
+    double ub = kth_dist();
+    int64_t count = n_seed;
+
+    // 2. FindLCA with R = gamma t ub
+    NodeInfo I = fetch_nodes(x);
+    if (!(gamma > 0.0)) gamma = estimate_gamma(x, I, 0.85);
+    if (gamma_used) *gamma_used = gamma;
+    const double Rlca = gamma * plan.t * ub;
+    std::vector<int64_t> found;
+    {
+        std::vector<int64_t> stack;
+        for (int64_t i = x->level_begin[0]; i < x->level_begin[1]; ++i) stack.push_back(i);
+        while (!stack.empty()) {
+            const int64_t e = stack.back();
+            stack.pop_back();
+            if (I.level[e] == x->levels - 1) continue;            // leaves: self-joined
+            if ((double)I.rad[e] < Rlca) {
+                found.push_back(e);
+            } else {
+                for (int64_t ch = x->level_begin[I.level[e] + 1]; ch < x->level_begin[I.level[e] + 2];
+                     ++ch)
+                    if (I.parent[ch] == e) stack.push_back(ch);
+            }
+        }
+    }
+    std::sort(found.begin(), found.end(), [&](int64_t a, int64_t b) {
+        return I.rad[a] != I.rad[b] ? I.rad[a] < I.rad[b] : a < b;
+    });
+
+    // 3. the found nodes, ascending radius
+    const int64_t leaf_base = x->level_begin[x->levels - 1];
+    NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
+               x->num_pivots};
+    ppd.alloc((size_t)n * sizeof(float));
+    hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
+                       x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
+    PMLSH_HIP(hipGetLastError());
+    const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
+    if (lds > 160 * 1024 - 256)
+        fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
+    PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int64_t tiles_total = 0, tiles_scanned = 0, n_cand_total = 0;
+    for (int64_t e : found) tiles_total += (int64_t)(I.le[e] - I.lf[e]) * (I.le[e] - I.lf[e] - 1) / 2;
+    std::vector<int2> tl;
+    int64_t cand_cap = 0;
+    for (int64_t e : found) {
+        if (count > T) break;
+        tl.clear();
+        for (int32_t a = I.lf[e]; a < I.le[e]; ++a)
+            for (int32_t b = a + 1; b < I.le[e]; ++b) tl.push_back(make_int2(a, b));
+        if (tl.empty()) continue;
+        tiles.alloc(tl.size() * sizeof(int2));
+        PMLSH_HIP(hipMemcpyAsync(tiles.p, tl.data(), tl.size() * sizeof(int2),
+                                 hipMemcpyHostToDevice, st));
+        tiles_scanned += (int64_t)tl.size();
+        const double R = plan.t * ub;
+        const float R2 = std::isinf(R) ? INFINITY : (float)(R * R);
+        const float limit = std::isinf(R)
+                                ? INFINITY
+                                : (float)R + (float)(1e-5 * (2.0 * x->coord_scale + R));
+        int64_t nc = 0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if (cand_cap < 1) {
+                cand_cap = int64_t(1) << 16;
+                cand.alloc(cand_cap);
+            }
+            reset_counter();
+            hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for((int64_t)tl.size(), 1)),
+                               dim3(WG), lds, st, x->proj_hi, x->proj_lo, ppd.as<float>(), v,
+                               leaf_base, x->perm, n, L, tiles.as<int2>(), (int64_t)tl.size(), R2,
+                               limit, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                               cand.jj.as<uint32_t>(), cand_cap,
+                               static_cast<unsigned long long*>(dcount.p));
+            PMLSH_HIP(hipGetLastError());
+            nc = read_counter();
+            if (nc <= cand_cap) break;
+            if (nc > kMaxCand)
+                fail(PMLSH_EUNSUPPORTED, "more than 2^28 candidate pairs in one node");
+            cand_cap = nc;
+            cand.alloc(cand_cap);
+        }
+        if (nc == 0) continue;
+        if (n_pool + nc > pool_cap) {
+            // grow the pool, keeping what it holds
+            const int64_t new_cap = std::max(2 * pool_cap, n_pool + nc);
+            kept.alloc(n_pool);
+            for (int f = 0; f < 3; ++f) {
+                void* src = f == 0 ? pool.k0.p : f == 1 ? pool.ii.p : pool.jj.p;
+                void* dst = f == 0 ? kept.k0.p : f == 1 ? kept.ii.p : kept.jj.p;
+                PMLSH_HIP(hipMemcpyAsync(dst, src, n_pool * 4, hipMemcpyDeviceToDevice, st));
+            }
+            PMLSH_HIP(hipStreamSynchronize(st));
+            pool.alloc(new_cap);
+            for (int f = 0; f < 3; ++f) {
+                void* src = f == 0 ? kept.k0.p : f == 1 ? kept.ii.p : kept.jj.p;
+                void* dst = f == 0 ? pool.k0.p : f == 1 ? pool.ii.p : pool.jj.p;
+                PMLSH_HIP(hipMemcpyAsync(dst, src, n_pool * 4, hipMemcpyDeviceToDevice, st));
+            }
+            pool_cap = new_cap;
+        }
+        hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(nc, WG / 16)), dim3(WG), 0, st,
+                           x->data, x->d_pad, x->inv_perm, cand.ii.as<uint32_t>(),
+                           cand.jj.as<uint32_t>(), nc, pool.k0.as<uint32_t>() + n_pool,
+                           pool.ii.as<uint32_t>() + n_pool, pool.jj.as<uint32_t>() + n_pool);
+        PMLSH_HIP(hipGetLastError());
+        n_pool += nc;
+        count += nc;
+        n_cand_total += nc;
+        ub = kth_dist();
+    }
+
+    // 4. the k nearest verified pairs
+    if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
+    SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                          n_pool, k, false, dhist.as<uint32_t>(), st);
+    top.alloc(k);
+    reset_counter();
+    hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
+                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                       n_pool, K, top.k0.as<uint32_t>(), top.ii.as<uint32_t>(),
+                       top.jj.as<uint32_t>(), (int64_t)k,
+                       static_cast<unsigned long long*>(dcount.p));
+    PMLSH_HIP(hipGetLastError());
+    if (read_counter() != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+    hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
+                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs, out_dist);
+    PMLSH_HIP(hipGetLastError());
+    PMLSH_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        stats->t = plan.t;
+        stats->ub = ub;
+        stats->budget = T;
+        stats->n_seed = n_seed;
+        stats->n_cand_raw = n_cand_total;
+        stats->n_cand = n_cand_total;
+        stats->tiles_total = tiles_total;
+        stats->tiles_scanned = tiles_scanned;
+    }
+}
+
+void export_nodes(const pmlsh_index* x, int32_t* level, int32_t* first_leaf, int32_t* end_leaf,
+                  float* radius) {
+    NodeInfo I = fetch_nodes(x);
+    std::copy(I.level.begin(), I.level.end(), level);
+    std::copy(I.lf.begin(), I.lf.end(), first_leaf);
+    std::copy(I.le.begin(), I.le.end(), end_leaf);
+    std::copy(I.rad.begin(), I.rad.end(), radius);
+}
+
 }  // namespace pmlsh

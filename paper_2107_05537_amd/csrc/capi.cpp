@@ -19,6 +19,11 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
 void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double beta,
                 int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
                 hipStream_t stream);
+void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, double beta,
+                 double gamma, int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
+                 double* gamma_used, hipStream_t st);
+void export_nodes(const pmlsh_index* x, int32_t* level, int32_t* first_leaf, int32_t* end_leaf,
+                  float* radius);
 
 namespace {
 thread_local std::string g_error;
@@ -280,6 +285,32 @@ int pmlsh_acp_bb(const pmlsh_index* index, int32_t k, double c, double confidenc
         if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
         run_acp_bb(index, k, c, confidence, beta, out_pairs, out_dist, stats,
                    static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_acp_lca(const pmlsh_index* index, int32_t k, double c, double confidence,
+                  double beta, double gamma, int64_t* out_pairs, float* out_dist,
+                  pmlsh_acp_stats* stats, double* gamma_used, void* stream) {
+    return guarded([&] {
+        if (!index) fail(PMLSH_EINVAL, "index is NULL");
+        if (!out_pairs || !out_dist) fail(PMLSH_EINVAL, "outputs must not be NULL");
+        if (index->n < 2) fail(PMLSH_EINVAL, "ACP needs n >= 2");
+        if (k < 1) fail(PMLSH_EINVAL, "k must be >= 1");
+        const double pairs = (double)index->n * (double)(index->n - 1) / 2.0;
+        if ((double)k > pairs) fail(PMLSH_EINVAL, "k must be <= n(n-1)/2");
+        if (k > PMLSH_MAX_K) fail(PMLSH_EUNSUPPORTED, "k above PMLSH_MAX_K");
+        if (std::isnan(gamma) || std::isinf(gamma)) fail(PMLSH_EINVAL, "gamma must be finite");
+        run_acp_lca(index, k, c, confidence, beta, gamma, out_pairs, out_dist, stats, gamma_used,
+                    static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_index_export_nodes(const pmlsh_index* index, int32_t* level, int32_t* first_leaf,
+                             int32_t* end_leaf, float* radius) {
+    return guarded([&] {
+        if (!index || !level || !first_leaf || !end_leaf || !radius)
+            fail(PMLSH_EINVAL, "NULL argument");
+        export_nodes(index, level, first_leaf, end_leaf, radius);
     });
 }
 

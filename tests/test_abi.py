@@ -125,6 +125,8 @@ def test_null_handles_rejected(lib):
     assert lib.pmlsh_acp(None, 1, 1.5, 0.9, 0.1, ids, ids, None, None) == pm.EINVAL
     assert lib.pmlsh_bc(None, ids, 1, 1.0, 1.5, 0.9, 0.1, ids, ids, None, None) == pm.EINVAL
     assert lib.pmlsh_acp_bb(None, 1, 1.5, 0.9, 0.1, ids, ids, None, None) == pm.EINVAL
+    assert lib.pmlsh_acp_lca(None, 1, 1.5, 0.9, 0.1, 0.0, ids, ids, None, None, None) == pm.EINVAL
+    assert lib.pmlsh_index_export_nodes(None, None, None, None, None) == pm.EINVAL
     assert lib.pmlsh_get_index_info(None, None) == pm.EINVAL
     assert lib.pmlsh_index_export_leaves(None, None, None) == pm.EINVAL
     assert lib.pmlsh_default_r_min(None, 1, None) == pm.EINVAL

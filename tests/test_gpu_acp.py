@@ -179,6 +179,53 @@ def test_branch_and_bound_matches_oracle(beta):
             >= len(pairs) - 1
 
 
+@pytest.mark.parametrize("scale,extra", [(1.0, None), (40.0, None), (40.0, 20)])
+def test_radius_filtering_lca_matches_oracle(scale, extra):
+    """Algorithms 4-5: FindLCA with gamma, live ub per node. gamma is the
+    library's estimate (Pr = 0.85) times `scale` (40 makes FindLCA return
+    nodes on this mixture, whose leaf pairs are then scanned); extra = 20
+    sets T to the seed count plus 20, so the scan stops after the first node
+    that passes T. The oracle gets the same gamma and the exported tree."""
+    pm = _gpu()
+    say(f"case: ACP FindLCA gamma x{scale} extra={extra}")
+    w = synth.parity(n=3000, n_queries=1)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A, leaf_size=16, fanout=4)
+    perm, offsets = idx.export_leaves()
+    nodes = idx.export_nodes()
+    n, k = D.shape[0], 10
+    n_seed = int(sum((offsets[b + 1] - offsets[b]) * (offsets[b + 1] - offsets[b] - 1) // 2
+                     for b in range(offsets.shape[0] - 1)))
+    beta = 0.05 if extra is None else (n_seed + extra - k) / (n * (n - 1) / 2)
+    say("estimating gamma")
+    _, _, st0 = idx.acp_lca(k, c=1.5, beta=beta)
+    gamma = st0["gamma"] * scale
+    assert gamma > 0 and math.isfinite(gamma)
+    say("running pmlsh_acp_lca with gamma", gamma)
+    pairs, dist, st = idx.acp_lca(k, c=1.5, beta=beta, gamma=gamma)
+    torch.cuda.synchronize()
+    assert st["gamma"] == gamma
+    t = chi2.radius_factor(1 / math.e, A.shape[0])
+    T = chi2.acp_budget(beta, n, k)
+    assert st["budget"] == T
+    say("stats", st, "; running the oracle")
+    res = oacp.radius_filtering_lca(D, oann.project(D, A), perm, offsets, nodes["level"],
+                                    nodes["first_leaf"], nodes["end_leaf"], nodes["radius"],
+                                    k, t, T, gamma)
+    say("oracle n_cand", res.n_cand, "margin", res.margin, res.margin_kind)
+    if scale > 1:
+        assert st["tiles_scanned"] > 0
+    pairs, dist = pairs.cpu().numpy(), dist.cpu().numpy().astype(np.float64)
+    assert st["n_seed"] == res.n_seed
+    if res.margin > FRAGILE:
+        assert st["n_cand"] == res.n_cand
+        assert pairs.tolist() == res.pairs.tolist()
+        np.testing.assert_allclose(dist, res.dist, rtol=TOL, atol=1e-7)
+    else:
+        assert len(set(map(tuple, pairs.tolist())) & set(map(tuple, res.pairs.tolist()))) \
+            >= len(pairs) - 1
+
+
 def test_free_releases_device_memory():
     """Building, using and freeing an index returns its device memory (the
     FP16 rows, chunk balls and the ACP buffers kept in the index included)."""

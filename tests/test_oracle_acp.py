@@ -204,3 +204,82 @@ def test_bb_candidates_are_the_projected_closest_pairs():
     res = acp.branch_and_bound(D, ann.project(D, Q.T.astype(np.float32)), k=5, T=5)
     pairs, _ = brute.closest_pairs(D, 5)
     assert res.pairs.tolist() == pairs.tolist()
+
+
+# ---- radius filtering with FindLCA (Algorithms 4-5)
+
+def _line_tree():
+    """8 points on a line (y = 0), 4 leaves of 2, two inner nodes of two
+    leaves each and a root; the projection is the first coordinate. All
+    coordinates and differences are exact binary fractions."""
+    x = [0, 0.125, 1, 1.125, 10, 10.125, 11, 11.125]
+    D = np.array([[v, 0.0] for v in x], dtype=np.float32)
+    Dp = ann.project(D, np.array([[1.0, 0.0]], dtype=np.float32))
+    perm = np.arange(8, dtype=np.int32)
+    offsets = np.array([0, 2, 4, 6, 8], dtype=np.int64)
+    #            root  A    B    leaves
+    level = np.array([0, 1, 1, 2, 2, 2, 2], dtype=np.int32)
+    first = np.array([0, 0, 2, 0, 1, 2, 3], dtype=np.int32)
+    end = np.array([4, 2, 4, 1, 2, 3, 4], dtype=np.int32)
+    radius = np.array([6.0, 0.6, 0.6, 0.05, 0.05, 0.05, 0.05], dtype=np.float32)
+    return D, Dp, perm, offsets, level, first, end, radius
+
+
+def test_lca_trace_stops_after_the_node_that_passes_T():
+    # seeds: four pairs at 0.125, ub (k = 2) = 0.125; t = 8, gamma = 1:
+    # R = 1, FindLCA returns A and B (radius 0.6). In A the cross pairs have
+    # projected distances 1, 1.125, 0.875, 1: only (1, 2) is below t ub = 1.
+    # count = 5 > T = 4 after A, so B is never scanned.
+    D, Dp, perm, off, lv, fl, el, rad = _line_tree()
+    res = acp.radius_filtering_lca(D, Dp, perm, off, lv, fl, el, rad, k=2, t=8.0, T=4,
+                                   gamma=1.0)
+    assert res.n_seed == 4 and res.n_cand == 1
+    assert res.pairs.tolist() == [[0, 1], [2, 3]]
+    res = acp.radius_filtering_lca(D, Dp, perm, off, lv, fl, el, rad, k=2, t=8.0, T=100,
+                                   gamma=1.0)
+    assert res.n_cand == 2           # (1, 2) in A and (5, 6) in B
+
+
+def test_lca_trace_findlca_descends_and_skips_leaves():
+    # gamma = 0.5: R = 0.5 is below every inner radius, FindLCA descends to
+    # the leaves, which it never returns: only the seeds are verified
+    D, Dp, perm, off, lv, fl, el, rad = _line_tree()
+    res = acp.radius_filtering_lca(D, Dp, perm, off, lv, fl, el, rad, k=2, t=8.0, T=100,
+                                   gamma=0.5)
+    assert res.n_cand == 0 and res.pairs.tolist() == [[0, 1], [2, 3]]
+
+
+def test_lca_trace_unbounded_ub_scans_the_root():
+    # k = 5 > 4 seeds: ub = +inf, R = +inf, FindLCA returns the root and all
+    # 24 cross-leaf pairs are verified; the fifth nearest is (1, 2) at 0.875
+    # (tied with (5, 6), which has the larger ids)
+    D, Dp, perm, off, lv, fl, el, rad = _line_tree()
+    res = acp.radius_filtering_lca(D, Dp, perm, off, lv, fl, el, rad, k=5, t=8.0, T=1000,
+                                   gamma=1.0)
+    assert res.n_cand == 24
+    assert res.pairs.tolist() == [[0, 1], [2, 3], [4, 5], [6, 7], [1, 2]]
+    assert res.dist[4] == 0.875
+
+
+def test_lca_with_root_found_equals_canonical_filter():
+    """With R above the root's radius the one node scanned is the root, with
+    the self-join ub, so the candidates are those of the canonical filter."""
+    w = synth.parity(n=600, n_queries=1)
+    D, A = w["D"], w["A"]
+    Dp = ann.project(D, A)
+    L = 32
+    perm = np.random.Generator(np.random.PCG64(1)).permutation(600).astype(np.int32)
+    off = np.array([min(600, b * L) for b in range(600 // L + 2)], dtype=np.int64)
+    off = np.unique(off)
+    nl = off.shape[0] - 1
+    level = np.concatenate([[0], np.ones(nl, dtype=np.int32)]).astype(np.int32)
+    first = np.concatenate([[0], np.arange(nl)]).astype(np.int32)
+    end = np.concatenate([[nl], np.arange(1, nl + 1)]).astype(np.int32)
+    radius = np.concatenate([[1.0], np.zeros(nl)]).astype(np.float32)
+    t = chi2.radius_factor(0.1, A.shape[0])
+    T = 10 ** 9
+    res = acp.radius_filtering_lca(D, Dp, perm, off, level, first, end, radius, k=5, t=t, T=T,
+                                   gamma=1e9)
+    ref = acp.run(D, Dp, perm, off, k=5, t=t, T=T)
+    assert res.pairs.tolist() == ref.pairs.tolist()
+    assert res.n_cand == ref.n_cand_raw
