@@ -380,6 +380,27 @@ typedef struct {
 int pmlsh_ann_timing_enable(int stage_mask);
 int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
 
+/*
+ * Test aid: process-wide switches of the group filter of the ANN bound kernel
+ * (the minima of 64-chunk groups that rule out the groups unable to hold a
+ * chunk chosen for tau or a chunk passing Eq. 5). Results are the same under
+ * every setting; only the work differs.
+ *   PMLSH_TUNE_GROUP_LIST         most groups (and 256-chunk blocks of the
+ *                                 Eq. 5 test) one query lists, 0..2048
+ *                                 (default 2048); when more qualify, or at 0,
+ *                                 the passes read the query's whole row
+ *   PMLSH_TUNE_GROUP_MINIMA_LDS   1 (default): the group minima are copied to
+ *                                 LDS when they fit (about 28,000 groups);
+ *                                 0: read from HBM in every pass
+ * value -1 restores the default; a key or value out of range: PMLSH_EINVAL.
+ * A call running while a switch changes may see either setting.
+ */
+#define PMLSH_TUNE_GROUP_LIST 0
+#define PMLSH_TUNE_GROUP_MINIMA_LDS 1
+#define PMLSH_N_TUNE 2
+
+int pmlsh_tune(int key, int64_t value);
+
 /* Message of the last failed call on this thread ("" if none). The pointer
  * stays valid until the next failing call on the same thread. */
 const char* pmlsh_last_error(void);

@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 __all__ = ["Index", "Server", "PmlshError", "plan_params", "library_path", "load_library",
-           "ann_timing_enable", "ann_timing_read"]
+           "ann_timing_enable", "ann_timing_read", "tune", "TUNE_GROUP_LIST",
+           "TUNE_GROUP_MINIMA_LDS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libpmlsh.so")
@@ -115,6 +116,7 @@ SIGNATURES = {
     "pmlsh_get_index_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "pmlsh_index_export_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p]),
+    "pmlsh_tune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64]),
     "pmlsh_ann_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "pmlsh_ann_timing_read": (ctypes.c_int, [ctypes.POINTER(_Timing), ctypes.c_int]),
     "pmlsh_last_error": (ctypes.c_char_p, []),
@@ -180,6 +182,16 @@ def plan_params(n: int, m: int, k: int, c: float, confidence: float, beta: float
     out = _Plan()
     _check(load_library().pmlsh_plan_params(n, m, k, c, confidence, beta, ctypes.byref(out)))
     return {f: getattr(out, f) for f, _ in _Plan._fields_}
+
+
+TUNE_GROUP_LIST = 0          # most 64-chunk groups the ANN bound lists per query
+TUNE_GROUP_MINIMA_LDS = 1    # group minima in LDS (1) or read from HBM (0)
+
+
+def tune(key: int, value: int = -1):
+    """Process-wide switch of the ANN bound kernel's group filter (pmlsh_tune;
+    -1 restores the default). Results do not depend on it."""
+    _check(load_library().pmlsh_tune(int(key), int(value)))
 
 
 def ann_timing_enable(enable: bool = True, stages=None):

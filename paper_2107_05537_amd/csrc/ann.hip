@@ -96,14 +96,18 @@ struct AnnArgs {
     // per query, bit-sliced: bit l of word 4 g + k is chunk 256 g + 4 l + k)
     const float* chunk_cen;
     const float* chunk_rad;
+    const float* group_rad;     // per 64 consecutive chunks: their largest radius
     uint64_t* qmask;
     int mwords;
     uint64_t* cmask;            // the same mask chunk-major: ceil(nq / 64) words per chunk
     int cwords;
     // squared distances from every query to every chunk centre (row stride
-    // ldc), as bf16 bit patterns rounded toward zero (lower bounds)
+    // ldc), as bf16 bit patterns rounded toward zero (lower bounds); from
+    // offset goff of a row, the minimum of each group of 64 chunks
     uint16_t* cdist;
-    int64_t ldc;
+    int64_t ldc, goff;
+    int glds;                   // bound kernel: group minima copied to LDS
+    int grp_cap;                // bound kernel: most groups or blocks listed (<= kGrpCap)
     int32_t* csel;              // per query: the chunks chosen for its bound (kSelCap)
     // bounded verification: FP16 rows (stride d16), their scales and error
     // bounds, and per C member a lower bound of its squared distance (the
@@ -1035,29 +1039,48 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
             }
         }
         __syncthreads();
-        // four threads per query row, 16 chunks (32 bytes) each; ldc is a
-        // multiple of 16, so a segment that starts below ldc lies inside the row
+        // four threads per query row, 16 chunks (32 bytes) each; goff is a
+        // multiple of 16, so a segment that starts below it lies inside the
+        // distance part of the row
         const int ql = threadIdx.x >> 2, seg = (threadIdx.x & 3) * 16;
-        if (ql < nqb && c0 + seg < a.ldc) {
+        uint32_t gm = 0xffffu;
+        if (c0 + seg < a.goff) {
             const uint4* src = reinterpret_cast<const uint4*>(&tile[ql][seg]);
-            uint4* dst = reinterpret_cast<uint4*>(a.cdist + (int64_t)(q0 + ql) * a.ldc + c0 + seg);
-            dst[0] = src[0];
-            dst[1] = src[1];
+            const uint4 x0 = src[0], x1 = src[1];
+            if (ql < nqb) {
+                uint4* dst = reinterpret_cast<uint4*>(a.cdist + (int64_t)(q0 + ql) * a.ldc + c0 + seg);
+                dst[0] = x0;
+                dst[1] = x1;
+            }
+            const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t h = (e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xffffu);
+                if (c0 + seg + e < nch) gm = min(gm, h);
+            }
         }
+        // the group minimum over the four threads of the row
+        gm = min(gm, (uint32_t)__shfl_xor((int)gm, 1));
+        gm = min(gm, (uint32_t)__shfl_xor((int)gm, 2));
+        if ((threadIdx.x & 3) == 0 && ql < nqb)
+            a.cdist[(int64_t)(q0 + ql) * a.ldc + a.goff + (c0 >> 6)] = (uint16_t)gm;
     }
 }
 
 // float bits >> 19 of 2^-64: the first of the fixed centre-distance bins
 constexpr uint32_t kCenBinBase = 63u << 4;
-// largest LDS footprint of the bound kernel with its row in LDS (two
-// workgroups per compute unit at the most)
-constexpr size_t kTauRowLds = 80 * 1024;
+// Groups (and 256-chunk blocks) the bound kernel lists per query at most, and
+// the largest LDS footprint of its group minima and group list (beyond it the
+// minima are read from HBM in every pass).
+constexpr int kGrpCap = 2048;
+constexpr size_t kTauGroupLds = 64 * 1024;
 
 // Upper bound tau on the budget-th smallest projected distance of one query,
 // and the query's row of the chunk mask:
 //   1. the squared distances from q' to every 64-point chunk centre (computed
-//      by dist_kernel, bf16 lower bounds), read four chunks per thread; with
-//      LROW the row is read from HBM once into LDS and every pass reads LDS;
+//      by dist_kernel, bf16 lower bounds), read four chunks per thread, and
+//      the minimum of every group of 64 chunks, which rules out the groups
+//      that cannot hold a chosen chunk or a passing one;
 //   2. the chunks nearest to q' that hold at least min(n, 2 * budget) points,
 //      chosen with a histogram of those distances weighted by chunk sizes;
 //   3. over the points of the chosen chunks, the budget-th smallest pd^2
@@ -1071,7 +1094,6 @@ constexpr size_t kTauRowLds = 80 * 1024;
 //
 // Mask layout (query-major, bit-sliced to match four chunks per thread): bit l
 // of word 4 g + k of a query's row is chunk 256 g + 4 l + k.
-template <bool LROW>
 __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
@@ -1080,31 +1102,21 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     load_query(a, qi, nullptr, qc);
     const int nch = (int)(a.n_pad16 >> 6);
     const int ng4 = (nch + 3) >> 2;
+    const int ngr = (nch + 63) >> 6;
     // four bf16 distances per 8-byte element (element g: chunks 4 g .. 4 g + 3)
-    const uint2* grow = reinterpret_cast<const uint2*>(a.cdist + qi * a.ldc);
-    uint2* lrow = reinterpret_cast<uint2*>(smem_raw + offsetof(Smem, skey));
-    // each thread's smallest stored value (bf16 patterns of non-negative
-    // values order as unsigned integers), taken while the row is copied to
-    // LDS (a row read from HBM in every pass skips this bound: an extra pass
-    // costs more there than the atomics it saves)
-    uint32_t tmin = 0xffffu;
-    auto min4 = [](const uint2& v) {
-        return min(min(v.x & 0xffffu, v.x >> 16), min(v.y & 0xffffu, v.y >> 16));
-    };
-    if (LROW) {
-        for (int g = threadIdx.x; g < ng4; g += WG) {
-            const uint2 v = grow[g];
-            lrow[g] = v;
-            if (4 * g + 3 < nch) tmin = min(tmin, min4(v));
-            else
-                for (int k = 0; 4 * g + k < nch; ++k)
-                    tmin = min(tmin, (k & 1) ? ((k < 2 ? v.x : v.y) >> 16)
-                                             : ((k < 2 ? v.x : v.y) & 0xffffu));
-        }
-        __syncthreads();
+    const uint2* row4 = reinterpret_cast<const uint2*>(a.cdist + qi * a.ldc);
+    const uint16_t* grow16 = a.cdist + qi * a.ldc + a.goff;
+    // the group minima (copied to LDS when a.glds is set, else read in the
+    // row), then the list of candidate groups
+    unsigned char* lds_free = smem_raw + offsetof(Smem, skey);
+    const uint16_t* gmin = grow16;
+    if (a.glds) {
+        uint16_t* g = reinterpret_cast<uint16_t*>(lds_free);
+        for (int j = threadIdx.x; j < ngr; j += WG) g[j] = grow16[j];
+        gmin = g;
+        lds_free += 2 * (size_t)((ngr + 7) & ~7);
     }
-    const uint2* row4 = LROW ? lrow : grow;
-    int32_t* sel = a.csel + qi * kSelCap;
+    int32_t* glist = reinterpret_cast<int32_t*>(lds_free);
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     // bf16 bit pattern k of an element (non-negative values: ordered as
     // unsigned integers)
@@ -1112,6 +1124,52 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         const uint32_t w = k < 2 ? v.x : v.y;
         return (k & 1) ? (w >> 16) : (w & 0xffffu);
     };
+    const uint32_t hbase = kCenBinBase;
+    auto cbin = [&](uint32_t h) { return min(max(h >> 3, hbase) - hbase, (uint32_t)(NB - 1)); };
+    const int64_t want = a.n < 2 * (int64_t)a.budget ? a.n : 2 * (int64_t)a.budget;
+    const int wc = (int)min<int64_t>(nch, (want + 63) / 64 + 1);
+
+    // b0 bounds the bin sought in step 1 from above: every group holds a
+    // chunk at its minimum, so with wc groups whose minima lie in bins <= b0
+    // at least wc chunks lie there, and only chunks in those bins need to be
+    // counted. A group whose minimum lies above b0 holds none of them: the
+    // passes visit only the ngl groups listed (the whole row when more than
+    // a.grp_cap groups qualify).
+    clear_hist(sh);
+    for (int j = threadIdx.x; j < ngr; j += WG) atomicAdd(&sh.hist[cbin(gmin[j])], 1u);
+    if (threadIdx.x == 0) {
+        sh.thr_bin = NB - 1;
+        sh.cnt0 = 0;
+    }
+    __syncthreads();
+    uint32_t b0 = NB - 1;
+    if (ngr >= wc) {
+        find_threshold(wc, sh);
+        b0 = (uint32_t)sh.thr_bin;
+    }
+    for (int j0 = 0; j0 < ngr; j0 += WG) {
+        const int j = j0 + threadIdx.x;
+        const bool take = j < ngr && cbin(gmin[j]) <= b0;
+        const int slot = wave_append(take, &sh.cnt0);
+        if (take && slot < a.grp_cap) glist[slot] = j;
+    }
+    __syncthreads();
+    const int ngl = sh.cnt0;
+    const bool grp = ngl <= a.grp_cap;
+    __syncthreads();
+    // f(g, element g of the row) for every element of the listed groups, or
+    // of the whole row (16 consecutive threads read a group's 128 bytes)
+    auto for_elems = [&](auto&& f) {
+        if (grp) {
+            for (int e = threadIdx.x; e < 16 * ngl; e += WG) {
+                const int g = 16 * glist[e >> 4] + (e & 15);
+                if (g < ng4) f(g, row4[g]);
+            }
+        } else {
+            for (int g = threadIdx.x; g < ng4; g += WG) f(g, row4[g]);
+        }
+    };
+    int32_t* sel = a.csel + qi * kSelCap;
 
     // 1: histogram of the centre distances (chunk counts) on fixed bins: 16
     // per octave of the squared distance over [2^-64, 2^64), clamped at both
@@ -1119,34 +1177,14 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     // bins up to the one where the running count reaches wc = min(n_chunks,
     // ceil(want / 64) + 1) chunks, want = min(n, 2 * budget) points (the
     // extra chunk covers the one chunk with fewer than 64 points).
-    // Only the low end of the histogram matters: with b0 the bin where the
-    // running count of the threads' minima reaches wc, at least wc chunks
-    // lie in bins <= b0, so the bin sought is <= b0 and only those chunks
-    // need to be counted (most of the row lies far above).
-    const uint32_t hbase = kCenBinBase;
-    auto cbin = [&](uint32_t h) { return min(max(h >> 3, hbase) - hbase, (uint32_t)(NB - 1)); };
-    const int64_t want = a.n < 2 * (int64_t)a.budget ? a.n : 2 * (int64_t)a.budget;
-    const int wc = (int)min<int64_t>(nch, (want + 63) / 64 + 1);
-    uint32_t b0 = NB - 1;
-    if (LROW && min(ng4, WG) >= wc) {
-        clear_hist(sh);
-        if (threadIdx.x < ng4) atomicAdd(&sh.hist[cbin(tmin)], 1u);
-        __syncthreads();
-        if (threadIdx.x == 0) sh.thr_bin = NB - 1;
-        __syncthreads();
-        find_threshold(wc, sh);
-        b0 = (uint32_t)sh.thr_bin;
-        __syncthreads();
-    }
     clear_hist(sh);
-    for (int g = threadIdx.x; g < ng4; g += WG) {
-        const uint2 v = row4[g];
+    for_elems([&](int g, const uint2& v) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t b = cbin(half_k(v, k));
             if (4 * g + k < nch && b <= b0) atomicAdd(&sh.hist[b], 1u);
         }
-    }
+    });
     __syncthreads();
     if (threadIdx.x == 0) sh.thr_bin = NB - 1;
     __syncthreads();
@@ -1163,14 +1201,13 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     if (in_bin - need > 8 && tbin != 0u && tbin != (uint32_t)(NB - 1)) {
         __syncthreads();
         clear_hist(sh);
-        for (int g = threadIdx.x; g < ng4; g += WG) {
-            const uint2 v = row4[g];
+        for_elems([&](int g, const uint2& v) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t h = half_k(v, k);
                 if (4 * g + k < nch && (h >> 3) == tbin + hbase) atomicAdd(&sh.hist[h & 7u], 1u);
             }
-        }
+        });
         __syncthreads();
         if (threadIdx.x == 0) sh.thr_bin = NB - 1;
         __syncthreads();
@@ -1187,8 +1224,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     if (threadIdx.x == 0) sh.cnt2 = 0;
     __syncthreads();
     float rmax = 0.f;
-    for (int g = threadIdx.x; g < ng4; g += WG) {
-        const uint2 v = row4[g];
+    for_elems([&](int g, const uint2& v) {
         bool tk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) tk[k] = 4 * g + k < nch && half_k(v, k) <= tlim;
@@ -1209,7 +1245,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
                 }
             }
         }
-    }
+    });
     for (int off = 32; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
     if (lane == 0) sh.red[wave] = __float_as_int(rmax);
     __syncthreads();
@@ -1253,7 +1289,9 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     int npass = 0;
     // 4: the chunk-ball test; the radius covers the FP32 errors of pd^2 and
     // of the test's own distance (relative 2^-16 and 1e-5 (tau + S)), the
-    // additive term the rounding of the expanded squared distance
+    // additive term the rounding of the expanded squared distance. A group
+    // whose minimum fails the test with the group's largest radius holds no
+    // passing chunk, and its part of the row is not read.
     {
         const float tq0 = sqrtf(R2);
         const float tq = tq0 * (1.f + 1.52587890625e-05f) + 1e-5f * (tq0 + a.coord_scale);
@@ -1261,11 +1299,19 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         const float dmarg = 64.f * 5.9604645e-08f * big * big;
         const int ng256 = (nch + 255) >> 8;
         const float4* rad4 = reinterpret_cast<const float4*>(a.chunk_rad);
-        for (int G = wave; G < ng256; G += NWAVE) {
+        auto group_live = [&](int j) {
+            const float r = a.group_rad[j] + tq;
+            return __uint_as_float((uint32_t)gmin[j] << 16) <= fmaf(r, r, dmarg);
+        };
+        // block G: chunks 256 G .. 256 G + 255, words 4 G .. 4 G + 3 of the row
+        auto test_block = [&](int G) {
             const int g = (G << 6) + lane;
+            bool live = g < ng4;
+            // chunks 4 g .. 4 g + 3 lie in group g / 16
+            if (live) live = group_live(g >> 4);
             uint2 v = make_uint2(0u, 0u);
             float4 rv = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (g < ng4) {
+            if (live) {
                 v = row4[g];
                 rv = rad4[g];
             }
@@ -1274,7 +1320,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             for (int k = 0; k < 4; ++k) {
                 const float r = (k == 0 ? rv.x : k == 1 ? rv.y : k == 2 ? rv.z : rv.w) + tq;
                 const float d2 = __uint_as_float(half_k(v, k) << 16);
-                bk[k] = __builtin_amdgcn_ballot_w64(g < ng4 && 4 * g + k < nch &&
+                bk[k] = __builtin_amdgcn_ballot_w64(live && 4 * g + k < nch &&
                                                     d2 <= fmaf(r, r, dmarg));
             }
             if (lane < 4) {
@@ -1282,7 +1328,35 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
                 a.qmask[qi * a.mwords + 4 * G + lane] = w;
             }
             npass += __popcll(bk[0]) + __popcll(bk[1]) + __popcll(bk[2]) + __popcll(bk[3]);
+        };
+        bool all_blocks = true;
+        if (a.grp_cap > 0) {
+            // blocks with a live group go to the list (the group list is no
+            // longer needed); the words of the other blocks are zero
+            if (threadIdx.x == 0) sh.cnt0 = 0;
+            __syncthreads();
+            for (int G0 = 0; G0 < ng256; G0 += WG) {
+                const int G = G0 + threadIdx.x;
+                bool live = false;
+                if (G < ng256)
+                    for (int j = 4 * G; j < min(4 * G + 4, ngr); ++j) live = live || group_live(j);
+                const int slot = wave_append(live, &sh.cnt0);
+                if (live && slot < a.grp_cap) glist[slot] = G;
+                if (G < ng256 && !live) {
+                    uint4* w = reinterpret_cast<uint4*>(a.qmask + qi * a.mwords + 4 * G);
+                    w[0] = make_uint4(0u, 0u, 0u, 0u);
+                    w[1] = make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
+            __syncthreads();
+            const int nbl = sh.cnt0;
+            if (nbl <= a.grp_cap) {
+                all_blocks = false;
+                for (int i = wave; i < nbl; i += NWAVE) test_block(glist[i]);
+            }
         }
+        if (all_blocks)
+            for (int G = wave; G < ng256; G += NWAVE) test_block(G);
     }
     // points the scan examines for this query: 64 per passing chunk
     npass = block_sum(lane == 0 ? npass : 0, sh);
@@ -1885,6 +1959,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.scale16 = x.scale16;
     a.chunk_cen = x.chunk_cen;
     a.chunk_rad = x.chunk_rad;
+    a.group_rad = x.group_rad;
     a.data16 = x.data16;
     a.d16_scale = x.data16_scale;
     a.d16_eps = x.data16_eps;
@@ -1899,7 +1974,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.cmask = L.ws_cmask;
         a.cwords = (int)((L.nq + 63) / 64);
         a.cdist = L.ws_cdist2;
-        a.ldc = (x.n_pad16 / 64 + 15) / 16 * 16;
+        a.ldc = cdist_row_len(x.n_pad16 / 64);
+        a.goff = cdist_row_offset_groups(x.n_pad16 / 64);
         a.csel = L.ws_csel;
         a.ws_clo = L.ws_clo;
         a.q_flag = L.q_flag;
@@ -1917,20 +1993,16 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         }
         {
             StageTimer tm(PMLSH_STAGE_TAU, stream);
-            // the query's row of centre distances stays in LDS (in place of
-            // the selection arrays the bound kernel does not use) when it
-            // fits there
-            const size_t row_bytes = (size_t)8 * ((nchunk + 3) / 4);
-            const size_t lds_row = offsetof(Smem, skey) + row_bytes;
-            if (lds_row <= kTauRowLds) {
-                const int lds_t = (int)std::max(lds_row, (size_t)lds0);
-                PMLSH_HIP(hipFuncSetAttribute((const void*)tau_kernel<true>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_t));
-                hipLaunchKernelGGL(tau_kernel<true>, dim3((unsigned)L.nq), dim3(WG), lds_t, stream, a);
-            } else {
-                hipLaunchKernelGGL(tau_kernel<false>, dim3((unsigned)L.nq), dim3(WG), lds0, stream,
-                                   a);
-            }
+            const int64_t ngr = (nchunk + 63) / 64;
+            a.grp_cap = (int)std::min<int64_t>(kGrpCap, std::max<int64_t>(0, tune_get(PMLSH_TUNE_GROUP_LIST)));
+            const size_t min_bytes = 2 * (size_t)((ngr + 7) & ~7);
+            a.glds = tune_get(PMLSH_TUNE_GROUP_MINIMA_LDS) != 0 &&
+                     min_bytes + 4 * (size_t)kGrpCap <= kTauGroupLds;
+            const size_t lds_t = std::max((size_t)lds0, offsetof(Smem, skey) +
+                                          (a.glds ? min_bytes : 0) + 4 * (size_t)kGrpCap);
+            PMLSH_HIP(hipFuncSetAttribute((const void*)tau_kernel,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_t));
+            hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), (unsigned)lds_t, stream, a);
             PMLSH_HIP(hipGetLastError());
             const int64_t waves = (L.nq + 63) / 64 * a.mwords;
             hipLaunchKernelGGL(mask_transpose_kernel, dim3((unsigned)((waves + NWAVE - 1) / NWAVE)),

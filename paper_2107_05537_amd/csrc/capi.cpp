@@ -66,7 +66,7 @@ AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
     w.per_query = (int64_t)MP * 4 + 64 + B * 8 + 3 * (int64_t)k * 4 +
                   (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
-    w.ldc = (w.nchunk + 15) / 16 * 16;
+    w.ldc = cdist_row_len(w.nchunk);
     w.mwords = 4 * ((w.nchunk + 255) / 256);
     const int64_t per_query_all =
         w.per_query + (w.fast ? 8 * w.mwords + 2 * w.ldc + 4 * kSelCap + (w.nchunk + 7) / 8 : 0);
@@ -354,6 +354,16 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset) {
     return guarded([&] {
         if (!out) fail(PMLSH_EINVAL, "out is NULL");
         timing_read(out, reset != 0);
+    });
+}
+
+int pmlsh_tune(int key, int64_t value) {
+    return guarded([&] {
+        if (key < 0 || key >= PMLSH_N_TUNE) fail(PMLSH_EINVAL, "unknown tuning key");
+        if (value == -1) value = tune_default(key);
+        const int64_t hi = key == PMLSH_TUNE_GROUP_LIST ? 2048 : 1;
+        if (value < 0 || value > hi) fail(PMLSH_EINVAL, "tuning value out of range");
+        tune_set(key, value);
     });
 }
 

@@ -26,6 +26,14 @@ constexpr float kScanMarginWeight = 0.001953125f + 0.00006103515625f;
 // the largest budget of the batched path).
 constexpr int kSelCap = 1024;
 
+// Row of the per-query chunk-distance matrix (bf16 values): the n_chunk
+// distances, padded to a multiple of 16, then the minimum of every group of
+// 64 chunks, padded to a multiple of 16.
+inline int64_t cdist_row_offset_groups(int64_t n_chunk) { return (n_chunk + 15) / 16 * 16; }
+inline int64_t cdist_row_len(int64_t n_chunk) {
+    return cdist_row_offset_groups(n_chunk) + ((n_chunk + 63) / 64 + 15) / 16 * 16;
+}
+
 // Thread-local error message returned by pmlsh_last_error().
 void set_error(const std::string& msg);
 void clear_error();
@@ -151,6 +159,7 @@ struct pmlsh_index {
     float scale16 = 1.f;         // power-of-two scale s of those rows
     float* chunk_cen = nullptr;  // n_pad16 / 64 x MP: centre of each 64-point chunk
     float* chunk_rad = nullptr;  // n_pad16 / 64: radius covering the chunk's points
+    float* group_rad = nullptr;  // per 64 consecutive chunks: the largest of their radii
     uint16_t* data16 = nullptr;  // n x d16 FP16 copy of D_leaf, rows scaled by a power of two
     float* data16_scale = nullptr;  // n: that power of two
     float* data16_eps = nullptr;    // n: bound on |row - scale * FP16 row|
@@ -177,6 +186,10 @@ namespace pmlsh {
 
 // ---------------------------------------------------------------- timing
 bool timing_enabled(int stage);
+// process-wide switches of pmlsh_tune
+int64_t tune_default(int key);
+int64_t tune_get(int key);
+void tune_set(int key, int64_t value);
 void timing_set(unsigned stage_mask);
 void timing_read(pmlsh_ann_timing* out, bool reset);
 

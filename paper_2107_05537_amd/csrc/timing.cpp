@@ -4,6 +4,7 @@
 // read, and then reused, so a timed stage adds two event records per launch
 // and no host synchronisation to the query path.
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -95,5 +96,14 @@ void timing_read(pmlsh_ann_timing* out, bool reset) {
         if (reset) { g_ms[i] = 0; g_count[i] = 0; }
     }
 }
+
+// ---------------------------------------------------------------- switches
+namespace {
+std::atomic<int64_t> g_tune[PMLSH_N_TUNE] = {{2048}, {1}};
+}  // namespace
+
+int64_t tune_default(int key) { return key == PMLSH_TUNE_GROUP_LIST ? 2048 : 1; }
+int64_t tune_get(int key) { return g_tune[key].load(std::memory_order_relaxed); }
+void tune_set(int key, int64_t value) { g_tune[key].store(value, std::memory_order_relaxed); }
 
 }  // namespace pmlsh

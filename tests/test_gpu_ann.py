@@ -313,10 +313,49 @@ def test_headline_scale_sampled():
     say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
 
 
-def test_large_n_row_in_hbm_sampled():
-    """2,600,000 x 16 mixture: the per-query row of chunk-centre distances is
-    too long for LDS, so the bound kernel reads it from HBM in every pass;
-    16 sampled queries of one launch checked against the oracle."""
+GROUP_SETTINGS = [(2048, 0), (0, 1), (1, 1), (7, 0)]
+
+
+def _with_tuning(pm, cap, lds, fn):
+    pm.tune(pm.TUNE_GROUP_LIST, cap)
+    pm.tune(pm.TUNE_GROUP_MINIMA_LDS, lds)
+    try:
+        return fn()
+    finally:
+        pm.tune(pm.TUNE_GROUP_LIST, -1)
+        pm.tune(pm.TUNE_GROUP_MINIMA_LDS, -1)
+
+
+def test_group_filter_settings_agree(parity_wl):
+    """The bound kernel's group filter with its minima in HBM, with no group
+    list (whole-row passes), and with lists too short for the qualifying
+    groups: every answer equals the default run's, which the oracle pins."""
+    pm = _gpu()
+    D, A, Q = parity_wl["D"], parity_wl["A"], parity_wl["Q"]
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    for beta in (0.01, 0.1):
+        ref = [t.cpu().numpy() for t in idx.ann(Qd, 10, c=1.5, beta=beta, stats=True)]
+        for cap, lds in GROUP_SETTINGS:
+            say(f"case: beta={beta} group list {cap} minima in LDS {lds}")
+            out = _with_tuning(pm, cap, lds,
+                               lambda: [t.cpu().numpy() for t in
+                                        idx.ann(Qd, 10, c=1.5, beta=beta, stats=True)])
+            np.testing.assert_array_equal(out[0], ref[0])
+            np.testing.assert_array_equal(out[1], ref[1])
+            np.testing.assert_array_equal(out[2][:, :3], ref[2][:, :3])
+    with pytest.raises(pm.PmlshError):
+        pm.tune(pm.TUNE_GROUP_LIST, 2049)
+    with pytest.raises(pm.PmlshError):
+        pm.tune(2, 0)
+
+
+def test_large_n_sampled():
+    """2,600,000 x 16 mixture (635 groups of 64 chunks per query row): 16
+    sampled queries of one launch checked against the oracle, and the whole
+    launch repeated under every setting of the group filter (minima in HBM,
+    whole-row passes, short lists) with identical answers."""
     pm = _gpu()
     say("case: n=2.6M, d=16")
     spec = synth.MixtureSpec(n=2_600_000, d=16, n_centres=2_000, centre_std=2.0,
@@ -328,8 +367,8 @@ def test_large_n_row_in_hbm_sampled():
     idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
     B = min(D.shape[0], math.ceil(beta * D.shape[0]) + k)
     r0 = oracle_r_min(D, 0x5EED, B)
-    ids, dist, st = idx.ann(torch.from_numpy(Q).to(dev), k, c=1.5, beta=beta, r_min=r0,
-                            stats=True)
+    Qd = torch.from_numpy(Q).to(dev)
+    ids, dist, st = idx.ann(Qd, k, c=1.5, beta=beta, r_min=r0, stats=True)
     torch.cuda.synchronize()
     ids, dist, st = ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
     from oracle import ann as oann
@@ -338,3 +377,11 @@ def test_large_n_row_in_hbm_sampled():
     res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
     compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
     say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
+    for cap, lds in GROUP_SETTINGS:
+        say(f"case: n=2.6M group list {cap} minima in LDS {lds}")
+        o_ids, o_dist, o_st = _with_tuning(
+            pm, cap, lds, lambda: [t.cpu().numpy() for t in
+                                   idx.ann(Qd, k, c=1.5, beta=beta, r_min=r0, stats=True)])
+        np.testing.assert_array_equal(o_ids, ids)
+        np.testing.assert_array_equal(o_dist, dist)
+        np.testing.assert_array_equal(o_st[:, :3], st[:, :3])
