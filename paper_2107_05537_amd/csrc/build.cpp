@@ -127,7 +127,13 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
 
     // ---- tree
     HostTree T;
-    build_tree(proj.data(), n, x->leaf_size, x->fanout, x->num_pivots, &T);
+    {
+        std::vector<int32_t> perm;
+        std::vector<SplitNode> split;
+        device_split(static_cast<const float*>(phi.p), n, x->leaf_size, st, &perm, &split);
+        build_tree(proj.data(), n, x->leaf_size, x->fanout, x->num_pivots, std::move(perm), split,
+                   &T);
+    }
     x->levels = T.levels;
     x->n_nodes = T.n_nodes;
     x->level_begin = T.level_begin;

@@ -126,9 +126,23 @@ struct HostTree {
     float coord_scale = 0.f;              // max ||o'|| + max ||p_i||
 };
 
-// Bulk-loads the tree over projected points proj (n x MP, original order).
-void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
-                int num_pivots, HostTree* out);
+// Binary split tree of the leaf order: node 0 is the root; a node covers the
+// leaves [leaf_begin, leaf_end); left and right are -1 for a leaf.
+struct SplitNode {
+    int64_t leaf_begin, leaf_end;
+    int32_t left, right;
+};
+
+// Recursive gap-aware splits of the leaf order on the device, level by level
+// (bulkload.hip): proj is the device projection (n x MP, original order);
+// returns the leaf order (leaf position -> id) and the split tree.
+void device_split(const float* proj, int64_t n, int leaf, hipStream_t st,
+                  std::vector<int32_t>* perm, std::vector<SplitNode>* nodes);
+
+// Bulk-loads the tree over projected points proj (host, n x MP, original
+// order) from the leaf order and split tree of device_split.
+void build_tree(const float* proj, int64_t n, int leaf_size, int fanout, int num_pivots,
+                std::vector<int32_t> perm, const std::vector<SplitNode>& split, HostTree* out);
 
 // ---------------------------------------------------------------- index
 struct DeviceTree {

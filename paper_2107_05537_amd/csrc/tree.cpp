@@ -5,9 +5,10 @@
 // whole point set is known up front, so the tree is bulk-loaded:
 //   * global pivots p_1..p_s by farthest-point selection (the paper only asks
 //     for pivots that keep the node regions small);
-//   * leaves by recursive median splits along the coordinate of largest
-//     variance, the left part always holding a whole number of leaves, so
-//     every leaf has exactly leaf_size points except the last one;
+//   * leaves by recursive gap-aware splits along each node's principal
+//     direction (computed on the device, bulkload.hip), the left part always
+//     holding a whole number of leaves, so every leaf has exactly leaf_size
+//     points except the last one;
 //   * inner levels from the binary split tree: level l holds the maximal
 //     subtrees with at most fanout^(H-1-l) leaves, so inner nodes are compact
 //     regions and the fanout is about `fanout` (not exactly).
@@ -69,118 +70,10 @@ double dist64(const float* a, const float* b) {
     return std::sqrt(s);
 }
 
-// Recursive split of idx[b, e) into whole leaves. A node is cut along its
-// principal direction (power iteration on its 16 x 16 covariance) at the
-// leaf boundary, within the middle 60 % of its leaves, where the sorted
-// projections show the widest gap, so cuts fall between clusters rather
-// than through them. Ties in the projection are ordered by id.
-struct BinNode {
-    int64_t leaf_begin, leaf_end;   // leaf range [begin, end)
-    int32_t left, right;            // children (-1 for a leaf)
-};
-
-struct Splitter {
-    const float* proj;
-    int64_t leaf;
-    std::vector<int32_t>& idx;
-    std::vector<BinNode> nodes;
-    std::mutex mu;
-
-    int32_t add_node(int64_t b, int64_t e) {
-        std::lock_guard<std::mutex> lk(mu);
-        nodes.push_back({b / leaf, (e + leaf - 1) / leaf, -1, -1});
-        return (int32_t)nodes.size() - 1;
-    }
-    void set_children(int32_t id, int32_t l, int32_t r) {
-        std::lock_guard<std::mutex> lk(mu);
-        nodes[id].left = l;
-        nodes[id].right = r;
-    }
-
-    void direction(int64_t b, int64_t e, double* dir) const {
-        double mean[MP] = {0};
-        for (int64_t i = b; i < e; ++i) {
-            const float* p = proj + (int64_t)idx[i] * MP;
-            for (int j = 0; j < MP; ++j) mean[j] += p[j];
-        }
-        const double cnt = (double)(e - b);
-        for (int j = 0; j < MP; ++j) mean[j] /= cnt;
-        double cov[MP][MP] = {{0}};
-        for (int64_t i = b; i < e; ++i) {
-            const float* p = proj + (int64_t)idx[i] * MP;
-            double c[MP];
-            for (int j = 0; j < MP; ++j) c[j] = p[j] - mean[j];
-            for (int j = 0; j < MP; ++j)
-                for (int k = j; k < MP; ++k) cov[j][k] += c[j] * c[k];
-        }
-        for (int j = 0; j < MP; ++j)
-            for (int k = 0; k < j; ++k) cov[j][k] = cov[k][j];
-        // start from the coordinate axis of largest variance
-        int ax = 0;
-        for (int j = 1; j < MP; ++j)
-            if (cov[j][j] > cov[ax][ax]) ax = j;
-        for (int j = 0; j < MP; ++j) dir[j] = j == ax ? 1.0 : 0.0;
-        for (int it = 0; it < 30; ++it) {
-            double nd[MP] = {0}, nrm = 0;
-            for (int j = 0; j < MP; ++j) {
-                for (int k = 0; k < MP; ++k) nd[j] += cov[j][k] * dir[k];
-                nrm += nd[j] * nd[j];
-            }
-            nrm = std::sqrt(nrm);
-            if (!(nrm > 0)) break;
-            for (int j = 0; j < MP; ++j) dir[j] = nd[j] / nrm;
-        }
-    }
-
-    int32_t split(int64_t b, int64_t e, int depth) {
-        const int32_t id = add_node(b, e);
-        const int64_t cnt = e - b;
-        if (cnt <= leaf) return id;
-        const int64_t nleaves = (cnt + leaf - 1) / leaf;
-        double dir[MP];
-        direction(b, e, dir);
-        std::vector<std::pair<double, int32_t>> key((size_t)cnt);
-        for (int64_t i = 0; i < cnt; ++i) {
-            const float* p = proj + (int64_t)idx[b + i] * MP;
-            double v = 0;
-            for (int j = 0; j < MP; ++j) v += dir[j] * p[j];
-            key[(size_t)i] = {v, idx[b + i]};
-        }
-        std::sort(key.begin(), key.end());
-        for (int64_t i = 0; i < cnt; ++i) idx[b + i] = key[(size_t)i].second;
-        // candidate cuts after j whole leaves, j in the middle 60 %
-        int64_t jlo = std::max<int64_t>(1, (nleaves * 2) / 10);
-        int64_t jhi = std::min<int64_t>(nleaves - 1, nleaves - (nleaves * 2) / 10);
-        if (jhi < jlo) jlo = jhi = nleaves / 2;
-        int64_t best = nleaves / 2;
-        double gap = -1;
-        for (int64_t j = jlo; j <= jhi; ++j) {
-            const int64_t p = j * leaf;
-            if (p <= 0 || p >= cnt) continue;
-            const double g = key[(size_t)p].first - key[(size_t)p - 1].first;
-            if (g > gap) { gap = g; best = j; }
-        }
-        const int64_t mid = b + best * leaf;
-        key.clear();
-        key.shrink_to_fit();
-        int32_t l = -1, r = -1;
-        if (depth < 4 && cnt > 200000) {
-            std::thread left([&] { l = split(b, mid, depth + 1); });
-            r = split(mid, e, depth + 1);
-            left.join();
-        } else {
-            l = split(b, mid, depth + 1);
-            r = split(mid, e, depth + 1);
-        }
-        set_children(id, l, r);
-        return id;
-    }
-};
-
 }  // namespace
 
-void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
-                int num_pivots, HostTree* out) {
+void build_tree(const float* proj, int64_t n, int leaf_size, int fanout, int num_pivots,
+                std::vector<int32_t> perm_in, const std::vector<SplitNode>& bt, HostTree* out) {
     HostTree& T = *out;
     const int s = num_pivots;
 
@@ -213,14 +106,10 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
         }
     }
 
-    // ---- leaf order by recursive gap-aware splits; the binary split tree is
-    // recorded (leaf ranges) to derive the inner levels from it
-    T.perm.resize(n);
-    std::iota(T.perm.begin(), T.perm.end(), 0);
-    Splitter sp{proj, leaf_size, T.perm};
-    sp.split(0, n, 0);
+    // ---- leaf order and binary split tree (leaf ranges) of the recursive
+    // gap-aware splits; the inner levels are derived from the split tree
+    T.perm = std::move(perm_in);
     const int64_t n_leaves = (n + leaf_size - 1) / leaf_size;
-    const std::vector<BinNode>& bt = sp.nodes;   // node 0 is the root
 
     // Level l (of H) holds the maximal binary subtrees with at most
     // fanout^(H-1-l) leaves, left to right: compact regions, nested in the
@@ -230,7 +119,7 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout,
         std::vector<std::pair<int64_t, int64_t>> out;   // leaf ranges
         std::vector<int32_t> stack{0};
         while (!stack.empty()) {
-            const BinNode& b = bt[stack.back()];
+            const SplitNode& b = bt[stack.back()];
             stack.pop_back();
             if (b.leaf_end - b.leaf_begin <= cap || b.left < 0) {
                 out.push_back({b.leaf_begin, b.leaf_end});
