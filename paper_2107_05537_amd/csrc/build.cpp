@@ -107,7 +107,7 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         H = static_cast<const float*>(hsrc.p);
     }
     // Device data is not scanned for non-finite values separately: the
-    // projection propagates any NaN/inf into O', which is checked on the host.
+    // projection propagates any NaN/inf into O', which is checked below.
     x->hash = dev_alloc<float>(x, (int64_t)MP * d);
     PMLSH_HIP(hipMemsetAsync(x->hash, 0, (size_t)MP * d * sizeof(float), st));
     PMLSH_HIP(hipMemcpyAsync(x->hash, H, (size_t)a->m * d * sizeof(float),
@@ -118,12 +118,8 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     PMLSH_HIP(hipMalloc(&phi.p, (size_t)n * MP * sizeof(float)));
     PMLSH_HIP(hipMalloc(&plo.p, (size_t)n * MP * sizeof(float)));
     launch_project(D, n, d, d, x->hash, static_cast<float*>(phi.p), static_cast<float*>(plo.p), st);
-    std::vector<float> proj((size_t)n * MP);
-    PMLSH_HIP(hipMemcpyAsync(proj.data(), phi.p, proj.size() * sizeof(float),
-                             hipMemcpyDeviceToHost, st));
-    PMLSH_HIP(hipStreamSynchronize(st));
-    for (float v : proj)
-        if (!std::isfinite(v)) fail(PMLSH_EINVAL, "data or hash holds a non-finite value");
+    if (!device_all_finite(static_cast<const float*>(phi.p), n * MP, st))
+        fail(PMLSH_EINVAL, "data or hash holds a non-finite value");
 
     // ---- tree
     HostTree T;
@@ -131,8 +127,11 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         std::vector<int32_t> perm;
         std::vector<SplitNode> split;
         device_split(static_cast<const float*>(phi.p), n, x->leaf_size, st, &perm, &split);
-        build_tree(proj.data(), n, x->leaf_size, x->fanout, x->num_pivots, std::move(perm), split,
-                   &T);
+        x->perm = dev_alloc<int32_t>(x, n);
+        PMLSH_HIP(hipMemcpyAsync(x->perm, perm.data(), (size_t)n * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+        build_tree(static_cast<const float*>(phi.p), n, x->leaf_size, x->fanout, x->num_pivots,
+                   std::move(perm), x->perm, split, st, &T);
     }
     x->levels = T.levels;
     x->n_nodes = T.n_nodes;
@@ -147,7 +146,6 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         PMLSH_HIP(hipMemcpyAsync(*dst, vec.data(), vec.size() * sizeof(E),
                                  hipMemcpyHostToDevice, st));
     };
-    upload(T.perm, &x->perm);
     std::vector<int32_t> inv(n);
     for (int64_t j = 0; j < n; ++j) inv[T.perm[j]] = (int32_t)j;
     upload(inv, &x->inv_perm);
@@ -188,27 +186,22 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         launch_augment16(x->proj_hi, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
         // covering ball of every 64-point chunk of the leaf order (the leaves
         // themselves when the leaf size is 64): FP64 mean rounded to FP32,
-        // radius measured from that FP32 centre and rounded up
+        // radius measured from that FP32 centre in FP64, widened by 1e-6 and
+        // rounded up
         const int64_t nch = x->n_pad16 / 64;
-        // radii padded with zeros to a multiple of 16 chunks (vector loads)
-        std::vector<float> ccen((size_t)nch * MP, 0.f), crad((size_t)((nch + 15) / 16 * 16), 0.f);
+        std::vector<int64_t> c0((size_t)nch), c1((size_t)nch);
         for (int64_t c = 0; c < nch; ++c) {
-            const int64_t j0 = c * 64, j1 = std::min<int64_t>(n, j0 + 64);
-            double mean[MP] = {0.0};
-            for (int64_t j = j0; j < j1; ++j)
-                for (int t = 0; t < MP; ++t) mean[t] += proj[(size_t)T.perm[j] * MP + t];
-            for (int t = 0; t < MP; ++t) ccen[(size_t)c * MP + t] = (float)(mean[t] / (double)(j1 - j0));
-            double r2 = 0.0;
-            for (int64_t j = j0; j < j1; ++j) {
-                double acc = 0.0;
-                for (int t = 0; t < MP; ++t) {
-                    const double dlt = (double)proj[(size_t)T.perm[j] * MP + t] - ccen[(size_t)c * MP + t];
-                    acc += dlt * dlt;
-                }
-                r2 = std::max(r2, acc);
-            }
-            crad[c] = std::nextafter((float)(std::sqrt(r2) * (1.0 + 1e-6)), INFINITY);
+            c0[(size_t)c] = c * 64;
+            c1[(size_t)c] = std::min<int64_t>(n, c * 64 + 64);
         }
+        std::vector<float> ccen;
+        std::vector<double> r64, unused;
+        device_ball_summaries(static_cast<const float*>(phi.p), x->perm, c0, c1, nullptr, 0, st,
+                              &ccen, &r64, &unused);
+        // radii padded with zeros to a multiple of 16 chunks (vector loads)
+        std::vector<float> crad((size_t)((nch + 15) / 16 * 16), 0.f);
+        for (int64_t c = 0; c < nch; ++c)
+            crad[(size_t)c] = std::nextafter((float)(r64[(size_t)c] * (1.0 + 1e-6)), INFINITY);
         // largest radius of every 64 consecutive chunks, padded with zeros to
         // a multiple of 16 groups
         const int64_t ngr = (nch + 63) / 64;

@@ -30,9 +30,10 @@ struct Piece {
     int32_t b, e;                // positions [b, e) of the leaf order
 };
 
-// Coordinate sums of every piece (four waves, shuffle then LDS, fixed order).
+// Coordinate sums of every piece (four waves, shuffle then LDS, fixed order);
+// positions are ids when perm is null.
 __global__ __launch_bounds__(256) void bl_sum_kernel(const float* __restrict__ proj,
-                                                      const int32_t* __restrict__ perm,
+                                                      const int32_t* perm,
                                                       const Piece* __restrict__ pieces,
                                                       double* __restrict__ part) {
     const Piece pc = pieces[blockIdx.x];
@@ -40,7 +41,8 @@ __global__ __launch_bounds__(256) void bl_sum_kernel(const float* __restrict__ p
 #pragma unroll
     for (int j = 0; j < MP; ++j) acc[j] = 0.0;
     for (int i = pc.b + (int)threadIdx.x; i < pc.e; i += 256) {
-        const float4* p = reinterpret_cast<const float4*>(proj + (int64_t)perm[i] * MP);
+        const int64_t row = perm ? (int64_t)perm[i] : (int64_t)i;
+        const float4* p = reinterpret_cast<const float4*>(proj + row * MP);
 #pragma unroll
         for (int q = 0; q < MP / 4; ++q) {
             const float4 v = p[q];
@@ -224,6 +226,199 @@ __global__ __launch_bounds__(256) void bl_cut_kernel(const int32_t* __restrict__
     if (lane == 0) mid[s] = b + (gap < 0.0 ? nleaves / 2 : best) * leaf;
 }
 
+__device__ __forceinline__ double dist64(const float* p, const float* c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+        const double t = (double)p[j] - (double)c[j];
+        acc = fma(t, t, acc);
+    }
+    return sqrt(acc);
+}
+
+// Mean of every node (sums / count, from bl_reduce_kernel) rounded to FP32.
+__global__ void bl_centre_kernel(const double* __restrict__ mean, int64_t count,
+                                 float* __restrict__ cf) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) cf[t] = (float)mean[t];
+}
+
+// Per piece: the largest FP64 distance of its points to their node's FP32
+// centre, and for every pivot the smallest and largest distance to it
+// (width 1 + 2 s per piece; min and max do not depend on the order).
+__global__ __launch_bounds__(256) void bl_ring_kernel(const float* __restrict__ proj,
+                                                       const int32_t* __restrict__ perm,
+                                                       const Piece* __restrict__ pieces,
+                                                       const float* __restrict__ cf,
+                                                       const float* __restrict__ piv, int s,
+                                                       double* __restrict__ part) {
+    const Piece pc = pieces[blockIdx.x];
+    __shared__ float c[MP];
+    __shared__ float pv[PMLSH_MAX_PIVOTS][MP];
+    __shared__ double red[4][1 + 2 * PMLSH_MAX_PIVOTS];
+    if (threadIdx.x < MP) c[threadIdx.x] = cf[(int64_t)pc.seg * MP + threadIdx.x];
+    if (threadIdx.x < s * MP) pv[threadIdx.x / MP][threadIdx.x % MP] = piv[threadIdx.x];
+    __syncthreads();
+    double rad = 0.0, lo[PMLSH_MAX_PIVOTS], hi[PMLSH_MAX_PIVOTS];
+#pragma unroll
+    for (int t = 0; t < PMLSH_MAX_PIVOTS; ++t) {
+        lo[t] = __longlong_as_double(0x7ff0000000000000ll);
+        hi[t] = 0.0;
+    }
+    for (int i = pc.b + (int)threadIdx.x; i < pc.e; i += 256) {
+        float p[MP];
+        const float4* src = reinterpret_cast<const float4*>(proj + (int64_t)perm[i] * MP);
+#pragma unroll
+        for (int q = 0; q < MP / 4; ++q) {
+            const float4 v = src[q];
+            p[4 * q] = v.x;
+            p[4 * q + 1] = v.y;
+            p[4 * q + 2] = v.z;
+            p[4 * q + 3] = v.w;
+        }
+        rad = fmax(rad, dist64(p, c));
+#pragma unroll
+        for (int t = 0; t < PMLSH_MAX_PIVOTS; ++t) {
+            if (t < s) {
+                const double dd = dist64(p, pv[t]);
+                lo[t] = fmin(lo[t], dd);
+                hi[t] = fmax(hi[t], dd);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
+#pragma unroll
+    for (int t = 0; t < PMLSH_MAX_PIVOTS; ++t) {
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[t] = fmin(lo[t], __shfl_xor(lo[t], off));
+            hi[t] = fmax(hi[t], __shfl_xor(hi[t], off));
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = rad;
+        for (int t = 0; t < s; ++t) {
+            red[w][1 + 2 * t] = lo[t];
+            red[w][2 + 2 * t] = hi[t];
+        }
+    }
+    __syncthreads();
+    const int width = 1 + 2 * s;
+    if (threadIdx.x < width) {
+        const int e = threadIdx.x;
+        const bool is_min = e >= 1 && (e & 1);
+        double v = red[0][e];
+        for (int k = 1; k < 4; ++k) v = is_min ? fmin(v, red[k][e]) : fmax(v, red[k][e]);
+        part[(int64_t)blockIdx.x * width + e] = v;
+    }
+}
+
+// Per node and entry, the max (entry 0 and the even ones) or min (odd ones)
+// over its pieces.
+__global__ void bl_reduce_ring_kernel(const double* __restrict__ part, int width,
+                                      const int32_t* __restrict__ piece_begin, int m,
+                                      double* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * width) return;
+    const int sg = (int)(t / width), e = (int)(t % width);
+    const bool is_min = e >= 1 && (e & 1);
+    double v = part[(int64_t)piece_begin[sg] * width + e];
+    for (int p = piece_begin[sg] + 1; p < piece_begin[sg + 1]; ++p) {
+        const double x = part[(int64_t)p * width + e];
+        v = is_min ? fmin(v, x) : fmax(v, x);
+    }
+    out[t] = v;
+}
+
+// Farthest-point step over the ids [0, n): the distance of every point to
+// ref (an FP32 row), folded into mind[i] = min(mind[i], distance) when mind
+// is given; per workgroup the largest value and its smallest id.
+__global__ __launch_bounds__(256) void bl_far_kernel(const float* __restrict__ proj, int64_t n,
+                                                      const float* __restrict__ ref,
+                                                      double* mind, double* __restrict__ bval,
+                                                      int64_t* __restrict__ bidx) {
+    __shared__ float r[MP];
+    __shared__ double sv[4];
+    __shared__ int64_t si[4];
+    if (threadIdx.x < MP) r[threadIdx.x] = ref[threadIdx.x];
+    __syncthreads();
+    double best = -1.0;
+    int64_t bi = 0x7fffffffffffffffll;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double v = dist64(proj + i * MP, r);
+        if (mind) {
+            v = fmin(mind[i], v);
+            mind[i] = v;
+        }
+        if (v > best) { best = v; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int64_t oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = best;
+        si[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w)
+            if (sv[w] > best || (sv[w] == best && si[w] < bi)) { best = sv[w]; bi = si[w]; }
+        bval[blockIdx.x] = best;
+        bidx[blockIdx.x] = bi;
+    }
+}
+
+// The largest value over the workgroups of bl_far_kernel (smallest id on
+// ties); its point is copied to dst (an FP32 row) and its value to *val.
+__global__ __launch_bounds__(256) void bl_pick_kernel(const float* __restrict__ proj,
+                                                       const double* __restrict__ bval,
+                                                       const int64_t* __restrict__ bidx, int nb,
+                                                       float* __restrict__ dst,
+                                                       double* __restrict__ val) {
+    __shared__ double sv[4];
+    __shared__ int64_t si[4];
+    __shared__ int64_t pick;
+    double best = -1.0;
+    int64_t bi = 0x7fffffffffffffffll;
+    for (int b = threadIdx.x; b < nb; b += 256)
+        if (bval[b] > best || (bval[b] == best && bidx[b] < bi)) { best = bval[b]; bi = bidx[b]; }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int64_t oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = best;
+        si[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w)
+            if (sv[w] > best || (sv[w] == best && si[w] < bi)) { best = sv[w]; bi = si[w]; }
+        sv[0] = best;
+        pick = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x < MP && dst) dst[threadIdx.x] = proj[pick * MP + threadIdx.x];
+    if (threadIdx.x == 0 && val) *val = sv[0];
+}
+
+// Any non-finite value among count floats sets *flag (a plain store).
+__global__ void bl_finite_kernel(const float* __restrict__ x, int64_t count,
+                                 int32_t* __restrict__ flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) *flag = 1;
+}
+
+__global__ void bl_fill_kernel(double* __restrict__ x, int64_t count, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
 template <class T>
 struct DevVec {
     T* p = nullptr;
@@ -361,6 +556,164 @@ void device_split(const float* proj, int64_t n, int leaf, hipStream_t st,
     PMLSH_HIP(hipMemcpyAsync(perm_out->data(), perm.p, (size_t)n * sizeof(int32_t),
                              hipMemcpyDeviceToHost, st));
     PMLSH_HIP(hipStreamSynchronize(st));
+}
+
+namespace {
+
+// Pieces of at most kPiece positions for every range [p0[s], p1[s]), and the
+// first piece of every range (m + 1 entries).
+void make_pieces(const std::vector<int64_t>& p0, const std::vector<int64_t>& p1,
+                 std::vector<Piece>* pieces, std::vector<int32_t>* first) {
+    pieces->clear();
+    first->assign(p0.size() + 1, 0);
+    for (size_t sg = 0; sg < p0.size(); ++sg) {
+        if (p1[sg] > 0x7fffffffLL - kPiece) fail(PMLSH_EUNSUPPORTED, "point count out of range");
+        (*first)[sg] = (int32_t)pieces->size();
+        for (int64_t x = p0[sg]; x < p1[sg]; x += kPiece)
+            pieces->push_back({(int32_t)sg, (int32_t)x, (int32_t)std::min(p1[sg], x + kPiece)});
+    }
+    (*first)[p0.size()] = (int32_t)pieces->size();
+}
+
+}  // namespace
+
+bool device_all_finite(const float* x, int64_t count, hipStream_t st) {
+    DevVec<int32_t> flag;
+    int32_t* f = flag.get(1);
+    PMLSH_HIP(hipMemsetAsync(f, 0, sizeof(int32_t), st));
+    const int64_t blocks = std::min<int64_t>(4096, (count + 255) / 256);
+    if (blocks > 0)
+        hipLaunchKernelGGL(bl_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, count, f);
+    PMLSH_HIP(hipGetLastError());
+    int32_t h = 0;
+    PMLSH_HIP(hipMemcpyAsync(&h, f, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PMLSH_HIP(hipStreamSynchronize(st));
+    return h == 0;
+}
+
+void device_pivots(const float* proj, int64_t n, int s, hipStream_t st, std::vector<float>* pivots,
+                   double* max_norm) {
+    constexpr int kFarBlocks = 1024;
+    DevVec<double> bval, mind, part, mean, val;
+    DevVec<int64_t> bidx;
+    DevVec<float> rows;                 // centroid, zero row, then the s pivots
+    DevVec<Piece> d_pieces;
+    DevVec<int32_t> d_first;
+    const int nb = (int)std::min<int64_t>(kFarBlocks, (n + 255) / 256);
+    double* bv = bval.get((size_t)nb);
+    int64_t* bi = bidx.get((size_t)nb);
+    float* rw = rows.get((size_t)(2 + s) * MP);
+    double* dv = val.get(1);
+    PMLSH_HIP(hipMemsetAsync(rw, 0, (size_t)(2 + s) * MP * sizeof(float), st));
+    // largest norm: the farthest point from the zero row
+    hipLaunchKernelGGL(bl_far_kernel, dim3((unsigned)nb), dim3(256), 0, st, proj, n, rw + MP,
+                       nullptr, bv, bi);
+    hipLaunchKernelGGL(bl_pick_kernel, dim3(1), dim3(256), 0, st, proj, bv, bi, nb, nullptr, dv);
+    PMLSH_HIP(hipGetLastError());
+    PMLSH_HIP(hipMemcpyAsync(max_norm, dv, sizeof(double), hipMemcpyDeviceToHost, st));
+    pivots->assign((size_t)s * MP, 0.f);
+    if (s > 0) {
+        // centroid: FP64 sums over pieces of the ids, reduced in order
+        std::vector<Piece> pieces;
+        std::vector<int32_t> first;
+        make_pieces({0}, {n}, &pieces, &first);
+        Piece* dp = d_pieces.get(pieces.size());
+        int32_t* df = d_first.get(first.size());
+        PMLSH_HIP(hipMemcpyAsync(dp, pieces.data(), pieces.size() * sizeof(Piece),
+                                 hipMemcpyHostToDevice, st));
+        PMLSH_HIP(hipMemcpyAsync(df, first.data(), first.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+        double* pt = part.get(pieces.size() * MP);
+        double* mn = mean.get(MP);
+        hipLaunchKernelGGL(bl_sum_kernel, dim3((unsigned)pieces.size()), dim3(256), 0, st, proj,
+                           nullptr, dp, pt);
+        hipLaunchKernelGGL(bl_reduce_kernel, dim3(1), dim3(256), 0, st, pt, MP, df, 1, nullptr, mn);
+        PMLSH_HIP(hipGetLastError());
+        // the reduce kernel sums; the mean divides by n in FP64 on the host
+        double sums[MP];
+        PMLSH_HIP(hipMemcpyAsync(sums, mn, sizeof(sums), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        float cf[MP];
+        for (int j = 0; j < MP; ++j) cf[j] = (float)(sums[j] / (double)n);
+        PMLSH_HIP(hipMemcpyAsync(rw, cf, sizeof(cf), hipMemcpyHostToDevice, st));
+        // first pivot: the point farthest from the centroid; then each next
+        // pivot is the point farthest from the pivots chosen so far
+        double* md = mind.get((size_t)n);
+        hipLaunchKernelGGL(bl_fill_kernel, dim3(1024), dim3(256), 0, st, md, n,
+                           __builtin_huge_val());
+        hipLaunchKernelGGL(bl_far_kernel, dim3((unsigned)nb), dim3(256), 0, st, proj, n, rw, nullptr,
+                           bv, bi);
+        hipLaunchKernelGGL(bl_pick_kernel, dim3(1), dim3(256), 0, st, proj, bv, bi, nb,
+                           rw + 2 * MP, nullptr);
+        for (int p = 1; p < s; ++p) {
+            hipLaunchKernelGGL(bl_far_kernel, dim3((unsigned)nb), dim3(256), 0, st, proj, n,
+                               rw + (size_t)(1 + p) * MP, md, bv, bi);
+            hipLaunchKernelGGL(bl_pick_kernel, dim3(1), dim3(256), 0, st, proj, bv, bi, nb,
+                               rw + (size_t)(2 + p) * MP, nullptr);
+        }
+        PMLSH_HIP(hipGetLastError());
+        PMLSH_HIP(hipMemcpyAsync(pivots->data(), rw + 2 * MP, (size_t)s * MP * sizeof(float),
+                                 hipMemcpyDeviceToHost, st));
+    }
+    PMLSH_HIP(hipStreamSynchronize(st));
+}
+
+void device_ball_summaries(const float* proj, const int32_t* perm, const std::vector<int64_t>& p0,
+                           const std::vector<int64_t>& p1, const float* pivots, int s,
+                           hipStream_t st, std::vector<float>* centre, std::vector<double>* radius,
+                           std::vector<double>* ring) {
+    const int64_t m = (int64_t)p0.size();
+    const int width = 1 + 2 * s;
+    centre->assign((size_t)m * MP, 0.f);
+    radius->assign((size_t)m, 0.0);
+    ring->assign((size_t)m * 2 * s, 0.0);
+    if (m == 0) return;
+    std::vector<Piece> pieces;
+    std::vector<int32_t> first;
+    make_pieces(p0, p1, &pieces, &first);
+    std::vector<int32_t> cnt((size_t)m);
+    for (int64_t i = 0; i < m; ++i) cnt[(size_t)i] = (int32_t)(p1[(size_t)i] - p0[(size_t)i]);
+    DevVec<Piece> d_pieces;
+    DevVec<int32_t> d_first, d_cnt;
+    DevVec<double> part, mean, out;
+    DevVec<float> cf, piv;
+    Piece* dp = d_pieces.get(pieces.size());
+    int32_t* df = d_first.get(first.size());
+    int32_t* dc = d_cnt.get((size_t)m);
+    PMLSH_HIP(hipMemcpyAsync(dp, pieces.data(), pieces.size() * sizeof(Piece),
+                             hipMemcpyHostToDevice, st));
+    PMLSH_HIP(hipMemcpyAsync(df, first.data(), first.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, st));
+    PMLSH_HIP(hipMemcpyAsync(dc, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             st));
+    const int np = (int)pieces.size();
+    double* pt = part.get((size_t)np * std::max(MP, width));
+    double* mn = mean.get((size_t)m * MP);
+    float* c = cf.get((size_t)m * MP);
+    double* o = out.get((size_t)m * width);
+    float* pv = piv.get((size_t)std::max(1, s) * MP);
+    if (s > 0)
+        PMLSH_HIP(hipMemcpyAsync(pv, pivots, (size_t)s * MP * sizeof(float), hipMemcpyHostToDevice,
+                                 st));
+    hipLaunchKernelGGL(bl_sum_kernel, dim3((unsigned)np), dim3(256), 0, st, proj, perm, dp, pt);
+    hipLaunchKernelGGL(bl_reduce_kernel, dim3((unsigned)((m * MP + 255) / 256)), dim3(256), 0, st,
+                       pt, MP, df, (int)m, dc, mn);
+    hipLaunchKernelGGL(bl_centre_kernel, dim3((unsigned)((m * MP + 255) / 256)), dim3(256), 0, st,
+                       mn, m * MP, c);
+    hipLaunchKernelGGL(bl_ring_kernel, dim3((unsigned)np), dim3(256), 0, st, proj, perm, dp, c, pv,
+                       s, pt);
+    hipLaunchKernelGGL(bl_reduce_ring_kernel, dim3((unsigned)((m * width + 255) / 256)), dim3(256),
+                       0, st, pt, width, df, (int)m, o);
+    PMLSH_HIP(hipGetLastError());
+    std::vector<double> h((size_t)m * width);
+    PMLSH_HIP(hipMemcpyAsync(centre->data(), c, (size_t)m * MP * sizeof(float),
+                             hipMemcpyDeviceToHost, st));
+    PMLSH_HIP(hipMemcpyAsync(h.data(), o, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    PMLSH_HIP(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < m; ++i) {
+        (*radius)[(size_t)i] = h[(size_t)(i * width)];
+        for (int t = 0; t < 2 * s; ++t) (*ring)[(size_t)(i * 2 * s + t)] = h[(size_t)(i * width + 1 + t)];
+    }
 }
 
 }  // namespace pmlsh

@@ -139,10 +139,28 @@ struct SplitNode {
 void device_split(const float* proj, int64_t n, int leaf, hipStream_t st,
                   std::vector<int32_t>* perm, std::vector<SplitNode>* nodes);
 
-// Bulk-loads the tree over projected points proj (host, n x MP, original
-// order) from the leaf order and split tree of device_split.
+// Device reductions of the bulk-load (bulkload.hip). device_all_finite:
+// whether count floats are all finite. device_pivots: s pivots by
+// farthest-point selection over the ids (started from the point farthest
+// from the centroid, smallest id on ties) and the largest FP64 norm of a
+// point. device_ball_summaries: for every range [p0, p1) of the leaf order
+// (perm on the device), the FP64 mean rounded to FP32 (m x MP), the largest
+// FP64 distance of its points to that centre, and per pivot the smallest and
+// largest FP64 distance (m x 2 s, min then max).
+bool device_all_finite(const float* x, int64_t count, hipStream_t st);
+void device_pivots(const float* proj, int64_t n, int s, hipStream_t st, std::vector<float>* pivots,
+                   double* max_norm);
+void device_ball_summaries(const float* proj, const int32_t* perm, const std::vector<int64_t>& p0,
+                           const std::vector<int64_t>& p1, const float* pivots, int s,
+                           hipStream_t st, std::vector<float>* centre, std::vector<double>* radius,
+                           std::vector<double>* ring);
+
+// Bulk-loads the tree over the device projection proj (n x MP, original
+// order) from the leaf order (host perm, and its device copy perm_dev) and
+// the split tree of device_split.
 void build_tree(const float* proj, int64_t n, int leaf_size, int fanout, int num_pivots,
-                std::vector<int32_t> perm, const std::vector<SplitNode>& split, HostTree* out);
+                std::vector<int32_t> perm, const int32_t* perm_dev,
+                const std::vector<SplitNode>& split, hipStream_t st, HostTree* out);
 
 // ---------------------------------------------------------------- index
 struct DeviceTree {

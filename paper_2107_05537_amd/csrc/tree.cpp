@@ -21,34 +21,11 @@
 
 #include <algorithm>
 #include <cmath>
-#include <mutex>
-#include <numeric>
-#include <thread>
 
 #include "internal.hpp"
 
 namespace pmlsh {
 namespace {
-
-int hw_threads() {
-    unsigned h = std::thread::hardware_concurrency();
-    return h == 0 ? 4 : (int)std::min(h, 64u);
-}
-
-template <class F>
-void parallel_for(int64_t count, F fn) {
-    int nt = (int)std::min<int64_t>(hw_threads(), std::max<int64_t>(1, count / 64));
-    if (nt <= 1) {
-        for (int64_t i = 0; i < count; ++i) fn(i);
-        return;
-    }
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t)
-        th.emplace_back([&, t] {
-            for (int64_t i = t; i < count; i += nt) fn(i);
-        });
-    for (auto& x : th) x.join();
-}
 
 float round_up(double v) {
     float f = (float)v;
@@ -61,50 +38,18 @@ float round_down(double v) {
     return f;
 }
 
-double dist64(const float* a, const float* b) {
-    double s = 0;
-    for (int j = 0; j < MP; ++j) {
-        double t = (double)a[j] - (double)b[j];
-        s += t * t;
-    }
-    return std::sqrt(s);
-}
-
 }  // namespace
 
 void build_tree(const float* proj, int64_t n, int leaf_size, int fanout, int num_pivots,
-                std::vector<int32_t> perm_in, const std::vector<SplitNode>& bt, HostTree* out) {
+                std::vector<int32_t> perm_in, const int32_t* perm_dev,
+                const std::vector<SplitNode>& bt, hipStream_t st, HostTree* out) {
     HostTree& T = *out;
     const int s = num_pivots;
 
     // ---- pivots: farthest-point selection, started from the point farthest
-    // from the centroid (ties by smallest id)
-    T.pivots.assign((size_t)s * MP, 0.f);
-    if (s > 0) {
-        double cen[MP] = {0};
-        for (int64_t i = 0; i < n; ++i)
-            for (int j = 0; j < MP; ++j) cen[j] += proj[i * MP + j];
-        float cf[MP];
-        for (int j = 0; j < MP; ++j) cf[j] = (float)(cen[j] / (double)n);
-        std::vector<double> mind(n, std::numeric_limits<double>::infinity());
-        int64_t pick = 0;
-        double best = -1;
-        for (int64_t i = 0; i < n; ++i) {
-            double dd = dist64(proj + i * MP, cf);
-            if (dd > best) { best = dd; pick = i; }
-        }
-        for (int p = 0; p < s; ++p) {
-            std::copy(proj + pick * MP, proj + pick * MP + MP, T.pivots.begin() + (size_t)p * MP);
-            int64_t next = 0;
-            double far = -1;
-            for (int64_t i = 0; i < n; ++i) {
-                double dd = dist64(proj + i * MP, proj + pick * MP);
-                if (dd < mind[i]) mind[i] = dd;
-                if (mind[i] > far) { far = mind[i]; next = i; }
-            }
-            pick = next;
-        }
-    }
+    // from the centroid (ties by smallest id), on the device
+    double maxnorm = 0.0;
+    device_pivots(proj, n, s, st, &T.pivots, &maxnorm);
 
     // ---- leaf order and binary split tree (leaf ranges) of the recursive
     // gap-aware splits; the inner levels are derived from the split tree
@@ -175,48 +120,26 @@ void build_tree(const float* proj, int64_t n, int leaf_size, int fanout, int num
         }
     }
 
-    // ---- node summaries
-    const std::vector<int32_t>& perm = T.perm;
-    parallel_for(N, [&](int64_t i) {
-        double cen[MP] = {0};
-        for (int64_t q = p0[i]; q < p1[i]; ++q) {
-            const float* p = proj + (int64_t)perm[q] * MP;
-            for (int j = 0; j < MP; ++j) cen[j] += p[j];
-        }
-        float cf[MP];
-        const double c = (double)(p1[i] - p0[i]);
-        for (int j = 0; j < MP; ++j) cf[j] = (float)(cen[j] / c);
-        double rad = 0, lo[PMLSH_MAX_PIVOTS], hi[PMLSH_MAX_PIVOTS];
-        for (int t = 0; t < s; ++t) { lo[t] = std::numeric_limits<double>::infinity(); hi[t] = 0; }
-        for (int64_t q = p0[i]; q < p1[i]; ++q) {
-            const float* p = proj + (int64_t)perm[q] * MP;
-            rad = std::max(rad, dist64(p, cf));
-            for (int t = 0; t < s; ++t) {
-                double dd = dist64(p, &T.pivots[(size_t)t * MP]);
-                lo[t] = std::min(lo[t], dd);
-                hi[t] = std::max(hi[t], dd);
-            }
-        }
-        for (int j = 0; j < MP; ++j) T.centre[(size_t)j * N + i] = cf[j];
-        T.radius[i] = round_up(rad);
+    // ---- node summaries (device reductions over each node's points)
+    std::vector<float> cen;
+    std::vector<double> rad, ring;
+    device_ball_summaries(proj, perm_dev, p0, p1, T.pivots.data(), s, st, &cen, &rad, &ring);
+    for (int64_t i = 0; i < N; ++i) {
+        for (int j = 0; j < MP; ++j) T.centre[(size_t)j * N + i] = cen[(size_t)i * MP + j];
+        T.radius[i] = round_up(rad[(size_t)i]);
         for (int t = 0; t < s; ++t) {
-            T.hr_min[(size_t)t * N + i] = round_down(lo[t]);
-            T.hr_max[(size_t)t * N + i] = round_up(hi[t]);
+            T.hr_min[(size_t)t * N + i] = round_down(ring[(size_t)(i * 2 * s + 2 * t)]);
+            T.hr_max[(size_t)t * N + i] = round_up(ring[(size_t)(i * 2 * s + 2 * t + 1)]);
         }
-    });
-
-    double maxnorm = 0, pivnorm = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        double s2 = 0;
-        for (int j = 0; j < MP; ++j) s2 += (double)proj[i * MP + j] * proj[i * MP + j];
-        maxnorm = std::max(maxnorm, s2);
     }
+
+    double pivnorm = 0;
     for (int t = 0; t < s; ++t) {
         double s2 = 0;
         for (int j = 0; j < MP; ++j) s2 += (double)T.pivots[(size_t)t * MP + j] * T.pivots[(size_t)t * MP + j];
         pivnorm = std::max(pivnorm, s2);
     }
-    T.coord_scale = (float)(std::sqrt(maxnorm) + std::sqrt(pivnorm));
+    T.coord_scale = (float)(maxnorm + std::sqrt(pivnorm));
 }
 
 }  // namespace pmlsh
