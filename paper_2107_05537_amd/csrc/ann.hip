@@ -108,7 +108,6 @@ struct AnnArgs {
     int64_t ldc, goff;
     int glds;                   // bound kernel: group minima copied to LDS
     int grp_cap;                // bound kernel: most groups or blocks listed (<= kGrpCap)
-    int32_t* csel;              // per query: the chunks chosen for its bound (kSelCap)
     // bounded verification: FP16 rows (stride d16), their scales and error
     // bounds, and per C member a lower bound of its squared distance (the
     // upper bound goes to ws_cdist; equal bounds mean the exact value)
@@ -1107,7 +1106,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     const uint2* row4 = reinterpret_cast<const uint2*>(a.cdist + qi * a.ldc);
     const uint16_t* grow16 = a.cdist + qi * a.ldc + a.goff;
     // the group minima (copied to LDS when a.glds is set, else read in the
-    // row), then the list of candidate groups
+    // row), then the list of candidate groups and the list of chosen chunks
     unsigned char* lds_free = smem_raw + offsetof(Smem, skey);
     const uint16_t* gmin = grow16;
     if (a.glds) {
@@ -1117,6 +1116,8 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         lds_free += 2 * (size_t)((ngr + 7) & ~7);
     }
     int32_t* glist = reinterpret_cast<int32_t*>(lds_free);
+    // the chunks chosen for the bound (step 2)
+    int32_t* sel = glist + kGrpCap;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     // bf16 bit pattern k of an element (non-negative values: ordered as
     // unsigned integers)
@@ -1169,7 +1170,6 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             for (int g = threadIdx.x; g < ng4; g += WG) f(g, row4[g]);
         }
     };
-    int32_t* sel = a.csel + qi * kSelCap;
 
     // 1: histogram of the centre distances (chunk counts) on fixed bins: 16
     // per octave of the squared distance over [2^-64, 2^64), clamped at both
@@ -1264,13 +1264,24 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     const uint32_t base2 = hb2 > (uint32_t)(NB - 1) ? hb2 - (uint32_t)(NB - 1) : 0u;
     clear_hist(sh);
     int cnt = 0;
-    for (int e = threadIdx.x; e < nsel * 64; e += WG) {
-        const int64_t pos = ((int64_t)sel[e >> 6] << 6) + (e & 63);
-        if (pos < a.n) {
-            const float pd2 = proj_dist2(a.proj + pos * MP, qc.qp);
-            if (pd2 <= R2) {
-                atomicAdd(&sh.hist[radius_bin(pd2, base2)], 1u);
-                ++cnt;
+    {
+        // four points per thread in flight: their row loads go out together
+        constexpr int PU = 4;
+        for (int e0 = threadIdx.x; e0 < nsel * 64; e0 += PU * WG) {
+            float pd2[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int e = e0 + u * WG;
+                const int64_t pos = e < nsel * 64 ? ((int64_t)sel[e >> 6] << 6) + (e & 63) : a.n;
+                pd2[u] = pos < a.n ? proj_dist2(a.proj + pos * MP, qc.qp)
+                                   : __int_as_float(0x7f800000);
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                if (pd2[u] <= R2) {
+                    atomicAdd(&sh.hist[radius_bin(pd2[u], base2)], 1u);
+                    ++cnt;
+                }
             }
         }
     }
@@ -1303,31 +1314,53 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             const float r = a.group_rad[j] + tq;
             return __uint_as_float((uint32_t)gmin[j] << 16) <= fmaf(r, r, dmarg);
         };
-        // block G: chunks 256 G .. 256 G + 255, words 4 G .. 4 G + 3 of the row
-        auto test_block = [&](int G) {
-            const int g = (G << 6) + lane;
-            bool live = g < ng4;
-            // chunks 4 g .. 4 g + 3 lie in group g / 16
-            if (live) live = group_live(g >> 4);
-            uint2 v = make_uint2(0u, 0u);
-            float4 rv = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (live) {
-                v = row4[g];
-                rv = rad4[g];
-            }
-            uint64_t bk[4];
+        // blocks G[0..BU): chunks 256 G .. 256 G + 255, words 4 G .. 4 G + 3
+        // of the row (G < 0: none); the loads of all of them go out first. A
+        // listed block is read whole, its groups' minima only mask the test.
+        constexpr int BU = 4;
+        auto test_blocks = [&](const int (&G)[BU], bool listed) {
+            uint2 v[BU];
+            float4 rv[BU];
+            bool live[BU];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float r = (k == 0 ? rv.x : k == 1 ? rv.y : k == 2 ? rv.z : rv.w) + tq;
-                const float d2 = __uint_as_float(half_k(v, k) << 16);
-                bk[k] = __builtin_amdgcn_ballot_w64(live && 4 * g + k < nch &&
-                                                    d2 <= fmaf(r, r, dmarg));
+            for (int u = 0; u < BU; ++u) {
+                const int g = (G[u] << 6) + lane;
+                live[u] = G[u] >= 0 && g < ng4;
+                v[u] = make_uint2(0u, 0u);
+                rv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (live[u] && listed) {
+                    v[u] = row4[g];
+                    rv[u] = rad4[g];
+                }
             }
-            if (lane < 4) {
-                const uint64_t w = lane == 0 ? bk[0] : lane == 1 ? bk[1] : lane == 2 ? bk[2] : bk[3];
-                a.qmask[qi * a.mwords + 4 * G + lane] = w;
+#pragma unroll
+            for (int u = 0; u < BU; ++u) {
+                const int g = (G[u] << 6) + lane;
+                // chunks 4 g .. 4 g + 3 lie in group g / 16
+                if (live[u]) live[u] = group_live(g >> 4);
+                if (live[u] && !listed) {
+                    v[u] = row4[g];
+                    rv[u] = rad4[g];
+                }
             }
-            npass += __popcll(bk[0]) + __popcll(bk[1]) + __popcll(bk[2]) + __popcll(bk[3]);
+#pragma unroll
+            for (int u = 0; u < BU; ++u) {
+                if (G[u] < 0) continue;
+                const int g = (G[u] << 6) + lane;
+                uint64_t bk[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float r = (k == 0 ? rv[u].x : k == 1 ? rv[u].y : k == 2 ? rv[u].z : rv[u].w) + tq;
+                    const float d2 = __uint_as_float(half_k(v[u], k) << 16);
+                    bk[k] = __builtin_amdgcn_ballot_w64(live[u] && 4 * g + k < nch &&
+                                                        d2 <= fmaf(r, r, dmarg));
+                }
+                if (lane < 4) {
+                    const uint64_t w = lane == 0 ? bk[0] : lane == 1 ? bk[1] : lane == 2 ? bk[2] : bk[3];
+                    a.qmask[qi * a.mwords + 4 * G[u] + lane] = w;
+                }
+                npass += __popcll(bk[0]) + __popcll(bk[1]) + __popcll(bk[2]) + __popcll(bk[3]);
+            }
         };
         bool all_blocks = true;
         if (a.grp_cap > 0) {
@@ -1352,11 +1385,27 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             const int nbl = sh.cnt0;
             if (nbl <= a.grp_cap) {
                 all_blocks = false;
-                for (int i = wave; i < nbl; i += NWAVE) test_block(glist[i]);
+                for (int i0 = wave; i0 < nbl; i0 += BU * NWAVE) {
+                    int G[BU];
+#pragma unroll
+                    for (int u = 0; u < BU; ++u) {
+                        const int i = i0 + u * NWAVE;
+                        G[u] = i < nbl ? glist[i] : -1;
+                    }
+                    test_blocks(G, true);
+                }
             }
         }
         if (all_blocks)
-            for (int G = wave; G < ng256; G += NWAVE) test_block(G);
+            for (int G0 = wave; G0 < ng256; G0 += BU * NWAVE) {
+                int G[BU];
+#pragma unroll
+                for (int u = 0; u < BU; ++u) {
+                    const int g = G0 + u * NWAVE;
+                    G[u] = g < ng256 ? g : -1;
+                }
+                test_blocks(G, false);
+            }
     }
     // points the scan examines for this query: 64 per passing chunk
     npass = block_sum(lane == 0 ? npass : 0, sh);
@@ -1976,7 +2025,6 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.cdist = L.ws_cdist2;
         a.ldc = cdist_row_len(x.n_pad16 / 64);
         a.goff = cdist_row_offset_groups(x.n_pad16 / 64);
-        a.csel = L.ws_csel;
         a.ws_clo = L.ws_clo;
         a.q_flag = L.q_flag;
         a.l_count = L.l_count;
@@ -1999,7 +2047,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
             a.glds = tune_get(PMLSH_TUNE_GROUP_MINIMA_LDS) != 0 &&
                      min_bytes + 4 * (size_t)kGrpCap <= kTauGroupLds;
             const size_t lds_t = std::max((size_t)lds0, offsetof(Smem, skey) +
-                                          (a.glds ? min_bytes : 0) + 4 * (size_t)kGrpCap);
+                                          (a.glds ? min_bytes : 0) +
+                                          4 * (size_t)(kGrpCap + kSelCap));
             PMLSH_HIP(hipFuncSetAttribute((const void*)tau_kernel,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_t));
             hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), (unsigned)lds_t, stream, a);

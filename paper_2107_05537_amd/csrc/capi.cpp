@@ -69,11 +69,11 @@ AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
     w.ldc = cdist_row_len(w.nchunk);
     w.mwords = 4 * ((w.nchunk + 255) / 256);
     const int64_t per_query_all =
-        w.per_query + (w.fast ? 8 * w.mwords + 2 * w.ldc + 4 * kSelCap + (w.nchunk + 7) / 8 : 0);
+        w.per_query + (w.fast ? 8 * w.mwords + 2 * w.ldc + (w.nchunk + 7) / 8 : 0);
     w.batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     w.batch = std::min<int64_t>(w.batch, 65535);
     const int64_t mask_bytes =
-        w.fast ? w.batch * (8 * w.mwords + 2 * w.ldc + 4 * kSelCap) + w.nchunk * ((w.batch + 63) / 64) * 8
+        w.fast ? w.batch * (8 * w.mwords + 2 * w.ldc) + w.nchunk * ((w.batch + 63) / 64) * 8
                : 0;
     w.slots = front_slots(x, w.fast, w.batch);
     w.bytes = w.batch * w.per_query + mask_bytes + w.slots * 2 * x->n_leaves * 4;
@@ -125,8 +125,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     float* qproj = reinterpret_cast<float*>(base);
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
     uint16_t* cdist2 = qaug + batch * 32;
-    int32_t* csel = reinterpret_cast<int32_t*>(cdist2 + (fast ? batch * ldc : 0));
-    uint64_t* qmask = reinterpret_cast<uint64_t*>(csel + (fast ? batch * kSelCap : 0));
+    uint64_t* qmask = reinterpret_cast<uint64_t*>(cdist2 + (fast ? batch * ldc : 0));
     uint64_t* cmask = qmask + (fast ? batch * mwords : 0);
     uint32_t* list = reinterpret_cast<uint32_t*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
@@ -167,7 +166,6 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
                 L.ws_clo = clo;
                 L.ws_cmask = cmask;
                 L.ws_cdist2 = cdist2;
-                L.ws_csel = csel;
                 L.q_flag = q_flag;
                 L.l_count = l_count;
                 L.q_scanned = q_scanned;

@@ -282,7 +282,6 @@ struct AnnLaunch {
     uint64_t* ws_qmask;     // nq x mask words: chunks each query must scan
     uint64_t* ws_cmask;     // the same, chunk-major: chunks x ceil(nq / 64) words
     uint16_t* ws_cdist2;    // nq x ldc: squared distances to the chunk centres (bf16, rounded down)
-    int32_t* ws_csel;       // nq x ldc: chunks chosen for the bound
     int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;

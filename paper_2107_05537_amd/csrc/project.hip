@@ -37,16 +37,36 @@ __global__ __launch_bounds__(256) void project_kernel(
     const int64_t row0 = (int64_t)blockIdx.x * PJ_ROWS;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < d; k0 += PJ_KC) {
-        for (int i = tid; i < PJ_ROWS * PJ_KC; i += 256) {
-            const int r = i / PJ_KC, c = i % PJ_KC;
-            const int64_t gr = row0 + r;
-            const int gc = k0 + c;
-            xs[r][c] = (gr < rows && gc < d) ? x[gr * ld + gc] : 0.f;
-        }
-        for (int i = tid; i < MP * PJ_KC; i += 256) {
-            const int r = i / PJ_KC, c = i % PJ_KC;
-            const int gc = k0 + c;
-            hs[r][c] = gc < d ? hash[(int64_t)r * d + gc] : 0.f;
+        // every load of the step is issued before the LDS stores: thread t
+        // reads columns c0 .. c0 + 3 of rows t / 64 + 4 u (u = 0..3), c0 = 4 (t % 64)
+        {
+            const int c0 = 4 * (tid & 63), r0 = tid >> 6;
+            float xv[PJ_ROWS / 4][4], hv[MP / 4][4];
+#pragma unroll
+            for (int u = 0; u < PJ_ROWS / 4; ++u) {
+                const int64_t gr = row0 + r0 + 4 * u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gc = k0 + c0 + e;
+                    xv[u][e] = (gr < rows && gc < d) ? x[gr * ld + gc] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < MP / 4; ++u) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gc = k0 + c0 + e;
+                    hv[u][e] = gc < d ? hash[(int64_t)(r0 + 4 * u) * d + gc] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PJ_ROWS / 4; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) xs[r0 + 4 * u][c0 + e] = xv[u][e];
+#pragma unroll
+            for (int u = 0; u < MP / 4; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) hs[r0 + 4 * u][c0 + e] = hv[u][e];
         }
         __syncthreads();
         // each wave takes 64 of the staged columns. A operand: row
