@@ -599,19 +599,28 @@ __device__ void verify_list(const AnnArgs& a, const float* qs, const int32_t* cp
             row[r] = reinterpret_cast<const float4*>(a.data + (int64_t)cpos[mi[r]] * a.d_pad);
             acc[r] = 0.f;
         }
-#pragma unroll 2
-        for (int c = l16; c < d4; c += 16) {
-            float4 x[VR];
-#pragma unroll
-            for (int r = 0; r < VR; ++r) x[r] = row[r][c];
-            const float4 y = q4[c];
+        // two words of every row per lane and step, all loads issued before
+        // the first use; the operations and their order are those of verify
+        for (int c0 = l16; c0 < d4; c0 += 32) {
+            float4 x[VR][2];
 #pragma unroll
             for (int r = 0; r < VR; ++r) {
-                float t;
-                t = y.x - x[r].x; acc[r] = __fmaf_rn(t, t, acc[r]);
-                t = y.y - x[r].y; acc[r] = __fmaf_rn(t, t, acc[r]);
-                t = y.z - x[r].z; acc[r] = __fmaf_rn(t, t, acc[r]);
-                t = y.w - x[r].w; acc[r] = __fmaf_rn(t, t, acc[r]);
+                x[r][0] = row[r][c0];
+                x[r][1] = c0 + 16 < d4 ? row[r][c0 + 16] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int c = c0 + 16 * u;
+                if (u == 1 && c >= d4) break;
+                const float4 y = q4[c];
+#pragma unroll
+                for (int r = 0; r < VR; ++r) {
+                    float t;
+                    t = y.x - x[r][u].x; acc[r] = __fmaf_rn(t, t, acc[r]);
+                    t = y.y - x[r][u].y; acc[r] = __fmaf_rn(t, t, acc[r]);
+                    t = y.z - x[r][u].z; acc[r] = __fmaf_rn(t, t, acc[r]);
+                    t = y.w - x[r][u].w; acc[r] = __fmaf_rn(t, t, acc[r]);
+                }
             }
         }
 #pragma unroll
@@ -656,23 +665,33 @@ __device__ void verify16(const AnnArgs& a, const float* qs, const int32_t* cpos,
             sc[r] = a.d16_scale[pr[r]];
             acc[r] = 0.f;
         }
-#pragma unroll 2
-        for (int c = l16; c < d8; c += 16) {
-            uint4 h[VR];
-#pragma unroll
-            for (int r = 0; r < VR; ++r) h[r] = row[r][c];
-            float y[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) y[e] = qs[8 * c + e];
+        // two 16-byte words of every row per lane and step, all loads issued
+        // before the first use (words past the row read as zero halves, and
+        // the query's zero padding makes their terms zero)
+        for (int c0 = l16; c0 < d8; c0 += 32) {
+            uint4 h[VR][2];
 #pragma unroll
             for (int r = 0; r < VR; ++r) {
-                const uint32_t w[4] = {h[r].x, h[r].y, h[r].z, h[r].w};
+                h[r][0] = row[r][c0];
+                h[r][1] = c0 + 16 < d8 ? row[r][c0 + 16] : make_uint4(0u, 0u, 0u, 0u);
+            }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint16_t bits = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
-                    const float xv = (float)__builtin_bit_cast(_Float16, bits);
-                    const float t = __fmaf_rn(-sc[r], xv, y[e]);
-                    acc[r] = __fmaf_rn(t, t, acc[r]);
+            for (int u = 0; u < 2; ++u) {
+                const int c = c0 + 16 * u;
+                if (u == 1 && c >= d8) break;
+                float y[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) y[e] = qs[8 * c + e];
+#pragma unroll
+                for (int r = 0; r < VR; ++r) {
+                    const uint32_t w[4] = {h[r][u].x, h[r][u].y, h[r][u].z, h[r][u].w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint16_t bits = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+                        const float xv = (float)__builtin_bit_cast(_Float16, bits);
+                        const float t = __fmaf_rn(-sc[r], xv, y[e]);
+                        acc[r] = __fmaf_rn(t, t, acc[r]);
+                    }
                 }
             }
         }
