@@ -1389,9 +1389,12 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
             __syncthreads();
             for (int G0 = 0; G0 < ng256; G0 += WG) {
                 const int G = G0 + threadIdx.x;
+                // the four tests are independent (their loads go out together)
                 bool live = false;
                 if (G < ng256)
-                    for (int j = 4 * G; j < min(4 * G + 4, ngr); ++j) live = live || group_live(j);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        if (4 * G + jj < ngr) live |= group_live(4 * G + jj);
                 const int slot = wave_append(live, &sh.cnt0);
                 if (live && slot < a.grp_cap) glist[slot] = G;
                 if (G < ng256 && !live) {
