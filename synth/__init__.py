@@ -54,7 +54,8 @@ SPECS = {
                             sigma_lo=0.2, sigma_hi=0.5, n_queries=10_000),
 }
 
-SEEDS = {"parity": 20210712, "headline": 20210713, "acp": 20210714, "serving": 20210715}
+SEEDS = {"parity": 20210712, "headline": 20210713, "acp": 20210714, "serving": 20210715,
+         "heavy": 20210716}
 
 
 def _draw_points(rng, labels, centres, sigmas, d):
@@ -150,6 +151,24 @@ def uniform_cube(seed: int, n: int, d: int, n_queries: int, m: int = M_DEFAULT,
     rng = np.random.Generator(np.random.PCG64(seed))
     D = rng.uniform(lo, hi, size=(n, d)).astype(np.float32)
     Q = rng.uniform(lo, hi, size=(n_queries, d)).astype(np.float32)
+    A = hash_matrix(rng, m, d)
+    return {"D": D, "Q": Q, "A": A}
+
+
+def heavy_tailed(seed: int = SEEDS["heavy"], n: int = 1_000_000, d: int = 960,
+                 n_queries: int = 10_000, m: int = M_DEFAULT):
+    """Mixed-precision workload: non-negative heavy-tailed features, every
+    coordinate |N(0,1)|^1.5, rows L2-normalised and scaled by 100; queries
+    drawn the same way."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def rows(count):
+        x = np.abs(rng.standard_normal((count, d))) ** 1.5
+        x *= 100.0 / np.linalg.norm(x, axis=1, keepdims=True)
+        return x.astype(np.float32)
+
+    D = rows(n)
+    Q = rows(n_queries)
     A = hash_matrix(rng, m, d)
     return {"D": D, "Q": Q, "A": A}
 

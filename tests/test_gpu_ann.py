@@ -163,6 +163,26 @@ def test_shapes(n, d, m, leaf, fan, piv):
     compare_ann(D, Q, res, ids, dist, st)
 
 
+@pytest.mark.parametrize("c", [1.2, 1.5, 2.0])
+def test_heavy_tailed_d960(c):
+    """The mixed-precision workload's shape and value distribution at a size
+    the oracle finishes quickly: 20,000 x 960 non-negative heavy-tailed rows
+    (|N(0,1)|^1.5, L2-normalised, x100), 32 queries, k = 10, every c of the
+    workload. d = 960 gives FP16 rows of 120 words (a ragged last step of
+    the verification) and FP32 rows of 240 words."""
+    pm = _gpu()
+    say(f"case: heavy-tailed n=20000 d=960 c={c}")
+    w = synth.heavy_tailed(n=20_000, n_queries=32)
+    D, A, Q = w["D"], w["A"], w["Q"]
+    k, beta = 10, 0.05
+    B = min(D.shape[0], math.ceil(beta * D.shape[0]) + k)
+    r0 = oracle_r_min(D, 5, B)
+    res, _ = oracle_ann(D, A, Q, k, c, 0.9, beta, r_min=r0)
+    idx, ids, dist, st = _run(pm, D, A, Q, k, c, 0.9, beta, r0, sample_seed=5)
+    compare_ann(D, Q, res, ids, dist, st)
+    say("exit kinds", np.bincount(st[:, 2], minlength=3), "rounds", np.bincount(st[:, 0]))
+
+
 @pytest.mark.parametrize("scale", [1e-4, 1e4])
 def test_data_scale_extremes(scale):
     """The same mixture scaled by 1e-4 and 1e4: the FP16 scan rows, the bf16
@@ -311,6 +331,34 @@ def test_headline_scale_sampled():
     res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
     compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
     say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
+
+
+def test_serving_scale_sampled():
+    """The serving index at full size, 10,000,000 x 128 FP16-valued points in
+    [0, 255] around 10,000 centres, one 1,024-query launch at the serving
+    beta (1e-4, B = 1,010): 8 sampled queries checked against the oracle
+    for k = 10, c = 1.5 and 4 for k = 100, c = 2.0 (2,441 groups of 64
+    chunks per distance row)."""
+    pm = _gpu()
+    say("case: serving scale, n=10M d=128")
+    w = synth.serving(n_queries=1024)
+    D, A, Q = w["D"], w["A"], w["Q"]
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    from oracle import ann as oann
+    Dp = oann.project(D, A)
+    Qd = torch.from_numpy(Q).to(dev)
+    beta = 1e-4
+    for k, c, sample in ((10, 1.5, np.arange(0, 1024, 128)), (100, 2.0, np.arange(64, 1024, 256))):
+        say(f"case: serving scale k={k} c={c}")
+        B = min(D.shape[0], math.ceil(beta * D.shape[0]) + k)
+        r0 = idx.default_r_min(B)
+        ids, dist, st = idx.ann(Qd, k, c=c, beta=beta, r_min=r0, stats=True)
+        torch.cuda.synchronize()
+        ids, dist, st = ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
+        res, _ = oracle_ann(D, A, Q[sample], k, c, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
+        compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
+        say("exit kinds", np.bincount(st[:, 2], minlength=3), "rounds", np.bincount(st[:, 0]))
 
 
 GROUP_SETTINGS = [(2048, 0), (0, 1), (1, 1), (7, 0)]
