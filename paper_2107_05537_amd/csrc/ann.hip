@@ -748,11 +748,111 @@ __device__ __forceinline__ void load_query(const AnnArgs& a, int64_t qi, float* 
 
 // Writes the k members of C (the first n_ver entries, n_ver >= k) with the
 // smallest (distance^2 bits, id), in that order, and the per-query statistics.
-__device__ void write_topk(const AnnArgs& a, int64_t qi, const int32_t* cpos, const float* cdist,
-                           int n_ver, int rounds, int exit_kind, int64_t scanned, Smem& sh) {
+// Relative error bound of the FP32 squared distance that verify computes
+// (16 lanes, d_pad / 16 terms each, four shuffle additions).
+__device__ __forceinline__ float verify_gamma(const AnnArgs& a) {
+    return 2.f * 5.9604645e-08f * (float)(a.d_pad / 16 + 8);
+}
+
+constexpr int kRerankCap = 512;   // members the FP64 re-rank takes at most
+
+// FP64 re-rank of the top-k, for near ties of the FP32 distances: every
+// member whose exact FP32 squared distance v32 is at most kth32 (1 + 4 gamma),
+// kth32 the k-th smallest v32 (+inf with at most k members), gets its squared
+// distance in FP64 from its FP32 row; since v32 is within a factor 1 +- gamma
+// of that value, no member outside can be among the k nearest in FP64. The k
+// smallest (FP64 value, id) are written, each distance as the FP32 rounding
+// of the FP64 root. src(j, v32, member) gives the cnt candidates. Returns
+// false, writing nothing, when more than kRerankCap members qualify.
+template <class Src>
+__device__ bool rerank_topk64(const AnnArgs& a, int64_t qi, const float* qs, const int32_t* cpos,
+                              int cnt, float kth32, Src&& src, Smem& sh) {
+    double* d64 = reinterpret_cast<double*>(sh.hist);
+    int32_t* mem = reinterpret_cast<int32_t*>(d64 + kRerankCap);
+    int32_t* pid = mem + kRerankCap;
+    static_assert(NB * sizeof(uint32_t) >= kRerankCap * 16, "re-rank lists must fit the histogram");
+    const double lim = (double)kth32 * (1.0 + 4.0 * (double)verify_gamma(a));
+    __syncthreads();
+    if (threadIdx.x == 0) sh.cnt2 = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < cnt; b0 += WG) {
+        const int j = b0 + threadIdx.x;
+        float v = 0.f;
+        int mi = 0;
+        if (j < cnt) src(j, v, mi);
+        const bool take = j < cnt && (double)v <= lim;
+        const int slot = wave_append(take, &sh.cnt2);
+        if (take && slot < kRerankCap) {
+            mem[slot] = mi;
+            pid[slot] = a.perm[cpos[mi]];
+        }
+    }
+    __syncthreads();
+    const int np = sh.cnt2;
+    if (np > kRerankCap) return false;
+    // FP64 squared distances, 16 lanes per member (differences of FP32
+    // values are exact in FP64)
+    {
+        const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+        const int d4 = a.d_pad >> 2;
+        const float4* q4 = reinterpret_cast<const float4*>(qs);
+        for (int base = 0; base < np; base += WG / 16) {
+            const int j = base + g;
+            double acc = 0.0;
+            if (j < np) {
+                const float4* row = reinterpret_cast<const float4*>(a.data + (int64_t)cpos[mem[j]] * a.d_pad);
+                for (int c = l16; c < d4; c += 16) {
+                    const float4 x = row[c], y = q4[c];
+                    double t;
+                    t = (double)y.x - (double)x.x; acc = fma(t, t, acc);
+                    t = (double)y.y - (double)x.y; acc = fma(t, t, acc);
+                    t = (double)y.z - (double)x.z; acc = fma(t, t, acc);
+                    t = (double)y.w - (double)x.w; acc = fma(t, t, acc);
+                }
+            }
+            acc += __shfl_xor(acc, 8, 16);
+            acc += __shfl_xor(acc, 4, 16);
+            acc += __shfl_xor(acc, 2, 16);
+            acc += __shfl_xor(acc, 1, 16);
+            if (j < np && l16 == 0) d64[j] = acc;
+        }
+    }
+    __syncthreads();
+    // rank by (FP64 value, id); ids are distinct
+    for (int j = threadIdx.x; j < np; j += WG) {
+        const double v = d64[j];
+        const int32_t id = pid[j];
+        int rank = 0;
+        for (int y = 0; y < np; ++y) rank += d64[y] < v || (d64[y] == v && pid[y] < id);
+        if (rank < a.k) {
+            a.out_ids[qi * a.k + rank] = (int64_t)id;
+            a.out_dist[qi * a.k + rank] = (float)sqrt(v);
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+__device__ void write_topk(const AnnArgs& a, int64_t qi, const float* qs, const int32_t* cpos,
+                           const float* cdist, int n_ver, int rounds, int exit_kind,
+                           int64_t scanned, Smem& sh) {
     const int32_t* perm = a.perm;
     const int k = a.k;
+    bool done = false;
     if (n_ver <= CAP) {
+        // the k-th smallest FP32 value, then the FP64 re-rank
+        float kth32 = __int_as_float(0x7f800000);
+        if (n_ver > k) {
+            for (int i = threadIdx.x; i < n_ver; i += WG)
+                sh.skey[i] = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
+            __syncthreads();
+            kth32 = __uint_as_float((uint32_t)(lds_select(n_ver, k, sh) >> 32));
+        }
+        done = rerank_topk64(a, qi, qs, cpos, n_ver, kth32,
+                             [&](int j, float& v, int& mi) { v = cdist[j]; mi = j; }, sh);
+    }
+    if (done) {
+    } else if (n_ver <= CAP) {
         for (int i = threadIdx.x; i < n_ver; i += WG)
             sh.skey[i] = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
         __syncthreads();
@@ -946,7 +1046,7 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
         r = a.c * r;
     }
 
-    write_topk(a, qi, cpos, cdist, n_ver, rounds, exit_kind, scanned, sh);
+    write_topk(a, qi, qs, cpos, cdist, n_ver, rounds, exit_kind, scanned, sh);
 }
 
 // ------------------------------------------------------------------------
@@ -1879,11 +1979,14 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     __syncthreads();
     const float hk = n_ver > a.k ? __uint_as_float((uint32_t)(lds_select(n_ver, a.k, sh) >> 32))
                                  : __int_as_float(0x7f800000);
+    // members that the FP64 order of the re-rank could still place among the
+    // k nearest: lower bound within a factor 1 + 4 gamma of hk
+    const float hkw = (float)((double)hk * (1.0 + 4.0 * (double)verify_gamma(a)) * (1.0 + 1e-7));
     if (threadIdx.x == 0) sh.cnt1 = 0;
     __syncthreads();
     for (int b0 = 0; b0 < n_ver; b0 += WG) {
         const int i = b0 + threadIdx.x;
-        const bool take = i < n_ver && lo2[i] <= hk && lo2[i] != hi2[i];
+        const bool take = i < n_ver && lo2[i] <= hkw && lo2[i] != hi2[i];
         const int slot = wave_append(take, &sh.cnt1);
         if (take) ilist[slot] = i;
     }
@@ -1895,7 +1998,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     __syncthreads();
     for (int b0 = 0; b0 < n_ver; b0 += WG) {
         const int i = b0 + threadIdx.x;
-        const bool take = i < n_ver && lo2[i] <= hk;
+        const bool take = i < n_ver && lo2[i] <= hkw;
         const int slot = wave_append(take, &sh.cnt1);
         if (take) {
             sh.skey[slot] = ((uint64_t)__float_as_uint(hi2[i]) << 32) | (uint32_t)perm[cpos[i]];
@@ -1904,7 +2007,32 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     }
     __syncthreads();
     const int m = sh.cnt1;
-    if (m <= WG) {
+    // the k-th smallest exact FP32 value among them, then the FP64 re-rank
+    float kth32 = __int_as_float(0x7f800000);
+    if (m > a.k) {
+        if (m <= WG) {
+            if (threadIdx.x < m) {
+                const uint64_t key = sh.skey[threadIdx.x];
+                int rank = 0;
+                for (int y = 0; y < m; ++y) rank += sh.skey[y] < key;
+                if (rank == a.k - 1) sh.thr_bin = (int)(uint32_t)(key >> 32);
+            }
+            __syncthreads();
+            kth32 = __uint_as_float((uint32_t)sh.thr_bin);
+            __syncthreads();
+        } else {
+            kth32 = __uint_as_float((uint32_t)(lds_select(m, a.k, sh) >> 32));
+        }
+    }
+    const bool done = rerank_topk64(
+        a, qi, qs, cpos, m, kth32,
+        [&](int j, float& v, int& mi) {
+            v = __uint_as_float((uint32_t)(sh.skey[j] >> 32));
+            mi = sh.spos[j];
+        },
+        sh);
+    if (done) {
+    } else if (m <= WG) {
         // keys are distinct (ids): the rank of each among the m is its slot
         if (threadIdx.x < m) {
             const uint64_t key = sh.skey[threadIdx.x];
