@@ -1105,9 +1105,20 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
         return v;
     };
     float4 cnext = load_cen(blockIdx.x * DCB);
-    for (int e = threadIdx.x; e < DQB * MP; e += WG) {
-        const int r = e / MP, t = e % MP;
-        sq[r][t] = r < nqb ? a.qp[(int64_t)(q0 + r) * MP + t] : 0.f;
+    {
+        // every load of the staging goes out before the LDS stores
+        constexpr int PER = DQB * MP / WG;
+        float v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * WG, r = e / MP;
+            v[u] = r < nqb ? a.qp[(int64_t)(q0 + r) * MP + e % MP] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * WG;
+            sq[e / MP][e % MP] = v[u];
+        }
     }
     __syncthreads();
     if (threadIdx.x < DQB) {
@@ -1230,7 +1241,20 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     const uint16_t* gmin = grow16;
     if (a.glds) {
         uint16_t* g = reinterpret_cast<uint16_t*>(lds_free);
-        for (int j = threadIdx.x; j < ngr; j += WG) g[j] = grow16[j];
+        // eight loads per thread go out before their LDS stores
+        for (int j0 = threadIdx.x; j0 < ngr; j0 += 8 * WG) {
+            uint16_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u * WG;
+                v[u] = j < ngr ? grow16[j] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u * WG;
+                if (j < ngr) g[j] = v[u];
+            }
+        }
         gmin = g;
         lds_free += 2 * (size_t)((ngr + 7) & ~7);
     }
