@@ -801,13 +801,22 @@ __device__ bool rerank_topk64(const AnnArgs& a, int64_t qi, const float* qs, con
             double acc = 0.0;
             if (j < np) {
                 const float4* row = reinterpret_cast<const float4*>(a.data + (int64_t)cpos[mem[j]] * a.d_pad);
-                for (int c = l16; c < d4; c += 16) {
-                    const float4 x = row[c], y = q4[c];
-                    double t;
-                    t = (double)y.x - (double)x.x; acc = fma(t, t, acc);
-                    t = (double)y.y - (double)x.y; acc = fma(t, t, acc);
-                    t = (double)y.z - (double)x.z; acc = fma(t, t, acc);
-                    t = (double)y.w - (double)x.w; acc = fma(t, t, acc);
+                // four words per lane and step, loaded before their first use
+                for (int c0 = l16; c0 < d4; c0 += 64) {
+                    float4 x[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        x[u] = c0 + 16 * u < d4 ? row[c0 + 16 * u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (c0 + 16 * u >= d4) break;
+                        const float4 y = q4[c0 + 16 * u];
+                        double t;
+                        t = (double)y.x - (double)x[u].x; acc = fma(t, t, acc);
+                        t = (double)y.y - (double)x[u].y; acc = fma(t, t, acc);
+                        t = (double)y.z - (double)x[u].z; acc = fma(t, t, acc);
+                        t = (double)y.w - (double)x[u].w; acc = fma(t, t, acc);
+                    }
                 }
             }
             acc += __shfl_xor(acc, 8, 16);
@@ -2031,25 +2040,10 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     }
     __syncthreads();
     const int m = sh.cnt1;
-    // the k-th smallest exact FP32 value among them, then the FP64 re-rank
-    float kth32 = __int_as_float(0x7f800000);
-    if (m > a.k) {
-        if (m <= WG) {
-            if (threadIdx.x < m) {
-                const uint64_t key = sh.skey[threadIdx.x];
-                int rank = 0;
-                for (int y = 0; y < m; ++y) rank += sh.skey[y] < key;
-                if (rank == a.k - 1) sh.thr_bin = (int)(uint32_t)(key >> 32);
-            }
-            __syncthreads();
-            kth32 = __uint_as_float((uint32_t)sh.thr_bin);
-            __syncthreads();
-        } else {
-            kth32 = __uint_as_float((uint32_t)(lds_select(m, a.k, sh) >> 32));
-        }
-    }
+    // all of them go to the FP64 re-rank: their exact FP32 values are at
+    // most hk (1 + 4 gamma), a superset of the members the re-rank needs
     const bool done = rerank_topk64(
-        a, qi, qs, cpos, m, kth32,
+        a, qi, qs, cpos, m, __int_as_float(0x7f800000),
         [&](int j, float& v, int& mi) {
             v = __uint_as_float((uint32_t)(sh.skey[j] >> 32));
             mi = sh.spos[j];
