@@ -92,13 +92,11 @@ struct AnnArgs {
     int64_t n_pad16;
     float scale16;
     uint16_t* qaug;
-    // chunk balls and the query x chunk bit mask of their test (mwords words
-    // per query, bit-sliced: bit l of word 4 g + k is chunk 256 g + 4 l + k)
+    // chunk balls, and per query the radius tq of their test (Eq. 5) and
+    // the margin of the stored squared distances, from the bound kernel
     const float* chunk_cen;
     const float* chunk_rad;
-    const float* group_rad;     // per 64 consecutive chunks: their largest radius
-    uint64_t* qmask;
-    int mwords;
+    float2* qtest;
     uint64_t* cmask;            // the same mask chunk-major: ceil(nq / 64) words per chunk
     int cwords;
     // squared distances from every query to every chunk centre (row stride
@@ -1223,15 +1221,13 @@ constexpr size_t kTauGroupLds = 64 * 1024;
 //      chosen with a histogram of those distances weighted by chunk sizes;
 //   3. over the points of the chosen chunks, the budget-th smallest pd^2
 //      (upper edge of its histogram bin) is tau^2;
-//   4. the chunk-ball test of Eq. 5 for every chunk: the chunk can hold a
-//      point within tau of q' only if |q' - centre| <= radius + tau.
+//   4. the radius of the chunk-ball test of Eq. 5 (a chunk can hold a point
+//      within tau of q' only if |q' - centre| <= radius + tau), applied to
+//      every chunk by mask_kernel.
 // The chosen points are data points, so the ball of radius tau holds at least
 // `budget` points and therefore the budget nearest points by projected
 // distance. The choice of chunks only affects how tight tau is, never its
 // validity.
-//
-// Mask layout (query-major, bit-sliced to match four chunks per thread): bit l
-// of word 4 g + k of a query's row is chunk 256 g + 4 l + k.
 __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
@@ -1449,125 +1445,20 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         R2 = __int_as_float(0x7f800000);
     }
 
-    int npass = 0;
-    // 4: the chunk-ball test; the radius covers the FP32 errors of pd^2 and
-    // of the test's own distance (relative 2^-16 and 1e-5 (tau + S)), the
-    // additive term the rounding of the expanded squared distance. A group
-    // whose minimum fails the test with the group's largest radius holds no
-    // passing chunk, and its part of the row is not read.
-    {
+    // 4: the radius of the chunk-ball test, which mask_kernel applies: it
+    // covers the FP32 errors of pd^2 and of the test's own distance
+    // (relative 2^-16 and 1e-5 (tau + S)); the margin covers the rounding
+    // of the expanded squared distance (64 u (|q'| + S)^2)
+    if (threadIdx.x == 0) {
         const float tq0 = sqrtf(R2);
         const float tq = tq0 * (1.f + 1.52587890625e-05f) + 1e-5f * (tq0 + a.coord_scale);
         const float big = sqrtf(qc.qn2) + a.coord_scale;
-        const float dmarg = 64.f * 5.9604645e-08f * big * big;
-        const int ng256 = (nch + 255) >> 8;
-        const float4* rad4 = reinterpret_cast<const float4*>(a.chunk_rad);
-        auto group_live = [&](int j) {
-            const float r = a.group_rad[j] + tq;
-            return __uint_as_float((uint32_t)gmin[j] << 16) <= fmaf(r, r, dmarg);
-        };
-        // blocks G[0..BU): chunks 256 G .. 256 G + 255, words 4 G .. 4 G + 3
-        // of the row (G < 0: none); the loads of all of them go out first. A
-        // listed block is read whole, its groups' minima only mask the test.
-        constexpr int BU = 4;
-        auto test_blocks = [&](const int (&G)[BU], bool listed) {
-            uint2 v[BU];
-            float4 rv[BU];
-            bool live[BU];
-#pragma unroll
-            for (int u = 0; u < BU; ++u) {
-                const int g = (G[u] << 6) + lane;
-                live[u] = G[u] >= 0 && g < ng4;
-                v[u] = make_uint2(0u, 0u);
-                rv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (live[u] && listed) {
-                    v[u] = row4[g];
-                    rv[u] = rad4[g];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < BU; ++u) {
-                const int g = (G[u] << 6) + lane;
-                // chunks 4 g .. 4 g + 3 lie in group g / 16
-                if (live[u]) live[u] = group_live(g >> 4);
-                if (live[u] && !listed) {
-                    v[u] = row4[g];
-                    rv[u] = rad4[g];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < BU; ++u) {
-                if (G[u] < 0) continue;
-                const int g = (G[u] << 6) + lane;
-                uint64_t bk[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float r = (k == 0 ? rv[u].x : k == 1 ? rv[u].y : k == 2 ? rv[u].z : rv[u].w) + tq;
-                    const float d2 = __uint_as_float(half_k(v[u], k) << 16);
-                    bk[k] = __builtin_amdgcn_ballot_w64(live[u] && 4 * g + k < nch &&
-                                                        d2 <= fmaf(r, r, dmarg));
-                }
-                if (lane < 4) {
-                    const uint64_t w = lane == 0 ? bk[0] : lane == 1 ? bk[1] : lane == 2 ? bk[2] : bk[3];
-                    a.qmask[qi * a.mwords + 4 * G[u] + lane] = w;
-                }
-                npass += __popcll(bk[0]) + __popcll(bk[1]) + __popcll(bk[2]) + __popcll(bk[3]);
-            }
-        };
-        bool all_blocks = true;
-        if (a.grp_cap > 0) {
-            // blocks with a live group go to the list (the group list is no
-            // longer needed); the words of the other blocks are zero
-            if (threadIdx.x == 0) sh.cnt0 = 0;
-            __syncthreads();
-            for (int G0 = 0; G0 < ng256; G0 += WG) {
-                const int G = G0 + threadIdx.x;
-                // the four tests are independent (their loads go out together)
-                bool live = false;
-                if (G < ng256)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        if (4 * G + jj < ngr) live |= group_live(4 * G + jj);
-                const int slot = wave_append(live, &sh.cnt0);
-                if (live && slot < a.grp_cap) glist[slot] = G;
-                if (G < ng256 && !live) {
-                    uint4* w = reinterpret_cast<uint4*>(a.qmask + qi * a.mwords + 4 * G);
-                    w[0] = make_uint4(0u, 0u, 0u, 0u);
-                    w[1] = make_uint4(0u, 0u, 0u, 0u);
-                }
-            }
-            __syncthreads();
-            const int nbl = sh.cnt0;
-            if (nbl <= a.grp_cap) {
-                all_blocks = false;
-                for (int i0 = wave; i0 < nbl; i0 += BU * NWAVE) {
-                    int G[BU];
-#pragma unroll
-                    for (int u = 0; u < BU; ++u) {
-                        const int i = i0 + u * NWAVE;
-                        G[u] = i < nbl ? glist[i] : -1;
-                    }
-                    test_blocks(G, true);
-                }
-            }
-        }
-        if (all_blocks)
-            for (int G0 = wave; G0 < ng256; G0 += BU * NWAVE) {
-                int G[BU];
-#pragma unroll
-                for (int u = 0; u < BU; ++u) {
-                    const int g = G0 + u * NWAVE;
-                    G[u] = g < ng256 ? g : -1;
-                }
-                test_blocks(G, false);
-            }
+        a.qtest[qi] = make_float2(tq, 64.f * 5.9604645e-08f * big * big);
     }
-    // points the scan examines for this query: 64 per passing chunk
-    npass = block_sum(lane == 0 ? npass : 0, sh);
 
     if (threadIdx.x == 0) {
         a.l_count[qi] = 0u;
-        a.q_scanned[qi] = (uint32_t)min<int64_t>(64ll * npass, 0x7fffffff);
+        a.q_scanned[qi] = 0u;   // mask_kernel adds 64 per passing chunk
         a.q_flag[qi] = 0;
         // The query's FP16 row of the matrix-core scan. thr = tau^2 - |q'|^2
         // plus 96 u (|q'| + S)^2 (S bounds every |o'|) covers the FP32 errors
@@ -1607,26 +1498,78 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     }
 }
 
-// Chunk-major copy of the chunk mask for the scan: one wave per 64 queries
-// and one word column (chunks 256 g + 4 l + k, l = 0..63, for column 4 g + k);
-// a ballot per chunk turns the 64 queries' bits into that chunk's word.
-__global__ __launch_bounds__(WG) void mask_transpose_kernel(AnnArgs a) {
+// The chunk-ball test of Eq. 5 for every (query, chunk) pair of the batch,
+// written as the chunk-major mask the scan reads: bit l of word qb of chunk
+// c is query 64 qb + l. A workgroup takes 64 queries x 256 chunks: thread t
+// holds chunks c = 2 (t % 128) and c + 1 of its block and the queries
+// 32 (t / 128) .. + 31, reads the two stored squared centre distances of
+// each query row in one 4-byte load (128 threads cover 512 contiguous bytes
+// of a row) and tests d^2 <= (radius + tq)^2 + margin with the query's
+// (tq, margin) from the bound kernel. The two halves of every chunk's word
+// meet in LDS; each query's passing chunks, 64 points each, are added to its
+// scan count.
+constexpr int MQB = 64;    // queries per workgroup (one mask word)
+constexpr int MCH = 256;   // chunks per workgroup: two per thread of a query half
+static_assert(MCH == 2 * (WG / 2), "each half of the workgroup covers the block's chunks");
+
+__global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
+    __shared__ float2 qt[MQB];
+    __shared__ uint32_t hib[MCH];
+    __shared__ uint32_t cnt[MQB];
+    const int nch = (int)(a.n_pad16 >> 6);
+    const int q0 = blockIdx.y * MQB;
+    const int nqb = min(MQB, a.nq - q0);
+    const int cp = threadIdx.x & 127, qh = threadIdx.x >> 7;
+    const int c = blockIdx.x * MCH + 2 * cp;
     const int lane = lane_id();
-    const int64_t wid = ((int64_t)blockIdx.x * WG + threadIdx.x) >> 6;
-    const int64_t ncol = a.mwords;
-    const int64_t qb = wid / ncol, col = wid % ncol;
-    if (qb * 64 >= a.nq) return;
-    const int64_t q = qb * 64 + lane;
-    const uint64_t w = q < a.nq ? a.qmask[q * a.mwords + col] : 0ull;
-    const int64_t nchunk = a.n_pad16 >> 6;
-    const int64_t cbase = ((col >> 2) << 8) + (col & 3);
-    uint64_t mine = 0;   // the word of chunk cbase + 4 lane
-    for (int l = 0; l < 64; ++l) {
-        const uint64_t m = __builtin_amdgcn_ballot_w64((w >> l) & 1ull);
-        if (lane == l) mine = m;
+    if (threadIdx.x < MQB) {
+        qt[threadIdx.x] = (int)threadIdx.x < nqb ? a.qtest[q0 + threadIdx.x] : make_float2(0.f, 0.f);
+        cnt[threadIdx.x] = 0u;
     }
-    const int64_t c = cbase + 4 * lane;
-    if (c < nchunk) a.cmask[c * a.cwords + qb] = mine;
+    __syncthreads();
+    const float r0 = c < nch ? a.chunk_rad[c] : 0.f;
+    const float r1 = c + 1 < nch ? a.chunk_rad[c + 1] : 0.f;
+    uint32_t b0 = 0u, b1 = 0u;
+    constexpr int QU = 8;   // query rows whose loads go out together
+    for (int g0 = 0; g0 < 32; g0 += QU) {
+        uint32_t w[QU];
+#pragma unroll
+        for (int u = 0; u < QU; ++u) {
+            const int q = qh * 32 + g0 + u;
+            // c is even and ldc a multiple of 16: an aligned pair inside the row
+            w[u] = q < nqb && c < nch
+                       ? *reinterpret_cast<const uint32_t*>(a.cdist + (int64_t)(q0 + q) * a.ldc + c)
+                       : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < QU; ++u) {
+            const int q = qh * 32 + g0 + u;
+            const float2 t = qt[q];
+            const float ra = r0 + t.x, rb = r1 + t.x;
+            const bool p0 = q < nqb && c < nch && __uint_as_float(w[u] << 16) <= fmaf(ra, ra, t.y);
+            const bool p1 = q < nqb && c + 1 < nch &&
+                            __uint_as_float(w[u] & 0xffff0000u) <= fmaf(rb, rb, t.y);
+            b0 |= (uint32_t)p0 << (g0 + u);
+            b1 |= (uint32_t)p1 << (g0 + u);
+            const int np = __popcll(__builtin_amdgcn_ballot_w64(p0)) +
+                           __popcll(__builtin_amdgcn_ballot_w64(p1));
+            if (lane == 0 && np) atomicAdd(&cnt[q], (uint32_t)np);
+        }
+    }
+    if (qh == 1) {
+        hib[2 * cp] = b0;
+        hib[2 * cp + 1] = b1;
+    }
+    __syncthreads();
+    if (qh == 0) {
+        if (c < nch)
+            a.cmask[(int64_t)c * a.cwords + blockIdx.y] = (uint64_t)b0 | ((uint64_t)hib[2 * cp] << 32);
+        if (c + 1 < nch)
+            a.cmask[(int64_t)(c + 1) * a.cwords + blockIdx.y] =
+                (uint64_t)b1 | ((uint64_t)hib[2 * cp + 1] << 32);
+    }
+    if ((int)threadIdx.x < nqb && cnt[threadIdx.x])
+        atomicAdd(&a.q_scanned[q0 + threadIdx.x], 64u * cnt[threadIdx.x]);
 }
 
 // ---- Matrix-core scan (the range filter of the batched path) ----
@@ -2176,7 +2119,6 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.scale16 = x.scale16;
     a.chunk_cen = x.chunk_cen;
     a.chunk_rad = x.chunk_rad;
-    a.group_rad = x.group_rad;
     a.data16 = x.data16;
     a.d16_scale = x.data16_scale;
     a.d16_eps = x.data16_eps;
@@ -2186,8 +2128,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     if (ann_fast_path(L.budget)) {
         a.qaug = L.ws_qaug;
-        a.qmask = L.ws_qmask;
-        a.mwords = (int)(4 * ((x.n_pad16 / 64 + 255) / 256));
+        a.qtest = L.ws_qtest;
         a.cmask = L.ws_cmask;
         a.cwords = (int)((L.nq + 63) / 64);
         a.cdist = L.ws_cdist2;
@@ -2221,9 +2162,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_t));
             hipLaunchKernelGGL(tau_kernel, dim3((unsigned)L.nq), dim3(WG), (unsigned)lds_t, stream, a);
             PMLSH_HIP(hipGetLastError());
-            const int64_t waves = (L.nq + 63) / 64 * a.mwords;
-            hipLaunchKernelGGL(mask_transpose_kernel, dim3((unsigned)((waves + NWAVE - 1) / NWAVE)),
-                               dim3(WG), 0, stream, a);
+            dim3 mgrid((unsigned)((nchunk + MCH - 1) / MCH), (unsigned)((L.nq + MQB - 1) / MQB));
+            hipLaunchKernelGGL(mask_kernel, mgrid, dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
         // one resident wave of workgroups striding over the chunks

@@ -38,7 +38,6 @@ struct TmpBuf {
 void index_release(pmlsh_index* x) {
     if (!x) return;
     void* bufs[] = {x->data, x->proj_hi, x->proj_lo, x->proj16, x->chunk_cen, x->chunk_rad,
-                    x->group_rad,
                     x->data16, x->data16_scale, x->data16_eps, x->perm, x->inv_perm, x->hash,
                     x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max,
                     x->tree.child_begin, x->tree.child_end, x->tree.npts,
@@ -202,14 +201,8 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         std::vector<float> crad((size_t)((nch + 15) / 16 * 16), 0.f);
         for (int64_t c = 0; c < nch; ++c)
             crad[(size_t)c] = std::nextafter((float)(r64[(size_t)c] * (1.0 + 1e-6)), INFINITY);
-        // largest radius of every 64 consecutive chunks, padded with zeros to
-        // a multiple of 16 groups
-        const int64_t ngr = (nch + 63) / 64;
-        std::vector<float> grad((size_t)((ngr + 15) / 16 * 16), 0.f);
-        for (int64_t c = 0; c < nch; ++c) grad[c / 64] = std::max(grad[c / 64], crad[c]);
         upload(ccen, &x->chunk_cen);
         upload(crad, &x->chunk_rad);
-        upload(grad, &x->group_rad);
     }
 
     // ---- r_min sample (Section 5.2): FP64 distances of sampled pairs

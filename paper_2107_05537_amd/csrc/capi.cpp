@@ -46,7 +46,7 @@ namespace {
 // 64-bit word per chunk and 64 queries, both layouts); plus the frontier
 // lists of the per-query kernel's workgroups.
 struct AnnWorkspace {
-    int64_t B, pool_q, per_query, nchunk, ldc, mwords, batch, slots, bytes;
+    int64_t B, pool_q, per_query, nchunk, ldc, batch, slots, bytes;
     bool fast;
 };
 
@@ -67,13 +67,12 @@ AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
                   (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
     w.ldc = cdist_row_len(w.nchunk);
-    w.mwords = 4 * ((w.nchunk + 255) / 256);
     const int64_t per_query_all =
-        w.per_query + (w.fast ? 8 * w.mwords + 2 * w.ldc + (w.nchunk + 7) / 8 : 0);
+        w.per_query + (w.fast ? 8 + 2 * w.ldc + (w.nchunk + 7) / 8 : 0);
     w.batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     w.batch = std::min<int64_t>(w.batch, 65535);
     const int64_t mask_bytes =
-        w.fast ? w.batch * (8 * w.mwords + 2 * w.ldc) + w.nchunk * ((w.batch + 63) / 64) * 8
+        w.fast ? w.batch * (8 + 2 * w.ldc) + w.nchunk * ((w.batch + 63) / 64) * 8
                : 0;
     w.slots = front_slots(x, w.fast, w.batch);
     w.bytes = w.batch * w.per_query + mask_bytes + w.slots * 2 * x->n_leaves * 4;
@@ -116,7 +115,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     if (nq == 0) return;
     const AnnWorkspace w = ann_workspace(x, nq, k, plan.budget);
     const int64_t B = w.B, pool_q = w.pool_q, nchunk = w.nchunk, ldc = w.ldc,
-                  mwords = w.mwords, batch = w.batch;
+                  batch = w.batch;
     const bool fast = w.fast;
     void* ws = ws_alloc((size_t)w.bytes, st);
     char* base = static_cast<char*>(ws);
@@ -125,8 +124,8 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     float* qproj = reinterpret_cast<float*>(base);
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
     uint16_t* cdist2 = qaug + batch * 32;
-    uint64_t* qmask = reinterpret_cast<uint64_t*>(cdist2 + (fast ? batch * ldc : 0));
-    uint64_t* cmask = qmask + (fast ? batch * mwords : 0);
+    float2* qtest = reinterpret_cast<float2*>(cdist2 + (fast ? batch * ldc : 0));
+    uint64_t* cmask = reinterpret_cast<uint64_t*>(qtest + (fast ? batch : 0));
     uint32_t* list = reinterpret_cast<uint32_t*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
     int32_t* cpos = front + w.slots * 2 * x->n_leaves;
@@ -162,7 +161,7 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             L.ws_topk = topk;
             if (fast) {
                 L.ws_qaug = qaug;
-                L.ws_qmask = qmask;
+                L.ws_qtest = qtest;
                 L.ws_clo = clo;
                 L.ws_cmask = cmask;
                 L.ws_cdist2 = cdist2;

@@ -191,7 +191,6 @@ struct pmlsh_index {
     float scale16 = 1.f;         // power-of-two scale s of those rows
     float* chunk_cen = nullptr;  // n_pad16 / 64 x MP: centre of each 64-point chunk
     float* chunk_rad = nullptr;  // n_pad16 / 64: radius covering the chunk's points
-    float* group_rad = nullptr;  // per 64 consecutive chunks: the largest of their radii
     uint16_t* data16 = nullptr;  // n x d16 FP16 copy of D_leaf, rows scaled by a power of two
     float* data16_scale = nullptr;  // n: that power of two
     float* data16_eps = nullptr;    // n: bound on |row - scale * FP16 row|
@@ -279,7 +278,7 @@ struct AnnLaunch {
     uint32_t* q_scanned;
     uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
     uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
-    uint64_t* ws_qmask;     // nq x mask words: chunks each query must scan
+    float2* ws_qtest;       // nq: radius and margin of each query's chunk-ball test
     uint64_t* ws_cmask;     // the same, chunk-major: chunks x ceil(nq / 64) words
     uint16_t* ws_cdist2;    // nq x ldc: squared distances to the chunk centres (bf16, rounded down)
     int64_t pool_cap;       // candidate region per query
