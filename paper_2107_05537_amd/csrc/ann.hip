@@ -66,6 +66,8 @@ struct AnnArgs {
     float coord_scale;
     const float* q;
     const float* qp;
+    const float* qp_lo;         // FP32 rounding of (projection - qp)
+    const float* proj_lo;       // the same for the data, leaf order
     int k;
     int32_t budget;
     double c, t, r_min;
@@ -1787,6 +1789,75 @@ __global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
     scan_flush(a, ss, wave, lane, wn, qw0, nqw);
 }
 
+// The budget cut of L in the FP64 order. The FP32 pd^2 of a pool entry
+// (direct differences of the FP32 projections) is within
+// E = 2^-22 pd (|q'| + S) + 2^-19 pd^2 of its value from the FP64 projections
+// (the FP32 roundings of both projections and of the differences, and the
+// FP32 sum of 16 squares), so only entries whose FP32 value lies within a
+// band of 2E around the B-th value (kth) can be ordered differently in FP64.
+// Their pd^2 is recomputed in FP64 from the hi and lo halves of both
+// projections: the entries below the band are in L, the first B - below of
+// the band by (FP64 pd^2, id) join them, everything else leaves (key ~0).
+// Returns false, marking nothing, when the band holds more than 512 entries.
+__device__ bool cut_fp64(const AnnArgs& a, int64_t qi, const QueryCtx& qc, int n, int B,
+                         uint64_t kth, Smem& sh) {
+    constexpr int kBandCap = 512;
+    int32_t* band = reinterpret_cast<int32_t*>(sh.hist);            // entry, ~entry if out
+    uint32_t* bid = reinterpret_cast<uint32_t*>(sh.hist + kBandCap); // its id
+    double* b64 = reinterpret_cast<double*>(sh.hist + 2 * kBandCap); // its FP64 pd^2
+    static_assert(NB >= 4 * kBandCap, "the band must fit the histogram");
+    const float k2 = __uint_as_float((uint32_t)(kth >> 32));
+    const float big = sqrtf(qc.qn2) + a.coord_scale;
+    const float e = 2.f * (2.384185791015625e-07f * sqrtf(k2) * big + 1.9073486328125e-06f * k2);
+    const float blo = k2 - 2.f * e, bhi = k2 + 2.f * e;
+    __syncthreads();
+    if (threadIdx.x == 0) sh.cnt2 = 0;
+    __syncthreads();
+    int below = 0;
+    for (int b0 = 0; b0 < n; b0 += WG) {
+        const int i = b0 + threadIdx.x;
+        const float v = i < n ? __uint_as_float((uint32_t)(sh.skey[i] >> 32)) : __int_as_float(0x7f800000);
+        below += i < n && v < blo;
+        const bool inb = i < n && v >= blo && v <= bhi;
+        const int slot = wave_append(inb, &sh.cnt2);
+        if (inb && slot < kBandCap) {
+            band[slot] = i;
+            bid[slot] = (uint32_t)sh.skey[i];
+        }
+    }
+    below = block_sum(below, sh);
+    const int nb = sh.cnt2;
+    if (nb > kBandCap || below >= B || below + nb < B) return false;
+    for (int j = threadIdx.x; j < nb; j += WG) {
+        const int64_t pos = sh.spos[band[j]];
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            const double o = (double)a.proj[pos * MP + t] + (double)a.proj_lo[pos * MP + t];
+            const double q = (double)a.qp[qi * MP + t] + (double)a.qp_lo[qi * MP + t];
+            const double dd = q - o;
+            acc = fma(dd, dd, acc);
+        }
+        b64[j] = acc;
+    }
+    __syncthreads();
+    const int need = B - below;
+    for (int j = threadIdx.x; j < nb; j += WG) {
+        const double v = b64[j];
+        const uint32_t id = bid[j];
+        int rank = 0;
+        for (int y = 0; y < nb; ++y) rank += b64[y] < v || (b64[y] == v && bid[y] < id);
+        if (rank >= need) band[j] = ~band[j];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nb; j += WG)
+        if (band[j] < 0) sh.skey[~band[j]] = ~0ull;
+    for (int i = threadIdx.x; i < n; i += WG)
+        if (__uint_as_float((uint32_t)(sh.skey[i] >> 32)) > bhi) sh.skey[i] = ~0ull;
+    __syncthreads();
+    return true;
+}
+
 __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
@@ -1843,9 +1914,11 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         __syncthreads();
         if (n > B) {
             const uint64_t kth = lds_select(n, B, sh);
-            for (int i = threadIdx.x; i < n; i += WG)
-                if (sh.skey[i] > kth) sh.skey[i] = ~0ull;
-            __syncthreads();
+            if (!cut_fp64(a, qi, qc, n, B, kth, sh)) {
+                for (int i = threadIdx.x; i < n; i += WG)
+                    if (sh.skey[i] > kth) sh.skey[i] = ~0ull;
+                __syncthreads();
+            }
         }
         nl = n;
     } else {
@@ -2099,6 +2172,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.coord_scale = x.coord_scale;
     a.q = L.queries;
     a.qp = L.qproj;
+    a.qp_lo = L.qproj_lo;
+    a.proj_lo = x.proj_lo;
     a.k = L.k;
     a.budget = (int32_t)L.budget;
     a.c = L.c;

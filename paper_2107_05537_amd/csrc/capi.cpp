@@ -63,7 +63,7 @@ AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
     w.B = B;
     w.fast = ann_fast_path(B);
     w.pool_q = w.fast ? ann_pool_per_query(x->n) : 0;
-    w.per_query = (int64_t)MP * 4 + 64 + B * 8 + 3 * (int64_t)k * 4 +
+    w.per_query = (int64_t)MP * 8 + 64 + B * 8 + 3 * (int64_t)k * 4 +
                   (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
     w.ldc = cdist_row_len(w.nchunk);
@@ -122,7 +122,8 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     // projections and FP16 scan rows first: every row starts on a 64-byte
     // boundary
     float* qproj = reinterpret_cast<float*>(base);
-    uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj + batch * MP);
+    float* qproj_lo = qproj + batch * MP;
+    uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj_lo + batch * MP);
     uint16_t* cdist2 = qaug + batch * 32;
     float2* qtest = reinterpret_cast<float2*>(cdist2 + (fast ? batch * ldc : 0));
     uint64_t* cmask = reinterpret_cast<uint64_t*>(qtest + (fast ? batch : 0));
@@ -141,12 +142,13 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
             const float* qb = queries + q0 * x->d;
             {
                 StageTimer tm(PMLSH_STAGE_PROJECT, st);
-                launch_project(qb, nb, x->d, x->d, x->hash, qproj, nullptr, st);
+                launch_project(qb, nb, x->d, x->d, x->hash, qproj, qproj_lo, st);
             }
             AnnLaunch L{};
             L.idx = x;
             L.queries = qb;
             L.qproj = qproj;
+            L.qproj_lo = qproj_lo;
             L.nq = nb;
             L.k = k;
             L.c = c;

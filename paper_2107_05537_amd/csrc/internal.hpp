@@ -261,6 +261,7 @@ struct AnnLaunch {
     const pmlsh_index* idx;
     const float* queries;   // nq x d (caller layout)
     const float* qproj;     // nq x MP
+    const float* qproj_lo;  // nq x MP: FP32 rounding of (projection - qproj)
     int64_t nq;
     int k;
     double c, t, r_min;
