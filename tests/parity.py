@@ -52,8 +52,23 @@ def _tie_groups(d, tol):
     return groups
 
 
-def compare_ann(D, Q, res, ids, dist, stats=None):
+# Decisions the batched path takes in the FP64 order (the budget cut of L and
+# the top-k order): a query whose other margins are clear must match the
+# oracle exactly when these two exceed FP64 resolution (the FP64 projections
+# and distances of both sides differ by their summation order only).
+FP64_DECIDED = ("topk_order", "budget_cut")
+FP64_RESOLUTION = 1e-11
+
+
+def _fp64_exact(r):
+    return all(v > (FP64_RESOLUTION if kind in FP64_DECIDED else FRAGILE)
+               for kind, v in r.margins.items())
+
+
+def compare_ann(D, Q, res, ids, dist, stats=None, fp64=False):
     """res: oracle results; ids/dist/stats: library outputs as NumPy arrays.
+    With fp64 (queries answered by the batched path), near ties of the budget
+    cut and of the top-k order are held to exact agreement too.
     Returns (number of queries with a near-tie in the top-k order only,
     number with a near-tie at a candidate-set decision)."""
     n_order, n_set = 0, 0
@@ -61,7 +76,7 @@ def compare_ann(D, Q, res, ids, dist, stats=None):
         gi = ids[qi].tolist()
         gd = dist[qi].astype(np.float64)
         oi = r.ids.tolist()
-        if r.margin > FRAGILE:
+        if r.margin > FRAGILE or (fp64 and _fp64_exact(r)):
             assert gi == oi, (qi, gi, oi, r.margin_kind, r.margin)
             np.testing.assert_allclose(gd, r.dist, rtol=TOL, atol=1e-6,
                                        err_msg=f"query {qi}")

@@ -55,7 +55,7 @@ def test_parity_workload_full(parity_wl):
     idx, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.1, r0)
     # the library's own r_min rule reproduces the oracle's
     assert idx.default_r_min(B) == pytest.approx(r0, rel=1e-12)
-    nf = compare_ann(D, Q, res, ids, dist, st)
+    nf = compare_ann(D, Q, res, ids, dist, st, fp64=True)
     say("fragile queries:", nf)
     # default r_min (0) gives the same answers as passing it explicitly
     ids2, dist2 = idx.ann(torch.from_numpy(Q).cuda(), 10, c=1.5, confidence=0.9, beta=0.1)
@@ -160,7 +160,7 @@ def test_shapes(n, d, m, leaf, fan, piv):
                               fanout=fan, num_pivots=piv, sample_seed=3)
     info = idx.info()
     say("levels", info["levels"], "leaves", info["n_leaves"])
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 @pytest.mark.parametrize("c", [1.2, 1.5, 2.0])
@@ -179,7 +179,7 @@ def test_heavy_tailed_d960(c):
     r0 = oracle_r_min(D, 5, B)
     res, _ = oracle_ann(D, A, Q, k, c, 0.9, beta, r_min=r0)
     idx, ids, dist, st = _run(pm, D, A, Q, k, c, 0.9, beta, r0, sample_seed=5)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
     say("exit kinds", np.bincount(st[:, 2], minlength=3), "rounds", np.bincount(st[:, 0]))
 
 
@@ -329,7 +329,7 @@ def test_headline_scale_sampled():
     Dp = oann.project(D, A)
     sample = np.arange(0, 1024, 64)
     res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
-    compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
+    compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample], fp64=True)
     say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
 
 
@@ -357,7 +357,7 @@ def test_serving_scale_sampled():
         torch.cuda.synchronize()
         ids, dist, st = ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
         res, _ = oracle_ann(D, A, Q[sample], k, c, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
-        compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
+        compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample], fp64=True)
         say("exit kinds", np.bincount(st[:, 2], minlength=3), "rounds", np.bincount(st[:, 0]))
 
 
@@ -423,7 +423,7 @@ def test_large_n_sampled():
     Dp = oann.project(D, A)
     sample = np.arange(0, 512, 32)
     res, _ = oracle_ann(D, A, Q[sample], k, 1.5, 1 - 1 / math.e, beta, r_min=r0, Dp=Dp)
-    compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample])
+    compare_ann(D, Q[sample], res, ids[sample], dist[sample], st[sample], fp64=True)
     say("exit kinds", np.bincount(st[:, 2]), "rounds", np.bincount(st[:, 0]))
     for cap, lds in GROUP_SETTINGS:
         say(f"case: n=2.6M group list {cap} minima in LDS {lds}")
