@@ -905,6 +905,22 @@ __device__ void write_topk(const AnnArgs& a, int64_t qi, const float* qs, const 
         block_select(c_src, [&](int32_t i, int slot) { if (slot < k) topk[slot] = i; }, 0ull,
                      ~0ull, k, false, 0, sh);
         __syncthreads();
+        // the k-th smallest FP32 value (the largest of the k selected), then
+        // the FP64 re-rank
+        float kmax = 0.f;
+        for (int j = threadIdx.x; j < k; j += WG) kmax = fmaxf(kmax, cdist[topk[j]]);
+        for (int off = 32; off > 0; off >>= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, off));
+        if (lane_id() == 0) sh.red[threadIdx.x >> 6] = __float_as_int(kmax);
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NWAVE; ++w) kmax = fmaxf(kmax, __int_as_float(sh.red[w]));
+        __syncthreads();
+        if (rerank_topk64(a, qi, qs, cpos, n_ver, kmax,
+                          [&](int j, float& v, int& mi) { v = cdist[j]; mi = j; }, sh))
+            done = true;
+    }
+    if (!done && n_ver > CAP) {
+        const int32_t* topk = a.ws_topk + qi * 3 * (int64_t)a.k;
         for (int j = threadIdx.x; j < k; j += WG) {
             const int i = topk[j];
             sh.skey[j] = ((uint64_t)__float_as_uint(cdist[i]) << 32) | (uint32_t)perm[cpos[i]];
@@ -943,6 +959,84 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
         __syncthreads();
         ann_one(a, qi, fa, fb, qs, sh);
     }
+}
+
+// The budget cut of the per-query path in the FP64 order, as cut_fp64 does
+// for the batched path: the need members chosen from the shell (FP32 keys,
+// in cpos[n_ver, n_ver + need)) are replaced by the shell's entries below a
+// band of 2E around the largest chosen FP32 pd^2 and the first band entries
+// by (FP64 pd^2, id). The band stays inside the shell (entries of earlier
+// rounds are in C by ball membership). Nothing changes when the band holds
+// more than 512 entries.
+template <class BallSrc>
+__device__ void shell_cut_fp64(const AnnArgs& a, int64_t qi, const QueryCtx& qc, BallSrc& ball_src,
+                               uint32_t lo_hi, int n_ver, int need, int32_t* cpos, Smem& sh) {
+    constexpr int kBandCap = 512;
+    int32_t* bpos = reinterpret_cast<int32_t*>(sh.hist);
+    uint32_t* bid = reinterpret_cast<uint32_t*>(sh.hist + kBandCap);
+    double* b64 = reinterpret_cast<double*>(sh.hist + 2 * kBandCap);
+    static_assert(NB >= 4 * kBandCap, "the band must fit the histogram");
+    // the largest FP32 pd^2 among the chosen
+    float kmax = 0.f;
+    for (int j = threadIdx.x; j < need; j += WG)
+        kmax = fmaxf(kmax, proj_dist2(a.proj + (int64_t)cpos[n_ver + j] * MP, qc.qp));
+    for (int off = 32; off > 0; off >>= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, off));
+    if (lane_id() == 0) sh.red[threadIdx.x >> 6] = __float_as_int(kmax);
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) kmax = fmaxf(kmax, __int_as_float(sh.red[w]));
+    __syncthreads();
+    const float big = sqrtf(qc.qn2) + a.coord_scale;
+    const float e = 2.f * (2.384185791015625e-07f * sqrtf(kmax) * big + 1.9073486328125e-06f * kmax);
+    const float blo = fmaxf(kmax - 2.f * e, __uint_as_float(lo_hi)), bhi = kmax + 2.f * e;
+    if (threadIdx.x == 0) sh.cnt2 = 0;
+    __syncthreads();
+    int below = 0;
+    ball_src([&](bool mem, uint64_t key, int32_t pos) {
+        const float v = __uint_as_float((uint32_t)(key >> 32));
+        below += mem && v < blo;
+        const bool inb = mem && v >= blo && v <= bhi;
+        const int slot = wave_append(inb, &sh.cnt2);
+        if (inb && slot < kBandCap) {
+            bpos[slot] = pos;
+            bid[slot] = (uint32_t)key;
+        }
+    });
+    below = block_sum(below, sh);
+    const int nb = sh.cnt2;
+    if (nb > kBandCap || below > need || below + nb < need) return;
+    for (int j = threadIdx.x; j < nb; j += WG) {
+        const int64_t pos = bpos[j];
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            const double o = (double)a.proj[pos * MP + t] + (double)a.proj_lo[pos * MP + t];
+            const double q = (double)a.qp[qi * MP + t] + (double)a.qp_lo[qi * MP + t];
+            const double dd = q - o;
+            acc = fma(dd, dd, acc);
+        }
+        b64[j] = acc;
+    }
+    __syncthreads();
+    // C's shell part again: the entries below the band, then the band's
+    // first need - below
+    if (threadIdx.x == 0) sh.cnt2 = 0;
+    __syncthreads();
+    ball_src([&](bool mem, uint64_t key, int32_t pos) {
+        const bool take = mem && __uint_as_float((uint32_t)(key >> 32)) < blo;
+        const int slot = wave_append(take, &sh.cnt2);
+        if (take) cpos[n_ver + slot] = pos;
+    });
+    __syncthreads();
+    const int keep = need - below;
+    for (int j = threadIdx.x; j < nb; j += WG) {
+        const double v = b64[j];
+        const uint32_t id = bid[j];
+        int rank = 0;
+        for (int y = 0; y < nb; ++y) rank += b64[y] < v || (b64[y] == v && bid[y] < id);
+        if (rank < keep) cpos[n_ver + below + rank] = bpos[j];
+    }
+    __syncthreads();
 }
 
 // Algorithm 2 for query qi, round by round with PM-tree walks.
@@ -1033,6 +1127,7 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
                          },
                          klo, khi, need, true, shell, sh);
             __syncthreads();
+            shell_cut_fp64(a, qi, qc, ball_src, lo_hi, n_ver, need, cpos, sh);
             verify(a, qs, cpos, cdist, n_ver, B);
             n_ver = B;
             exit_kind = PMLSH_EXIT_BUDGET;

@@ -52,10 +52,10 @@ def _tie_groups(d, tol):
     return groups
 
 
-# Decisions the batched path takes in the FP64 order (the budget cut of L and
-# the top-k order): a query whose other margins are clear must match the
-# oracle exactly when these two exceed FP64 resolution (the FP64 projections
-# and distances of both sides differ by their summation order only).
+# Decisions the library takes in the FP64 order (the budget cut and the
+# top-k order): a query whose other margins are clear must match the oracle
+# exactly when these two exceed FP64 resolution (the FP64 projections and
+# distances of both sides differ by their summation order only).
 FP64_DECIDED = ("topk_order", "budget_cut")
 FP64_RESOLUTION = 1e-11
 
@@ -67,8 +67,9 @@ def _fp64_exact(r):
 
 def compare_ann(D, Q, res, ids, dist, stats=None, fp64=False):
     """res: oracle results; ids/dist/stats: library outputs as NumPy arrays.
-    With fp64 (queries answered by the batched path), near ties of the budget
-    cut and of the top-k order are held to exact agreement too.
+    With fp64, near ties of the budget cut and of the top-k order (decided in
+    the FP64 order by both paths of the library) are held to exact agreement
+    too.
     Returns (number of queries with a near-tie in the top-k order only,
     number with a near-tie at a candidate-set decision)."""
     n_order, n_set = 0, 0

@@ -85,7 +85,7 @@ def test_projected_knn_special_case(parity_wl):
     res, B = oracle_ann(D, A, Q, 8, 1.5, 0.9, 0.0, r_min=1e30)
     assert B == 8
     _, ids, dist, st = _run(pm, D, A, Q, 8, 1.5, 0.9, 0.0, 1e30)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 @pytest.mark.parametrize("scale,beta,k,expect", [(0.05, 0.1, 10, "multi"),
@@ -101,7 +101,7 @@ def test_multi_round_and_line4(parity_wl, scale, beta, k, expect):
     r0 = scale * oracle_r_min(D, 7, B)
     res, _ = oracle_ann(D, A, Q, k, 1.5, 0.9, beta, r_min=r0)
     _, ids, dist, st = _run(pm, D, A, Q, k, 1.5, 0.9, beta, r0)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
     kinds = {r.exit_kind for r in res}
     rounds = max(r.rounds for r in res)
     say("exit kinds", kinds, "max rounds", rounds)
@@ -121,7 +121,7 @@ def test_topk_larger_than_one_workgroup(parity_wl):
     res, B = oracle_ann(D, A, Q, 300, 1.5, 0.9, 0.05, r_min=1e30)
     assert B == 800
     _, ids, dist, st = _run(pm, D, A, Q, 300, 1.5, 0.9, 0.05, 1e30)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 def test_budget_larger_than_one_sort(parity_wl):
@@ -134,7 +134,7 @@ def test_budget_larger_than_one_sort(parity_wl):
     res, B = oracle_ann(D, A, Q, 50, 1.5, 0.9, 0.4, r_min=1e30)
     assert B == 4050
     _, ids, dist, st = _run(pm, D, A, Q, 50, 1.5, 0.9, 0.4, 1e30)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 @pytest.mark.parametrize("n,d,m,leaf,fan,piv", [
@@ -201,7 +201,7 @@ def test_data_scale_extremes(scale):
     r0 = oracle_r_min(D, 3, B)
     res, _ = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.05, r_min=r0)
     _, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.05, r0, sample_seed=3)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 def test_ties_duplicates_and_self_queries():
@@ -220,7 +220,7 @@ def test_ties_duplicates_and_self_queries():
     _, ids, dist, st = _run(pm, D, A, Q, 7, 1.5, 0.9, 0.1, 1e30, leaf_size=16)
     # duplicates tie exactly in FP32 as in FP64, so both sides break the tie
     # on the id: the answers must agree id for id
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
     assert np.array_equal(ids, np.stack([r.ids for r in res]))
     assert np.all(dist[:10, 0] == 0)
 
@@ -240,7 +240,7 @@ def test_far_queries_take_the_per_query_path():
     Q = np.concatenate([Qn, Qf])
     res, B = oracle_ann(D, A, Q, 5, 1.5, 0.9, 0.05, r_min=1.0)
     _, ids, dist, st = _run(pm, D, A, Q, 5, 1.5, 0.9, 0.05, 1.0)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 def test_stage_overflow_takes_the_per_query_path():
@@ -259,7 +259,7 @@ def test_stage_overflow_takes_the_per_query_path():
     res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=1.0)
     assert B < 5000
     _, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.1, 1.0)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
     assert np.array_equal(ids, np.stack([r.ids for r in res]))
 
 
@@ -277,7 +277,7 @@ def test_tiny_inputs():
     D = rng.standard_normal((9, 8)).astype(np.float32)
     res, B = oracle_ann(D, A, Q, 9, 2.0, 0.9, 0.0, r_min=1e-3)
     _, ids, dist, st = _run(pm, D, A, Q, 9, 2.0, 0.9, 0.0, 1e-3)
-    compare_ann(D, Q, res, ids, dist, st)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
 
 
 def test_empty_batch_and_errors(parity_wl):
