@@ -140,7 +140,13 @@ int pmlsh_default_r_min(const pmlsh_index* index, int64_t budget, double* r_min)
  * (c) if they number >= B, the candidate set C is the B of them nearest to q'
  *     in the projected space (ties by id) and the loop stops; otherwise
  *     C is all of them and r <- c*r.
- * The answer is the k members of C nearest to q by exact distance.
+ * The answer is the k members of C nearest to q by exact distance, in
+ * (distance, id) order; out_dist holds Euclidean distances (not squared).
+ * Precision: projected and exact distances are computed in FP32; where the
+ * FP32 values leave the order open within their rounding error, the budget
+ * cut in (c) and the order of the answer are decided on FP64 values (the
+ * FP64 projection and FP64 distances from the FP32 rows), and out_dist is
+ * the FP32 rounding of the FP64 distance.
  * Asynchronous on `stream`. Errors: EINVAL, ENOMEM (workspace), EDEVICE,
  * EUNSUPPORTED (k > PMLSH_MAX_K).
  */
