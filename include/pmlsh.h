@@ -146,7 +146,8 @@ int pmlsh_default_r_min(const pmlsh_index* index, int64_t budget, double* r_min)
  * FP32 values leave the order open within their rounding error, the budget
  * cut in (c) and the order of the answer are decided on FP64 values (the
  * FP64 projection and FP64 distances from the FP32 rows), and out_dist is
- * the FP32 rounding of the FP64 distance.
+ * the FP32 rounding of the FP64 distance (more than 512 members within FP32
+ * rounding of the k-th keep the FP32 order and distances).
  * Asynchronous on `stream`. Errors: EINVAL, ENOMEM (workspace), EDEVICE,
  * EUNSUPPORTED (k > PMLSH_MAX_K).
  */
