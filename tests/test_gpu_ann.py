@@ -14,7 +14,7 @@ import pytest
 
 import synth
 from oracle import brute
-from parity import compare_ann, oracle_ann, oracle_r_min, say
+from parity import TOL, compare_ann, oracle_ann, oracle_r_min, say
 
 pytestmark = pytest.mark.gpu
 
@@ -223,6 +223,41 @@ def test_ties_duplicates_and_self_queries():
     compare_ann(D, Q, res, ids, dist, st, fp64=True)
     assert np.array_equal(ids, np.stack([r.ids for r in res]))
     assert np.all(dist[:10, 0] == 0)
+
+
+def test_fp64_decisions_fall_back_on_mass_ties():
+    """700 exact copies of one point among 3,000 others, the query on top of
+    them and B = 601 (beta = 0.1, k = 1 ... 20): the budget cut's band and the
+    top-k's near-tie set both hold more than 512 entries, so both FP64
+    decisions fall back to the FP32 order, which on exact ties is the id
+    order as in the oracle. C is the 601 copies with the smallest ids and the
+    answer the k smallest of them, at distance 0 from a query equal to the
+    point; a query slightly off the point gets the same ids."""
+    pm = _gpu()
+    say("case: 700 copies of one point")
+    rng = np.random.Generator(np.random.PCG64(7))
+    d = 32
+    others = (rng.standard_normal((3000, d)) * 3.0 + 10.0).astype(np.float32)
+    p0 = rng.standard_normal(d).astype(np.float32)
+    D = np.concatenate([others, np.repeat(p0[None, :], 700, axis=0)])
+    order = rng.permutation(D.shape[0])
+    D = D[order]
+    copies = np.sort(np.flatnonzero(np.all(D == p0[None, :], axis=1)))
+    assert copies.size == 700
+    A = rng.standard_normal((15, d)).astype(np.float32)
+    Q = np.stack([p0, p0 + np.float32(1e-3)])
+    n = D.shape[0]
+    beta = 600.0 / n
+    for k in (1, 20):
+        res, B = oracle_ann(D, A, Q, k, 1.5, 0.9, beta, r_min=1e30)
+        assert B > 512 and B < 700
+        _, ids, dist, st = _run(pm, D, A, Q, k, 1.5, 0.9, beta, 1e30)
+        for qi in range(2):
+            assert ids[qi].tolist() == copies[:k].tolist(), (k, qi, ids[qi])
+            assert ids[qi].tolist() == res[qi].ids.tolist()
+            assert st[qi, 1] == B and st[qi, 2] == res[qi].exit_kind
+        assert np.all(dist[0] == 0)
+        np.testing.assert_allclose(dist[1], res[1].dist, rtol=TOL, atol=1e-6)
 
 
 def test_far_queries_take_the_per_query_path():
