@@ -48,7 +48,7 @@ extern "C" {
 #define PMLSH_MAX_K 1024        /* results per ANN query / ACP call          */
 
 /* exit kinds reported per ANN query (Algorithm 2)                          */
-#define PMLSH_EXIT_LINE4 1      /* k verified points within c*r              */
+#define PMLSH_EXIT_NEAR 1      /* k verified points within c*r              */
 #define PMLSH_EXIT_BUDGET 2     /* the range query reached beta*n + k points */
 
 typedef struct pmlsh_index pmlsh_index; /* opaque, owned by the caller once built */

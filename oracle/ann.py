@@ -39,7 +39,7 @@ import math
 
 import numpy as np
 
-EXIT_LINE4 = 1     # enough verified points within c*r
+EXIT_NEAR = 1     # enough verified points within c*r
 EXIT_BUDGET = 2    # the ball reached the budget B
 
 
@@ -94,9 +94,9 @@ def query(D: np.ndarray, Dp: np.ndarray, q: np.ndarray, qp: np.ndarray,
         if rounds > 0:
             thr = c * r
             margins.append((float(np.min(np.abs(cand_dist - thr))) / thr
-                            if cand.size else math.inf, "line4"))
+                            if cand.size else math.inf, "cr_stop"))
             if int(np.count_nonzero(cand_dist <= thr)) >= k:
-                exit_kind = EXIT_LINE4
+                exit_kind = EXIT_NEAR
                 break
         R = t * r
         rounds += 1

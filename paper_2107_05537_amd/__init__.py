@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libpmlsh.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
-EXIT_LINE4, EXIT_BUDGET = 1, 2
+EXIT_NEAR, EXIT_BUDGET = 1, 2
 MAX_K = 1024
 
 

@@ -3,7 +3,7 @@
 //
 // Per round i (radius r_i = r_min * c^i):
 //   1. from the second round on, count the verified candidates within c*r_i
-//      of q and stop when there are at least k (Algorithm 2, line 4);
+//      of q and stop when there are at least k (the stopping test of Algorithm 2);
 //   2. walk the flattened PM-tree level by level, keeping the nodes that pass
 //      the PM-tree access test of Eq. 5 for the range query (q', t*r_i); the
 //      surviving leaves go to a per-query list in global memory;
@@ -1068,7 +1068,7 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
             const float thr2 = (float)(cr * cr);
             int loc = 0;
             for (int i = threadIdx.x; i < n_ver; i += WG) loc += cdist[i] <= thr2;
-            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
+            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_NEAR; break; }
         }
         if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
         const double Rd = a.t * r;
@@ -2057,7 +2057,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     uint32_t prev_bits = 0;
     for (;;) {
         if (rounds > 0) {
-            // line 4: at least k verified members within c r
+            // the c r stop: at least k verified members within c r
             const double cr = a.c * r;
             const float thr2 = (float)(cr * cr);
             int sure = 0, maybe = 0;
@@ -2083,7 +2083,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
                 for (int i = threadIdx.x; i < n_ver; i += WG) loc += hi2[i] <= thr2;
                 sure = block_sum(loc, sh);
             }
-            if (sure >= a.k) { exit_kind = PMLSH_EXIT_LINE4; break; }
+            if (sure >= a.k) { exit_kind = PMLSH_EXIT_NEAR; break; }
         }
         if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
         const double Rd = a.t * r;

@@ -90,9 +90,9 @@ def test_projected_knn_special_case(parity_wl):
 
 @pytest.mark.parametrize("scale,beta,k,expect", [(0.05, 0.1, 10, "multi"),
                                                  (0.3, 0.02, 1, "multi"),
-                                                 (0.5, 0.05, 100, "line4")])
-def test_multi_round_and_line4(parity_wl, scale, beta, k, expect):
-    """Small first radius: several range queries, line-4 and budget exits."""
+                                                 (0.5, 0.05, 100, "cr_stop")])
+def test_multi_round_and_cr_stop(parity_wl, scale, beta, k, expect):
+    """Small first radius: several range queries, c r stops and budget exits."""
     pm = _gpu()
     w = parity_wl
     D, A, Q = w["D"], w["A"], w["Q"][:60]
@@ -108,7 +108,7 @@ def test_multi_round_and_line4(parity_wl, scale, beta, k, expect):
     if expect == "multi":
         assert rounds >= 2          # several range queries
     else:
-        assert 1 in kinds           # Algorithm 2's line-4 exit
+        assert 1 in kinds           # Algorithm 2's c r stop
 
 
 def test_topk_larger_than_one_workgroup(parity_wl):

@@ -3,7 +3,7 @@
 * Hand-traced runs on points on a line, where the projection is the first
   coordinate (m = 1, A = [1, 0]) and t is set to 1, so every projected
   distance, ball and round can be followed by hand. They fix the closed
-  ball, the line-4 test against c times the enlarged radius, the growth
+  ball, the c r stopping test against c times the enlarged radius, the growth
   r <- c r, the budget exit and the (pd, id) order of the budget cut.
 * Special cases that reduce to exact search: with B = n and an unbounded
   first radius the answer is the exact kNN (checked with SciPy's k-d tree);
@@ -34,41 +34,41 @@ def _line(points, qpt=(0.0, 0.0)):
 ON_AXIS = [(1, 0), (2, 0), (4, 0), (8, 0), (16, 0)]
 
 
-def test_trace_closed_ball_and_line4():
+def test_trace_closed_ball_and_cr_stop():
     # r = 0.5: ball empty.  r = 1: the point at projected distance exactly 1
-    # is inside the closed ball, C = {0}.  r = 2: line 4 with c r = 4 finds
+    # is inside the closed ball, C = {0}.  r = 2: the c r stop with c r = 4 finds
     # 1 <= 4 and stops after two range queries.  An open ball would need a
     # third range query.
     D, Dp, q, qp = _line(ON_AXIS)
     res = ann.query(D, Dp, q, qp, k=1, c=2.0, t=1.0, budget=3, r_min=0.5)
     assert res.ids.tolist() == [0]
     assert res.dist.tolist() == [1.0]
-    assert res.exit_kind == ann.EXIT_LINE4
+    assert res.exit_kind == ann.EXIT_NEAR
     assert res.rounds == 2
     assert res.r_final == 2.0
 
 
-def test_trace_line4_needs_k_points():
+def test_trace_cr_stop_needs_k_points():
     D, Dp, q, qp = _line(ON_AXIS)
     res = ann.query(D, Dp, q, qp, k=2, c=2.0, t=1.0, budget=3, r_min=0.5)
-    # r=.5 {} ; r=1 {0} ; r=2: line4 (c r = 4) counts 1 < 2, ball {0,1} < 3 ;
-    # r=4: line4 (c r = 8) counts 2 -> stop
+    # r=.5 {} ; r=1 {0} ; r=2: the c r stop (c r = 4) counts 1 < 2, ball {0,1} < 3 ;
+    # r=4: the c r stop (c r = 8) counts 2 -> stop
     assert res.ids.tolist() == [0, 1]
-    assert res.rounds == 3 and res.exit_kind == ann.EXIT_LINE4
+    assert res.rounds == 3 and res.exit_kind == ann.EXIT_NEAR
     assert res.n_cand == 2
 
 
 def test_trace_budget_exit():
     D, Dp, q, qp = _line(ON_AXIS)
     res = ann.query(D, Dp, q, qp, k=2, c=2.0, t=1.0, budget=2, r_min=0.5)
-    # r=2: line4 counts 1 < 2, then the ball {0,1} reaches B = 2
+    # r=2: the c r stop counts 1 < 2, then the ball {0,1} reaches B = 2
     assert res.ids.tolist() == [0, 1]
     assert res.rounds == 3 and res.exit_kind == ann.EXIT_BUDGET
 
 
-def test_trace_line4_uses_enlarged_radius():
+def test_trace_cr_stop_uses_enlarged_radius():
     # point 0 is nearest in projection (pd 1) but at exact distance sqrt(10).
-    # After the first range query (r = 1, C = {0}), r becomes 2 and line 4
+    # After the first range query (r = 1, C = {0}), r becomes 2 and the c r stop
     # compares sqrt(10) with c r = 4: stop with point 0. Comparing with r or
     # with c times the old radius (2) would not stop and would return point 1.
     D, Dp, q, qp = _line([(1, 3), (2, 0), (4, 0), (8, 0), (16, 0)])
@@ -147,7 +147,7 @@ def test_invariants_and_theorem1(small_mixture):
         assert key == sorted(key)
         assert np.all(r.dist >= dstar - 1e-12)          # rank-wise >= exact
         assert r.n_cand <= B
-        if r.exit_kind == ann.EXIT_LINE4:
+        if r.exit_kind == ann.EXIT_NEAR:
             assert r.dist[-1] <= c * r.r_final
         assert metrics.overall_ratio(r.dist, dstar) >= 1.0
         good += r.dist[0] <= c * c * dstar[0]
@@ -170,11 +170,11 @@ def test_parity_workload_quality():
     assert rec >= 0.95
 
 
-def test_trace_line4_threshold_is_c_times_r():
+def test_trace_cr_stop_threshold_is_c_times_r():
     # point 0: projected distance 1, exact sqrt(26) = 5.10.  After r = 1
-    # (C = {0}) the radius becomes 2 and line 4 compares 5.10 with c r = 4:
+    # (C = {0}) the radius becomes 2 and the c r stop compares 5.10 with c r = 4:
     # no stop.  The ball at r = 2 adds point 1 (exact 2); r becomes 4 and
-    # line 4 (c r = 8) stops; the answer is point 1.  A test against c^2 r
+    # the c r stop (c r = 8) ends the loop; the answer is point 1.  A test against c^2 r
     # would stop one round early with point 0.
     D, Dp, q, qp = _line([(1, 5), (2, 0), (4, 0), (8, 0), (16, 0)])
     res = ann.query(D, Dp, q, qp, k=1, c=2.0, t=1.0, budget=4, r_min=1.0)
@@ -184,7 +184,7 @@ def test_trace_line4_threshold_is_c_times_r():
 
 def test_trace_radius_grows_by_c():
     # B = 5 is never reached before r = 8: r = 1 {0}, 2 {0,1}, 4 {0,1,2},
-    # line 4 never fires because k = 5 > |C|; at r = 16 the ball holds all
+    # the c r stop never fires because k = 5 > |C|; at r = 16 the ball holds all
     # five points (>= B): 5 range queries with r = 1, 2, 4, 8, 16.
     D, Dp, q, qp = _line(ON_AXIS)
     res = ann.query(D, Dp, q, qp, k=5, c=2.0, t=1.0, budget=5, r_min=1.0)
