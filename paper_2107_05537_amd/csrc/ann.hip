@@ -2130,36 +2130,45 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     __syncthreads();
     for (int b0 = 0; b0 < n_ver; b0 += WG) {
         const int i = b0 + threadIdx.x;
-        const bool take = i < n_ver && lo2[i] <= hkw && lo2[i] != hi2[i];
-        const int slot = wave_append(take, &sh.cnt1);
-        if (take) ilist[slot] = i;
-    }
-    __syncthreads();
-    verify_list(a, qs, cpos, ilist, sh.cnt1, lo2, hi2);
-    __syncthreads();
-    // the possible members, now exact, keyed by (distance^2 bits, id)
-    if (threadIdx.x == 0) sh.cnt1 = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < n_ver; b0 += WG) {
-        const int i = b0 + threadIdx.x;
         const bool take = i < n_ver && lo2[i] <= hkw;
         const int slot = wave_append(take, &sh.cnt1);
-        if (take) {
-            sh.skey[slot] = ((uint64_t)__float_as_uint(hi2[i]) << 32) | (uint32_t)perm[cpos[i]];
-            sh.spos[slot] = i;
-        }
+        if (take) sh.spos[slot] = i;
     }
     __syncthreads();
     const int m = sh.cnt1;
-    // all of them go to the FP64 re-rank: their exact FP32 values are at
-    // most hk (1 + 4 gamma), a superset of the members the re-rank needs
-    const bool done = rerank_topk64(
-        a, qi, qs, cpos, m, __int_as_float(0x7f800000),
-        [&](int j, float& v, int& mi) {
-            v = __uint_as_float((uint32_t)(sh.skey[j] >> 32));
-            mi = sh.spos[j];
-        },
-        sh);
+    // all of them go to the FP64 re-rank, which decides their order from
+    // their rows (no FP32 value is needed; the set holds every member the
+    // FP64 order can place among the k nearest)
+    bool done = false;
+    if (m <= kRerankCap)
+        done = rerank_topk64(
+            a, qi, qs, cpos, m, __int_as_float(0x7f800000),
+            [&](int j, float& v, int& mi) {
+                v = 0.f;
+                mi = sh.spos[j];
+            },
+            sh);
+    if (!done) {
+        // the FP32 order: exact values for the members still bounded, then
+        // keys (distance^2 bits, id)
+        if (threadIdx.x == 0) sh.cnt2 = 0;
+        __syncthreads();
+        for (int b0 = 0; b0 < m; b0 += WG) {
+            const int j = b0 + threadIdx.x;
+            const int i = j < m ? sh.spos[j] : 0;
+            const bool take = j < m && lo2[i] != hi2[i];
+            const int slot = wave_append(take, &sh.cnt2);
+            if (take) ilist[slot] = i;
+        }
+        __syncthreads();
+        verify_list(a, qs, cpos, ilist, sh.cnt2, lo2, hi2);
+        __syncthreads();
+        for (int j = threadIdx.x; j < m; j += WG) {
+            const int i = sh.spos[j];
+            sh.skey[j] = ((uint64_t)__float_as_uint(hi2[i]) << 32) | (uint32_t)perm[cpos[i]];
+        }
+        __syncthreads();
+    }
     if (done) {
     } else if (m <= WG) {
         // keys are distinct (ids): the rank of each among the m is its slot
