@@ -1004,7 +1004,8 @@ __device__ void shell_cut_fp64(const AnnArgs& a, int64_t qi, const QueryCtx& qc,
     });
     below = block_sum(below, sh);
     const int nb = sh.cnt2;
-    if (nb > kBandCap || below > need || below + nb < need) return;
+    // a band that is taken whole leaves the FP32 choice as it is
+    if (nb > kBandCap || below > need || below + nb <= need) return;
     for (int j = threadIdx.x; j < nb; j += WG) {
         const int64_t pos = bpos[j];
         double acc = 0.0;
@@ -1923,6 +1924,13 @@ __device__ bool cut_fp64(const AnnArgs& a, int64_t qi, const QueryCtx& qc, int n
     below = block_sum(below, sh);
     const int nb = sh.cnt2;
     if (nb > kBandCap || below >= B || below + nb < B) return false;
+    if (below + nb == B) {
+        // the whole band is in L whatever its FP64 order
+        for (int i = threadIdx.x; i < n; i += WG)
+            if (__uint_as_float((uint32_t)(sh.skey[i] >> 32)) > bhi) sh.skey[i] = ~0ull;
+        __syncthreads();
+        return true;
+    }
     for (int j = threadIdx.x; j < nb; j += WG) {
         const int64_t pos = sh.spos[band[j]];
         double acc = 0.0;
