@@ -24,7 +24,10 @@ against the FP16 matrix peak for the filter, bytes against 8 TB/s for the
 HBM-bound stages), with the HBM traffic that rocprofv3 counters measured for
 that kernel when profiles/ holds them for the current kernel sources; the
 FP64 CPU oracle timed on this host on a bounded sample of the same queries;
-(c,k)-ACP time per call on the planted-pair workload for k = 1, 10, 100.
+(c,k)-ACP time per call on the planted-pair workload for k = 1, 10, 100;
+the serving loop on the 10,000,000 x 128 index (Poisson request streams of
+mixed k and c at several rates: queries/s and p50/p99 request latency of
+the server and of plain per-request calls, and both at saturation).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
