@@ -190,6 +190,11 @@ int pmlsh_bc(const pmlsh_index* index, const float* queries, int64_t nq, double 
  *   pmlsh_plan_params.
  *   out_pairs k x 2 int64 device pointer (i < j); out_dist k FP32 device.
  *   stats     optional host pointer, filled on success.
+ * Precision: distances are computed in FP32; the order of the answer (step 4,
+ * ties by (i, j)) is decided on FP64 distances from the FP32 rows for every
+ * pair within FP32 rounding of the k-th one, and out_dist is the FP32
+ * rounding of the FP64 distance (more than 1,024 such pairs keep the FP32
+ * order and distances). The same holds for pmlsh_acp_bb and pmlsh_acp_lca.
  * Synchronous: returns after the work on `stream` has completed.
  * Errors: EINVAL, ENOMEM (candidate buffers), EDEVICE, EUNSUPPORTED.
  */

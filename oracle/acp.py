@@ -49,6 +49,14 @@ class AcpResult:
     n_cand_raw: int        # candidates before the T cut
     margin: float
     margin_kind: str
+    margins: dict = dataclasses.field(default_factory=dict)   # smallest margin per kind
+
+
+def _by_kind(margins) -> dict:
+    out = {}
+    for v, kind in margins:
+        out[kind] = min(v, out.get(kind, math.inf))
+    return out
 
 
 def _pair_key_order(dist: np.ndarray, pi: np.ndarray, pj: np.ndarray):
@@ -164,7 +172,8 @@ def run(D: np.ndarray, Dp: np.ndarray, perm: np.ndarray, offsets: np.ndarray,
     return AcpResult(pairs=np.stack([ai[top], aj[top]], axis=1),
                      dist=ad[top], ub=ub, n_seed=int(si.shape[0]),
                      n_cand=int(ci.shape[0]), n_cand_raw=int(n_raw),
-                     margin=mval, margin_kind=mkind)
+                     margin=mval, margin_kind=mkind,
+                     margins=_by_kind(margins))
 
 
 def _all_pairs_pd(Dp: np.ndarray, block: int = 256):
@@ -216,7 +225,8 @@ def branch_and_bound(D: np.ndarray, Dp: np.ndarray, k: int, T: int) -> AcpResult
     top = oo[:kk]
     return AcpResult(pairs=np.stack([ci[top], cj[top]], axis=1), dist=cd[top],
                      ub=float(pd[o[T - 1]]), n_seed=0, n_cand=int(T),
-                     n_cand_raw=int(T), margin=mval, margin_kind=mkind)
+                     n_cand_raw=int(T), margin=mval, margin_kind=mkind,
+                     margins=_by_kind(margins))
 
 
 def radius_filtering_lca(D: np.ndarray, Dp: np.ndarray, perm: np.ndarray, offsets: np.ndarray,
@@ -303,4 +313,5 @@ def radius_filtering_lca(D: np.ndarray, Dp: np.ndarray, perm: np.ndarray, offset
     top = o[:kk]
     return AcpResult(pairs=np.stack([ai[top], aj[top]], axis=1), dist=ad[top], ub=ub,
                      n_seed=int(si.shape[0]), n_cand=n_cand, n_cand_raw=n_cand,
-                     margin=mval, margin_kind=mkind)
+                     margin=mval, margin_kind=mkind,
+                     margins=_by_kind(margins))

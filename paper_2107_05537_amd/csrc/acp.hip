@@ -440,6 +440,71 @@ __global__ __launch_bounds__(WG) void acp_final_kernel(
     }
 }
 
+constexpr int kTopBand = 1024;   // pairs the FP64 top-k takes at most (>= PMLSH_MAX_K)
+
+// Top-k in the FP64 order of Section 6 (distance, then i, then j). The `count`
+// pairs are every pair whose FP32 distance lies within the verify error band
+// of the FP32 k-th one, so the exact top-k is among them; each gets its squared
+// distance in FP64 from the FP32 rows and the k smallest by (d^2, i, j) are
+// written (16 lanes per pair, as in the FP32 verify).
+__global__ __launch_bounds__(WG) void acp_final64_kernel(
+    const float* __restrict__ data, int d_pad, const int32_t* __restrict__ inv_perm,
+    const uint32_t* __restrict__ ii, const uint32_t* __restrict__ jj, int count, int k,
+    int64_t* __restrict__ out_pairs, float* __restrict__ out_dist) {
+    __shared__ double dk[kTopBand];
+    __shared__ uint64_t pk[kTopBand];
+    const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int d4 = d_pad >> 2;
+    int P = 1;
+    while (P < count) P <<= 1;
+    for (int base = 0; base < P; base += WG / 16) {
+        const int e = base + g;
+        double acc = 0.0;
+        if (e < count) {
+            const float4* r1 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[ii[e]] * d_pad);
+            const float4* r2 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[jj[e]] * d_pad);
+            for (int c = l16; c < d4; c += 16) {
+                const float4 x = r1[c], y = r2[c];
+                double t;
+                t = (double)x.x - (double)y.x; acc = fma(t, t, acc);
+                t = (double)x.y - (double)y.y; acc = fma(t, t, acc);
+                t = (double)x.z - (double)y.z; acc = fma(t, t, acc);
+                t = (double)x.w - (double)y.w; acc = fma(t, t, acc);
+            }
+        }
+        acc += __shfl_xor(acc, 8, 16);
+        acc += __shfl_xor(acc, 4, 16);
+        acc += __shfl_xor(acc, 2, 16);
+        acc += __shfl_xor(acc, 1, 16);
+        if (l16 == 0 && e < P) {
+            dk[e] = e < count ? acc : INFINITY;
+            pk[e] = e < count ? (((uint64_t)ii[e] << 32) | jj[e]) : ~0ull;
+        }
+    }
+    __syncthreads();
+    for (int s = 2; s <= P; s <<= 1) {
+        for (int j = s >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += WG) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & s) == 0;
+                    const bool gt = dk[i] > dk[ixj] || (dk[i] == dk[ixj] && pk[i] > pk[ixj]);
+                    if (gt == up) {
+                        const double td = dk[i]; dk[i] = dk[ixj]; dk[ixj] = td;
+                        const uint64_t tp = pk[i]; pk[i] = pk[ixj]; pk[ixj] = tp;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < k; i += WG) {
+        out_pairs[2 * i] = (int64_t)(pk[i] >> 32);
+        out_pairs[2 * i + 1] = (int64_t)(pk[i] & 0xffffffffull);
+        out_dist[i] = (float)sqrt(dk[i]);
+    }
+}
+
 // ---------------------------------------------------------------- host side
 // Workspace buffer of one role, kept in the index between calls and grown
 // (freed and allocated anew) only when a call needs more than it holds.
@@ -532,6 +597,52 @@ SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, in
 }
 
 }  // namespace
+
+// The k nearest pairs of the verified pool, in (distance, i, j) order. The FP32
+// k-th distance bounds the band of pairs that can belong to the exact top-k
+// (verify error 2u(d/16 + 8) relative, taken twice over); their order is taken
+// in FP64. A band of more than kTopBand pairs (mass ties) keeps the FP32 order.
+void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, Triplets& top,
+               DevBuf& dhist, DevBuf& dcount, int64_t* out_pairs, float* out_dist,
+               hipStream_t st) {
+    auto gather = [&](SelKey K, int64_t cap) -> int64_t {
+        PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
+                           pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                           pool.jj.as<uint32_t>(), n_pool, K, top.k0.as<uint32_t>(),
+                           top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), cap,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        unsigned long long v = 0;
+        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        return (int64_t)v;
+    };
+    const SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                                pool.jj.as<uint32_t>(), n_pool, k, false,
+                                dhist.as<uint32_t>(), st);
+    top.alloc(kTopBand);
+    float kth;
+    std::memcpy(&kth, &K.v0, sizeof(kth));
+    const double gamma = 2.0 * 5.9604645e-08 * (double)(x->d_pad / 16 + 8);
+    const float lim = std::nextafter((float)((double)kth * (1.0 + 4.0 * gamma)), INFINITY);
+    uint32_t lim_bits;
+    std::memcpy(&lim_bits, &lim, sizeof(lim_bits));
+    const int64_t m = gather(SelKey{0, lim_bits, 0, 0}, kTopBand);
+    if (m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+    if (m <= kTopBand) {
+        hipLaunchKernelGGL(acp_final64_kernel, dim3(1), dim3(WG), 0, st, x->data, x->d_pad,
+                           x->inv_perm, top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), (int)m,
+                           k, out_pairs, out_dist);
+    } else {
+        if (gather(K, k) != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+        hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
+                           top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs,
+                           out_dist);
+    }
+    PMLSH_HIP(hipGetLastError());
+    PMLSH_HIP(hipStreamSynchronize(st));
+}
 
 void run_acp(const pmlsh_index* x, int k, double c, double confidence, double beta,
              int64_t* out_pairs, float* out_dist, pmlsh_acp_stats* stats,
@@ -690,22 +801,8 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
 
     // ---- top-k over the pool
-    SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
-                          n_pool, k, false, dhist.as<uint32_t>(), st);
     Triplets top(x, S_TOP);
-    top.alloc(k);
-    reset_counter();
-    hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
-                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
-                       n_pool, K, top.k0.as<uint32_t>(), top.ii.as<uint32_t>(),
-                       top.jj.as<uint32_t>(), (int64_t)k,
-                       static_cast<unsigned long long*>(dcount.p));
-    PMLSH_HIP(hipGetLastError());
-    if (read_counter() != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
-    hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
-                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs, out_dist);
-    PMLSH_HIP(hipGetLastError());
-    PMLSH_HIP(hipStreamSynchronize(st));
+    pool_topk(x, pool, n_pool, k, top, dhist, dcount, out_pairs, out_dist, st);
 
     if (stats) {
         stats->t = plan.t;
@@ -880,21 +977,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
                        pool.jj.as<uint32_t>());
     PMLSH_HIP(hipGetLastError());
     if (keep < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
-    SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
-                          keep, k, false, dhist.as<uint32_t>(), st);
-    top.alloc(k);
-    reset_counter();
-    hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(keep, WG)), dim3(WG), 0, st,
-                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
-                       keep, K, top.k0.as<uint32_t>(), top.ii.as<uint32_t>(),
-                       top.jj.as<uint32_t>(), (int64_t)k,
-                       static_cast<unsigned long long*>(dcount.p));
-    PMLSH_HIP(hipGetLastError());
-    if (read_counter() != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
-    hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
-                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs, out_dist);
-    PMLSH_HIP(hipGetLastError());
-    PMLSH_HIP(hipStreamSynchronize(st));
+    pool_topk(x, pool, keep, k, top, dhist, dcount, out_pairs, out_dist, st);
     if (stats) {
         stats->t = plan.t;
         stats->ub = std::sqrt((double)d2);
@@ -1190,21 +1273,7 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
 
     // 4. the k nearest verified pairs
     if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
-    SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
-                          n_pool, k, false, dhist.as<uint32_t>(), st);
-    top.alloc(k);
-    reset_counter();
-    hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
-                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
-                       n_pool, K, top.k0.as<uint32_t>(), top.ii.as<uint32_t>(),
-                       top.jj.as<uint32_t>(), (int64_t)k,
-                       static_cast<unsigned long long*>(dcount.p));
-    PMLSH_HIP(hipGetLastError());
-    if (read_counter() != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
-    hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
-                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs, out_dist);
-    PMLSH_HIP(hipGetLastError());
-    PMLSH_HIP(hipStreamSynchronize(st));
+    pool_topk(x, pool, n_pool, k, top, dhist, dcount, out_pairs, out_dist, st);
     if (stats) {
         stats->t = plan.t;
         stats->ub = ub;

@@ -65,6 +65,17 @@ def _fp64_exact(r):
                for kind, v in r.margins.items())
 
 
+ACP_FP64_DECIDED = ("topk_order",)
+
+
+def acp_exact(r):
+    """An ACP result the library must reproduce exactly: every decision it
+    takes on FP32 has an oracle margin above FRAGILE, and the top-k order
+    (taken in the FP64 order by the library) one above the FP64 resolution."""
+    return all(v > (FP64_RESOLUTION if kind in ACP_FP64_DECIDED else FRAGILE)
+               for kind, v in r.margins.items())
+
+
 def compare_ann(D, Q, res, ids, dist, stats=None, fp64=False):
     """res: oracle results; ids/dist/stats: library outputs as NumPy arrays.
     With fp64, near ties of the budget cut and of the top-k order (decided in
