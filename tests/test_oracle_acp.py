@@ -47,6 +47,26 @@ def test_single_leaf_is_exact(small):
     assert res.n_cand_raw == 0
 
 
+def test_topk_margin_is_the_smallest_relative_gap(small):
+    """The per-kind margins: with one leaf the top-k margin is the smallest
+    relative gap between consecutive exact distances of the k + 1 closest
+    pairs (pdist as the reference), the reported margin is the smallest of
+    all kinds, and a duplicated point (two pairs at one distance inside the
+    top-k) gives a top-k margin of 0."""
+    D, A, Dp = small
+    n, k = D.shape[0], 25
+    res = acp.run(D, Dp, np.arange(n), np.array([0, n]), k=k, t=3.0, T=10 ** 9)
+    _, ed = _exact_pairs(D, k + 1)
+    assert res.margins["topk_order"] == pytest.approx(float(np.min(np.diff(ed) / ed[:-1])),
+                                                      rel=1e-9)
+    assert res.margin == min(res.margins.values())
+    ep, _ = _exact_pairs(D, 1)
+    D2 = np.concatenate([D, D[ep[0, 0]][None]])
+    Dp2 = ann.project(D2, A)
+    res2 = acp.run(D2, Dp2, np.arange(n + 1), np.array([0, n + 1]), k=k, t=3.0, T=10 ** 9)
+    assert res2.margins["topk_order"] == 0.0
+
+
 def test_singleton_leaves_unbounded_budget_is_exact(small):
     D, A, Dp = small
     n, k = D.shape[0], 10
