@@ -195,20 +195,29 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_kernel(
     __shared__ int npl;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const float u = 5.9604645e-08f;
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    // a contiguous run of the tile list per workgroup: the filter appends the
+    // tiles of one first leaf in runs, so the first leaf's rows stay in LDS
+    // from one tile to the next
+    const int64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t_end = min(n_tiles, ((int64_t)blockIdx.x + 1) * per);
+    int held = -1;
+    for (int64_t t = (int64_t)blockIdx.x * per; t < t_end; ++t) {
         const int2 tl = tiles[t];
         const int64_t a0 = (int64_t)tl.x * L, b0 = (int64_t)tl.y * L;
         const int ca = (int)(n - a0 < L ? n - a0 : L);
         const int cb = (int)(n - b0 < L ? n - b0 : L);
-        for (int e = threadIdx.x; e < ca * MP; e += WG) {
-            h1[e] = phi[a0 * MP + e];
-            l1[e] = plo[a0 * MP + e];
+        if (tl.x != held) {
+            for (int e = threadIdx.x; e < ca * MP; e += WG) {
+                h1[e] = phi[a0 * MP + e];
+                l1[e] = plo[a0 * MP + e];
+            }
+            for (int e = threadIdx.x; e < ca; e += WG) id1[e] = perm[a0 + e];
+            held = tl.x;
         }
         for (int e = threadIdx.x; e < cb * MP; e += WG) {
             h2[e] = phi[b0 * MP + e];
             l2[e] = plo[b0 * MP + e];
         }
-        for (int e = threadIdx.x; e < ca; e += WG) id1[e] = perm[a0 + e];
         for (int e = threadIdx.x; e < cb; e += WG) {
             id2[e] = perm[b0 + e];
             pb[e] = ppd[b0 + e];
