@@ -135,17 +135,52 @@ __device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b
 }
 
 // Leaf pairs (e1 < e2; with diag also e1 = e2) whose Mindist can fall below
-// `limit`.
+// `limit`. One workgroup per first leaf e1: its kept tiles are compacted in
+// LDS and appended with one global atomic per flush, so a row's tiles lie
+// together in the list (the tile scan keeps e1's rows across them) and the
+// single counter sees a few thousand atomics instead of one per wave.
+constexpr int kRowBuf = 2048;
 __global__ __launch_bounds__(WG) void acp_tile_filter_kernel(
     NodeView v, int64_t leaf_base, int64_t n_leaves, float limit, int diag,
     int2* __restrict__ tiles, int64_t cap, unsigned long long* __restrict__ counter) {
-    const int64_t e1 = blockIdx.y;
-    const int64_t e2 = (int64_t)blockIdx.x * WG + threadIdx.x;
-    bool keep = false;
-    if (e2 > e1 && e2 < n_leaves) keep = mindist(v, leaf_base + e1, leaf_base + e2) <= limit;
-    if (diag && e2 == e1) keep = true;
-    const int64_t slot = wave_append_global(keep, counter);
-    if (keep && slot < cap) tiles[slot] = make_int2((int)e1, (int)e2);
+    __shared__ int rowbuf[kRowBuf];
+    __shared__ int wcount[WG / 64];
+    __shared__ int nrow;
+    __shared__ unsigned long long gbase;
+    const int64_t e1 = blockIdx.x;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) nrow = 0;
+    __syncthreads();
+    for (int64_t s0 = diag ? e1 : e1 + 1; s0 < n_leaves; s0 += WG) {
+        const int64_t e2 = s0 + threadIdx.x;
+        bool keep = false;
+        if (e2 < n_leaves)
+            keep = e2 == e1 || mindist(v, leaf_base + e1, leaf_base + e2) <= limit;
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) wcount[wave] = __popcll(m);
+        __syncthreads();
+        int off = nrow, tot = 0;
+        for (int w = 0; w < WG / 64; ++w) {
+            if (w < wave) off += wcount[w];
+            tot += wcount[w];
+        }
+        if (keep) rowbuf[off + __popcll(m & ((1ull << lane) - 1ull))] = (int)e2;
+        __syncthreads();
+        if (threadIdx.x == 0) nrow += tot;
+        __syncthreads();
+        const int cnt = nrow;
+        if (cnt > 0 && (cnt > kRowBuf - WG || s0 + WG >= n_leaves)) {
+            if (threadIdx.x == 0) gbase = atomicAdd(counter, (unsigned long long)cnt);
+            __syncthreads();
+            for (int q = threadIdx.x; q < cnt; q += WG) {
+                const int64_t slot = (int64_t)gbase + q;
+                if (slot < cap) tiles[slot] = make_int2((int)e1, rowbuf[q]);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) nrow = 0;
+            __syncthreads();
+        }
+    }
 }
 
 // Distance from every point (hi + lo) to the centre of its own leaf, FP32:
@@ -725,7 +760,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         const int64_t leaf_base = x->level_begin[x->levels - 1];
         NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
                    x->num_pivots};
-        dim3 grid((unsigned)((NL + WG - 1) / WG), (unsigned)NL);
+        dim3 grid((unsigned)NL);
         hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL, limit,
                            0, tiles.as<int2>(), tiles_total,
                            static_cast<unsigned long long*>(dcount.p));
@@ -893,7 +928,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
                                 ? INFINITY
                                 : (float)(R + 1e-5 * (2.0 * x->coord_scale + R)) * 1.0001f;
         reset_counter();
-        dim3 grid((unsigned)((NL + WG - 1) / WG), (unsigned)NL);
+        dim3 grid((unsigned)NL);
         hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL,
                            limit, 1, tiles.as<int2>(), tiles_all,
                            static_cast<unsigned long long*>(dcount.p));
