@@ -157,6 +157,27 @@ int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq,
               void* stream);
 
 /*
+ * pmlsh_ann for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, results and errors are those of pmlsh_ann; the same kernels
+ * run. The workspace is a fixed array of PMLSH_NOALLOC_SCRATCH_BYTES in the
+ * library's code object, one copy per device (held until the process ends),
+ * instead of the caching allocator: no hipMalloc, hipFree or other
+ * allocating routine is called, and per-stage timing is skipped. The
+ * queries run in batches that fit the array; EUNSUPPORTED when not even one
+ * query of this index fits (its message gives the bytes one query needs).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (the kernels initialise all they read): calls that overlap on one
+ * device, on any streams, race and must be serialised by the caller.
+ */
+#define PMLSH_NOALLOC_SCRATCH_BYTES (64LL * 1024 * 1024)
+
+int pmlsh_ann_noalloc(const pmlsh_index* index, const float* queries, int64_t nq,
+                      int32_t k, double c, double confidence, double beta, double r_min,
+                      int64_t* out_ids, float* out_dist, int32_t* out_stats,
+                      void* stream);
+
+/*
  * (r,c)-BC (ball cover) query, Algorithm 1 (Section 5.1), for a batch of
  * queries: one range query of radius t*r around q' with the budget
  * B = beta*n + 1 (the same reading of the budget as pmlsh_ann: when the ball

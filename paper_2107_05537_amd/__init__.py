@@ -95,6 +95,10 @@ SIGNATURES = {
                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pmlsh_ann_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pmlsh_bc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
@@ -313,6 +317,15 @@ class Index:
     def ann_into(self, queries, k, c, confidence, beta, r_min, ids, dist, stats=None):
         """Like ann() but writes into caller-provided GPU tensors (no allocation)."""
         _check(load_library().pmlsh_ann(
+            self._h, queries.data_ptr(), queries.shape[0], k, c, confidence, beta, r_min,
+            ids.data_ptr(), dist.data_ptr(), stats.data_ptr() if stats is not None else None,
+            _stream_handle(queries.device)))
+
+    def ann_noalloc(self, queries, k, c, confidence, beta, r_min, ids, dist, stats=None):
+        """pmlsh_ann_noalloc into caller-provided GPU tensors: the workspace is
+        the library's fixed per-device array (calls overlapping on one device
+        race). Enqueued on the current stream."""
+        _check(load_library().pmlsh_ann_noalloc(
             self._h, queries.data_ptr(), queries.shape[0], k, c, confidence, beta, r_min,
             ids.data_ptr(), dist.data_ptr(), stats.data_ptr() if stats is not None else None,
             _stream_handle(queries.device)))

@@ -58,7 +58,16 @@ int64_t front_slots(const pmlsh_index* x, bool fast, int64_t batch) {
     return std::min<int64_t>({batch, fast ? 256 : 2048, by_memory});
 }
 
-AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
+// Bytes of the workspace layout for batches of `batch` queries and `slots`
+// frontier-list pairs (unrounded).
+int64_t ann_layout_bytes(const pmlsh_index* x, const AnnWorkspace& w, int64_t batch,
+                         int64_t slots) {
+    const int64_t mask_bytes =
+        w.fast ? batch * (8 + 2 * w.ldc) + w.nchunk * ((batch + 63) / 64) * 8 : 0;
+    return batch * w.per_query + mask_bytes + slots * 2 * x->n_leaves * 4;
+}
+
+AnnWorkspace ann_workspace_base(const pmlsh_index* x, int k, int64_t B) {
     AnnWorkspace w{};
     w.B = B;
     w.fast = ann_fast_path(B);
@@ -67,19 +76,41 @@ AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
                   (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
     w.ldc = cdist_row_len(w.nchunk);
+    return w;
+}
+
+AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
+    AnnWorkspace w = ann_workspace_base(x, k, B);
     const int64_t per_query_all =
         w.per_query + (w.fast ? 8 + 2 * w.ldc + (w.nchunk + 7) / 8 : 0);
     w.batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     w.batch = std::min<int64_t>(w.batch, 65535);
-    const int64_t mask_bytes =
-        w.fast ? w.batch * (8 + 2 * w.ldc) + w.nchunk * ((w.batch + 63) / 64) * 8
-               : 0;
     w.slots = front_slots(x, w.fast, w.batch);
-    w.bytes = w.batch * w.per_query + mask_bytes + w.slots * 2 * x->n_leaves * 4;
+    w.bytes = ann_layout_bytes(x, w, w.batch, w.slots);
     // sizes rounded up (to 1 MiB, or 64 MiB above 256 MiB) so that calls of
     // different batch sizes reuse the same pool blocks
     const int64_t q = w.bytes > (int64_t(256) << 20) ? int64_t(64) << 20 : int64_t(1) << 20;
     w.bytes = (w.bytes + q - 1) / q * q;
+    return w;
+}
+
+// Layout that fits a fixed region of cap bytes: at most a quarter of it for
+// the frontier lists, the largest batch that fits in the rest. batch = 0
+// when not even one query fits.
+AnnWorkspace ann_workspace_in(const pmlsh_index* x, int64_t nq, int k, int64_t B, int64_t cap) {
+    AnnWorkspace w = ann_workspace_base(x, k, B);
+    const int64_t per_slot = 2 * x->n_leaves * 4;
+    int64_t slots = std::min<int64_t>(w.fast ? 256 : 2048, (cap / 4) / per_slot);
+    slots = std::max<int64_t>(slots, 1);
+    int64_t lo = 0, hi = std::min<int64_t>(nq, 65535);
+    while (lo < hi) {   // largest batch with bytes <= cap
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (ann_layout_bytes(x, w, mid, std::min(slots, mid)) <= cap) lo = mid;
+        else hi = mid - 1;
+    }
+    w.batch = lo;
+    w.slots = std::min(slots, std::max<int64_t>(lo, 1));
+    w.bytes = lo > 0 ? ann_layout_bytes(x, w, w.batch, w.slots) : 0;
     return w;
 }
 
@@ -105,19 +136,16 @@ int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
     return nq > 0 ? ann_workspace(x, nq, k, plan.budget).bytes : 0;
 }
 
-void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
-             double confidence, double beta, double r_min, int64_t* out_ids,
-             float* out_dist, int32_t* out_stats, hipStream_t st, int max_rounds) {
-    pmlsh_plan plan;
-    plan_params(x->n, x->m, k, c, confidence, beta, &plan);
-    if (!(r_min > 0.0)) r_min = index_default_r_min(x, plan.budget);
-    if (!std::isfinite(r_min)) fail(PMLSH_EINVAL, "r_min must be finite");
-    if (nq == 0) return;
-    const AnnWorkspace w = ann_workspace(x, nq, k, plan.budget);
+namespace {
+
+// The batches of one ANN call over the workspace region ws laid out by w.
+void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
+                    const pmlsh_plan& plan, double r_min, int64_t* out_ids, float* out_dist,
+                    int32_t* out_stats, hipStream_t st, int max_rounds, const AnnWorkspace& w,
+                    void* ws) {
     const int64_t B = w.B, pool_q = w.pool_q, nchunk = w.nchunk, ldc = w.ldc,
                   batch = w.batch;
     const bool fast = w.fast;
-    void* ws = ws_alloc((size_t)w.bytes, st);
     char* base = static_cast<char*>(ws);
     // projections and FP16 scan rows first: every row starts on a 64-byte
     // boundary
@@ -136,53 +164,94 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     int32_t* q_flag = reinterpret_cast<int32_t*>(clo + (fast ? batch * B : 0));
     uint32_t* l_count = reinterpret_cast<uint32_t*>(q_flag + batch);
     uint32_t* q_scanned = l_count + batch;
-    try {
-        for (int64_t q0 = 0; q0 < nq; q0 += batch) {
-            const int64_t nb = std::min(batch, nq - q0);
-            const float* qb = queries + q0 * x->d;
-            {
-                StageTimer tm(PMLSH_STAGE_PROJECT, st);
-                launch_project(qb, nb, x->d, x->d, x->hash, qproj, qproj_lo, st);
-            }
-            AnnLaunch L{};
-            L.idx = x;
-            L.queries = qb;
-            L.qproj = qproj;
-            L.qproj_lo = qproj_lo;
-            L.nq = nb;
-            L.k = k;
-            L.c = c;
-            L.t = plan.t;
-            L.r_min = r_min;
-            L.max_rounds = max_rounds;
-            L.budget = B;
-            L.ws_front = front;
-            L.front_slots = std::min<int64_t>(w.slots, nb);
-            L.ws_cpos = cpos;
-            L.ws_cdist = cdist;
-            L.ws_topk = topk;
-            if (fast) {
-                L.ws_qaug = qaug;
-                L.ws_qtest = qtest;
-                L.ws_clo = clo;
-                L.ws_cmask = cmask;
-                L.ws_cdist2 = cdist2;
-                L.q_flag = q_flag;
-                L.l_count = l_count;
-                L.q_scanned = q_scanned;
-                L.l_list = list;
-                L.pool_cap = pool_q;
-            }
-            L.out_ids = out_ids + q0 * k;
-            L.out_dist = out_dist + q0 * k;
-            L.out_stats = out_stats ? out_stats + q0 * 4 : nullptr;
-            launch_ann(L, st);
+    for (int64_t q0 = 0; q0 < nq; q0 += batch) {
+        const int64_t nb = std::min(batch, nq - q0);
+        const float* qb = queries + q0 * x->d;
+        {
+            StageTimer tm(PMLSH_STAGE_PROJECT, st);
+            launch_project(qb, nb, x->d, x->d, x->hash, qproj, qproj_lo, st);
         }
+        AnnLaunch L{};
+        L.idx = x;
+        L.queries = qb;
+        L.qproj = qproj;
+        L.qproj_lo = qproj_lo;
+        L.nq = nb;
+        L.k = k;
+        L.c = c;
+        L.t = plan.t;
+        L.r_min = r_min;
+        L.max_rounds = max_rounds;
+        L.budget = B;
+        L.ws_front = front;
+        L.front_slots = std::min<int64_t>(w.slots, nb);
+        L.ws_cpos = cpos;
+        L.ws_cdist = cdist;
+        L.ws_topk = topk;
+        if (fast) {
+            L.ws_qaug = qaug;
+            L.ws_qtest = qtest;
+            L.ws_clo = clo;
+            L.ws_cmask = cmask;
+            L.ws_cdist2 = cdist2;
+            L.q_flag = q_flag;
+            L.l_count = l_count;
+            L.q_scanned = q_scanned;
+            L.l_list = list;
+            L.pool_cap = pool_q;
+        }
+        L.out_ids = out_ids + q0 * k;
+        L.out_dist = out_dist + q0 * k;
+        L.out_stats = out_stats ? out_stats + q0 * 4 : nullptr;
+        launch_ann(L, st);
+    }
+}
+
+// Plan and first radius of one ANN call (host only).
+double ann_plan(const pmlsh_index* x, int k, double c, double confidence, double beta,
+                double r_min, pmlsh_plan* plan) {
+    plan_params(x->n, x->m, k, c, confidence, beta, plan);
+    if (!(r_min > 0.0)) r_min = index_default_r_min(x, plan->budget);
+    if (!std::isfinite(r_min)) fail(PMLSH_EINVAL, "r_min must be finite");
+    return r_min;
+}
+
+}  // namespace
+
+void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
+             double confidence, double beta, double r_min, int64_t* out_ids,
+             float* out_dist, int32_t* out_stats, hipStream_t st, int max_rounds) {
+    pmlsh_plan plan;
+    r_min = ann_plan(x, k, c, confidence, beta, r_min, &plan);
+    if (nq == 0) return;
+    const AnnWorkspace w = ann_workspace(x, nq, k, plan.budget);
+    void* ws = ws_alloc((size_t)w.bytes, st);
+    try {
+        run_ann_region(x, queries, nq, k, c, plan, r_min, out_ids, out_dist, out_stats, st,
+                       max_rounds, w, ws);
     } catch (...) {
         ws_free(ws, st);
         throw;
     }
     ws_free(ws, st);
+}
+
+void run_ann_in(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
+                double confidence, double beta, double r_min, int64_t* out_ids,
+                float* out_dist, int32_t* out_stats, hipStream_t st,
+                const std::function<void*()>& region_of_device, int64_t region_bytes) {
+    pmlsh_plan plan;
+    r_min = ann_plan(x, k, c, confidence, beta, r_min, &plan);
+    if (nq == 0) return;
+    const AnnWorkspace w = ann_workspace_in(x, nq, k, plan.budget, region_bytes);
+    if (w.batch < 1) {
+        const AnnWorkspace one = ann_workspace_in(x, 1, k, plan.budget, int64_t(1) << 62);
+        fail(PMLSH_EUNSUPPORTED,
+             "one query of this index needs " + std::to_string(one.bytes) +
+                 " bytes of workspace; the fixed region holds " + std::to_string(region_bytes));
+    }
+    run_ann_region(x, queries, nq, k, c, plan, r_min, out_ids, out_dist, out_stats, st, 0, w,
+                   region_of_device());
 }
 
 }  // namespace pmlsh

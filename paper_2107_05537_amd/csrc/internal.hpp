@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <exception>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -96,6 +97,15 @@ int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
 void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
              double confidence, double beta, double r_min, int64_t* out_ids,
              float* out_dist, int32_t* out_stats, hipStream_t st, int max_rounds = 0);
+// pmlsh_ann over a fixed device region of region_bytes instead of the
+// caching allocator: the queries go through in batches that fit it;
+// EUNSUPPORTED (before any HIP call) when not even one query fits. The
+// region's address is asked of region_of_device only after that check.
+// Allocates no device memory.
+void run_ann_in(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
+                double confidence, double beta, double r_min, int64_t* out_ids,
+                float* out_dist, int32_t* out_stats, hipStream_t st,
+                const std::function<void*()>& region_of_device, int64_t region_bytes);
 // (r,c)-BC answers from the per-query stats of one round with k = 1.
 void launch_bc_finalize(int64_t* ids, float* dist, const int32_t* stats, int64_t nq, float cr,
                         hipStream_t stream);
@@ -223,6 +233,19 @@ int64_t tune_get(int key);
 void tune_set(int key, int64_t value);
 void timing_set(unsigned stage_mask);
 void timing_read(pmlsh_ann_timing* out, bool reset);
+
+// While an object of this class lives, StageTimer on the same thread times
+// nothing (no events are created or recorded).
+class TimingOff {
+public:
+    TimingOff();
+    ~TimingOff();
+    TimingOff(const TimingOff&) = delete;
+    TimingOff& operator=(const TimingOff&) = delete;
+
+private:
+    bool prev_;
+};
 
 // Brackets the launches issued during its lifetime with HIP events when
 // per-stage timing is enabled.

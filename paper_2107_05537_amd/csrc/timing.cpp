@@ -53,8 +53,15 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
+namespace {
+thread_local bool g_off = false;   // set by TimingOff on this thread
+}  // namespace
+
+TimingOff::TimingOff() : prev_(g_off) { g_off = true; }
+TimingOff::~TimingOff() { g_off = prev_; }
+
 StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
-    if (!timing_enabled(stage)) return;
+    if (g_off || !timing_enabled(stage)) return;
     a_ = take_event();
     b_ = take_event();
     PMLSH_HIP(hipEventRecord(a_, st_));
