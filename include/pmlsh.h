@@ -94,7 +94,8 @@ int pmlsh_build(const pmlsh_build_args* args, pmlsh_index** out);
 void pmlsh_free(pmlsh_index* index);
 
 /*
- * Query parameters of Algorithm 2 (Lemma 3, Eq. 10, Lemma 5, Section 5.2).
+ * Query parameters of Algorithm 2 (Lemma 3, Section 4.3; Eq. 10 and Lemma 5,
+ * Section 5.3; the budget of Section 5.2).
  * Host-only computation: never touches the GPU.
  *   confidence  Pr[E1] = 1 - alpha1 in (0,1): t = sqrt(chi^2_{alpha1}(m)),
  *               the upper alpha1 quantile (Lemma 3, first line of Eq. 10).
@@ -307,7 +308,7 @@ int pmlsh_server_get_stats(pmlsh_server* server, pmlsh_server_stats* out);
 void pmlsh_server_destroy(pmlsh_server* server);
 
 /*
- * (c,k)-ACP by the branch-and-bound algorithm (Algorithm 3, Section 6.2):
+ * (c,k)-ACP by the branch-and-bound algorithm (Algorithm 3, Section 6.1):
  * the T = beta*n(n-1)/2 + k pairs (capped at n(n-1)/2) with the smallest
  * projected distances over all pairs, ties by (i, j), are verified and the k
  * with the smallest exact distance (ties by (i, j)) are returned. Arguments,

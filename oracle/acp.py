@@ -25,7 +25,7 @@ takes it as data (a permutation and leaf offsets), never as code.
 Candidates are found by brute force over all pairs: no tree is used here, so
 a pruned pair scan elsewhere is checked for losing nothing.
 
-``branch_and_bound`` is the branch-and-bound algorithm of Section 6.2
+``branch_and_bound`` is the branch-and-bound algorithm of Section 6.1
 (Algorithm 3) in the same brute-force form: the T projected-closest pairs,
 verified. ``radius_filtering_lca`` is Algorithm 4 as printed (FindLCA with
 gamma, a live ub, the count > T stop), with the tree as data.
@@ -195,7 +195,7 @@ def _all_pairs_pd(Dp: np.ndarray, block: int = 256):
 
 
 def branch_and_bound(D: np.ndarray, Dp: np.ndarray, k: int, T: int) -> AcpResult:
-    """(c,k)-ACP by branch and bound, Section 6.2 (Algorithm 3).
+    """(c,k)-ACP by branch and bound, Section 6.1 (Algorithm 3).
 
     The best-first search over node pairs with the Mindist bound stops once
     no unexamined node pair can hold a pair closer (in the projected space)

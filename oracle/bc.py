@@ -43,6 +43,14 @@ class BcResult:
     n_cand: int        # |C|
     margin: float
     margin_kind: str
+    margins: dict = dataclasses.field(default_factory=dict)   # smallest margin per kind
+
+
+def _by_kind(margins) -> dict:
+    out = {}
+    for v, kind in margins:
+        out[kind] = min(v, out.get(kind, math.inf))
+    return out
 
 
 def query(D: np.ndarray, Dp: np.ndarray, q: np.ndarray, qp: np.ndarray, r: float,
@@ -66,7 +74,8 @@ def query(D: np.ndarray, Dp: np.ndarray, q: np.ndarray, qp: np.ndarray, r: float
         cand = order[:n_ball]
         kind = None
     if cand.size == 0:
-        return BcResult(-1, math.inf, KIND_NONE, 0, *min(margins, key=lambda x: x[0]))
+        return BcResult(-1, math.inf, KIND_NONE, 0, *min(margins, key=lambda x: x[0]),
+                        margins=_by_kind(margins))
     dist = exact_dist(D, q, cand)
     o = np.lexsort((cand, dist))
     best, best_d = int(cand[o[0]]), float(dist[o[0]])
@@ -79,8 +88,8 @@ def query(D: np.ndarray, Dp: np.ndarray, q: np.ndarray, qp: np.ndarray, r: float
         kind = KIND_FOUND if best_d <= c * r else KIND_NONE
     mval, mkind = min(margins, key=lambda x: x[0])
     if kind == KIND_NONE:
-        return BcResult(-1, math.inf, kind, int(cand.size), mval, mkind)
-    return BcResult(best, best_d, kind, int(cand.size), mval, mkind)
+        return BcResult(-1, math.inf, kind, int(cand.size), mval, mkind, _by_kind(margins))
+    return BcResult(best, best_d, kind, int(cand.size), mval, mkind, _by_kind(margins))
 
 
 def run(D: np.ndarray, A: np.ndarray, Q: np.ndarray, r: float, c: float, t: float,

@@ -860,7 +860,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     }
 }
 
-// (c,k)-ACP by the branch-and-bound algorithm (Algorithm 3, Section 6.2): the
+// (c,k)-ACP by the branch-and-bound algorithm (Algorithm 3, Section 6.1): the
 // T pairs with the smallest projected distances over all pairs (ties by
 // (i, j)) are verified and the k nearest returned. Best-first search with
 // Mindist pruning finds exactly those T pairs; here a projected distance d_T

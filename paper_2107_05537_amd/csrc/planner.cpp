@@ -1,5 +1,5 @@
 // Host-side FP64 planner: chi-square quantiles and the parameter setting of
-// PM-LSH (Lemma 3, Eq. 10 and Lemma 5 in Section 5.3), the candidate budgets
+// PM-LSH (Lemma 3 in Section 4.3; Eq. 10 and Lemma 5 in Section 5.3), the candidate budgets
 // of Algorithm 2 and Section 6.3, and the SplitMix64 generator used by the
 // r_min sample of Section 5.2.
 //

@@ -2,13 +2,15 @@
 the one pmlsh_ann gives it alone, bit for bit, whatever it was batched with;
 admission under a tight HBM budget; argument errors."""
 
+import math
 import threading
 
 import numpy as np
 import pytest
 
 import synth
-from parity import say
+from oracle import chi2
+from parity import compare_ann, oracle_ann, oracle_r_min, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -80,6 +82,20 @@ def test_each_request_alone_equals_in_the_mix(served):
         torch.cuda.synchronize()
         assert torch.equal(ids, ids0)
         assert torch.equal(dist, dist0)
+    # served answers against the oracle: the first three queries of every
+    # eighth request (each request has its own k and c)
+    D, A = w["D"], w["A"]
+    for i in range(0, len(reqs), 8):
+        Q, k, c = reqs[i]
+        ids, dist = results[i]
+        rows = slice(0, min(3, Q.shape[0]))
+        Qn = Q[rows].cpu().numpy()
+        B = chi2.ann_budget(0.05, D.shape[0], k)
+        r0 = oracle_r_min(D, 0x5EED, B)
+        res, _ = oracle_ann(D, A, Qn, k, c, 0.9, 0.05, r_min=r0)
+        say(f"request {i}: k={k} c={c}, {Qn.shape[0]} queries against the oracle")
+        compare_ann(D, Qn, res, ids[rows].cpu().numpy(), dist[rows].cpu().numpy(), fp64=True,
+                    min_exact_frac=0.0)
 
 
 def test_tight_hbm_budget_still_serves_one_launch_at_a_time(served):
