@@ -381,7 +381,8 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
                               int64_t* offsets);
 
 /*
- * Tracing aid: per-stage GPU time of pmlsh_ann. pmlsh_ann_timing_enable takes
+ * Tracing aid: per-stage GPU time of pmlsh_ann and pmlsh_acp.
+ * pmlsh_ann_timing_enable takes
  * a process-wide mask of stages (bit s = stage s; 0 turns timing off,
  * (1 << PMLSH_N_STAGES) - 1 times every stage; other values: PMLSH_EINVAL).
  * Each launch of a timed stage is bracketed by two HIP events on the caller's
@@ -396,6 +397,13 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
  *   PMLSH_STAGE_PERQUERY  per-query kernel (queries outside the batched path)
  *   PMLSH_STAGE_DIST      squared distances from every query to every 64-point
  *                         chunk centre (input of the bound and of Eq. 5)
+ * and of pmlsh_acp (Section 6.3), one launch each per call:
+ *   PMLSH_STAGE_ACP_SELFJOIN  exact distances of every within-leaf pair
+ *   PMLSH_STAGE_ACP_SELECT    ub = the k-th smallest of them (on the device)
+ *   PMLSH_STAGE_ACP_TILES     parent distances and the Mindist (Eq. 11) leaf-pair test
+ *   PMLSH_STAGE_ACP_SCAN      projected pair scan of the surviving leaf pairs
+ *   PMLSH_STAGE_ACP_VERIFY    seeds of the top-k band and exact distances of the candidates
+ *   PMLSH_STAGE_ACP_TOPK      top-k of the verified pairs (FP64 order in the band)
  * Host-side bookkeeping only; enabling it does not change any result.
  */
 #define PMLSH_STAGE_PROJECT 0
@@ -404,7 +412,13 @@ int pmlsh_index_export_leaves(const pmlsh_index* index, int32_t* perm,
 #define PMLSH_STAGE_FINISH 3
 #define PMLSH_STAGE_PERQUERY 4
 #define PMLSH_STAGE_DIST 5
-#define PMLSH_N_STAGES 6
+#define PMLSH_STAGE_ACP_SELFJOIN 6
+#define PMLSH_STAGE_ACP_SELECT 7
+#define PMLSH_STAGE_ACP_TILES 8
+#define PMLSH_STAGE_ACP_SCAN 9
+#define PMLSH_STAGE_ACP_VERIFY 10
+#define PMLSH_STAGE_ACP_TOPK 11
+#define PMLSH_N_STAGES 12
 
 typedef struct {
     double ms[PMLSH_N_STAGES];

@@ -74,11 +74,13 @@ class _ServerStats(ctypes.Structure):
                 ("latency_p99_ms", ctypes.c_double), ("latency_max_ms", ctypes.c_double)]
 
 
+STAGES = ("project", "tau", "filter", "finish", "per_query", "dist",
+          "acp_selfjoin", "acp_select", "acp_tiles", "acp_scan", "acp_verify", "acp_topk")
+
+
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
-
-
-STAGES = ("project", "tau", "filter", "finish", "per_query", "dist")
+    _fields_ = [("ms", ctypes.c_double * len(STAGES)),
+                ("launches", ctypes.c_int64 * len(STAGES))]
 
 _LIB = None
 

@@ -335,6 +335,449 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_kernel(
     }
 }
 
+// ---------------------------------------------------------------- wave scan
+// Leaves of at most 64 points: one wave per leaf computes the parent
+// distances PD of its points (as acp_pd_kernel) and sorts them ascending
+// (ties by position) across its lanes: spd holds the sorted values (+inf
+// past the leaf's count), sidx the position of each in the leaf.
+__global__ __launch_bounds__(WG) void acp_pd_sorted_kernel(
+    const float* __restrict__ phi, const float* __restrict__ plo, NodeView v, int64_t leaf_base,
+    int64_t n, int L, int64_t n_leaves, float* __restrict__ ppd, float* __restrict__ spd,
+    uint8_t* __restrict__ sidx) {
+    const int64_t leaf = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    if (leaf >= n_leaves) return;          // the whole wave leaves together
+    const int lane = lane_id();
+    const int64_t p0 = leaf * L;
+    const int cnt = (int)(n - p0 < L ? n - p0 : L);
+    float val = INFINITY;
+    if (lane < cnt) {
+        const int64_t node = leaf_base + leaf;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) {
+            const float dt = __fadd_rn(
+                __fsub_rn(phi[(p0 + lane) * MP + t], v.cen[(int64_t)t * v.n_nodes + node]),
+                plo[(p0 + lane) * MP + t]);
+            acc = __fmaf_rn(dt, dt, acc);
+        }
+        val = sqrtf(acc);
+        ppd[p0 + lane] = val;
+    }
+    int idx = lane;
+    // bitonic network over the 64 lanes on (value, position)
+    for (int s = 2; s <= 64; s <<= 1) {
+        for (int j = s >> 1; j > 0; j >>= 1) {
+            const float ov = __shfl_xor(val, j);
+            const int oi = __shfl_xor(idx, j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & s) == 0);
+            const bool other_less = ov < val || (ov == val && oi < idx);
+            if (keep_min == other_less) {
+                val = ov;
+                idx = oi;
+            }
+        }
+    }
+    spd[leaf * 64 + lane] = val;
+    sidx[leaf * 64 + lane] = (uint8_t)idx;
+}
+
+// Number of the 64 ascending values y (one per lane) below v (strict) or at
+// most v; every lane of the wave must call it.
+__device__ __forceinline__ int count_sorted(float y, float v, bool strict) {
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const float yy = __shfl(y, pos + step - 1);
+        if (strict ? yy < v : yy <= v) pos += step;
+    }
+    const float yy = __shfl(y, pos);
+    if (strict ? yy < v : yy <= v) ++pos;
+    return pos;
+}
+
+__device__ __forceinline__ float readlane_f(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Lanes with a PD candidate range of at most this many pairs each take them
+// one by one; a wider tile is scanned whole.
+constexpr int kSparseMax = 40;
+
+// The pairs of the surviving tiles (leaves of at most 64 points), one wave
+// per contiguous run of the tile list; lane a holds point a of the first
+// leaf (its hi/lo projection in registers, kept while the first leaf stays
+// the same).
+//   1. lane a computes x = dist(a, centre of e2); the pairs (a, b) whose PD
+//      bound |x - PD(b)| (less its FP32 error, as in acp_tile_scan_kernel)
+//      stays below Rlim have PD(b) inside an interval around x, found by
+//      binary search in e2's sorted PDs (the interval is widened so that it
+//      holds every such b);
+//   2. each b of the interval gets the same per-pair PD test and, when it
+//      passes, the projected distance from the hi/lo coordinates; pairs
+//      with pd^2 < R2 are emitted. When some lane's interval is wide, the
+//      whole tile is scanned instead: lanes take b, the loop takes a.
+// The emitted set is the set acp_tile_scan_kernel emits for the same tiles.
+__global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
+    const float* __restrict__ phi, const float* __restrict__ plo, const float* __restrict__ ppd,
+    const float* __restrict__ spd, const uint8_t* __restrict__ sidx, NodeView v,
+    int64_t leaf_base, const int32_t* __restrict__ perm, int64_t n, int L,
+    const int2* __restrict__ tiles, int64_t n_tiles, float R2, float Rlim,
+    uint32_t* __restrict__ ck0, uint32_t* __restrict__ cii, uint32_t* __restrict__ cjj,
+    int64_t cap, unsigned long long* __restrict__ counter) {
+    const int lane = lane_id();
+    const int64_t gw = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (WG / 64);
+    const int64_t per = (n_tiles + nw - 1) / nw;
+    const int64_t t_beg = gw * per;
+    const int64_t t_end = t_beg + per < n_tiles ? t_beg + per : n_tiles;
+    const float u = 5.9604645e-08f;
+    float h1[MP], l1[MP];
+    int held = -1, ca = 0;
+    uint32_t id1 = 0;
+    for (int64_t t = t_beg; t < t_end; ++t) {
+        const int2 tl = tiles[t];
+        const int e1 = __builtin_amdgcn_readfirstlane(tl.x);
+        const int e2 = __builtin_amdgcn_readfirstlane(tl.y);
+        const int64_t a0 = (int64_t)e1 * L, b0 = (int64_t)e2 * L;
+        if (e1 != held) {
+            ca = (int)(n - a0 < L ? n - a0 : L);
+            const int a = lane < ca ? lane : 0;
+            const float4* hp = reinterpret_cast<const float4*>(phi + (a0 + a) * MP);
+            const float4* lp = reinterpret_cast<const float4*>(plo + (a0 + a) * MP);
+#pragma unroll
+            for (int q = 0; q < MP / 4; ++q) {
+                const float4 hv = hp[q], lv = lp[q];
+                h1[4 * q] = hv.x; h1[4 * q + 1] = hv.y; h1[4 * q + 2] = hv.z; h1[4 * q + 3] = hv.w;
+                l1[4 * q] = lv.x; l1[4 * q + 1] = lv.y; l1[4 * q + 2] = lv.z; l1[4 * q + 3] = lv.w;
+            }
+            id1 = (uint32_t)perm[a0 + a];
+            held = e1;
+        }
+        const int cb = (int)(n - b0 < L ? n - b0 : L);
+        const bool diag = e1 == e2;
+        // 1. distance to the centre of e2, interval of PD(b)
+        const int64_t node2 = leaf_base + e2;
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < MP; ++j) {
+            const float dt = __fadd_rn(__fsub_rn(h1[j], v.cen[(int64_t)j * v.n_nodes + node2]), l1[j]);
+            acc = __fmaf_rn(dt, dt, acc);
+        }
+        const float x = sqrtf(acc);
+        const float y = spd[(int64_t)e2 * 64 + lane];
+        const int sb = sidx[(int64_t)e2 * 64 + lane];
+        // |x - y| - 32u (x + y) < Rlim implies y in (lov, hiv) in exact
+        // arithmetic; the bounds are widened by 1e-6 (x + Rlim), far more than
+        // the FP32 rounding of that test and of the bounds themselves
+        float lov = (x * (1.f - 32.f * u) - Rlim) / (1.f + 32.f * u);
+        float hiv = (x * (1.f + 32.f * u) + Rlim) / (1.f - 32.f * u);
+        const float wid = (x + (Rlim < INFINITY ? Rlim : 0.f)) * 1e-6f + 1e-30f;
+        lov -= wid;
+        hiv += wid;
+        if (lane >= ca) {
+            lov = INFINITY;
+            hiv = -INFINITY;
+        }
+        const int lo = count_sorted(y, lov, true);
+        int hi = count_sorted(y, hiv, false);
+        hi = hi < cb ? hi : cb;
+        const int mine = hi > lo ? hi - lo : 0;
+        const int widest = wave_max(mine);
+        if (widest == 0) continue;
+        if (widest <= kSparseMax) {
+            // 2a. lane by lane
+            for (int it = 0; it < widest; ++it) {
+                const int pos = lo + (it < mine ? it : 0);
+                const float yb = __shfl(y, pos);
+                const int b = __shfl(sb, pos);
+                bool hit = false;
+                float pd2 = 0.f;
+                uint32_t id2 = 0;
+                if (it < mine && (!diag || b > lane) &&
+                    fabsf(x - yb) - 32.f * u * (x + yb) < Rlim) {
+                    const float4* hp = reinterpret_cast<const float4*>(phi + (b0 + b) * MP);
+                    const float4* lp = reinterpret_cast<const float4*>(plo + (b0 + b) * MP);
+#pragma unroll
+                    for (int q = 0; q < MP / 4; ++q) {
+                        const float4 hv = hp[q], lv = lp[q];
+                        float dt;
+                        dt = __fadd_rn(__fsub_rn(h1[4 * q], hv.x), __fsub_rn(l1[4 * q], lv.x));
+                        pd2 = __fmaf_rn(dt, dt, pd2);
+                        dt = __fadd_rn(__fsub_rn(h1[4 * q + 1], hv.y), __fsub_rn(l1[4 * q + 1], lv.y));
+                        pd2 = __fmaf_rn(dt, dt, pd2);
+                        dt = __fadd_rn(__fsub_rn(h1[4 * q + 2], hv.z), __fsub_rn(l1[4 * q + 2], lv.z));
+                        pd2 = __fmaf_rn(dt, dt, pd2);
+                        dt = __fadd_rn(__fsub_rn(h1[4 * q + 3], hv.w), __fsub_rn(l1[4 * q + 3], lv.w));
+                        pd2 = __fmaf_rn(dt, dt, pd2);
+                    }
+                    hit = pd2 < R2;
+                    id2 = (uint32_t)perm[b0 + b];
+                }
+                const int64_t slot = wave_append_global(hit, counter);
+                if (hit && slot < cap) {
+                    ck0[slot] = __float_as_uint(pd2);
+                    cii[slot] = id1 < id2 ? id1 : id2;
+                    cjj[slot] = id1 < id2 ? id2 : id1;
+                }
+            }
+        } else {
+            // 2b. the whole tile: lane b holds point b of e2, the loop takes a
+            const int b = lane < cb ? lane : 0;
+            float h2[MP], l2[MP];
+            const float4* hp = reinterpret_cast<const float4*>(phi + (b0 + b) * MP);
+            const float4* lp = reinterpret_cast<const float4*>(plo + (b0 + b) * MP);
+#pragma unroll
+            for (int q = 0; q < MP / 4; ++q) {
+                const float4 hv = hp[q], lv = lp[q];
+                h2[4 * q] = hv.x; h2[4 * q + 1] = hv.y; h2[4 * q + 2] = hv.z; h2[4 * q + 3] = hv.w;
+                l2[4 * q] = lv.x; l2[4 * q + 1] = lv.y; l2[4 * q + 2] = lv.z; l2[4 * q + 3] = lv.w;
+            }
+            const float yb = ppd[b0 + b];
+            const uint32_t id2 = (uint32_t)perm[b0 + b];
+            for (int a = 0; a < ca; ++a) {
+                const float xa = readlane_f(x, a);
+                bool hit = false;
+                float pd2 = 0.f;
+                if (lane < cb && (!diag || lane > a) &&
+                    fabsf(xa - yb) - 32.f * u * (xa + yb) < Rlim) {
+#pragma unroll
+                    for (int j = 0; j < MP; ++j) {
+                        const float dt = __fadd_rn(__fsub_rn(readlane_f(h1[j], a), h2[j]),
+                                                   __fsub_rn(readlane_f(l1[j], a), l2[j]));
+                        pd2 = __fmaf_rn(dt, dt, pd2);
+                    }
+                    hit = pd2 < R2;
+                }
+                const uint32_t ia = (uint32_t)__builtin_amdgcn_readlane((int)id1, a);
+                const int64_t slot = wave_append_global(hit, counter);
+                if (hit && slot < cap) {
+                    ck0[slot] = __float_as_uint(pd2);
+                    cii[slot] = ia < id2 ? ia : id2;
+                    cjj[slot] = ia < id2 ? id2 : ia;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- seeds
+// Self-join of leaves of at most 64 points, one workgroup per leaf: the
+// squared distance of every pair a < b, FP32 direct differences. The
+// triangle of 4 x 4 point blocks (136 blocks) is split over two halves of
+// every 64-dimension chunk (272 tasks); a task keeps its block's 16 pairs in
+// two interleaved accumulators each, so every FP32 sum is a chain of
+// d_pad / 4 terms and the squared distance carries a relative error of at
+// most (d_pad / 4 + 4) u (two chains per half, two halves). Writes the
+// distance bits of pair (a, b) at seed_off[leaf] + a (2 cnt - a - 1) / 2 +
+// b - a - 1 (and, with ii/jj, the ids i < j), and adds the top 11 bits of
+// every distance to the device-wide histogram ghist (first radix pass of the
+// k-th smallest seed).
+constexpr int SJ_THREADS = 320;
+constexpr int SJ_TASKS = 272;
+constexpr int SJ_CK = 64;
+__global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
+    const float* __restrict__ data, int d_pad, const int32_t* __restrict__ perm, int64_t n,
+    int L, const int64_t* __restrict__ seed_off, uint32_t* __restrict__ k0,
+    uint32_t* __restrict__ ii, uint32_t* __restrict__ jj, uint32_t* __restrict__ ghist) {
+    __shared__ float xs[64][SJ_CK + 1];
+    __shared__ float part[SJ_TASKS / 2][16];
+    __shared__ uint32_t hist[NB];
+    const int64_t leaf = blockIdx.x;
+    const int64_t p0 = leaf * L;
+    const int cnt = (int)(n - p0 < L ? n - p0 : L);
+    const int t = threadIdx.x;
+    for (int i = t; i < NB; i += SJ_THREADS) hist[i] = 0;
+    const bool task = t < SJ_TASKS;
+    const int bl = t >> 1, half = t & 1;
+    int bi = 0, rem = task ? bl : 0;
+    while (rem >= 16 - bi) {
+        rem -= 16 - bi;
+        ++bi;
+    }
+    const int bj = bi + rem;
+    float acc0[16], acc1[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) { acc0[q] = 0.f; acc1[q] = 0.f; }
+    for (int c0 = 0; c0 < d_pad; c0 += SJ_CK) {
+        const int w = d_pad - c0 < SJ_CK ? d_pad - c0 : SJ_CK;
+        __syncthreads();
+        for (int e = t; e < 64 * (SJ_CK / 4); e += SJ_THREADS) {
+            const int r = e / (SJ_CK / 4), q = e % (SJ_CK / 4);
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < cnt && 4 * q < w)
+                val = *reinterpret_cast<const float4*>(data + (p0 + r) * d_pad + c0 + 4 * q);
+            xs[r][4 * q] = val.x;
+            xs[r][4 * q + 1] = val.y;
+            xs[r][4 * q + 2] = val.z;
+            xs[r][4 * q + 3] = val.w;
+        }
+        __syncthreads();
+        if (task) {
+            for (int i = 0; i < SJ_CK / 2; i += 2) {
+                const int dd = half * (SJ_CK / 2) + i;
+                float xa[4], xb[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { xa[r] = xs[4 * bi + r][dd]; xb[r] = xs[4 * bj + r][dd]; }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float df = __fsub_rn(xa[r], xb[s]);
+                        acc0[4 * r + s] = __fmaf_rn(df, df, acc0[4 * r + s]);
+                    }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { xa[r] = xs[4 * bi + r][dd + 1]; xb[r] = xs[4 * bj + r][dd + 1]; }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float df = __fsub_rn(xa[r], xb[s]);
+                        acc1[4 * r + s] = __fmaf_rn(df, df, acc1[4 * r + s]);
+                    }
+            }
+        }
+    }
+    // combine: the two chains of each half, then the two halves
+    if (task && half == 1) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) part[bl][q] = __fadd_rn(acc0[q], acc1[q]);
+    }
+    __syncthreads();
+    if (task && half == 0) {
+        const int64_t out0 = seed_off[leaf];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int a = 4 * bi + r, b = 4 * bj + s;
+                if (a < b && b < cnt) {
+                    const float d2 = __fadd_rn(__fadd_rn(acc0[4 * r + s], acc1[4 * r + s]),
+                                               part[bl][4 * r + s]);
+                    const uint32_t bits = __float_as_uint(d2);
+                    const int64_t p = out0 + (int64_t)a * (2 * cnt - a - 1) / 2 + (b - a - 1);
+                    k0[p] = bits;
+                    if (ii) {
+                        const uint32_t ia = (uint32_t)perm[p0 + a], ib = (uint32_t)perm[p0 + b];
+                        ii[p] = ia < ib ? ia : ib;
+                        jj[p] = ia < ib ? ib : ia;
+                    }
+                    atomicAdd(&hist[bits >> 21], 1u);
+                }
+            }
+    }
+    __syncthreads();
+    for (int i = t; i < NB; i += SJ_THREADS)
+        if (hist[i]) atomicAdd(&ghist[i], hist[i]);
+}
+
+// Device-side radix select of the need-th smallest of `count` 32-bit keys:
+// the state holds the bits resolved so far (prefix, pbits) and the rank
+// still to find among the keys with that prefix. A histogram pass counts the
+// next `width` bits of the keys that carry the prefix; the pick kernel finds
+// the bin holding the rank, extends the prefix, and clears the histogram.
+struct SelState {
+    uint32_t prefix;
+    int32_t pbits;
+    int64_t need;
+};
+
+__global__ __launch_bounds__(WG) void acp_sel_hist_kernel(
+    const uint32_t* __restrict__ keys, int64_t count, const SelState* __restrict__ state,
+    int shift, int width, uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[NB];
+    for (int i = threadIdx.x; i < NB; i += WG) h[i] = 0;
+    __syncthreads();
+    const uint32_t prefix = state->prefix;
+    const int pbits = state->pbits;
+    const uint32_t mask = (1u << width) - 1u;
+    for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * WG) {
+        const uint32_t x = keys[e];
+        if (pbits == 0 || (x >> (32 - pbits)) == prefix) atomicAdd(&h[(x >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += WG)
+        if (h[i]) atomicAdd(&ghist[i], h[i]);
+}
+
+__global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__ ghist,
+                                                          SelState* __restrict__ state,
+                                                          int width) {
+    __shared__ uint32_t tot[WG];
+    const int per = NB / WG;                 // 8 bins per thread
+    uint32_t mine = 0;
+    for (int i = 0; i < per; ++i) mine += ghist[threadIdx.x * per + i];
+    tot[threadIdx.x] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t need = state->need;
+        int64_t cum = 0;
+        int bin = -1;
+        for (int th = 0; th < WG && bin < 0; ++th) {
+            if (cum + tot[th] >= need) {
+                for (int i = 0; i < per; ++i) {
+                    const uint32_t c = ghist[th * per + i];
+                    if (cum + c >= need) { bin = th * per + i; break; }
+                    cum += c;
+                }
+            } else {
+                cum += tot[th];
+            }
+        }
+        if (bin < 0) bin = (1 << width) - 1;   // unreachable while need <= count
+        state->prefix = (state->prefix << width) | (uint32_t)bin;
+        state->pbits += width;
+        state->need = need - cum;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
+}
+
+// Within-leaf pairs whose distance bits are at most lim (the band of the
+// top-k, or every seed when lim is +inf): (bits, i, j) appended to the pool.
+__global__ __launch_bounds__(WG) void acp_seed_band_kernel(
+    const uint32_t* __restrict__ k0, const int64_t* __restrict__ seed_off,
+    const int32_t* __restrict__ perm, int64_t n, int L, uint32_t lim,
+    uint32_t* __restrict__ ok0, uint32_t* __restrict__ oii, uint32_t* __restrict__ ojj,
+    int64_t cap, unsigned long long* __restrict__ counter) {
+    const int64_t leaf = blockIdx.x;
+    const int64_t p0 = leaf * L;
+    const int cnt = (int)(n - p0 < L ? n - p0 : L);
+    const int P = cnt * (cnt - 1) / 2;
+    const int64_t off = seed_off[leaf];
+    for (int base = 0; base < P; base += WG) {
+        const int p = base + threadIdx.x;
+        uint32_t key = 0;
+        bool take = false;
+        if (p < P) {
+            key = k0[off + p];
+            take = key <= lim;
+        }
+        uint32_t i = 0, j = 0;
+        if (take) {
+            int a = 0, rem = p;
+            while (rem >= cnt - 1 - a) { rem -= cnt - 1 - a; ++a; }
+            const uint32_t ia = (uint32_t)perm[p0 + a], ib = (uint32_t)perm[p0 + a + 1 + rem];
+            i = ia < ib ? ia : ib;
+            j = ia < ib ? ib : ia;
+        }
+        const int64_t slot = wave_append_global(take, counter);
+        if (take && slot < cap) { ok0[slot] = key; oii[slot] = i; ojj[slot] = j; }
+    }
+}
+
 // ---------------------------------------------------------------- verify
 __global__ __launch_bounds__(WG) void acp_verify_kernel(
     const float* __restrict__ data, int d_pad, const int32_t* __restrict__ inv_perm,
@@ -549,12 +992,42 @@ __global__ __launch_bounds__(WG) void acp_final64_kernel(
     }
 }
 
+// The pool pairs whose FP32 distance bits are at most the band limit of the
+// selected k-th key (state->prefix): kth (1 + band), rounded up one ulp, the
+// same limit pool_topk states on the host.
+__global__ __launch_bounds__(WG) void acp_band_gather_kernel(
+    const uint32_t* __restrict__ k0, const uint32_t* __restrict__ ii,
+    const uint32_t* __restrict__ jj, int64_t count, const SelState* __restrict__ state,
+    double band, uint32_t* __restrict__ ok0, uint32_t* __restrict__ oii,
+    uint32_t* __restrict__ ojj, int64_t cap, unsigned long long* __restrict__ counter) {
+    const float kth = __uint_as_float(state->prefix);
+    const uint32_t lim = __float_as_uint(nextafterf((float)((double)kth * (1.0 + band)), INFINITY));
+    for (int64_t base = (int64_t)blockIdx.x * WG; base < count; base += (int64_t)gridDim.x * WG) {
+        const int64_t e = base + threadIdx.x;
+        bool take = false;
+        uint32_t a = 0;
+        if (e < count) {
+            a = k0[e];
+            take = a <= lim;
+        }
+        const int64_t slot = wave_append_global(take, counter);
+        if (take && slot < cap) { ok0[slot] = a; oii[slot] = ii[e]; ojj[slot] = jj[e]; }
+    }
+}
+
+__global__ void acp_sel_init_kernel(SelState* state, int64_t need) {
+    state->prefix = 0;
+    state->pbits = 0;
+    state->need = need;
+}
+
 // ---------------------------------------------------------------- host side
 // Workspace buffer of one role, kept in the index between calls and grown
 // (freed and allocated anew) only when a call needs more than it holds.
 enum Slot {
     S_HIST, S_COUNT, S_DOFF, S_TILES, S_PPD, S_SEEDS, S_CAND = S_SEEDS + 3, S_KEPT = S_CAND + 3,
-    S_POOL = S_KEPT + 3, S_TOP = S_POOL + 3, S_COUNT_ALL = S_TOP + 3
+    S_POOL = S_KEPT + 3, S_TOP = S_POOL + 3, S_SPD = S_TOP + 3, S_SIDX, S_STATE, S_GHIST,
+    S_COUNT_ALL
 };
 
 struct DevBuf {
@@ -640,46 +1113,177 @@ SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, in
     return K;
 }
 
+
+// Device-side selection of the need-th smallest of `count` 32-bit keys (no
+// host round trip): three histogram passes of 11, 11 and 10 bits, each
+// followed by the pick kernel; the key is left in state->prefix and ghist is
+// left cleared. With first_done the first pass (top 11 bits) is already in
+// ghist; otherwise ghist must be clear on entry.
+void device_select(const uint32_t* keys, int64_t count, int64_t need, SelState* state,
+                   uint32_t* ghist, bool first_done, hipStream_t st) {
+    hipLaunchKernelGGL(acp_sel_init_kernel, dim3(1), dim3(1), 0, st, state, need);
+    PMLSH_HIP(hipGetLastError());
+    const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
+    for (int pass = 0; pass < 3; ++pass) {
+        if (pass > 0 || !first_done) {
+            hipLaunchKernelGGL(acp_sel_hist_kernel, dim3(grid_for(count, WG * 16)), dim3(WG), 0,
+                               st, keys, count, state, shifts[pass], widths[pass], ghist);
+            PMLSH_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(acp_sel_pick_kernel, dim3(1), dim3(WG), 0, st, ghist, state,
+                           widths[pass]);
+        PMLSH_HIP(hipGetLastError());
+    }
+}
+
+// Relative error bound of the FP32 squared distances in a pool: the verify
+// kernel sums d_pad / 16 terms per lane and four shuffle levels, (d_pad / 16
+// + 6) u; the self-join of leaves of at most 64 points sums chains of
+// d_pad / 4 terms, (d_pad / 4 + 4) u; the self-join of larger leaves one
+// chain of d_pad terms, (d_pad + 2) u. The band of the FP64 top-k is sized
+// with twice the largest bound of the kernels that filled the pool.
+double pool_gamma(const pmlsh_index* x, bool has_seeds) {
+    const double u = 5.9604645e-08;
+    double g = (double)(x->d_pad / 16 + 8);
+    if (has_seeds) g = std::max(g, x->leaf_size <= 64 ? (double)(x->d_pad / 4 + 4)
+                                                      : (double)(x->d_pad + 2));
+    return 2.0 * u * g;
+}
+
+// Self-join of every leaf: distance bits to k0 (and ids to ii/jj when given),
+// in the triangular layout of seed_off. For leaves of at most 64 points the
+// first radix pass of the k-th seed is added to ghist (returns true).
+bool launch_self_join(const pmlsh_index* x, const int64_t* doff, uint32_t* k0, uint32_t* ii,
+                      uint32_t* jj, uint32_t* ghist, hipStream_t st) {
+    if (x->leaf_size <= 64) {
+        hipLaunchKernelGGL(acp_seed_join_kernel, dim3((unsigned)x->n_leaves), dim3(SJ_THREADS), 0,
+                           st, x->data, x->d_pad, x->perm, x->n, x->leaf_size, doff, k0, ii, jj,
+                           ghist);
+        PMLSH_HIP(hipGetLastError());
+        return true;
+    }
+    if (!ii || !jj) fail(PMLSH_EDEVICE, "self-join of large leaves needs id buffers");
+    hipLaunchKernelGGL(acp_self_join_kernel, dim3((unsigned)x->n_leaves), dim3(WG), 0, st,
+                       x->data, x->d_pad, x->perm, x->n, x->leaf_size, doff, k0, ii, jj);
+    PMLSH_HIP(hipGetLastError());
+    return false;
+}
+
+// Pair scan of a tile list (leaf pairs) against the projected radius: the
+// wave-per-tile kernel on the leaves' sorted parent distances when leaves
+// hold at most 64 points, the workgroup-per-tile kernel otherwise. Both emit
+// exactly the pairs of the tiles with pd^2 < R2 (and a < b on diagonal
+// tiles), counted in *counter and written while below cap.
+struct TileScan {
+    const pmlsh_index* x;
+    hipStream_t st;
+    NodeView v;
+    int64_t leaf_base;
+    DevBuf ppd, spd, sidx;
+    bool wave = false;
+    size_t lds = 0;
+
+    TileScan(const pmlsh_index* idx, hipStream_t s)
+        : x(idx), st(s),
+          v{idx->tree.centre, idx->tree.radius, idx->tree.hr_min, idx->tree.hr_max, idx->n_nodes,
+            idx->num_pivots},
+          leaf_base(idx->level_begin[idx->levels - 1]), ppd(idx, S_PPD), spd(idx, S_SPD),
+          sidx(idx, S_SIDX) {}
+
+    // parent distances (and their per-leaf sorted copies) of every point
+    void prepare() {
+        const int64_t n = x->n, NL = x->n_leaves;
+        const int L = x->leaf_size;
+        ppd.alloc((size_t)n * sizeof(float));
+        wave = L <= 64;
+        if (wave) {
+            spd.alloc((size_t)NL * 64 * sizeof(float));
+            sidx.alloc((size_t)NL * 64);
+            hipLaunchKernelGGL(acp_pd_sorted_kernel, dim3((unsigned)((NL + 3) / 4)), dim3(WG), 0,
+                               st, x->proj_hi, x->proj_lo, v, leaf_base, n, L, NL,
+                               ppd.as<float>(), spd.as<float>(), sidx.as<uint8_t>());
+            PMLSH_HIP(hipGetLastError());
+            return;
+        }
+        hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
+                           x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
+        PMLSH_HIP(hipGetLastError());
+        lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
+        if (lds > 160 * 1024 - 256)
+            fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
+        PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+
+    void scan(const int2* tiles, int64_t n_tiles, float R2, float Rlim, uint32_t* k0,
+              uint32_t* ii, uint32_t* jj, int64_t cap, unsigned long long* counter) {
+        if (n_tiles <= 0) return;
+        if (wave) {
+            const int64_t waves = std::min<int64_t>(n_tiles, 16384);
+            hipLaunchKernelGGL(acp_tile_scan_wave_kernel, dim3((unsigned)((waves + 3) / 4)),
+                               dim3(WG), 0, st, x->proj_hi, x->proj_lo, ppd.as<float>(),
+                               spd.as<float>(), sidx.as<uint8_t>(), v, leaf_base, x->perm, x->n,
+                               x->leaf_size, tiles, n_tiles, R2, Rlim, k0, ii, jj, cap, counter);
+        } else {
+            hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds, st,
+                               x->proj_hi, x->proj_lo, ppd.as<float>(), v, leaf_base, x->perm,
+                               x->n, x->leaf_size, tiles, n_tiles, R2, Rlim, k0, ii, jj, cap,
+                               counter);
+        }
+        PMLSH_HIP(hipGetLastError());
+    }
+};
+
 }  // namespace
 
-// The k nearest pairs of the verified pool, in (distance, i, j) order. The FP32
-// k-th distance bounds the band of pairs that can belong to the exact top-k
-// (verify error 2u(d/16 + 8) relative, taken twice over); their order is taken
-// in FP64. A band of more than kTopBand pairs (mass ties) keeps the FP32 order.
-void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, Triplets& top,
-               DevBuf& dhist, DevBuf& dcount, int64_t* out_pairs, float* out_dist,
-               hipStream_t st) {
-    auto gather = [&](SelKey K, int64_t cap) -> int64_t {
-        PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
-        hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
-                           pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
-                           pool.jj.as<uint32_t>(), n_pool, K, top.k0.as<uint32_t>(),
-                           top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), cap,
-                           static_cast<unsigned long long*>(dcount.p));
-        PMLSH_HIP(hipGetLastError());
-        unsigned long long v = 0;
-        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
-        return (int64_t)v;
-    };
-    const SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
-                                pool.jj.as<uint32_t>(), n_pool, k, false,
-                                dhist.as<uint32_t>(), st);
+// The k nearest pairs of the verified pool, in (distance, i, j) order. The
+// FP32 k-th distance (selected on the device) bounds the band of pairs that
+// can belong to the exact top-k: every pool value carries a relative error
+// of at most gamma (pool_gamma), so a pair whose exact distance is at most
+// the exact k-th one has an FP32 value within kth (1 + 4 gamma); the band's
+// order is taken in FP64. A band of more than kTopBand pairs (mass ties)
+// keeps the FP32 order.
+void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, double gamma,
+               Triplets& top, DevBuf& dhist, DevBuf& dcount, int64_t* out_pairs,
+               float* out_dist, hipStream_t st) {
+    DevBuf dstate(x, S_STATE), ghist(x, S_GHIST);
+    dstate.alloc(sizeof(SelState));
+    ghist.alloc(NB * sizeof(uint32_t));
+    PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
+    device_select(pool.k0.as<uint32_t>(), n_pool, k, dstate.as<SelState>(),
+                  ghist.as<uint32_t>(), false, st);
     top.alloc(kTopBand);
-    float kth;
-    std::memcpy(&kth, &K.v0, sizeof(kth));
-    const double gamma = 2.0 * 5.9604645e-08 * (double)(x->d_pad / 16 + 8);
-    const float lim = std::nextafter((float)((double)kth * (1.0 + 4.0 * gamma)), INFINITY);
-    uint32_t lim_bits;
-    std::memcpy(&lim_bits, &lim, sizeof(lim_bits));
-    const int64_t m = gather(SelKey{0, lim_bits, 0, 0}, kTopBand);
-    if (m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
-    if (m <= kTopBand) {
+    PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(acp_band_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
+                       pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(),
+                       n_pool, dstate.as<SelState>(), 4.0 * gamma, top.k0.as<uint32_t>(),
+                       top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), (int64_t)kTopBand,
+                       static_cast<unsigned long long*>(dcount.p));
+    PMLSH_HIP(hipGetLastError());
+    unsigned long long m = 0;
+    PMLSH_HIP(hipMemcpyAsync(&m, dcount.p, sizeof(m), hipMemcpyDeviceToHost, st));
+    PMLSH_HIP(hipStreamSynchronize(st));
+    if ((int64_t)m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+    if ((int64_t)m <= kTopBand) {
         hipLaunchKernelGGL(acp_final64_kernel, dim3(1), dim3(WG), 0, st, x->data, x->d_pad,
                            x->inv_perm, top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), (int)m,
                            k, out_pairs, out_dist);
     } else {
-        if (gather(K, k) != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+        // mass ties: the k smallest full keys (distance bits, i, j) in FP32
+        const SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                                    pool.jj.as<uint32_t>(), n_pool, k, false,
+                                    dhist.as<uint32_t>(), st);
+        PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_pool, WG)), dim3(WG), 0, st,
+                           pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                           pool.jj.as<uint32_t>(), n_pool, K, top.k0.as<uint32_t>(),
+                           top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), (int64_t)k,
+                           static_cast<unsigned long long*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        unsigned long long g = 0;
+        PMLSH_HIP(hipMemcpyAsync(&g, dcount.p, sizeof(g), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        if ((int64_t)g != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
         hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
                            top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs,
                            out_dist);
@@ -699,9 +1303,11 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
 
     std::lock_guard<std::mutex> lock(x->acp_mu);
     if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});
-    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT);
+    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), dstate(x, S_STATE), ghist(x, S_GHIST);
     dhist.alloc(NB * sizeof(uint32_t));
     dcount.alloc(sizeof(unsigned long long));
+    dstate.alloc(sizeof(SelState));
+    ghist.alloc(NB * sizeof(uint32_t));
     auto reset_counter = [&] {
         PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
     };
@@ -711,8 +1317,8 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         PMLSH_HIP(hipStreamSynchronize(st));
         return (int64_t)v;
     };
-
-    // ---- seeds: every within-leaf pair
+    // ---- seeds: every within-leaf pair (distance bits only; the ids of the
+    // few seeds the top-k can use are recovered from their position)
     std::vector<int64_t> seed_off(NL + 1, 0);
     for (int64_t b = 0; b < NL; ++b) {
         const int64_t cnt = std::min<int64_t>(L, n - b * L);
@@ -720,27 +1326,38 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     }
     const int64_t n_seed = seed_off[NL];
     Triplets seeds(x, S_SEEDS);
-    seeds.alloc(n_seed);
+    DevBuf doff(x, S_DOFF);
+    bool first_done = false;
+    PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
     if (n_seed > 0) {
-        DevBuf doff(x, S_DOFF);
+        seeds.k0.alloc((size_t)n_seed * 4);
+        if (L > 64) {
+            seeds.ii.alloc((size_t)n_seed * 4);
+            seeds.jj.alloc((size_t)n_seed * 4);
+        }
         doff.alloc((NL + 1) * sizeof(int64_t));
         PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
                                  hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(acp_self_join_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
-                           x->d_pad, x->perm, n, L, doff.as<int64_t>(), seeds.k0.as<uint32_t>(),
-                           seeds.ii.as<uint32_t>(), seeds.jj.as<uint32_t>());
-        PMLSH_HIP(hipGetLastError());
-        PMLSH_HIP(hipStreamSynchronize(st));
+        StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
+        first_done = launch_self_join(x, doff.as<int64_t>(), seeds.k0.as<uint32_t>(),
+                                      L > 64 ? seeds.ii.as<uint32_t>() : nullptr,
+                                      L > 64 ? seeds.jj.as<uint32_t>() : nullptr,
+                                      ghist.as<uint32_t>(), st);
     }
 
-    // ---- ub: k-th smallest seed distance
+    // ---- ub: k-th smallest seed distance (selected on the device)
     double ub = HUGE_VAL;
+    uint32_t ub2_bits = 0x7f800000u;
     if (n_seed >= k) {
-        SelKey K = select_kth(seeds.k0.as<uint32_t>(), seeds.ii.as<uint32_t>(),
-                              seeds.jj.as<uint32_t>(), n_seed, k, true, dhist.as<uint32_t>(), st);
-        uint32_t bits = K.v0;
+        StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
+        device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
+                      ghist.as<uint32_t>(), first_done, st);
+        SelState hs{};
+        PMLSH_HIP(hipMemcpyAsync(&hs, dstate.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        ub2_bits = hs.prefix;
         float ub2;
-        std::memcpy(&ub2, &bits, 4);
+        std::memcpy(&ub2, &ub2_bits, 4);
         ub = std::sqrt((double)ub2);
     }
     const double R = plan.t * ub;
@@ -752,21 +1369,21 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     const int64_t tiles_total = NL * (NL - 1) / 2;
     int64_t n_tiles = 0;
     DevBuf tiles(x, S_TILES);
+    TileScan scan(x, st);
     if (tiles_total > 0) {
         if (tiles_total > (int64_t(1) << 31) || NL > 65535)
             fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
         tiles.alloc((size_t)tiles_total * sizeof(int2));
         reset_counter();
-        const int64_t leaf_base = x->level_begin[x->levels - 1];
-        NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
-                   x->num_pivots};
+        StageTimer tm(PMLSH_STAGE_ACP_TILES, st);
+        scan.prepare();
         dim3 grid((unsigned)NL);
-        hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL, limit,
-                           0, tiles.as<int2>(), tiles_total,
+        hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, scan.v, scan.leaf_base,
+                           NL, limit, 0, tiles.as<int2>(), tiles_total,
                            static_cast<unsigned long long*>(dcount.p));
         PMLSH_HIP(hipGetLastError());
-        n_tiles = read_counter();
     }
+    if (tiles_total > 0) n_tiles = read_counter();
 
     // ---- pair scan of the surviving tiles
     constexpr int64_t kMaxCand = int64_t(1) << 28;
@@ -774,30 +1391,15 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     int64_t n_raw = 0;
     if (n_tiles > 0) {
         int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
-        // parent distances of every point (PD of the PM-tree leaf entries)
-        DevBuf ppd(x, S_PPD);
-        ppd.alloc((size_t)n * sizeof(float));
-        const int64_t leaf_base = x->level_begin[x->levels - 1];
-        NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
-                   x->num_pivots};
-        hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
-                           x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
-        PMLSH_HIP(hipGetLastError());
-        const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
-        if (lds > 160 * 1024 - 256)
-            fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
-        PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         for (int attempt = 0; attempt < 2; ++attempt) {
             cand.alloc(cap);
             reset_counter();
-            hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds,
-                               st, x->proj_hi, x->proj_lo, ppd.as<float>(), v, leaf_base,
-                               x->perm, n, L, tiles.as<int2>(), n_tiles, R2, limit,
-                               cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
-                               cand.jj.as<uint32_t>(), cap,
-                               static_cast<unsigned long long*>(dcount.p));
-            PMLSH_HIP(hipGetLastError());
+            {
+                StageTimer tm(PMLSH_STAGE_ACP_SCAN, st);
+                scan.scan(tiles.as<int2>(), n_tiles, R2, limit, cand.k0.as<uint32_t>(),
+                          cand.ii.as<uint32_t>(), cand.jj.as<uint32_t>(), cap,
+                          static_cast<unsigned long long*>(dcount.p));
+            }
             n_raw = read_counter();
             if (n_raw <= cap) break;
             if (n_raw > kMaxCand)
@@ -826,27 +1428,63 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         cands = &kept;
     }
 
-    // ---- verify the candidates; the pool is seeds followed by candidates
-    Triplets pool(x, S_POOL);
-    const int64_t n_pool = n_seed + n_keep;
-    pool.alloc(n_pool);
-    if (n_seed > 0) {
-        PMLSH_HIP(hipMemcpyAsync(pool.k0.p, seeds.k0.p, n_seed * 4, hipMemcpyDeviceToDevice, st));
-        PMLSH_HIP(hipMemcpyAsync(pool.ii.p, seeds.ii.p, n_seed * 4, hipMemcpyDeviceToDevice, st));
-        PMLSH_HIP(hipMemcpyAsync(pool.jj.p, seeds.jj.p, n_seed * 4, hipMemcpyDeviceToDevice, st));
+    // ---- the pool: the seeds within the band of the top-k (every seed when
+    // there are fewer than k), then the verified candidates. The pool's k-th
+    // FP32 distance is at most the seeds' k-th (ub^2), so every seed its
+    // FP64 band can hold lies within ub^2 (1 + 4 gamma).
+    const double gamma = pool_gamma(x, true);
+    uint32_t seed_lim = 0xffffffffu;
+    if (n_seed >= k) {
+        float ub2;
+        std::memcpy(&ub2, &ub2_bits, 4);
+        const float lim = std::nextafter((float)((double)ub2 * (1.0 + 4.0 * gamma)), INFINITY);
+        std::memcpy(&seed_lim, &lim, 4);
     }
+    Triplets pool(x, S_POOL);
+    int64_t seed_cap = std::min<int64_t>(n_seed, std::max<int64_t>(4096, 4 * (int64_t)k));
+    int64_t n_band = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        pool.alloc(std::max<int64_t>(seed_cap + n_keep, 1));
+        if (n_seed == 0) break;
+        reset_counter();
+        StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
+        if (L > 64) {
+            const SelKey all{0, seed_lim, 0, 0};
+            hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_seed, WG)), dim3(WG), 0, st,
+                               seeds.k0.as<uint32_t>(), seeds.ii.as<uint32_t>(),
+                               seeds.jj.as<uint32_t>(), n_seed, all, pool.k0.as<uint32_t>(),
+                               pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(), seed_cap,
+                               static_cast<unsigned long long*>(dcount.p));
+        } else {
+            hipLaunchKernelGGL(acp_seed_band_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
+                               seeds.k0.as<uint32_t>(), doff.as<int64_t>(), x->perm, n, L,
+                               seed_lim, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                               pool.jj.as<uint32_t>(), seed_cap,
+                               static_cast<unsigned long long*>(dcount.p));
+        }
+        PMLSH_HIP(hipGetLastError());
+        n_band = read_counter();
+        if (n_band <= seed_cap) break;
+        seed_cap = n_band;
+    }
+    if (n_band > seed_cap) fail(PMLSH_EDEVICE, "seed band grew between two passes");
+    const int64_t n_pool = n_band + n_keep;
     if (n_keep > 0) {
+        StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
         hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(n_keep, WG / 16)), dim3(WG), 0, st,
                            x->data, x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(),
-                           cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_seed,
-                           pool.ii.as<uint32_t>() + n_seed, pool.jj.as<uint32_t>() + n_seed);
+                           cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_band,
+                           pool.ii.as<uint32_t>() + n_band, pool.jj.as<uint32_t>() + n_band);
         PMLSH_HIP(hipGetLastError());
     }
     if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
 
     // ---- top-k over the pool
     Triplets top(x, S_TOP);
-    pool_topk(x, pool, n_pool, k, top, dhist, dcount, out_pairs, out_dist, st);
+    {
+        StageTimer tm(PMLSH_STAGE_ACP_TOPK, st);
+        pool_topk(x, pool, n_pool, k, gamma, top, dhist, dcount, out_pairs, out_dist, st);
+    }
 
     if (stats) {
         stats->t = plan.t;
@@ -884,7 +1522,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
 
     std::lock_guard<std::mutex> lock(x->acp_mu);
     if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});
-    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), tiles(x, S_TILES), ppd(x, S_PPD);
+    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), tiles(x, S_TILES);
     Triplets cand(x, S_CAND), kept(x, S_KEPT), pool(x, S_POOL), top(x, S_TOP);
     dhist.alloc(NB * sizeof(uint32_t));
     dcount.alloc(sizeof(unsigned long long));
@@ -897,18 +1535,10 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     auto reset_counter = [&] {
         PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
     };
-    const int64_t leaf_base = x->level_begin[x->levels - 1];
-    NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
-               x->num_pivots};
-    ppd.alloc((size_t)n * sizeof(float));
-    hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
-                       x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
-    PMLSH_HIP(hipGetLastError());
-    const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
-    if (lds > 160 * 1024 - 256)
-        fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
-    PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    TileScan tscan(x, st);
+    tscan.prepare();
+    const int64_t leaf_base = tscan.leaf_base;
+    const NodeView v = tscan.v;
     const int64_t tiles_all = NL * (NL - 1) / 2 + NL;
     tiles.alloc((size_t)tiles_all * sizeof(int2));
 
@@ -939,14 +1569,11 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     auto scan = [&](int64_t n_tiles, float d2, float limit, int64_t cap) -> int64_t {
         const float R2 = std::isinf(d2) ? INFINITY : std::nextafter(d2, INFINITY);
         reset_counter();
-        hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds, st,
-                           x->proj_hi, x->proj_lo, ppd.as<float>(), v, leaf_base, x->perm, n, L,
-                           tiles.as<int2>(), n_tiles, R2, limit,
-                           cap > 0 ? cand.k0.as<uint32_t>() : nullptr,
-                           cap > 0 ? cand.ii.as<uint32_t>() : nullptr,
-                           cap > 0 ? cand.jj.as<uint32_t>() : nullptr, cap,
-                           static_cast<unsigned long long*>(dcount.p));
-        PMLSH_HIP(hipGetLastError());
+        tscan.scan(tiles.as<int2>(), n_tiles, R2, limit,
+                   cap > 0 ? cand.k0.as<uint32_t>() : nullptr,
+                   cap > 0 ? cand.ii.as<uint32_t>() : nullptr,
+                   cap > 0 ? cand.jj.as<uint32_t>() : nullptr, cap,
+                   static_cast<unsigned long long*>(dcount.p));
         return read_counter();
     };
     auto limit_of = [&](float d2) {
@@ -1021,7 +1648,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
                        pool.jj.as<uint32_t>());
     PMLSH_HIP(hipGetLastError());
     if (keep < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
-    pool_topk(x, pool, keep, k, top, dhist, dcount, out_pairs, out_dist, st);
+    pool_topk(x, pool, keep, k, pool_gamma(x, false), top, dhist, dcount, out_pairs, out_dist, st);
     if (stats) {
         stats->t = plan.t;
         stats->ub = std::sqrt((double)d2);
@@ -1158,11 +1785,12 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
 
     std::lock_guard<std::mutex> lock(x->acp_mu);
     if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});
-    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), tiles(x, S_TILES), ppd(x, S_PPD);
+    DevBuf dhist(x, S_HIST), dcount(x, S_COUNT), tiles(x, S_TILES), ghist(x, S_GHIST);
     Triplets seeds(x, S_SEEDS), cand(x, S_CAND), pool(x, S_POOL), kept(x, S_KEPT),
         top(x, S_TOP);
     dhist.alloc(NB * sizeof(uint32_t));
     dcount.alloc(sizeof(unsigned long long));
+    ghist.alloc(NB * sizeof(uint32_t));
     auto reset_counter = [&] {
         PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
     };
@@ -1188,10 +1816,9 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
         doff.alloc((NL + 1) * sizeof(int64_t));
         PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
                                  hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(acp_self_join_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
-                           x->d_pad, x->perm, n, L, doff.as<int64_t>(), pool.k0.as<uint32_t>(),
-                           pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>());
-        PMLSH_HIP(hipGetLastError());
+        PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
+        launch_self_join(x, doff.as<int64_t>(), pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                         pool.jj.as<uint32_t>(), ghist.as<uint32_t>(), st);
         PMLSH_HIP(hipStreamSynchronize(st));
     }
     int64_t n_pool = n_seed;
@@ -1233,18 +1860,8 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
     });
 
     // 3. the found nodes, ascending radius
-    const int64_t leaf_base = x->level_begin[x->levels - 1];
-    NodeView v{x->tree.centre, x->tree.radius, x->tree.hr_min, x->tree.hr_max, x->n_nodes,
-               x->num_pivots};
-    ppd.alloc((size_t)n * sizeof(float));
-    hipLaunchKernelGGL(acp_pd_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
-                       x->proj_hi, x->proj_lo, v, leaf_base, n, L, ppd.as<float>());
-    PMLSH_HIP(hipGetLastError());
-    const size_t lds = (size_t)L * MP * 4 * 4 + (size_t)L * 4 * 4 + (size_t)64 * 64 * 4;
-    if (lds > 160 * 1024 - 256)
-        fail(PMLSH_EUNSUPPORTED, "ACP leaves of this size do not fit the tile scan's LDS");
-    PMLSH_HIP(hipFuncSetAttribute((const void*)acp_tile_scan_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    TileScan tscan(x, st);
+    tscan.prepare();
     int64_t tiles_total = 0, tiles_scanned = 0, n_cand_total = 0;
     for (int64_t e : found) tiles_total += (int64_t)(I.le[e] - I.lf[e]) * (I.le[e] - I.lf[e] - 1) / 2;
     std::vector<int2> tl;
@@ -1271,13 +1888,9 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
                 cand.alloc(cand_cap);
             }
             reset_counter();
-            hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for((int64_t)tl.size(), 1)),
-                               dim3(WG), lds, st, x->proj_hi, x->proj_lo, ppd.as<float>(), v,
-                               leaf_base, x->perm, n, L, tiles.as<int2>(), (int64_t)tl.size(), R2,
-                               limit, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
-                               cand.jj.as<uint32_t>(), cand_cap,
-                               static_cast<unsigned long long*>(dcount.p));
-            PMLSH_HIP(hipGetLastError());
+            tscan.scan(tiles.as<int2>(), (int64_t)tl.size(), R2, limit, cand.k0.as<uint32_t>(),
+                       cand.ii.as<uint32_t>(), cand.jj.as<uint32_t>(), cand_cap,
+                       static_cast<unsigned long long*>(dcount.p));
             nc = read_counter();
             if (nc <= cand_cap) break;
             if (nc > kMaxCand)
@@ -1317,7 +1930,8 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
 
     // 4. the k nearest verified pairs
     if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
-    pool_topk(x, pool, n_pool, k, top, dhist, dcount, out_pairs, out_dist, st);
+    pool_topk(x, pool, n_pool, k, pool_gamma(x, true), top, dhist, dcount, out_pairs, out_dist,
+              st);
     if (stats) {
         stats->t = plan.t;
         stats->ub = ub;
