@@ -65,14 +65,15 @@ def log(*a):
 
 
 def exact_knn_gpu(torch, D, Q, k, chunk=128):
-    """Ground-truth exact kNN (ids sorted by (distance, id)) for recall.
+    """Ground-truth exact kNN: ids sorted by (distance, id) and their FP64
+    distances, for recall and overall ratio.
 
     Measurement only, not part of the timed path: FP64 distances by the
     norm expansion on the GPU pick 4k candidates, which are re-ranked by FP64
     direct differences."""
     Dd = D.double()
     dn = (Dd * Dd).sum(1)
-    out = []
+    out, outd = [], []
     for s in range(0, Q.shape[0], chunk):
         q = Q[s:s + chunk].double()
         d2 = (q * q).sum(1, keepdim=True) + dn[None, :] - 2.0 * (q @ Dd.T)
@@ -85,7 +86,29 @@ def exact_knn_gpu(torch, D, Q, k, chunk=128):
         ex, cand = torch.gather(ex, 1, o), torch.gather(cand, 1, o)
         o = torch.argsort(ex, dim=1, stable=True)
         out.append(torch.gather(cand, 1, o)[:, :k])
-    return torch.cat(out)
+        outd.append(torch.gather(ex, 1, o)[:, :k].sqrt())
+    return torch.cat(out), torch.cat(outd)
+
+
+def overall_ratio(torch, D, Q, ids, truth_dist, chunk=256):
+    """Overall ratio of Eqs. 12 and 14 (Section 7.1): the mean over queries
+    and ranks of the returned point's distance over the exact i-th nearest
+    neighbour's distance, both in FP64 (ranks at exact distance 0 count 1
+    when the returned distance is 0 too)."""
+    k = ids.shape[1]
+    tot, cnt = 0.0, 0
+    for s in range(0, Q.shape[0], chunk):
+        e = min(Q.shape[0], s + chunk)
+        q = Q[s:e].double()
+        dd = D[ids[s:e].reshape(-1)].double().reshape(e - s, k, -1) - q[:, None, :]
+        got = (dd * dd).sum(2).sqrt()
+        ex = truth_dist[s:e, :k]
+        r = torch.where(ex > 0, got / torch.where(ex > 0, ex, torch.ones_like(ex)),
+                        torch.where(got > 0, torch.full_like(got, float("inf")),
+                                    torch.ones_like(got)))
+        tot += float(r.sum())
+        cnt += r.numel()
+    return tot / max(1, cnt)
 
 
 def recall_at_k(ids, truth):
@@ -101,33 +124,93 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(w, beta, r_min, budget_s=12.0, max_q=64):
-    """The FP64 oracle on this host's cores, bounded sample of the queries."""
+_CPU = {}     # workload and oracle projection, inherited by the forked CPU workers
+
+
+def _cpu_worker(task):
+    """One CPU-baseline worker: the oracle's Algorithm 2 for the queries
+    [q0, q1) of the headline workload, as long as the time budget lasts."""
     from oracle import ann as oann
-    from oracle import chi2
-    D, A, Q = w["D"], w["A"], w["Q"]
-    n = D.shape[0]
-    t = chi2.radius_factor(1 - CONF, A.shape[0])
-    B = chi2.ann_budget(beta, n, K)
-    Dp = oann.project(D, A)              # index construction, not timed
-    done = 0
+    q0, q1, t, budget, r_min, budget_s = task
+    D, Dp, Q, A = _CPU["D"], _CPU["Dp"], _CPU["Q"], _CPU["A"]
     t0 = time.perf_counter()
-    while done < max_q and time.perf_counter() - t0 < budget_s:
-        qp = oann.project(Q[done:done + 1], A)[0]
-        oann.query(D, Dp, Q[done], qp, K, C, t, B, r_min)
+    done = 0
+    for qi in range(q0, q1):
+        if done and time.perf_counter() - t0 > budget_s:
+            break
+        qp = oann.project(Q[qi:qi + 1], A)[0]
+        oann.query(D, Dp, Q[qi], qp, K, C, t, budget, r_min)
         done += 1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of the 10,000 queries at beta={beta}, "
-                      f"{dt:.1f} s on one host thread (FP64 NumPy, projection of D precomputed)"}
+    return done, time.perf_counter() - t0
+
+
+def start_cpu_pool(w, workers):
+    """Forks the CPU-baseline workers before anything touches the GPU, so the
+    children hold no GPU handle; they inherit the workload and the oracle's
+    FP64 projection of the data (index construction, not timed)."""
+    import multiprocessing as mp
+    from oracle import ann as oann
+    _CPU.update(D=w["D"], Q=w["Q"], A=w["A"], Dp=oann.project(w["D"], w["A"]))
+    return mp.get_context("fork").Pool(workers)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pool, workers, n, beta, r_min):
+    """The FP64 oracle (Algorithm 2 as in oracle/ann.py, NumPy) on this host:
+    one worker alone on the first queries (about 8 s), then every worker at
+    once on its own slice of the next queries (about 1.5 s each)."""
+    from oracle import chi2
+    t = chi2.radius_factor(1 - CONF, 15)
+    B = chi2.ann_budget(beta, n, K)
+    done1, dt1 = pool.apply(_cpu_worker, ((0, 64, t, B, r_min, 8.0),))
+    per = 16
+    tasks = [(64 + i * per, 64 + (i + 1) * per, t, B, r_min, 1.5) for i in range(workers)]
+    t0 = time.perf_counter()
+    res = pool.map(_cpu_worker, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    cpu_s = dt1 + sum(r[1] for r in res)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"value": round(done / wall, 2), "unit": "queries/s", "cores": workers,
+            "kind": "oracle",
+            "sample": (f"{done} queries (numbers 64..{64 + workers * per - 1} of the 10,000, "
+                       f"each worker taking its own slice) at beta={beta}, {workers} worker "
+                       f"processes at once, {wall:.1f} s wall; FP64 NumPy oracle, projection "
+                       f"of D precomputed; {cpu_s:.0f} s of CPU work in all"),
+            "one_core": {"value": round(done1 / dt1, 2), "unit": "queries/s",
+                         "sample": f"first {done1} of the 10,000 queries, {dt1:.1f} s"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": avail}
+
+
+FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 
 
 def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
     """(c,k)-ACP on 200,000 x 512 with 2,000 planted near-duplicate pairs:
-    time per call for each k (index built beforehand, data resident in HBM)
-    and whether the k pairs returned are the k closest planted pairs."""
+    time per call for each k (index built beforehand, data resident in HBM),
+    recall and overall ratio (Eqs. 12-14) against the exact k closest pairs
+    (the k closest planted pairs: each copy is ~0.023 from its original,
+    every other pair several units apart), and the roofline of the two
+    largest kernels from the library's per-stage HIP events: the self-join
+    against HBM (4 n d_pad bytes, every row read once, Section 8(d)'s seed
+    term) and the pair scan against the FP32 peak (3 x 16 flops per pair of
+    every leaf pair that survives the Mindist test)."""
     import synth
     w = synth.planted_pairs()
+    n, d = w["D"].shape
     D = torch.from_numpy(w["D"]).to(dev)
     A = torch.from_numpy(w["A"]).to(dev)
     torch.cuda.synchronize()
@@ -135,23 +218,56 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
     idx = pm.Index(D, A)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    L = idx.info()["leaf_size"]
+    d_pad = (d + 3) // 4 * 4
     Dn = w["D"].astype(np.float64)
     pl = w["pairs"]
     pd_ = np.sqrt(((Dn[pl[:, 0]] - Dn[pl[:, 1]]) ** 2).sum(1))
     order = np.lexsort((pl[:, 1], pl[:, 0], pd_))
+    acp_stages = ["acp_selfjoin", "acp_select", "acp_tiles", "acp_scan", "acp_verify",
+                  "acp_topk"]
     per_k = []
     for k in ks:
         pairs, dist, st = idx.acp(k, c=c)                     # warm-up
         torch.cuda.synchronize()
+        pm.ann_timing_read(reset=True)
+        pm.ann_timing_enable(True, stages=acp_stages)
         t0 = time.perf_counter()
         for _ in range(calls):
             pairs, dist, st = idx.acp(k, c=c)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / calls
-        correct = pairs.cpu().numpy().tolist() == pl[order[:k]].tolist()
-        log(f"ACP k={k}: {ms:.2f} ms per call, stats {st}, planted pairs found: {correct}")
+        pm.ann_timing_enable(False)
+        tm = pm.ann_timing_read(reset=True)
+        stage_ms = {s_: round(tm[s_]["ms"] / max(1, tm[s_]["launches"]), 4) for s_ in acp_stages
+                    if tm[s_]["launches"]}
+        got = pairs.cpu().numpy()
+        exact = pl[order[:k]]
+        correct = got.tolist() == exact.tolist()
+        gd = np.sqrt(((Dn[got[:, 0]] - Dn[got[:, 1]]) ** 2).sum(1))
+        ratio = float(np.mean(gd / pd_[order[:k]]))
+        rec = len(set(map(tuple, got.tolist())) & set(map(tuple, exact.tolist()))) / k
+        sj_bytes = 4.0 * n * d_pad
+        sj_ms = stage_ms.get("acp_selfjoin")
+        scan_flops = 48.0 * st["tiles_scanned"] * L * L
+        sc_ms = stage_ms.get("acp_scan")
+        roof = {
+            "selfjoin": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "work": sj_bytes, "per_launch_ms": sj_ms,
+                         "achieved": round(sj_bytes / (sj_ms * 1e-3) / 1e9, 1) if sj_ms else None},
+            "scan": {"bound": "alu", "unit": "TFLOP/s", "peak": FP32_PEAK_TFLOPS,
+                     "work": scan_flops, "per_launch_ms": sc_ms,
+                     "achieved": round(scan_flops / (sc_ms * 1e-3) / 1e12, 2) if sc_ms else None},
+        }
+        for r_ in roof.values():
+            r_["frac"] = round(r_["achieved"] / r_["peak"], 4) if r_["achieved"] else None
+        log(f"ACP k={k}: {ms:.3f} ms per call, stages {stage_ms}, recall {rec:.3f}, "
+            f"ratio {ratio:.6f}, roofline {roof}")
         per_k.append({"k": k, "ms_per_call": round(ms, 3), "calls": calls,
                       "k_closest_planted_pairs_returned": bool(correct),
+                      "recall": rec, "overall_ratio": round(ratio, 6),
+                      "stages_ms": stage_ms, "roofline": roof,
+                      "n_seed": int(st["n_seed"]), "ub": st["ub"],
                       "tiles_scanned": int(st["tiles_scanned"]),
                       "tiles_total": int(st["tiles_total"]), "candidates": int(st["n_cand"]),
                       "budget_T": int(st["budget"])})
@@ -267,8 +383,9 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
     torch.cuda.synchronize()
     sat_pl = nq_tot / (time.perf_counter() - t_0)
     log(f"saturation: server {sat_srv:.0f} queries/s, plain {sat_pl:.0f} queries/s")
-    # recall@k of the server's answers on a sample of the heaviest stream
-    rec = []
+    # recall@k and overall ratio (Eqs. 12-14) of the server's answers on a
+    # sample of the heaviest stream, against exact FP64 kNN
+    rec, rat = [], []
     Dd = D.double()
     for i in range(0, len(hs), max(1, len(hs) // 16)):
         ids, _ = hs[i].wait()
@@ -277,15 +394,20 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
         for j in range(0, e_ - s_, max(1, (e_ - s_) // 4)):
             q = Q[s_ + j].double()
             d2 = ((Dd - q) ** 2).sum(1)
-            true = set(torch.topk(d2, k, largest=False).indices.tolist())
-            rec.append(len(true & set(ids[j].tolist())) / k)
+            tv, ti = torch.topk(d2, k, largest=False)
+            rec.append(len(set(ti.tolist()) & set(ids[j].tolist())) / k)
+            got = d2[ids[j]].sqrt()
+            ex = tv.sqrt()
+            rat.append(float(torch.where(ex > 0, got / torch.where(ex > 0, ex, torch.ones_like(ex)),
+                                         torch.ones_like(ex)).mean()))
     del Dd
     return {"workload": "10,000,000 x 128 FP16 values in [0, 255], 10,000 centres, sigma 8; "
                         "Poisson requests of 1..4,096 queries, k in {1,10,50,100}, "
                         "c in {1.2,1.5,2.0}",
             "beta": beta, "build_s": round(build_s, 1), "per_rate": per_rate,
             "saturation_qps": {"server": round(sat_srv, 1), "plain": round(sat_pl, 1)},
-            "recall_sampled": round(float(np.mean(rec)), 4), "recall_samples": len(rec)}
+            "recall_sampled": round(float(np.mean(rec)), 4),
+            "overall_ratio_sampled": round(float(np.mean(rat)), 6), "recall_samples": len(rec)}
 
 
 def main():
@@ -313,15 +435,19 @@ def main():
                                    f"--gpus {args.gpus} is not supported"}))
         sys.exit(2)
 
-    import torch
-    import paper_2107_05537_amd as pm
     import synth
-
-    pm.load_library()
-    dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
     w = synth.headline()
     log(f"workload generated in {time.perf_counter() - t0:.1f} s")
+    # the CPU-baseline workers are forked before anything touches the GPU
+    cpu_workers = 16
+    pool = None if args.no_cpu else start_cpu_pool(w, cpu_workers)
+
+    import torch
+    import paper_2107_05537_amd as pm
+
+    pm.load_library()
+    dev = torch.device("cuda", 0)
     D = torch.from_numpy(w["D"]).to(dev)
     A = torch.from_numpy(w["A"]).to(dev)
     Q = torch.from_numpy(w["Q"]).to(dev)
@@ -339,7 +465,7 @@ def main():
     truth = None
     if not args.no_truth:
         t0 = time.perf_counter()
-        truth_all = exact_knn_gpu(torch, D, Q, 10 if args.no_ksweep else max(KS))
+        truth_all, truth_dist = exact_knn_gpu(torch, D, Q, 10 if args.no_ksweep else max(KS))
         truth = truth_all[:, :K]
         torch.cuda.synchronize()
         log(f"ground truth in {time.perf_counter() - t0:.1f} s")
@@ -375,9 +501,10 @@ def main():
     B = plan["budget"]
     r_min = idx.default_r_min(B)
 
-    # recall/ratio and algorithmic bytes at the operating point
+    # recall, overall ratio and the per-query work at the operating point
     run_all(beta)
     rec = recall_at_k(ids, truth) if truth is not None else None
+    ratio = overall_ratio(torch, D, Q, ids, truth_dist) if truth is not None else None
     st = stats.cpu().numpy().astype(np.int64)
     batch_scan = [float(st[s:e, 3].sum()) for s, e in batches]
     batch_cand = [float(st[s:e, 1].sum()) for s, e in batches]
@@ -446,39 +573,69 @@ def main():
         lat.append(ev0.elapsed_time(ev1))
     lat = np.array(lat)
 
-    # roofline of the dominant stage, from its live per-launch duration
+    # roofline of the dominant stage, from its live per-launch duration.
+    # `achieved` follows the per-query algorithmic work of Section 8(d):
+    #   bytes(q) = 4d + 64 N_scan + 116 N_node + 8 N_ball + (4d + 8) |C| + 12k
+    # of which the finishing kernel (budget cut, verification, top-k) moves
+    # 8 N_ball + (4d + 8) |C| + 4d + 12k (N_ball >= |C|: |C| is used, a lower
+    # bound, as the pool size is not reported per query), the filter 64 N_scan
+    # bytes, the chunk-distance stages the bf16 distance row. The finishing
+    # kernel reads FP16 rows where the verification allows it, so its own
+    # byte model is reported beside it ("fp16_rows").
     d_pad = (d + 3) // 4 * 4
+    d16 = (d + 7) // 8 * 8
     launches = max(1, stages[dom]["launches"])
     per_launch_ms = stages[dom]["ms"] / launches
+    q_l = p_queries / launches                       # queries per probed launch
+    c_l = cand_rows / launches                       # members of C per launch
+    s_l = scan_pts / launches                        # points scanned per launch
+
+    def rate(work, unit):
+        return work / (per_launch_ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
+
+    models = {}
     if dom == "filter":
-        # a 16-term dot product (32 flops) per point of every chunk that
-        # passes the query's chunk-ball test, on the FP16 matrix cores
-        work = 32.0 * scan_pts / launches
-        achieved = work / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2),
-                "peak": FP16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP16_MFMA_PEAK_TFLOPS, 4)}
+        work = 64.0 * s_l
+        models["mfma_flops"] = {"work": 32.0 * s_l, "unit": "TFLOP/s",
+                                "peak": FP16_MFMA_PEAK_TFLOPS}
     elif dom in ("dist", "tau"):
-        # the bf16 chunk-distance row of every query, written and read
         ldc = ((n + 63) // 64 + 15) // 16 * 16
-        work = 2.0 * ldc * p_queries / launches
-        achieved = work / (per_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        work = 2.0 * ldc * q_l
     else:
-        # bounded verification: the FP16 row and the 64 B projection row of
-        # every member of C, the FP32 rows of the k answers, the query and
-        # the output
-        d16 = (d + 7) // 8 * 8
-        work = ((2.0 * d16 + 64.0) * cand_rows
-                + (4.0 * d_pad * K + 4 * d + 12 * K) * p_queries) / launches
-        achieved = work / (per_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        work = (8.0 * c_l + (4.0 * d + 8.0) * c_l + (4.0 * d + 12.0 * K) * q_l)
+        models["fp16_rows"] = {"work": (2.0 * d16 + 64.0) * c_l
+                               + (4.0 * d_pad * K + 4 * d + 12 * K) * q_l,
+                               "unit": "GB/s", "peak": HBM_PEAK_GBS}
+    achieved = rate(work, "GB/s")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "model": "Section 8(d) algorithmic bytes"}
+    for m_ in models.values():
+        m_["achieved"] = round(rate(m_["work"], m_["unit"]), 2)
+        m_["frac"] = round(m_["achieved"] / m_["peak"], 4)
+    roof["other_models"] = models
     roof["kernel"] = {"dist": "dist_kernel", "tau": "tau_kernel", "filter": "scan_kernel",
                       "finish": "finish_kernel", "per_query": "ann_kernel"}[dom]
     roof["per_launch_ms"] = round(per_launch_ms, 4)
     roof["work_per_launch"] = work
+    roof["queries_per_launch"] = q_l
+
+    # the whole step under the same model (every query of a batch tests all
+    # n/64 chunk balls in the chunk-distance pass: N_node = n/64 per query)
+    n_chunk = (n + 63) // 64
+    nq_all = st.shape[0]
+    wq = {"N_scan": float(st[:, 3].mean()), "C": float(st[:, 1].mean()),
+          "N_ball_lower_bound": float(st[:, 1].mean()), "N_node": n_chunk,
+          "rounds": float(st[:, 0].mean()),
+          "exit_kinds": np.bincount(st[:, 2], minlength=3)[1:].tolist()}
+    terms = {"query": 4.0 * d, "scan": 64.0 * wq["N_scan"], "nodes": 116.0 * n_chunk,
+             "ball": 8.0 * wq["C"], "verify": (4.0 * d + 8.0) * wq["C"], "out": 12.0 * K}
+    wq["bytes_8d"] = {k_: round(v_, 1) for k_, v_ in terms.items()}
+    wq["bytes_8d_total"] = round(sum(terms.values()), 1)
+    wq["step_gbs_8d"] = round(sum(terms.values()) * queries / wall / 1e9, 1)
+    wq["step_gbs_8d_without_nodes"] = round((sum(terms.values()) - terms["nodes"]) * queries
+                                            / wall / 1e9, 1)
+    log(f"work per query: {wq}")
 
     traffic = None
     if os.path.exists(PMC_FILE):
@@ -523,12 +680,17 @@ def main():
             timed(k, b_k, rmin_k, 10, ids_k, dist_k, stats)          # warm-up
             wall_k, q_k = timed(k, b_k, rmin_k, args.steps, ids_k, dist_k, stats)
             log(f"k={k}: beta={b_k:g} recall@{k}={rec_k:.4f} {q_k / wall_k:.0f} queries/s")
+            ratio_k = overall_ratio(torch, D, Q, ids_k, truth_dist[:, :k])
             ksweep.append({"k": k, "beta": b_k, "budget_B": B_k, f"recall@{k}": round(rec_k, 4),
+                           "overall_ratio": round(ratio_k, 6),
                            "queries_per_s": round(q_k / wall_k, 1)})
 
     cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(w, beta, r_min)
+    if pool is not None:
+        cpu = cpu_baseline(pool, cpu_workers, n, beta, r_min)
+        pool.close()
+        pool.join()
+        log(f"cpu baseline: {cpu}")
     acp = None
     serving = None
     if not (args.no_acp and args.no_serving):
@@ -559,6 +721,8 @@ def main():
                    "beta": beta, "budget_B": B, "r_min": r_min,
                    "batch": BATCH, "streams": len(streams), "parallelism": "single GPU"},
         "recall@10": round(rec, 4) if rec is not None else None,
+        "overall_ratio": round(ratio, 6) if ratio is not None else None,
+        "work_per_query": wq,
         "sweep": sweep,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),

@@ -118,7 +118,10 @@ struct NodeView {
 };
 
 // Mindist of Eq. 11: the larger of the pivot-ring gap and the centre gap.
-__device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b) {
+// Once the centre gap exceeds `limit` the rings cannot change whether the
+// result exceeds it, and they are not read.
+__device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b,
+                                         float limit = INFINITY) {
     float acc = 0.f;
 #pragma unroll
     for (int j = 0; j < MP; ++j) {
@@ -126,6 +129,7 @@ __device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b
         acc = fmaf(t, t, acc);
     }
     float m = sqrtf(acc) - v.rad[a] - v.rad[b];
+    if (m > limit) return m;
     for (int i = 0; i < v.s; ++i) {
         const int64_t oa = (int64_t)i * v.n_nodes + a, ob = (int64_t)i * v.n_nodes + b;
         m = fmaxf(m, v.hrmin[ob] - v.hrmax[oa]);
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(WG) void acp_tile_filter_kernel(
         const int64_t e2 = s0 + threadIdx.x;
         bool keep = false;
         if (e2 < n_leaves)
-            keep = e2 == e1 || mindist(v, leaf_base + e1, leaf_base + e2) <= limit;
+            keep = e2 == e1 || mindist(v, leaf_base + e1, leaf_base + e2, limit) <= limit;
         const uint64_t m = __ballot(keep);
         if (lane == 0) wcount[wave] = __popcll(m);
         __syncthreads();
@@ -446,10 +450,31 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
     float h1[MP], l1[MP];
     int held = -1, ca = 0;
     uint32_t id1 = 0;
+    // the next tile's index, centre and sorted PDs are loaded while the
+    // current one is scanned
+    int2 nt = t_beg < t_end ? tiles[t_beg] : make_int2(0, 0);
+    float ncen[MP], ny = 0.f;
+    int nsb = 0;
+    auto fetch = [&](int e) {
+        const int64_t node = leaf_base + e;
+#pragma unroll
+        for (int j = 0; j < MP; ++j) ncen[j] = v.cen[(int64_t)j * v.n_nodes + node];
+        ny = spd[(int64_t)e * 64 + lane];
+        nsb = sidx[(int64_t)e * 64 + lane];
+    };
+    if (t_beg < t_end) fetch(__builtin_amdgcn_readfirstlane(nt.y));
     for (int64_t t = t_beg; t < t_end; ++t) {
-        const int2 tl = tiles[t];
-        const int e1 = __builtin_amdgcn_readfirstlane(tl.x);
-        const int e2 = __builtin_amdgcn_readfirstlane(tl.y);
+        const int e1 = __builtin_amdgcn_readfirstlane(nt.x);
+        const int e2 = __builtin_amdgcn_readfirstlane(nt.y);
+        float cen[MP];
+#pragma unroll
+        for (int j = 0; j < MP; ++j) cen[j] = ncen[j];
+        const float y = ny;
+        const int sb = nsb;
+        if (t + 1 < t_end) {
+            nt = tiles[t + 1];
+            fetch(__builtin_amdgcn_readfirstlane(nt.y));
+        }
         const int64_t a0 = (int64_t)e1 * L, b0 = (int64_t)e2 * L;
         if (e1 != held) {
             ca = (int)(n - a0 < L ? n - a0 : L);
@@ -468,16 +493,13 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
         const int cb = (int)(n - b0 < L ? n - b0 : L);
         const bool diag = e1 == e2;
         // 1. distance to the centre of e2, interval of PD(b)
-        const int64_t node2 = leaf_base + e2;
         float acc = 0.f;
 #pragma unroll
         for (int j = 0; j < MP; ++j) {
-            const float dt = __fadd_rn(__fsub_rn(h1[j], v.cen[(int64_t)j * v.n_nodes + node2]), l1[j]);
+            const float dt = __fadd_rn(__fsub_rn(h1[j], cen[j]), l1[j]);
             acc = __fmaf_rn(dt, dt, acc);
         }
         const float x = sqrtf(acc);
-        const float y = spd[(int64_t)e2 * 64 + lane];
-        const int sb = sidx[(int64_t)e2 * 64 + lane];
         // |x - y| - 32u (x + y) < Rlim implies y in (lov, hiv) in exact
         // arithmetic; the bounds are widened by 1e-6 (x + Rlim), far more than
         // the FP32 rounding of that test and of the bounds themselves
@@ -573,6 +595,76 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
 }
 
 // ---------------------------------------------------------------- seeds
+// Device-side radix select of the need-th smallest of `count` 32-bit keys:
+// the state holds the bits resolved so far (prefix, pbits) and the rank
+// still to find among the keys with that prefix. A histogram pass counts the
+// next `width` bits of the keys that carry the prefix; the pick kernel finds
+// the bin holding the rank, extends the prefix, and clears the histogram.
+struct SelState {
+    uint32_t prefix;
+    int32_t pbits;
+    int64_t need;
+};
+
+// Rank selection in a histogram of NB bins by a workgroup of WG threads:
+// the bin b with cum(b) < need <= cum(b) + h[b] (cum(b) = the count of the
+// bins below b) and cum(b). Thread t sums bins [8t, 8t + 8), a block-wide
+// inclusive scan of those sums finds the one thread whose range holds the
+// rank, which walks its eight bins.
+__device__ void pick_bin(const uint32_t* h, int64_t need, int* out_bin, int64_t* out_cum) {
+    __shared__ int64_t wtot[WG / 64];
+    const int per = NB / WG, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t v = 0;
+    for (int i = 0; i < per; ++i) v += h[threadIdx.x * per + i];
+    int64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) incl += wtot[w];
+    const int64_t excl = incl - v;
+    if (excl < need && incl >= need) {
+        int64_t cum = excl;
+        int bin = threadIdx.x * per + per - 1;
+        for (int i = 0; i < per; ++i) {
+            const int64_t c = h[threadIdx.x * per + i];
+            if (cum + c >= need) { bin = threadIdx.x * per + i; break; }
+            cum += c;
+        }
+        *out_bin = bin;
+        *out_cum = cum;
+    }
+    __syncthreads();
+}
+
+// The pick step (one workgroup of WG threads): the bin of the device-wide
+// histogram holding rank `need`, the prefix extended by it, the rank within
+// it; the histogram is cleared for the next pass.
+__global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__ ghist,
+                                                          SelState* __restrict__ state,
+                                                          int width) {
+    __shared__ uint32_t h[NB];
+    __shared__ int s_bin;
+    __shared__ int64_t s_cum;
+    for (int i = threadIdx.x; i < NB; i += WG) h[i] = ghist[i];
+    if (threadIdx.x == 0) {
+        s_bin = (1 << width) - 1;       // unreachable while need <= count
+        s_cum = 0;
+    }
+    __syncthreads();
+    const int64_t need = state->need;
+    pick_bin(h, need, &s_bin, &s_cum);
+    if (threadIdx.x == 0) {
+        state->prefix = (state->prefix << width) | (uint32_t)s_bin;
+        state->pbits += width;
+        state->need = need - s_cum;
+    }
+    for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
+}
+
 // Self-join of leaves of at most 64 points, one workgroup per leaf: the
 // squared distance of every pair a < b, FP32 direct differences. The
 // triangle of 4 x 4 point blocks (136 blocks) is split over two halves of
@@ -682,17 +774,6 @@ __global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
         if (hist[i]) atomicAdd(&ghist[i], hist[i]);
 }
 
-// Device-side radix select of the need-th smallest of `count` 32-bit keys:
-// the state holds the bits resolved so far (prefix, pbits) and the rank
-// still to find among the keys with that prefix. A histogram pass counts the
-// next `width` bits of the keys that carry the prefix; the pick kernel finds
-// the bin holding the rank, extends the prefix, and clears the histogram.
-struct SelState {
-    uint32_t prefix;
-    int32_t pbits;
-    int64_t need;
-};
-
 __global__ __launch_bounds__(WG) void acp_sel_hist_kernel(
     const uint32_t* __restrict__ keys, int64_t count, const SelState* __restrict__ state,
     int shift, int width, uint32_t* __restrict__ ghist) {
@@ -710,39 +791,6 @@ __global__ __launch_bounds__(WG) void acp_sel_hist_kernel(
     __syncthreads();
     for (int i = threadIdx.x; i < NB; i += WG)
         if (h[i]) atomicAdd(&ghist[i], h[i]);
-}
-
-__global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__ ghist,
-                                                          SelState* __restrict__ state,
-                                                          int width) {
-    __shared__ uint32_t tot[WG];
-    const int per = NB / WG;                 // 8 bins per thread
-    uint32_t mine = 0;
-    for (int i = 0; i < per; ++i) mine += ghist[threadIdx.x * per + i];
-    tot[threadIdx.x] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t need = state->need;
-        int64_t cum = 0;
-        int bin = -1;
-        for (int th = 0; th < WG && bin < 0; ++th) {
-            if (cum + tot[th] >= need) {
-                for (int i = 0; i < per; ++i) {
-                    const uint32_t c = ghist[th * per + i];
-                    if (cum + c >= need) { bin = th * per + i; break; }
-                    cum += c;
-                }
-            } else {
-                cum += tot[th];
-            }
-        }
-        if (bin < 0) bin = (1 << width) - 1;   // unreachable while need <= count
-        state->prefix = (state->prefix << width) | (uint32_t)bin;
-        state->pbits += width;
-        state->need = need - cum;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
 }
 
 // Within-leaf pairs whose distance bits are at most lim (the band of the
@@ -992,6 +1040,127 @@ __global__ __launch_bounds__(WG) void acp_final64_kernel(
     }
 }
 
+constexpr int kSmallPool = 16384;   // pools the one-workgroup top-k takes
+constexpr size_t kSmallTopkLds =
+    (size_t)kSmallPool * 4 + (size_t)NB * 4 + (size_t)kTopBand * 8 + (size_t)kTopBand * 8;
+
+// Top-k of a pool of at most kSmallPool pairs in one workgroup: the k-th
+// smallest FP32 key by radix select in LDS (11, 11, 10 bits), the band
+// kth (1 + band) rounded up one ulp, and the band's order in FP64 as in
+// acp_final64_kernel. status[0] receives the band size m; when m exceeds
+// kTopBand nothing is written and the caller falls back to the FP32 order.
+__global__ __launch_bounds__(WG) void acp_topk_small_kernel(
+    const uint32_t* __restrict__ k0, const uint32_t* __restrict__ ii,
+    const uint32_t* __restrict__ jj, int count, int k, double band,
+    const float* __restrict__ data, int d_pad, const int32_t* __restrict__ inv_perm,
+    int64_t* __restrict__ out_pairs, float* __restrict__ out_dist, int* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* dk = reinterpret_cast<double*>(smem);
+    uint64_t* pk = reinterpret_cast<uint64_t*>(dk + kTopBand);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(pk + kTopBand);
+    uint32_t* h = keys + kSmallPool;
+    __shared__ uint32_t s_prefix;
+    __shared__ int s_pbits, s_need, s_m, s_bin;
+    __shared__ int64_t s_cum;
+    for (int e = threadIdx.x; e < count; e += WG) keys[e] = k0[e];
+    if (threadIdx.x == 0) {
+        s_prefix = 0;
+        s_pbits = 0;
+        s_need = k;
+        s_m = 0;
+    }
+    const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int i = threadIdx.x; i < NB; i += WG) h[i] = 0;
+        __syncthreads();
+        const uint32_t prefix = s_prefix;
+        const int pbits = s_pbits;
+        const uint32_t mask = (1u << widths[pass]) - 1u;
+        for (int e = threadIdx.x; e < count; e += WG) {
+            const uint32_t x = keys[e];
+            if (pbits == 0 || (x >> (32 - pbits)) == prefix)
+                atomicAdd(&h[(x >> shifts[pass]) & mask], 1u);
+        }
+        __syncthreads();
+        const int need = s_need;
+        if (threadIdx.x == 0) {
+            s_bin = (int)mask;          // unreachable while need <= count
+            s_cum = 0;
+        }
+        __syncthreads();
+        pick_bin(h, need, &s_bin, &s_cum);
+        if (threadIdx.x == 0) {
+            s_prefix = (s_prefix << widths[pass]) | (uint32_t)s_bin;
+            s_pbits += widths[pass];
+            s_need = need - (int)s_cum;
+        }
+        __syncthreads();
+    }
+    const float kth = __uint_as_float(s_prefix);
+    const uint32_t lim = __float_as_uint(nextafterf((float)((double)kth * (1.0 + band)), INFINITY));
+    for (int e = threadIdx.x; e < count; e += WG) {
+        if (keys[e] <= lim) {
+            const int slot = atomicAdd(&s_m, 1);
+            if (slot < kTopBand) pk[slot] = ((uint64_t)ii[e] << 32) | jj[e];
+        }
+    }
+    __syncthreads();
+    const int m = s_m;
+    if (threadIdx.x == 0) *status = m;
+    if (m > kTopBand) return;
+    const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    const int d4 = d_pad >> 2;
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int base = 0; base < P; base += WG / 16) {
+        const int e = base + g;
+        double acc = 0.0;
+        if (e < m) {
+            const uint64_t key = pk[e];
+            const float4* r1 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[(uint32_t)(key >> 32)] * d_pad);
+            const float4* r2 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[(uint32_t)key] * d_pad);
+            for (int c = l16; c < d4; c += 16) {
+                const float4 x = r1[c], y = r2[c];
+                double t;
+                t = (double)x.x - (double)y.x; acc = fma(t, t, acc);
+                t = (double)x.y - (double)y.y; acc = fma(t, t, acc);
+                t = (double)x.z - (double)y.z; acc = fma(t, t, acc);
+                t = (double)x.w - (double)y.w; acc = fma(t, t, acc);
+            }
+        }
+        acc += __shfl_xor(acc, 8, 16);
+        acc += __shfl_xor(acc, 4, 16);
+        acc += __shfl_xor(acc, 2, 16);
+        acc += __shfl_xor(acc, 1, 16);
+        if (l16 == 0 && e < P) {
+            dk[e] = e < m ? acc : INFINITY;
+            if (e >= m) pk[e] = ~0ull;
+        }
+    }
+    __syncthreads();
+    for (int sz = 2; sz <= P; sz <<= 1) {
+        for (int j = sz >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += WG) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & sz) == 0;
+                    const bool gt = dk[i] > dk[ixj] || (dk[i] == dk[ixj] && pk[i] > pk[ixj]);
+                    if (gt == up) {
+                        const double td = dk[i]; dk[i] = dk[ixj]; dk[ixj] = td;
+                        const uint64_t tp = pk[i]; pk[i] = pk[ixj]; pk[ixj] = tp;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < k; i += WG) {
+        out_pairs[2 * i] = (int64_t)(pk[i] >> 32);
+        out_pairs[2 * i + 1] = (int64_t)(pk[i] & 0xffffffffull);
+        out_dist[i] = (float)sqrt(dk[i]);
+    }
+}
+
 // The pool pairs whose FP32 distance bits are at most the band limit of the
 // selected k-th key (state->prefix): kth (1 + band), rounded up one ulp, the
 // same limit pool_topk states on the host.
@@ -1118,11 +1287,15 @@ SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, in
 // host round trip): three histogram passes of 11, 11 and 10 bits, each
 // followed by the pick kernel; the key is left in state->prefix and ghist is
 // left cleared. With first_done the first pass (top 11 bits) is already in
-// ghist; otherwise ghist must be clear on entry.
-void device_select(const uint32_t* keys, int64_t count, int64_t need, SelState* state,
-                   uint32_t* ghist, bool first_done, hipStream_t st) {
+// ghist (the self-join adds it); otherwise ghist must be clear on entry.
+void sel_init(SelState* state, int64_t need, hipStream_t st) {
     hipLaunchKernelGGL(acp_sel_init_kernel, dim3(1), dim3(1), 0, st, state, need);
     PMLSH_HIP(hipGetLastError());
+}
+
+void device_select(const uint32_t* keys, int64_t count, int64_t need, SelState* state,
+                   uint32_t* ghist, bool first_done, hipStream_t st) {
+    sel_init(state, need, st);
     const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
     for (int pass = 0; pass < 3; ++pass) {
         if (pass > 0 || !first_done) {
@@ -1249,6 +1422,23 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
     DevBuf dstate(x, S_STATE), ghist(x, S_GHIST);
     dstate.alloc(sizeof(SelState));
     ghist.alloc(NB * sizeof(uint32_t));
+    if (n_pool <= kSmallPool) {
+        // one workgroup: select, band and FP64 order; falls through on mass ties
+        PMLSH_HIP(hipFuncSetAttribute((const void*)acp_topk_small_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kSmallTopkLds));
+        hipLaunchKernelGGL(acp_topk_small_kernel, dim3(1), dim3(WG), kSmallTopkLds, st,
+                           pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                           pool.jj.as<uint32_t>(), (int)n_pool, k, 4.0 * gamma, x->data,
+                           x->d_pad, x->inv_perm, out_pairs, out_dist,
+                           static_cast<int*>(dcount.p));
+        PMLSH_HIP(hipGetLastError());
+        int m = 0;
+        PMLSH_HIP(hipMemcpyAsync(&m, dcount.p, sizeof(m), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        if (m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
+        if (m <= kTopBand) return;
+    }
     PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
     device_select(pool.k0.as<uint32_t>(), n_pool, k, dstate.as<SelState>(),
                   ghist.as<uint32_t>(), false, st);
