@@ -116,12 +116,24 @@ def recall_at_k(ids, truth):
     return float((hit / truth.shape[1]).mean())
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("ann.hip", "project.hip", "internal.hpp")):
     h = hashlib.sha256()
-    for f in ("ann.hip", "project.hip", "internal.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2107_05537_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel, sha_key, files):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary in
+    profiles/, when it was taken on the current kernel sources."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    with open(PMC_FILE) as fh:
+        pmc = json.load(fh)
+    if pmc.get(sha_key) != kernel_source_hash(files):
+        return None
+    return pmc.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 _CPU = {}     # workload and oracle projection, inherited by the forked CPU workers
@@ -261,6 +273,14 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
         }
         for r_ in roof.values():
             r_["frac"] = round(r_["achieved"] / r_["peak"], 4) if r_["achieved"] else None
+        roof["selfjoin"]["flops"] = 3.0 * d * st["n_seed"]
+        roof["selfjoin"]["flops_achieved_tflops"] = (
+            round(roof["selfjoin"]["flops"] / (sj_ms * 1e-3) / 1e12, 2) if sj_ms else None)
+        acp_files = ("acp.hip", "internal.hpp")
+        roof["selfjoin"]["traffic"] = pmc_traffic("acp_seed_join_kernel", "acp_source_sha",
+                                                  acp_files)
+        roof["scan"]["traffic"] = pmc_traffic("acp_tile_scan_wave_kernel", "acp_source_sha",
+                                              acp_files)
         log(f"ACP k={k}: {ms:.3f} ms per call, stages {stage_ms}, recall {rec:.3f}, "
             f"ratio {ratio:.6f}, roofline {roof}")
         per_k.append({"k": k, "ms_per_call": round(ms, 3), "calls": calls,
@@ -637,14 +657,11 @@ def main():
                                             / wall / 1e9, 1)
     log(f"work per query: {wq}")
 
-    traffic = None
-    if os.path.exists(PMC_FILE):
-        with open(PMC_FILE) as fh:
-            pmc = json.load(fh)
-        kern = pmc.get("kernels", {}).get(roof["kernel"])
-        if (pmc.get("kernel_source_sha") == kernel_source_hash() and kern
-                and pmc.get("beta") == beta):
-            traffic = kern.get("hbm_bytes_per_launch")
+    traffic = pmc_traffic(roof["kernel"], "kernel_source_sha",
+                          ("ann.hip", "project.hip", "internal.hpp"))
+    with open(PMC_FILE) as fh:
+        if json.load(fh).get("beta") != beta:
+            traffic = None
     roof["traffic"] = traffic
 
     if args.calib_copy:
@@ -730,7 +747,7 @@ def main():
         "other_k": ksweep,
         "roofline": roof,
         "stages_ms_per_batch": {k: round(v["ms"] / max(1, v["launches"]), 4)
-                                for k, v in warm.items()},
+                                for k, v in warm.items() if not k.startswith("acp")},
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
         "acp": acp,
