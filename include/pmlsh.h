@@ -158,6 +158,37 @@ int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq,
               void* stream);
 
 /*
+ * (c,k)-ANN, Algorithm 2 (Section 5.2), for a batch whose queries carry
+ * their own parameters: query i is answered exactly as pmlsh_ann would
+ * answer it alone with k = args[i].k, c = args[i].c, confidence =
+ * args[i].confidence, beta = args[i].beta and r_min = args[i].r_min (each
+ * as in pmlsh_ann). Algorithm 2 is run per query, so one launch serves all
+ * of them and no answer depends on the others.
+ *   args        host array of nq entries.
+ *   out_stride  row stride of out_ids / out_dist, >= the largest k; query
+ *               i's answer is written to row i, the first args[i].k entries.
+ *   out_ids     nq x out_stride int64 device pointer; out_dist the same FP32.
+ *   out_stats   optional nq x 4 int32 device pointer, as for pmlsh_ann.
+ * The per-query parameters are copied to the device on `stream`; the call
+ * returns after that copy (it waits for the work queued on the stream before
+ * it) and leaves the search itself asynchronous. Errors: EINVAL (an entry or
+ * out_stride invalid, naming the entry), EUNSUPPORTED (a k above
+ * PMLSH_MAX_K), ENOMEM, EDEVICE.
+ */
+typedef struct {
+    int32_t k;
+    int32_t reserved;
+    double c;
+    double confidence;
+    double beta;
+    double r_min;
+} pmlsh_query_args;
+
+int pmlsh_ann_mixed(const pmlsh_index* index, const float* queries, int64_t nq,
+                    const pmlsh_query_args* args, int32_t out_stride, int64_t* out_ids,
+                    float* out_dist, int32_t* out_stats, void* stream);
+
+/*
  * pmlsh_ann for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Arguments, results and errors are those of pmlsh_ann; the same kernels
@@ -429,10 +460,11 @@ int pmlsh_ann_timing_enable(int stage_mask);
 int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
 
 /*
- * Test aid: process-wide switches of the group filter of the ANN bound kernel
- * (the minima of 64-chunk groups that rule out the groups unable to hold a
- * chunk chosen for tau or a chunk passing Eq. 5). Results are the same under
- * every setting; only the work differs.
+ * Test aid: process-wide switches of the ANN path: the group filter of the
+ * bound kernel (the minima of 64-chunk groups that rule out the groups unable
+ * to hold a chunk chosen for tau or a chunk passing Eq. 5), and the choice of
+ * the plain FP32 per-query path for whole launches. Results are the same
+ * under every setting; only the work differs.
  *   PMLSH_TUNE_GROUP_LIST         most groups (and 256-chunk blocks of the
  *                                 Eq. 5 test) one query lists, 0..2048
  *                                 (default 2048); when more qualify, or at 0,
@@ -440,12 +472,18 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
  *   PMLSH_TUNE_GROUP_MINIMA_LDS   1 (default): the group minima are copied to
  *                                 LDS when they fit (about 28,000 groups);
  *                                 0: read from HBM in every pass
+ *   PMLSH_TUNE_FP32_PATH          0 (default): the batched path (FP16 matrix-core
+ *                                 filter, FP16 verification rows with bounds);
+ *                                 1: every query of a launch takes the per-query
+ *                                 kernel (PM-tree walk with Eq. 5, FP32 projected
+ *                                 and exact distances), the plain FP32 path
  * value -1 restores the default; a key or value out of range: PMLSH_EINVAL.
  * A call running while a switch changes may see either setting.
  */
 #define PMLSH_TUNE_GROUP_LIST 0
 #define PMLSH_TUNE_GROUP_MINIMA_LDS 1
-#define PMLSH_N_TUNE 2
+#define PMLSH_TUNE_FP32_PATH 2
+#define PMLSH_N_TUNE 3
 
 int pmlsh_tune(int key, int64_t value);
 

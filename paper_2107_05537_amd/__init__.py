@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = ["Index", "Server", "PmlshError", "plan_params", "library_path", "load_library",
            "ann_timing_enable", "ann_timing_read", "tune", "TUNE_GROUP_LIST",
-           "TUNE_GROUP_MINIMA_LDS"]
+           "TUNE_GROUP_MINIMA_LDS", "TUNE_FP32_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libpmlsh.so")
@@ -63,6 +63,12 @@ class _Info(ctypes.Structure):
                 ("sample_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
+class _QueryArgs(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("reserved", ctypes.c_int32), ("c", ctypes.c_double),
+                ("confidence", ctypes.c_double), ("beta", ctypes.c_double),
+                ("r_min", ctypes.c_double)]
+
+
 class _ServerArgs(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_int64)]
@@ -97,6 +103,10 @@ SIGNATURES = {
                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pmlsh_ann_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.POINTER(_QueryArgs), ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "pmlsh_ann_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
@@ -192,6 +202,7 @@ def plan_params(n: int, m: int, k: int, c: float, confidence: float, beta: float
 
 TUNE_GROUP_LIST = 0          # most 64-chunk groups the ANN bound lists per query
 TUNE_GROUP_MINIMA_LDS = 1    # group minima in LDS (1) or read from HBM (0)
+TUNE_FP32_PATH = 2           # 1: whole launches on the plain FP32 per-query kernel
 
 
 def tune(key: int, value: int = -1):
@@ -322,6 +333,34 @@ class Index:
             self._h, queries.data_ptr(), queries.shape[0], k, c, confidence, beta, r_min,
             ids.data_ptr(), dist.data_ptr(), stats.data_ptr() if stats is not None else None,
             _stream_handle(queries.device)))
+
+    def ann_mixed(self, queries, params, out_stride: int = 0, stats: bool = False):
+        """(c,k)-ANN with per-query parameters: params is a list of dicts (one
+        per row of `queries`) with keys k and optionally c (1.5), confidence
+        (1 - 1/e), beta (-1) and r_min (0). Returns ids int64 and dist float32
+        tensors of shape (nq, out_stride) (out_stride 0: the largest k); row i
+        holds query i's answer in its first k entries. Enqueued on the current
+        stream."""
+        torch = _torch()
+        Q = _require_gpu_f32("queries", queries)
+        if Q.ndim != 2 or Q.shape[1] != self.d:
+            raise ValueError(f"queries must be (nq, {self.d})")
+        nq = Q.shape[0]
+        if len(params) != nq:
+            raise ValueError("one parameter set per query")
+        arr = (_QueryArgs * max(1, nq))()
+        for i, p in enumerate(params):
+            arr[i] = _QueryArgs(int(p["k"]), 0, float(p.get("c", 1.5)),
+                                float(p.get("confidence", 1 - 1 / math.e)),
+                                float(p.get("beta", -1.0)), float(p.get("r_min", 0.0)))
+        stride = out_stride if out_stride > 0 else max([int(p["k"]) for p in params] or [1])
+        ids = torch.full((nq, stride), -1, dtype=torch.int64, device=Q.device)
+        dist = torch.full((nq, stride), float("inf"), dtype=torch.float32, device=Q.device)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=Q.device) if stats else None
+        _check(load_library().pmlsh_ann_mixed(
+            self._h, Q.data_ptr(), nq, arr, stride, ids.data_ptr(), dist.data_ptr(),
+            st.data_ptr() if st is not None else None, _stream_handle(Q.device)))
+        return (ids, dist, st) if stats else (ids, dist)
 
     def ann_noalloc(self, queries, k, c, confidence, beta, r_min, ids, dist, stats=None):
         """pmlsh_ann_noalloc into caller-provided GPU tensors: the workspace is

@@ -68,9 +68,14 @@ struct AnnArgs {
     const float* qp;
     const float* qp_lo;         // FP32 rounding of (projection - qp)
     const float* proj_lo;       // the same for the data, leaf order
+    // Algorithm 2's parameters, the same for every query of the launch, or
+    // per query from qpar (then k and budget here are the largest of the
+    // launch and serve as strides of the per-query workspace)
     int k;
     int32_t budget;
     double c, t, r_min;
+    const AnnQueryParams* qpar;
+    int out_stride;             // row stride of out_ids / out_dist (>= every k)
     int max_rounds;             // range queries per query at most ((r,c)-BC: 1)
     int32_t* ws_front;
     int32_t* ws_cpos;
@@ -132,6 +137,18 @@ struct Smem {
 static_assert(offsetof(Smem, skey) % 16 == 0, "row area must be 16-byte aligned");
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// The parameters of query qi of the launch.
+__device__ __forceinline__ AnnQueryParams query_params(const AnnArgs& a, int64_t qi) {
+    if (a.qpar) return a.qpar[qi];
+    AnnQueryParams p;
+    p.c = a.c;
+    p.t = a.t;
+    p.r_min = a.r_min;
+    p.k = a.k;
+    p.budget = a.budget;
+    return p;
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     return (1ull << lane_id()) - 1ull;
@@ -767,6 +784,7 @@ constexpr int kRerankCap = 512;   // members the FP64 re-rank takes at most
 template <class Src>
 __device__ bool rerank_topk64(const AnnArgs& a, int64_t qi, const float* qs, const int32_t* cpos,
                               int cnt, float kth32, Src&& src, Smem& sh) {
+    const int k = query_params(a, qi).k;
     double* d64 = reinterpret_cast<double*>(sh.hist);
     int32_t* mem = reinterpret_cast<int32_t*>(d64 + kRerankCap);
     int32_t* pid = mem + kRerankCap;
@@ -833,9 +851,9 @@ __device__ bool rerank_topk64(const AnnArgs& a, int64_t qi, const float* qs, con
         const int32_t id = pid[j];
         int rank = 0;
         for (int y = 0; y < np; ++y) rank += d64[y] < v || (d64[y] == v && pid[y] < id);
-        if (rank < a.k) {
-            a.out_ids[qi * a.k + rank] = (int64_t)id;
-            a.out_dist[qi * a.k + rank] = (float)sqrt(v);
+        if (rank < k) {
+            a.out_ids[qi * a.out_stride + rank] = (int64_t)id;
+            a.out_dist[qi * a.out_stride + rank] = (float)sqrt(v);
         }
     }
     __syncthreads();
@@ -846,7 +864,7 @@ __device__ void write_topk(const AnnArgs& a, int64_t qi, const float* qs, const 
                            const float* cdist, int n_ver, int rounds, int exit_kind,
                            int64_t scanned, Smem& sh) {
     const int32_t* perm = a.perm;
-    const int k = a.k;
+    const int k = query_params(a, qi).k;
     bool done = false;
     if (n_ver <= CAP) {
         // the k-th smallest FP32 value, then the FP64 re-rank
@@ -888,8 +906,8 @@ __device__ void write_topk(const AnnArgs& a, int64_t qi, const float* qs, const 
         bitonic_sort(m, sh);
         for (int j = threadIdx.x; j < k; j += WG) {
             const uint64_t key = sh.skey[j];
-            a.out_ids[qi * k + j] = (int64_t)(uint32_t)key;
-            a.out_dist[qi * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+            a.out_ids[qi * a.out_stride + j] = (int64_t)(uint32_t)key;
+            a.out_dist[qi * a.out_stride + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
         }
     } else {
         auto c_src = [&](auto&& v) {
@@ -929,8 +947,8 @@ __device__ void write_topk(const AnnArgs& a, int64_t qi, const float* qs, const 
         bitonic_sort(k, sh);
         for (int j = threadIdx.x; j < k; j += WG) {
             const uint64_t key = sh.skey[j];
-            a.out_ids[qi * k + j] = (int64_t)(uint32_t)key;
-            a.out_dist[qi * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+            a.out_ids[qi * a.out_stride + j] = (int64_t)(uint32_t)key;
+            a.out_dist[qi * a.out_stride + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
         }
     }
     if (a.out_stats && threadIdx.x == 0) {
@@ -1050,12 +1068,13 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
     const float qn2 = qc.qn2;
     __syncthreads();
 
+    const AnnQueryParams qpar = query_params(a, qi);
     int32_t* cpos = a.ws_cpos + qi * (int64_t)a.budget;
     float* cdist = a.ws_cdist + qi * (int64_t)a.budget;
     const int32_t* perm = a.perm;
-    const int B = a.budget;
+    const int B = qpar.budget;
 
-    double r = a.r_min;
+    double r = qpar.r_min;
     int n_ver = 0;
     int rounds = 0;
     int exit_kind = 0;
@@ -1065,14 +1084,14 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
 
     for (;;) {
         if (rounds > 0) {
-            const double cr = a.c * r;
+            const double cr = qpar.c * r;
             const float thr2 = (float)(cr * cr);
             int loc = 0;
             for (int i = threadIdx.x; i < n_ver; i += WG) loc += cdist[i] <= thr2;
-            if (block_sum(loc, sh) >= a.k) { exit_kind = PMLSH_EXIT_NEAR; break; }
+            if (block_sum(loc, sh) >= qpar.k) { exit_kind = PMLSH_EXIT_NEAR; break; }
         }
         if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
-        const double Rd = a.t * r;
+        const double Rd = qpar.t * r;
         const float R = (float)Rd;
         const float R2 = (float)(Rd * Rd);
         ++rounds;
@@ -1148,7 +1167,7 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
         prev_hi = hi_hi;
         first = false;
         if (rounds >= a.max_rounds) break;
-        r = a.c * r;
+        r = qpar.c * r;
     }
 
     write_topk(a, qi, qs, cpos, cdist, n_ver, rounds, exit_kind, scanned, sh);
@@ -1373,7 +1392,8 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     };
     const uint32_t hbase = kCenBinBase;
     auto cbin = [&](uint32_t h) { return min(max(h >> 3, hbase) - hbase, (uint32_t)(NB - 1)); };
-    const int64_t want = a.n < 2 * (int64_t)a.budget ? a.n : 2 * (int64_t)a.budget;
+    const int32_t budget = query_params(a, qi).budget;
+    const int64_t want = a.n < 2 * (int64_t)budget ? a.n : 2 * (int64_t)budget;
     const int wc = (int)min<int64_t>(nch, (want + 63) / 64 + 1);
 
     // b0 bounds the bin sought in step 1 from above: every group holds a
@@ -1532,10 +1552,10 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         }
     }
     __syncthreads();
-    if (block_sum(cnt, sh) >= a.budget) {
+    if (block_sum(cnt, sh) >= budget) {
         if (threadIdx.x == 0) sh.thr_bin = NB - 1;
         __syncthreads();
-        find_threshold(a.budget, sh);
+        find_threshold(budget, sh);
         const float e2 = __uint_as_float((base2 + (uint32_t)sh.thr_bin + 1u) << 15);
         if (e2 < R2) R2 = e2;
     } else {
@@ -1966,7 +1986,9 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
     float* qs = reinterpret_cast<float*>(smem_raw + ((sizeof(Smem) + 15) & ~size_t(15)));
     const int64_t qi = blockIdx.x;
-    const int B = a.budget;
+    const AnnQueryParams qpar = query_params(a, qi);
+    const int B = qpar.budget;
+    const int k = qpar.k;
     const uint32_t cnt = a.l_count[qi];
     if (cnt > (uint32_t)a.q_cap || cnt < (uint32_t)B) {
         // list overflow, or the bound fell short: the per-query kernel answers
@@ -1975,8 +1997,8 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     }
     QueryCtx qc;
     load_query(a, qi, qs, qc);
-    int32_t* cpos = a.ws_cpos + qi * (int64_t)B;
-    float* cdist = a.ws_cdist + qi * (int64_t)B;
+    int32_t* cpos = a.ws_cpos + qi * (int64_t)a.budget;
+    float* cdist = a.ws_cdist + qi * (int64_t)a.budget;
     const uint32_t* list = a.l_list + qi * a.q_cap;
     const int32_t* perm = a.perm;
     const int n = (int)cnt;
@@ -2057,16 +2079,16 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     // a decision that the bounds cannot settle reads the FP32 rows of the
     // members concerned (verify_list), so every decision equals the one
     // taken on exact values. The index lists live in the histogram space.
-    float* lo2 = a.ws_clo + qi * (int64_t)B;
+    float* lo2 = a.ws_clo + qi * (int64_t)a.budget;
     float* hi2 = cdist;
     int32_t* ilist = reinterpret_cast<int32_t*>(sh.hist);
-    double r = a.r_min;
+    double r = qpar.r_min;
     int n_ver = 0, rounds = 0, exit_kind = 0;
     uint32_t prev_bits = 0;
     for (;;) {
         if (rounds > 0) {
             // the c r stop: at least k verified members within c r
-            const double cr = a.c * r;
+            const double cr = qpar.c * r;
             const float thr2 = (float)(cr * cr);
             int sure = 0, maybe = 0;
             for (int i = threadIdx.x; i < n_ver; i += WG) {
@@ -2075,7 +2097,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
             }
             sure = block_sum(sure, sh);
             maybe = block_sum(maybe, sh);
-            if (sure < a.k && sure + maybe >= a.k) {
+            if (sure < k && sure + maybe >= k) {
                 if (threadIdx.x == 0) sh.cnt1 = 0;
                 __syncthreads();
                 for (int b0 = 0; b0 < n_ver; b0 += WG) {
@@ -2091,10 +2113,10 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
                 for (int i = threadIdx.x; i < n_ver; i += WG) loc += hi2[i] <= thr2;
                 sure = block_sum(loc, sh);
             }
-            if (sure >= a.k) { exit_kind = PMLSH_EXIT_NEAR; break; }
+            if (sure >= k) { exit_kind = PMLSH_EXIT_NEAR; break; }
         }
         if (rounds >= MAX_ROUNDS) r = __longlong_as_double(0x7ff0000000000000ll);
-        const double Rd = a.t * r;
+        const double Rd = qpar.t * r;
         const uint32_t r2bits = __float_as_uint((float)(Rd * Rd));
         // members of L that the ball gains this round go to C after the
         // n_ver verified ones
@@ -2120,7 +2142,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
         __syncthreads();
         if (nb == B) { exit_kind = PMLSH_EXIT_BUDGET; break; }
         if (rounds >= a.max_rounds) break;
-        r = a.c * r;
+        r = qpar.c * r;
     }
 
     // Top-k: the k smallest upper bounds give hk; only members with lo2 <= hk
@@ -2129,7 +2151,7 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     for (int i = threadIdx.x; i < n_ver; i += WG)
         sh.skey[i] = ((uint64_t)__float_as_uint(hi2[i]) << 32) | (uint32_t)i;
     __syncthreads();
-    const float hk = n_ver > a.k ? __uint_as_float((uint32_t)(lds_select(n_ver, a.k, sh) >> 32))
+    const float hk = n_ver > k ? __uint_as_float((uint32_t)(lds_select(n_ver, k, sh) >> 32))
                                  : __int_as_float(0x7f800000);
     // members that the FP64 order of the re-rank could still place among the
     // k nearest: lower bound within a factor 1 + 4 gamma of hk
@@ -2184,13 +2206,13 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
             const uint64_t key = sh.skey[threadIdx.x];
             int rank = 0;
             for (int y = 0; y < m; ++y) rank += sh.skey[y] < key;
-            if (rank < a.k) {
-                a.out_ids[qi * a.k + rank] = (int64_t)(uint32_t)key;
-                a.out_dist[qi * a.k + rank] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+            if (rank < k) {
+                a.out_ids[qi * a.out_stride + rank] = (int64_t)(uint32_t)key;
+                a.out_dist[qi * a.out_stride + rank] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
             }
         }
     } else {
-        const uint64_t kth = lds_select(m, a.k, sh);
+        const uint64_t kth = lds_select(m, k, sh);
         uint64_t* tmp = reinterpret_cast<uint64_t*>(sh.hist);
         if (threadIdx.x == 0) sh.cnt1 = 0;
         __syncthreads();
@@ -2201,13 +2223,13 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
             if (take) tmp[slot] = sh.skey[i];
         }
         __syncthreads();
-        for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) sh.skey[j2] = tmp[j2];
+        for (int j2 = threadIdx.x; j2 < k; j2 += WG) sh.skey[j2] = tmp[j2];
         __syncthreads();
-        bitonic_sort(a.k, sh);
-        for (int j2 = threadIdx.x; j2 < a.k; j2 += WG) {
+        bitonic_sort(k, sh);
+        for (int j2 = threadIdx.x; j2 < k; j2 += WG) {
             const uint64_t key = sh.skey[j2];
-            a.out_ids[qi * a.k + j2] = (int64_t)(uint32_t)key;
-            a.out_dist[qi * a.k + j2] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+            a.out_ids[qi * a.out_stride + j2] = (int64_t)(uint32_t)key;
+            a.out_dist[qi * a.out_stride + j2] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
         }
     }
     if (a.out_stats && threadIdx.x == 0) {
@@ -2286,6 +2308,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.qp = L.qproj;
     a.qp_lo = L.qproj_lo;
     a.proj_lo = x.proj_lo;
+    a.qpar = L.qpar;
+    a.out_stride = L.out_stride > 0 ? L.out_stride : L.k;
     a.k = L.k;
     a.budget = (int32_t)L.budget;
     a.c = L.c;
@@ -2313,7 +2337,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     const int lds = ann_lds_bytes(x.d16);
     PMLSH_HIP(hipFuncSetAttribute((const void*)ann_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    if (ann_fast_path(L.budget)) {
+    if (L.fast) {
         a.qaug = L.ws_qaug;
         a.qtest = L.ws_qtest;
         a.cmask = L.ws_cmask;

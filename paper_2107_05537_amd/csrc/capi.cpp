@@ -70,7 +70,9 @@ int64_t ann_layout_bytes(const pmlsh_index* x, const AnnWorkspace& w, int64_t ba
 AnnWorkspace ann_workspace_base(const pmlsh_index* x, int k, int64_t B) {
     AnnWorkspace w{};
     w.B = B;
-    w.fast = ann_fast_path(B);
+    // the batched path, unless the budget exceeds its limit or the plain
+    // FP32 path is switched on (read once per call: layout and launch agree)
+    w.fast = ann_fast_path(B) && tune_get(PMLSH_TUNE_FP32_PATH) == 0;
     w.pool_q = w.fast ? ann_pool_per_query(x->n) : 0;
     w.per_query = (int64_t)MP * 8 + 64 + B * 8 + 3 * (int64_t)k * 4 +
                   (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
@@ -138,11 +140,23 @@ int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
 
 namespace {
 
+// Parameters of one ANN call: the same for every query, or per query from
+// the device array qpar (then k and budget are the largest of the call).
+struct AnnCall {
+    int k;
+    int64_t budget;
+    double c, t, r_min;
+    const AnnQueryParams* qpar;
+    int out_stride;
+    int max_rounds;
+};
+
 // The batches of one ANN call over the workspace region ws laid out by w.
-void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
-                    const pmlsh_plan& plan, double r_min, int64_t* out_ids, float* out_dist,
-                    int32_t* out_stats, hipStream_t st, int max_rounds, const AnnWorkspace& w,
-                    void* ws) {
+void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, const AnnCall& call,
+                    int64_t* out_ids, float* out_dist, int32_t* out_stats, hipStream_t st,
+                    const AnnWorkspace& w, void* ws) {
+    const int k = call.k;
+    const int stride = call.out_stride > 0 ? call.out_stride : k;
     const int64_t B = w.B, pool_q = w.pool_q, nchunk = w.nchunk, ldc = w.ldc,
                   batch = w.batch;
     const bool fast = w.fast;
@@ -178,11 +192,14 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, int 
         L.qproj_lo = qproj_lo;
         L.nq = nb;
         L.k = k;
-        L.c = c;
-        L.t = plan.t;
-        L.r_min = r_min;
-        L.max_rounds = max_rounds;
+        L.c = call.c;
+        L.t = call.t;
+        L.r_min = call.r_min;
+        L.max_rounds = call.max_rounds;
         L.budget = B;
+        L.qpar = call.qpar ? call.qpar + q0 : nullptr;
+        L.out_stride = stride;
+        L.fast = fast;
         L.ws_front = front;
         L.front_slots = std::min<int64_t>(w.slots, nb);
         L.ws_cpos = cpos;
@@ -200,8 +217,8 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, int 
             L.l_list = list;
             L.pool_cap = pool_q;
         }
-        L.out_ids = out_ids + q0 * k;
-        L.out_dist = out_dist + q0 * k;
+        L.out_ids = out_ids + q0 * stride;
+        L.out_dist = out_dist + q0 * stride;
         L.out_stats = out_stats ? out_stats + q0 * 4 : nullptr;
         launch_ann(L, st);
     }
@@ -225,10 +242,10 @@ void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, doub
     r_min = ann_plan(x, k, c, confidence, beta, r_min, &plan);
     if (nq == 0) return;
     const AnnWorkspace w = ann_workspace(x, nq, k, plan.budget);
+    const AnnCall call{k, plan.budget, c, plan.t, r_min, nullptr, k, max_rounds};
     void* ws = ws_alloc((size_t)w.bytes, st);
     try {
-        run_ann_region(x, queries, nq, k, c, plan, r_min, out_ids, out_dist, out_stats, st,
-                       max_rounds, w, ws);
+        run_ann_region(x, queries, nq, call, out_ids, out_dist, out_stats, st, w, ws);
     } catch (...) {
         ws_free(ws, st);
         throw;
@@ -250,8 +267,63 @@ void run_ann_in(const pmlsh_index* x, const float* queries, int64_t nq, int k, d
              "one query of this index needs " + std::to_string(one.bytes) +
                  " bytes of workspace; the fixed region holds " + std::to_string(region_bytes));
     }
-    run_ann_region(x, queries, nq, k, c, plan, r_min, out_ids, out_dist, out_stats, st, 0, w,
-                   region_of_device());
+    const AnnCall call{k, plan.budget, c, plan.t, r_min, nullptr, k, 0};
+    run_ann_region(x, queries, nq, call, out_ids, out_dist, out_stats, st, w, region_of_device());
+}
+
+void plan_queries(const pmlsh_index* x, const pmlsh_query_args* args, int64_t nq,
+                  std::vector<AnnQueryParams>* out, int* kmax, int64_t* bmax) {
+    out->resize((size_t)nq);
+    *kmax = 1;
+    *bmax = 1;
+    for (int64_t i = 0; i < nq; ++i) {
+        const pmlsh_query_args& q = args[i];
+        try {
+            validate_ann(x, nullptr, 0, q.k, nullptr, nullptr, q.r_min);
+            pmlsh_plan plan;
+            plan_params(x->n, x->m, q.k, q.c, q.confidence, q.beta, &plan);
+            double r_min = q.r_min;
+            if (!(r_min > 0.0)) r_min = index_default_r_min(x, plan.budget);
+            if (!std::isfinite(r_min)) fail(PMLSH_EINVAL, "r_min must be finite");
+            AnnQueryParams& p = (*out)[(size_t)i];
+            p.c = q.c;
+            p.t = plan.t;
+            p.r_min = r_min;
+            p.k = q.k;
+            p.budget = (int32_t)plan.budget;
+            *kmax = std::max(*kmax, q.k);
+            *bmax = std::max<int64_t>(*bmax, plan.budget);
+        } catch (const Error& e) {
+            fail(e.code, "query " + std::to_string(i) + ": " + e.msg);
+        }
+    }
+}
+
+int64_t ann_workspace_bytes_mixed(const pmlsh_index* x, int64_t nq, int kmax, int64_t bmax) {
+    return nq > 0 ? ann_workspace(x, nq, kmax, bmax).bytes : 0;
+}
+
+void run_ann_mixed(const pmlsh_index* x, const float* queries, int64_t nq,
+                   const AnnQueryParams* qpar, int kmax, int64_t bmax, int out_stride,
+                   int64_t* out_ids, float* out_dist, int32_t* out_stats, hipStream_t st,
+                   void* region, int64_t region_bytes) {
+    if (nq == 0) return;
+    const AnnCall call{kmax, bmax, 0.0, 0.0, 0.0, qpar, out_stride, 0};
+    if (region) {
+        const AnnWorkspace w = ann_workspace_in(x, nq, kmax, bmax, region_bytes);
+        if (w.batch < 1) fail(PMLSH_ENOMEM, "the workspace region holds no query");
+        run_ann_region(x, queries, nq, call, out_ids, out_dist, out_stats, st, w, region);
+        return;
+    }
+    const AnnWorkspace w = ann_workspace(x, nq, kmax, bmax);
+    void* ws = ws_alloc((size_t)w.bytes, st);
+    try {
+        run_ann_region(x, queries, nq, call, out_ids, out_dist, out_stats, st, w, ws);
+    } catch (...) {
+        ws_free(ws, st);
+        throw;
+    }
+    ws_free(ws, st);
 }
 
 }  // namespace pmlsh
@@ -294,6 +366,37 @@ int pmlsh_ann(const pmlsh_index* index, const float* queries, int64_t nq, int32_
         validate_ann(index, queries, nq, k, out_ids, out_dist, r_min);
         run_ann(index, queries, nq, k, c, confidence, beta, r_min, out_ids, out_dist,
                 out_stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+int pmlsh_ann_mixed(const pmlsh_index* index, const float* queries, int64_t nq,
+                    const pmlsh_query_args* args, int32_t out_stride, int64_t* out_ids,
+                    float* out_dist, int32_t* out_stats, void* stream) {
+    return guarded([&] {
+        if (!index) fail(PMLSH_EINVAL, "index is NULL");
+        if (nq < 0) fail(PMLSH_EINVAL, "nq must be >= 0");
+        if (nq == 0) return;
+        if (!queries || !args || !out_ids || !out_dist)
+            fail(PMLSH_EINVAL, "queries, args and outputs must not be NULL");
+        std::vector<AnnQueryParams> params;
+        int kmax = 1;
+        int64_t bmax = 1;
+        plan_queries(index, args, nq, &params, &kmax, &bmax);
+        if (out_stride < kmax) fail(PMLSH_EINVAL, "out_stride must be >= every k");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        void* dp = ws_alloc(params.size() * sizeof(AnnQueryParams), st);
+        try {
+            PMLSH_HIP(hipMemcpyAsync(dp, params.data(), params.size() * sizeof(AnnQueryParams),
+                                     hipMemcpyHostToDevice, st));
+            // the host copy of the parameters lives until this call returns
+            PMLSH_HIP(hipStreamSynchronize(st));
+            run_ann_mixed(index, queries, nq, static_cast<const AnnQueryParams*>(dp), kmax, bmax,
+                          out_stride, out_ids, out_dist, out_stats, st, nullptr, 0);
+        } catch (...) {
+            ws_free(dp, st);
+            throw;
+        }
+        ws_free(dp, st);
     });
 }
 

@@ -85,6 +85,13 @@ int guarded(F&& fn) {
 void* ws_alloc(size_t bytes, hipStream_t st);
 void ws_free(void* p, hipStream_t st);
 
+// Parameters of one query of a launch whose queries differ in k, c,
+// confidence, beta or r_min (device array, one entry per query).
+struct AnnQueryParams {
+    double c, t, r_min;
+    int32_t k, budget;
+};
+
 // ---------------------------------------------------------------- ANN host path
 // Argument checks of pmlsh_ann (throw EINVAL / EUNSUPPORTED).
 void validate_ann(const pmlsh_index* index, const float* queries, int64_t nq, int k,
@@ -97,6 +104,20 @@ int64_t ann_workspace_bytes(const pmlsh_index* x, int64_t nq, int k, double c,
 void run_ann(const pmlsh_index* x, const float* queries, int64_t nq, int k, double c,
              double confidence, double beta, double r_min, int64_t* out_ids,
              float* out_dist, int32_t* out_stats, hipStream_t st, int max_rounds = 0);
+// A batch of queries with per-query parameters: the device array qpar (nq
+// entries, from plan_queries), the largest k and budget among them, and the
+// row stride of the outputs (>= kmax). region / region_bytes: a fixed
+// device region for the workspace (null: the caching allocator).
+void run_ann_mixed(const pmlsh_index* x, const float* queries, int64_t nq,
+                   const AnnQueryParams* qpar, int kmax, int64_t bmax, int out_stride,
+                   int64_t* out_ids, float* out_dist, int32_t* out_stats, hipStream_t st,
+                   void* region, int64_t region_bytes);
+// Host plan of per-query parameters (t, B and the default r_min resolved);
+// throws EINVAL / EUNSUPPORTED like pmlsh_ann for an invalid entry.
+void plan_queries(const pmlsh_index* x, const pmlsh_query_args* args, int64_t nq,
+                  std::vector<AnnQueryParams>* out, int* kmax, int64_t* bmax);
+// Workspace bytes of run_ann_mixed on nq queries with these largest k, B.
+int64_t ann_workspace_bytes_mixed(const pmlsh_index* x, int64_t nq, int kmax, int64_t bmax);
 // pmlsh_ann over a fixed device region of region_bytes instead of the
 // caching allocator: the queries go through in batches that fit it;
 // EUNSUPPORTED (before any HIP call) when not even one query fits. The
@@ -309,6 +330,9 @@ struct AnnLaunch {
     int64_t* out_ids;
     float* out_dist;
     int32_t* out_stats;
+    const AnnQueryParams* qpar = nullptr;   // per-query parameters (then k, budget: the largest)
+    int out_stride = 0;                     // output row stride (0: k)
+    bool fast = false;                      // the batched path (its workspace fields are set)
 };
 void launch_ann(const AnnLaunch& a, hipStream_t stream);
 int ann_lds_bytes(int d_pad);

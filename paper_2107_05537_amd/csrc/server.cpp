@@ -1,13 +1,15 @@
 // Serving loop: continuous batching of (c,k)-ANN requests on a resident
 // index. Requests wait in arrival order; one host worker thread forms each
-// launch from the oldest waiting request and the later requests with the same
-// parameters (Algorithm 2 is run per query, so queries of different requests
-// with equal parameters can share a launch without changing any answer),
-// gathers their queries into a staging buffer on the server's stream, runs
-// the batched ANN path and scatters the answers. Launches are admitted while
-// a launch slot is free and the staging plus workspace bytes in flight stay
-// within the HBM budget; completions are found by polling one HIP event per
-// launch.
+// launch from the waiting requests in arrival order, whatever their k, c,
+// confidence, beta and r_min (Algorithm 2 is run per query with its own
+// parameters, so a launch changes no answer), gathers their queries and
+// per-query parameters into the buffers of a launch slot, runs the batched
+// ANN path on them and scatters the answers. A launch is admitted while a
+// slot is free and the workspace of the launches in flight stays within the
+// HBM budget. Each slot owns its device buffers (queries, answers,
+// parameters, workspace), a pinned host buffer for the parameters and a
+// completion event, all created with the server and grown only when a
+// launch needs more, so serving does not allocate.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -30,6 +32,7 @@ struct Request {
     int64_t nq = 0;
     int32_t k = 0;
     double c = 0, confidence = 0, beta = 0, r_min = 0;
+    AnnQueryParams params{};      // the plan of every query of the request
     int64_t* out_ids = nullptr;
     float* out_dist = nullptr;
     hipEvent_t ready = nullptr;   // work of the submitting stream, or null
@@ -39,11 +42,6 @@ struct Request {
     int status = PMLSH_OK;
     bool done = false;
     Clock::time_point t_submit;
-
-    bool same_class(const Request& o) const {
-        return k == o.k && c == o.c && confidence == o.confidence && beta == o.beta &&
-               r_min == o.r_min;
-    }
 };
 
 struct Segment {
@@ -51,9 +49,22 @@ struct Segment {
     int64_t req_off, count;
 };
 
+// Buffers of one launch slot, grown (never shrunk) to the largest launch
+// it has served.
+struct Slot {
+    float* q = nullptr;                 // queries, max_batch x d
+    int64_t* ids = nullptr;             // answers, rows of kcap
+    float* dist = nullptr;
+    AnnQueryParams* params = nullptr;   // device, per query
+    AnnQueryParams* hparams = nullptr;  // pinned host staging of the same
+    void* ws = nullptr;                 // ANN workspace
+    int64_t rows = 0, kcap = 0, ws_bytes = 0;
+    hipEvent_t done = nullptr;
+};
+
 struct Launch {
     std::vector<Segment> segs;
-    hipEvent_t done = nullptr;
+    int slot = -1;
     int64_t bytes = 0;
     int status = PMLSH_OK;
 };
@@ -79,6 +90,8 @@ struct pmlsh_server {
     // worker-only state
     std::deque<pmlsh::Launch> inflight;
     int64_t bytes_inflight = 0;
+    std::vector<pmlsh::Slot> slots;
+    std::vector<int> free_slots;
 
     // counters (under mu)
     int64_t n_requests = 0, n_queries = 0, n_launches = 0;
@@ -90,17 +103,15 @@ struct pmlsh_server {
 namespace pmlsh {
 namespace {
 
-// Finishes the oldest launch if its event has completed (or fails it).
-// Returns true if a launch was retired.
+// Finishes the oldest launch if its slot's event has completed (or fails
+// it); with block, waits for it. Returns true if a launch was retired.
 bool retire_one(pmlsh_server* s, bool block) {
     if (s->inflight.empty()) return false;
     Launch& L = s->inflight.front();
-    // a launch without an event had its stream synchronised when issued
-    hipError_t e = hipSuccess;
-    if (L.done) e = block ? hipEventSynchronize(L.done) : hipEventQuery(L.done);
+    Slot& sl = s->slots[(size_t)L.slot];
+    hipError_t e = block ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
     if (e == hipErrorNotReady) return false;
     if (e != hipSuccess && L.status == PMLSH_OK) L.status = PMLSH_EDEVICE;
-    if (L.done) (void)hipEventDestroy(L.done);
     const auto now = Clock::now();
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -121,25 +132,19 @@ bool retire_one(pmlsh_server* s, bool block) {
         ++s->n_launches;
     }
     s->bytes_inflight -= L.bytes;
+    s->free_slots.push_back(L.slot);
     s->inflight.pop_front();
     s->cv_done.notify_all();
     return true;
 }
 
-// Takes the next launch's segments from the waiting requests (under mu):
-// the oldest request's parameters, then every later request with the same
-// ones, in arrival order, up to max_batch queries.
+// Takes the next launch's segments from the waiting requests (under mu): in
+// arrival order, up to max_batch queries; a larger request is split.
 std::vector<Segment> take_batch(pmlsh_server* s) {
     std::vector<Segment> segs;
-    if (s->waiting.empty()) return segs;
-    const Request head = *s->waiting.front();
     int64_t room = s->max_batch;
     for (auto it = s->waiting.begin(); it != s->waiting.end() && room > 0;) {
         Request& r = **it;
-        if (!r.same_class(head)) {
-            ++it;
-            continue;
-        }
         const int64_t take = std::min(room, r.nq - r.issued);
         segs.push_back({*it, r.issued, take});
         r.issued += take;
@@ -166,34 +171,87 @@ void untake(pmlsh_server* s, std::vector<Segment>& segs) {
                      });
 }
 
-int64_t launch_bytes(const pmlsh_server* s, const Request& r, int64_t nb) {
-    const int64_t staging = nb * ((int64_t)s->idx->d * 4 + (int64_t)r.k * 12);
-    return staging + ann_workspace_bytes(s->idx, nb, r.k, r.c, r.confidence, r.beta);
+// Shape of a launch: queries, largest k and budget.
+struct Shape {
+    int64_t nb = 0;
+    int kmax = 1;
+    int64_t bmax = 1;
+};
+
+Shape shape_of(const std::vector<Segment>& segs) {
+    Shape sh;
+    for (auto& sg : segs) {
+        sh.nb += sg.count;
+        sh.kmax = std::max(sh.kmax, sg.req->params.k);
+        sh.bmax = std::max<int64_t>(sh.bmax, sg.req->params.budget);
+    }
+    return sh;
 }
 
-// Issues one launch on the server's stream. Errors fail the launch's
-// requests; the event still marks the point after which its buffers are free.
-void issue(pmlsh_server* s, Launch& L) {
-    const Request& p = *L.segs.front().req;
+int64_t launch_bytes(const pmlsh_server* s, const Shape& sh) {
+    return ann_workspace_bytes_mixed(s->idx, sh.nb, sh.kmax, sh.bmax);
+}
+
+void slot_release(Slot& sl) {
+    (void)hipFree(sl.q);
+    (void)hipFree(sl.ids);
+    (void)hipFree(sl.dist);
+    (void)hipFree(sl.params);
+    (void)hipHostFree(sl.hparams);
+    (void)hipFree(sl.ws);
+    sl.q = nullptr;
+    sl.ids = nullptr;
+    sl.dist = nullptr;
+    sl.params = nullptr;
+    sl.hparams = nullptr;
+    sl.ws = nullptr;
+    sl.rows = sl.kcap = sl.ws_bytes = 0;
+}
+
+// Sizes a slot for `rows` queries with answers of up to kcap entries and a
+// workspace of ws_bytes (called with the slot idle).
+void slot_reserve(const pmlsh_server* s, Slot& sl, int64_t rows, int64_t kcap, int64_t ws_bytes) {
+    if (rows > sl.rows || kcap > sl.kcap) {
+        rows = std::max(rows, sl.rows);
+        kcap = std::max(kcap, sl.kcap);
+        (void)hipFree(sl.q);
+        (void)hipFree(sl.ids);
+        (void)hipFree(sl.dist);
+        (void)hipFree(sl.params);
+        (void)hipHostFree(sl.hparams);
+        sl.q = nullptr;
+        sl.ids = nullptr;
+        sl.dist = nullptr;
+        sl.params = nullptr;
+        sl.hparams = nullptr;
+        sl.rows = sl.kcap = 0;
+        PMLSH_HIP(hipMalloc(&sl.q, (size_t)rows * s->idx->d * sizeof(float)));
+        PMLSH_HIP(hipMalloc(&sl.ids, (size_t)rows * kcap * sizeof(int64_t)));
+        PMLSH_HIP(hipMalloc(&sl.dist, (size_t)rows * kcap * sizeof(float)));
+        PMLSH_HIP(hipMalloc(&sl.params, (size_t)rows * sizeof(AnnQueryParams)));
+        PMLSH_HIP(hipHostMalloc(&sl.hparams, (size_t)rows * sizeof(AnnQueryParams),
+                                hipHostMallocDefault));
+        sl.rows = rows;
+        sl.kcap = kcap;
+    }
+    if (ws_bytes > sl.ws_bytes) {
+        (void)hipFree(sl.ws);
+        sl.ws = nullptr;
+        sl.ws_bytes = 0;
+        PMLSH_HIP(hipMalloc(&sl.ws, (size_t)ws_bytes));
+        sl.ws_bytes = ws_bytes;
+    }
+}
+
+// Issues one launch on the server's stream in its slot. Errors fail the
+// launch's requests; the slot's event still marks the point after which its
+// buffers are free.
+void issue(pmlsh_server* s, Launch& L, const Shape& shp) {
     const int d = s->idx->d;
-    const int k = p.k;
-    int64_t nb = 0;
-    for (auto& sg : L.segs) nb += sg.count;
     hipStream_t st = s->stream;
+    Slot& sl = s->slots[(size_t)L.slot];
     L.status = guarded([&] {
-        // staging buffers, released in stream order after the scatter copies
-        struct Staging {
-            void* p = nullptr;
-            hipStream_t st;
-            explicit Staging(hipStream_t s_) : st(s_) {}
-            ~Staging() { ws_free(p, st); }
-        } bq(st), bid(st), bdist(st);
-        bq.p = ws_alloc((size_t)nb * d * 4, st);
-        bid.p = ws_alloc((size_t)nb * k * 8, st);
-        bdist.p = ws_alloc((size_t)nb * k * 4, st);
-        float* sq = static_cast<float*>(bq.p);
-        int64_t* sid = static_cast<int64_t*>(bid.p);
-        float* sdist = static_cast<float*>(bdist.p);
+        slot_reserve(s, sl, shp.nb, shp.kmax, L.bytes);
         int64_t off = 0;
         for (auto& sg : L.segs) {
             Request& r = *sg.req;
@@ -201,32 +259,34 @@ void issue(pmlsh_server* s, Launch& L) {
                 PMLSH_HIP(hipStreamWaitEvent(st, r.ready, 0));
                 r.ready_waited = true;
             }
-            PMLSH_HIP(hipMemcpyAsync(sq + off * d, r.q + sg.req_off * d, (size_t)sg.count * d * 4,
-                                     hipMemcpyDeviceToDevice, st));
+            PMLSH_HIP(hipMemcpyAsync(sl.q + off * d, r.q + sg.req_off * d,
+                                     (size_t)sg.count * d * 4, hipMemcpyDeviceToDevice, st));
+            for (int64_t i = 0; i < sg.count; ++i) sl.hparams[off + i] = r.params;
             off += sg.count;
         }
-        run_ann(s->idx, sq, nb, k, p.c, p.confidence, p.beta, p.r_min, sid, sdist, nullptr, st);
+        PMLSH_HIP(hipMemcpyAsync(sl.params, sl.hparams, (size_t)shp.nb * sizeof(AnnQueryParams),
+                                 hipMemcpyHostToDevice, st));
+        run_ann_mixed(s->idx, sl.q, shp.nb, sl.params, shp.kmax, shp.bmax, shp.kmax, sl.ids,
+                      sl.dist, nullptr, st, sl.ws, sl.ws_bytes);
         off = 0;
         for (auto& sg : L.segs) {
             Request& r = *sg.req;
-            PMLSH_HIP(hipMemcpyAsync(r.out_ids + sg.req_off * k, sid + off * k,
-                                     (size_t)sg.count * k * 8, hipMemcpyDeviceToDevice, st));
-            PMLSH_HIP(hipMemcpyAsync(r.out_dist + sg.req_off * k, sdist + off * k,
-                                     (size_t)sg.count * k * 4, hipMemcpyDeviceToDevice, st));
+            const size_t k = (size_t)r.k;
+            PMLSH_HIP(hipMemcpy2DAsync(r.out_ids + sg.req_off * r.k, k * 8, sl.ids + off * shp.kmax,
+                                       (size_t)shp.kmax * 8, k * 8, (size_t)sg.count,
+                                       hipMemcpyDeviceToDevice, st));
+            PMLSH_HIP(hipMemcpy2DAsync(r.out_dist + sg.req_off * r.k, k * 4,
+                                       sl.dist + off * shp.kmax, (size_t)shp.kmax * 4, k * 4,
+                                       (size_t)sg.count, hipMemcpyDeviceToDevice, st));
             off += sg.count;
         }
     });
-    if (hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
-        L.done = nullptr;
+    if (hipEventRecord(sl.done, st) != hipSuccess) {
         (void)hipStreamSynchronize(st);
         if (L.status == PMLSH_OK) L.status = PMLSH_EDEVICE;
-        return;
-    }
-    if (hipEventRecord(L.done, st) != hipSuccess) {
-        (void)hipEventDestroy(L.done);
-        L.done = nullptr;
-        (void)hipStreamSynchronize(st);
-        if (L.status == PMLSH_OK) L.status = PMLSH_EDEVICE;
+        // the event's last record stands for an earlier launch: its query
+        // would report this one as complete, which after the synchronisation
+        // above it is
     }
 }
 
@@ -237,30 +297,50 @@ void worker_loop(pmlsh_server* s) {
         while (retire_one(s, false)) {
         }
         // admit launches while a slot and the budget allow
-        bool issued = false;
-        while ((int)s->inflight.size() < s->max_inflight) {
+        while (!s->free_slots.empty()) {
             std::vector<Segment> segs;
+            Shape shp;
+            int64_t bytes = 0;
             {
                 std::lock_guard<std::mutex> g(s->mu);
                 segs = take_batch(s);
                 if (segs.empty()) break;
-                int64_t nb = 0;
-                for (auto& sg : segs) nb += sg.count;
-                const int64_t bytes = launch_bytes(s, *segs.front().req, nb);
+                shp = shape_of(segs);
+                bytes = launch_bytes(s, shp);
                 if (!s->inflight.empty() && s->bytes_inflight + bytes > s->hbm_budget) {
                     untake(s, segs);
                     break;
                 }
-                s->inflight.emplace_back();
-                s->inflight.back().segs = std::move(segs);
-                s->inflight.back().bytes = bytes;
-                s->bytes_inflight += bytes;
             }
-            issue(s, s->inflight.back());
-            issued = true;
+            s->inflight.emplace_back();
+            Launch& L = s->inflight.back();
+            L.segs = std::move(segs);
+            L.bytes = bytes;
+            L.slot = s->free_slots.back();
+            s->free_slots.pop_back();
+            s->bytes_inflight += bytes;
+            issue(s, L, shp);
         }
         if (!s->inflight.empty()) {
-            if (!issued) std::this_thread::sleep_for(std::chrono::microseconds(20));
+            bool can_admit = false;
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                can_admit = !s->waiting.empty() && !s->free_slots.empty();
+            }
+            if (!can_admit) {
+                // nothing to admit until a launch completes: wait for the
+                // oldest, unless requests arrive that a free slot could take
+                std::unique_lock<std::mutex> lk(s->mu);
+                if (s->free_slots.empty() || s->waiting.empty()) {
+                    if (s->free_slots.empty()) {
+                        lk.unlock();
+                        retire_one(s, true);
+                    } else {
+                        s->cv_work.wait_for(lk, std::chrono::microseconds(50),
+                                            [&] { return s->stop || !s->waiting.empty(); });
+                    }
+                }
+            }
             continue;
         }
         std::unique_lock<std::mutex> lk(s->mu);
@@ -297,10 +377,34 @@ int pmlsh_server_create(const pmlsh_index* index, const pmlsh_server_args* args,
         }
         PMLSH_HIP(hipSetDevice(index->device));
         PMLSH_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        auto cleanup = [&] {
+            for (auto& sl : s->slots) {
+                slot_release(sl);
+                if (sl.done) (void)hipEventDestroy(sl.done);
+            }
+            (void)hipStreamDestroy(s->stream);
+        };
+        try {
+            // slots sized for full launches of k up to 100 within the
+            // batched path's budget limit; larger launches grow them
+            s->slots.resize((size_t)s->max_inflight);
+            const int64_t ws0 =
+                ann_workspace_bytes_mixed(index, s->max_batch, std::min<int64_t>(100, index->n),
+                                          std::min<int64_t>(2048, index->n));
+            for (int i = 0; i < s->max_inflight; ++i) {
+                Slot& sl = s->slots[(size_t)i];
+                PMLSH_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+                slot_reserve(s.get(), sl, s->max_batch, std::min<int64_t>(100, index->n), ws0);
+                s->free_slots.push_back(s->max_inflight - 1 - i);
+            }
+        } catch (...) {
+            cleanup();
+            throw;
+        }
         try {
             s->worker = std::thread(worker_loop, s.get());
         } catch (const std::exception&) {
-            (void)hipStreamDestroy(s->stream);
+            cleanup();
             fail(PMLSH_EDEVICE, "cannot start the server thread");
         }
         *out = s.release();
@@ -313,10 +417,14 @@ int pmlsh_server_submit(pmlsh_server* server, const float* queries, int64_t nq, 
     return guarded([&] {
         if (!server || !ticket) fail(PMLSH_EINVAL, "NULL argument");
         validate_ann(server->idx, queries, nq, k, out_ids, out_dist, r_min);
-        // parameter checks of the planner, before anything is queued
-        pmlsh_plan plan;
-        plan_params(server->idx->n, server->idx->m, k, c, confidence, beta, &plan);
+        // the request's plan (parameter checks included), before anything is queued
+        const pmlsh_query_args qa{k, 0, c, confidence, beta, r_min};
+        std::vector<AnnQueryParams> plan;
+        int kmax = 1;
+        int64_t bmax = 1;
+        plan_queries(server->idx, &qa, 1, &plan, &kmax, &bmax);
         auto r = std::make_shared<Request>();
+        r->params = plan[0];
         r->q = queries;
         r->nq = nq;
         r->k = k;
@@ -411,6 +519,10 @@ void pmlsh_server_destroy(pmlsh_server* server) {
     if (server->worker.joinable()) server->worker.join();
     if (server->stream) {
         (void)hipStreamSynchronize(server->stream);
+        for (auto& sl : server->slots) {
+            slot_release(sl);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
         (void)hipStreamDestroy(server->stream);
     }
     delete server;

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import brute
+from oracle import brute, chi2
 from parity import TOL, compare_ann, oracle_ann, oracle_r_min, say
 
 pytestmark = pytest.mark.gpu
@@ -483,7 +483,7 @@ def test_group_filter_settings_agree(parity_wl):
     with pytest.raises(pm.PmlshError):
         pm.tune(pm.TUNE_GROUP_LIST, 2049)
     with pytest.raises(pm.PmlshError):
-        pm.tune(2, 0)
+        pm.tune(3, 0)
 
 
 def test_large_n_sampled():
@@ -520,3 +520,70 @@ def test_large_n_sampled():
         np.testing.assert_array_equal(o_ids, ids)
         np.testing.assert_array_equal(o_dist, dist)
         np.testing.assert_array_equal(o_st[:, :3], st[:, :3])
+
+
+def test_mixed_parameters_in_one_launch(parity_wl):
+    """pmlsh_ann_mixed: 150 queries with their own k, c, confidence and beta
+    in one call. Every row equals the query answered alone by pmlsh_ann with
+    its own parameters (bit for bit: Algorithm 2 runs per query), and a
+    sample agrees with the oracle. A second call adds one query whose budget
+    exceeds the batched path's limit, which sends the launch to the
+    per-query kernel."""
+    pm = _gpu()
+    D, A, Q = parity_wl["D"], parity_wl["A"], parity_wl["Q"]
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    rng = np.random.Generator(np.random.PCG64(31))
+    nq = 150
+    rows = rng.integers(0, Q.shape[0], size=nq)
+    Qm = (Q[rows] + 0.05 * rng.standard_normal((nq, Q.shape[1]))).astype(np.float32)
+    params = [{"k": int(rng.choice([1, 7, 10, 50, 300])), "c": float(rng.choice([1.2, 1.5, 2.0])),
+               "confidence": float(rng.choice([0.9, 1 - 1 / math.e])),
+               "beta": float(rng.choice([0.01, 0.05, 0.1]))} for _ in range(nq)]
+    Qd = torch.from_numpy(Qm).to(dev)
+    for extra in (False, True):
+        say(f"case: mixed parameters, one launch (budget above the batched limit: {extra})")
+        ps = list(params)
+        if extra:
+            ps[7] = {"k": 10, "c": 1.5, "confidence": 0.9, "beta": 0.3}
+        ids, dist, st = idx.ann_mixed(Qd, ps, stats=True)
+        torch.cuda.synchronize()
+        ids, dist, st = ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()
+        for i, p in enumerate(ps):
+            a_ids, a_dist, a_st = idx.ann(Qd[i:i + 1], p["k"], c=p["c"], confidence=p["confidence"],
+                                          beta=p["beta"], stats=True)
+            assert ids[i, :p["k"]].tolist() == a_ids.cpu().numpy()[0].tolist(), (i, p)
+            assert np.array_equal(dist[i, :p["k"]], a_dist.cpu().numpy()[0]), (i, p)
+            assert st[i, :3].tolist() == a_st.cpu().numpy()[0, :3].tolist(), (i, p)
+    # the oracle on every tenth query
+    for i in range(0, nq, 10):
+        p = params[i]
+        B = chi2.ann_budget(p["beta"], D.shape[0], p["k"])
+        r0 = oracle_r_min(D, 0x5EED, B)
+        res, _ = oracle_ann(D, A, Qm[i:i + 1], p["k"], p["c"], p["confidence"], p["beta"],
+                            r_min=r0)
+        compare_ann(D, Qm[i:i + 1], res, ids[i:i + 1, :p["k"]], dist[i:i + 1, :p["k"]],
+                    st[i:i + 1], fp64=True, min_exact_frac=0.0)
+
+
+def test_fp32_path_equals_batched_path(parity_wl):
+    """The plain FP32 path (every query on the per-query kernel: PM-tree walk
+    with Eq. 5, FP32 distances) gives the batched path's answers."""
+    pm = _gpu()
+    D, A, Q = parity_wl["D"], parity_wl["A"], parity_wl["Q"]
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    for k, beta in ((10, 0.1), (50, 0.02)):
+        say(f"case: FP32 path k={k} beta={beta}")
+        ref = [t.cpu().numpy() for t in idx.ann(Qd, k, c=1.5, confidence=0.9, beta=beta,
+                                                stats=True)]
+        pm.tune(pm.TUNE_FP32_PATH, 1)
+        try:
+            out = [t.cpu().numpy() for t in idx.ann(Qd, k, c=1.5, confidence=0.9, beta=beta,
+                                                    stats=True)]
+        finally:
+            pm.tune(pm.TUNE_FP32_PATH, -1)
+        np.testing.assert_array_equal(out[0], ref[0])
+        np.testing.assert_array_equal(out[1], ref[1])
+        np.testing.assert_array_equal(out[2][:, :3], ref[2][:, :3])
