@@ -299,6 +299,16 @@ void plan_queries(const pmlsh_index* x, const pmlsh_query_args* args, int64_t nq
     }
 }
 
+void run_ann_planned(const pmlsh_index* x, const float* queries, int64_t nq,
+                     const AnnQueryParams& p, int64_t* out_ids, float* out_dist, hipStream_t st,
+                     void* region, int64_t region_bytes) {
+    if (nq == 0) return;
+    const AnnWorkspace w = ann_workspace_in(x, nq, p.k, p.budget, region_bytes);
+    if (w.batch < 1) fail(PMLSH_ENOMEM, "the workspace region holds no query");
+    const AnnCall call{p.k, p.budget, p.c, p.t, p.r_min, nullptr, p.k, 0};
+    run_ann_region(x, queries, nq, call, out_ids, out_dist, nullptr, st, w, region);
+}
+
 int64_t ann_workspace_bytes_mixed(const pmlsh_index* x, int64_t nq, int kmax, int64_t bmax) {
     return nq > 0 ? ann_workspace(x, nq, kmax, bmax).bytes : 0;
 }

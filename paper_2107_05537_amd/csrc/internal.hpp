@@ -112,6 +112,11 @@ void run_ann_mixed(const pmlsh_index* x, const float* queries, int64_t nq,
                    const AnnQueryParams* qpar, int kmax, int64_t bmax, int out_stride,
                    int64_t* out_ids, float* out_dist, int32_t* out_stats, hipStream_t st,
                    void* region, int64_t region_bytes);
+// A batch of queries sharing one plan (from plan_queries), its answers
+// written with row stride k, the workspace in the given device region.
+void run_ann_planned(const pmlsh_index* x, const float* queries, int64_t nq,
+                     const AnnQueryParams& p, int64_t* out_ids, float* out_dist, hipStream_t st,
+                     void* region, int64_t region_bytes);
 // Host plan of per-query parameters (t, B and the default r_min resolved);
 // throws EINVAL / EUNSUPPORTED like pmlsh_ann for an invalid entry.
 void plan_queries(const pmlsh_index* x, const pmlsh_query_args* args, int64_t nq,

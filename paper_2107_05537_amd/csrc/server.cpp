@@ -252,6 +252,19 @@ void issue(pmlsh_server* s, Launch& L, const Shape& shp) {
     Slot& sl = s->slots[(size_t)L.slot];
     L.status = guarded([&] {
         slot_reserve(s, sl, shp.nb, shp.kmax, L.bytes);
+        if (L.segs.size() == 1) {
+            // one request: its own queries and outputs, its plan as scalars
+            const Segment& sg = L.segs.front();
+            Request& r = *sg.req;
+            if (r.ready && !r.ready_waited) {
+                PMLSH_HIP(hipStreamWaitEvent(st, r.ready, 0));
+                r.ready_waited = true;
+            }
+            const AnnQueryParams& p = r.params;
+            run_ann_planned(s->idx, r.q + sg.req_off * d, sg.count, p, r.out_ids + sg.req_off * r.k,
+                            r.out_dist + sg.req_off * r.k, st, sl.ws, sl.ws_bytes);
+            return;
+        }
         int64_t off = 0;
         for (auto& sg : L.segs) {
             Request& r = *sg.req;
