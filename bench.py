@@ -35,6 +35,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -208,6 +209,61 @@ def cpu_baseline(pool, workers, n, beta, r_min):
 
 
 FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+
+
+def config3_bench(pm, torch, dev, cs=(1.2, 1.5, 2.0),
+                  betas=(0.001, 0.002, 0.005, 0.02, 0.05), nq_eval=1024, k=10,
+                  conf=1 - 1 / math.e, point_limit_s=20.0):
+    """Low-contrast 1,000,000 x 960 workload (every coordinate |N(0,1)|^1.5,
+    rows L2-normalised and scaled by 100): for every c, recall@10 and overall
+    ratio (Eqs. 12-14) against exact FP64 kNN over the first nq_eval queries,
+    and queries/s of the calls, as beta grows. Budgets above the batched
+    path's limit go to the per-query path. A c stops at the first beta whose
+    call takes longer than point_limit_s."""
+    import synth
+    t0 = time.perf_counter()
+    w = synth.heavy_tailed()
+    D = torch.from_numpy(w["D"]).to(dev)
+    A = torch.from_numpy(w["A"]).to(dev)
+    Q = torch.from_numpy(w["Q"][:nq_eval]).to(dev)
+    n = D.shape[0]
+    del w
+    t1 = time.perf_counter()
+    idx = pm.Index(D, A)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t1
+    truth, truth_dist = exact_knn_gpu(torch, D, Q, k, chunk=64)
+    torch.cuda.synchronize()
+    log(f"config 3: data {t1 - t0:.1f} s, index {build_s:.1f} s, exact kNN done")
+    rows = []
+    for c in cs:
+        for beta in betas:
+            plan = pm.plan_params(n, A.shape[0], k, c, conf, beta)
+            idx.ann(Q[:64], k, c=c, confidence=conf, beta=beta)
+            torch.cuda.synchronize()
+            t_0 = time.perf_counter()
+            ids, _, st = idx.ann(Q, k, c=c, confidence=conf, beta=beta, stats=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t_0
+            rec = recall_at_k(ids, truth)
+            rat = overall_ratio(torch, D, Q, ids, truth_dist)
+            stn = st.cpu().numpy().astype(np.int64)
+            row = {"c": c, "beta": beta, "budget_B": int(plan["budget"]),
+                   "path": "batched" if plan["budget"] <= 2048 else "per-query",
+                   "recall@10": round(rec, 4), "overall_ratio": round(rat, 6),
+                   "queries_per_s": round(Q.shape[0] / el, 1),
+                   "mean_C": round(float(stn[:, 1].mean()), 1),
+                   "mean_rounds": round(float(stn[:, 0].mean()), 3)}
+            log(f"config 3: {row}")
+            rows.append(row)
+            if el > point_limit_s:
+                break
+    del idx
+    return {"workload": "heavy-tailed 1,000,000 x 960 (|N(0,1)|^1.5, rows L2-normalised x 100), "
+                        f"first {nq_eval} of 10,000 queries, k={k}",
+            "truth": "exact kNN in FP64 on the GPU (norm-expansion shortlist of 4k, "
+                     "re-ranked by FP64 direct differences)",
+            "build_s": round(build_s, 2), "points": rows}
 
 
 def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
@@ -417,6 +473,8 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
         """One synchronous call per request in arrival order."""
         if fp32:
             pm.tune(pm.TUNE_FP32_PATH, 1)
+        gc.collect()
+        gc.disable()
         try:
             lat, last = [], 0.0
             start = time.perf_counter() + 0.05
@@ -430,6 +488,7 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
                 lat.append((last - (start + t_arr)) * 1e3)
             return lat, last - start
         finally:
+            gc.enable()
             if fp32:
                 pm.tune(pm.TUNE_FP32_PATH, -1)
 
@@ -463,6 +522,15 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
         srv = pm.Server(idx, max_batch=1024, max_inflight=2)
         handles = [None] * len(reqs)
         done_t = [0.0] * len(reqs)
+        sub_t = [0.0] * len(reqs)
+        # answers allocated before the stream starts; Python's collector off
+        # while it runs (a collection pass stalls the submitting thread)
+        outs = [(torch.empty((e_ - s_, r[2]), dtype=torch.int64, device=dev),
+                 torch.empty((e_ - s_, r[2]), dtype=torch.float32, device=dev))
+                for (s_, e_), r in zip(sl, reqs)]
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
         start = time.perf_counter() + 0.05
 
         def submitter():
@@ -470,23 +538,37 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
                 while time.perf_counter() < start + t_arr:
                     time.sleep(0.0001)
                 s_, e_ = sl[i]
-                handles[i] = srv.submit(Q[s_:e_], k, c=c, confidence=conf, beta=beta)
+                sub_t[i] = time.perf_counter()
+                handles[i] = srv.submit(Q[s_:e_], k, c=c, confidence=conf, beta=beta,
+                                        out=outs[i])
 
-        th = threading.Thread(target=submitter)
-        th.start()
-        for i in range(len(reqs)):
-            while handles[i] is None:
-                time.sleep(0.0001)
-            handles[i].wait()
-            done_t[i] = time.perf_counter()
-        th.join()
+        try:
+            th = threading.Thread(target=submitter)
+            th.start()
+            for i in range(len(reqs)):
+                while handles[i] is None:
+                    time.sleep(0.0001)
+                handles[i].wait()
+                done_t[i] = time.perf_counter()
+            th.join()
+        finally:
+            gc.enable()
         st = srv.stats()
         srv.close()
         lat_srv = [(done_t[i] - (start + reqs[i][0])) * 1e3 for i in range(len(reqs))]
+        lag = [(sub_t[i] - (start + reqs[i][0])) * 1e3 for i in range(len(reqs))]
         wall_srv = max(done_t) - start
         row = {"offered_qps": rate, "requests": len(reqs), "queries": nq_tot,
                "server": {"qps": round(nq_tot / wall_srv, 1), "p50_ms": pct(lat_srv, 50),
-                          "p99_ms": pct(lat_srv, 99), "launches": int(st["launches"])}}
+                          "p99_ms": pct(lat_srv, 99), "launches": int(st["launches"]),
+                          "submit_to_done_p99_ms": round(float(st["latency_p99_ms"]), 3),
+                          "submit_to_done_max_ms": round(float(st["latency_max_ms"]), 3),
+                          "submit_lag_max_ms": round(max(lag), 3)}}
+        slow = sorted(range(len(reqs)), key=lambda i: -lat_srv[i])[:3]
+        log("  slowest server requests (index, arrival ms, size, k, c, latency ms, "
+            "submit lag ms): "
+            + str([(i, round(reqs[i][0] * 1e3, 2), reqs[i][1], reqs[i][2], reqs[i][3],
+                    round(lat_srv[i], 2), round(lag[i], 2)) for i in slow]))
         # the plain FP32 path where it can keep up (offered rate below its
         # throughput), and per-request calls of the batched path
         if rate < 0.8 * fp32_qps:
@@ -574,6 +656,8 @@ def main():
                     help="skip the serving-loop run on the 10,000,000 x 128 index")
     ap.add_argument("--no-ksweep", action="store_true",
                     help="skip the operating points for k = 1, 50, 100")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the 1,000,000 x 960 low-contrast sweep over c and beta")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -835,8 +919,12 @@ def main():
         log(f"cpu baseline: {cpu}")
     acp = None
     serving = None
-    if not (args.no_acp and args.no_serving):
+    config3 = None
+    if not (args.no_acp and args.no_serving and args.no_config3):
         del idx
+        torch.cuda.empty_cache()
+    if not args.no_config3:
+        config3 = config3_bench(pm, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_acp:
         acp = acp_bench(pm, torch, dev)
@@ -877,6 +965,7 @@ def main():
         "cpu_baseline": cpu,
         "acp": acp,
         "serving": serving,
+        "config3": config3,
     }
     print(json.dumps(out), flush=True)
 

@@ -486,14 +486,25 @@ class Server:
                                                   ctypes.byref(self._h)))
 
     def submit(self, queries, k: int, c: float = 1.5, confidence: float = 1 - 1 / math.e,
-               beta: float = -1.0, r_min: float = 0.0) -> Request:
+               beta: float = -1.0, r_min: float = 0.0, out=None) -> Request:
+        """Queues a request; `out` = (ids int64 (nq, k), dist float32 (nq, k)),
+        contiguous on the queries' device, receives the answers (allocated
+        here when None)."""
         torch = _torch()
         Q = _require_gpu_f32("queries", queries)
         if Q.ndim != 2 or Q.shape[1] != self.index.d:
             raise ValueError(f"queries must be (nq, {self.index.d})")
         nq = Q.shape[0]
-        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
-        dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        else:
+            ids, dist = out
+            for name, t, dt in (("ids", ids, torch.int64), ("dist", dist, torch.float32)):
+                if (t.dtype != dt or t.device != Q.device or tuple(t.shape) != (nq, k)
+                        or not t.is_contiguous()):
+                    raise ValueError(f"out {name} must be a contiguous ({nq}, {k}) {dt} "
+                                     f"tensor on {Q.device}")
         ticket = ctypes.c_uint64(0)
         _check(load_library().pmlsh_server_submit(
             self._h, Q.data_ptr(), nq, k, c, confidence, beta, r_min, ids.data_ptr(),

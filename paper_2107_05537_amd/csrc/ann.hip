@@ -1709,30 +1709,40 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
 // a processor that compares one pair at a time, while the matrix cores
 // compare all pairs of a batch at 16 x 16 x 32 per instruction.
 //
-// Grid: x strides over 64-point chunks, y over blocks of 1,024 queries. Each
-// wave keeps the FP16 rows of its 16 query tiles in registers as B operands
-// (lane l: query 16 t + l % 16, halves 8 (l / 16) .. + 7); the chunk's four
-// 16-point tiles are the A operands. A result register r of lane l holds
-// point 4 (l / 16) + r of the tile and query l % 16.
+// Grid: x strides over 64-point chunks, y over blocks of 1,024 queries; wave
+// w of a workgroup owns a quarter of the block's mask words (256 queries).
+// For each chunk a wave packs the queries whose chunk-ball test passed (the
+// set bits of its mask words) into a list and runs the MFMA on groups of 16
+// listed queries, so a group's 16 columns are all queries that may hold
+// candidates in the chunk (the last group is padded with a row whose product
+// with every point is positive). The FP16 rows of the block's queries sit in
+// LDS as B operands (lane l: listed query 16 g + l % 16, halves
+// 8 (l / 16) .. + 7); the chunk's four 16-point tiles are the A operands
+// (lane l: point 16 t + l % 16, same halves). Halves 24..31 are zero in every
+// point and query row: neither is stored, and lanes 48..63 hold zeros. A
+// result register r of lane l holds point 4 (l / 16) + r of the tile and
+// listed query l % 16.
 
-constexpr int SQB = 1024;               // queries per scan block
-constexpr int SQT = SQB / 16 / NWAVE;   // query tiles per wave
+constexpr int SQB = 512;                // queries per scan block
+constexpr int SQW = SQB / NWAVE;        // queries per wave
+constexpr int SWW = SQW / 64;           // mask words per wave
 constexpr int SSTG = 1024;              // candidates staged per wave
+constexpr int SPAD = SQB;               // index of the padding row
 
-constexpr int SQW = SQT * 16;           // queries per wave
-
-// Per-wave candidate stages: every wave stages, counts and flushes its own
-// candidates, so the scan needs no workgroup barrier.
-struct ScanShared {
+// Query rows, then per-wave candidate stages: every wave packs, stages,
+// counts and flushes its own candidates, so after the rows are loaded the
+// scan needs no workgroup barrier.
+struct __align__(16) ScanShared {
+    uint16_t qrow[SQB + 1][kScanRow];       // FP16 query rows of the block, padding row last
     uint32_t pos[NWAVE][SSTG];          // staged candidates: leaf position
     uint8_t qid[NWAVE][SSTG];           // and query within the wave's range
     uint32_t hits[NWAVE][SQW], base[NWAVE][SQW];
-    uint8_t ovf[NWAVE][SQW];            // query lost candidates to a full stage
+    // queries of the wave passing the chunk, by column: slot 16 g + j of the
+    // list is lcol[j][g]
+    uint8_t lcol[NWAVE][16][SQW / 16];
 };
-
-// Arrays read at wave-uniform addresses and never written by the kernel: the
-// constant address space turns their reads into scalar loads.
-typedef __attribute__((address_space(4))) const uint64_t cuint64;
+static_assert(SWW * 64 == SQW && SWW <= 4, "a wave's queries are whole mask words");
+static_assert(sizeof(ScanShared) <= 53 * 1024, "three scan workgroups per compute unit");
 
 __device__ __forceinline__ half8_t load_half8(const uint16_t* p) {
     return __builtin_bit_cast(half8_t, *reinterpret_cast<const uint4*>(p));
@@ -1744,64 +1754,8 @@ __device__ __forceinline__ void scan_mfma(const half8_t (&av)[4], half8_t b, flo
         cc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[mt], b, float4_t{}, 0, 0, 0);
 }
 
-// Stages the negative results of one 64-point x 16-query block. Register r
-// of the four tiles is tested together first; most register positions hold
-// no candidate.
-__device__ __forceinline__ void scan_emit(ScanShared& ss, int wave, int lane, uint32_t& wn,
-                                          const float4_t (&cc)[4], int64_t p0, int qt) {
-    const int q = qt + (lane & 15);     // query within the wave's range
-    const uint32_t prow = (uint32_t)p0 + 4u * (uint32_t)(lane >> 4);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint32_t z = __float_as_uint(cc[0][r]) | __float_as_uint(cc[1][r]) |
-                           __float_as_uint(cc[2][r]) | __float_as_uint(cc[3][r]);
-        if (!__builtin_amdgcn_ballot_w64((int32_t)z < 0)) continue;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const bool c = __float_as_int(cc[mt][r]) < 0;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(c);
-            if (!m) continue;
-            const uint32_t nh = (uint32_t)__popcll(m);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const uint32_t pos = prow + (uint32_t)(mt * 16 + r);
-            if (wn + nh <= (uint32_t)SSTG) {
-                if (c) {
-                    ss.pos[wave][wn + rank] = pos;
-                    ss.qid[wave][wn + rank] = (uint8_t)q;
-                }
-                wn += nh;
-            } else if (c) {
-                // stage full within one chunk: the query is marked and handed
-                // to the per-query path (its pool count passes the capacity)
-                ss.ovf[wave][q] = 1u;
-            }
-        }
-    }
-}
-
-// The wave's query tiles T, T + 1, ... with compile-time register indices.
-// A tile is computed only when its 16-bit field of the chunk mask (one bit
-// per query) is non-zero.
-template <int T>
-__device__ __forceinline__ void scan_tiles(ScanShared& ss, int wave, int lane, uint32_t& wn,
-                                           const half8_t (&av)[4], const half8_t (&bq)[SQT],
-                                           int nt, int64_t p0, int t0, const uint64_t* cm) {
-    if constexpr (T < SQT) {
-        if (T < nt) {
-            // t0 is a multiple of 4: tile T's field is in word T / 4
-            if ((cm[T >> 2] >> (16 * (T & 3))) & 0xffffull) {
-                float4_t cc[4];
-                scan_mfma(av, bq[T], cc);
-                scan_emit(ss, wave, lane, wn, cc, p0, T * 16);
-            }
-        }
-        scan_tiles<T + 1>(ss, wave, lane, wn, av, bq, nt, p0, t0, cm);
-    }
-}
-
 // Writes the wave's staged candidates to the pool with one reservation per
-// query (queries qw0 .. qw0 + SQW - 1 of the batch) and empties the stage.
+// query (queries qw0 .. qw0 + nqw - 1 of the batch) and empties the stage.
 // Only this wave touches its part of the shared memory.
 __device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared& ss, int wave, int lane, uint32_t& wn,
                            int64_t qw0, int nqw) {
@@ -1810,10 +1764,9 @@ __device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared& ss, int
     for (uint32_t e = lane; e < wn; e += 64) atomicAdd(&hits[ss.qid[wave][e]], 1u);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     for (int e = lane; e < nqw; e += 64) {
-        const uint32_t h = hits[e] + (ss.ovf[wave][e] ? (uint32_t)a.q_cap + 1u : 0u);
+        const uint32_t h = hits[e];
         if (h) base[e] = atomicAdd(&a.l_count[qw0 + e], h);
         hits[e] = 0u;
-        ss.ovf[wave][e] = 0u;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     for (uint32_t e = lane; e < wn; e += 64) {
@@ -1827,80 +1780,163 @@ __device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared& ss, int
     wn = 0;
 }
 
-__global__ __launch_bounds__(WG) void scan_kernel(AnnArgs a) {
+// Stages the negative results of one 64-point x 16-query group (q: the
+// lane's query within the wave's range), flushing the stage first whenever
+// a ballot's candidates would not fit, so no candidate is lost. The group is
+// skipped when no result is negative; otherwise register r of the four tiles
+// is tested together first, since most register positions hold no candidate.
+__device__ __forceinline__ void scan_emit(const AnnArgs& a, ScanShared& ss, int wave, int lane,
+                                          uint32_t& wn, const float4_t (&cc)[4], int64_t p0, int q,
+                                          int64_t qw0, int nqw) {
+    // a result is a candidate when its sign bit is set
+    uint32_t z[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        z[r] = __float_as_uint(cc[0][r]) | __float_as_uint(cc[1][r]) | __float_as_uint(cc[2][r]) |
+               __float_as_uint(cc[3][r]);
+    if (!__builtin_amdgcn_ballot_w64((int32_t)(z[0] | z[1] | z[2] | z[3]) < 0)) return;
+    const uint32_t prow = (uint32_t)p0 + 4u * (uint32_t)(lane >> 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (!__builtin_amdgcn_ballot_w64((int32_t)z[r] < 0)) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bool c = __float_as_int(cc[mt][r]) < 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(c);
+            if (!m) continue;
+            const uint32_t nh = (uint32_t)__popcll(m);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (wn + nh > (uint32_t)SSTG) scan_flush(a, ss, wave, lane, wn, qw0, nqw);
+            if (c) {
+                ss.pos[wave][wn + rank] = prow + (uint32_t)(mt * 16 + r);
+                ss.qid[wave][wn + rank] = (uint8_t)q;
+            }
+            wn += nh;
+        }
+    }
+}
+
+// three workgroups per compute unit: 12 waves to hide the LDS and matrix-core
+// latencies of the group loop
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void scan_kernel(AnnArgs a) {
     __shared__ ScanShared ss;
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int l16 = lane & 15, lq = lane >> 4;
+    const int lq = lane >> 4;
     const int q0 = blockIdx.y * SQB;
     const int nqb = min(SQB, a.nq - q0);
-    const int ntile = (nqb + 15) >> 4;
-    // tiles per wave, a multiple of 4 so that each wave's tiles start on a
-    // 64-query word of the chunk mask
-    const int tpw = (((ntile + NWAVE - 1) / NWAVE) + 3) & ~3;
-    const int t0 = wave * tpw;
-    const int nt = max(0, min(ntile - t0, tpw));
-    for (int e = lane; e < SQW; e += 64) {
-        ss.hits[wave][e] = 0u;
-        ss.ovf[wave][e] = 0u;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int64_t qw0 = (int64_t)q0 + t0 * 16;          // first query of this wave
-    const int nqw = max(0, min(nqb - t0 * 16, nt * 16));  // its queries
+    const int nwq = (nqb + 63) >> 6;            // mask words of this query block
+    // mask words per wave: the block's words split evenly, whole words each
+    const int wpw = (nwq + NWAVE - 1) / NWAVE;
+    const int w0 = wave * wpw;                  // first word of this wave
+    const int nw = max(0, min(nwq - w0, wpw));
+    const int64_t qw0 = (int64_t)q0 + w0 * 64;  // first query of this wave
+    const int nqw = max(0, min(nqb - w0 * 64, nw * 64));   // its queries
 
-    half8_t bq[SQT];
-#pragma unroll
-    for (int t = 0; t < SQT; ++t) {
-        bq[t] = half8_t{};
-        const int qc = (t0 + t) * 16 + l16;
-        if (t < nt && qc < nqb) bq[t] = load_half8(a.qaug + (int64_t)(q0 + qc) * 32 + lq * 8);
+    // the block's query rows (halves 0..23; 16 bytes per thread and step)
+    for (int e = threadIdx.x; e < (SQB + 1) * 3; e += WG) {
+        const int r = e / 3, part = e - 3 * r;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r < nqb) {
+            v = *reinterpret_cast<const uint4*>(a.qaug + (int64_t)(q0 + r) * 32 + part * 8);
+        } else if (r == SPAD && part == 2) {
+            v.y = 0x3c00u;   // half 18 = 1: the product with any point is >= 0
+        }
+        *reinterpret_cast<uint4*>(&ss.qrow[r][part * 8]) = v;
     }
+    for (int e = lane; e < SQW; e += 64) ss.hits[wave][e] = 0u;
+    __syncthreads();
 
     uint32_t wn = 0;
-    // Point chunks, strided over the workgroups. The FP16 rows are loaded two
-    // chunks ahead and the mask words (scalar loads) one chunk ahead.
+    // Point chunks, strided over the workgroups. Four slots of FP16 rows and
+    // mask words are in flight per wave (12 KB of rows); the loop is unrolled
+    // over the slots so that each is refilled in place after its chunk.
     const int64_t nchunk = a.n_pad16 >> 6;
     const int64_t G = gridDim.x;
-    const int nwq = (nqb + 63) >> 6;   // mask words of this query block
-    auto load_rows = [&](int64_t cc, half8_t (&dst)[4]) {
-        if (cc < nchunk) {
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-                dst[mt] = load_half8(a.proj16 + ((cc << 6) + mt * 16 + l16) * 32 + lq * 8);
-        }
+    const int l16 = lane & 15;
+    // lane i packs the two queries 2 i, 2 i + 1 of the wave's range, held in
+    // mask word i / 32 (the 32 lanes of a word load it together)
+    const int pk_word = lane >> 5, pk_shift = 2 * (lane & 31);
+    const bool mword = pk_word < nw;
+    const uint64_t* mbase = a.cmask + (q0 >> 6) + w0 + pk_word;
+    const uint16_t* rbase = a.proj16 + (l16 * kScanRow + lq * 8);
+    const int64_t mstride = a.cwords;
+    struct Slot {
+        half8_t r[4];
+        uint64_t m;
     };
-    auto load_mask = [&](int64_t cc, uint64_t (&dst)[SQT / 4]) {
-        if (cc < nchunk) {
-            cuint64* crow = (cuint64*)(a.cmask + cc * a.cwords + (q0 >> 6));
+    // lanes 48..63 hold halves 24..31 of the A operand, zero in every row
+    auto load = [&](int64_t cc, Slot& dst) {
+        dst.m = 0ull;
 #pragma unroll
-            for (int k = 0; k < SQT / 4; ++k) {
-                const int wi = (t0 >> 2) + k;
-                dst[k] = wi < nwq ? crow[wi] : 0ull;
+        for (int mt = 0; mt < 4; ++mt) dst.r[mt] = half8_t{};
+        if (cc < nchunk) {
+            if (mword) dst.m = mbase[cc * mstride];
+            if (lq < 3) {
+                const uint16_t* rp = rbase + cc * (64 * kScanRow);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) dst.r[mt] = load_half8(rp + mt * 16 * kScanRow);
             }
         }
     };
-    int64_t c = blockIdx.x;
-    half8_t a1[4], a2[4];
-    uint64_t m1[SQT / 4];
-    load_rows(c, a1);
-    load_rows(c + G, a2);
-    load_mask(c, m1);
-    for (; c < nchunk; c += G) {
-        half8_t av[4];
-        uint64_t cm[SQT / 4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            av[mt] = a1[mt];
-            a1[mt] = a2[mt];
+    uint8_t (*lcol)[SQW / 16] = ss.lcol[wave];
+    auto chunk = [&](const Slot& cur, int64_t cc) {
+        // the list of passing queries: each lane's set bits at the count of
+        // set bits in the lanes below it
+        const uint32_t pk = (uint32_t)(cur.m >> pk_shift) & 3u;
+        const uint64_t b0 = __builtin_amdgcn_ballot_w64(pk & 1u);
+        const uint64_t b1 = __builtin_amdgcn_ballot_w64(pk >> 1);
+        const int total = __popcll(b0) + __popcll(b1);
+        if (total == 0) return;
+        uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u)) +
+                      __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
+        if (pk & 1u) {
+            lcol[at & 15][at >> 4] = (uint8_t)(2 * lane);
+            ++at;
         }
-#pragma unroll
-        for (int k = 0; k < SQT / 4; ++k) cm[k] = m1[k];
-        load_rows(c + 2 * G, a2);
-        load_mask(c + G, m1);
-        // room for a chunk's typical candidates; a chunk that alone overflows
-        // the stage marks its queries instead
+        if (pk & 2u) lcol[at & 15][at >> 4] = (uint8_t)(2 * lane + 1);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // room for a chunk's typical candidates (a fuller chunk flushes
+        // inside the emit)
         if (wn > (uint32_t)(SSTG - 256)) scan_flush(a, ss, wave, lane, wn, qw0, nqw);
-        scan_tiles<0>(ss, wave, lane, wn, av, bq, nt, c << 6, t0, cm);
+        const uint8_t* mycol = lcol[l16];
+        // two groups per step: their row reads and matrix products go out
+        // before either result is examined
+        for (int g = 0; g < total; g += 32) {
+            const bool two = g + 16 < total;
+            const int qa = g + l16 < total ? (int)mycol[g >> 4] : -1;
+            const int qb = two && g + 16 + l16 < total ? (int)mycol[(g >> 4) + 1] : -1;
+            half8_t ba = half8_t{}, bb = half8_t{};
+            if (lq < 3) {
+                ba = load_half8(&ss.qrow[qa >= 0 ? w0 * 64 + qa : SPAD][lq * 8]);
+                if (two) bb = load_half8(&ss.qrow[qb >= 0 ? w0 * 64 + qb : SPAD][lq * 8]);
+            }
+            float4_t ca[4], cb[4];
+            scan_mfma(cur.r, ba, ca);
+            if (two) scan_mfma(cur.r, bb, cb);
+            scan_emit(a, ss, wave, lane, wn, ca, cc << 6, qa, qw0, nqw);
+            if (two) scan_emit(a, ss, wave, lane, wn, cb, cc << 6, qb, qw0, nqw);
+        }
+    };
+    int64_t c = blockIdx.x;
+    Slot s0, s1, s2, s3;
+    load(c, s0);
+    load(c + G, s1);
+    load(c + 2 * G, s2);
+    load(c + 3 * G, s3);
+    for (; c < nchunk; c += 4 * G) {
+        chunk(s0, c);
+        load(c + 4 * G, s0);
+        if (c + G >= nchunk) break;
+        chunk(s1, c + G);
+        load(c + 5 * G, s1);
+        if (c + 2 * G >= nchunk) break;
+        chunk(s2, c + 2 * G);
+        load(c + 6 * G, s2);
+        if (c + 3 * G >= nchunk) break;
+        chunk(s3, c + 3 * G);
+        load(c + 7 * G, s3);
     }
     scan_flush(a, ss, wave, lane, wn, qw0, nqw);
 }

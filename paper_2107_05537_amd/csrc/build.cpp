@@ -181,7 +181,7 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
         if (S > 0.f && std::isfinite(S)) (void)std::frexp(S, &e);
         x->scale16 = std::ldexp(1.f, 5 - e);
         x->n_pad16 = (n + 63) / 64 * 64;
-        x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * 32);
+        x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * kScanRow);
         launch_augment16(x->proj_hi, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
         // covering ball of every 64-point chunk of the leaf order (the leaves
         // themselves when the leaf size is 64): FP64 mean rounded to FP32,

@@ -23,6 +23,11 @@ constexpr int MP = 16;
 // scan: 2^-9 bounds the FP16 rounding of the projected dot product, the extra
 // 2^-14 absorbs the rounding of the margin term itself.
 constexpr float kScanMarginWeight = 0.001953125f + 0.00006103515625f;
+// halves per FP16 row of the matrix-core scan: 21 terms (16 coordinates,
+// the hi and lo halves of the norm, two ones and the margin term) padded to
+// a multiple of eight; the eight halves the 32-deep MFMA reads beyond them
+// are zero and are not stored
+constexpr int kScanRow = 24;
 // Chunks the ANN bound may choose per query (64 points each; at least twice
 // the largest budget of the batched path).
 constexpr int kSelCap = 1024;
@@ -222,7 +227,7 @@ struct pmlsh_index {
     float* data = nullptr;       // n x d_pad, zero padded
     float* proj_hi = nullptr;    // n x MP: FP32 rounding of the FP64 projection
     float* proj_lo = nullptr;    // n x MP: FP32 rounding of (projection - hi)
-    uint16_t* proj16 = nullptr;  // n_pad16 x 32 FP16 rows of the matrix-core scan
+    uint16_t* proj16 = nullptr;  // n_pad16 x kScanRow FP16 rows of the matrix-core scan
     int64_t n_pad16 = 0;         // n rounded up to 64
     float scale16 = 1.f;         // power-of-two scale s of those rows
     float* chunk_cen = nullptr;  // n_pad16 / 64 x MP: centre of each 64-point chunk

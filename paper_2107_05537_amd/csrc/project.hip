@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void gather_proj_kernel(
     }
 }
 
-// Rows of the FP16 matrix-core scan, 32 halves per point (the layout is
+// Rows of the FP16 matrix-core scan, kScanRow halves per point (the layout is
 // described with scan_kernel): s * o' (16 dims, pad zero), the hi/lo FP16 pair
 // of s^2 ||o'||^2, two ones that carry the query's threshold pair, and
 // cm * s * ||o'||, the weight of the rounding margin. Rows from n to n_pad are
@@ -134,9 +134,9 @@ __global__ __launch_bounds__(256) void augment16_kernel(
     uint4* __restrict__ out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_pad) return;
-    _Float16 v[32];
+    _Float16 v[kScanRow];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = (_Float16)0.f;
+    for (int i = 0; i < kScanRow; ++i) v[i] = (_Float16)0.f;
     if (p < n) {
         float o[MP];
         float on2 = 0.f;
@@ -156,8 +156,9 @@ __global__ __launch_bounds__(256) void augment16_kernel(
         v[20] = (_Float16)(cm * s * sqrtf(on2));
     }
     const uint4* src = reinterpret_cast<const uint4*>(v);
+    constexpr int kParts = kScanRow / 8;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[p * 4 + i] = src[i];
+    for (int i = 0; i < kParts; ++i) out[p * kParts + i] = src[i];
 }
 
 // FP16 copy of the leaf-order data for the bounded verification: one wave

@@ -162,10 +162,14 @@ def heavy_tailed(seed: int = SEEDS["heavy"], n: int = 1_000_000, d: int = 960,
     drawn the same way."""
     rng = np.random.Generator(np.random.PCG64(seed))
 
-    def rows(count):
-        x = np.abs(rng.standard_normal((count, d))) ** 1.5
-        x *= 100.0 / np.linalg.norm(x, axis=1, keepdims=True)
-        return x.astype(np.float32)
+    def rows(count, block=65_536):
+        # drawn in row blocks (the same numbers as one draw) to bound memory
+        out = np.empty((count, d), dtype=np.float32)
+        for s in range(0, count, block):
+            x = np.abs(rng.standard_normal((min(block, count - s), d))) ** 1.5
+            x *= 100.0 / np.linalg.norm(x, axis=1, keepdims=True)
+            out[s:s + x.shape[0]] = x
+        return out
 
     D = rows(n)
     Q = rows(n_queries)

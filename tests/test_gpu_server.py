@@ -130,6 +130,17 @@ def test_server_errors_and_empty_request(served):
     with pytest.raises(pm.PmlshError) as e:
         srv.submit(Q, pm.MAX_K + 1)
     assert e.value.code in (pm.EINVAL, pm.EUNSUPPORTED)
+    bad = (torch.empty((4, 4), dtype=torch.int64, device=dev),
+           torch.empty((4, 5), dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError):
+        srv.submit(Q, 5, out=bad)
+    # answers into caller-owned tensors equal those of a lone call
+    out = (torch.full((4, 5), -7, dtype=torch.int64, device=dev),
+           torch.full((4, 5), -7.0, dtype=torch.float32, device=dev))
+    ids_o, dist_o = srv.submit(Q, 5, out=out).wait()
+    assert ids_o.data_ptr() == out[0].data_ptr() and dist_o.data_ptr() == out[1].data_ptr()
+    ids_a, dist_a = idx.ann(Q, 5)
+    assert torch.equal(ids_o, ids_a) and torch.equal(dist_o, dist_a)
     h = srv.submit(Q[:0], 5)
     assert h.done()
     ids, dist = h.wait()
