@@ -258,12 +258,33 @@ def config3_bench(pm, torch, dev, cs=(1.2, 1.5, 2.0),
             rows.append(row)
             if el > point_limit_s:
                 break
+    # the mixed-precision filter projection at one point of the sweep
+    mixed = []
+    for name, mode in (("fp16", pm.FILTER_GEMM_FP16), ("bf16", pm.FILTER_GEMM_BF16)):
+        c, beta = 1.5, 0.002
+        idx_m = pm.Index(D, A, filter_gemm=mode)
+        ids0, dist0 = idx.ann(Q, k, c=c, confidence=conf, beta=beta)
+        idx_m.ann(Q[:64], k, c=c, confidence=conf, beta=beta)
+        torch.cuda.synchronize()
+        t_0 = time.perf_counter()
+        ids_m, dist_m = idx_m.ann(Q, k, c=c, confidence=conf, beta=beta)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t_0
+        row = {"filter_gemm": name, "c": c, "beta": beta,
+               "eps_max": round(float(idx_m.info()["eps_max"]), 4),
+               "recall@10": round(recall_at_k(ids_m, truth), 4),
+               "overall_ratio": round(overall_ratio(torch, D, Q, ids_m, truth_dist), 6),
+               "answers_equal_exact_index": bool(torch.equal(ids_m, ids0) and torch.equal(dist_m, dist0)),
+               "queries_per_s": round(Q.shape[0] / el, 1)}
+        log(f"config 3: {row}")
+        mixed.append(row)
+        del idx_m
     del idx
     return {"workload": "heavy-tailed 1,000,000 x 960 (|N(0,1)|^1.5, rows L2-normalised x 100), "
                         f"first {nq_eval} of 10,000 queries, k={k}",
             "truth": "exact kNN in FP64 on the GPU (norm-expansion shortlist of 4k, "
                      "re-ranked by FP64 direct differences)",
-            "build_s": round(build_s, 2), "points": rows}
+            "build_s": round(build_s, 2), "points": rows, "mixed_precision": mixed}
 
 
 def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
@@ -656,6 +677,8 @@ def main():
                     help="skip the serving-loop run on the 10,000,000 x 128 index")
     ap.add_argument("--no-ksweep", action="store_true",
                     help="skip the operating points for k = 1, 50, 100")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP16/BF16 filter-projection runs at the headline point")
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the 1,000,000 x 960 low-contrast sweep over c and beta")
     args = ap.parse_args()
@@ -911,6 +934,50 @@ def main():
                            "overall_ratio": round(ratio_k, 6),
                            "queries_per_s": round(q_k / wall_k, 1)})
 
+    # mixed-precision filter projection at the same operating point: FP16 and
+    # BF16 matrix-core projections behind the filter rows, radius widened by
+    # their bound; answers must equal the exact index's
+    mixed = []
+    if not args.no_mixed:
+        for name, mode in (("fp16", pm.FILTER_GEMM_FP16), ("bf16", pm.FILTER_GEMM_BF16)):
+            idx_m = pm.Index(D, A, filter_gemm=mode)
+            ids_m = torch.empty_like(ids)
+            dist_m = torch.empty_like(dist)
+            for s_, e_ in batches:
+                idx_m.ann_into(Q[s_:e_], K, C, CONF, beta, r_min, ids_m[s_:e_], dist_m[s_:e_],
+                               stats[s_:e_])
+            torch.cuda.synchronize()
+            same = bool(torch.equal(ids_m, ids) and torch.equal(dist_m, dist))
+            pm.ann_timing_read(reset=True)
+            pm.ann_timing_enable(True)
+            for i in range(min(args.steps, 20)):
+                s_, e_ = batches[i % len(batches)]
+                idx_m.ann_into(Q[s_:e_], K, C, CONF, beta, r_min, ids_m[s_:e_], dist_m[s_:e_],
+                               stats[s_:e_])
+            torch.cuda.synchronize()
+            pm.ann_timing_enable(False)
+            tm_m = pm.ann_timing_read(reset=True)
+            torch.cuda.synchronize()
+            t_0 = time.perf_counter()
+            q_m = 0
+            for i in range(args.steps):
+                s_, e_ = batches[i % len(batches)]
+                idx_m.ann_into(Q[s_:e_], K, C, CONF, beta, r_min, ids_m[s_:e_], dist_m[s_:e_],
+                               stats[s_:e_])
+                q_m += e_ - s_
+            torch.cuda.synchronize()
+            qps_m = q_m / (time.perf_counter() - t_0)
+            info_m = idx_m.info()
+            row = {"filter_gemm": name, "eps_max": round(float(info_m["eps_max"]), 5),
+                   "queries_per_s": round(qps_m, 1), "answers_equal_exact_index": same,
+                   "stages_ms_per_batch": {k: round(v["ms"] / max(1, v["launches"]), 4)
+                                           for k, v in tm_m.items()
+                                           if v["launches"] and not k.startswith("acp")}}
+            log(f"mixed precision: {row}")
+            mixed.append(row)
+            del idx_m
+            torch.cuda.empty_cache()
+
     cpu = None
     if pool is not None:
         cpu = cpu_baseline(pool, cpu_workers, n, beta, r_min)
@@ -958,6 +1025,7 @@ def main():
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "per": "batch of up to 1,024 queries, alone on one stream"},
         "other_k": ksweep,
+        "mixed_precision": mixed,
         "roofline": roof,
         "stages_ms_per_batch": {k: round(v["ms"] / max(1, v["launches"]), 4)
                                 for k, v in warm.items() if not k.startswith("acp")},

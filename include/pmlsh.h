@@ -68,9 +68,24 @@ typedef struct pmlsh_index pmlsh_index; /* opaque, owned by the caller once buil
  *   sample_seed  seed of the pair sample that estimates the distance
  *                distribution F used for r_min (Section 5.2).
  *   r_min_kappa  r_min = kappa * F^-1(B/n); in (0, 1]; 0 selects 0.9.
+ *   filter_gemm  projection behind the FP16 rows of the batched range
+ *                filter: 0 rounds the FP64 projection (Eq. 3, Section 3.2);
+ *                PMLSH_FILTER_GEMM_FP16 / _BF16 compute it on the matrix cores
+ *                from FP16 / BF16 inputs with FP32 accumulation (points at
+ *                build, queries per batch), each row with a bound eps on its
+ *                distance to the exact projection; the filter then widens
+ *                its radius by eps(query) + max eps(point), so it still passes
+ *                every point the exact projection would. Every later decision
+ *                (pool distances, budget cut, rounds, verification) uses the
+ *                FP64-accurate projection, so answers do not depend on this
+ *                choice; the pool, and with it the time, grows with the
+ *                widening. EUNSUPPORTED if a value exceeds the input format.
  * Errors: EINVAL (arguments, non-finite values), ENOMEM, EDEVICE,
  * EUNSUPPORTED. On success *out receives the index; free it with pmlsh_free.
  */
+#define PMLSH_FILTER_GEMM_FP16 1
+#define PMLSH_FILTER_GEMM_BF16 2
+
 typedef struct {
     const float* data;
     int64_t n;
@@ -81,7 +96,7 @@ typedef struct {
     int32_t num_pivots;
     int32_t leaf_size;
     int32_t fanout;
-    int32_t reserved;
+    int32_t filter_gemm;
     uint64_t sample_seed;
     double r_min_kappa;
     void* stream;
@@ -400,9 +415,18 @@ typedef struct {
     int64_t n_nodes;      /* all levels                                       */
     int64_t sample_size;  /* pairs in the r_min sample                        */
     int64_t device_bytes; /* HBM held by the index                            */
+    int32_t filter_gemm;  /* as built (0, PMLSH_FILTER_GEMM_FP16 or _BF16)     */
+    float eps_max;        /* largest point bound eps of that projection (0 for 0) */
 } pmlsh_index_info;
 
 int pmlsh_get_index_info(const pmlsh_index* index, pmlsh_index_info* out);
+
+/* The low-precision projection of an index built with filter_gemm != 0, for
+ * checking its bound: recomputes, for every point in id order, the m
+ * coordinates the filter's rows come from (host buffer of n x m floats) and
+ * the bound eps on their Euclidean distance to the exact projection (host
+ * buffer of n floats). EINVAL if the index was built with filter_gemm = 0. */
+int pmlsh_index_filter_projection(const pmlsh_index* index, float* proj, float* eps);
 
 /* Leaf partition of the index, for checking ACP against an independent
  * implementation: leaf b holds the ids perm[offsets[b] .. offsets[b+1]).

@@ -38,7 +38,7 @@ class _BuildArgs(ctypes.Structure):
                 ("hash", ctypes.c_void_p), ("m", ctypes.c_int32),
                 ("data_on_device", ctypes.c_int32), ("num_pivots", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("fanout", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("sample_seed", ctypes.c_uint64),
+                ("filter_gemm", ctypes.c_int32), ("sample_seed", ctypes.c_uint64),
                 ("r_min_kappa", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
@@ -60,7 +60,8 @@ class _Info(ctypes.Structure):
                 ("leaf_size", ctypes.c_int32), ("fanout", ctypes.c_int32),
                 ("num_pivots", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("n_leaves", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
-                ("sample_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("sample_size", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("filter_gemm", ctypes.c_int32), ("eps_max", ctypes.c_float)]
 
 
 class _QueryArgs(ctypes.Structure):
@@ -129,6 +130,8 @@ SIGNATURES = {
     "pmlsh_index_export_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_void_p]),
+    "pmlsh_index_filter_projection": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_void_p]),
     "pmlsh_get_index_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "pmlsh_index_export_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p]),
@@ -200,6 +203,9 @@ def plan_params(n: int, m: int, k: int, c: float, confidence: float, beta: float
     return {f: getattr(out, f) for f, _ in _Plan._fields_}
 
 
+FILTER_GEMM_FP16 = 1          # filter rows from an FP16-input matrix-core projection
+FILTER_GEMM_BF16 = 2          # ... from a BF16-input one
+
 TUNE_GROUP_LIST = 0          # most 64-chunk groups the ANN bound lists per query
 TUNE_GROUP_MINIMA_LDS = 1    # group minima in LDS (1) or read from HBM (0)
 TUNE_FP32_PATH = 2           # 1: whole launches on the plain FP32 per-query kernel
@@ -241,7 +247,8 @@ class Index:
     """
 
     def __init__(self, data, hash, num_pivots: int = 5, leaf_size: int = 64,
-                 fanout: int = 16, sample_seed: int = 0x5EED, r_min_kappa: float = 0.9):
+                 fanout: int = 16, sample_seed: int = 0x5EED, r_min_kappa: float = 0.9,
+                 filter_gemm: int = 0):
         lib = load_library()
         self._h = ctypes.c_void_p()
         args = _BuildArgs()
@@ -273,6 +280,7 @@ class Index:
         args.num_pivots, args.leaf_size, args.fanout = num_pivots, leaf_size, fanout
         args.sample_seed = sample_seed
         args.r_min_kappa = r_min_kappa
+        args.filter_gemm = filter_gemm
         args.stream = stream
         _check(lib.pmlsh_build(ctypes.byref(args), ctypes.byref(self._h)))
         if self.device is None:
@@ -290,6 +298,17 @@ class Index:
         out = _Info()
         _check(load_library().pmlsh_get_index_info(self._h, ctypes.byref(out)))
         return {f: getattr(out, f) for f, _ in _Info._fields_}
+
+    def filter_projection(self):
+        """Low-precision projection behind the filter rows of an index built
+        with filter_gemm != 0, recomputed in id order: (proj (n, m), eps (n,))
+        float32 NumPy arrays, eps bounding each row's distance to the exact
+        projection."""
+        proj = np.empty((self.n, self.m), dtype=np.float32)
+        eps = np.empty(self.n, dtype=np.float32)
+        _check(load_library().pmlsh_index_filter_projection(self._h, proj.ctypes.data,
+                                                            eps.ctypes.data))
+        return proj, eps
 
     def default_r_min(self, budget: int) -> float:
         v = ctypes.c_double()

@@ -64,6 +64,10 @@ struct AnnArgs {
     int d, d_pad;
     int32_t level_begin[MAX_LEVELS + 1];
     float coord_scale;
+    float scan_scale;           // bound on the norm of every scan-row projection
+    const float* qlp;           // low-precision query projections of the filter, or null
+    const float* qeps;          // their bounds
+    float eps_max;              // largest bound of the points' scan-row projections
     const float* q;
     const float* qp;
     const float* qp_lo;         // FP32 rounding of (projection - qp)
@@ -1579,25 +1583,38 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         a.q_scanned[qi] = 0u;   // mask_kernel adds 64 per passing chunk
         a.q_flag[qi] = 0;
         // The query's FP16 row of the matrix-core scan. thr = tau^2 - |q'|^2
-        // plus 96 u (|q'| + S)^2 (S bounds every |o'|) covers the FP32 errors
-        // of the exact pd^2 and of |q'|^2; the further 2^-15 (|q'| + S)^2
-        // covers the FP32 accumulation of the scan and its hi/lo splits.
+        // plus 96 u (|q'| + S)^2 (S bounds every |o'| of a scan row) covers
+        // the FP32 errors of the exact pd^2 and of |q'|^2; the further
+        // 2^-15 (|q'| + S)^2 covers the FP32 accumulation of the scan and its
+        // hi/lo splits. When the rows come from the low-precision projection,
+        // q' is the query's own low-precision projection and tau grows by
+        // eps(query) + eps_max, which bounds how far a point's low-precision
+        // projected distance lies from its exact one.
         const float u = 5.9604645e-08f;   // 2^-24
-        const float qn = sqrtf(qc.qn2);
-        const float big = qn + a.coord_scale;
-        const float thr = (R2 + 96.f * u * big * big) - qc.qn2 + 3.0517578e-05f * big * big;
+        const float* qv = a.qlp ? a.qlp + qi * MP : qc.qp;
+        float qv2 = qc.qn2, R2s = R2;
+        if (a.qlp) {
+            qv2 = 0.f;
+#pragma unroll
+            for (int t = 0; t < MP; ++t) qv2 = fmaf(qv[t], qv[t], qv2);
+            const float tw = (sqrtf(R2) + (a.qeps[qi] + a.eps_max)) * (1.f + 2.384185791015625e-07f);
+            R2s = tw * tw * (1.f + 2.384185791015625e-07f);
+        }
+        const float qn = sqrtf(qv2);
+        const float big = qn + a.scan_scale;
+        const float thr = (R2s + 96.f * u * big * big) - qv2 + 3.0517578e-05f * big * big;
         const float s = a.scale16;
         const float v = -(s * s) * thr;
         float qmax = 0.f;
 #pragma unroll
-        for (int t = 0; t < MP; ++t) qmax = fmaxf(qmax, fabsf(qc.qp[t]));
+        for (int t = 0; t < MP; ++t) qmax = fmaxf(qmax, fabsf(qv[t]));
         const bool ok = fabsf(v) < 30000.f && 2.f * s * qmax < 30000.f && s * qn < 30000.f;
         _Float16 w[32];
 #pragma unroll
         for (int i = 0; i < 32; ++i) w[i] = (_Float16)0.f;
         if (ok) {
 #pragma unroll
-            for (int t = 0; t < MP; ++t) w[t] = (_Float16)(-2.f * s * qc.qp[t]);
+            for (int t = 0; t < MP; ++t) w[t] = (_Float16)(-2.f * s * qv[t]);
             w[16] = (_Float16)1.f;
             w[17] = (_Float16)1.f;
             const _Float16 hi = (_Float16)v;
@@ -2340,6 +2357,10 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     a.d_pad = x.d_pad;
     for (int l = 0; l <= x.levels; ++l) a.level_begin[l] = (int32_t)x.level_begin[l];
     a.coord_scale = x.coord_scale;
+    a.scan_scale = x.scan_scale;
+    a.eps_max = x.eps_max;
+    a.qlp = nullptr;
+    a.qeps = nullptr;
     a.q = L.queries;
     a.qp = L.qproj;
     a.qp_lo = L.qproj_lo;
@@ -2375,6 +2396,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     if (L.fast) {
         a.qaug = L.ws_qaug;
+        a.qlp = L.ws_qlp;
+        a.qeps = L.ws_qeps;
         a.qtest = L.ws_qtest;
         a.cmask = L.ws_cmask;
         a.cwords = (int)((L.nq + 63) / 64);

@@ -64,6 +64,9 @@ static void validate_build(const pmlsh_build_args* a) {
         fail(PMLSH_EINVAL, "fanout must be 0 or a power of two in 2..64");
     if (!(a->r_min_kappa >= 0.0 && a->r_min_kappa <= 1.0))
         fail(PMLSH_EINVAL, "r_min_kappa must be in [0, 1]");
+    if (a->filter_gemm != 0 && a->filter_gemm != PMLSH_FILTER_GEMM_FP16 &&
+        a->filter_gemm != PMLSH_FILTER_GEMM_BF16)
+        fail(PMLSH_EINVAL, "filter_gemm must be 0, PMLSH_FILTER_GEMM_FP16 or PMLSH_FILTER_GEMM_BF16");
     if (!a->data_on_device) {
         // host data: finiteness is checked before anything touches the GPU
         const int64_t total = a->n * (int64_t)a->d;
@@ -87,6 +90,7 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     x->leaf_size = a->leaf_size ? a->leaf_size : 64;
     x->fanout = a->fanout ? a->fanout : 16;
     x->kappa = a->r_min_kappa > 0.0 ? a->r_min_kappa : 0.9;
+    x->filter_gemm = a->filter_gemm;
     PMLSH_HIP(hipGetDevice(&x->device));
     const int64_t n = a->n;
     const int d = a->d;
@@ -174,15 +178,42 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     launch_half_rows(x->data, n, x->d_pad, x->d16, x->data16, x->data16_scale, x->data16_eps, st);
 
     // ---- FP16 rows of the matrix-core scan, scaled by a power of two s with
-    // s * max ||o'|| < 32, so every entry stays far inside the FP16 range
+    // s * max ||o'|| < 32, so every entry stays far inside the FP16 range.
+    // With filter_gemm the rows come from the low-precision projection of the
+    // leaf-order data, whose norms are within eps_max of the exact ones.
     {
+        const float* proj_scan = x->proj_hi;
+        TmpBuf lp, lpe;
+        x->scan_scale = x->coord_scale;
+        if (x->filter_gemm) {
+            PMLSH_HIP(hipMalloc(&lp.p, (size_t)n * MP * sizeof(float)));
+            PMLSH_HIP(hipMalloc(&lpe.p, (size_t)n * sizeof(float)));
+            float* lpp = static_cast<float*>(lp.p);
+            float* lpep = static_cast<float*>(lpe.p);
+            launch_project_lp(x->data, n, d, x->d_pad, x->hash, x->filter_gemm, lpp, lpep, st);
+            if (!device_all_finite(lpp, n * MP, st) || !device_all_finite(lpep, n, st))
+                fail(PMLSH_EUNSUPPORTED, "data exceeds the range of the filter's input format");
+            std::vector<float> e(n);
+            PMLSH_HIP(hipMemcpyAsync(e.data(), lpep, (size_t)n * sizeof(float),
+                                     hipMemcpyDeviceToHost, st));
+            PMLSH_HIP(hipStreamSynchronize(st));
+            float emax = 0.f;
+            for (float v : e) emax = std::max(emax, v);
+            x->eps_max = emax;
+            // an upper bound of the sum (FP32 addition rounded up twice)
+            x->scan_scale = std::nextafter(std::nextafter(x->coord_scale + emax, INFINITY), INFINITY);
+            proj_scan = lpp;
+        }
         int e = 0;
-        const float S = x->coord_scale;
+        const float S = x->scan_scale;
         if (S > 0.f && std::isfinite(S)) (void)std::frexp(S, &e);
         x->scale16 = std::ldexp(1.f, 5 - e);
         x->n_pad16 = (n + 63) / 64 * 64;
         x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * kScanRow);
-        launch_augment16(x->proj_hi, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
+        launch_augment16(proj_scan, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
+        // the temporary projection is released with the scope: the rows are
+        // built first
+        PMLSH_HIP(hipStreamSynchronize(st));
         // covering ball of every 64-point chunk of the leaf order (the leaves
         // themselves when the leaf size is 64): FP64 mean rounded to FP32,
         // radius measured from that FP32 centre in FP64, widened by 1e-6 and

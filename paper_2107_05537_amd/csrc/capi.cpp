@@ -75,7 +75,8 @@ AnnWorkspace ann_workspace_base(const pmlsh_index* x, int k, int64_t B) {
     w.fast = ann_fast_path(B) && tune_get(PMLSH_TUNE_FP32_PATH) == 0;
     w.pool_q = w.fast ? ann_pool_per_query(x->n) : 0;
     w.per_query = (int64_t)MP * 8 + 64 + B * 8 + 3 * (int64_t)k * 4 +
-                  (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0);
+                  (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0) +
+                  (w.fast && x->filter_gemm ? (MP + 1) * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
     w.ldc = cdist_row_len(w.nchunk);
     return w;
@@ -178,12 +179,17 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
     int32_t* q_flag = reinterpret_cast<int32_t*>(clo + (fast ? batch * B : 0));
     uint32_t* l_count = reinterpret_cast<uint32_t*>(q_flag + batch);
     uint32_t* q_scanned = l_count + batch;
+    // low-precision query projections and their bounds (filter_gemm)
+    float* qlp = reinterpret_cast<float*>(q_scanned + batch);
+    float* qeps = qlp + batch * MP;
+    const bool lp = fast && x->filter_gemm != 0;
     for (int64_t q0 = 0; q0 < nq; q0 += batch) {
         const int64_t nb = std::min(batch, nq - q0);
         const float* qb = queries + q0 * x->d;
         {
             StageTimer tm(PMLSH_STAGE_PROJECT, st);
             launch_project(qb, nb, x->d, x->d, x->hash, qproj, qproj_lo, st);
+            if (lp) launch_project_lp(qb, nb, x->d, x->d, x->hash, x->filter_gemm, qlp, qeps, st);
         }
         AnnLaunch L{};
         L.idx = x;
@@ -214,6 +220,8 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
             L.q_flag = q_flag;
             L.l_count = l_count;
             L.q_scanned = q_scanned;
+            L.ws_qlp = lp ? qlp : nullptr;
+            L.ws_qeps = lp ? qeps : nullptr;
             L.l_list = list;
             L.pool_cap = pool_q;
         }
@@ -510,7 +518,36 @@ int pmlsh_get_index_info(const pmlsh_index* index, pmlsh_index_info* out) {
         i.n_nodes = index->n_nodes;
         i.sample_size = (int64_t)index->sample_sorted.size();
         i.device_bytes = index->device_bytes;
+        i.filter_gemm = index->filter_gemm;
+        i.eps_max = index->eps_max;
         *out = i;
+    });
+}
+
+int pmlsh_index_filter_projection(const pmlsh_index* index, float* proj, float* eps) {
+    return guarded([&] {
+        if (!index || !proj || !eps) fail(PMLSH_EINVAL, "NULL argument");
+        if (!index->filter_gemm) fail(PMLSH_EINVAL, "the index was built with filter_gemm = 0");
+        const int64_t n = index->n;
+        PMLSH_HIP(hipSetDevice(index->device));
+        struct Buf {
+            float* p = nullptr;
+            ~Buf() { if (p) (void)hipFree(p); }
+        } dp, de;
+        PMLSH_HIP(hipMalloc(&dp.p, (size_t)n * MP * sizeof(float)));
+        PMLSH_HIP(hipMalloc(&de.p, (size_t)n * sizeof(float)));
+        launch_project_lp(index->data, n, index->d, index->d_pad, index->hash,
+                          index->filter_gemm, dp.p, de.p, nullptr);
+        std::vector<float> hp((size_t)n * MP), he((size_t)n);
+        PMLSH_HIP(hipMemcpy(hp.data(), dp.p, hp.size() * sizeof(float), hipMemcpyDeviceToHost));
+        PMLSH_HIP(hipMemcpy(he.data(), de.p, he.size() * sizeof(float), hipMemcpyDeviceToHost));
+        // leaf order -> id order
+        const int m = index->m;
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t id = index->perm_host[(size_t)j];
+            for (int i = 0; i < m; ++i) proj[id * m + i] = hp[(size_t)j * MP + i];
+            eps[id] = he[(size_t)j];
+        }
     });
 }
 

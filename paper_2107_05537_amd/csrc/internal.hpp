@@ -247,6 +247,12 @@ struct pmlsh_index {
     std::vector<double> sample_sorted;   // ascending pair distances (r_min rule)
     double kappa = 0.9;
     float coord_scale = 0.f;
+    // projection behind the scan rows (0: the FP64 one; else the FP16/BF16
+    // matrix-core one), the largest bound of its points and the bound on the
+    // norm of every scan-row projection (coord_scale + eps_max)
+    int filter_gemm = 0;
+    float eps_max = 0.f;
+    float scan_scale = 0.f;
     // (c,k)-ACP workspace kept between calls: one device buffer per role,
     // grown on demand, freed with the index; calls on one index serialise on
     // the mutex
@@ -304,6 +310,10 @@ void launch_gather_rows(const float* src, int d, int64_t ld_src, const int32_t* 
                         int64_t rows, float* dst, int d_pad, hipStream_t stream);
 void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
                         float* dst, hipStream_t stream);
+// Low-precision projection (FP16 or BF16 inputs, FP32 accumulation) of rows
+// x (stride ld) with its per-row bound eps (mode: PMLSH_FILTER_GEMM_*).
+void launch_project_lp(const float* x, int64_t rows, int d, int64_t ld, const float* hash,
+                       int mode, float* out, float* eps, hipStream_t stream);
 void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm,
                       uint16_t* out, hipStream_t stream);
 void launch_half_rows(const float* data, int64_t n, int d_pad, int d16, uint16_t* out,
@@ -333,6 +343,8 @@ struct AnnLaunch {
     uint32_t* q_scanned;
     uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
     uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
+    float* ws_qlp;          // nq x MP low-precision query projections (filter_gemm), or null
+    float* ws_qeps;         // nq: their bounds
     float2* ws_qtest;       // nq: radius and margin of each query's chunk-ball test
     uint64_t* ws_cmask;     // the same, chunk-major: chunks x ceil(nq / 64) words
     uint16_t* ws_cdist2;    // nq x ldc: squared distances to the chunk centres (bf16, rounded down)

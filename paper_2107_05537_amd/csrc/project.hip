@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace pmlsh {
@@ -96,6 +98,111 @@ __global__ __launch_bounds__(256) void project_kernel(
             out_hi[gr * MP + col] = hi;
             if (out_lo) out_lo[gr * MP + col] = (float)(v - (double)hi);
         }
+    }
+}
+
+// Low-precision projection for the matrix-core filter (mixed-precision
+// configuration): o' = (a_1.o, ..., a_m.o) with every input rounded to FP16
+// or BF16 and the products summed in FP32 on the matrix cores
+// (v_mfma_f32_16x16x32_f16 / _bf16), and per row a bound eps on the
+// Euclidean norm of (o'_lp - o'), o' being the exact projection of the FP32
+// row. With u the unit roundoff of the input format and eta its largest
+// absolute error below the normal range (flushed subnormals included), a
+// rounded input is a~ = a + da with |da| <= u |a| + eta, so
+//   |a~ o~ - a o| <= (2u + u^2) |a o| + (1 + u) eta (|a| + |o|) + eta^2.
+// The product of two rounded inputs is exact in FP32, and summing d of them
+// in FP32 in any order (a truncating adder included, unit 2^-23) adds at most
+// g_d sum |a~ o~|, g_d = d 2^-23 / (1 - d 2^-23). Bounding |a o| through
+// |a~| and |o~| and collecting terms (u <= 2^-8), per coordinate
+//   e_i <= c1 S_i + eta' (A_i + X) + 2 d eta'^2,
+//   c1 = ((2u + u^2) / (1 - u)^2 + g_d) / (1 - g_d),  eta' = 1.02 eta,
+// with S_i the FP32 matrix-core sum of |a~_ij| |o~_j| (at least 1 - g_d
+// times the exact sum), A_i = sum_j |a_ij| and X = sum_j |o_j| (FP32 sums,
+// within the 2% slack of eta'). eps is the FP32 norm of (e_i), enlarged by
+// 2^-16 for the rounding of its own evaluation.
+//
+// One wave projects 16 rows: lane l holds row l % 16 and hash function
+// l % 16 for the inputs k = 32 s + 8 (l / 16) .. + 7 of every 32-wide step.
+template <bool BF16>
+__global__ __launch_bounds__(256) void project_lp_kernel(
+    const float* __restrict__ x, int64_t rows, int d, int64_t ld,
+    const float* __restrict__ hash, float c1, float eta,
+    float* __restrict__ out, float* __restrict__ eps) {
+    typedef __attribute__((ext_vector_type(8))) _Float16 h8;
+    typedef __attribute__((ext_vector_type(8))) __bf16 b8;
+    typedef __attribute__((ext_vector_type(4))) float f4;
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (row0 >= rows) return;
+    const int r = lane & 15, kq = 8 * (lane >> 4);
+    const int64_t gr = row0 + r;
+    const bool rv = gr < rows;
+    f4 acc = {0.f, 0.f, 0.f, 0.f}, accs = {0.f, 0.f, 0.f, 0.f};
+    float xs = 0.f, as = 0.f;   // partial sums of |o_j| (row r) and |a_rj| (function r)
+    for (int k0 = 0; k0 < d; k0 += 32) {
+        float xv[8], hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + kq + e;
+            xv[e] = rv && k < d ? x[gr * ld + k] : 0.f;
+            hv[e] = k < d ? hash[(int64_t)r * d + k] : 0.f;
+            xs += fabsf(xv[e]);
+            as += fabsf(hv[e]);
+        }
+        if constexpr (BF16) {
+            b8 xa, ha, xb, hb;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                xa[e] = (__bf16)xv[e];
+                ha[e] = (__bf16)hv[e];
+                xb[e] = (__bf16)fabsf(xv[e]);
+                hb[e] = (__bf16)fabsf(hv[e]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, ha, acc, 0, 0, 0);
+            accs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb, hb, accs, 0, 0, 0);
+        } else {
+            h8 xa, ha, xb, hb;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                xa[e] = (_Float16)xv[e];
+                ha[e] = (_Float16)hv[e];
+                xb[e] = (_Float16)fabsf(xv[e]);
+                hb[e] = (_Float16)fabsf(hv[e]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(xa, ha, acc, 0, 0, 0);
+            accs = __builtin_amdgcn_mfma_f32_16x16x32_f16(xb, hb, accs, 0, 0, 0);
+        }
+    }
+    // the four lanes of a row (function) hold quarters of its sums
+    xs += __shfl_xor(xs, 16);
+    xs += __shfl_xor(xs, 32);
+    as += __shfl_xor(as, 16);
+    as += __shfl_xor(as, 32);
+    // result register i of lane l: row 4 (l / 16) + i, function l % 16
+    const int fn = lane & 15;
+    const float a_sum = as;   // lane l holds A for function l % 16
+    float e2[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = 4 * (lane >> 4) + i;
+        const float x_sum = __shfl(xs, rr);   // lane rr holds X of row rr
+        // a zero hash row (m < 16) projects exactly to zero
+        const float e = a_sum > 0.f ? c1 * accs[i] + eta * (a_sum + x_sum) + 2.f * (float)d * eta * eta
+                                    : 0.f;
+        e2[i] = e * e;
+        const int64_t g = row0 + rr;
+        if (g < rows) out[g * MP + fn] = acc[i];
+    }
+    // norm over the 16 functions: the 16 lanes of each quarter
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float v = e2[i];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        const int64_t g = row0 + 4 * (lane >> 4) + i;
+        if (fn == 0 && g < rows) eps[g] = sqrtf(v) * (1.f + 1.52587890625e-05f);
     }
 }
 
@@ -245,6 +352,27 @@ void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
     if (rows <= 0) return;
     hipLaunchKernelGGL(gather_proj_kernel, dim3(grid_for(rows * MP)), dim3(256), 0,
                        stream, src, perm, rows, dst);
+    PMLSH_HIP(hipGetLastError());
+}
+
+void launch_project_lp(const float* x, int64_t rows, int d, int64_t ld, const float* hash,
+                       int mode, float* out, float* eps, hipStream_t stream) {
+    if (rows <= 0) return;
+    // unit roundoff and largest absolute error below the normal range
+    const double u = mode == PMLSH_FILTER_GEMM_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -11);
+    const double eta = mode == PMLSH_FILTER_GEMM_BF16 ? std::ldexp(1.0, -126) : std::ldexp(1.0, -14);
+    const double ud = (double)d * std::ldexp(1.0, -23);
+    const double gd = ud / (1.0 - ud);
+    const double c1 = ((2.0 * u + u * u) / ((1.0 - u) * (1.0 - u)) + gd) / (1.0 - gd);
+    const float c1f = (float)(c1 * (1.0 + 1e-6));
+    const float etaf = (float)(1.02 * eta);
+    const unsigned grid = (unsigned)((rows + 63) / 64);
+    if (mode == PMLSH_FILTER_GEMM_BF16)
+        hipLaunchKernelGGL(project_lp_kernel<true>, dim3(grid), dim3(256), 0, stream, x, rows, d,
+                           ld, hash, c1f, etaf, out, eps);
+    else
+        hipLaunchKernelGGL(project_lp_kernel<false>, dim3(grid), dim3(256), 0, stream, x, rows, d,
+                           ld, hash, c1f, etaf, out, eps);
     PMLSH_HIP(hipGetLastError());
 }
 

@@ -97,6 +97,7 @@ def _build_args(**kw):
 @pytest.mark.parametrize("kw", [
     {"n": 0}, {"d": 0}, {"m": 0}, {"m": 17}, {"num_pivots": 9}, {"num_pivots": -1},
     {"leaf_size": 4}, {"leaf_size": 300}, {"fanout": 3}, {"fanout": 128},
+    {"filter_gemm": 3}, {"filter_gemm": -1},
     {"r_min_kappa": 1.5}, {"data": None}, {"hash": None},
 ])
 def test_build_rejects_before_touching_gpu(lib, kw):
