@@ -91,6 +91,7 @@ struct AnnArgs {
     // leaf-major fast path (per query): radius bound, its square and test
     // slack, fallback flag, candidate count, scanned points, candidate list
     int32_t* q_flag;
+    uint32_t* pq_list;          // count, then the queries flagged for the per-query kernel
     uint32_t* l_count;          // candidates per query
     uint32_t* q_scanned;
     uint32_t* l_list;           // nq x q_cap leaf positions (candidate pool)
@@ -976,8 +977,16 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
     // lists of slot b (G = gridDim.x slots)
     int32_t* fa = a.ws_front + (int64_t)blockIdx.x * 2 * a.n_leaves;
     int32_t* fb = fa + a.n_leaves;
+    if (a.pq_list) {
+        // the queries the batched path flagged
+        const uint32_t npq = a.pq_list[0];
+        for (uint32_t j = blockIdx.x; j < npq; j += gridDim.x) {
+            __syncthreads();
+            ann_one(a, (int64_t)a.pq_list[1 + j], fa, fb, qs, sh);
+        }
+        return;
+    }
     for (int64_t qi = blockIdx.x; qi < a.nq; qi += gridDim.x) {
-        if (a.q_flag && a.q_flag[qi] == 0) continue;   // answered by the leaf-major path
         __syncthreads();
         ann_one(a, qi, fa, fb, qs, sh);
     }
@@ -1582,6 +1591,7 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         a.l_count[qi] = 0u;
         a.q_scanned[qi] = 0u;   // mask_kernel adds 64 per passing chunk
         a.q_flag[qi] = 0;
+        if (qi == 0) a.pq_list[0] = 0u;   // the flagged list of the batch starts empty
         // The query's FP16 row of the matrix-core scan. thr = tau^2 - |q'|^2
         // plus 96 u (|q'| + S)^2 (S bounds every |o'| of a scan row) covers
         // the FP32 errors of the exact pd^2 and of |q'|^2; the further
@@ -2045,7 +2055,10 @@ __global__ __launch_bounds__(WG) void finish_kernel(AnnArgs a) {
     const uint32_t cnt = a.l_count[qi];
     if (cnt > (uint32_t)a.q_cap || cnt < (uint32_t)B) {
         // list overflow, or the bound fell short: the per-query kernel answers
-        if (threadIdx.x == 0) a.q_flag[qi] = 1;
+        if (threadIdx.x == 0) {
+            a.q_flag[qi] = 1;
+            a.pq_list[1 + atomicAdd(&a.pq_list[0], 1u)] = (uint32_t)qi;
+        }
         return;
     }
     QueryCtx qc;
@@ -2406,6 +2419,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.goff = cdist_row_offset_groups(x.n_pad16 / 64);
         a.ws_clo = L.ws_clo;
         a.q_flag = L.q_flag;
+        a.pq_list = L.pq_list;
         a.l_count = L.l_count;
         a.q_scanned = L.q_scanned;
         a.l_list = L.l_list;

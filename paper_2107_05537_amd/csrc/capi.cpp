@@ -63,7 +63,7 @@ int64_t front_slots(const pmlsh_index* x, bool fast, int64_t batch) {
 int64_t ann_layout_bytes(const pmlsh_index* x, const AnnWorkspace& w, int64_t batch,
                          int64_t slots) {
     const int64_t mask_bytes =
-        w.fast ? batch * (8 + 2 * w.ldc) + w.nchunk * ((batch + 63) / 64) * 8 : 0;
+        w.fast ? batch * (8 + 2 * w.ldc) + w.nchunk * ((batch + 63) / 64) * 8 + 64 : 0;
     return batch * w.per_query + mask_bytes + slots * 2 * x->n_leaves * 4;
 }
 
@@ -75,7 +75,7 @@ AnnWorkspace ann_workspace_base(const pmlsh_index* x, int k, int64_t B) {
     w.fast = ann_fast_path(B) && tune_get(PMLSH_TUNE_FP32_PATH) == 0;
     w.pool_q = w.fast ? ann_pool_per_query(x->n) : 0;
     w.per_query = (int64_t)MP * 8 + 64 + B * 8 + 3 * (int64_t)k * 4 +
-                  (w.fast ? 3 * 4 + w.pool_q * 4 + B * 4 : 0) +
+                  (w.fast ? 4 * 4 + w.pool_q * 4 + B * 4 : 0) +
                   (w.fast && x->filter_gemm ? (MP + 1) * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
     w.ldc = cdist_row_len(w.nchunk);
@@ -179,8 +179,10 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
     int32_t* q_flag = reinterpret_cast<int32_t*>(clo + (fast ? batch * B : 0));
     uint32_t* l_count = reinterpret_cast<uint32_t*>(q_flag + batch);
     uint32_t* q_scanned = l_count + batch;
+    // count, then the queries the batched path hands to the per-query kernel
+    uint32_t* pq_list = q_scanned + batch;
     // low-precision query projections and their bounds (filter_gemm)
-    float* qlp = reinterpret_cast<float*>(q_scanned + batch);
+    float* qlp = reinterpret_cast<float*>(pq_list + batch + 1);
     float* qeps = qlp + batch * MP;
     const bool lp = fast && x->filter_gemm != 0;
     for (int64_t q0 = 0; q0 < nq; q0 += batch) {
@@ -220,6 +222,7 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
             L.q_flag = q_flag;
             L.l_count = l_count;
             L.q_scanned = q_scanned;
+            L.pq_list = pq_list;
             L.ws_qlp = lp ? qlp : nullptr;
             L.ws_qeps = lp ? qeps : nullptr;
             L.l_list = list;

@@ -341,6 +341,7 @@ struct AnnLaunch {
     int32_t* q_flag;
     uint32_t* l_count;
     uint32_t* q_scanned;
+    uint32_t* pq_list;      // count, then the queries flagged for the per-query kernel
     uint32_t* l_list;       // nq x pool_cap leaf positions (candidate pool)
     uint16_t* ws_qaug;      // nq x 32 FP16 query rows of the matrix-core scan
     float* ws_qlp;          // nq x MP low-precision query projections (filter_gemm), or null

@@ -121,8 +121,10 @@ __global__ __launch_bounds__(256) void project_kernel(
 // within the 2% slack of eta'). eps is the FP32 norm of (e_i), enlarged by
 // 2^-16 for the rounding of its own evaluation.
 //
-// One wave projects 16 rows: lane l holds row l % 16 and hash function
-// l % 16 for the inputs k = 32 s + 8 (l / 16) .. + 7 of every 32-wide step.
+// A workgroup projects 16 rows; its four waves take the 32-wide input steps
+// in turn (wave w: steps w, w + 4, ...) and the partial tiles are summed in
+// LDS. Lane l holds row l % 16 and hash function l % 16 for the inputs
+// k = 32 s + 8 (l / 16) .. + 7 of a step.
 template <bool BF16>
 __global__ __launch_bounds__(256) void project_lp_kernel(
     const float* __restrict__ x, int64_t rows, int d, int64_t ld,
@@ -131,15 +133,15 @@ __global__ __launch_bounds__(256) void project_lp_kernel(
     typedef __attribute__((ext_vector_type(8))) _Float16 h8;
     typedef __attribute__((ext_vector_type(8))) __bf16 b8;
     typedef __attribute__((ext_vector_type(4))) float f4;
-    const int lane = threadIdx.x & 63;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (row0 >= rows) return;
+    __shared__ float part[3][64][10];   // waves 1..3: acc, accs, xs, as per lane
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * 16;
     const int r = lane & 15, kq = 8 * (lane >> 4);
     const int64_t gr = row0 + r;
     const bool rv = gr < rows;
     f4 acc = {0.f, 0.f, 0.f, 0.f}, accs = {0.f, 0.f, 0.f, 0.f};
     float xs = 0.f, as = 0.f;   // partial sums of |o_j| (row r) and |a_rj| (function r)
-    for (int k0 = 0; k0 < d; k0 += 32) {
+    for (int k0 = 32 * wave; k0 < d; k0 += 128) {
         float xv[8], hv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -172,6 +174,30 @@ __global__ __launch_bounds__(256) void project_lp_kernel(
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(xa, ha, acc, 0, 0, 0);
             accs = __builtin_amdgcn_mfma_f32_16x16x32_f16(xb, hb, accs, 0, 0, 0);
         }
+    }
+    if (wave > 0) {
+        float* p = part[wave - 1][lane];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            p[i] = acc[i];
+            p[4 + i] = accs[i];
+        }
+        p[8] = xs;
+        p[9] = as;
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    // the sums over the waves, in a fixed order
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        const float* p = part[w][lane];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            acc[i] += p[i];
+            accs[i] += p[4 + i];
+        }
+        xs += p[8];
+        as += p[9];
     }
     // the four lanes of a row (function) hold quarters of its sums
     xs += __shfl_xor(xs, 16);
@@ -366,7 +392,7 @@ void launch_project_lp(const float* x, int64_t rows, int d, int64_t ld, const fl
     const double c1 = ((2.0 * u + u * u) / ((1.0 - u) * (1.0 - u)) + gd) / (1.0 - gd);
     const float c1f = (float)(c1 * (1.0 + 1e-6));
     const float etaf = (float)(1.02 * eta);
-    const unsigned grid = (unsigned)((rows + 63) / 64);
+    const unsigned grid = (unsigned)((rows + 15) / 16);
     if (mode == PMLSH_FILTER_GEMM_BF16)
         hipLaunchKernelGGL(project_lp_kernel<true>, dim3(grid), dim3(256), 0, stream, x, rows, d,
                            ld, hash, c1f, etaf, out, eps);
