@@ -287,7 +287,7 @@ def config3_bench(pm, torch, dev, cs=(1.2, 1.5, 2.0),
             "build_s": round(build_s, 2), "points": rows, "mixed_precision": mixed}
 
 
-def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
+def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3, with_variants=True):
     """(c,k)-ACP on 200,000 x 512 with 2,000 planted near-duplicate pairs:
     time per call for each k (index built beforehand, data resident in HBM),
     recall and overall ratio (Eqs. 12-14) against the exact k closest pairs
@@ -376,7 +376,7 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3):
     variants = []
     k_v = 10
     exact = pl[order[:k_v]]
-    for beta_v in (-1.0, 1e-4):
+    for beta_v in ((-1.0, 1e-4) if with_variants else ()):
         for name, fn in (("canonical", lambda: idx.acp(k_v, c=c, beta=beta_v)),
                          ("branch_and_bound", lambda: idx.acp_bb(k_v, c=c, beta=beta_v)),
                          ("radius_filtering_lca", lambda: idx.acp_lca(k_v, c=c, beta=beta_v))):
@@ -677,6 +677,8 @@ def main():
                     help="skip the serving-loop run on the 10,000,000 x 128 index")
     ap.add_argument("--no-ksweep", action="store_true",
                     help="skip the operating points for k = 1, 50, 100")
+    ap.add_argument("--no-acp-variants", action="store_true",
+                    help="skip the branch-and-bound and FindLCA ACP variants (profiler runs)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP16/BF16 filter-projection runs at the headline point")
     ap.add_argument("--no-config3", action="store_true",
@@ -994,7 +996,7 @@ def main():
         config3 = config3_bench(pm, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_acp:
-        acp = acp_bench(pm, torch, dev)
+        acp = acp_bench(pm, torch, dev, with_variants=not args.no_acp_variants)
         torch.cuda.empty_cache()
     if not args.no_serving:
         serving = serving_bench(pm, torch, dev)

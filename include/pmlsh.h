@@ -358,8 +358,9 @@ void pmlsh_server_destroy(pmlsh_server* server);
  * the T = beta*n(n-1)/2 + k pairs (capped at n(n-1)/2) with the smallest
  * projected distances over all pairs, ties by (i, j), are verified and the k
  * with the smallest exact distance (ties by (i, j)) are returned. Arguments,
- * outputs and errors as pmlsh_acp; EUNSUPPORTED when more than 2^28 pairs
- * lie within the T-th smallest projected distance. In stats, ub is that
+ * outputs and errors as pmlsh_acp; EUNSUPPORTED when T exceeds 2^28 (known
+ * before any GPU work) or more than 2^28 pairs lie within the T-th smallest
+ * projected distance. In stats, ub is that
  * distance's bound d_T used by the scan, n_seed is 0, n_cand_raw the pairs
  * within d_T, n_cand = T. Synchronous.
  */

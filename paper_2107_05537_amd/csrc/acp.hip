@@ -1709,6 +1709,9 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     const int64_t T = std::min<int64_t>(plan.acp_budget, n_pairs);
     constexpr int64_t kMaxCand = int64_t(1) << 28;
     if (NL > 65535) fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
+    // the T projected-closest pairs are collected at once: a larger budget
+    // cannot be served, which is known before any scan
+    if (T > kMaxCand) fail(PMLSH_EUNSUPPORTED, "the budget T exceeds the 2^28 pairs one call collects");
 
     std::lock_guard<std::mutex> lock(x->acp_mu);
     if ((int)x->acp_bufs.size() < S_COUNT_ALL) x->acp_bufs.resize(S_COUNT_ALL, {nullptr, 0});

@@ -264,6 +264,24 @@ def test_branch_and_bound_matches_oracle(beta):
                                        rerun=rerun))
 
 
+def test_branch_and_bound_budget_above_its_cap_fails_at_once():
+    """T above the 2^28 pairs one branch-and-bound call collects is rejected
+    before any scan: 24,000 points at beta = 1 give T = 287,988,000."""
+    import time
+    pm = _gpu()
+    say("case: ACP branch and bound, T above 2^28")
+    rng = np.random.Generator(np.random.PCG64(8))
+    D = rng.standard_normal((24_000, 8)).astype(np.float32)
+    A = rng.standard_normal((15, 8)).astype(np.float32)
+    idx = _index(pm, D, A)
+    t0 = time.perf_counter()
+    with pytest.raises(pm.PmlshError) as e:
+        idx.acp_bb(10, c=1.5, beta=1.0)
+    assert e.value.code == pm.EUNSUPPORTED
+    assert "2^28" in str(e.value)
+    assert time.perf_counter() - t0 < 1.0
+
+
 @pytest.mark.parametrize("scale,extra", [(1.0, None), (40.0, None), (40.0, 20)])
 def test_radius_filtering_lca_matches_oracle(scale, extra):
     """Algorithms 4-5: FindLCA with gamma, live ub per node. gamma is the
