@@ -264,6 +264,34 @@ def test_branch_and_bound_matches_oracle(beta):
                                        rerun=rerun))
 
 
+def test_every_tile_and_pair_on_long_rows():
+    """20,000 points in leaves of 8 (2,500 leaves, rows of up to 2,500
+    tiles: the tile filter flushes its LDS row buffer mid-row and the wave
+    scan walks long contiguous runs) through branch and bound at beta = 1,
+    so every tile and every pair is kept: the counts are the full triangle
+    and the answer is the exact k closest pairs."""
+    from oracle import brute
+    pm = _gpu()
+    say("case: ACP branch and bound, 2,500 leaves of 8, every pair")
+    rng = np.random.Generator(np.random.PCG64(21))
+    n, d, k = 20_000, 8, 10
+    D = rng.standard_normal((n, d)).astype(np.float32)
+    A = rng.standard_normal((15, d)).astype(np.float32)
+    idx = _index(pm, D, A, leaf_size=8)
+    NL = idx.info()["n_leaves"]
+    assert NL == 2500
+    pairs, dist, st = idx.acp_bb(k, c=1.5, beta=1.0)
+    torch.cuda.synchronize()
+    assert st["tiles_scanned"] == NL * (NL + 1) // 2
+    assert st["n_cand_raw"] == n * (n - 1) // 2
+    ep, ed = brute.closest_pairs(D, k + 1)
+    got_d = dist.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got_d, ed[:k], rtol=TOL)
+    gaps = np.diff(ed) / ed[1:]
+    if gaps.min() > 1e-5:
+        assert pairs.cpu().numpy().tolist() == ep[:k].tolist()
+
+
 def test_branch_and_bound_budget_above_its_cap_fails_at_once():
     """T above the 2^28 pairs one branch-and-bound call collects is rejected
     before any scan: 24,000 points at beta = 1 give T = 287,988,000."""
