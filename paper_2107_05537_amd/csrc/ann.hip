@@ -1750,10 +1750,20 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
 // result register r of lane l holds point 4 (l / 16) + r of the tile and
 // listed query l % 16.
 
-constexpr int SQB = 512;                // queries per scan block
+#ifndef PMLSH_SCAN_QB
+#define PMLSH_SCAN_QB 512
+#endif
+#ifndef PMLSH_SCAN_STAGE
+#define PMLSH_SCAN_STAGE 1024
+#endif
+#ifndef PMLSH_SCAN_WAVES_PER_EU
+#define PMLSH_SCAN_WAVES_PER_EU 3
+#endif
+constexpr int SQB = PMLSH_SCAN_QB;      // queries per scan block
 constexpr int SQW = SQB / NWAVE;        // queries per wave
 constexpr int SWW = SQW / 64;           // mask words per wave
-constexpr int SSTG = 1024;              // candidates staged per wave
+constexpr int QPL = SQW / 64;           // queries per lane in the list building
+constexpr int SSTG = PMLSH_SCAN_STAGE;  // candidates staged per wave
 constexpr int SPAD = SQB;               // index of the padding row
 
 // Query rows, then per-wave candidate stages: every wave packs, stages,
@@ -1769,7 +1779,8 @@ struct __align__(16) ScanShared {
     uint8_t lcol[NWAVE][16][SQW / 16];
 };
 static_assert(SWW * 64 == SQW && SWW <= 4, "a wave's queries are whole mask words");
-static_assert(sizeof(ScanShared) <= 53 * 1024, "three scan workgroups per compute unit");
+static_assert(sizeof(ScanShared) * PMLSH_SCAN_WAVES_PER_EU <= 160 * 1024,
+              "the scan workgroups of a compute unit fit its LDS");
 
 __device__ __forceinline__ half8_t load_half8(const uint16_t* p) {
     return __builtin_bit_cast(half8_t, *reinterpret_cast<const uint4*>(p));
@@ -1844,9 +1855,7 @@ __device__ __forceinline__ void scan_emit(const AnnArgs& a, ScanShared& ss, int 
     }
 }
 
-// three workgroups per compute unit: 12 waves to hide the LDS and matrix-core
-// latencies of the group loop
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void scan_kernel(AnnArgs a) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PMLSH_SCAN_WAVES_PER_EU))) void scan_kernel(AnnArgs a) {
     __shared__ ScanShared ss;
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1882,9 +1891,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void sc
     const int64_t nchunk = a.n_pad16 >> 6;
     const int64_t G = gridDim.x;
     const int l16 = lane & 15;
-    // lane i packs the two queries 2 i, 2 i + 1 of the wave's range, held in
-    // mask word i / 32 (the 32 lanes of a word load it together)
-    const int pk_word = lane >> 5, pk_shift = 2 * (lane & 31);
+    // lane i packs the QPL queries QPL i .. QPL i + QPL - 1 of the wave's
+    // range, held in mask word i / (64 / QPL) (those lanes load it together)
+    const int pk_word = lane / (64 / QPL), pk_shift = QPL * (lane % (64 / QPL));
     const bool mword = pk_word < nw;
     const uint64_t* mbase = a.cmask + (q0 >> 6) + w0 + pk_word;
     const uint16_t* rbase = a.proj16 + (l16 * kScanRow + lq * 8);
@@ -1911,18 +1920,23 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void sc
     auto chunk = [&](const Slot& cur, int64_t cc) {
         // the list of passing queries: each lane's set bits at the count of
         // set bits in the lanes below it
-        const uint32_t pk = (uint32_t)(cur.m >> pk_shift) & 3u;
-        const uint64_t b0 = __builtin_amdgcn_ballot_w64(pk & 1u);
-        const uint64_t b1 = __builtin_amdgcn_ballot_w64(pk >> 1);
-        const int total = __popcll(b0) + __popcll(b1);
-        if (total == 0) return;
-        uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u)) +
-                      __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
-        if (pk & 1u) {
-            lcol[at & 15][at >> 4] = (uint8_t)(2 * lane);
-            ++at;
+        const uint32_t pk = (uint32_t)(cur.m >> pk_shift) & ((1u << QPL) - 1u);
+        int total = 0;
+        uint32_t at = 0;
+#pragma unroll
+        for (int b = 0; b < QPL; ++b) {
+            const uint64_t bb = __builtin_amdgcn_ballot_w64((pk >> b) & 1u);
+            total += __popcll(bb);
+            at += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u));
         }
-        if (pk & 2u) lcol[at & 15][at >> 4] = (uint8_t)(2 * lane + 1);
+        if (total == 0) return;
+#pragma unroll
+        for (int b = 0; b < QPL; ++b)
+            if ((pk >> b) & 1u) {
+                lcol[at & 15][at >> 4] = (uint8_t)(QPL * lane + b);
+                ++at;
+            }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // room for a chunk's typical candidates (a fuller chunk flushes
         // inside the emit)
