@@ -64,7 +64,8 @@ struct AnnArgs {
     int d, d_pad;
     int32_t level_begin[MAX_LEVELS + 1];
     float coord_scale;
-    float scan_scale;           // bound on the norm of every scan-row projection
+    float scan_scale;           // bound on |o' - scen| over the scan rows
+    float scen[MP];             // centre of the scan rows
     const float* qlp;           // low-precision query projections of the filter, or null
     const float* qeps;          // their bounds
     float eps_max;              // largest bound of the points' scan-row projections
@@ -1592,21 +1593,25 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         a.q_scanned[qi] = 0u;   // mask_kernel adds 64 per passing chunk
         a.q_flag[qi] = 0;
         if (qi == 0) a.pq_list[0] = 0u;   // the flagged list of the batch starts empty
-        // The query's FP16 row of the matrix-core scan. thr = tau^2 - |q'|^2
-        // plus 96 u (|q'| + S)^2 (S bounds every |o'| of a scan row) covers
-        // the FP32 errors of the exact pd^2 and of |q'|^2; the further
+        // The query's FP16 row of the matrix-core scan, q' taken relative to
+        // the centre of the rows. thr = tau^2 - |q'|^2 plus 96 u (|q'| + S)^2
+        // (S bounds every |o'| of a scan row) covers the FP32 errors of the
+        // exact pd^2, of the centring and of |q'|^2; the further
         // 2^-15 (|q'| + S)^2 covers the FP32 accumulation of the scan and its
         // hi/lo splits. When the rows come from the low-precision projection,
         // q' is the query's own low-precision projection and tau grows by
         // eps(query) + eps_max, which bounds how far a point's low-precision
         // projected distance lies from its exact one.
         const float u = 5.9604645e-08f;   // 2^-24
-        const float* qv = a.qlp ? a.qlp + qi * MP : qc.qp;
-        float qv2 = qc.qn2, R2s = R2;
-        if (a.qlp) {
-            qv2 = 0.f;
+        const float* qsrc = a.qlp ? a.qlp + qi * MP : qc.qp;
+        float qv[MP];
+        float qv2 = 0.f, R2s = R2;
 #pragma unroll
-            for (int t = 0; t < MP; ++t) qv2 = fmaf(qv[t], qv[t], qv2);
+        for (int t = 0; t < MP; ++t) {
+            qv[t] = qsrc[t] - a.scen[t];
+            qv2 = fmaf(qv[t], qv[t], qv2);
+        }
+        if (a.qlp) {
             const float tw = (sqrtf(R2) + (a.qeps[qi] + a.eps_max)) * (1.f + 2.384185791015625e-07f);
             R2s = tw * tw * (1.f + 2.384185791015625e-07f);
         }
@@ -2385,6 +2390,7 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
     for (int l = 0; l <= x.levels; ++l) a.level_begin[l] = (int32_t)x.level_begin[l];
     a.coord_scale = x.coord_scale;
     a.scan_scale = x.scan_scale;
+    for (int t = 0; t < MP; ++t) a.scen[t] = x.scan_centre[t];
     a.eps_max = x.eps_max;
     a.qlp = nullptr;
     a.qeps = nullptr;

@@ -177,43 +177,9 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
     x->data16_eps = dev_alloc<float>(x, n);
     launch_half_rows(x->data, n, x->d_pad, x->d16, x->data16, x->data16_scale, x->data16_eps, st);
 
-    // ---- FP16 rows of the matrix-core scan, scaled by a power of two s with
-    // s * max ||o'|| < 32, so every entry stays far inside the FP16 range.
-    // With filter_gemm the rows come from the low-precision projection of the
-    // leaf-order data, whose norms are within eps_max of the exact ones.
+    // ---- chunk balls, then the FP16 rows of the matrix-core scan
     {
-        const float* proj_scan = x->proj_hi;
-        TmpBuf lp, lpe;
-        x->scan_scale = x->coord_scale;
-        if (x->filter_gemm) {
-            PMLSH_HIP(hipMalloc(&lp.p, (size_t)n * MP * sizeof(float)));
-            PMLSH_HIP(hipMalloc(&lpe.p, (size_t)n * sizeof(float)));
-            float* lpp = static_cast<float*>(lp.p);
-            float* lpep = static_cast<float*>(lpe.p);
-            launch_project_lp(x->data, n, d, x->d_pad, x->hash, x->filter_gemm, lpp, lpep, st);
-            if (!device_all_finite(lpp, n * MP, st) || !device_all_finite(lpep, n, st))
-                fail(PMLSH_EUNSUPPORTED, "data exceeds the range of the filter's input format");
-            std::vector<float> e(n);
-            PMLSH_HIP(hipMemcpyAsync(e.data(), lpep, (size_t)n * sizeof(float),
-                                     hipMemcpyDeviceToHost, st));
-            PMLSH_HIP(hipStreamSynchronize(st));
-            float emax = 0.f;
-            for (float v : e) emax = std::max(emax, v);
-            x->eps_max = emax;
-            // an upper bound of the sum (FP32 addition rounded up twice)
-            x->scan_scale = std::nextafter(std::nextafter(x->coord_scale + emax, INFINITY), INFINITY);
-            proj_scan = lpp;
-        }
-        int e = 0;
-        const float S = x->scan_scale;
-        if (S > 0.f && std::isfinite(S)) (void)std::frexp(S, &e);
-        x->scale16 = std::ldexp(1.f, 5 - e);
         x->n_pad16 = (n + 63) / 64 * 64;
-        x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * kScanRow);
-        launch_augment16(proj_scan, n, x->n_pad16, x->scale16, kScanMarginWeight, x->proj16, st);
-        // the temporary projection is released with the scope: the rows are
-        // built first
-        PMLSH_HIP(hipStreamSynchronize(st));
         // covering ball of every 64-point chunk of the leaf order (the leaves
         // themselves when the leaf size is 64): FP64 mean rounded to FP32,
         // radius measured from that FP32 centre in FP64, widened by 1e-6 and
@@ -234,6 +200,66 @@ pmlsh_index* index_build(const pmlsh_build_args* a) {
             crad[(size_t)c] = std::nextafter((float)(r64[(size_t)c] * (1.0 + 1e-6)), INFINITY);
         upload(ccen, &x->chunk_cen);
         upload(crad, &x->chunk_rad);
+
+        // The scan rows are centred on mu, the mean of the projected points
+        // (from the chunk centres weighted by their counts, FP64, rounded to
+        // FP32): distances do not change, and the rounding margin of the
+        // FP16 products, which grows with |o' - mu| |q' - mu|, shrinks when
+        // the data sits away from the origin. S bounds every |o' - mu|: the
+        // largest |centre - mu| + radius over the chunks (FP64, widened by
+        // 1e-6, rounded up).
+        double mu64[MP] = {};
+        for (int64_t c = 0; c < nch; ++c) {
+            const double w = (double)(c1[(size_t)c] - c0[(size_t)c]);
+            for (int t = 0; t < MP; ++t) mu64[t] += w * (double)ccen[(size_t)(c * MP + t)];
+        }
+        for (int t = 0; t < MP; ++t) x->scan_centre[t] = (float)(mu64[t] / (double)n);
+        double smax = 0.0;
+        for (int64_t c = 0; c < nch; ++c) {
+            double s2 = 0.0;
+            for (int t = 0; t < MP; ++t) {
+                const double dd = (double)ccen[(size_t)(c * MP + t)] - (double)x->scan_centre[t];
+                s2 += dd * dd;
+            }
+            smax = std::max(smax, std::sqrt(s2) + (double)crad[(size_t)c]);
+        }
+        x->scan_scale = std::nextafter((float)(smax * (1.0 + 1e-6)), INFINITY);
+
+        // FP16 rows scaled by a power of two s with s * S < 32, so every
+        // entry stays far inside the FP16 range. With filter_gemm the rows
+        // come from the low-precision projection of the leaf-order data,
+        // whose points are within eps_max of the exact ones.
+        const float* proj_scan = x->proj_hi;
+        TmpBuf lp, lpe;
+        if (x->filter_gemm) {
+            PMLSH_HIP(hipMalloc(&lp.p, (size_t)n * MP * sizeof(float)));
+            PMLSH_HIP(hipMalloc(&lpe.p, (size_t)n * sizeof(float)));
+            float* lpp = static_cast<float*>(lp.p);
+            float* lpep = static_cast<float*>(lpe.p);
+            launch_project_lp(x->data, n, d, x->d_pad, x->hash, x->filter_gemm, lpp, lpep, st);
+            if (!device_all_finite(lpp, n * MP, st) || !device_all_finite(lpep, n, st))
+                fail(PMLSH_EUNSUPPORTED, "data exceeds the range of the filter's input format");
+            std::vector<float> e(n);
+            PMLSH_HIP(hipMemcpyAsync(e.data(), lpep, (size_t)n * sizeof(float),
+                                     hipMemcpyDeviceToHost, st));
+            PMLSH_HIP(hipStreamSynchronize(st));
+            float emax = 0.f;
+            for (float v : e) emax = std::max(emax, v);
+            x->eps_max = emax;
+            // an upper bound of the sum (FP32 addition rounded up twice)
+            x->scan_scale = std::nextafter(std::nextafter(x->scan_scale + emax, INFINITY), INFINITY);
+            proj_scan = lpp;
+        }
+        int e = 0;
+        const float S = x->scan_scale;
+        if (S > 0.f && std::isfinite(S)) (void)std::frexp(S, &e);
+        x->scale16 = std::ldexp(1.f, 5 - e);
+        x->proj16 = dev_alloc<uint16_t>(x, x->n_pad16 * kScanRow);
+        launch_augment16(proj_scan, n, x->n_pad16, x->scale16, kScanMarginWeight, x->scan_centre,
+                         x->proj16, st);
+        // the temporary projection is released with the scope: the rows are
+        // built first
+        PMLSH_HIP(hipStreamSynchronize(st));
     }
 
     // ---- r_min sample (Section 5.2): FP64 distances of sampled pairs

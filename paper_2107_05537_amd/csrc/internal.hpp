@@ -252,7 +252,8 @@ struct pmlsh_index {
     // norm of every scan-row projection (coord_scale + eps_max)
     int filter_gemm = 0;
     float eps_max = 0.f;
-    float scan_scale = 0.f;
+    float scan_scale = 0.f;      // bound on |o' - scan_centre| over the scan rows
+    float scan_centre[pmlsh::MP] = {};  // centre of the scan rows (mean projected point)
     // (c,k)-ACP workspace kept between calls: one device buffer per role,
     // grown on demand, freed with the index; calls on one index serialise on
     // the mutex
@@ -314,7 +315,7 @@ void launch_gather_proj(const float* src, const int32_t* perm, int64_t rows,
 // x (stride ld) with its per-row bound eps (mode: PMLSH_FILTER_GEMM_*).
 void launch_project_lp(const float* x, int64_t rows, int d, int64_t ld, const float* hash,
                        int mode, float* out, float* eps, hipStream_t stream);
-void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm,
+void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm, const float* centre,
                       uint16_t* out, hipStream_t stream);
 void launch_half_rows(const float* data, int64_t n, int d_pad, int d16, uint16_t* out,
                       float* scale, float* eps, hipStream_t stream);

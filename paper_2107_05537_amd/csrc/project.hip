@@ -258,12 +258,17 @@ __global__ __launch_bounds__(256) void gather_proj_kernel(
 }
 
 // Rows of the FP16 matrix-core scan, kScanRow halves per point (the layout is
-// described with scan_kernel): s * o' (16 dims, pad zero), the hi/lo FP16 pair
+// described with scan_kernel), o' taken relative to the centre mu of the
+// rows: s * o' (16 dims, pad zero), the hi/lo FP16 pair
 // of s^2 ||o'||^2, two ones that carry the query's threshold pair, and
 // cm * s * ||o'||, the weight of the rounding margin. Rows from n to n_pad are
 // zero, which never produce a candidate.
+struct Centre {
+    float v[MP];
+};
+
 __global__ __launch_bounds__(256) void augment16_kernel(
-    const float* __restrict__ proj, int64_t n, int64_t n_pad, float s, float cm,
+    const float* __restrict__ proj, int64_t n, int64_t n_pad, float s, float cm, Centre mu,
     uint4* __restrict__ out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_pad) return;
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(256) void augment16_kernel(
         float on2 = 0.f;
 #pragma unroll
         for (int t = 0; t < MP; ++t) {
-            o[t] = proj[p * MP + t];
+            o[t] = proj[p * MP + t] - mu.v[t];
             on2 = fmaf(o[t], o[t], on2);
         }
 #pragma unroll
@@ -402,11 +407,13 @@ void launch_project_lp(const float* x, int64_t rows, int d, int64_t ld, const fl
     PMLSH_HIP(hipGetLastError());
 }
 
-void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm,
+void launch_augment16(const float* proj, int64_t n, int64_t n_pad, float s, float cm, const float* centre,
                       uint16_t* out, hipStream_t stream) {
     if (n_pad <= 0) return;
+    Centre mu{};
+    for (int t = 0; t < MP; ++t) mu.v[t] = centre[t];
     hipLaunchKernelGGL(augment16_kernel, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0,
-                       stream, proj, n, n_pad, s, cm, reinterpret_cast<uint4*>(out));
+                       stream, proj, n, n_pad, s, cm, mu, reinterpret_cast<uint4*>(out));
     PMLSH_HIP(hipGetLastError());
 }
 

@@ -183,6 +183,23 @@ def test_heavy_tailed_d960(c):
     say("exit kinds", np.bincount(st[:, 2], minlength=3), "rounds", np.bincount(st[:, 0]))
 
 
+def test_data_far_from_the_origin():
+    """The parity mixture shifted by +30 in every coordinate (the projected
+    points then sit far from the origin): the scan rows are centred on the
+    mean projected point, and answers must match the oracle's."""
+    pm = _gpu()
+    say("case: data offset +30")
+    w = synth.parity(n=6000, n_queries=40)
+    D = (w["D"] + 30.0).astype(np.float32)
+    Q = (w["Q"] + 30.0).astype(np.float32)
+    A = w["A"]
+    res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=1.0)
+    r0 = oracle_r_min(D, 3, B)
+    res, _ = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=r0)
+    _, ids, dist, st = _run(pm, D, A, Q, 10, 1.5, 0.9, 0.1, r0, sample_seed=3)
+    compare_ann(D, Q, res, ids, dist, st, fp64=True)
+
+
 @pytest.mark.parametrize("scale", [1e-4, 1e4])
 def test_data_scale_extremes(scale):
     """The same mixture scaled by 1e-4 and 1e4: the FP16 scan rows, the bf16
