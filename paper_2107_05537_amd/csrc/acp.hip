@@ -1,7 +1,11 @@
 // (c,k)-ACP by radius filtering (Section 6.3) on gfx950.
 //
-//   seeds    every pair inside one leaf, exact FP32 squared distance by direct
-//            differences (acp_self_join_kernel);
+//   seeds    every pair inside one leaf: lower and upper bounds of its squared
+//            distance from an FP16 matrix-core Gram kernel, and the exact FP32
+//            distance of the seeds that can reach the top-k (leaves of at most
+//            64 points; acp_seed_gram_kernel), else exact FP32 squared
+//            distances by direct differences for all (acp_seed_join_kernel,
+//            acp_self_join_kernel);
 //   ub       the k-th smallest seed distance (device-wide radix select);
 //   tiles    leaf pairs (e1 < e2) whose Mindist of Eq. 11 can fall below
 //            t*ub (acp_tile_filter_kernel), a lossless skip of whole leaf pairs;
@@ -665,6 +669,48 @@ __global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__
     for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
 }
 
+// The need-th smallest of the first min(*dev_count, cap) keys, by one
+// workgroup (three radix passes of 11, 11 and 10 bits over keys that stay in
+// L2); the key is left in state->prefix (all 32 bits).
+__global__ __launch_bounds__(WG) void acp_kth_small_kernel(const uint32_t* __restrict__ keys,
+                                                           int64_t cap,
+                                                           const unsigned long long* __restrict__ dev_count,
+                                                           int64_t need, SelState* __restrict__ state) {
+    __shared__ uint32_t h[NB];
+    __shared__ int s_bin;
+    __shared__ int64_t s_cum;
+    const int64_t real = (int64_t)*dev_count;
+    const int64_t cnt = real < cap ? real : cap;
+    uint32_t prefix = 0;
+    int pbits = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+        const int width = pass < 2 ? 11 : 10;
+        const int shift = 32 - pbits - width;
+        const uint32_t mask = (1u << width) - 1u;
+        for (int i = threadIdx.x; i < NB; i += WG) h[i] = 0;
+        if (threadIdx.x == 0) {
+            s_bin = (1 << width) - 1;
+            s_cum = 0;
+        }
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < cnt; e += WG) {
+            const uint32_t x = keys[e];
+            if (pbits == 0 || (x >> (32 - pbits)) == prefix) atomicAdd(&h[(x >> shift) & mask], 1u);
+        }
+        __syncthreads();
+        pick_bin(h, need, &s_bin, &s_cum);
+        prefix = (prefix << width) | (uint32_t)s_bin;
+        pbits += width;
+        need -= s_cum;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        state->prefix = prefix;
+        state->pbits = 32;
+        state->need = need;
+    }
+}
+
 // Self-join of leaves of at most 64 points, one workgroup per leaf: the
 // squared distance of every pair a < b, FP32 direct differences. The
 // triangle of 4 x 4 point blocks (136 blocks) is split over two halves of
@@ -774,6 +820,221 @@ __global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
         if (hist[i]) atomicAdd(&ghist[i], hist[i]);
 }
 
+// Seed bounds of leaves of at most 64 points on the FP16 matrix cores: the
+// squared distances by the Gram identity |a - b|^2 = |a|^2 + |b|^2 - 2 a.b,
+// over the leaf's rows taken relative to its first point x0, scaled by the
+// power of two sc = 1 / (2 S) (S the largest FP16-row scale of the leaf, so
+// every |a_i - x0_i| sc < 2^15) and rounded to FP16: a~ = fp16(sc fl(a - x0)).
+// One workgroup per leaf. The 64 x 64 Gram matrix is the ten 16 x 16 tiles on
+// or above the diagonal (v_mfma_f32_16x16x32_f16, FP32 sums), three, three,
+// two and two per wave; the rows pass through LDS 32 coordinates at a time,
+// their loads issued two steps ahead.
+//
+// Bounds (rigorous, in scaled units, K the coordinates summed):
+//   rounding to FP16 and the FP32 centring: |a~ - sc (a - x0)| <= rho_a =
+//     4.9e-4 |a~| + 1.02 2^-14 sqrt(K) (the last term covers inputs below the
+//     FP16 normal range, flushed or not);
+//   FP32 sums of K exact FP16 products in any order (a truncating adder
+//     included): |G_ab - a~.b~| <= g_K |a~| |b~|, g_K = K 2^-23 / (1 - K 2^-23),
+//     so |a~| <= A_a = sqrt(G_aa / (1 - g_K));
+//   d2 = (G_aa + G_bb) - 2 G_ab lies within E = (g_K + 2^-22) (A_a + A_b)^2 of
+//     |a~ - b~|^2.
+// So sc |a - b| lies in [sqrt(d2 - E) - rho_a - rho_b, sqrt(d2 + E) + rho_a +
+// rho_b]. Both ends, squared and divided by sc^2 (widened by 2^-18 for their
+// own FP32 evaluation), are written as the pair's bounds (FP32 bit patterns)
+// in the triangular layout of seed_off; the top 11 bits of every upper bound
+// go to ghist (first radix pass of the k-th smallest upper bound).
+constexpr int SG_LD = 40;   // LDS row stride of the staged FP16 rows, in halves
+
+__global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
+    const float* __restrict__ data, int d_pad, const float* __restrict__ row_scale, int64_t n,
+    int L, const int64_t* __restrict__ seed_off, float gk, uint32_t* __restrict__ hi_out,
+    uint32_t* __restrict__ lo_out, uint32_t* __restrict__ ghist) {
+    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    __shared__ __align__(16) _Float16 xs[2][64][SG_LD];
+    __shared__ float gnorm[64], anorm[64], rho[64];
+    __shared__ float s_sc;
+    const int64_t leaf = blockIdx.x;
+    const int64_t p0 = leaf * L;
+    const int cnt = (int)(n - p0 < L ? n - p0 : L);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    // staging: thread t converts coordinates 8 (t % 4) .. + 7 of row t / 4
+    const int r = t >> 2, q = (t & 3) * 8;
+    const bool rv = r < cnt;
+    const float* rowp = data + (p0 + (rv ? r : 0)) * d_pad;
+    const float* x0p = data + p0 * d_pad;
+    struct Stage { float4 a0, a1, z0, z1; };
+    auto ld4 = [&](const float* p, int c) {
+        return c < d_pad ? *reinterpret_cast<const float4*>(p + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto load = [&](Stage& s, int k0) {
+        s.a0 = ld4(rowp, k0 + q);
+        s.a1 = ld4(rowp, k0 + q + 4);
+        s.z0 = ld4(x0p, k0 + q);
+        s.z1 = ld4(x0p, k0 + q + 4);
+    };
+    const int nst = (d_pad + 31) / 32;
+    Stage s0, s1;
+    load(s0, 0);
+    if (nst > 1) load(s1, 32);
+    if (wave == 0) {
+        float s = lane < cnt ? row_scale[p0 + lane] : 0.f;
+        for (int off = 32; off > 0; off >>= 1) s = fmaxf(s, __shfl_xor(s, off));
+        if (lane == 0) s_sc = 0.5f / s;
+    }
+    __syncthreads();
+    const float sc = s_sc;
+    auto store = [&](const Stage& s, int buf) {
+        h8 v;
+        v[0] = (_Float16)(__fsub_rn(s.a0.x, s.z0.x) * sc);
+        v[1] = (_Float16)(__fsub_rn(s.a0.y, s.z0.y) * sc);
+        v[2] = (_Float16)(__fsub_rn(s.a0.z, s.z0.z) * sc);
+        v[3] = (_Float16)(__fsub_rn(s.a0.w, s.z0.w) * sc);
+        v[4] = (_Float16)(__fsub_rn(s.a1.x, s.z1.x) * sc);
+        v[5] = (_Float16)(__fsub_rn(s.a1.y, s.z1.y) * sc);
+        v[6] = (_Float16)(__fsub_rn(s.a1.z, s.z1.z) * sc);
+        v[7] = (_Float16)(__fsub_rn(s.a1.w, s.z1.w) * sc);
+        if (!rv) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
+        }
+        *reinterpret_cast<h8*>(&xs[buf][r][q]) = v;
+    };
+    // the wave's tiles (bi, bj): w0 (0,0) (1,1) (0,1), w1 (2,2) (3,3) (2,3),
+    // w2 (0,2) (0,3), w3 (1,2) (1,3)
+    const int nt = wave < 2 ? 3 : 2;
+    int bi[3], bj[3];
+    if (wave < 2) {
+        bi[0] = 2 * wave; bj[0] = 2 * wave;
+        bi[1] = 2 * wave + 1; bj[1] = 2 * wave + 1;
+        bi[2] = 2 * wave; bj[2] = 2 * wave + 1;
+    } else {
+        bi[0] = wave - 2; bj[0] = 2;
+        bi[1] = wave - 2; bj[1] = 3;
+        bi[2] = 0; bj[2] = 0;
+    }
+    f4v acc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    auto mma = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (j < nt) {
+                const h8 fa = *reinterpret_cast<const h8*>(&xs[buf][16 * bi[j] + l16][8 * lq]);
+                const h8 fb = *reinterpret_cast<const h8*>(&xs[buf][16 * bj[j] + l16][8 * lq]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, fb, acc[j], 0, 0, 0);
+            }
+        }
+    };
+    // stage st is in buffer st % 2; s0 holds the even stages, s1 the odd ones
+    auto step = [&](int st, Stage& nxt) {
+        mma(st & 1);
+        if (st + 1 < nst) {
+            store(nxt, (st + 1) & 1);
+            if (st + 3 < nst) load(nxt, 32 * (st + 3));
+        }
+        __syncthreads();
+    };
+    store(s0, 0);
+    if (nst > 2) load(s0, 64);
+    __syncthreads();
+    for (int st = 0; st < nst; st += 2) {
+        step(st, s1);
+        if (st + 1 < nst) step(st + 1, s0);
+    }
+
+    // the squared norms from the diagonal tiles; the staging area becomes the
+    // histogram
+    uint32_t* hist = reinterpret_cast<uint32_t*>(&xs[0][0][0]);
+    static_assert(sizeof(xs) >= NB * sizeof(uint32_t), "the histogram reuses the staging area");
+    for (int i = t; i < NB; i += WG) hist[i] = 0;
+    if (wave < 2) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (l16 == 4 * lq + v) gnorm[16 * bi[j] + l16] = acc[j][v];
+    }
+    __syncthreads();
+    const float Kf = (float)(32 * nst);
+    if (t < 64) {
+        const float A = sqrtf(fmaxf(gnorm[t], 0.f) / (1.f - gk)) * (1.f + 9.5367431640625e-07f);
+        anorm[t] = A;
+        rho[t] = 4.9e-4f * A + 1.02f * 6.103515625e-05f * sqrtf(Kf) * (1.f + 9.5367431640625e-07f);
+    }
+    __syncthreads();
+    const float ek = (gk + 2.384185791015625e-07f) * (1.f + 3.814697265625e-06f);
+    const float inv = 1.f / sc;            // a power of two: exact
+    const float up = 1.f + 3.814697265625e-06f, dn = 1.f - 3.814697265625e-06f;
+    const int64_t out0 = seed_off[leaf];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (j < nt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * bi[j] + 4 * lq + v, b = 16 * bj[j] + l16;
+                if (a < b && b < cnt) {
+                    const float d2 = (gnorm[a] + gnorm[b]) - 2.f * acc[j][v];
+                    const float sA = anorm[a] + anorm[b];
+                    const float E = ek * sA * sA;
+                    const float rr = rho[a] + rho[b];
+                    const float sh = sqrtf(fmaxf(d2 + E, 0.f)) * up + rr;
+                    const float sl = sqrtf(fmaxf(d2 - E, 0.f)) * dn - rr * up;
+                    const float hi = (sh * inv) * (sh * inv) * up;
+                    const float lo = sl > 0.f ? (sl * inv) * (sl * inv) * dn : 0.f;
+                    const uint32_t hb = __float_as_uint(hi);
+                    const int64_t p = out0 + (int64_t)a * (2 * cnt - a - 1) / 2 + (b - a - 1);
+                    hi_out[p] = hb;
+                    lo_out[p] = __float_as_uint(lo);
+                    atomicAdd(&hist[hb >> 21], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < NB; i += WG)
+        if (hist[i]) atomicAdd(&ghist[i], hist[i]);
+}
+
+// Seeds whose lower bound is at most U (1 + widen), U the upper edge of the
+// radix bin that holds the k-th smallest upper bound (the selection's prefix
+// of state->pbits bits), or every seed when all is set: their ids (i < j)
+// are appended, one workgroup per leaf.
+__global__ __launch_bounds__(WG) void acp_seed_gram_band_kernel(
+    const uint32_t* __restrict__ lo, const int64_t* __restrict__ seed_off,
+    const int32_t* __restrict__ perm, int64_t n, int L, const SelState* __restrict__ state,
+    float widen, int all, uint32_t* __restrict__ oii, uint32_t* __restrict__ ojj, int64_t cap,
+    unsigned long long* __restrict__ counter) {
+    const int64_t leaf = blockIdx.x;
+    const int64_t p0 = leaf * L;
+    const int cnt = (int)(n - p0 < L ? n - p0 : L);
+    const int P = cnt * (cnt - 1) / 2;
+    const int64_t off = seed_off[leaf];
+    float lim = INFINITY;
+    if (!all) {
+        const int pb = state->pbits;
+        const uint32_t low = pb >= 32 ? 0u : (1u << (32 - pb)) - 1u;
+        const uint32_t top = pb >= 32 ? state->prefix : state->prefix << (32 - pb);
+        lim = __uint_as_float(top | low) * (1.f + widen) * (1.f + 3.814697265625e-06f);
+    }
+    for (int base = 0; base < P; base += WG) {
+        const int p = base + threadIdx.x;
+        const bool take = p < P && __uint_as_float(lo[off + p]) <= lim;
+        uint32_t i = 0, j = 0;
+        if (take) {
+            int a = 0, rem = p;
+            while (rem >= cnt - 1 - a) { rem -= cnt - 1 - a; ++a; }
+            const uint32_t ia = (uint32_t)perm[p0 + a], ib = (uint32_t)perm[p0 + a + 1 + rem];
+            i = ia < ib ? ia : ib;
+            j = ia < ib ? ib : ia;
+        }
+        const int64_t slot = wave_append_global(take, counter);
+        if (take && slot < cap) { oii[slot] = i; ojj[slot] = j; }
+    }
+}
+
 __global__ __launch_bounds__(WG) void acp_sel_hist_kernel(
     const uint32_t* __restrict__ keys, int64_t count, const SelState* __restrict__ state,
     int shift, int width, uint32_t* __restrict__ ghist) {
@@ -827,12 +1088,25 @@ __global__ __launch_bounds__(WG) void acp_seed_band_kernel(
 }
 
 // ---------------------------------------------------------------- verify
+// Exact FP32 squared distance of `count` pairs (16 lanes per pair). With
+// dev_count the pairs are the first min(*dev_count, count) and the keys of the
+// rest of the `count` slots are set to +inf bits (ignored by a selection of
+// a rank within the real pairs).
 __global__ __launch_bounds__(WG) void acp_verify_kernel(
     const float* __restrict__ data, int d_pad, const int32_t* __restrict__ inv_perm,
     const uint32_t* __restrict__ cii, const uint32_t* __restrict__ cjj, int64_t count,
-    uint32_t* __restrict__ k0, uint32_t* __restrict__ ii, uint32_t* __restrict__ jj) {
+    uint32_t* __restrict__ k0, uint32_t* __restrict__ ii, uint32_t* __restrict__ jj,
+    const unsigned long long* __restrict__ dev_count) {
     const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
     const int d4 = d_pad >> 2;
+    if (dev_count) {
+        const int64_t real = (int64_t)*dev_count;
+        const int64_t lim = real < count ? real : count;
+        for (int64_t e = lim + (int64_t)blockIdx.x * WG + threadIdx.x; e < count;
+             e += (int64_t)gridDim.x * WG)
+            k0[e] = 0xffffffffu;
+        count = lim;
+    }
     for (int64_t base = (int64_t)blockIdx.x * (WG / 16); base < count;
          base += (int64_t)gridDim.x * (WG / 16)) {
         const int64_t e = base + g;
@@ -1196,7 +1470,7 @@ __global__ void acp_sel_init_kernel(SelState* state, int64_t need) {
 enum Slot {
     S_HIST, S_COUNT, S_DOFF, S_TILES, S_PPD, S_SEEDS, S_CAND = S_SEEDS + 3, S_KEPT = S_CAND + 3,
     S_POOL = S_KEPT + 3, S_TOP = S_POOL + 3, S_SPD = S_TOP + 3, S_SIDX, S_STATE, S_GHIST,
-    S_COUNT_ALL
+    S_SLO, S_STATE2, S_BAND, S_COUNT_ALL = S_BAND + 3
 };
 
 struct DevBuf {
@@ -1288,16 +1562,18 @@ SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, in
 // followed by the pick kernel; the key is left in state->prefix and ghist is
 // left cleared. With first_done the first pass (top 11 bits) is already in
 // ghist (the self-join adds it); otherwise ghist must be clear on entry.
+// With passes < 3 only the leading 11 or 22 bits of the key are resolved
+// (state->pbits of them in state->prefix).
 void sel_init(SelState* state, int64_t need, hipStream_t st) {
     hipLaunchKernelGGL(acp_sel_init_kernel, dim3(1), dim3(1), 0, st, state, need);
     PMLSH_HIP(hipGetLastError());
 }
 
 void device_select(const uint32_t* keys, int64_t count, int64_t need, SelState* state,
-                   uint32_t* ghist, bool first_done, hipStream_t st) {
+                   uint32_t* ghist, bool first_done, hipStream_t st, int passes = 3) {
     sel_init(state, need, st);
     const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         if (pass > 0 || !first_done) {
             hipLaunchKernelGGL(acp_sel_hist_kernel, dim3(grid_for(count, WG * 16)), dim3(WG), 0,
                                st, keys, count, state, shifts[pass], widths[pass], ghist);
@@ -1507,41 +1783,24 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         PMLSH_HIP(hipStreamSynchronize(st));
         return (int64_t)v;
     };
-    // ---- seeds: every within-leaf pair (distance bits only; the ids of the
-    // few seeds the top-k can use are recovered from their position)
+    // ---- seeds: every within-leaf pair
     std::vector<int64_t> seed_off(NL + 1, 0);
     for (int64_t b = 0; b < NL; ++b) {
         const int64_t cnt = std::min<int64_t>(L, n - b * L);
         seed_off[b + 1] = seed_off[b] + cnt * (cnt - 1) / 2;
     }
     const int64_t n_seed = seed_off[NL];
-    Triplets seeds(x, S_SEEDS);
-    DevBuf doff(x, S_DOFF);
-    bool first_done = false;
+    Triplets seeds(x, S_SEEDS), band(x, S_BAND);
+    DevBuf doff(x, S_DOFF), slo(x, S_SLO);
+    double ub = HUGE_VAL;
+    uint32_t ub2_bits = 0x7f800000u;
     PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
     if (n_seed > 0) {
-        seeds.k0.alloc((size_t)n_seed * 4);
-        if (L > 64) {
-            seeds.ii.alloc((size_t)n_seed * 4);
-            seeds.jj.alloc((size_t)n_seed * 4);
-        }
         doff.alloc((NL + 1) * sizeof(int64_t));
         PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
                                  hipMemcpyHostToDevice, st));
-        StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
-        first_done = launch_self_join(x, doff.as<int64_t>(), seeds.k0.as<uint32_t>(),
-                                      L > 64 ? seeds.ii.as<uint32_t>() : nullptr,
-                                      L > 64 ? seeds.jj.as<uint32_t>() : nullptr,
-                                      ghist.as<uint32_t>(), st);
     }
-
-    // ---- ub: k-th smallest seed distance (selected on the device)
-    double ub = HUGE_VAL;
-    uint32_t ub2_bits = 0x7f800000u;
-    if (n_seed >= k) {
-        StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
-        device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
-                      ghist.as<uint32_t>(), first_done, st);
+    auto read_ub = [&] {
         SelState hs{};
         PMLSH_HIP(hipMemcpyAsync(&hs, dstate.p, sizeof(hs), hipMemcpyDeviceToHost, st));
         PMLSH_HIP(hipStreamSynchronize(st));
@@ -1549,6 +1808,114 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         float ub2;
         std::memcpy(&ub2, &ub2_bits, 4);
         ub = std::sqrt((double)ub2);
+    };
+
+    // Leaves of at most 64 points: bounds of every seed from the FP16 Gram
+    // kernel, U >= the k-th smallest upper bound, and exact FP32 distances
+    // (the verify kernel's) for the band of seeds whose lower bound is at most
+    // U (1 + 8 gamma) only. The k seeds of smallest exact distance lie in the
+    // band (their lower bounds are at most U), so its k-th FP32 distance ub2
+    // is at most U (1 + gamma / 2), and any seed outside the band has an FP32
+    // distance above U (1 + 8 gamma) (1 - gamma / 2) > ub2 (1 + 4 gamma): ub2
+    // is the k-th FP32 seed distance over all seeds, and the band holds every
+    // seed the pool takes. A band above band_max (mass ties) falls back to
+    // the direct self-join.
+    const double gamma_v = pool_gamma(x, false);
+    const int gram_k = 32 * ((x->d_pad + 31) / 32);
+    bool gram = false;
+    int64_t n_band = 0;
+    if (n_seed > 0 && L <= 64 && gram_k <= 65536) {
+        seeds.k0.alloc((size_t)n_seed * 4);
+        slo.alloc((size_t)n_seed * 4);
+        const double ukd = (double)gram_k * std::ldexp(1.0, -23);
+        const float gk = (float)(ukd / (1.0 - ukd) * (1.0 + 1e-6));
+        {
+            StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
+            hipLaunchKernelGGL(acp_seed_gram_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
+                               x->d_pad, x->data16_scale, n, L, doff.as<int64_t>(), gk,
+                               seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
+            PMLSH_HIP(hipGetLastError());
+        }
+        StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
+        const bool all = n_seed < k;
+        // U: the upper edge of the 22-bit radix bin of the k-th smallest upper
+        // bound (at least that bound, and at most 2^-19 above it)
+        if (!all)
+            device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
+                          ghist.as<uint32_t>(), true, st, 2);
+        // The band is gathered, verified and its k-th selected without a host
+        // round trip: the verify and selection kernels read the band's size
+        // on the device, and the size comes back with the selected key. A
+        // band beyond the capacity is gathered again at its size.
+        DevBuf dstate2(x, S_STATE2);
+        dstate2.alloc(sizeof(SelState));
+        const int64_t band_max = std::max<int64_t>(int64_t(1) << 20, n_seed / 8);
+        int64_t bcap = std::min<int64_t>(n_seed, std::max<int64_t>(int64_t(1) << 16, 4 * (int64_t)k));
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            band.alloc(bcap);
+            reset_counter();
+            hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
+                               slo.as<uint32_t>(), doff.as<int64_t>(), x->perm, n, L,
+                               dstate.as<SelState>(), (float)(8.0 * gamma_v), all ? 1 : 0,
+                               band.ii.as<uint32_t>(), band.jj.as<uint32_t>(), bcap,
+                               static_cast<unsigned long long*>(dcount.p));
+            PMLSH_HIP(hipGetLastError());
+            hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(bcap, WG / 16)), dim3(WG), 0, st,
+                               x->data, x->d_pad, x->inv_perm, band.ii.as<uint32_t>(),
+                               band.jj.as<uint32_t>(), bcap, band.k0.as<uint32_t>(),
+                               band.ii.as<uint32_t>(), band.jj.as<uint32_t>(),
+                               static_cast<const unsigned long long*>(dcount.p));
+            PMLSH_HIP(hipGetLastError());
+            if (!all) {
+                hipLaunchKernelGGL(acp_kth_small_kernel, dim3(1), dim3(WG), 0, st,
+                                   band.k0.as<uint32_t>(), bcap,
+                                   static_cast<const unsigned long long*>(dcount.p), (int64_t)k,
+                                   dstate2.as<SelState>());
+                PMLSH_HIP(hipGetLastError());
+            }
+            unsigned long long nb = 0;
+            SelState hs{};
+            PMLSH_HIP(hipMemcpyAsync(&nb, dcount.p, sizeof(nb), hipMemcpyDeviceToHost, st));
+            PMLSH_HIP(hipMemcpyAsync(&hs, dstate2.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+            PMLSH_HIP(hipStreamSynchronize(st));
+            n_band = (int64_t)nb;
+            if (n_band <= bcap) {
+                gram = true;
+                if (!all) {
+                    ub2_bits = hs.prefix;
+                    float ub2;
+                    std::memcpy(&ub2, &ub2_bits, 4);
+                    ub = std::sqrt((double)ub2);
+                }
+                break;
+            }
+            if (n_band > band_max) break;
+            bcap = n_band;
+        }
+    }
+    if (!gram && n_seed > 0) {
+        // direct self-join: exact distance bits of every seed (the ids of the
+        // few seeds the top-k can use are recovered from their position)
+        seeds.k0.alloc((size_t)n_seed * 4);
+        if (L > 64) {
+            seeds.ii.alloc((size_t)n_seed * 4);
+            seeds.jj.alloc((size_t)n_seed * 4);
+        }
+        bool first_done;
+        {
+            StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
+            first_done = launch_self_join(x, doff.as<int64_t>(), seeds.k0.as<uint32_t>(),
+                                          L > 64 ? seeds.ii.as<uint32_t>() : nullptr,
+                                          L > 64 ? seeds.jj.as<uint32_t>() : nullptr,
+                                          ghist.as<uint32_t>(), st);
+        }
+        // ---- ub: k-th smallest seed distance (selected on the device)
+        if (n_seed >= k) {
+            StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
+            device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
+                          ghist.as<uint32_t>(), first_done, st);
+            read_ub();
+        }
     }
     const double R = plan.t * ub;
     const float R2 = std::isinf(R) ? INFINITY : (float)(R * R);
@@ -1622,7 +1989,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     // there are fewer than k), then the verified candidates. The pool's k-th
     // FP32 distance is at most the seeds' k-th (ub^2), so every seed its
     // FP64 band can hold lies within ub^2 (1 + 4 gamma).
-    const double gamma = pool_gamma(x, true);
+    const double gamma = gram ? gamma_v : pool_gamma(x, true);
     uint32_t seed_lim = 0xffffffffu;
     if (n_seed >= k) {
         float ub2;
@@ -1631,15 +1998,23 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         std::memcpy(&seed_lim, &lim, 4);
     }
     Triplets pool(x, S_POOL);
-    int64_t seed_cap = std::min<int64_t>(n_seed, std::max<int64_t>(4096, 4 * (int64_t)k));
-    int64_t n_band = 0;
+    int64_t seed_cap = gram ? n_band
+                            : std::min<int64_t>(n_seed, std::max<int64_t>(4096, 4 * (int64_t)k));
+    int64_t n_pool_seeds = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         pool.alloc(std::max<int64_t>(seed_cap + n_keep, 1));
         if (n_seed == 0) break;
         reset_counter();
         StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
-        if (L > 64) {
-            const SelKey all{0, seed_lim, 0, 0};
+        const SelKey all{0, seed_lim, 0, 0};
+        if (gram) {
+            if (n_band > 0)
+                hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_band, WG)), dim3(WG), 0, st,
+                                   band.k0.as<uint32_t>(), band.ii.as<uint32_t>(),
+                                   band.jj.as<uint32_t>(), n_band, all, pool.k0.as<uint32_t>(),
+                                   pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(), seed_cap,
+                                   static_cast<unsigned long long*>(dcount.p));
+        } else if (L > 64) {
             hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_seed, WG)), dim3(WG), 0, st,
                                seeds.k0.as<uint32_t>(), seeds.ii.as<uint32_t>(),
                                seeds.jj.as<uint32_t>(), n_seed, all, pool.k0.as<uint32_t>(),
@@ -1653,18 +2028,19 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
                                static_cast<unsigned long long*>(dcount.p));
         }
         PMLSH_HIP(hipGetLastError());
-        n_band = read_counter();
-        if (n_band <= seed_cap) break;
-        seed_cap = n_band;
+        n_pool_seeds = read_counter();
+        if (n_pool_seeds <= seed_cap) break;
+        seed_cap = n_pool_seeds;
     }
-    if (n_band > seed_cap) fail(PMLSH_EDEVICE, "seed band grew between two passes");
-    const int64_t n_pool = n_band + n_keep;
+    if (n_pool_seeds > seed_cap) fail(PMLSH_EDEVICE, "seed band grew between two passes");
+    const int64_t n_pool = n_pool_seeds + n_keep;
     if (n_keep > 0) {
         StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
         hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(n_keep, WG / 16)), dim3(WG), 0, st,
                            x->data, x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(),
-                           cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_band,
-                           pool.ii.as<uint32_t>() + n_band, pool.jj.as<uint32_t>() + n_band);
+                           cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_pool_seeds,
+                           pool.ii.as<uint32_t>() + n_pool_seeds,
+                           pool.jj.as<uint32_t>() + n_pool_seeds, nullptr);
         PMLSH_HIP(hipGetLastError());
     }
     if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
@@ -1838,7 +2214,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(keep, WG / 16)), dim3(WG), 0, st, x->data,
                        x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(), cands->jj.as<uint32_t>(),
                        keep, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
-                       pool.jj.as<uint32_t>());
+                       pool.jj.as<uint32_t>(), nullptr);
     PMLSH_HIP(hipGetLastError());
     if (keep < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
     pool_topk(x, pool, keep, k, pool_gamma(x, false), top, dhist, dcount, out_pairs, out_dist, st);
@@ -2113,7 +2489,7 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
         hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(nc, WG / 16)), dim3(WG), 0, st,
                            x->data, x->d_pad, x->inv_perm, cand.ii.as<uint32_t>(),
                            cand.jj.as<uint32_t>(), nc, pool.k0.as<uint32_t>() + n_pool,
-                           pool.ii.as<uint32_t>() + n_pool, pool.jj.as<uint32_t>() + n_pool);
+                           pool.ii.as<uint32_t>() + n_pool, pool.jj.as<uint32_t>() + n_pool, nullptr);
         PMLSH_HIP(hipGetLastError());
         n_pool += nc;
         count += nc;

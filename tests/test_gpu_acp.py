@@ -155,6 +155,83 @@ def test_single_leaf_mass_ties_keep_fp32_order():
     assert np.all(dist.cpu().numpy() == 0)
 
 
+@pytest.mark.parametrize("groups", [100, 1000])
+def test_seed_bounds_mass_ties(groups):
+    """Groups of 64 identical points in leaves of 64: every within-group seed
+    is at distance 0, so ub = 0, no pair is a candidate, and the answer is
+    the k smallest (i, j) among the zero-distance seeds. With 100 groups the
+    band of seeds the Gram bounds cannot separate from the k-th (every zero
+    pair, about 200,000) is verified exactly; with 1,000 groups it exceeds
+    2^20 pairs and the direct self-join takes over."""
+    pm = _gpu()
+    say(f"case: ACP seed bounds, {groups} groups of 64 identical points")
+    rng = np.random.Generator(np.random.PCG64(31))
+    d, k = 24, 50
+    centres = (rng.standard_normal((groups, d)) * 10).astype(np.float32)
+    lab = rng.permutation(np.repeat(np.arange(groups), 64))
+    D = centres[lab]
+    A = rng.standard_normal((15, d)).astype(np.float32)
+    idx = _index(pm, D, A, leaf_size=64)
+    perm, offsets = idx.export_leaves()
+    zi, zj = [], []
+    for b in range(offsets.shape[0] - 1):
+        ids = np.sort(perm[offsets[b]:offsets[b + 1]]).astype(np.int64)
+        a, c = np.triu_indices(ids.shape[0], k=1)
+        same = lab[ids[a]] == lab[ids[c]]
+        zi.append(ids[a][same])
+        zj.append(ids[c][same])
+    zi, zj = np.concatenate(zi), np.concatenate(zj)
+    say("zero-distance seeds", zi.shape[0])
+    if groups == 1000:
+        assert zi.shape[0] > 1 << 20
+    o = np.lexsort((zj, zi))[:k]
+    pairs, dist, st = idx.acp(k)
+    torch.cuda.synchronize()
+    say("stats", st)
+    assert st["ub"] == 0.0
+    assert st["n_cand_raw"] == 0
+    assert pairs.cpu().numpy().tolist() == np.stack([zi[o], zj[o]], 1).tolist()
+    assert np.all(dist.cpu().numpy() == 0)
+
+
+def test_planted_far_from_the_origin():
+    """The small planted workload shifted by +1000 in every coordinate: the
+    Gram bounds of the seeds are taken relative to each leaf's first point,
+    so ub and the answers must still match the oracle's."""
+    pm = _gpu()
+    say("case: ACP planted n=3000 d=32, offset +1000")
+    w = synth.planted_pairs(n=3000, d=32, n_centres=10)
+    D = (w["D"] + 1000.0).astype(np.float32)
+    A = w["A"]
+    idx = _index(pm, D, A)
+    for k in (1, 10):
+        pairs, dist, st = idx.acp(k, c=1.5)
+        torch.cuda.synchronize()
+        res, T = _oracle(idx, D, A, k, 1.5, 1 - 1 / math.e, -1.0)
+        say("k", k, "stats", st)
+        assert st["ub"] == pytest.approx(res.ub, rel=TOL)
+        _compare(res, pairs, dist, st)
+
+
+def test_fewer_seeds_than_k_in_small_leaves():
+    """k above the number of seeds with leaves of 8: ub = inf, every seed
+    enters the pool and every cross-leaf pair is a candidate."""
+    pm = _gpu()
+    say("case: ACP ub = inf, leaves of 8")
+    rng = np.random.Generator(np.random.PCG64(13))
+    D = rng.standard_normal((100, 16)).astype(np.float32)
+    A = rng.standard_normal((15, 16)).astype(np.float32)
+    idx = _index(pm, D, A, leaf_size=8, fanout=2)
+    _, _, st = idx.acp(1, beta=1.0)
+    k = st["n_seed"] + 10
+    assert k <= 1024
+    pairs, dist, st = idx.acp(k, beta=1.0)
+    torch.cuda.synchronize()
+    res, _ = _oracle(idx, D, A, k, 1.5, 1 - 1 / math.e, 1.0)
+    assert math.isinf(st["ub"])
+    _compare(res, pairs, dist, st)
+
+
 def test_budget_binding_and_unbounded_ub():
     pm = _gpu()
     say("case: ACP budget cut / ub = inf")
