@@ -842,13 +842,14 @@ __global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
 // So sc |a - b| lies in [sqrt(d2 - E) - rho_a - rho_b, sqrt(d2 + E) + rho_a +
 // rho_b]. Both ends, squared and divided by sc^2 (widened by 2^-18 for their
 // own FP32 evaluation), are written as the pair's bounds (FP32 bit patterns)
-// in the triangular layout of seed_off; the top 11 bits of every upper bound
-// go to ghist (first radix pass of the k-th smallest upper bound).
+// in the triangular layout of the seeds (leaf b's pairs from b L (L - 1) / 2
+// on); the top 11 bits of every upper bound go to ghist (first radix pass of
+// the k-th smallest upper bound).
 constexpr int SG_LD = 40;   // LDS row stride of the staged FP16 rows, in halves
 
 __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
     const float* __restrict__ data, int d_pad, const float* __restrict__ row_scale, int64_t n,
-    int L, const int64_t* __restrict__ seed_off, float gk, uint32_t* __restrict__ hi_out,
+    int L, float gk, uint32_t* __restrict__ hi_out,
     uint32_t* __restrict__ lo_out, uint32_t* __restrict__ ghist) {
     typedef _Float16 h8 __attribute__((ext_vector_type(8)));
     typedef float f4v __attribute__((ext_vector_type(4)));
@@ -968,7 +969,8 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
     const float ek = (gk + 2.384185791015625e-07f) * (1.f + 3.814697265625e-06f);
     const float inv = 1.f / sc;            // a power of two: exact
     const float up = 1.f + 3.814697265625e-06f, dn = 1.f - 3.814697265625e-06f;
-    const int64_t out0 = seed_off[leaf];
+    // every leaf before the last holds L points
+    const int64_t out0 = leaf * (int64_t)(L * (L - 1) / 2);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         if (j < nt) {
@@ -1001,17 +1003,17 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
 // Seeds whose lower bound is at most U (1 + widen), U the upper edge of the
 // radix bin that holds the k-th smallest upper bound (the selection's prefix
 // of state->pbits bits), or every seed when all is set: their ids (i < j)
-// are appended, one workgroup per leaf.
+// are appended, one workgroup per leaf (leaves of at most 64 points).
 __global__ __launch_bounds__(WG) void acp_seed_gram_band_kernel(
-    const uint32_t* __restrict__ lo, const int64_t* __restrict__ seed_off,
-    const int32_t* __restrict__ perm, int64_t n, int L, const SelState* __restrict__ state,
+    const uint32_t* __restrict__ lo, const int32_t* __restrict__ perm, int64_t n, int L,
+    const SelState* __restrict__ state,
     float widen, int all, uint32_t* __restrict__ oii, uint32_t* __restrict__ ojj, int64_t cap,
     unsigned long long* __restrict__ counter) {
     const int64_t leaf = blockIdx.x;
     const int64_t p0 = leaf * L;
     const int cnt = (int)(n - p0 < L ? n - p0 : L);
     const int P = cnt * (cnt - 1) / 2;
-    const int64_t off = seed_off[leaf];
+    const int64_t off = leaf * (int64_t)(L * (L - 1) / 2);
     float lim = INFINITY;
     if (!all) {
         const int pb = state->pbits;
@@ -1019,9 +1021,18 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_band_kernel(
         const uint32_t top = pb >= 32 ? state->prefix : state->prefix << (32 - pb);
         lim = __uint_as_float(top | low) * (1.f + widen) * (1.f + 3.814697265625e-06f);
     }
-    for (int base = 0; base < P; base += WG) {
-        const int p = base + threadIdx.x;
-        const bool take = p < P && __uint_as_float(lo[off + p]) <= lim;
+    // every lower bound of the leaf (at most 2,016) is loaded before any test
+    constexpr int PER = (64 * 63 / 2 + WG - 1) / WG;
+    float v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = u * WG + threadIdx.x;
+        v[u] = p < P ? __uint_as_float(lo[off + p]) : INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = u * WG + threadIdx.x;
+        const bool take = p < P && v[u] <= lim;
         uint32_t i = 0, j = 0;
         if (take) {
             int a = 0, rem = p;
@@ -1795,11 +1806,6 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     double ub = HUGE_VAL;
     uint32_t ub2_bits = 0x7f800000u;
     PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
-    if (n_seed > 0) {
-        doff.alloc((NL + 1) * sizeof(int64_t));
-        PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
-                                 hipMemcpyHostToDevice, st));
-    }
     auto read_ub = [&] {
         SelState hs{};
         PMLSH_HIP(hipMemcpyAsync(&hs, dstate.p, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -1832,7 +1838,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         {
             StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
             hipLaunchKernelGGL(acp_seed_gram_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
-                               x->d_pad, x->data16_scale, n, L, doff.as<int64_t>(), gk,
+                               x->d_pad, x->data16_scale, n, L, gk,
                                seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
             PMLSH_HIP(hipGetLastError());
         }
@@ -1855,7 +1861,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
             band.alloc(bcap);
             reset_counter();
             hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
-                               slo.as<uint32_t>(), doff.as<int64_t>(), x->perm, n, L,
+                               slo.as<uint32_t>(), x->perm, n, L,
                                dstate.as<SelState>(), (float)(8.0 * gamma_v), all ? 1 : 0,
                                band.ii.as<uint32_t>(), band.jj.as<uint32_t>(), bcap,
                                static_cast<unsigned long long*>(dcount.p));
@@ -1896,6 +1902,9 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     if (!gram && n_seed > 0) {
         // direct self-join: exact distance bits of every seed (the ids of the
         // few seeds the top-k can use are recovered from their position)
+        doff.alloc((NL + 1) * sizeof(int64_t));
+        PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, st));
         seeds.k0.alloc((size_t)n_seed * 4);
         if (L > 64) {
             seeds.ii.alloc((size_t)n_seed * 4);
