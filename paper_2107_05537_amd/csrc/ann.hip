@@ -969,7 +969,11 @@ __device__ void write_topk(const AnnArgs& a, int64_t qi, const float* qs, const 
 __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, float* qs,
                         Smem& sh);
 
-__global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
+__global__ __launch_bounds__(WG) void ann_kernel(AnnArgs args) {
+    // the argument block read in place (constant memory): naming the
+    // parameter itself lets the compiler copy all of it into scratch memory
+    (void)args;
+    const AnnArgs& a = *(const AnnArgs*)__builtin_amdgcn_kernarg_segment_ptr();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Smem& sh = *reinterpret_cast<Smem*>(smem_raw);
     float* qs = reinterpret_cast<float*>(smem_raw + ((sizeof(Smem) + 15) & ~size_t(15)));
@@ -978,18 +982,11 @@ __global__ __launch_bounds__(WG) void ann_kernel(AnnArgs a) {
     // lists of slot b (G = gridDim.x slots)
     int32_t* fa = a.ws_front + (int64_t)blockIdx.x * 2 * a.n_leaves;
     int32_t* fb = fa + a.n_leaves;
-    if (a.pq_list) {
-        // the queries the batched path flagged
-        const uint32_t npq = a.pq_list[0];
-        for (uint32_t j = blockIdx.x; j < npq; j += gridDim.x) {
-            __syncthreads();
-            ann_one(a, (int64_t)a.pq_list[1 + j], fa, fb, qs, sh);
-        }
-        return;
-    }
-    for (int64_t qi = blockIdx.x; qi < a.nq; qi += gridDim.x) {
+    // every query, or only those the batched path flagged (a.pq_list)
+    const int64_t total = a.pq_list ? (int64_t)a.pq_list[0] : a.nq;
+    for (int64_t j = blockIdx.x; j < total; j += gridDim.x) {
         __syncthreads();
-        ann_one(a, qi, fa, fb, qs, sh);
+        ann_one(a, a.pq_list ? (int64_t)a.pq_list[1 + j] : j, fa, fb, qs, sh);
     }
 }
 
