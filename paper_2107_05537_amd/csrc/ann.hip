@@ -112,11 +112,13 @@ struct AnnArgs {
     float2* qtest;
     uint64_t* cmask;            // the same mask chunk-major: ceil(nq / 64) words per chunk
     int cwords;
-    // squared distances from every query to every chunk centre (row stride
-    // ldc), as bf16 bit patterns rounded toward zero (lower bounds); from
-    // offset goff of a row, the minimum of each group of 64 chunks
+    // squared distances from every query to every chunk centre, as bf16 bit
+    // patterns rounded toward zero (lower bounds), in blocks of 64 queries x
+    // 64 chunks (cdist_at); the minimum of each group of 64 chunks (row
+    // stride gld)
     uint16_t* cdist;
-    int64_t ldc, goff;
+    uint16_t* cgmin;
+    int64_t cgroups, gld;
     int glds;                   // bound kernel: group minima copied to LDS
     int grp_cap;                // bound kernel: most groups or blocks listed (<= kGrpCap)
     // bounded verification: FP16 rows (stride d16), their scales and error
@@ -128,6 +130,11 @@ struct AnnArgs {
     int d16;
     float* ws_clo;
 };
+
+// Element (query q, chunk c) of the blocked chunk-distance matrix.
+__device__ __forceinline__ int64_t cdist_at(const AnnArgs& a, int64_t q, int64_t c) {
+    return (((q >> 6) * a.cgroups + (c >> 6)) << 12) + ((q & 63) << 6) + (c & 63);
+}
 
 // skey and spos come last: the bound kernel uses only the fields before
 // them and keeps its row of centre distances in their place.
@@ -1210,10 +1217,10 @@ __device__ void ann_one(const AnnArgs& a, int64_t qi, int32_t* fa, int32_t* fb, 
 // each wave a strip of 16 queries x 64 chunks per sub-tile (four 16 x 16
 // tiles of v_mfma_f32_16x16x4_f32, K = 16 in four steps; the next
 // sub-tile's centres are loaded meanwhile); each sub-tile goes through LDS
-// so that every query's 64 values leave as one 128-byte segment. Row q of the output holds the query's distances
-// (stride ldc) as bf16 bit patterns, rounded toward zero (the FP32 value's
-// upper half), so each stored value is at most the FP32 value and above it
-// by less than a factor 1 + 2^-7. The expansion's rounding error, in any
+// and leaves as one block of the matrix (64 queries x 64 chunks, 8 KB
+// contiguous). The values are bf16 bit patterns, rounded toward zero (the
+// FP32 value's upper half), so each stored value is at most the FP32 value
+// and above it by less than a factor 1 + 2^-7. The expansion's rounding error, in any
 // summation order of the 16 products, stays below 64 u (|q'| + S)^2 (S
 // bounds every centre norm); the chunk-ball test adds that much to its
 // threshold and tests the rounded-down value, and the choice of chunks for
@@ -1303,16 +1310,16 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
             }
         }
         __syncthreads();
-        // four threads per query row, 16 chunks (32 bytes) each; goff is a
-        // multiple of 16, so a segment that starts below it lies inside the
-        // distance part of the row
+        // four threads per query row, 16 chunks (32 bytes) each: the sub-tile
+        // (64 queries x 64 chunks) is one block of the matrix, written as
+        // one contiguous 8 KB run
         const int ql = threadIdx.x >> 2, seg = (threadIdx.x & 3) * 16;
         uint32_t gm = 0xffffu;
-        if (c0 + seg < a.goff) {
+        {
             const uint4* src = reinterpret_cast<const uint4*>(&tile[ql][seg]);
             const uint4 x0 = src[0], x1 = src[1];
             if (ql < nqb) {
-                uint4* dst = reinterpret_cast<uint4*>(a.cdist + (int64_t)(q0 + ql) * a.ldc + c0 + seg);
+                uint4* dst = reinterpret_cast<uint4*>(a.cdist + cdist_at(a, q0 + ql, c0 + seg));
                 dst[0] = x0;
                 dst[1] = x1;
             }
@@ -1327,7 +1334,7 @@ __global__ __launch_bounds__(WG) void dist_kernel(AnnArgs a) {
         gm = min(gm, (uint32_t)__shfl_xor((int)gm, 1));
         gm = min(gm, (uint32_t)__shfl_xor((int)gm, 2));
         if ((threadIdx.x & 3) == 0 && ql < nqb)
-            a.cdist[(int64_t)(q0 + ql) * a.ldc + a.goff + (c0 >> 6)] = (uint16_t)gm;
+            a.cgmin[(int64_t)(q0 + ql) * a.gld + (c0 >> 6)] = (uint16_t)gm;
     }
 }
 
@@ -1365,9 +1372,12 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
     const int nch = (int)(a.n_pad16 >> 6);
     const int ng4 = (nch + 3) >> 2;
     const int ngr = (nch + 63) >> 6;
-    // four bf16 distances per 8-byte element (element g: chunks 4 g .. 4 g + 3)
-    const uint2* row4 = reinterpret_cast<const uint2*>(a.cdist + qi * a.ldc);
-    const uint16_t* grow16 = a.cdist + qi * a.ldc + a.goff;
+    // four bf16 distances per 8-byte element (element g: chunks 4 g .. 4 g + 3;
+    // the 16 elements of a group of 64 chunks are contiguous)
+    const uint2* cd4 = reinterpret_cast<const uint2*>(a.cdist + cdist_at(a, qi, 0));
+    const int64_t band_stride4 = 1024;   // uint2 elements per block
+    auto row4 = [&](int g) { return cd4[(int64_t)(g >> 4) * band_stride4 + (g & 15)]; };
+    const uint16_t* grow16 = a.cgmin + qi * a.gld;
     // the group minima (copied to LDS when a.glds is set, else read in the
     // row), then the list of candidate groups and the list of chosen chunks
     unsigned char* lds_free = smem_raw + offsetof(Smem, skey);
@@ -1441,10 +1451,10 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
         if (grp) {
             for (int e = threadIdx.x; e < 16 * ngl; e += WG) {
                 const int g = 16 * glist[e >> 4] + (e & 15);
-                if (g < ng4) f(g, row4[g]);
+                if (g < ng4) f(g, row4(g));
             }
         } else {
-            for (int g = threadIdx.x; g < ng4; g += WG) f(g, row4[g]);
+            for (int g = threadIdx.x; g < ng4; g += WG) f(g, row4(g));
         }
     };
 
@@ -1683,9 +1693,9 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
 #pragma unroll
         for (int u = 0; u < QU; ++u) {
             const int q = qh * 32 + g0 + u;
-            // c is even and ldc a multiple of 16: an aligned pair inside the row
+            // c is even: an aligned pair inside one block row
             w[u] = q < nqb && c < nch
-                       ? *reinterpret_cast<const uint32_t*>(a.cdist + (int64_t)(q0 + q) * a.ldc + c)
+                       ? *reinterpret_cast<const uint32_t*>(a.cdist + cdist_at(a, q0 + q, c))
                        : 0u;
         }
 #pragma unroll
@@ -2432,8 +2442,9 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         a.cmask = L.ws_cmask;
         a.cwords = (int)((L.nq + 63) / 64);
         a.cdist = L.ws_cdist2;
-        a.ldc = cdist_row_len(x.n_pad16 / 64);
-        a.goff = cdist_row_offset_groups(x.n_pad16 / 64);
+        a.cgmin = L.ws_cgmin;
+        a.cgroups = cdist_groups(x.n_pad16 / 64);
+        a.gld = cdist_gmin_len(x.n_pad16 / 64);
         a.ws_clo = L.ws_clo;
         a.q_flag = L.q_flag;
         a.pq_list = L.pq_list;

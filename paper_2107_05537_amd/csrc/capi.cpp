@@ -46,7 +46,7 @@ namespace {
 // 64-bit word per chunk and 64 queries, both layouts); plus the frontier
 // lists of the per-query kernel's workgroups.
 struct AnnWorkspace {
-    int64_t B, pool_q, per_query, nchunk, ldc, batch, slots, bytes;
+    int64_t B, pool_q, per_query, nchunk, batch, slots, bytes;
     bool fast;
 };
 
@@ -63,7 +63,8 @@ int64_t front_slots(const pmlsh_index* x, bool fast, int64_t batch) {
 int64_t ann_layout_bytes(const pmlsh_index* x, const AnnWorkspace& w, int64_t batch,
                          int64_t slots) {
     const int64_t mask_bytes =
-        w.fast ? batch * (8 + 2 * w.ldc) + w.nchunk * ((batch + 63) / 64) * 8 + 64 : 0;
+        w.fast ? batch * 8 + 2 * cdist_elems(batch, w.nchunk) + w.nchunk * ((batch + 63) / 64) * 8 + 64
+               : 0;
     return batch * w.per_query + mask_bytes + slots * 2 * x->n_leaves * 4;
 }
 
@@ -78,14 +79,16 @@ AnnWorkspace ann_workspace_base(const pmlsh_index* x, int k, int64_t B) {
                   (w.fast ? 4 * 4 + w.pool_q * 4 + B * 4 : 0) +
                   (w.fast && x->filter_gemm ? (MP + 1) * 4 : 0);
     w.nchunk = x->n_pad16 / 64;
-    w.ldc = cdist_row_len(w.nchunk);
     return w;
 }
 
 AnnWorkspace ann_workspace(const pmlsh_index* x, int64_t nq, int k, int64_t B) {
     AnnWorkspace w = ann_workspace_base(x, k, B);
+    // per query, with the distance blocks of a 64-query band spread over it
     const int64_t per_query_all =
-        w.per_query + (w.fast ? 8 + 2 * w.ldc + (w.nchunk + 7) / 8 : 0);
+        w.per_query + (w.fast ? 8 + 2 * (64 * cdist_groups(w.nchunk) + cdist_gmin_len(w.nchunk)) +
+                                    (w.nchunk + 7) / 8
+                              : 0);
     w.batch = std::max<int64_t>(1, std::min<int64_t>(nq, kWorkspaceCap / per_query_all));
     w.batch = std::min<int64_t>(w.batch, 65535);
     w.slots = front_slots(x, w.fast, w.batch);
@@ -158,8 +161,7 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
                     const AnnWorkspace& w, void* ws) {
     const int k = call.k;
     const int stride = call.out_stride > 0 ? call.out_stride : k;
-    const int64_t B = w.B, pool_q = w.pool_q, nchunk = w.nchunk, ldc = w.ldc,
-                  batch = w.batch;
+    const int64_t B = w.B, pool_q = w.pool_q, nchunk = w.nchunk, batch = w.batch;
     const bool fast = w.fast;
     char* base = static_cast<char*>(ws);
     // projections and FP16 scan rows first: every row starts on a 64-byte
@@ -168,7 +170,8 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
     float* qproj_lo = qproj + batch * MP;
     uint16_t* qaug = reinterpret_cast<uint16_t*>(qproj_lo + batch * MP);
     uint16_t* cdist2 = qaug + batch * 32;
-    float2* qtest = reinterpret_cast<float2*>(cdist2 + (fast ? batch * ldc : 0));
+    uint16_t* cgmin = cdist2 + (fast ? cdist_block_elems(batch, nchunk) : 0);
+    float2* qtest = reinterpret_cast<float2*>(cdist2 + (fast ? cdist_elems(batch, nchunk) : 0));
     uint64_t* cmask = reinterpret_cast<uint64_t*>(qtest + (fast ? batch : 0));
     uint32_t* list = reinterpret_cast<uint32_t*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
@@ -219,6 +222,7 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
             L.ws_clo = clo;
             L.ws_cmask = cmask;
             L.ws_cdist2 = cdist2;
+            L.ws_cgmin = cgmin;
             L.q_flag = q_flag;
             L.l_count = l_count;
             L.q_scanned = q_scanned;

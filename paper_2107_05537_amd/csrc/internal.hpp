@@ -32,12 +32,19 @@ constexpr int kScanRow = 24;
 // the largest budget of the batched path).
 constexpr int kSelCap = 1024;
 
-// Row of the per-query chunk-distance matrix (bf16 values): the n_chunk
-// distances, padded to a multiple of 16, then the minimum of every group of
-// 64 chunks, padded to a multiple of 16.
-inline int64_t cdist_row_offset_groups(int64_t n_chunk) { return (n_chunk + 15) / 16 * 16; }
-inline int64_t cdist_row_len(int64_t n_chunk) {
-    return cdist_row_offset_groups(n_chunk) + ((n_chunk + 63) / 64 + 15) / 16 * 16;
+// The batch's chunk-distance matrix (bf16 values) is stored in blocks of 64
+// queries x 64 chunks (8 KB, a query's 64 chunks contiguous inside), the
+// blocks of one band of 64 queries in chunk order, so that a workgroup tile
+// of the kernels that write and read it is one contiguous run; then the
+// minimum of every group of 64 chunks, a row of cdist_gmin_len entries per
+// query.
+inline int64_t cdist_groups(int64_t n_chunk) { return (n_chunk + 63) / 64; }
+inline int64_t cdist_gmin_len(int64_t n_chunk) { return (cdist_groups(n_chunk) + 15) / 16 * 16; }
+inline int64_t cdist_block_elems(int64_t batch, int64_t n_chunk) {
+    return (batch + 63) / 64 * 4096 * cdist_groups(n_chunk);
+}
+inline int64_t cdist_elems(int64_t batch, int64_t n_chunk) {
+    return cdist_block_elems(batch, n_chunk) + batch * cdist_gmin_len(n_chunk);
 }
 
 // Thread-local error message returned by pmlsh_last_error().
@@ -349,7 +356,9 @@ struct AnnLaunch {
     float* ws_qeps;         // nq: their bounds
     float2* ws_qtest;       // nq: radius and margin of each query's chunk-ball test
     uint64_t* ws_cmask;     // the same, chunk-major: chunks x ceil(nq / 64) words
-    uint16_t* ws_cdist2;    // nq x ldc: squared distances to the chunk centres (bf16, rounded down)
+    uint16_t* ws_cdist2;    // squared distances to the chunk centres (bf16, rounded down), in
+                            // blocks of 64 queries x 64 chunks
+    uint16_t* ws_cgmin;     // nq x cdist_gmin_len: their minimum per group of 64 chunks
     int64_t pool_cap;       // candidate region per query
     int64_t* out_ids;
     float* out_dist;
