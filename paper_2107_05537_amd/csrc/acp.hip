@@ -649,7 +649,7 @@ __device__ void pick_bin(const uint32_t* h, int64_t need, int* out_bin, int64_t*
 // it; the histogram is cleared for the next pass.
 __global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__ ghist,
                                                           SelState* __restrict__ state,
-                                                          int width) {
+                                                          int width, int64_t need0) {
     __shared__ uint32_t h[NB];
     __shared__ int s_bin;
     __shared__ int64_t s_cum;
@@ -659,11 +659,13 @@ __global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__
         s_cum = 0;
     }
     __syncthreads();
-    const int64_t need = state->need;
+    // need0 >= 0: the first pass (the state is not read, it starts empty)
+    const bool first = need0 >= 0;
+    const int64_t need = first ? need0 : state->need;
     pick_bin(h, need, &s_bin, &s_cum);
     if (threadIdx.x == 0) {
-        state->prefix = (state->prefix << width) | (uint32_t)s_bin;
-        state->pbits += width;
+        state->prefix = ((first ? 0u : state->prefix) << width) | (uint32_t)s_bin;
+        state->pbits = (first ? 0 : state->pbits) + width;
         state->need = need - s_cum;
     }
     for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
@@ -1003,17 +1005,26 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
 // Seeds whose lower bound is at most U (1 + widen), U the upper edge of the
 // radix bin that holds the k-th smallest upper bound (the selection's prefix
 // of state->pbits bits), or every seed when all is set: their ids (i < j)
-// are appended, one workgroup per leaf (leaves of at most 64 points).
-__global__ __launch_bounds__(WG) void acp_seed_gram_band_kernel(
+// are appended. One wave per leaf (leaves of at most 64 points, at most
+// 2,016 pairs, all loaded before any test), so the whole grid is resident
+// at once.
+__global__ __launch_bounds__(64) void acp_seed_gram_band_kernel(
     const uint32_t* __restrict__ lo, const int32_t* __restrict__ perm, int64_t n, int L,
-    const SelState* __restrict__ state,
-    float widen, int all, uint32_t* __restrict__ oii, uint32_t* __restrict__ ojj, int64_t cap,
-    unsigned long long* __restrict__ counter) {
+    const SelState* __restrict__ state, float widen, int all, uint32_t* __restrict__ oii,
+    uint32_t* __restrict__ ojj, int64_t cap, unsigned long long* __restrict__ counter) {
     const int64_t leaf = blockIdx.x;
     const int64_t p0 = leaf * L;
     const int cnt = (int)(n - p0 < L ? n - p0 : L);
     const int P = cnt * (cnt - 1) / 2;
     const int64_t off = leaf * (int64_t)(L * (L - 1) / 2);
+    const int lane = threadIdx.x;
+    constexpr int PER = (64 * 63 / 2 + 63) / 64;
+    float v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = u * 64 + lane;
+        v[u] = p < P ? __uint_as_float(lo[off + p]) : INFINITY;
+    }
     float lim = INFINITY;
     if (!all) {
         const int pb = state->pbits;
@@ -1021,17 +1032,13 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_band_kernel(
         const uint32_t top = pb >= 32 ? state->prefix : state->prefix << (32 - pb);
         lim = __uint_as_float(top | low) * (1.f + widen) * (1.f + 3.814697265625e-06f);
     }
-    // every lower bound of the leaf (at most 2,016) is loaded before any test
-    constexpr int PER = (64 * 63 / 2 + WG - 1) / WG;
-    float v[PER];
+    uint64_t any = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) any |= __ballot(v[u] <= lim);
+    if (any == 0) return;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int p = u * WG + threadIdx.x;
-        v[u] = p < P ? __uint_as_float(lo[off + p]) : INFINITY;
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int p = u * WG + threadIdx.x;
+        const int p = u * 64 + lane;
         const bool take = p < P && v[u] <= lim;
         uint32_t i = 0, j = 0;
         if (take) {
@@ -1052,8 +1059,9 @@ __global__ __launch_bounds__(WG) void acp_sel_hist_kernel(
     __shared__ uint32_t h[NB];
     for (int i = threadIdx.x; i < NB; i += WG) h[i] = 0;
     __syncthreads();
-    const uint32_t prefix = state->prefix;
-    const int pbits = state->pbits;
+    // shift 21: the first pass (the state is not read)
+    const uint32_t prefix = shift == 21 ? 0u : state->prefix;
+    const int pbits = shift == 21 ? 0 : state->pbits;
     const uint32_t mask = (1u << width) - 1u;
     for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < count;
          e += (int64_t)gridDim.x * WG) {
@@ -1469,11 +1477,6 @@ __global__ __launch_bounds__(WG) void acp_band_gather_kernel(
     }
 }
 
-__global__ void acp_sel_init_kernel(SelState* state, int64_t need) {
-    state->prefix = 0;
-    state->pbits = 0;
-    state->need = need;
-}
 
 // ---------------------------------------------------------------- host side
 // Workspace buffer of one role, kept in the index between calls and grown
@@ -1574,15 +1577,10 @@ SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, in
 // left cleared. With first_done the first pass (top 11 bits) is already in
 // ghist (the self-join adds it); otherwise ghist must be clear on entry.
 // With passes < 3 only the leading 11 or 22 bits of the key are resolved
-// (state->pbits of them in state->prefix).
-void sel_init(SelState* state, int64_t need, hipStream_t st) {
-    hipLaunchKernelGGL(acp_sel_init_kernel, dim3(1), dim3(1), 0, st, state, need);
-    PMLSH_HIP(hipGetLastError());
-}
-
+// (state->pbits of them in state->prefix). The first pass starts from an
+// empty state without reading it.
 void device_select(const uint32_t* keys, int64_t count, int64_t need, SelState* state,
                    uint32_t* ghist, bool first_done, hipStream_t st, int passes = 3) {
-    sel_init(state, need, st);
     const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
     for (int pass = 0; pass < passes; ++pass) {
         if (pass > 0 || !first_done) {
@@ -1591,7 +1589,7 @@ void device_select(const uint32_t* keys, int64_t count, int64_t need, SelState* 
             PMLSH_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(acp_sel_pick_kernel, dim3(1), dim3(WG), 0, st, ghist, state,
-                           widths[pass]);
+                           widths[pass], pass == 0 ? need : (int64_t)-1);
         PMLSH_HIP(hipGetLastError());
     }
 }
@@ -1860,7 +1858,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         for (int attempt = 0; attempt < 2; ++attempt) {
             band.alloc(bcap);
             reset_counter();
-            hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
+            hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(64), 0, st,
                                slo.as<uint32_t>(), x->perm, n, L,
                                dstate.as<SelState>(), (float)(8.0 * gamma_v), all ? 1 : 0,
                                band.ii.as<uint32_t>(), band.jj.as<uint32_t>(), bcap,
