@@ -287,7 +287,7 @@ def config3_bench(pm, torch, dev, cs=(1.2, 1.5, 2.0),
             "build_s": round(build_s, 2), "points": rows, "mixed_precision": mixed}
 
 
-def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3, with_variants=True):
+def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=10, with_variants=True):
     """(c,k)-ACP on 200,000 x 512 with 2,000 planted near-duplicate pairs:
     time per call for each k (index built beforehand, data resident in HBM),
     recall and overall ratio (Eqs. 12-14) against the exact k closest pairs
@@ -319,13 +319,18 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=3, with_variants=Tru
     for k in ks:
         pairs, dist, st = idx.acp(k, c=c)                     # warm-up
         torch.cuda.synchronize()
-        pm.ann_timing_read(reset=True)
-        pm.ann_timing_enable(True, stages=acp_stages)
+        # the calls are timed without stage events; the stage split comes
+        # from as many further calls with the events on
         t0 = time.perf_counter()
         for _ in range(calls):
             pairs, dist, st = idx.acp(k, c=c)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / calls
+        pm.ann_timing_read(reset=True)
+        pm.ann_timing_enable(True, stages=acp_stages)
+        for _ in range(3):
+            idx.acp(k, c=c)
+        torch.cuda.synchronize()
         pm.ann_timing_enable(False)
         tm = pm.ann_timing_read(reset=True)
         stage_ms = {s_: round(tm[s_]["ms"] / max(1, tm[s_]["launches"]), 4) for s_ in acp_stages

@@ -142,6 +142,16 @@ __device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b
     return m;
 }
 
+// The radii of one canonical call, computed on the device from the selected
+// seed distance so that no host round trip separates the seeds from the
+// tile filter and the pair scan (the same arithmetic as the host's).
+struct AcpRadius {
+    float R2;          // (t ub)^2, the pair filter's squared radius
+    float limit;       // t ub plus the rounding slack of the node tests
+    uint32_t seed_lim; // bits of ub^2 (1 + 4 gamma) rounded up: seeds the pool takes
+    uint32_t pad;
+};
+
 // Leaf pairs (e1 < e2; with diag also e1 = e2) whose Mindist can fall below
 // `limit`. One workgroup per first leaf e1: its kept tiles are compacted in
 // LDS and appended with one global atomic per flush, so a row's tiles lie
@@ -150,7 +160,9 @@ __device__ __forceinline__ float mindist(const NodeView& v, int64_t a, int64_t b
 constexpr int kRowBuf = 2048;
 __global__ __launch_bounds__(WG) void acp_tile_filter_kernel(
     NodeView v, int64_t leaf_base, int64_t n_leaves, float limit, int diag,
-    int2* __restrict__ tiles, int64_t cap, unsigned long long* __restrict__ counter) {
+    int2* __restrict__ tiles, int64_t cap, unsigned long long* __restrict__ counter,
+    const AcpRadius* __restrict__ rad) {
+    if (rad) limit = rad->limit;
     __shared__ int rowbuf[kRowBuf];
     __shared__ int wcount[WG / 64];
     __shared__ int nrow;
@@ -443,7 +455,13 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
     int64_t leaf_base, const int32_t* __restrict__ perm, int64_t n, int L,
     const int2* __restrict__ tiles, int64_t n_tiles, float R2, float Rlim,
     uint32_t* __restrict__ ck0, uint32_t* __restrict__ cii, uint32_t* __restrict__ cjj,
-    int64_t cap, unsigned long long* __restrict__ counter) {
+    int64_t cap, unsigned long long* __restrict__ counter,
+    const unsigned long long* __restrict__ dn_tiles, const AcpRadius* __restrict__ rad) {
+    if (dn_tiles) n_tiles = (int64_t)*dn_tiles;
+    if (rad) {
+        R2 = rad->R2;
+        Rlim = rad->limit;
+    }
     const int lane = lane_id();
     const int64_t gw = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (WG / 64);
@@ -669,6 +687,23 @@ __global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__
         state->need = need - s_cum;
     }
     for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
+}
+
+// ub^2 = the key left in state->prefix (has_ub), else ub = +inf.
+__global__ void acp_radius_kernel(const SelState* __restrict__ state, int has_ub, double t,
+                                  double gamma, float coord_scale, AcpRadius* __restrict__ out) {
+    const float ub2 = has_ub ? __uint_as_float(state->prefix) : INFINITY;
+    const double ub = has_ub ? sqrt((double)ub2) : HUGE_VAL;
+    const double R = t * ub;
+    const bool inf = isinf(R);
+    const float slack = (float)(1e-5 * (2.0 * (double)coord_scale + (inf ? 0.0 : R)));
+    AcpRadius r;
+    r.R2 = inf ? INFINITY : (float)(R * R);
+    r.limit = inf ? INFINITY : (float)R + slack;
+    r.seed_lim = has_ub ? __float_as_uint(nextafterf((float)((double)ub2 * (1.0 + 4.0 * gamma)), INFINITY))
+                        : 0xffffffffu;
+    r.pad = 0u;
+    *out = r;
 }
 
 // The need-th smallest of the first min(*dev_count, cap) keys, by one
@@ -1346,7 +1381,10 @@ __global__ __launch_bounds__(WG) void acp_topk_small_kernel(
     const uint32_t* __restrict__ k0, const uint32_t* __restrict__ ii,
     const uint32_t* __restrict__ jj, int count, int k, double band,
     const float* __restrict__ data, int d_pad, const int32_t* __restrict__ inv_perm,
-    int64_t* __restrict__ out_pairs, float* __restrict__ out_dist, int* __restrict__ status) {
+    int64_t* __restrict__ out_pairs, float* __restrict__ out_dist, int* __restrict__ status,
+    const unsigned long long* __restrict__ dn_add) {
+    // dn_add: the pool holds a further *dn_add pairs counted on the device
+    if (dn_add) count += (int)*dn_add;
     extern __shared__ __align__(16) unsigned char smem[];
     double* dk = reinterpret_cast<double*>(smem);
     uint64_t* pk = reinterpret_cast<uint64_t*>(dk + kTopBand);
@@ -1484,7 +1522,7 @@ __global__ __launch_bounds__(WG) void acp_band_gather_kernel(
 enum Slot {
     S_HIST, S_COUNT, S_DOFF, S_TILES, S_PPD, S_SEEDS, S_CAND = S_SEEDS + 3, S_KEPT = S_CAND + 3,
     S_POOL = S_KEPT + 3, S_TOP = S_POOL + 3, S_SPD = S_TOP + 3, S_SIDX, S_STATE, S_GHIST,
-    S_SLO, S_STATE2, S_BAND, S_COUNT_ALL = S_BAND + 3
+    S_SLO, S_STATE2, S_COUNTS, S_RADIUS, S_BAND, S_COUNT_ALL = S_BAND + 3
 };
 
 struct DevBuf {
@@ -1673,16 +1711,21 @@ struct TileScan {
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
 
+    // With dn_tiles and rad (leaves of at most 64 points only), the tile count
+    // and the radii are read on the device and n_tiles only bounds the count.
     void scan(const int2* tiles, int64_t n_tiles, float R2, float Rlim, uint32_t* k0,
-              uint32_t* ii, uint32_t* jj, int64_t cap, unsigned long long* counter) {
+              uint32_t* ii, uint32_t* jj, int64_t cap, unsigned long long* counter,
+              const unsigned long long* dn_tiles = nullptr, const AcpRadius* rad = nullptr) {
         if (n_tiles <= 0) return;
         if (wave) {
             const int64_t waves = std::min<int64_t>(n_tiles, 16384);
             hipLaunchKernelGGL(acp_tile_scan_wave_kernel, dim3((unsigned)((waves + 3) / 4)),
                                dim3(WG), 0, st, x->proj_hi, x->proj_lo, ppd.as<float>(),
                                spd.as<float>(), sidx.as<uint8_t>(), v, leaf_base, x->perm, x->n,
-                               x->leaf_size, tiles, n_tiles, R2, Rlim, k0, ii, jj, cap, counter);
+                               x->leaf_size, tiles, n_tiles, R2, Rlim, k0, ii, jj, cap, counter,
+                               dn_tiles, rad);
         } else {
+            if (dn_tiles || rad) fail(PMLSH_EDEVICE, "device radii need leaves of at most 64 points");
             hipLaunchKernelGGL(acp_tile_scan_kernel, dim3(grid_for(n_tiles, 1)), dim3(WG), lds, st,
                                x->proj_hi, x->proj_lo, ppd.as<float>(), v, leaf_base, x->perm,
                                x->n, x->leaf_size, tiles, n_tiles, R2, Rlim, k0, ii, jj, cap,
@@ -1701,13 +1744,27 @@ struct TileScan {
 // the exact k-th one has an FP32 value within kth (1 + 4 gamma); the band's
 // order is taken in FP64. A band of more than kTopBand pairs (mass ties)
 // keeps the FP32 order.
+// With dn_add the pool holds n_pool + *dn_add pairs (counted on the device),
+// at most n_max; the count is read back only when the one-workgroup kernel
+// cannot finish alone.
 void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, double gamma,
                Triplets& top, DevBuf& dhist, DevBuf& dcount, int64_t* out_pairs,
-               float* out_dist, hipStream_t st) {
+               float* out_dist, hipStream_t st, const unsigned long long* dn_add = nullptr,
+               int64_t n_max = 0) {
     DevBuf dstate(x, S_STATE), ghist(x, S_GHIST);
     dstate.alloc(sizeof(SelState));
     ghist.alloc(NB * sizeof(uint32_t));
-    if (n_pool <= kSmallPool) {
+    auto exact_count = [&] {
+        unsigned long long extra = 0;
+        PMLSH_HIP(hipMemcpyAsync(&extra, dn_add, sizeof(extra), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        n_pool += (int64_t)extra;
+        dn_add = nullptr;
+        if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
+    };
+    if (dn_add && n_max > kSmallPool) exact_count();
+    if (n_pool < k && !dn_add) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
+    if ((dn_add ? n_max : n_pool) <= kSmallPool) {
         // one workgroup: select, band and FP64 order; falls through on mass ties
         PMLSH_HIP(hipFuncSetAttribute((const void*)acp_topk_small_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1716,13 +1773,14 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
                            pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
                            pool.jj.as<uint32_t>(), (int)n_pool, k, 4.0 * gamma, x->data,
                            x->d_pad, x->inv_perm, out_pairs, out_dist,
-                           static_cast<int*>(dcount.p));
+                           static_cast<int*>(dcount.p), dn_add);
         PMLSH_HIP(hipGetLastError());
         int m = 0;
         PMLSH_HIP(hipMemcpyAsync(&m, dcount.p, sizeof(m), hipMemcpyDeviceToHost, st));
         PMLSH_HIP(hipStreamSynchronize(st));
         if (m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
         if (m <= kTopBand) return;
+        if (dn_add) exact_count();
     }
     PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
     device_select(pool.k0.as<uint32_t>(), n_pool, k, dstate.as<SelState>(),
@@ -1826,80 +1884,58 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     // the direct self-join.
     const double gamma_v = pool_gamma(x, false);
     const int gram_k = 32 * ((x->d_pad + 31) / 32);
-    bool gram = false;
-    int64_t n_band = 0;
-    if (n_seed > 0 && L <= 64 && gram_k <= 65536) {
-        seeds.k0.alloc((size_t)n_seed * 4);
-        slo.alloc((size_t)n_seed * 4);
-        const double ukd = (double)gram_k * std::ldexp(1.0, -23);
-        const float gk = (float)(ukd / (1.0 - ukd) * (1.0 + 1e-6));
-        {
-            StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
-            hipLaunchKernelGGL(acp_seed_gram_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
-                               x->d_pad, x->data16_scale, n, L, gk,
-                               seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
+    bool gram = false, deferred = false, all_seeds = n_seed < k;
+    int64_t n_band = 0, band_max = 0, bcap = 0;
+    DevBuf dstate2(x, S_STATE2), dcnts(x, S_COUNTS), drad(x, S_RADIUS);
+    dcnts.alloc(4 * sizeof(unsigned long long));
+    drad.alloc(sizeof(AcpRadius));
+    auto take_ub = [&](const SelState& hs) {
+        ub2_bits = hs.prefix;
+        float ub2;
+        std::memcpy(&ub2, &ub2_bits, 4);
+        ub = std::sqrt((double)ub2);
+    };
+    // the band at capacity bcap: gathered (its size counted in dcnts[0]),
+    // verified, and its k-th selected into dstate2, all on the device
+    auto launch_band = [&] {
+        unsigned long long* cnt = dcnts.as<unsigned long long>();
+        band.alloc(bcap);
+        PMLSH_HIP(hipMemsetAsync(dcnts.p, 0, 4 * sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(64), 0, st,
+                           slo.as<uint32_t>(), x->perm, n, L, dstate.as<SelState>(),
+                           (float)(8.0 * gamma_v), all_seeds ? 1 : 0, band.ii.as<uint32_t>(),
+                           band.jj.as<uint32_t>(), bcap, cnt);
+        PMLSH_HIP(hipGetLastError());
+        hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(bcap, WG / 16)), dim3(WG), 0, st,
+                           x->data, x->d_pad, x->inv_perm, band.ii.as<uint32_t>(),
+                           band.jj.as<uint32_t>(), bcap, band.k0.as<uint32_t>(),
+                           band.ii.as<uint32_t>(), band.jj.as<uint32_t>(),
+                           static_cast<const unsigned long long*>(cnt));
+        PMLSH_HIP(hipGetLastError());
+        if (!all_seeds) {
+            hipLaunchKernelGGL(acp_kth_small_kernel, dim3(1), dim3(WG), 0, st,
+                               band.k0.as<uint32_t>(), bcap,
+                               static_cast<const unsigned long long*>(cnt), (int64_t)k,
+                               dstate2.as<SelState>());
             PMLSH_HIP(hipGetLastError());
         }
-        StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
-        const bool all = n_seed < k;
-        // U: the upper edge of the 22-bit radix bin of the k-th smallest upper
-        // bound (at least that bound, and at most 2^-19 above it)
-        if (!all)
-            device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
-                          ghist.as<uint32_t>(), true, st, 2);
-        // The band is gathered, verified and its k-th selected without a host
-        // round trip: the verify and selection kernels read the band's size
-        // on the device, and the size comes back with the selected key. A
-        // band beyond the capacity is gathered again at its size.
-        DevBuf dstate2(x, S_STATE2);
-        dstate2.alloc(sizeof(SelState));
-        const int64_t band_max = std::max<int64_t>(int64_t(1) << 20, n_seed / 8);
-        int64_t bcap = std::min<int64_t>(n_seed, std::max<int64_t>(int64_t(1) << 16, 4 * (int64_t)k));
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            band.alloc(bcap);
-            reset_counter();
-            hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(64), 0, st,
-                               slo.as<uint32_t>(), x->perm, n, L,
-                               dstate.as<SelState>(), (float)(8.0 * gamma_v), all ? 1 : 0,
-                               band.ii.as<uint32_t>(), band.jj.as<uint32_t>(), bcap,
-                               static_cast<unsigned long long*>(dcount.p));
-            PMLSH_HIP(hipGetLastError());
-            hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(bcap, WG / 16)), dim3(WG), 0, st,
-                               x->data, x->d_pad, x->inv_perm, band.ii.as<uint32_t>(),
-                               band.jj.as<uint32_t>(), bcap, band.k0.as<uint32_t>(),
-                               band.ii.as<uint32_t>(), band.jj.as<uint32_t>(),
-                               static_cast<const unsigned long long*>(dcount.p));
-            PMLSH_HIP(hipGetLastError());
-            if (!all) {
-                hipLaunchKernelGGL(acp_kth_small_kernel, dim3(1), dim3(WG), 0, st,
-                                   band.k0.as<uint32_t>(), bcap,
-                                   static_cast<const unsigned long long*>(dcount.p), (int64_t)k,
-                                   dstate2.as<SelState>());
-                PMLSH_HIP(hipGetLastError());
-            }
-            unsigned long long nb = 0;
-            SelState hs{};
-            PMLSH_HIP(hipMemcpyAsync(&nb, dcount.p, sizeof(nb), hipMemcpyDeviceToHost, st));
-            PMLSH_HIP(hipMemcpyAsync(&hs, dstate2.p, sizeof(hs), hipMemcpyDeviceToHost, st));
-            PMLSH_HIP(hipStreamSynchronize(st));
-            n_band = (int64_t)nb;
-            if (n_band <= bcap) {
-                gram = true;
-                if (!all) {
-                    ub2_bits = hs.prefix;
-                    float ub2;
-                    std::memcpy(&ub2, &ub2_bits, 4);
-                    ub = std::sqrt((double)ub2);
-                }
-                break;
-            }
-            if (n_band > band_max) break;
-            bcap = n_band;
-        }
-    }
-    if (!gram && n_seed > 0) {
-        // direct self-join: exact distance bits of every seed (the ids of the
-        // few seeds the top-k can use are recovered from their position)
+    };
+    // the band's size (and ub) read back: true when the band fit its capacity
+    auto read_band = [&]() -> bool {
+        unsigned long long nb = 0;
+        SelState hs{};
+        PMLSH_HIP(hipMemcpyAsync(&nb, dcnts.p, sizeof(nb), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipMemcpyAsync(&hs, dstate2.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        n_band = (int64_t)nb;
+        if (n_band > bcap) return false;
+        if (!all_seeds) take_ub(hs);
+        return true;
+    };
+    // direct self-join: exact distance bits of every seed (the ids of the
+    // few seeds the top-k can use are recovered from their position)
+    auto direct_seeds = [&] {
+        gram = false;
         doff.alloc((NL + 1) * sizeof(int64_t));
         PMLSH_HIP(hipMemcpyAsync(doff.p, seed_off.data(), (NL + 1) * sizeof(int64_t),
                                  hipMemcpyHostToDevice, st));
@@ -1916,46 +1952,85 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
                                           L > 64 ? seeds.jj.as<uint32_t>() : nullptr,
                                           ghist.as<uint32_t>(), st);
         }
-        // ---- ub: k-th smallest seed distance (selected on the device)
+        // ub: k-th smallest seed distance (selected on the device)
         if (n_seed >= k) {
             StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
             device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
                           ghist.as<uint32_t>(), first_done, st);
             read_ub();
         }
+    };
+    if (n_seed > 0 && L <= 64 && gram_k <= 65536) {
+        seeds.k0.alloc((size_t)n_seed * 4);
+        slo.alloc((size_t)n_seed * 4);
+        const double ukd = (double)gram_k * std::ldexp(1.0, -23);
+        const float gk = (float)(ukd / (1.0 - ukd) * (1.0 + 1e-6));
+        {
+            StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
+            hipLaunchKernelGGL(acp_seed_gram_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
+                               x->d_pad, x->data16_scale, n, L, gk,
+                               seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
+            PMLSH_HIP(hipGetLastError());
+        }
+        StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);
+        all_seeds = n_seed < k;
+        // U: the upper edge of the 22-bit radix bin of the k-th smallest upper
+        // bound (at least that bound, and at most 2^-19 above it)
+        if (!all_seeds)
+            device_select(seeds.k0.as<uint32_t>(), n_seed, k, dstate.as<SelState>(),
+                          ghist.as<uint32_t>(), true, st, 2);
+        // The band is gathered, verified and its k-th selected without a host
+        // round trip (the verify and selection kernels read the band's size
+        // on the device), and the radii follow on the device: the tile filter
+        // and the pair scan run before the host reads anything back. A band
+        // beyond its capacity is gathered again at its size, and what
+        // followed it is redone.
+        dstate2.alloc(sizeof(SelState));
+        band_max = std::max<int64_t>(int64_t(1) << 20, n_seed / 8);
+        bcap = std::min<int64_t>(n_seed, std::max<int64_t>(int64_t(1) << 16, 4 * (int64_t)k));
+        launch_band();
+        hipLaunchKernelGGL(acp_radius_kernel, dim3(1), dim3(1), 0, st, dstate2.as<SelState>(),
+                           all_seeds ? 0 : 1, plan.t, gamma_v, x->coord_scale, drad.as<AcpRadius>());
+        PMLSH_HIP(hipGetLastError());
+        deferred = true;
     }
-    const double R = plan.t * ub;
-    const float R2 = std::isinf(R) ? INFINITY : (float)(R * R);
-    const float slack = (float)(1e-5 * (2.0 * x->coord_scale + (std::isinf(R) ? 0.0 : R)));
-    const float limit = std::isinf(R) ? INFINITY : (float)R + slack;
+    if (!deferred && n_seed > 0) direct_seeds();
 
-    // ---- tiles surviving Mindist (Eq. 11)
+    // ---- tiles surviving Mindist (Eq. 11), then the pair scan of those tiles
     const int64_t tiles_total = NL * (NL - 1) / 2;
+    if (tiles_total > (int64_t(1) << 31) || NL > 65535)
+        fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
     int64_t n_tiles = 0;
     DevBuf tiles(x, S_TILES);
     TileScan scan(x, st);
-    if (tiles_total > 0) {
-        if (tiles_total > (int64_t(1) << 31) || NL > 65535)
-            fail(PMLSH_EUNSUPPORTED, "ACP supports at most 65535 leaves");
-        tiles.alloc((size_t)tiles_total * sizeof(int2));
-        reset_counter();
-        StageTimer tm(PMLSH_STAGE_ACP_TILES, st);
-        scan.prepare();
-        dim3 grid((unsigned)NL);
-        hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, scan.v, scan.leaf_base,
-                           NL, limit, 0, tiles.as<int2>(), tiles_total,
-                           static_cast<unsigned long long*>(dcount.p));
-        PMLSH_HIP(hipGetLastError());
-    }
-    if (tiles_total > 0) n_tiles = read_counter();
-
-    // ---- pair scan of the surviving tiles
     constexpr int64_t kMaxCand = int64_t(1) << 28;
     Triplets cand(x, S_CAND);
     int64_t n_raw = 0;
-    if (n_tiles > 0) {
-        int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
-        for (int attempt = 0; attempt < 2; ++attempt) {
+    int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
+    double R = 0.0;
+    float R2 = 0.f, limit = 0.f;
+    auto set_radii = [&] {
+        R = plan.t * ub;
+        R2 = std::isinf(R) ? INFINITY : (float)(R * R);
+        const float slack = (float)(1e-5 * (2.0 * x->coord_scale + (std::isinf(R) ? 0.0 : R)));
+        limit = std::isinf(R) ? INFINITY : (float)R + slack;
+    };
+    // tile filter and pair scan with host radii and host round trips
+    auto tiles_and_scan = [&] {
+        n_tiles = 0;
+        n_raw = 0;
+        if (tiles_total > 0) {
+            tiles.alloc((size_t)tiles_total * sizeof(int2));
+            reset_counter();
+            StageTimer tm(PMLSH_STAGE_ACP_TILES, st);
+            scan.prepare();
+            hipLaunchKernelGGL(acp_tile_filter_kernel, dim3((unsigned)NL), dim3(WG), 0, st, scan.v,
+                               scan.leaf_base, NL, limit, 0, tiles.as<int2>(), tiles_total,
+                               static_cast<unsigned long long*>(dcount.p), nullptr);
+            PMLSH_HIP(hipGetLastError());
+        }
+        if (tiles_total > 0) n_tiles = read_counter();
+        for (int attempt = 0; n_tiles > 0 && attempt < 2; ++attempt) {
             cand.alloc(cap);
             reset_counter();
             {
@@ -1970,6 +2045,68 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
                 fail(PMLSH_EUNSUPPORTED, "more than 2^28 candidate pairs pass the radius filter");
             cap = n_raw;
         }
+    };
+    if (deferred) {
+        unsigned long long* cnt = dcnts.as<unsigned long long>();
+        if (tiles_total > 0) {
+            tiles.alloc((size_t)tiles_total * sizeof(int2));
+            {
+                StageTimer tm(PMLSH_STAGE_ACP_TILES, st);
+                scan.prepare();
+                hipLaunchKernelGGL(acp_tile_filter_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
+                                   scan.v, scan.leaf_base, NL, 0.f, 0, tiles.as<int2>(), tiles_total,
+                                   cnt + 1, drad.as<AcpRadius>());
+                PMLSH_HIP(hipGetLastError());
+            }
+            cand.alloc(cap);
+            StageTimer tm(PMLSH_STAGE_ACP_SCAN, st);
+            scan.scan(tiles.as<int2>(), tiles_total, 0.f, 0.f, cand.k0.as<uint32_t>(),
+                      cand.ii.as<uint32_t>(), cand.jj.as<uint32_t>(), cap, cnt + 2, cnt + 1,
+                      drad.as<AcpRadius>());
+        }
+        // the one read of this sequence: band size, ub, tile and candidate counts
+        unsigned long long hc[3] = {0, 0, 0};
+        SelState hs{};
+        PMLSH_HIP(hipMemcpyAsync(hc, dcnts.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipMemcpyAsync(&hs, dstate2.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+        PMLSH_HIP(hipStreamSynchronize(st));
+        n_band = (int64_t)hc[0];
+        if (n_band <= bcap) {
+            gram = true;
+            if (!all_seeds) take_ub(hs);
+            set_radii();
+            n_tiles = (int64_t)hc[1];
+            n_raw = (int64_t)hc[2];
+            if (n_raw > cap) {
+                // the candidate buffer overflowed: scan again at the full count
+                if (n_raw > kMaxCand)
+                    fail(PMLSH_EUNSUPPORTED, "more than 2^28 candidate pairs pass the radius filter");
+                cap = n_raw;
+                cand.alloc(cap);
+                reset_counter();
+                {
+                    StageTimer tm(PMLSH_STAGE_ACP_SCAN, st);
+                    scan.scan(tiles.as<int2>(), n_tiles, R2, limit, cand.k0.as<uint32_t>(),
+                              cand.ii.as<uint32_t>(), cand.jj.as<uint32_t>(), cap,
+                              static_cast<unsigned long long*>(dcount.p));
+                }
+                if (read_counter() != n_raw) fail(PMLSH_EDEVICE, "pair scan count changed");
+            }
+        } else {
+            // the band outgrew its capacity: gather it again at its size (or
+            // take the direct self-join), then the tiles and the scan
+            if (n_band <= band_max) {
+                bcap = n_band;
+                launch_band();
+                gram = read_band();
+            }
+            if (!gram) direct_seeds();
+            set_radii();
+            tiles_and_scan();
+        }
+    } else {
+        set_radii();
+        tiles_and_scan();
     }
 
     // ---- budget T: keep the projected-nearest candidates
@@ -2005,58 +2142,81 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         std::memcpy(&seed_lim, &lim, 4);
     }
     Triplets pool(x, S_POOL);
-    int64_t seed_cap = gram ? n_band
-                            : std::min<int64_t>(n_seed, std::max<int64_t>(4096, 4 * (int64_t)k));
-    int64_t n_pool_seeds = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        pool.alloc(std::max<int64_t>(seed_cap + n_keep, 1));
-        if (n_seed == 0) break;
-        reset_counter();
-        StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
-        const SelKey all{0, seed_lim, 0, 0};
-        if (gram) {
-            if (n_band > 0)
+    Triplets top(x, S_TOP);
+    if (gram) {
+        // the verified candidates first (their number is known), then the
+        // band's seeds appended on a device counter: the pool's size is read
+        // back only if the top-k cannot finish in one workgroup
+        pool.alloc(std::max<int64_t>(n_band + n_keep, 1));
+        unsigned long long* nseeds = dcnts.as<unsigned long long>() + 3;
+        PMLSH_HIP(hipMemsetAsync(nseeds, 0, sizeof(unsigned long long), st));
+        {
+            StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
+            if (n_keep > 0) {
+                hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(n_keep, WG / 16)), dim3(WG), 0, st,
+                                   x->data, x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(),
+                                   cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>(),
+                                   pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(), nullptr);
+                PMLSH_HIP(hipGetLastError());
+            }
+            if (n_band > 0) {
+                const SelKey all{0, seed_lim, 0, 0};
                 hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_band, WG)), dim3(WG), 0, st,
                                    band.k0.as<uint32_t>(), band.ii.as<uint32_t>(),
-                                   band.jj.as<uint32_t>(), n_band, all, pool.k0.as<uint32_t>(),
+                                   band.jj.as<uint32_t>(), n_band, all,
+                                   pool.k0.as<uint32_t>() + n_keep, pool.ii.as<uint32_t>() + n_keep,
+                                   pool.jj.as<uint32_t>() + n_keep, n_band, nseeds);
+                PMLSH_HIP(hipGetLastError());
+            }
+        }
+        StageTimer tm(PMLSH_STAGE_ACP_TOPK, st);
+        pool_topk(x, pool, n_keep, k, gamma, top, dhist, dcount, out_pairs, out_dist, st, nseeds,
+                  n_keep + n_band);
+    } else {
+        int64_t seed_cap = std::min<int64_t>(n_seed, std::max<int64_t>(4096, 4 * (int64_t)k));
+        int64_t n_pool_seeds = 0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            pool.alloc(std::max<int64_t>(seed_cap + n_keep, 1));
+            if (n_seed == 0) break;
+            reset_counter();
+            StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
+            const SelKey all{0, seed_lim, 0, 0};
+            if (L > 64) {
+                hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_seed, WG)), dim3(WG), 0, st,
+                                   seeds.k0.as<uint32_t>(), seeds.ii.as<uint32_t>(),
+                                   seeds.jj.as<uint32_t>(), n_seed, all, pool.k0.as<uint32_t>(),
                                    pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(), seed_cap,
                                    static_cast<unsigned long long*>(dcount.p));
-        } else if (L > 64) {
-            hipLaunchKernelGGL(acp_gather_kernel, dim3(grid_for(n_seed, WG)), dim3(WG), 0, st,
-                               seeds.k0.as<uint32_t>(), seeds.ii.as<uint32_t>(),
-                               seeds.jj.as<uint32_t>(), n_seed, all, pool.k0.as<uint32_t>(),
-                               pool.ii.as<uint32_t>(), pool.jj.as<uint32_t>(), seed_cap,
-                               static_cast<unsigned long long*>(dcount.p));
-        } else {
-            hipLaunchKernelGGL(acp_seed_band_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
-                               seeds.k0.as<uint32_t>(), doff.as<int64_t>(), x->perm, n, L,
-                               seed_lim, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
-                               pool.jj.as<uint32_t>(), seed_cap,
-                               static_cast<unsigned long long*>(dcount.p));
+            } else {
+                hipLaunchKernelGGL(acp_seed_band_kernel, dim3((unsigned)NL), dim3(WG), 0, st,
+                                   seeds.k0.as<uint32_t>(), doff.as<int64_t>(), x->perm, n, L,
+                                   seed_lim, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+                                   pool.jj.as<uint32_t>(), seed_cap,
+                                   static_cast<unsigned long long*>(dcount.p));
+            }
+            PMLSH_HIP(hipGetLastError());
+            n_pool_seeds = read_counter();
+            if (n_pool_seeds <= seed_cap) break;
+            seed_cap = n_pool_seeds;
         }
-        PMLSH_HIP(hipGetLastError());
-        n_pool_seeds = read_counter();
-        if (n_pool_seeds <= seed_cap) break;
-        seed_cap = n_pool_seeds;
-    }
-    if (n_pool_seeds > seed_cap) fail(PMLSH_EDEVICE, "seed band grew between two passes");
-    const int64_t n_pool = n_pool_seeds + n_keep;
-    if (n_keep > 0) {
-        StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
-        hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(n_keep, WG / 16)), dim3(WG), 0, st,
-                           x->data, x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(),
-                           cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_pool_seeds,
-                           pool.ii.as<uint32_t>() + n_pool_seeds,
-                           pool.jj.as<uint32_t>() + n_pool_seeds, nullptr);
-        PMLSH_HIP(hipGetLastError());
-    }
-    if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
+        if (n_pool_seeds > seed_cap) fail(PMLSH_EDEVICE, "seed band grew between two passes");
+        const int64_t n_pool = n_pool_seeds + n_keep;
+        if (n_keep > 0) {
+            StageTimer tm(PMLSH_STAGE_ACP_VERIFY, st);
+            hipLaunchKernelGGL(acp_verify_kernel, dim3(grid_for(n_keep, WG / 16)), dim3(WG), 0, st,
+                               x->data, x->d_pad, x->inv_perm, cands->ii.as<uint32_t>(),
+                               cands->jj.as<uint32_t>(), n_keep, pool.k0.as<uint32_t>() + n_pool_seeds,
+                               pool.ii.as<uint32_t>() + n_pool_seeds,
+                               pool.jj.as<uint32_t>() + n_pool_seeds, nullptr);
+            PMLSH_HIP(hipGetLastError());
+        }
+        if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
 
-    // ---- top-k over the pool
-    Triplets top(x, S_TOP);
-    {
-        StageTimer tm(PMLSH_STAGE_ACP_TOPK, st);
-        pool_topk(x, pool, n_pool, k, gamma, top, dhist, dcount, out_pairs, out_dist, st);
+        // ---- top-k over the pool
+        {
+            StageTimer tm(PMLSH_STAGE_ACP_TOPK, st);
+            pool_topk(x, pool, n_pool, k, gamma, top, dhist, dcount, out_pairs, out_dist, st);
+        }
     }
 
     if (stats) {
@@ -2137,7 +2297,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
         dim3 grid((unsigned)NL);
         hipLaunchKernelGGL(acp_tile_filter_kernel, grid, dim3(WG), 0, st, v, leaf_base, NL,
                            limit, 1, tiles.as<int2>(), tiles_all,
-                           static_cast<unsigned long long*>(dcount.p));
+                           static_cast<unsigned long long*>(dcount.p), nullptr);
         PMLSH_HIP(hipGetLastError());
         return read_counter();
     };
