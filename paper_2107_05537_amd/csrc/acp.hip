@@ -1041,50 +1041,92 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
 // radix bin that holds the k-th smallest upper bound (the selection's prefix
 // of state->pbits bits), or every seed when all is set: their ids (i < j)
 // are appended. One wave per leaf (leaves of at most 64 points, at most
-// 2,016 pairs, all loaded before any test), so the whole grid is resident
-// at once.
-__global__ __launch_bounds__(64) void acp_seed_gram_band_kernel(
+// 2,016 pairs, all loaded before any test), sixteen leaves per workgroup:
+// the workgroup's pairs are gathered in LDS and appended with one global
+// atomic (a few thousand pairs spread over as many leaves would otherwise
+// queue that many atomics on one counter); pairs beyond the LDS buffer (mass
+// ties) are appended one wave at a time.
+constexpr int kBandWaves = 16;
+constexpr int kBandLds = 2048;
+
+__global__ __launch_bounds__(64 * kBandWaves) void acp_seed_gram_band_kernel(
     const uint32_t* __restrict__ lo, const int32_t* __restrict__ perm, int64_t n, int L,
-    const SelState* __restrict__ state, float widen, int all, uint32_t* __restrict__ oii,
-    uint32_t* __restrict__ ojj, int64_t cap, unsigned long long* __restrict__ counter) {
-    const int64_t leaf = blockIdx.x;
-    const int64_t p0 = leaf * L;
-    const int cnt = (int)(n - p0 < L ? n - p0 : L);
-    const int P = cnt * (cnt - 1) / 2;
-    const int64_t off = leaf * (int64_t)(L * (L - 1) / 2);
-    const int lane = threadIdx.x;
-    constexpr int PER = (64 * 63 / 2 + 63) / 64;
-    float v[PER];
+    int64_t n_leaves, const SelState* __restrict__ state, float widen, int all,
+    uint32_t* __restrict__ oii, uint32_t* __restrict__ ojj, int64_t cap,
+    unsigned long long* __restrict__ counter) {
+    __shared__ uint32_t bi[kBandLds], bj[kBandLds];
+    __shared__ unsigned int nl;
+    __shared__ unsigned long long gbase;
+    const int lane = threadIdx.x & 63;
+    const int64_t leaf = (int64_t)blockIdx.x * kBandWaves + (threadIdx.x >> 6);
+    if (threadIdx.x == 0) nl = 0u;
+    __syncthreads();
+    if (leaf < n_leaves) {
+        const int64_t p0 = leaf * L;
+        const int cnt = (int)(n - p0 < L ? n - p0 : L);
+        const int P = cnt * (cnt - 1) / 2;
+        const int64_t off = leaf * (int64_t)(L * (L - 1) / 2);
+        constexpr int PER = (64 * 63 / 2 + 63) / 64;
+        float v[PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int p = u * 64 + lane;
-        v[u] = p < P ? __uint_as_float(lo[off + p]) : INFINITY;
-    }
-    float lim = INFINITY;
-    if (!all) {
-        const int pb = state->pbits;
-        const uint32_t low = pb >= 32 ? 0u : (1u << (32 - pb)) - 1u;
-        const uint32_t top = pb >= 32 ? state->prefix : state->prefix << (32 - pb);
-        lim = __uint_as_float(top | low) * (1.f + widen) * (1.f + 3.814697265625e-06f);
-    }
-    uint64_t any = 0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) any |= __ballot(v[u] <= lim);
-    if (any == 0) return;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int p = u * 64 + lane;
-        const bool take = p < P && v[u] <= lim;
-        uint32_t i = 0, j = 0;
-        if (take) {
-            int a = 0, rem = p;
-            while (rem >= cnt - 1 - a) { rem -= cnt - 1 - a; ++a; }
-            const uint32_t ia = (uint32_t)perm[p0 + a], ib = (uint32_t)perm[p0 + a + 1 + rem];
-            i = ia < ib ? ia : ib;
-            j = ia < ib ? ib : ia;
+        for (int u = 0; u < PER; ++u) {
+            const int p = u * 64 + lane;
+            v[u] = p < P ? __uint_as_float(lo[off + p]) : INFINITY;
         }
-        const int64_t slot = wave_append_global(take, counter);
-        if (take && slot < cap) { oii[slot] = i; ojj[slot] = j; }
+        float lim = INFINITY;
+        if (!all) {
+            const int pb = state->pbits;
+            const uint32_t low = pb >= 32 ? 0u : (1u << (32 - pb)) - 1u;
+            const uint32_t top = pb >= 32 ? state->prefix : state->prefix << (32 - pb);
+            lim = __uint_as_float(top | low) * (1.f + widen) * (1.f + 3.814697265625e-06f);
+        }
+        uint64_t any = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) any |= __ballot(v[u] <= lim);
+        if (any) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int p = u * 64 + lane;
+                const bool take = p < P && v[u] <= lim;
+                const uint64_t m = __ballot(take);
+                if (m == 0) continue;
+                uint32_t i = 0, j = 0;
+                if (take) {
+                    int a = 0, rem = p;
+                    while (rem >= cnt - 1 - a) { rem -= cnt - 1 - a; ++a; }
+                    const uint32_t ia = (uint32_t)perm[p0 + a], ib = (uint32_t)perm[p0 + a + 1 + rem];
+                    i = ia < ib ? ia : ib;
+                    j = ia < ib ? ib : ia;
+                }
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                unsigned int base = 0u;
+                if (lane == leader) base = atomicAdd(&nl, (unsigned int)__popcll(m));
+                base = (unsigned int)__shfl((int)base, leader);
+                const unsigned int slot = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+                const bool spill = take && slot >= (unsigned int)kBandLds;
+                if (take && !spill) {
+                    bi[slot] = i;
+                    bj[slot] = j;
+                }
+                const int64_t g = wave_append_global(spill, counter);
+                if (spill && g < cap) {
+                    oii[g] = i;
+                    ojj[g] = j;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const unsigned int tot = nl < (unsigned int)kBandLds ? nl : (unsigned int)kBandLds;
+    if (tot == 0u) return;
+    if (threadIdx.x == 0) gbase = atomicAdd(counter, (unsigned long long)tot);
+    __syncthreads();
+    for (unsigned int t = threadIdx.x; t < tot; t += 64 * kBandWaves) {
+        const unsigned long long g = gbase + t;
+        if ((int64_t)g < cap) {
+            oii[g] = bi[t];
+            ojj[g] = bj[t];
+        }
     }
 }
 
@@ -1901,8 +1943,9 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         unsigned long long* cnt = dcnts.as<unsigned long long>();
         band.alloc(bcap);
         PMLSH_HIP(hipMemsetAsync(dcnts.p, 0, 4 * sizeof(unsigned long long), st));
-        hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)NL), dim3(64), 0, st,
-                           slo.as<uint32_t>(), x->perm, n, L, dstate.as<SelState>(),
+        hipLaunchKernelGGL(acp_seed_gram_band_kernel, dim3((unsigned)((NL + kBandWaves - 1) / kBandWaves)),
+                           dim3(64 * kBandWaves), 0, st, slo.as<uint32_t>(), x->perm, n, L, NL,
+                           dstate.as<SelState>(),
                            (float)(8.0 * gamma_v), all_seeds ? 1 : 0, band.ii.as<uint32_t>(),
                            band.jj.as<uint32_t>(), bcap, cnt);
         PMLSH_HIP(hipGetLastError());
