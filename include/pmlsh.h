@@ -488,8 +488,9 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
  * Test aid: process-wide switches of the ANN path: the group filter of the
  * bound kernel (the minima of 64-chunk groups that rule out the groups unable
  * to hold a chunk chosen for tau or a chunk passing Eq. 5), and the choice of
- * the plain FP32 per-query path for whole launches. Results are the same
- * under every setting; only the work differs.
+ * the plain FP32 per-query path for whole launches; and the first buffer
+ * capacities of pmlsh_acp. Results are the same under every setting; only
+ * the work differs.
  *   PMLSH_TUNE_GROUP_LIST         most groups (and 256-chunk blocks of the
  *                                 Eq. 5 test) one query lists, 0..2048
  *                                 (default 2048); when more qualify, or at 0,
@@ -502,13 +503,20 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
  *                                 1: every query of a launch takes the per-query
  *                                 kernel (PM-tree walk with Eq. 5, FP32 projected
  *                                 and exact distances), the plain FP32 path
+ *   PMLSH_TUNE_ACP_FIRST_CAP      0 (default): pmlsh_acp's first capacities
+ *                                 for the candidate pairs (2^20, or 4 k) and
+ *                                 the band of seeds verified exactly (2^16, or
+ *                                 4 k); 1..2^20: both start at this value, so
+ *                                 that the passes that redo a stage at the
+ *                                 full count run on small inputs
  * value -1 restores the default; a key or value out of range: PMLSH_EINVAL.
  * A call running while a switch changes may see either setting.
  */
 #define PMLSH_TUNE_GROUP_LIST 0
 #define PMLSH_TUNE_GROUP_MINIMA_LDS 1
 #define PMLSH_TUNE_FP32_PATH 2
-#define PMLSH_N_TUNE 3
+#define PMLSH_TUNE_ACP_FIRST_CAP 3
+#define PMLSH_N_TUNE 4
 
 int pmlsh_tune(int key, int64_t value);
 

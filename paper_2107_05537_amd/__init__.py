@@ -209,6 +209,7 @@ FILTER_GEMM_BF16 = 2          # ... from a BF16-input one
 TUNE_GROUP_LIST = 0          # most 64-chunk groups the ANN bound lists per query
 TUNE_GROUP_MINIMA_LDS = 1    # group minima in LDS (1) or read from HBM (0)
 TUNE_FP32_PATH = 2           # 1: whole launches on the plain FP32 per-query kernel
+TUNE_ACP_FIRST_CAP = 3       # first capacity of ACP's candidate and band buffers (0: defaults)
 
 
 def tune(key: int, value: int = -1):

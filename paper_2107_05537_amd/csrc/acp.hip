@@ -1926,6 +1926,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     // the direct self-join.
     const double gamma_v = pool_gamma(x, false);
     const int gram_k = 32 * ((x->d_pad + 31) / 32);
+    const int64_t first_cap = tune_get(PMLSH_TUNE_ACP_FIRST_CAP);   // 0: the defaults
     bool gram = false, deferred = false, all_seeds = n_seed < k;
     int64_t n_band = 0, band_max = 0, bcap = 0;
     DevBuf dstate2(x, S_STATE2), dcnts(x, S_COUNTS), drad(x, S_RADIUS);
@@ -2030,7 +2031,8 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         // followed it is redone.
         dstate2.alloc(sizeof(SelState));
         band_max = std::max<int64_t>(int64_t(1) << 20, n_seed / 8);
-        bcap = std::min<int64_t>(n_seed, std::max<int64_t>(int64_t(1) << 16, 4 * (int64_t)k));
+        bcap = std::min<int64_t>(n_seed, first_cap > 0 ? first_cap
+                                                       : std::max<int64_t>(int64_t(1) << 16, 4 * (int64_t)k));
         launch_band();
         hipLaunchKernelGGL(acp_radius_kernel, dim3(1), dim3(1), 0, st, dstate2.as<SelState>(),
                            all_seeds ? 0 : 1, plan.t, gamma_v, x->coord_scale, drad.as<AcpRadius>());
@@ -2049,7 +2051,8 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     constexpr int64_t kMaxCand = int64_t(1) << 28;
     Triplets cand(x, S_CAND);
     int64_t n_raw = 0;
-    int64_t cap = std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
+    int64_t cap = first_cap > 0 ? first_cap
+                                : std::min<int64_t>(kMaxCand, std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)k));
     double R = 0.0;
     float R2 = 0.f, limit = 0.f;
     auto set_radii = [&] {

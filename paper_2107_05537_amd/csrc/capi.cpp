@@ -586,7 +586,9 @@ int pmlsh_tune(int key, int64_t value) {
     return guarded([&] {
         if (key < 0 || key >= PMLSH_N_TUNE) fail(PMLSH_EINVAL, "unknown tuning key");
         if (value == -1) value = tune_default(key);
-        const int64_t hi = key == PMLSH_TUNE_GROUP_LIST ? 2048 : 1;
+        const int64_t hi = key == PMLSH_TUNE_GROUP_LIST      ? 2048
+                           : key == PMLSH_TUNE_ACP_FIRST_CAP ? (int64_t(1) << 20)
+                                                             : 1;
         if (value < 0 || value > hi) fail(PMLSH_EINVAL, "tuning value out of range");
         tune_set(key, value);
     });

@@ -232,6 +232,33 @@ def test_fewer_seeds_than_k_in_small_leaves():
     _compare(res, pairs, dist, st)
 
 
+@pytest.mark.parametrize("first_cap", [1, 8])
+def test_small_first_capacities_redo_at_full_count(first_cap):
+    """ACP's first buffer capacities forced down (pmlsh_tune): the band of
+    seeds verified exactly and the candidate list overflow, the band is
+    gathered again at its size and the pair scan redone at the full count;
+    the answers and the counts must equal the oracle's as with the
+    defaults."""
+    pm = _gpu()
+    say(f"case: ACP first capacity {first_cap}")
+    w = synth.uniform_cube(3, 2500, 12, 1)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A, leaf_size=32, fanout=4)
+    base = idx.acp(20, c=1.5)
+    pm.tune(pm.TUNE_ACP_FIRST_CAP, first_cap)
+    try:
+        pairs, dist, st = idx.acp(20, c=1.5)
+        torch.cuda.synchronize()
+    finally:
+        pm.tune(pm.TUNE_ACP_FIRST_CAP, -1)
+    res, _ = _oracle(idx, D, A, 20, 1.5, 1 - 1 / math.e, -1.0)
+    say("stats", st, "oracle raw", res.n_cand_raw)
+    assert st["n_cand_raw"] > first_cap
+    _compare(res, pairs, dist, st)
+    assert pairs.cpu().numpy().tolist() == base[0].cpu().numpy().tolist()
+    assert st == base[2]
+
+
 def test_budget_binding_and_unbounded_ub():
     pm = _gpu()
     say("case: ACP budget cut / ub = inf")
