@@ -500,7 +500,7 @@ def test_group_filter_settings_agree(parity_wl):
     with pytest.raises(pm.PmlshError):
         pm.tune(pm.TUNE_GROUP_LIST, 2049)
     with pytest.raises(pm.PmlshError):
-        pm.tune(3, 0)
+        pm.tune(4, 0)
 
 
 def test_large_n_sampled():
