@@ -1762,8 +1762,17 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
 // result register r of lane l holds point 4 (l / 16) + r of the tile and
 // listed query l % 16.
 
+// Two block shapes of the scan: 512 queries per workgroup (128 per wave,
+// three workgroups per compute unit) for indexes of fewer than
+// kScanLargeChunks chunks, 1,024 (256 per wave, two per compute unit) above:
+// staging a block's query rows is a fixed cost per workgroup, paid back only
+// when a workgroup has many chunks to scan, and a wave's list of passing
+// queries then fills more of each 16-query group.
 #ifndef PMLSH_SCAN_QB
 #define PMLSH_SCAN_QB 512
+#endif
+#ifndef PMLSH_SCAN_QB_LARGE
+#define PMLSH_SCAN_QB_LARGE 1024
 #endif
 #ifndef PMLSH_SCAN_STAGE
 #define PMLSH_SCAN_STAGE 1024
@@ -1771,28 +1780,34 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
 #ifndef PMLSH_SCAN_WAVES_PER_EU
 #define PMLSH_SCAN_WAVES_PER_EU 3
 #endif
-constexpr int SQB = PMLSH_SCAN_QB;      // queries per scan block
-constexpr int SQW = SQB / NWAVE;        // queries per wave
-constexpr int SWW = SQW / 64;           // mask words per wave
-constexpr int QPL = SQW / 64;           // queries per lane in the list building
-constexpr int SSTG = PMLSH_SCAN_STAGE;  // candidates staged per wave
-constexpr int SPAD = SQB;               // index of the padding row
+#ifndef PMLSH_SCAN_WAVES_PER_EU_LARGE
+#define PMLSH_SCAN_WAVES_PER_EU_LARGE 2
+#endif
+constexpr int64_t kScanLargeChunks = 32768;   // 2,097,152 points
+constexpr int SSTG = PMLSH_SCAN_STAGE;        // candidates staged per wave
 
 // Query rows, then per-wave candidate stages: every wave packs, stages,
 // counts and flushes its own candidates, so after the rows are loaded the
-// scan needs no workgroup barrier.
+// scan needs no workgroup barrier. QB queries per block.
+template <int QB>
 struct __align__(16) ScanShared {
-    uint16_t qrow[SQB + 1][kScanRow];       // FP16 query rows of the block, padding row last
+    uint16_t qrow[QB + 1][kScanRow];    // FP16 query rows of the block, padding row last
     uint32_t pos[NWAVE][SSTG];          // staged candidates: leaf position
     uint8_t qid[NWAVE][SSTG];           // and query within the wave's range
-    uint32_t hits[NWAVE][SQW], base[NWAVE][SQW];
+    uint32_t hits[NWAVE][QB / NWAVE], base[NWAVE][QB / NWAVE];
     // queries of the wave passing the chunk, by column: slot 16 g + j of the
     // list is lcol[j][g]
-    uint8_t lcol[NWAVE][16][SQW / 16];
+    uint8_t lcol[NWAVE][16][QB / NWAVE / 16];
 };
-static_assert(SWW * 64 == SQW && SWW <= 4, "a wave's queries are whole mask words");
-static_assert(sizeof(ScanShared) * PMLSH_SCAN_WAVES_PER_EU <= 160 * 1024,
-              "the scan workgroups of a compute unit fit its LDS");
+template <int QB, int WPE>
+constexpr bool scan_shape_ok() {
+    return (QB / NWAVE) % 64 == 0 && QB / NWAVE / 64 <= 4 && QB / NWAVE <= 256 &&
+           sizeof(ScanShared<QB>) * WPE <= 160 * 1024;
+}
+static_assert(scan_shape_ok<PMLSH_SCAN_QB, PMLSH_SCAN_WAVES_PER_EU>() &&
+                  scan_shape_ok<PMLSH_SCAN_QB_LARGE, PMLSH_SCAN_WAVES_PER_EU_LARGE>(),
+              "a wave's queries are whole mask words (ids below 256), and the scan "
+              "workgroups of a compute unit fit its LDS");
 
 __device__ __forceinline__ half8_t load_half8(const uint16_t* p) {
     return __builtin_bit_cast(half8_t, *reinterpret_cast<const uint4*>(p));
@@ -1807,8 +1822,9 @@ __device__ __forceinline__ void scan_mfma(const half8_t (&av)[4], half8_t b, flo
 // Writes the wave's staged candidates to the pool with one reservation per
 // query (queries qw0 .. qw0 + nqw - 1 of the batch) and empties the stage.
 // Only this wave touches its part of the shared memory.
-__device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared& ss, int wave, int lane, uint32_t& wn,
-                           int64_t qw0, int nqw) {
+template <int QB>
+__device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared<QB>& ss, int wave, int lane,
+                                           uint32_t& wn, int64_t qw0, int nqw) {
     uint32_t* hits = ss.hits[wave];
     uint32_t* base = ss.base[wave];
     for (uint32_t e = lane; e < wn; e += 64) atomicAdd(&hits[ss.qid[wave][e]], 1u);
@@ -1835,7 +1851,8 @@ __device__ __forceinline__ void scan_flush(const AnnArgs& a, ScanShared& ss, int
 // a ballot's candidates would not fit, so no candidate is lost. The group is
 // skipped when no result is negative; otherwise register r of the four tiles
 // is tested together first, since most register positions hold no candidate.
-__device__ __forceinline__ void scan_emit(const AnnArgs& a, ScanShared& ss, int wave, int lane,
+template <int QB>
+__device__ __forceinline__ void scan_emit(const AnnArgs& a, ScanShared<QB>& ss, int wave, int lane,
                                           uint32_t& wn, const float4_t (&cc)[4], int64_t p0, int q,
                                           int64_t qw0, int nqw) {
     // a result is a candidate when its sign bit is set
@@ -1867,8 +1884,13 @@ __device__ __forceinline__ void scan_emit(const AnnArgs& a, ScanShared& ss, int 
     }
 }
 
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PMLSH_SCAN_WAVES_PER_EU))) void scan_kernel(AnnArgs a) {
-    __shared__ ScanShared ss;
+template <int QB, int WPE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE))) void scan_kernel(AnnArgs a) {
+    constexpr int SQB = QB;           // queries per scan block
+    constexpr int SQW = SQB / NWAVE;  // queries per wave
+    constexpr int QPL = SQW / 64;     // queries per lane in the list building
+    constexpr int SPAD = SQB;         // index of the padding row
+    __shared__ ScanShared<QB> ss;
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lq = lane >> 4;
@@ -2478,22 +2500,33 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
             hipLaunchKernelGGL(mask_kernel, mgrid, dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
-        // one resident wave of workgroups striding over the chunks
-        static thread_local int scan_slots[64] = {0};
-        int& slots = scan_slots[x.device & 63];
+        // one resident wave of workgroups striding over the chunks, in the
+        // block shape that suits the index's size
+        const bool large = nchunk >= kScanLargeChunks;
+        const void* scan_fn =
+            large ? (const void*)scan_kernel<PMLSH_SCAN_QB_LARGE, PMLSH_SCAN_WAVES_PER_EU_LARGE>
+                  : (const void*)scan_kernel<PMLSH_SCAN_QB, PMLSH_SCAN_WAVES_PER_EU>;
+        const int sqb = large ? PMLSH_SCAN_QB_LARGE : PMLSH_SCAN_QB;
+        static thread_local int scan_slots[64][2] = {};
+        int& slots = scan_slots[x.device & 63][large ? 1 : 0];
         if (slots == 0) {
             int per_cu = 0, cus = 0;
-            PMLSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scan_kernel, WG, 0));
+            PMLSH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scan_fn, WG, 0));
             PMLSH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x.device));
             slots = per_cu > 0 && cus > 0 ? per_cu * cus : (int)kScanBlocks;
         }
-        const int64_t ny = (L.nq + SQB - 1) / SQB;
+        const int64_t ny = (L.nq + sqb - 1) / sqb;
         int64_t gx = std::max<int64_t>(1, slots / ny);
         gx = std::min(gx, nchunk);   // at least one chunk per workgroup on average
         dim3 sgrid((unsigned)gx, (unsigned)ny);
         {
             StageTimer tm(PMLSH_STAGE_FILTER, stream);
-            hipLaunchKernelGGL(scan_kernel, sgrid, dim3(WG), 0, stream, a);
+            if (large)
+                hipLaunchKernelGGL((scan_kernel<PMLSH_SCAN_QB_LARGE, PMLSH_SCAN_WAVES_PER_EU_LARGE>),
+                                   sgrid, dim3(WG), 0, stream, a);
+            else
+                hipLaunchKernelGGL((scan_kernel<PMLSH_SCAN_QB, PMLSH_SCAN_WAVES_PER_EU>), sgrid,
+                                   dim3(WG), 0, stream, a);
             PMLSH_HIP(hipGetLastError());
         }
         PMLSH_HIP(hipFuncSetAttribute((const void*)finish_kernel,
