@@ -349,7 +349,7 @@ void worker_loop(pmlsh_server* s) {
                         lk.unlock();
                         retire_one(s, true);
                     } else {
-                        s->cv_work.wait_for(lk, std::chrono::microseconds(50),
+                        s->cv_work.wait_for(lk, std::chrono::microseconds(10),
                                             [&] { return s->stop || !s->waiting.empty(); });
                     }
                 }
