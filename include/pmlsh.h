@@ -488,8 +488,8 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
  * Test aid: process-wide switches of the ANN path: the group filter of the
  * bound kernel (the minima of 64-chunk groups that rule out the groups unable
  * to hold a chunk chosen for tau or a chunk passing Eq. 5), and the choice of
- * the plain FP32 per-query path for whole launches; and the first buffer
- * capacities of pmlsh_acp. Results are the same under every setting; only
+ * the plain FP32 per-query path for whole launches, the block shape of the
+ * range filter; and the first buffer capacities of pmlsh_acp. Results are the same under every setting; only
  * the work differs.
  *   PMLSH_TUNE_GROUP_LIST         most groups (and 256-chunk blocks of the
  *                                 Eq. 5 test) one query lists, 0..2048
@@ -509,6 +509,11 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
  *                                 4 k); 1..2^20: both start at this value, so
  *                                 that the passes that redo a stage at the
  *                                 full count run on small inputs
+ *   PMLSH_TUNE_SCAN_SHAPE         0 (default): the range filter's query block
+ *                                 follows the index's size (512 queries per
+ *                                 workgroup below 32,768 chunks of 64 points,
+ *                                 1,024 from there on); 1: always 512; 2:
+ *                                 always 1,024
  * value -1 restores the default; a key or value out of range: PMLSH_EINVAL.
  * A call running while a switch changes may see either setting.
  */
@@ -516,7 +521,8 @@ int pmlsh_ann_timing_read(pmlsh_ann_timing* out, int reset);
 #define PMLSH_TUNE_GROUP_MINIMA_LDS 1
 #define PMLSH_TUNE_FP32_PATH 2
 #define PMLSH_TUNE_ACP_FIRST_CAP 3
-#define PMLSH_N_TUNE 4
+#define PMLSH_TUNE_SCAN_SHAPE 4
+#define PMLSH_N_TUNE 5
 
 int pmlsh_tune(int key, int64_t value);
 

@@ -210,6 +210,7 @@ TUNE_GROUP_LIST = 0          # most 64-chunk groups the ANN bound lists per quer
 TUNE_GROUP_MINIMA_LDS = 1    # group minima in LDS (1) or read from HBM (0)
 TUNE_FP32_PATH = 2           # 1: whole launches on the plain FP32 per-query kernel
 TUNE_ACP_FIRST_CAP = 3       # first capacity of ACP's candidate and band buffers (0: defaults)
+TUNE_SCAN_SHAPE = 4          # range filter block: 0 by index size, 1: 512 queries, 2: 1,024
 
 
 def tune(key: int, value: int = -1):

@@ -2502,7 +2502,8 @@ void launch_ann(const AnnLaunch& L, hipStream_t stream) {
         }
         // one resident wave of workgroups striding over the chunks, in the
         // block shape that suits the index's size
-        const bool large = nchunk >= kScanLargeChunks;
+        const int64_t shape = tune_get(PMLSH_TUNE_SCAN_SHAPE);
+        const bool large = shape == 0 ? nchunk >= kScanLargeChunks : shape == 2;
         const void* scan_fn =
             large ? (const void*)scan_kernel<PMLSH_SCAN_QB_LARGE, PMLSH_SCAN_WAVES_PER_EU_LARGE>
                   : (const void*)scan_kernel<PMLSH_SCAN_QB, PMLSH_SCAN_WAVES_PER_EU>;

@@ -588,6 +588,7 @@ int pmlsh_tune(int key, int64_t value) {
         if (value == -1) value = tune_default(key);
         const int64_t hi = key == PMLSH_TUNE_GROUP_LIST      ? 2048
                            : key == PMLSH_TUNE_ACP_FIRST_CAP ? (int64_t(1) << 20)
+                           : key == PMLSH_TUNE_SCAN_SHAPE    ? 2
                                                              : 1;
         if (value < 0 || value > hi) fail(PMLSH_EINVAL, "tuning value out of range");
         tune_set(key, value);

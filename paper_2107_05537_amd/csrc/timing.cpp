@@ -106,13 +106,15 @@ void timing_read(pmlsh_ann_timing* out, bool reset) {
 
 // ---------------------------------------------------------------- switches
 namespace {
-std::atomic<int64_t> g_tune[PMLSH_N_TUNE] = {{2048}, {1}, {0}, {0}};
+std::atomic<int64_t> g_tune[PMLSH_N_TUNE] = {{2048}, {1}, {0}, {0}, {0}};
 }  // namespace
 
 int64_t tune_default(int key) {
     return key == PMLSH_TUNE_GROUP_LIST ? 2048
-           : key == PMLSH_TUNE_FP32_PATH || key == PMLSH_TUNE_ACP_FIRST_CAP ? 0
-                                                                          : 1;
+           : key == PMLSH_TUNE_FP32_PATH || key == PMLSH_TUNE_ACP_FIRST_CAP ||
+                   key == PMLSH_TUNE_SCAN_SHAPE
+               ? 0
+               : 1;
 }
 int64_t tune_get(int key) { return g_tune[key].load(std::memory_order_relaxed); }
 void tune_set(int key, int64_t value) { g_tune[key].store(value, std::memory_order_relaxed); }

@@ -170,17 +170,20 @@ def test_server_null_handles_rejected(lib):
 
 def test_tune_switches(lib):
     """pmlsh_tune takes the two switches of the bound kernel's group filter,
-    the FP32-path switch and ACP's first capacity within their ranges (-1
+    the FP32-path switch, the scan shape and ACP's first capacity within
+    their ranges (-1
     restores the default) and rejects anything else; it touches no GPU."""
     for key, good in ((pm.TUNE_GROUP_LIST, (0, 1, 2048, -1)), (pm.TUNE_GROUP_MINIMA_LDS, (0, 1, -1)),
-                      (pm.TUNE_FP32_PATH, (1, 0, -1)), (pm.TUNE_ACP_FIRST_CAP, (1, 1 << 20, 0, -1))):
+                      (pm.TUNE_FP32_PATH, (1, 0, -1)), (pm.TUNE_ACP_FIRST_CAP, (1, 1 << 20, 0, -1)),
+                      (pm.TUNE_SCAN_SHAPE, (1, 2, 0, -1))):
         for v in good:
             assert lib.pmlsh_tune(key, v) == 0
     for key, bad in ((pm.TUNE_GROUP_LIST, (2049, -2)), (pm.TUNE_GROUP_MINIMA_LDS, (2, -5)),
-                     (pm.TUNE_FP32_PATH, (2, -3)), (pm.TUNE_ACP_FIRST_CAP, ((1 << 20) + 1, -2))):
+                     (pm.TUNE_FP32_PATH, (2, -3)), (pm.TUNE_ACP_FIRST_CAP, ((1 << 20) + 1, -2)),
+                     (pm.TUNE_SCAN_SHAPE, (3, -2))):
         for v in bad:
             assert lib.pmlsh_tune(key, v) == pm.EINVAL
-    for key in (-1, 4, 99):
+    for key in (-1, 5, 99):
         assert lib.pmlsh_tune(key, 0) == pm.EINVAL
     with pytest.raises(pm.PmlshError):
         pm.tune(pm.TUNE_GROUP_LIST, 5000)

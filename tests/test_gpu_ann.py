@@ -500,7 +500,34 @@ def test_group_filter_settings_agree(parity_wl):
     with pytest.raises(pm.PmlshError):
         pm.tune(pm.TUNE_GROUP_LIST, 2049)
     with pytest.raises(pm.PmlshError):
-        pm.tune(4, 0)
+        pm.tune(5, 0)
+
+
+def test_scan_shapes_agree(parity_wl):
+    """The range filter in both block shapes (512 and 1,024 queries per
+    workgroup, pmlsh_tune) gives the same answers and statistics, and they
+    match the oracle."""
+    pm = _gpu()
+    D, A, Q = parity_wl["D"], parity_wl["A"], parity_wl["Q"]
+    dev = torch.device("cuda", 0)
+    idx = pm.Index(torch.from_numpy(D).to(dev), torch.from_numpy(A).to(dev))
+    Qd = torch.from_numpy(Q).to(dev)
+    res, B = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=1.0)
+    r0 = idx.default_r_min(B)
+    res, _ = oracle_ann(D, A, Q, 10, 1.5, 0.9, 0.1, r_min=r0)
+    outs = []
+    try:
+        for shape in (1, 2):
+            say(f"case: scan shape {shape}")
+            pm.tune(pm.TUNE_SCAN_SHAPE, shape)
+            ids, dist, st = idx.ann(Qd, 10, c=1.5, confidence=0.9, beta=0.1, r_min=r0, stats=True)
+            torch.cuda.synchronize()
+            outs.append((ids.cpu().numpy(), dist.cpu().numpy(), st.cpu().numpy()))
+    finally:
+        pm.tune(pm.TUNE_SCAN_SHAPE, -1)
+    for a_, b_ in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a_, b_)
+    compare_ann(D, Q, res, *outs[1], fp64=True)
 
 
 def test_large_n_sampled():
