@@ -110,7 +110,9 @@ struct AnnArgs {
     const float* chunk_cen;
     const float* chunk_rad;
     float2* qtest;
-    uint64_t* cmask;            // the same mask chunk-major: ceil(nq / 64) words per chunk
+    // the same mask chunk-major, in blocks of 256 chunks: word (chunk c, query
+    // band qb) at cmask_at(c, qb), cwords = ceil(nq / 64) bands
+    uint64_t* cmask;
     int cwords;
     // squared distances from every query to every chunk centre, as bf16 bit
     // patterns rounded toward zero (lower bounds), in blocks of 64 queries x
@@ -134,6 +136,12 @@ struct AnnArgs {
 // Element (query q, chunk c) of the blocked chunk-distance matrix.
 __device__ __forceinline__ int64_t cdist_at(const AnnArgs& a, int64_t q, int64_t c) {
     return (((q >> 6) * a.cgroups + (c >> 6)) << 12) + ((q & 63) << 6) + (c & 63);
+}
+
+// Mask word of chunk c and query band qb (queries 64 qb .. 64 qb + 63): the
+// 256 words of one band and one block of 256 chunks are contiguous.
+__device__ __forceinline__ int64_t cmask_at(const AnnArgs& a, int64_t c, int64_t qb) {
+    return (((c >> 8) * a.cwords + qb) << 8) + (c & 255);
 }
 
 // skey and spos come last: the bound kernel uses only the fields before
@@ -1720,9 +1728,9 @@ __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
     __syncthreads();
     if (qh == 0) {
         if (c < nch)
-            a.cmask[(int64_t)c * a.cwords + blockIdx.y] = (uint64_t)b0 | ((uint64_t)hib[2 * cp] << 32);
+            a.cmask[cmask_at(a, c, blockIdx.y)] = (uint64_t)b0 | ((uint64_t)hib[2 * cp] << 32);
         if (c + 1 < nch)
-            a.cmask[(int64_t)(c + 1) * a.cwords + blockIdx.y] =
+            a.cmask[cmask_at(a, c + 1, blockIdx.y)] =
                 (uint64_t)b1 | ((uint64_t)hib[2 * cp + 1] << 32);
     }
     if ((int)threadIdx.x < nqb && cnt[threadIdx.x])
@@ -1929,9 +1937,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // range, held in mask word i / (64 / QPL) (those lanes load it together)
     const int pk_word = lane / (64 / QPL), pk_shift = QPL * (lane % (64 / QPL));
     const bool mword = pk_word < nw;
-    const uint64_t* mbase = a.cmask + (q0 >> 6) + w0 + pk_word;
+    const int64_t mband = (q0 >> 6) + w0 + pk_word;
     const uint16_t* rbase = a.proj16 + (l16 * kScanRow + lq * 8);
-    const int64_t mstride = a.cwords;
+
     struct Slot {
         half8_t r[4];
         uint64_t m;
@@ -1942,7 +1950,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) dst.r[mt] = half8_t{};
         if (cc < nchunk) {
-            if (mword) dst.m = mbase[cc * mstride];
+            if (mword) dst.m = a.cmask[cmask_at(a, cc, mband)];
             if (lq < 3) {
                 const uint16_t* rp = rbase + cc * (64 * kScanRow);
 #pragma unroll

@@ -63,7 +63,8 @@ int64_t front_slots(const pmlsh_index* x, bool fast, int64_t batch) {
 int64_t ann_layout_bytes(const pmlsh_index* x, const AnnWorkspace& w, int64_t batch,
                          int64_t slots) {
     const int64_t mask_bytes =
-        w.fast ? batch * 8 + 2 * cdist_elems(batch, w.nchunk) + w.nchunk * ((batch + 63) / 64) * 8 + 64
+        w.fast ? batch * 8 + 2 * cdist_elems(batch, w.nchunk) +
+                     (w.nchunk + 255) / 256 * 256 * ((batch + 63) / 64) * 8 + 64
                : 0;
     return batch * w.per_query + mask_bytes + slots * 2 * x->n_leaves * 4;
 }
@@ -173,7 +174,8 @@ void run_ann_region(const pmlsh_index* x, const float* queries, int64_t nq, cons
     uint16_t* cgmin = cdist2 + (fast ? cdist_block_elems(batch, nchunk) : 0);
     float2* qtest = reinterpret_cast<float2*>(cdist2 + (fast ? cdist_elems(batch, nchunk) : 0));
     uint64_t* cmask = reinterpret_cast<uint64_t*>(qtest + (fast ? batch : 0));
-    uint32_t* list = reinterpret_cast<uint32_t*>(cmask + (fast ? nchunk * ((batch + 63) / 64) : 0));
+    uint32_t* list = reinterpret_cast<uint32_t*>(
+        cmask + (fast ? (nchunk + 255) / 256 * 256 * ((batch + 63) / 64) : 0));
     int32_t* front = reinterpret_cast<int32_t*>(list + batch * pool_q);
     int32_t* cpos = front + w.slots * 2 * x->n_leaves;
     float* cdist = reinterpret_cast<float*>(cpos + batch * B);

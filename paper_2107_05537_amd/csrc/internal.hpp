@@ -355,7 +355,7 @@ struct AnnLaunch {
     float* ws_qlp;          // nq x MP low-precision query projections (filter_gemm), or null
     float* ws_qeps;         // nq: their bounds
     float2* ws_qtest;       // nq: radius and margin of each query's chunk-ball test
-    uint64_t* ws_cmask;     // the same, chunk-major: chunks x ceil(nq / 64) words
+    uint64_t* ws_cmask;     // the same, chunk-major in blocks of 256 chunks x ceil(nq / 64) words
     uint16_t* ws_cdist2;    // squared distances to the chunk centres (bf16, rounded down), in
                             // blocks of 64 queries x 64 chunks
     uint16_t* ws_cgmin;     // nq x cdist_gmin_len: their minimum per group of 64 chunks
