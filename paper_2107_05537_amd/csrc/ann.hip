@@ -1666,72 +1666,78 @@ __global__ __launch_bounds__(WG) void tau_kernel(AnnArgs a) {
 // The chunk-ball test of Eq. 5 for every (query, chunk) pair of the batch,
 // written as the chunk-major mask the scan reads: bit l of word qb of chunk
 // c is query 64 qb + l. A workgroup takes 64 queries x 256 chunks: thread t
-// holds chunks c = 2 (t % 128) and c + 1 of its block and the queries
-// 32 (t / 128) .. + 31, reads the two stored squared centre distances of
-// each query row in one 4-byte load (128 threads cover 512 contiguous bytes
-// of a row) and tests d^2 <= (radius + tq)^2 + margin with the query's
-// (tq, margin) from the bound kernel. The two halves of every chunk's word
-// meet in LDS; each query's passing chunks, 64 points each, are added to its
-// scan count.
+// holds the eight chunks 8 (t % 32) .. + 7 of its block and the eight
+// queries 8 (t / 32) .. + 7, reads the eight stored squared centre distances
+// of each of its query rows in one 16-byte load (eight threads cover a
+// query's 128-byte row of a 64-chunk block) and tests d^2 <= (radius +
+// tq)^2 + margin with the query's (tq, margin) from the bound kernel. The
+// eight query bits of every chunk are one byte of its word, stored in LDS as
+// one 8-byte run per thread and assembled per chunk; each query's passing
+// chunks, 64 points each, are added to its scan count.
 constexpr int MQB = 64;    // queries per workgroup (one mask word)
-constexpr int MCH = 256;   // chunks per workgroup: two per thread of a query half
-static_assert(MCH == 2 * (WG / 2), "each half of the workgroup covers the block's chunks");
+constexpr int MCH = 256;   // chunks per workgroup: eight per thread of a query octet
+static_assert(MCH == 8 * 32 && MQB == 8 * (WG / 32), "thread t: chunk octet t % 32, query octet t / 32");
 
 __global__ __launch_bounds__(WG) void mask_kernel(AnnArgs a) {
     __shared__ float2 qt[MQB];
-    __shared__ uint32_t hib[MCH];
+    __shared__ __align__(16) uint8_t lb[MQB / 8][MCH];   // row qo: byte qo of every chunk's word
     __shared__ uint32_t cnt[MQB];
     const int nch = (int)(a.n_pad16 >> 6);
     const int q0 = blockIdx.y * MQB;
     const int nqb = min(MQB, a.nq - q0);
-    const int cp = threadIdx.x & 127, qh = threadIdx.x >> 7;
-    const int c = blockIdx.x * MCH + 2 * cp;
-    const int lane = lane_id();
+    const int co = threadIdx.x & 31, qo = threadIdx.x >> 5;
+    const int c0 = blockIdx.x * MCH + 8 * co;   // the thread's first chunk
     if (threadIdx.x < MQB) {
         qt[threadIdx.x] = (int)threadIdx.x < nqb ? a.qtest[q0 + threadIdx.x] : make_float2(0.f, 0.f);
         cnt[threadIdx.x] = 0u;
     }
-    __syncthreads();
-    const float r0 = c < nch ? a.chunk_rad[c] : 0.f;
-    const float r1 = c + 1 < nch ? a.chunk_rad[c + 1] : 0.f;
-    uint32_t b0 = 0u, b1 = 0u;
-    constexpr int QU = 8;   // query rows whose loads go out together
-    for (int g0 = 0; g0 < 32; g0 += QU) {
-        uint32_t w[QU];
+    // the eight rows' loads go out before any test
+    uint4 w[8];
 #pragma unroll
-        for (int u = 0; u < QU; ++u) {
-            const int q = qh * 32 + g0 + u;
-            // c is even: an aligned pair inside one block row
-            w[u] = q < nqb && c < nch
-                       ? *reinterpret_cast<const uint32_t*>(a.cdist + cdist_at(a, q0 + q, c))
-                       : 0u;
-        }
+    for (int u = 0; u < 8; ++u) {
+        const int q = 8 * qo + u;
+        w[u] = q < nqb && c0 < nch
+                   ? *reinterpret_cast<const uint4*>(a.cdist + cdist_at(a, q0 + q, c0))
+                   : make_uint4(0u, 0u, 0u, 0u);
+    }
+    float rad[8];
 #pragma unroll
-        for (int u = 0; u < QU; ++u) {
-            const int q = qh * 32 + g0 + u;
-            const float2 t = qt[q];
-            const float ra = r0 + t.x, rb = r1 + t.x;
-            const bool p0 = q < nqb && c < nch && __uint_as_float(w[u] << 16) <= fmaf(ra, ra, t.y);
-            const bool p1 = q < nqb && c + 1 < nch &&
-                            __uint_as_float(w[u] & 0xffff0000u) <= fmaf(rb, rb, t.y);
-            b0 |= (uint32_t)p0 << (g0 + u);
-            b1 |= (uint32_t)p1 << (g0 + u);
-            const int np = __popcll(__builtin_amdgcn_ballot_w64(p0)) +
-                           __popcll(__builtin_amdgcn_ballot_w64(p1));
-            if (lane == 0 && np) atomicAdd(&cnt[q], (uint32_t)np);
-        }
-    }
-    if (qh == 1) {
-        hib[2 * cp] = b0;
-        hib[2 * cp + 1] = b1;
-    }
+    for (int e = 0; e < 8; ++e) rad[e] = c0 + e < nch ? a.chunk_rad[c0 + e] : 0.f;
     __syncthreads();
-    if (qh == 0) {
-        if (c < nch)
-            a.cmask[cmask_at(a, c, blockIdx.y)] = (uint64_t)b0 | ((uint64_t)hib[2 * cp] << 32);
-        if (c + 1 < nch)
-            a.cmask[cmask_at(a, c + 1, blockIdx.y)] =
-                (uint64_t)b1 | ((uint64_t)hib[2 * cp + 1] << 32);
+    uint32_t bits[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};   // chunk e: the eight query bits
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int q = 8 * qo + u;
+        const float2 t = qt[q];
+        const uint32_t h[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+        uint32_t np = 0u;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t hb = (e & 1) ? (h[e >> 1] & 0xffff0000u) : (h[e >> 1] << 16);
+            const float ra = rad[e] + t.x;
+            const bool p = q < nqb && c0 + e < nch && __uint_as_float(hb) <= fmaf(ra, ra, t.y);
+            bits[e] |= (uint32_t)p << u;
+            np += p;
+        }
+        // the query's passing chunks over the 32 chunk octets (half a wave)
+        np += (uint32_t)__shfl_xor((int)np, 1);
+        np += (uint32_t)__shfl_xor((int)np, 2);
+        np += (uint32_t)__shfl_xor((int)np, 4);
+        np += (uint32_t)__shfl_xor((int)np, 8);
+        np += (uint32_t)__shfl_xor((int)np, 16);
+        if (co == 0 && np) cnt[q] = np;
+    }
+    // the eight chunks' bytes of this query octet in one 8-byte store
+    *reinterpret_cast<uint2*>(&lb[qo][8 * co]) =
+        make_uint2(bits[0] | (bits[1] << 8) | (bits[2] << 16) | (bits[3] << 24),
+                   bits[4] | (bits[5] << 8) | (bits[6] << 16) | (bits[7] << 24));
+    __syncthreads();
+    for (int i = threadIdx.x; i < MCH; i += WG) {
+        const int c = blockIdx.x * MCH + i;
+        uint64_t wd = 0ull;
+#pragma unroll
+        for (int o = 0; o < MQB / 8; ++o) wd |= (uint64_t)lb[o][i] << (8 * o);
+        if (c < nch) a.cmask[cmask_at(a, c, blockIdx.y)] = wd;
     }
     if ((int)threadIdx.x < nqb && cnt[threadIdx.x])
         atomicAdd(&a.q_scanned[q0 + threadIdx.x], 64u * cnt[threadIdx.x]);
