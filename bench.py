@@ -440,7 +440,7 @@ def exact_knn_gpu32(torch, D, Q, k, chunk=32):
 
 
 def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), duration_s=2.0,
-                  betas=(1e-4, 1.25e-4, 1.5e-4, 1.9e-4), conf=1 - 1 / math.e):
+                  betas=(5e-5, 7.5e-5, 1e-4, 1.25e-4, 1.5e-4, 1.9e-4), conf=1 - 1 / math.e):
     """Serving loop on a resident 10,000,000 x 128 index: Poisson request
     streams (sizes log-uniform in 1..4,096, k in {1,10,50,100}, c in
     {1.2,1.5,2.0}) answered by the continuous-batching server (requests of
@@ -657,7 +657,7 @@ def serving_bench(pm, torch, dev, rates=(5000, 20000, 50000, 400000, 800000), du
         ex = x_dist[r_, :k]
         rat.append(float(np.mean(np.where(ex > 0, gd / np.where(ex > 0, ex, 1.0), 1.0))))
     del Dd
-    return {"workload": "10,000,000 x 128 FP16 values in [0, 255], 10,000 centres, sigma 8; "
+    return {"workload": "10,000,000 x 128 FP16 values in [0, 255], 10,000 centres, sigma U[4, 16]; "
                         "Poisson requests of 1..4,096 queries, k in {1,10,50,100}, "
                         "c in {1.2,1.5,2.0}",
             "beta": beta, "beta_sweep": beta_sweep, "build_s": round(build_s, 1),

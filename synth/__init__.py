@@ -178,18 +178,22 @@ def heavy_tailed(seed: int = SEEDS["heavy"], n: int = 1_000_000, d: int = 960,
 
 
 def serving(seed: int = SEEDS["serving"], n: int = 10_000_000, d: int = 128,
-            n_centres: int = 10_000, sigma: float = 8.0, n_queries: int = 20_000,
+            n_centres: int = 10_000, sigma=None, n_queries: int = 20_000,
             m: int = M_DEFAULT):
     """Serving workload: a resident index of FP16-valued points in [0, 255].
 
-    Centres uniform in [0, 255]^d; each point is a centre plus N(0, sigma^2)
-    noise, clipped to [0, 255] and rounded to the nearest FP16 value (held as
-    float32); queries drawn the same way. The request stream is drawn
-    separately (``requests``).
+    Centres uniform in [0, 255]^d, each with its own spread sigma_c drawn
+    uniform in [4, 16] (or the fixed `sigma` when given); each point is a
+    centre plus N(0, sigma_c^2) noise, clipped to [0, 255] and rounded to the
+    nearest FP16 value (held as float32); queries drawn the same way. The
+    request stream is drawn separately (``requests``).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     centres = rng.uniform(0.0, 255.0, size=(n_centres, d)).astype(np.float32)
-    sig = np.full(n_centres, sigma, dtype=np.float32)
+    if sigma is None:
+        sig = rng.uniform(4.0, 16.0, size=n_centres).astype(np.float32)
+    else:
+        sig = np.full(n_centres, sigma, dtype=np.float32)
 
     def draw(count):
         lab = rng.integers(0, n_centres, size=count)
