@@ -689,9 +689,23 @@ __global__ __launch_bounds__(WG) void acp_sel_pick_kernel(uint32_t* __restrict__
     for (int i = threadIdx.x; i < NB; i += WG) ghist[i] = 0;
 }
 
-// ub^2 = the key left in state->prefix (has_ub), else ub = +inf.
+// ub^2 = the key left in state->prefix (has_ub), else ub = +inf. When the
+// band it was selected from outgrew its capacity (*band_count > band_cap) the
+// key means nothing and the call redoes these stages: the radii are then
+// empty, so that the tile filter and the pair scan in between do no work.
 __global__ void acp_radius_kernel(const SelState* __restrict__ state, int has_ub, double t,
-                                  double gamma, float coord_scale, AcpRadius* __restrict__ out) {
+                                  double gamma, float coord_scale,
+                                  const unsigned long long* __restrict__ band_count,
+                                  int64_t band_cap, AcpRadius* __restrict__ out) {
+    if ((int64_t)*band_count > band_cap) {
+        AcpRadius r;
+        r.R2 = -1.f;
+        r.limit = -INFINITY;
+        r.seed_lim = 0u;
+        r.pad = 0u;
+        *out = r;
+        return;
+    }
     const float ub2 = has_ub ? __uint_as_float(state->prefix) : INFINITY;
     const double ub = has_ub ? sqrt((double)ub2) : HUGE_VAL;
     const double R = t * ub;
@@ -2035,7 +2049,9 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
                                                        : std::max<int64_t>(int64_t(1) << 16, 4 * (int64_t)k));
         launch_band();
         hipLaunchKernelGGL(acp_radius_kernel, dim3(1), dim3(1), 0, st, dstate2.as<SelState>(),
-                           all_seeds ? 0 : 1, plan.t, gamma_v, x->coord_scale, drad.as<AcpRadius>());
+                           all_seeds ? 0 : 1, plan.t, gamma_v, x->coord_scale,
+                           static_cast<const unsigned long long*>(dcnts.p), bcap,
+                           drad.as<AcpRadius>());
         PMLSH_HIP(hipGetLastError());
         deferred = true;
     }
