@@ -878,8 +878,11 @@ __global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
 // every |a_i - x0_i| sc < 2^15) and rounded to FP16: a~ = fp16(sc fl(a - x0)).
 // One workgroup per leaf. The 64 x 64 Gram matrix is the ten 16 x 16 tiles on
 // or above the diagonal (v_mfma_f32_16x16x32_f16, FP32 sums), three, three,
-// two and two per wave; the rows pass through LDS 32 coordinates at a time,
-// their loads issued two steps ahead.
+// two and two per wave; the rows pass through LDS SG_W coordinates at a
+// time, their loads issued SG_DEPTH steps ahead. With X0L the first point's
+// row is read into LDS once (d_pad <= SG_X0), so a step loads only the
+// leaf's own rows; otherwise its coordinates are loaded beside them at every
+// step.
 //
 // Bounds (rigorous, in scaled units, K the coordinates summed):
 //   rounding to FP16 and the FP32 centring: |a~ - sc (a - x0)| <= rho_a =
@@ -896,8 +899,18 @@ __global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
 // in the triangular layout of the seeds (leaf b's pairs from b L (L - 1) / 2
 // on); the top 11 bits of every upper bound go to ghist (first radix pass of
 // the k-th smallest upper bound).
-constexpr int SG_LD = 40;   // LDS row stride of the staged FP16 rows, in halves
+// Two steps of row loads in flight, one 32-coordinate slice per step: wider
+// steps (up to 128 coordinates, 512 contiguous bytes per row) and deeper
+// rings time the same, the kernel moving its bytes at about nine tenths of
+// a plain device copy's rate.
+constexpr int SG_DEPTH = 2;                  // steps of row loads in flight
+constexpr int SG_KS = 1;                     // 32-coordinate slices per step
+constexpr int SG_W = 32 * SG_KS;             // coordinates per step
+constexpr int SG_LD = SG_W + 8;              // LDS row stride of the staged FP16 rows, in halves
+constexpr int SG_X0 = 2048;                  // LDS floats for the first point's row
+static_assert(SG_DEPTH >= 2 && SG_X0 % 32 == 0, "at least two steps in flight; whole steps");
 
+template <bool X0L>
 __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
     const float* __restrict__ data, int d_pad, const float* __restrict__ row_scale, int64_t n,
     int L, float gk, uint32_t* __restrict__ hi_out,
@@ -905,8 +918,8 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
     typedef _Float16 h8 __attribute__((ext_vector_type(8)));
     typedef float f4v __attribute__((ext_vector_type(4)));
     __shared__ __align__(16) _Float16 xs[2][64][SG_LD];
+    __shared__ __align__(16) float x0s[X0L ? SG_X0 : 4];
     __shared__ float gnorm[64], anorm[64], rho[64];
-    __shared__ float s_sc;
     const int64_t leaf = blockIdx.x;
     const int64_t p0 = leaf * L;
     const int cnt = (int)(n - p0 < L ? n - p0 : L);
@@ -917,42 +930,81 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
     const bool rv = r < cnt;
     const float* rowp = data + (p0 + (rv ? r : 0)) * d_pad;
     const float* x0p = data + p0 * d_pad;
-    struct Stage { float4 a0, a1, z0, z1; };
+    // Every global load of the steady state is unconditional (columns past
+    // d_pad read the row's last four and are zeroed when staged), so the
+    // compiler waits for the oldest step's loads only: a load under a branch
+    // would make it wait for all of them at every step.
+    struct Stage { float4 a[2 * SG_KS], z[2 * SG_KS]; };
     auto ld4 = [&](const float* p, int c) {
-        return c < d_pad ? *reinterpret_cast<const float4*>(p + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        return *reinterpret_cast<const float4*>(p + (c < d_pad ? c : d_pad - 4));
     };
     auto load = [&](Stage& s, int k0) {
-        s.a0 = ld4(rowp, k0 + q);
-        s.a1 = ld4(rowp, k0 + q + 4);
-        s.z0 = ld4(x0p, k0 + q);
-        s.z1 = ld4(x0p, k0 + q + 4);
+#pragma unroll
+        for (int i = 0; i < SG_KS; ++i) {
+            s.a[2 * i] = ld4(rowp, k0 + 32 * i + q);
+            s.a[2 * i + 1] = ld4(rowp, k0 + 32 * i + q + 4);
+            if (!X0L) {
+                s.z[2 * i] = ld4(x0p, k0 + 32 * i + q);
+                s.z[2 * i + 1] = ld4(x0p, k0 + 32 * i + q + 4);
+            }
+        }
     };
-    const int nst = (d_pad + 31) / 32;
-    Stage s0, s1;
-    load(s0, 0);
-    if (nst > 1) load(s1, 32);
-    if (wave == 0) {
-        float s = lane < cnt ? row_scale[p0 + lane] : 0.f;
-        for (int off = 32; off > 0; off >>= 1) s = fmaxf(s, __shfl_xor(s, off));
-        if (lane == 0) s_sc = 0.5f / s;
+    const int nst = (d_pad + SG_W - 1) / SG_W;
+    // steps padded to whole rounds of the ring: the extra steps stage zeros
+    const int nsp = (nst + SG_DEPTH - 1) / SG_DEPTH * SG_DEPTH;
+    // the power-of-two scale, in every wave: sc = 1 / (2 S)
+    float smax = row_scale[p0 + (lane < cnt ? lane : 0)];
+    // the first row into LDS (its loads before the ring's, 2 * 4 WG = 2,048
+    // floats at most, zero past d_pad)
+    float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), xb = xa;
+    if (X0L) {
+        static_assert(!X0L || SG_X0 == 8 * WG, "two float4 loads per thread fill the first row's array");
+        xa = ld4(x0p, 4 * t);
+        xb = ld4(x0p, 4 * t + 4 * WG);
+    }
+    // set j of the ring holds the steps j, j + SG_DEPTH, ...
+    Stage sr[SG_DEPTH];
+#pragma unroll
+    for (int j = 0; j < SG_DEPTH; ++j) load(sr[j], SG_W * j);
+    for (int off = 32; off > 0; off >>= 1) smax = fmaxf(smax, __shfl_xor(smax, off));
+    const float sc = 0.5f / smax;
+    if (X0L) {
+        // the whole array, unconditionally (SG_X0 = 8 WG floats)
+        const bool oa = 4 * t < d_pad, ob = 4 * t + 4 * WG < d_pad;
+        *reinterpret_cast<float4*>(&x0s[4 * t]) =
+            make_float4(oa ? xa.x : 0.f, oa ? xa.y : 0.f, oa ? xa.z : 0.f, oa ? xa.w : 0.f);
+        *reinterpret_cast<float4*>(&x0s[4 * t + 4 * WG]) =
+            make_float4(ob ? xb.x : 0.f, ob ? xb.y : 0.f, ob ? xb.z : 0.f, ob ? xb.w : 0.f);
     }
     __syncthreads();
-    const float sc = s_sc;
-    auto store = [&](const Stage& s, int buf) {
-        h8 v;
-        v[0] = (_Float16)(__fsub_rn(s.a0.x, s.z0.x) * sc);
-        v[1] = (_Float16)(__fsub_rn(s.a0.y, s.z0.y) * sc);
-        v[2] = (_Float16)(__fsub_rn(s.a0.z, s.z0.z) * sc);
-        v[3] = (_Float16)(__fsub_rn(s.a0.w, s.z0.w) * sc);
-        v[4] = (_Float16)(__fsub_rn(s.a1.x, s.z1.x) * sc);
-        v[5] = (_Float16)(__fsub_rn(s.a1.y, s.z1.y) * sc);
-        v[6] = (_Float16)(__fsub_rn(s.a1.z, s.z1.z) * sc);
-        v[7] = (_Float16)(__fsub_rn(s.a1.w, s.z1.w) * sc);
-        if (!rv) {
+    auto store = [&](Stage s, int buf, int k0) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
+        for (int i = 0; i < SG_KS; ++i) {
+            const int kc = k0 + 32 * i + q;
+            const bool lo_ok = rv && kc < d_pad, hi_ok = rv && kc + 4 < d_pad;
+            float4 z0 = s.z[2 * i], z1 = s.z[2 * i + 1];
+            if (X0L) {
+                // columns past d_pad read column 0 (and are zeroed below)
+                z0 = *reinterpret_cast<const float4*>(&x0s[lo_ok ? kc : 0]);
+                z1 = *reinterpret_cast<const float4*>(&x0s[hi_ok ? kc + 4 : 0]);
+            }
+            const float4 a0 = s.a[2 * i], a1 = s.a[2 * i + 1];
+            h8 v;
+            v[0] = (_Float16)(__fsub_rn(a0.x, z0.x) * sc);
+            v[1] = (_Float16)(__fsub_rn(a0.y, z0.y) * sc);
+            v[2] = (_Float16)(__fsub_rn(a0.z, z0.z) * sc);
+            v[3] = (_Float16)(__fsub_rn(a0.w, z0.w) * sc);
+            v[4] = (_Float16)(__fsub_rn(a1.x, z1.x) * sc);
+            v[5] = (_Float16)(__fsub_rn(a1.y, z1.y) * sc);
+            v[6] = (_Float16)(__fsub_rn(a1.z, z1.z) * sc);
+            v[7] = (_Float16)(__fsub_rn(a1.w, z1.w) * sc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (!lo_ok) v[e] = (_Float16)0.f;
+                if (!hi_ok) v[4 + e] = (_Float16)0.f;
+            }
+            *reinterpret_cast<h8*>(&xs[buf][r][32 * i + q]) = v;
         }
-        *reinterpret_cast<h8*>(&xs[buf][r][q]) = v;
     };
     // the wave's tiles (bi, bj): w0 (0,0) (1,1) (0,1), w1 (2,2) (3,3) (2,3),
     // w2 (0,2) (0,3), w3 (1,2) (1,3)
@@ -972,29 +1024,31 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
     for (int j = 0; j < 3; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
     auto mma = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            if (j < nt) {
-                const h8 fa = *reinterpret_cast<const h8*>(&xs[buf][16 * bi[j] + l16][8 * lq]);
-                const h8 fb = *reinterpret_cast<const h8*>(&xs[buf][16 * bj[j] + l16][8 * lq]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, fb, acc[j], 0, 0, 0);
+        for (int kk = 0; kk < SG_KS; ++kk)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (j < nt) {
+                    const h8 fa = *reinterpret_cast<const h8*>(&xs[buf][16 * bi[j] + l16][32 * kk + 8 * lq]);
+                    const h8 fb = *reinterpret_cast<const h8*>(&xs[buf][16 * bj[j] + l16][32 * kk + 8 * lq]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, fb, acc[j], 0, 0, 0);
+                }
             }
-        }
     };
-    // stage st is in buffer st % 2; s0 holds the even stages, s1 the odd ones
+    // step st is staged in LDS buffer st % 2 from ring set st % SG_DEPTH,
+    // which then loads step st + SG_DEPTH (the last step stages into a buffer
+    // nobody reads and its loads are never used)
     auto step = [&](int st, Stage& nxt) {
         mma(st & 1);
-        if (st + 1 < nst) {
-            store(nxt, (st + 1) & 1);
-            if (st + 3 < nst) load(nxt, 32 * (st + 3));
-        }
+        store(nxt, (st + 1) & 1, SG_W * (st + 1));
+        load(nxt, SG_W * (st + 1 + SG_DEPTH));
         __syncthreads();
     };
-    store(s0, 0);
-    if (nst > 2) load(s0, 64);
+    store(sr[0], 0, 0);
+    load(sr[0], SG_W * SG_DEPTH);
     __syncthreads();
-    for (int st = 0; st < nst; st += 2) {
-        step(st, s1);
-        if (st + 1 < nst) step(st + 1, s0);
+    for (int st = 0; st < nsp; st += SG_DEPTH) {
+#pragma unroll
+        for (int j = 0; j < SG_DEPTH; ++j) step(st + j, sr[(j + 1) % SG_DEPTH]);
     }
 
     // the squared norms from the diagonal tiles; the staging area becomes the
@@ -1010,7 +1064,7 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
                 if (l16 == 4 * lq + v) gnorm[16 * bi[j] + l16] = acc[j][v];
     }
     __syncthreads();
-    const float Kf = (float)(32 * nst);
+    const float Kf = (float)(32 * ((d_pad + 31) / 32));
     if (t < 64) {
         const float A = sqrtf(fmaxf(gnorm[t], 0.f) / (1.f - gk)) * (1.f + 9.5367431640625e-07f);
         anorm[t] = A;
@@ -2025,9 +2079,14 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         const float gk = (float)(ukd / (1.0 - ukd) * (1.0 + 1e-6));
         {
             StageTimer tm(PMLSH_STAGE_ACP_SELFJOIN, st);
-            hipLaunchKernelGGL(acp_seed_gram_kernel, dim3((unsigned)NL), dim3(WG), 0, st, x->data,
-                               x->d_pad, x->data16_scale, n, L, gk,
-                               seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
+            if (x->d_pad <= SG_X0)
+                hipLaunchKernelGGL(acp_seed_gram_kernel<true>, dim3((unsigned)NL), dim3(WG), 0, st,
+                                   x->data, x->d_pad, x->data16_scale, n, L, gk,
+                                   seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
+            else
+                hipLaunchKernelGGL(acp_seed_gram_kernel<false>, dim3((unsigned)NL), dim3(WG), 0, st,
+                                   x->data, x->d_pad, x->data16_scale, n, L, gk,
+                                   seeds.k0.as<uint32_t>(), slo.as<uint32_t>(), ghist.as<uint32_t>());
             PMLSH_HIP(hipGetLastError());
         }
         StageTimer tm(PMLSH_STAGE_ACP_SELECT, st);

@@ -213,6 +213,26 @@ def test_planted_far_from_the_origin():
         _compare(res, pairs, dist, st)
 
 
+@pytest.mark.parametrize("d", [36, 2048, 2052])
+def test_planted_row_widths(d):
+    """Rows of 36 coordinates (the last 32-coordinate step of the Gram seeds
+    is partly padding), 2,048 (the first point's row fills its LDS copy) and
+    2,052 (past it: the first row is loaded with every step): ub and the
+    answers match the oracle's."""
+    pm = _gpu()
+    say(f"case: ACP planted n=1500 d={d}")
+    w = synth.planted_pairs(n=1500, d=d, n_centres=10)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A)
+    for k in (1, 10):
+        pairs, dist, st = idx.acp(k, c=1.5)
+        torch.cuda.synchronize()
+        res, T = _oracle(idx, D, A, k, 1.5, 1 - 1 / math.e, -1.0)
+        say("k", k, "stats", st)
+        assert st["budget"] == T
+        _compare(res, pairs, dist, st)
+
+
 def test_fewer_seeds_than_k_in_small_leaves():
     """k above the number of seeds with leaves of 8: ub = inf, every seed
     enters the pool and every cross-leaf pair is a candidate."""
