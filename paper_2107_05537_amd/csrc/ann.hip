@@ -1943,32 +1943,33 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // range, held in mask word i / (64 / QPL) (those lanes load it together)
     const int pk_word = lane / (64 / QPL), pk_shift = QPL * (lane % (64 / QPL));
     const bool mword = pk_word < nw;
-    const int64_t mband = (q0 >> 6) + w0 + pk_word;
-    const uint16_t* rbase = a.proj16 + (l16 * kScanRow + lq * 8);
+    // Every slot load is unconditional, so that the compiler waits for the
+    // slot in use only (a load under a branch makes it wait for every slot in
+    // flight): a chunk past the end reads the last chunk (such a slot is never
+    // used), a lane without a mask word reads the block's first word, and
+    // lanes 48..63, whose halves 24..31 of the A operand are zero, read halves
+    // 16..23. What is not the chunk's is cleared where the slot is used.
+    const int64_t mband = (q0 >> 6) + (mword ? w0 + pk_word : 0);
+    const uint16_t* rbase = a.proj16 + (l16 * kScanRow + (lq < 3 ? lq : 2) * 8);
+    const uint32_t rkeep = lq < 3 ? 0xffffffffu : 0u;
 
     struct Slot {
         half8_t r[4];
         uint64_t m;
     };
-    // lanes 48..63 hold halves 24..31 of the A operand, zero in every row
     auto load = [&](int64_t cc, Slot& dst) {
-        dst.m = 0ull;
+        const int64_t ccl = cc < nchunk ? cc : nchunk - 1;
+        dst.m = a.cmask[cmask_at(a, ccl, mband)];
+        const uint16_t* rp = rbase + ccl * (64 * kScanRow);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) dst.r[mt] = half8_t{};
-        if (cc < nchunk) {
-            if (mword) dst.m = a.cmask[cmask_at(a, cc, mband)];
-            if (lq < 3) {
-                const uint16_t* rp = rbase + cc * (64 * kScanRow);
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt) dst.r[mt] = load_half8(rp + mt * 16 * kScanRow);
-            }
-        }
+        for (int mt = 0; mt < 4; ++mt) dst.r[mt] = load_half8(rp + mt * 16 * kScanRow);
     };
     uint8_t (*lcol)[SQW / 16] = ss.lcol[wave];
     auto chunk = [&](const Slot& cur, int64_t cc) {
         // the list of passing queries: each lane's set bits at the count of
         // set bits in the lanes below it
-        const uint32_t pk = (uint32_t)(cur.m >> pk_shift) & ((1u << QPL) - 1u);
+        const uint64_t cm = mword ? cur.m : 0ull;
+        const uint32_t pk = (uint32_t)(cm >> pk_shift) & ((1u << QPL) - 1u);
         int total = 0;
         uint32_t at = 0;
 #pragma unroll
@@ -1979,6 +1980,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u));
         }
         if (total == 0) return;
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        half8_t av[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            av[mt] = __builtin_bit_cast(half8_t, __builtin_bit_cast(u32x4, cur.r[mt]) & rkeep);
 #pragma unroll
         for (int b = 0; b < QPL; ++b)
             if ((pk >> b) & 1u) {
@@ -2002,8 +2008,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                 if (two) bb = load_half8(&ss.qrow[qb >= 0 ? w0 * 64 + qb : SPAD][lq * 8]);
             }
             float4_t ca[4], cb[4];
-            scan_mfma(cur.r, ba, ca);
-            if (two) scan_mfma(cur.r, bb, cb);
+            scan_mfma(av, ba, ca);
+            if (two) scan_mfma(av, bb, cb);
             scan_emit(a, ss, wave, lane, wn, ca, cc << 6, qa, qw0, nqw);
             if (two) scan_emit(a, ss, wave, lane, wn, cb, cc << 6, qb, qw0, nqw);
         }
