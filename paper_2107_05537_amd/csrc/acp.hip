@@ -472,8 +472,12 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
     float h1[MP], l1[MP];
     int held = -1, ca = 0;
     uint32_t id1 = 0;
-    // the next tile's index, centre and sorted PDs are loaded while the
-    // current one is scanned
+    // Two tiles ahead the tile's index is loaded, one tile ahead its second
+    // leaf's centre and sorted PDs (which need that index): a tile then waits
+    // for one memory round trip begun a whole tile earlier instead of two in
+    // a row. These loads are unconditional (past the wave's last tile they
+    // read it again), so the compiler waits for the oldest ones only.
+    const int64_t t_last = t_end - 1;
     int2 nt = t_beg < t_end ? tiles[t_beg] : make_int2(0, 0);
     float ncen[MP], ny = 0.f;
     int nsb = 0;
@@ -484,7 +488,11 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
         ny = spd[(int64_t)e * 64 + lane];
         nsb = sidx[(int64_t)e * 64 + lane];
     };
-    if (t_beg < t_end) fetch(__builtin_amdgcn_readfirstlane(nt.y));
+    int2 nt2 = nt;
+    if (t_beg < t_end) {
+        fetch(__builtin_amdgcn_readfirstlane(nt.y));
+        nt2 = tiles[t_beg + 1 <= t_last ? t_beg + 1 : t_last];
+    }
     for (int64_t t = t_beg; t < t_end; ++t) {
         const int e1 = __builtin_amdgcn_readfirstlane(nt.x);
         const int e2 = __builtin_amdgcn_readfirstlane(nt.y);
@@ -493,10 +501,9 @@ __global__ __launch_bounds__(WG) void acp_tile_scan_wave_kernel(
         for (int j = 0; j < MP; ++j) cen[j] = ncen[j];
         const float y = ny;
         const int sb = nsb;
-        if (t + 1 < t_end) {
-            nt = tiles[t + 1];
-            fetch(__builtin_amdgcn_readfirstlane(nt.y));
-        }
+        nt = nt2;                                          // tile t + 1 (or t_last)
+        fetch(__builtin_amdgcn_readfirstlane(nt.y));
+        nt2 = tiles[t + 2 <= t_last ? t + 2 : t_last];     // tile t + 2 (or t_last)
         const int64_t a0 = (int64_t)e1 * L, b0 = (int64_t)e2 * L;
         if (e1 != held) {
             ca = (int)(n - a0 < L ? n - a0 : L);
