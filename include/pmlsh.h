@@ -247,7 +247,11 @@ int pmlsh_bc(const pmlsh_index* index, const float* queries, int64_t nq, double 
 /*
  * (c,k)-ACP by radius filtering (Section 6.3, Algorithm 4), canonical form.
  *   1. every pair inside one leaf is verified; ub = the k-th smallest such
- *      distance (+inf if fewer than k pairs);
+ *      distance (+inf if fewer than k pairs). With leaves of at most 64
+ *      points every such pair first gets rigorous bounds from the Gram
+ *      matrix of its leaf (FP16 matrix cores), and only the pairs whose
+ *      bounds reach the k-th smallest upper bound get exact distances: ub
+ *      and the answer are those of verifying them all;
  *   2. every pair (i<j) in different leaves with projected distance < t*ub is
  *      a candidate; pairs of leaves whose Mindist (Eq. 11) is at least t*ub
  *      are skipped whole;
@@ -270,7 +274,7 @@ typedef struct {
     double t;
     double ub;            /* k-th smallest self-join distance                 */
     int64_t budget;       /* T                                                */
-    int64_t n_seed;       /* pairs verified by the self-join                  */
+    int64_t n_seed;       /* pairs inside one leaf (the self-join's seeds)    */
     int64_t n_cand_raw;   /* cross-leaf pairs with projected distance < t*ub  */
     int64_t n_cand;       /* candidates verified after the T cut              */
     int64_t tiles_total;  /* leaf pairs (e1 < e2)                             */
