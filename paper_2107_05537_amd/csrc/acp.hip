@@ -908,7 +908,7 @@ __global__ __launch_bounds__(SJ_THREADS) void acp_seed_join_kernel(
 // the k-th smallest upper bound).
 // Two steps of row loads in flight, one 32-coordinate slice per step: wider
 // steps (up to 128 coordinates, 512 contiguous bytes per row) and deeper
-// rings time the same, the kernel moving its bytes at about nine tenths of
+// rings are no faster, the kernel moving its bytes at about nine tenths of
 // a plain device copy's rate.
 constexpr int SG_DEPTH = 2;                  // steps of row loads in flight
 constexpr int SG_KS = 1;                     // 32-coordinate slices per step
@@ -989,11 +989,14 @@ __global__ __launch_bounds__(WG) void acp_seed_gram_kernel(
         for (int i = 0; i < SG_KS; ++i) {
             const int kc = k0 + 32 * i + q;
             const bool lo_ok = rv && kc < d_pad, hi_ok = rv && kc + 4 < d_pad;
-            float4 z0 = s.z[2 * i], z1 = s.z[2 * i + 1];
+            float4 z0, z1;
             if (X0L) {
                 // columns past d_pad read column 0 (and are zeroed below)
                 z0 = *reinterpret_cast<const float4*>(&x0s[lo_ok ? kc : 0]);
                 z1 = *reinterpret_cast<const float4*>(&x0s[hi_ok ? kc + 4 : 0]);
+            } else {
+                z0 = s.z[2 * i];
+                z1 = s.z[2 * i + 1];
             }
             const float4 a0 = s.a[2 * i], a1 = s.a[2 * i + 1];
             h8 v;
