@@ -1425,6 +1425,36 @@ __global__ __launch_bounds__(WG) void acp_final_kernel(
 
 constexpr int kTopBand = 1024;   // pairs the FP64 top-k takes at most (>= PMLSH_MAX_K)
 
+// FP64 squared distance of two FP32 rows over one lane's float4 columns
+// l16, l16 + 16, ... (d4 columns in all), summed in that ascending order; the
+// loads of eight columns go out together (clamped into the row, the extra
+// ones unused), so a row costs one memory round trip per 128 columns rather
+// than one per column.
+__device__ __forceinline__ double row_dist2_f64(const float4* __restrict__ r1,
+                                                const float4* __restrict__ r2, int l16, int d4) {
+    double acc = 0.0;
+    for (int c0 = l16; c0 < d4; c0 += 128) {
+        float4 x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = c0 + 16 * u < d4 ? c0 + 16 * u : c0;
+            x[u] = r1[c];
+            y[u] = r2[c];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (c0 + 16 * u < d4) {
+                double t;
+                t = (double)x[u].x - (double)y[u].x; acc = fma(t, t, acc);
+                t = (double)x[u].y - (double)y[u].y; acc = fma(t, t, acc);
+                t = (double)x[u].z - (double)y[u].z; acc = fma(t, t, acc);
+                t = (double)x[u].w - (double)y[u].w; acc = fma(t, t, acc);
+            }
+        }
+    }
+    return acc;
+}
+
 // Top-k in the FP64 order of Section 6 (distance, then i, then j). The `count`
 // pairs are every pair whose FP32 distance lies within the verify error band
 // of the FP32 k-th one, so the exact top-k is among them; each gets its squared
@@ -1446,14 +1476,7 @@ __global__ __launch_bounds__(WG) void acp_final64_kernel(
         if (e < count) {
             const float4* r1 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[ii[e]] * d_pad);
             const float4* r2 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[jj[e]] * d_pad);
-            for (int c = l16; c < d4; c += 16) {
-                const float4 x = r1[c], y = r2[c];
-                double t;
-                t = (double)x.x - (double)y.x; acc = fma(t, t, acc);
-                t = (double)x.y - (double)y.y; acc = fma(t, t, acc);
-                t = (double)x.z - (double)y.z; acc = fma(t, t, acc);
-                t = (double)x.w - (double)y.w; acc = fma(t, t, acc);
-            }
+            acc = row_dist2_f64(r1, r2, l16, d4);
         }
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
@@ -1570,14 +1593,7 @@ __global__ __launch_bounds__(WG) void acp_topk_small_kernel(
             const uint64_t key = pk[e];
             const float4* r1 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[(uint32_t)(key >> 32)] * d_pad);
             const float4* r2 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[(uint32_t)key] * d_pad);
-            for (int c = l16; c < d4; c += 16) {
-                const float4 x = r1[c], y = r2[c];
-                double t;
-                t = (double)x.x - (double)y.x; acc = fma(t, t, acc);
-                t = (double)x.y - (double)y.y; acc = fma(t, t, acc);
-                t = (double)x.z - (double)y.z; acc = fma(t, t, acc);
-                t = (double)x.w - (double)y.w; acc = fma(t, t, acc);
-            }
+            acc = row_dist2_f64(r1, r2, l16, d4);
         }
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
