@@ -1262,6 +1262,35 @@ __global__ __launch_bounds__(WG) void acp_seed_band_kernel(
 }
 
 // ---------------------------------------------------------------- verify
+// FP32 squared distance of two rows over one lane's float4 columns l16,
+// l16 + 16, ... (d4 columns in all), summed in that ascending order with the
+// eight columns' loads issued together (clamped into the row, the extra ones
+// unused): one memory round trip per 128 columns.
+__device__ __forceinline__ float row_dist2_f32(const float4* __restrict__ r1,
+                                               const float4* __restrict__ r2, int l16, int d4) {
+    float acc = 0.f;
+    for (int c0 = l16; c0 < d4; c0 += 128) {
+        float4 x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = c0 + 16 * u < d4 ? c0 + 16 * u : c0;
+            x[u] = r1[c];
+            y[u] = r2[c];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (c0 + 16 * u < d4) {
+                float t;
+                t = x[u].x - y[u].x; acc = __fmaf_rn(t, t, acc);
+                t = x[u].y - y[u].y; acc = __fmaf_rn(t, t, acc);
+                t = x[u].z - y[u].z; acc = __fmaf_rn(t, t, acc);
+                t = x[u].w - y[u].w; acc = __fmaf_rn(t, t, acc);
+            }
+        }
+    }
+    return acc;
+}
+
 // Exact FP32 squared distance of `count` pairs (16 lanes per pair). With
 // dev_count the pairs are the first min(*dev_count, count) and the keys of the
 // rest of the `count` slots are set to +inf bits (ignored by a selection of
@@ -1288,14 +1317,7 @@ __global__ __launch_bounds__(WG) void acp_verify_kernel(
         if (e < count) {
             const float4* r1 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[cii[e]] * d_pad);
             const float4* r2 = reinterpret_cast<const float4*>(data + (int64_t)inv_perm[cjj[e]] * d_pad);
-            for (int c = l16; c < d4; c += 16) {
-                const float4 x = r1[c], y = r2[c];
-                float t;
-                t = x.x - y.x; acc = __fmaf_rn(t, t, acc);
-                t = x.y - y.y; acc = __fmaf_rn(t, t, acc);
-                t = x.z - y.z; acc = __fmaf_rn(t, t, acc);
-                t = x.w - y.w; acc = __fmaf_rn(t, t, acc);
-            }
+            acc = row_dist2_f32(r1, r2, l16, d4);
         }
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
