@@ -1704,6 +1704,42 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Small device-to-host reads of an ACP call (counts, selection states,
+// histograms) go through a pinned host buffer of the index, kept with its
+// workspace: a copy into pageable host memory is staged by the runtime and
+// finishes before the next operation is issued, while copies into pinned
+// memory queue like kernels, so the reads of one step cost one
+// synchronisation. Calls on one index serialise on its mutex and every
+// HostReads waits before the next is made, so one buffer serves them all.
+constexpr size_t kHostReadBytes = 16384;
+struct HostReads {
+    unsigned char* base;
+    hipStream_t st;
+    size_t used = 0;
+    int n = 0;
+    struct Item {
+        void* dst;
+        size_t off, bytes;
+    } items[8];
+    HostReads(const pmlsh_index* x, hipStream_t s) : st(s) {
+        if (!x->acp_host) PMLSH_HIP(hipHostMalloc(&x->acp_host, kHostReadBytes, hipHostMallocDefault));
+        base = static_cast<unsigned char*>(x->acp_host);
+    }
+    void add(void* dst, const void* src, size_t bytes) {
+        const size_t off = (used + 15) & ~size_t(15);
+        if (n == 8 || off + bytes > kHostReadBytes) fail(PMLSH_EDEVICE, "host read staging overflow");
+        PMLSH_HIP(hipMemcpyAsync(base + off, src, bytes, hipMemcpyDeviceToHost, st));
+        items[n++] = {dst, off, bytes};
+        used = off + bytes;
+    }
+    void wait() {
+        PMLSH_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < n; ++i) std::memcpy(items[i].dst, base + items[i].off, items[i].bytes);
+        n = 0;
+        used = 0;
+    }
+};
+
 struct Triplets {
     DevBuf k0, ii, jj;
     int64_t cap = 0;
@@ -1724,7 +1760,7 @@ int grid_for(int64_t work, int per_block) {
 
 // Device-wide selection of the need-th smallest key. With value_only, only the
 // first sub-key (the distance bits) is resolved.
-SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, int64_t count,
+SelKey select_kth(const pmlsh_index* x, const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, int64_t count,
                   int64_t need, bool value_only, uint32_t* dhist, hipStream_t st) {
     SelKey K{0, 0, 0, 0};
     uint32_t v[3] = {0, 0, 0};
@@ -1741,9 +1777,11 @@ SelKey select_kth(const uint32_t* k0, const uint32_t* ii, const uint32_t* jj, in
             hipLaunchKernelGGL(acp_hist_kernel, dim3(grid_for(count, WG * 16)), dim3(WG), 0, st,
                                k0, ii, jj, count, s, dhist);
             PMLSH_HIP(hipGetLastError());
-            PMLSH_HIP(hipMemcpyAsync(h.data(), dhist, NB * sizeof(uint32_t),
-                                     hipMemcpyDeviceToHost, st));
-            PMLSH_HIP(hipStreamSynchronize(st));
+            {
+                HostReads rd(x, st);
+                rd.add(h.data(), dhist, NB * sizeof(uint32_t));
+                rd.wait();
+            }
             int64_t cum = 0;
             int T = -1;
             for (int b = 0; b < (1 << width); ++b) {
@@ -1914,8 +1952,11 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
     ghist.alloc(NB * sizeof(uint32_t));
     auto exact_count = [&] {
         unsigned long long extra = 0;
-        PMLSH_HIP(hipMemcpyAsync(&extra, dn_add, sizeof(extra), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&extra, dn_add, sizeof(extra));
+            rd.wait();
+        }
         n_pool += (int64_t)extra;
         dn_add = nullptr;
         if (n_pool < k) fail(PMLSH_EDEVICE, "fewer verified pairs than k");
@@ -1934,8 +1975,11 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
                            static_cast<int*>(dcount.p), dn_add);
         PMLSH_HIP(hipGetLastError());
         int m = 0;
-        PMLSH_HIP(hipMemcpyAsync(&m, dcount.p, sizeof(m), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&m, dcount.p, sizeof(m));
+            rd.wait();
+        }
         if (m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
         if (m <= kTopBand) return;
         if (dn_add) exact_count();
@@ -1952,8 +1996,11 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
                        static_cast<unsigned long long*>(dcount.p));
     PMLSH_HIP(hipGetLastError());
     unsigned long long m = 0;
-    PMLSH_HIP(hipMemcpyAsync(&m, dcount.p, sizeof(m), hipMemcpyDeviceToHost, st));
-    PMLSH_HIP(hipStreamSynchronize(st));
+    {
+        HostReads rd(x, st);
+        rd.add(&m, dcount.p, sizeof(m));
+        rd.wait();
+    }
     if ((int64_t)m < k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
     if ((int64_t)m <= kTopBand) {
         hipLaunchKernelGGL(acp_final64_kernel, dim3(1), dim3(WG), 0, st, x->data, x->d_pad,
@@ -1961,7 +2008,7 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
                            k, out_pairs, out_dist);
     } else {
         // mass ties: the k smallest full keys (distance bits, i, j) in FP32
-        const SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+        const SelKey K = select_kth(x, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
                                     pool.jj.as<uint32_t>(), n_pool, k, false,
                                     dhist.as<uint32_t>(), st);
         PMLSH_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), st));
@@ -1972,8 +2019,11 @@ void pool_topk(const pmlsh_index* x, Triplets& pool, int64_t n_pool, int k, doub
                            static_cast<unsigned long long*>(dcount.p));
         PMLSH_HIP(hipGetLastError());
         unsigned long long g = 0;
-        PMLSH_HIP(hipMemcpyAsync(&g, dcount.p, sizeof(g), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&g, dcount.p, sizeof(g));
+            rd.wait();
+        }
         if ((int64_t)g != k) fail(PMLSH_EDEVICE, "top-k selection lost pairs");
         hipLaunchKernelGGL(acp_final_kernel, dim3(1), dim3(WG), 0, st, top.k0.as<uint32_t>(),
                            top.ii.as<uint32_t>(), top.jj.as<uint32_t>(), k, out_pairs,
@@ -2004,8 +2054,11 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     };
     auto read_counter = [&]() -> int64_t {
         unsigned long long v = 0;
-        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&v, dcount.p, sizeof(v));
+            rd.wait();
+        }
         return (int64_t)v;
     };
     // ---- seeds: every within-leaf pair
@@ -2022,8 +2075,11 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     PMLSH_HIP(hipMemsetAsync(ghist.p, 0, NB * sizeof(uint32_t), st));
     auto read_ub = [&] {
         SelState hs{};
-        PMLSH_HIP(hipMemcpyAsync(&hs, dstate.p, sizeof(hs), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&hs, dstate.p, sizeof(hs));
+            rd.wait();
+        }
         ub2_bits = hs.prefix;
         float ub2;
         std::memcpy(&ub2, &ub2_bits, 4);
@@ -2084,9 +2140,12 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     auto read_band = [&]() -> bool {
         unsigned long long nb = 0;
         SelState hs{};
-        PMLSH_HIP(hipMemcpyAsync(&nb, dcnts.p, sizeof(nb), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipMemcpyAsync(&hs, dstate2.p, sizeof(hs), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&nb, dcnts.p, sizeof(nb));
+            rd.add(&hs, dstate2.p, sizeof(hs));
+            rd.wait();
+        }
         n_band = (int64_t)nb;
         if (n_band > bcap) return false;
         if (!all_seeds) take_ub(hs);
@@ -2236,9 +2295,12 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
         // the one read of this sequence: band size, ub, tile and candidate counts
         unsigned long long hc[3] = {0, 0, 0};
         SelState hs{};
-        PMLSH_HIP(hipMemcpyAsync(hc, dcnts.p, sizeof(hc), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipMemcpyAsync(&hs, dstate2.p, sizeof(hs), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(hc, dcnts.p, sizeof(hc));
+            rd.add(&hs, dstate2.p, sizeof(hs));
+            rd.wait();
+        }
         n_band = (int64_t)hc[0];
         if (n_band <= bcap) {
             gram = true;
@@ -2284,7 +2346,7 @@ void run_acp(const pmlsh_index* x, int k, double c, double confidence, double be
     Triplets kept(x, S_KEPT);
     const Triplets* cands = &cand;
     if (n_raw > keep && keep > 0) {
-        SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+        SelKey K = select_kth(x, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
                               cand.jj.as<uint32_t>(), n_raw, keep, false, dhist.as<uint32_t>(), st);
         kept.alloc(keep);
         reset_counter();
@@ -2433,8 +2495,11 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     dcount.alloc(sizeof(unsigned long long));
     auto read_counter = [&]() -> int64_t {
         unsigned long long v = 0;
-        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&v, dcount.p, sizeof(v));
+            rd.wait();
+        }
         return (int64_t)v;
     };
     auto reset_counter = [&] {
@@ -2498,7 +2563,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
         cand.alloc(std::max<int64_t>(n_in, 1));
         scan(nd, INFINITY, INFINITY, n_in);
         if (n_in >= T && n_in > 0) {
-            SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+            SelKey K = select_kth(x, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
                                   cand.jj.as<uint32_t>(), n_in, T, true, dhist.as<uint32_t>(),
                                   st);
             std::memcpy(&d2, &K.v0, 4);
@@ -2507,7 +2572,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
             // such pair, from a millionth of the coordinate range squared)
             float top2 = (float)(4e-6 * (double)x->coord_scale * (double)x->coord_scale);
             if (n_in > 0) {
-                SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+                SelKey K = select_kth(x, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
                                       cand.jj.as<uint32_t>(), n_in, n_in, true,
                                       dhist.as<uint32_t>(), st);
                 std::memcpy(&top2, &K.v0, 4);
@@ -2532,7 +2597,7 @@ void run_acp_bb(const pmlsh_index* x, int k, double c, double confidence, double
     const int64_t keep = std::min(T, n_raw);
     const Triplets* cands = &cand;
     if (n_raw > keep) {
-        SelKey K = select_kth(cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
+        SelKey K = select_kth(x, cand.k0.as<uint32_t>(), cand.ii.as<uint32_t>(),
                               cand.jj.as<uint32_t>(), n_raw, keep, false, dhist.as<uint32_t>(), st);
         kept.alloc(keep);
         reset_counter();
@@ -2701,8 +2766,11 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
     };
     auto read_counter = [&]() -> int64_t {
         unsigned long long v = 0;
-        PMLSH_HIP(hipMemcpyAsync(&v, dcount.p, sizeof(v), hipMemcpyDeviceToHost, st));
-        PMLSH_HIP(hipStreamSynchronize(st));
+        {
+            HostReads rd(x, st);
+            rd.add(&v, dcount.p, sizeof(v));
+            rd.wait();
+        }
         return (int64_t)v;
     };
 
@@ -2729,7 +2797,7 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
     int64_t n_pool = n_seed;
     auto kth_dist = [&]() -> double {
         if (n_pool < k) return HUGE_VAL;
-        SelKey K = select_kth(pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
+        SelKey K = select_kth(x, pool.k0.as<uint32_t>(), pool.ii.as<uint32_t>(),
                               pool.jj.as<uint32_t>(), n_pool, k, true, dhist.as<uint32_t>(), st);
         float v2;
         std::memcpy(&v2, &K.v0, 4);

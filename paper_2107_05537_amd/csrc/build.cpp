@@ -46,6 +46,7 @@ void index_release(pmlsh_index* x) {
         if (b) (void)hipFree(b);
     for (auto& b : x->acp_bufs)
         if (b.first) (void)hipFree(b.first);
+    if (x->acp_host) (void)hipHostFree(x->acp_host);
     delete x;
 }
 

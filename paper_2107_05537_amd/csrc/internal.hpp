@@ -266,6 +266,8 @@ struct pmlsh_index {
     // the mutex
     mutable std::mutex acp_mu;
     mutable std::vector<std::pair<void*, size_t>> acp_bufs;
+    // pinned host staging of the ACP calls' small device-to-host reads
+    mutable void* acp_host = nullptr;
 };
 
 namespace pmlsh {
