@@ -2808,7 +2808,11 @@ void run_acp_lca(const pmlsh_index* x, int k, double c, double confidence, doubl
 
     // 2. FindLCA with R = gamma t ub
     NodeInfo I = fetch_nodes(x);
-    if (!(gamma > 0.0)) gamma = estimate_gamma(x, I, 0.85);
+    if (!(gamma > 0.0)) {
+        // the estimate depends on the index alone (a fixed sample of pairs)
+        if (!(x->acp_gamma085 > 0.0)) x->acp_gamma085 = estimate_gamma(x, I, 0.85);
+        gamma = x->acp_gamma085;
+    }
     if (gamma_used) *gamma_used = gamma;
     const double Rlca = gamma * plan.t * ub;
     std::vector<int64_t> found;

@@ -268,6 +268,9 @@ struct pmlsh_index {
     mutable std::vector<std::pair<void*, size_t>> acp_bufs;
     // pinned host staging of the ACP calls' small device-to-host reads
     mutable void* acp_host = nullptr;
+    // FindLCA's gamma at Pr(gamma) = 0.85 (a fixed sample of the index, so
+    // computed once), 0 until the first call that estimates it
+    mutable double acp_gamma085 = 0.0;
 };
 
 namespace pmlsh {
