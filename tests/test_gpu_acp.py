@@ -484,6 +484,33 @@ def test_radius_filtering_lca_matches_oracle(scale, extra):
                                        rerun=rerun, check_raw=False))
 
 
+def test_lca_gamma_estimate_kept_with_the_index():
+    """FindLCA's gamma estimate depends on the index alone: the first call
+    without gamma computes it and later calls reuse it. Two such calls report
+    the same gamma and answers, a call given that gamma answers the same, and
+    a second index built from the same data (the build is deterministic)
+    estimates the same gamma afresh."""
+    pm = _gpu()
+    say("case: ACP FindLCA gamma kept with the index")
+    w = synth.parity(n=3000, n_queries=1)
+    D, A = w["D"], w["A"]
+    idx = _index(pm, D, A, leaf_size=16, fanout=4)
+    k = 10
+    p1, d1, s1 = idx.acp_lca(k, c=1.5, beta=0.05)
+    p2, d2, s2 = idx.acp_lca(k, c=1.5, beta=0.05)
+    p3, d3, s3 = idx.acp_lca(k, c=1.5, beta=0.05, gamma=s1["gamma"])
+    torch.cuda.synchronize()
+    say("gamma", s1["gamma"], s2["gamma"], s3["gamma"])
+    assert s1["gamma"] > 0 and math.isfinite(s1["gamma"])
+    assert s2["gamma"] == s1["gamma"] and s3["gamma"] == s1["gamma"]
+    for p, d in ((p2, d2), (p3, d3)):
+        assert torch.equal(p, p1) and torch.equal(d, d1)
+    idx2 = _index(pm, D, A, leaf_size=16, fanout=4)
+    _, _, s4 = idx2.acp_lca(k, c=1.5, beta=0.05)
+    torch.cuda.synchronize()
+    assert s4["gamma"] == s1["gamma"]
+
+
 def test_free_releases_device_memory():
     """Building, using and freeing an index returns its device memory (the
     FP16 rows, chunk balls and the ACP buffers kept in the index included)."""
