@@ -288,6 +288,40 @@ def config3_bench(pm, torch, dev, cs=(1.2, 1.5, 2.0),
             "build_s": round(build_s, 2), "points": rows, "mixed_precision": mixed}
 
 
+def copy_rate_gbs(torch, dev, nbytes=256 << 20, reps=10):
+    """HBM rate of a plain device copy (torch's copy kernel) of `nbytes`,
+    counting the bytes read and written, timed with events over `reps`
+    copies after a warm-up: what a streaming kernel reaches on this GPU, as
+    context for the roofline fractions (which stay against the published
+    peak)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2.0 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
+def with_copy_context(r, copy_gbs):
+    """Adds the plain-copy rate and, where the counters give the kernel's HBM
+    bytes per launch, the rate those bytes move at and its fraction of the
+    copy rate."""
+    r["copy_rate_gbs"] = copy_gbs
+    if r.get("traffic") and r.get("per_launch_ms"):
+        tr = r["traffic"] / (r["per_launch_ms"] * 1e-3) / 1e9
+        r["traffic_rate_gbs"] = round(tr, 1)
+        r["traffic_frac_of_copy"] = round(tr / copy_gbs, 4) if copy_gbs else None
+    return r
+
+
 def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=10, with_variants=True):
     """(c,k)-ACP on 200,000 x 512 with 2,000 planted near-duplicate pairs:
     time per call for each k (index built beforehand, data resident in HBM),
@@ -308,6 +342,7 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=10, with_variants=Tr
     idx = pm.Index(D, A)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    copy_gbs = copy_rate_gbs(torch, dev)
     L = idx.info()["leaf_size"]
     d_pad = (d + 3) // 4 * 4
     Dn = w["D"].astype(np.float64)
@@ -368,6 +403,7 @@ def acp_bench(pm, torch, dev, ks=(1, 10, 100), c=1.5, calls=10, with_variants=Tr
                                                   acp_files)
         roof["scan"]["traffic"] = pmc_traffic("acp_tile_scan_wave_kernel", "acp_source_sha",
                                               acp_files)
+        with_copy_context(roof["selfjoin"], copy_gbs)
         log(f"ACP k={k}: {ms:.3f} ms per call, stages {stage_ms}, recall {rec:.3f}, "
             f"ratio {ratio:.6f}, roofline {roof}")
         per_k.append({"k": k, "ms_per_call": round(ms, 3), "calls": calls,
@@ -907,6 +943,7 @@ def main():
         if json.load(fh).get("beta") != beta:
             traffic = None
     roof["traffic"] = traffic
+    with_copy_context(roof, copy_rate_gbs(torch, dev))
 
     if args.calib_copy:
         x = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).uniform_()
